@@ -1,0 +1,798 @@
+/*
+ * FP64 CPU oracle for FastQSL-style field-line tracing (Zhang et al. 2022).
+ *
+ * TEST INFRASTRUCTURE: loaded only by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg. It is never on the product path and shares no
+ * code with the HIP library.
+ *
+ * What it computes
+ *   - The magnetic field at any point is the trilinear interpolant of the node
+ *     values (Section 2.2, Eq. interp / w0 / w1). Inside one grid cell this is a
+ *     polynomial; across cell faces it is only continuous.
+ *   - A field line solves dr/ds = B/|B| (Section 2.1, Eq. rb). The oracle
+ *     approximates the exact solution of that ODE in the interpolated field: it
+ *     integrates cell by cell with every step confined to one closed cell (the
+ *     cell's own polynomial is used for all stages), and a step that would leave
+ *     the cell is cut back so that it ends exactly on the face it crosses first.
+ *     Within a cell the right-hand side is smooth, so the integrator keeps its full
+ *     order. The integrator is classic RK4 with step doubling and Richardson
+ *     extrapolation, the step controlled against a tolerance in grid spacings.
+ *   - Lines run both ways from the seed until they leave the box; the end point is
+ *     the exact intersection with the box face (the paper's boundary rule,
+ *     Section 2.1, read as "land on the face").
+ *   - The twist number Tw = integral of (curl B . B)/(4 pi B^2) dl (Section 1,
+ *     Eq. tw) is an extra component of the same ODE, curl B being node-wise
+ *     second-order differences (the stencil of Eq. grad_B, Section 4) interpolated
+ *     like B. The line length is another component.
+ *   - Q follows Method I (Section 2.1, Eq. D+-2 and Eq. D+-3): the Jacobians of
+ *     both end maps with respect to the seed-plane coordinates come from
+ *     differences over neighbouring seeds, D12 = D20 (D10)^-1 with the inverse
+ *     written as in Eq. D+-3, and Q = (a^2+b^2+c^2+d^2)/|Bn1/Bn2| (Section 1,
+ *     Eq. Q+- with |det D| replaced by the normal-field ratio).
+ */
+#include "fq_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define FATAL_BITS (ORC_OUTSIDE | ORC_NULLB | ORC_MAXSTEPS | ORC_NONFINITE)
+
+void orc_default_opts(orc_opts *o)
+{
+    o->tol = 1e-10;
+    o->h0 = 0.25;
+    o->hmax = 2.0;
+    o->max_steps = 1000000;
+    o->edge_eps = 1e-5;
+    o->want_tw = 1;
+    o->nthreads = 0;
+}
+
+static int64_t node(const orc_field *f, int64_t i, int64_t j, int64_t k)
+{
+    return (k * f->n[1] + j) * f->n[0] + i;
+}
+
+/* ------------------------------------------------------------------------------
+ * curl B at the nodes
+ * ---------------------------------------------------------------------------- */
+
+/* d p / d axis at node (i,j,k): central second-order differences inside, the
+ * one-sided second-order formula (-3 f0 + 4 f1 - f2) / 2h on the boundary nodes. */
+static double deriv(const orc_field *f, const double *p, int axis, int64_t i, int64_t j,
+                    int64_t k)
+{
+    int64_t idx[3] = {i, j, k};
+    int64_t n = f->n[axis];
+    double h = f->spacing[axis];
+    int64_t m = idx[axis];
+    int64_t a[3], b[3], c[3];
+    memcpy(a, idx, sizeof a);
+    memcpy(b, idx, sizeof b);
+    memcpy(c, idx, sizeof c);
+    if (n < 3) { /* two nodes only: the single first-order difference */
+        a[axis] = 0;
+        b[axis] = 1;
+        return (p[node(f, b[0], b[1], b[2])] - p[node(f, a[0], a[1], a[2])]) / h;
+    }
+    if (m == 0) {
+        b[axis] = 1;
+        c[axis] = 2;
+        return (-3.0 * p[node(f, a[0], a[1], a[2])] + 4.0 * p[node(f, b[0], b[1], b[2])] -
+                p[node(f, c[0], c[1], c[2])]) / (2.0 * h);
+    }
+    if (m == n - 1) {
+        b[axis] = n - 2;
+        c[axis] = n - 3;
+        return (3.0 * p[node(f, a[0], a[1], a[2])] - 4.0 * p[node(f, b[0], b[1], b[2])] +
+                p[node(f, c[0], c[1], c[2])]) / (2.0 * h);
+    }
+    a[axis] = m - 1;
+    b[axis] = m + 1;
+    return (p[node(f, b[0], b[1], b[2])] - p[node(f, a[0], a[1], a[2])]) / (2.0 * h);
+}
+
+int orc_curl(const orc_field *f, double *jx, double *jy, double *jz)
+{
+    if (f->n[0] < 2 || f->n[1] < 2 || f->n[2] < 2) return -1;
+    const double *bx = f->b[0], *by = f->b[1], *bz = f->b[2];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < f->n[2]; k++)
+        for (int64_t j = 0; j < f->n[1]; j++)
+            for (int64_t i = 0; i < f->n[0]; i++) {
+                int64_t q = node(f, i, j, k);
+                jx[q] = deriv(f, bz, 1, i, j, k) - deriv(f, by, 2, i, j, k);
+                jy[q] = deriv(f, bx, 2, i, j, k) - deriv(f, bz, 0, i, j, k);
+                jz[q] = deriv(f, by, 0, i, j, k) - deriv(f, bx, 1, i, j, k);
+            }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * trilinear interpolation (Eq. interp, w0, w1) in a given cell
+ * ---------------------------------------------------------------------------- */
+
+void orc_interp(const orc_field *f, const double *const p[3], const int64_t c[3],
+                const double r[3], double out[3])
+{
+    double w[3][2];
+    for (int a = 0; a < 3; a++) {
+        double lo = f->origin[a] + (double)c[a] * f->spacing[a];
+        double hi = f->origin[a] + (double)(c[a] + 1) * f->spacing[a];
+        w[a][0] = (hi - r[a]) / (hi - lo); /* omega_{.,0} */
+        w[a][1] = 1.0 - w[a][0];           /* omega_{.,1} */
+    }
+    for (int comp = 0; comp < 3; comp++) {
+        double s = 0.0;
+        for (int m = 0; m < 2; m++)
+            for (int n = 0; n < 2; n++)
+                for (int q = 0; q < 2; q++)
+                    s += w[0][m] * w[1][n] * w[2][q] *
+                         p[comp][node(f, c[0] + m, c[1] + n, c[2] + q)];
+        out[comp] = s;
+    }
+}
+
+/* The grid cell holding r: floor((r - origin)/spacing), clamped to [0, n-2] so
+ * that a point on an upper box face belongs to the last cell. */
+static void locate(const orc_field *f, const double r[3], int64_t c[3])
+{
+    for (int a = 0; a < 3; a++) {
+        double t = floor((r[a] - f->origin[a]) / f->spacing[a]);
+        int64_t i = (int64_t)t;
+        if (i < 0) i = 0;
+        if (i > f->n[a] - 2) i = f->n[a] - 2;
+        c[a] = i;
+    }
+}
+
+static double face_lo(const orc_field *f, const int64_t c[3], int a)
+{
+    return f->origin[a] + (double)c[a] * f->spacing[a];
+}
+
+static double face_hi(const orc_field *f, const int64_t c[3], int a)
+{
+    return f->origin[a] + (double)(c[a] + 1) * f->spacing[a];
+}
+
+static double box_lo(const orc_field *f, int a) { return f->origin[a]; }
+
+static double box_hi(const orc_field *f, int a)
+{
+    return f->origin[a] + (double)(f->n[a] - 1) * f->spacing[a];
+}
+
+static int in_box(const orc_field *f, const double r[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (!(r[a] >= box_lo(f, a) && r[a] <= box_hi(f, a))) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------------
+ * the line ODE (Eq. rb) with the twist integrand (Eq. tw) and length
+ * y = (x, y, z, Tw, l);  dy/ds = (sigma B/|B|, (curl B . B)/(4 pi |B|^2), 1)
+ * ---------------------------------------------------------------------------- */
+
+typedef struct {
+    const orc_field *f;
+    int64_t c[3];
+    int sigma;
+    int want_tw;
+    double bnull2; /* |B|^2 below this counts as a null */
+} line_ctx;
+
+static int rhs(const line_ctx *L, const double y[5], double dy[5])
+{
+    double B[3];
+    orc_interp(L->f, L->f->b, L->c, y, B);
+    double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    if (!isfinite(b2)) return ORC_NONFINITE;
+    if (b2 <= L->bnull2) return ORC_NULLB;
+    double bm = sqrt(b2);
+    for (int a = 0; a < 3; a++) dy[a] = (double)L->sigma * B[a] / bm;
+    dy[3] = 0.0;
+    if (L->want_tw) {
+        double J[3];
+        orc_interp(L->f, L->f->j, L->c, y, J);
+        double jb = J[0] * B[0] + J[1] * B[1] + J[2] * B[2];
+        if (!isfinite(jb)) return ORC_NONFINITE;
+        dy[3] = jb / (4.0 * M_PI * b2);
+    }
+    dy[4] = 1.0;
+    return 0;
+}
+
+/* one classic RK4 step of length t */
+static int rk4(const line_ctx *L, const double y[5], double t, double out[5])
+{
+    double k1[5], k2[5], k3[5], k4[5], z[5];
+    int st;
+    if ((st = rhs(L, y, k1))) return st;
+    for (int q = 0; q < 5; q++) z[q] = y[q] + 0.5 * t * k1[q];
+    if ((st = rhs(L, z, k2))) return st;
+    for (int q = 0; q < 5; q++) z[q] = y[q] + 0.5 * t * k2[q];
+    if ((st = rhs(L, z, k3))) return st;
+    for (int q = 0; q < 5; q++) z[q] = y[q] + t * k3[q];
+    if ((st = rhs(L, z, k4))) return st;
+    for (int q = 0; q < 5; q++)
+        out[q] = y[q] + t / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    return 0;
+}
+
+/* Step doubling: one step of t against two of t/2. The difference estimates the
+ * error (divided by 2^4 - 1); Richardson extrapolation gives the returned state.
+ * err is the position part in grid spacings. */
+static int rk4_doubled(const line_ctx *L, const double y[5], double t, double out[5],
+                       double *err)
+{
+    double one[5], half[5], two[5];
+    int st;
+    if ((st = rk4(L, y, t, one))) return st;
+    if ((st = rk4(L, y, 0.5 * t, half))) return st;
+    if ((st = rk4(L, half, 0.5 * t, two))) return st;
+    double e2 = 0.0;
+    for (int q = 0; q < 5; q++) {
+        double d = (two[q] - one[q]) / 15.0;
+        out[q] = two[q] + d;
+        if (q < 3) {
+            double g = d / L->f->spacing[q];
+            e2 += g * g;
+        }
+    }
+    *err = sqrt(e2);
+    return 0;
+}
+
+/* Length t in (0, t_hi] at which the step from y ends on the plane
+ * coordinate[a] = plane; g(0) and g(t_hi) must bracket the root. Illinois-modified
+ * regula falsi on g(t) = Phi(y, t)[a] - plane. */
+static int land(const line_ctx *L, const double y[5], int a, double plane, double t_hi,
+                double g_hi, double out[5], double *t_out)
+{
+    double ta = 0.0, ga = y[a] - plane;
+    double tb = t_hi, gb = g_hi;
+    double err, t = t_hi;
+    double tiny = 1e-13 * L->f->spacing[a];
+    int side = 0, st;
+    double cur[5];
+    memcpy(cur, out, sizeof cur);
+    for (int it = 0; it < 200; it++) {
+        t = (ta * gb - tb * ga) / (gb - ga);
+        if (!(t > ta && t < tb)) t = 0.5 * (ta + tb);
+        if ((st = rk4_doubled(L, y, t, cur, &err))) return st;
+        double gt = cur[a] - plane;
+        if (fabs(gt) <= tiny || (tb - ta) <= 1e-15 * t_hi) break;
+        if ((gt > 0) == (gb > 0)) {
+            tb = t;
+            gb = gt;
+            if (side == 1) ga *= 0.5;
+            side = 1;
+        } else {
+            ta = t;
+            ga = gt;
+            if (side == -1) gb *= 0.5;
+            side = -1;
+        }
+    }
+    memcpy(out, cur, sizeof cur);
+    *t_out = t;
+    return 0;
+}
+
+typedef struct {
+    double end[3];
+    int face;
+    double bn;
+    double tw, len;
+    int status;
+    int64_t nsteps;
+} half_line;
+
+/* Trace one half line (direction sigma) from seed until it leaves the box. */
+static void trace_half(const orc_field *f, const double seed[3], int sigma, const orc_opts *o,
+                       double bnull2, half_line *res)
+{
+    line_ctx L;
+    L.f = f;
+    L.sigma = sigma;
+    L.want_tw = o->want_tw;
+    L.bnull2 = bnull2;
+    double dmin = f->spacing[0];
+    if (f->spacing[1] < dmin) dmin = f->spacing[1];
+    if (f->spacing[2] < dmin) dmin = f->spacing[2];
+
+    double y[5] = {seed[0], seed[1], seed[2], 0.0, 0.0};
+    res->face = -1;
+    res->status = 0;
+    res->nsteps = 0;
+    res->tw = res->len = NAN;
+    res->bn = NAN;
+    for (int a = 0; a < 3; a++) res->end[a] = NAN;
+    if (!in_box(f, seed)) {
+        res->status = ORC_OUTSIDE;
+        return;
+    }
+    locate(f, seed, L.c);
+    double h = o->h0 * dmin;
+    const double hmax = o->hmax * dmin;
+    int64_t trials = 0;
+    for (;;) {
+        if (++trials > o->max_steps) {
+            res->status = ORC_MAXSTEPS;
+            return;
+        }
+        /* a point on a face of its cell, heading out through that face, moves to
+         * the neighbouring cell; if there is none the line has left the box */
+        double dy[5];
+        int st = rhs(&L, y, dy);
+        if (st) {
+            res->status = st;
+            return;
+        }
+        int exit_face = -1;
+        for (int a = 0; a < 3 && exit_face < 0; a++) {
+            if (y[a] == face_hi(f, L.c, a) && dy[a] > 0.0) {
+                if (L.c[a] == f->n[a] - 2) exit_face = 2 * a + 1;
+                else L.c[a]++;
+            } else if (y[a] == face_lo(f, L.c, a) && dy[a] < 0.0) {
+                if (L.c[a] == 0) exit_face = 2 * a;
+                else L.c[a]--;
+            }
+        }
+        if (exit_face >= 0) {
+            double B[3];
+            orc_interp(f, f->b, L.c, y, B);
+            memcpy(res->end, y, 3 * sizeof(double));
+            res->face = exit_face;
+            res->bn = B[exit_face / 2];
+            res->tw = y[3];
+            res->len = y[4];
+            return;
+        }
+
+        /* trial step within the current cell's polynomial */
+        double y1[5], err;
+        if ((st = rk4_doubled(&L, y, h, y1, &err))) {
+            res->status = st;
+            return;
+        }
+        if (err > o->tol) {
+            double s = 0.9 * pow(o->tol / err, 0.2);
+            h *= (s < 0.1 ? 0.1 : s);
+            continue;
+        }
+        /* accepted: does it stay in the closed cell? */
+        int out_axis[3] = {0, 0, 0}, any = 0;
+        for (int a = 0; a < 3; a++) {
+            if (y1[a] > face_hi(f, L.c, a)) out_axis[a] = 1, any = 1;
+            else if (y1[a] < face_lo(f, L.c, a)) out_axis[a] = -1, any = 1;
+        }
+        if (!any) {
+            memcpy(y, y1, sizeof y);
+            res->nsteps++;
+            double s = (err > 0.0) ? 0.9 * pow(o->tol / err, 0.2) : 4.0;
+            h *= (s > 4.0 ? 4.0 : s);
+            if (h > hmax) h = hmax;
+            continue;
+        }
+        /* the step leaves the cell: shorten it to end on the first face crossed
+         * (ties go to the lower axis) */
+        double t_best = h, y_best[5];
+        int a_best = -1;
+        for (int a = 0; a < 3; a++) {
+            if (!out_axis[a]) continue;
+            double plane = out_axis[a] > 0 ? face_hi(f, L.c, a) : face_lo(f, L.c, a);
+            double ya[5], ta;
+            memcpy(ya, y1, sizeof ya);
+            if ((st = land(&L, y, a, plane, h, y1[a] - plane, ya, &ta))) {
+                res->status = st;
+                return;
+            }
+            if (a_best < 0 || ta < t_best) {
+                t_best = ta;
+                a_best = a;
+                memcpy(y_best, ya, sizeof ya);
+                y_best[a] = plane;
+            }
+        }
+        /* keep the landed point in the closed cell (root tolerance only) */
+        for (int a = 0; a < 3; a++) {
+            if (a == a_best) continue;
+            double lo = face_lo(f, L.c, a), hi = face_hi(f, L.c, a);
+            if (y_best[a] < lo) y_best[a] = lo;
+            if (y_best[a] > hi) y_best[a] = hi;
+        }
+        memcpy(y, y_best, sizeof y);
+        res->nsteps++;
+    }
+}
+
+/* in-face coordinates of an end point on face `face`: the two other axes, in
+ * increasing axis order */
+static void inface(int face, const double e[3], double uv[2])
+{
+    int a = face / 2, m = 0;
+    for (int b = 0; b < 3; b++)
+        if (b != a) uv[m++] = e[b];
+}
+
+static int near_edge(const orc_field *f, int face, const double e[3], double eps)
+{
+    if (face < 0) return 0;
+    int a = face / 2;
+    for (int b = 0; b < 3; b++) {
+        if (b == a) continue;
+        if (e[b] - box_lo(f, b) < eps || box_hi(f, b) - e[b] < eps) return 1;
+    }
+    return 0;
+}
+
+static double field_scale2(const orc_field *f)
+{
+    int64_t nn = f->n[0] * f->n[1] * f->n[2];
+    double m = 0.0;
+    for (int64_t q = 0; q < nn; q++) {
+        double b2 = f->b[0][q] * f->b[0][q] + f->b[1][q] * f->b[1][q] +
+                    f->b[2][q] * f->b[2][q];
+        if (b2 > m) m = b2;
+    }
+    return m;
+}
+
+/* both halves of one line + B . normal at the seed */
+typedef struct {
+    double end_b[3], end_f[3];
+    int face_b, face_f;
+    double bn_b, bn_f, bn0;
+    double tw, len;
+    double len_b, len_f;
+    int status;
+    int64_t nsteps;
+} full_line;
+
+/* The two ends in the order used for S1 and S2. Normally S1 is the backward end
+ * and S2 the forward end. For a seed on a box face one half has zero length (the
+ * seed is its own end); that end is S1, whatever the polarity, so that
+ * neighbouring seeds on both sides of a polarity inversion line difference the
+ * same map (the seed -> far footpoint map). Q is symmetric in S1 <-> S2. */
+typedef struct {
+    const double *e1, *e2;
+    int f1, f2;
+    double bn1, bn2;
+} ends12;
+
+static ends12 order_ends(const full_line *l)
+{
+    ends12 r;
+    int swap = (l->len_f == 0.0 && l->len_b != 0.0);
+    r.e1 = swap ? l->end_f : l->end_b;
+    r.e2 = swap ? l->end_b : l->end_f;
+    r.f1 = swap ? l->face_f : l->face_b;
+    r.f2 = swap ? l->face_b : l->face_f;
+    r.bn1 = swap ? l->bn_f : l->bn_b;
+    r.bn2 = swap ? l->bn_b : l->bn_f;
+    return r;
+}
+
+static void trace_full(const orc_field *f, const double seed[3], const double nrm[3],
+                       const orc_opts *o, double bnull2, full_line *r)
+{
+    half_line hb, hf;
+    trace_half(f, seed, -1, o, bnull2, &hb);
+    trace_half(f, seed, +1, o, bnull2, &hf);
+    memcpy(r->end_b, hb.end, sizeof r->end_b);
+    memcpy(r->end_f, hf.end, sizeof r->end_f);
+    r->face_b = hb.face;
+    r->face_f = hf.face;
+    r->bn_b = hb.bn;
+    r->bn_f = hf.bn;
+    r->status = hb.status | hf.status;
+    r->nsteps = hb.nsteps + hf.nsteps;
+    r->tw = hb.tw + hf.tw;
+    r->len = hb.len + hf.len;
+    r->len_b = hb.len;
+    r->len_f = hf.len;
+    r->bn0 = NAN;
+    if (!(r->status & ORC_OUTSIDE)) {
+        int64_t c[3];
+        double B[3];
+        locate(f, seed, c);
+        orc_interp(f, f->b, c, seed, B);
+        r->bn0 = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+    }
+    if (!o->want_tw) r->tw = NAN;
+    if (r->status & FATAL_BITS) r->tw = r->len = NAN;
+    if (near_edge(f, r->face_b, r->end_b, o->edge_eps) ||
+        near_edge(f, r->face_f, r->end_f, o->edge_eps))
+        r->status |= ORC_EDGE;
+}
+
+static void store_line(orc_lines *out, int64_t i, const full_line *r)
+{
+    if (!out) return;
+    if (out->end_b) memcpy(out->end_b + 3 * i, r->end_b, 3 * sizeof(double));
+    if (out->end_f) memcpy(out->end_f + 3 * i, r->end_f, 3 * sizeof(double));
+    if (out->face_b) out->face_b[i] = (int8_t)r->face_b;
+    if (out->face_f) out->face_f[i] = (int8_t)r->face_f;
+    if (out->bn_b) out->bn_b[i] = r->bn_b;
+    if (out->bn_f) out->bn_f[i] = r->bn_f;
+    if (out->bn0) out->bn0[i] = r->bn0;
+    if (out->tw) out->tw[i] = r->tw;
+    if (out->len) out->len[i] = r->len;
+    if (out->status) out->status[i] = (uint16_t)r->status;
+    if (out->nsteps) out->nsteps[i] = r->nsteps;
+}
+
+static void set_threads(const orc_opts *o)
+{
+#ifdef _OPENMP
+    if (o->nthreads > 0) omp_set_num_threads(o->nthreads);
+#else
+    (void)o;
+#endif
+}
+
+int orc_trace(const orc_field *f, const double *seeds, int64_t n, const double *normal,
+              const orc_opts *o, orc_lines *out)
+{
+    static const double zn[3] = {0.0, 0.0, 1.0};
+    const double *nrm = normal ? normal : zn;
+    double bnull2 = 1e-60 * field_scale2(f);
+    set_threads(o);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        full_line r;
+        trace_full(f, seeds + 3 * i, nrm, o, bnull2, &r);
+        store_line(out, i, &r);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * Method I squashing factor at one point of a seed grid
+ * ---------------------------------------------------------------------------- */
+
+/* One seed-grid axis of the Jacobian: derivatives of the in-face end coordinates
+ * (u_b, v_b) and (u_f, v_f) with respect to the seed coordinate along the axis.
+ * Central differences when both neighbours end on the centre line's faces at both
+ * ends, else a one-sided difference with the neighbour that does; `m`/`p` are the
+ * minus/plus neighbours (NULL where the grid ends). Returns 0 if no usable
+ * neighbour exists. */
+static int axis_jacobian(const full_line *c, const full_line *m, const full_line *p,
+                         double delta, double d1[2], double d2[2], int *flags)
+{
+    ends12 ec = order_ends(c);
+    ends12 em = m ? order_ends(m) : ec, ep = p ? order_ends(p) : ec;
+    int okm = m && !(m->status & FATAL_BITS) && em.f1 == ec.f1 && em.f2 == ec.f2;
+    int okp = p && !(p->status & FATAL_BITS) && ep.f1 == ec.f1 && ep.f2 == ec.f2;
+    double c1[2], c2[2], m1[2], m2[2], p1[2], p2[2];
+    inface(ec.f1, ec.e1, c1);
+    inface(ec.f2, ec.e2, c2);
+    if (okm) {
+        inface(em.f1, em.e1, m1);
+        inface(em.f2, em.e2, m2);
+    }
+    if (okp) {
+        inface(ep.f1, ep.e1, p1);
+        inface(ep.f2, ep.e2, p2);
+    }
+    if (okm && okp) {
+        for (int q = 0; q < 2; q++) {
+            d1[q] = (p1[q] - m1[q]) / (2.0 * delta);
+            d2[q] = (p2[q] - m2[q]) / (2.0 * delta);
+        }
+        return 1;
+    }
+    if (okp) {
+        for (int q = 0; q < 2; q++) {
+            d1[q] = (p1[q] - c1[q]) / delta;
+            d2[q] = (p2[q] - c2[q]) / delta;
+        }
+        *flags |= ORC_ONESIDED;
+        return 1;
+    }
+    if (okm) {
+        for (int q = 0; q < 2; q++) {
+            d1[q] = (c1[q] - m1[q]) / delta;
+            d2[q] = (c2[q] - m2[q]) / delta;
+        }
+        *flags |= ORC_ONESIDED;
+        return 1;
+    }
+    return 0;
+}
+
+/* Q at a point with centre line c, neighbours along the two S0 axes (x0, y0) and
+ * spacings d0, d1. Eq. D+-2 and Eq. D+-3, then Eq. Q+- with |det D| -> |Bn1/Bn2|. */
+static double method1_q(const full_line *c, const full_line *xm, const full_line *xp,
+                        const full_line *ym, const full_line *yp, double d0, double d1,
+                        double bn0, int *flags)
+{
+    double d1x[2], d2x[2], d1y[2], d2y[2];
+    if (!axis_jacobian(c, xm, xp, d0, d1x, d2x, flags) ||
+        !axis_jacobian(c, ym, yp, d1, d1y, d2y, flags)) {
+        *flags |= ORC_MIXEDFACE;
+        return NAN;
+    }
+    ends12 ec = order_ends(c);
+    /* D10 = d(x1,y1)/d(x0,y0) */
+    double dx1dx0 = d1x[0], dx1dy0 = d1y[0], dy1dx0 = d1x[1], dy1dy0 = d1y[1];
+    /* D20 = d(x2,y2)/d(x0,y0) */
+    double dx2dx0 = d2x[0], dx2dy0 = d2y[0], dy2dx0 = d2x[1], dy2dy0 = d2y[1];
+    /* Eq. D+-3: (D10)^-1 = [[dy1/dy0, -dx1/dy0], [-dy1/dx0, dx1/dx0]] / |Bn0/Bn1| */
+    double s = fabs(bn0 / ec.bn1);
+    double i00 = dy1dy0 / s, i01 = -dx1dy0 / s, i10 = -dy1dx0 / s, i11 = dx1dx0 / s;
+    /* Eq. D+-2: D12 = D20 (D10)^-1 */
+    double a = dx2dx0 * i00 + dx2dy0 * i10;
+    double b = dx2dx0 * i01 + dx2dy0 * i11;
+    double cc = dy2dx0 * i00 + dy2dy0 * i10;
+    double d = dy2dx0 * i01 + dy2dy0 * i11;
+    /* Eq. Q+- with |det D12| -> |Bn1/Bn2| */
+    return (a * a + b * b + cc * cc + d * d) / fabs(ec.bn1 / ec.bn2);
+}
+
+static void cross(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int on_box_face(const orc_field *f, const double r[3])
+{
+    for (int a = 0; a < 3; a++) {
+        double tol = 1e-12 * f->spacing[a];
+        if (fabs(r[a] - box_lo(f, a)) <= tol || fabs(box_hi(f, a) - r[a]) <= tol) return 1;
+    }
+    return 0;
+}
+
+/* Section 4: where |Bn0/B| < 0.05 on an interior S0, rotate S0 perpendicular to the
+ * line and trace four neighbours there, Bn0 becoming |B|. U = e_a x b / |..| with
+ * e_a the axis least aligned with b, V = b x U. */
+static double rotated_q(const orc_field *f, const double r0[3], const double B[3],
+                        double delta, const full_line *c, const orc_opts *o, double bnull2,
+                        int *flags)
+{
+    double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    double bh[3] = {B[0] / bm, B[1] / bm, B[2] / bm};
+    int a = 0;
+    for (int q = 1; q < 3; q++)
+        if (fabs(bh[q]) < fabs(bh[a])) a = q;
+    double ea[3] = {0, 0, 0}, U[3], V[3];
+    ea[a] = 1.0;
+    cross(ea, bh, U);
+    double um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+    for (int q = 0; q < 3; q++) U[q] /= um;
+    cross(bh, U, V);
+    full_line nb[4];
+    const double *dir[2] = {U, V};
+    for (int ax = 0; ax < 2; ax++)
+        for (int sgn = 0; sgn < 2; sgn++) {
+            double s[3];
+            double step = sgn ? delta : -delta;
+            for (int q = 0; q < 3; q++) s[q] = r0[q] + step * dir[ax][q];
+            trace_full(f, s, bh, o, bnull2, &nb[2 * ax + sgn]);
+            if (nb[2 * ax + sgn].status & ORC_EDGE) *flags |= ORC_EDGE;
+        }
+    *flags |= ORC_ROTATED;
+    return method1_q(c, &nb[0], &nb[1], &nb[2], &nb[3], delta, delta, bm, flags);
+}
+
+/* Fill the map from traced lines on an nu x nv grid (i fastest). */
+static void assemble_map(const orc_field *f, const full_line *lines, const double *seeds,
+                         int64_t nu, int64_t nv, int64_t stride_layer, double du, double dv,
+                         const double nrm[3], int allow_rotation, const orc_opts *o,
+                         double bnull2, double *q, double *tw, double *len, uint16_t *status)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < nu * nv; p++) {
+        int64_t i = p % nu, j = p / nu;
+        int64_t idx = stride_layer + p;
+        const full_line *c = &lines[idx];
+        int flags = c->status;
+        double qv = NAN;
+        if (!(c->status & FATAL_BITS)) {
+            const full_line *xm = i > 0 ? &lines[idx - 1] : NULL;
+            const full_line *xp = i < nu - 1 ? &lines[idx + 1] : NULL;
+            const full_line *ym = j > 0 ? &lines[idx - nu] : NULL;
+            const full_line *yp = j < nv - 1 ? &lines[idx + nu] : NULL;
+            const full_line *nbs[4] = {xm, xp, ym, yp};
+            const double *r0 = seeds + 3 * idx;
+            double B[3];
+            int64_t cl[3];
+            locate(f, r0, cl);
+            orc_interp(f, f->b, cl, r0, B);
+            double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            double bn0 = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+            if (allow_rotation && !on_box_face(f, r0) && fabs(bn0) < 0.05 * bm) {
+                double delta = du < dv ? du : dv;
+                qv = rotated_q(f, r0, B, delta, c, o, bnull2, &flags);
+            } else {
+                for (int k = 0; k < 4; k++)
+                    if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
+                qv = method1_q(c, xm, xp, ym, yp, du, dv, bn0, &flags);
+            }
+        }
+        if (q) q[idx] = qv;
+        if (tw) tw[idx] = c->tw;
+        if (len) len[idx] = c->len;
+        if (status) status[idx] = (uint16_t)flags;
+    }
+}
+
+int orc_q2d(const orc_field *f, const double origin[3], const double u[3],
+            const double v[3], int64_t nu, int64_t nv, double du, double dv,
+            const orc_opts *o, double *q, double *tw, double *len, uint16_t *status,
+            orc_lines *lines_out)
+{
+    if (nu < 1 || nv < 1) return -1;
+    set_threads(o);
+    int64_t n = nu * nv;
+    double *seeds = (double *)malloc((size_t)n * 3 * sizeof(double));
+    full_line *lines = (full_line *)malloc((size_t)n * sizeof(full_line));
+    if (!seeds || !lines) {
+        free(seeds);
+        free(lines);
+        return -2;
+    }
+    for (int64_t j = 0; j < nv; j++)
+        for (int64_t i = 0; i < nu; i++)
+            for (int a = 0; a < 3; a++)
+                seeds[3 * (j * nu + i) + a] =
+                    origin[a] + (double)i * du * u[a] + (double)j * dv * v[a];
+    double nrm[3];
+    cross(u, v, nrm);
+    double bnull2 = 1e-60 * field_scale2(f);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) trace_full(f, seeds + 3 * i, nrm, o, bnull2, &lines[i]);
+    assemble_map(f, lines, seeds, nu, nv, 0, du, dv, nrm, 1, o, bnull2, q, tw, len, status);
+    if (lines_out)
+        for (int64_t i = 0; i < n; i++) store_line(lines_out, i, &lines[i]);
+    free(seeds);
+    free(lines);
+    return 0;
+}
+
+int orc_q3d(const orc_field *f, const double origin[3], const double spacing[3],
+            const int64_t nvox[3], const orc_opts *o, double *q, double *tw, double *len,
+            uint16_t *status, orc_lines *lines_out)
+{
+    if (nvox[0] < 1 || nvox[1] < 1 || nvox[2] < 1) return -1;
+    set_threads(o);
+    int64_t layer = nvox[0] * nvox[1];
+    int64_t n = layer * nvox[2];
+    double *seeds = (double *)malloc((size_t)n * 3 * sizeof(double));
+    full_line *lines = (full_line *)malloc((size_t)n * sizeof(full_line));
+    if (!seeds || !lines) {
+        free(seeds);
+        free(lines);
+        return -2;
+    }
+    for (int64_t k = 0; k < nvox[2]; k++)
+        for (int64_t j = 0; j < nvox[1]; j++)
+            for (int64_t i = 0; i < nvox[0]; i++) {
+                int64_t p = (k * nvox[1] + j) * nvox[0] + i;
+                seeds[3 * p + 0] = origin[0] + (double)i * spacing[0];
+                seeds[3 * p + 1] = origin[1] + (double)j * spacing[1];
+                seeds[3 * p + 2] = origin[2] + (double)k * spacing[2];
+            }
+    const double nrm[3] = {0.0, 0.0, 1.0};
+    double bnull2 = 1e-60 * field_scale2(f);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) trace_full(f, seeds + 3 * i, nrm, o, bnull2, &lines[i]);
+    for (int64_t k = 0; k < nvox[2]; k++)
+        assemble_map(f, lines, seeds, nvox[0], nvox[1], k * layer, spacing[0], spacing[1],
+                     nrm, 1, o, bnull2, q, tw, len, status);
+    if (lines_out)
+        for (int64_t i = 0; i < n; i++) store_line(lines_out, i, &lines[i]);
+    free(seeds);
+    free(lines);
+    return 0;
+}

