@@ -1,0 +1,205 @@
+/*
+ * fastqsl.h — C-ABI of the MI355X field-line tracer for the squashing factor Q and
+ * the twist number Tw (Zhang, Chen, Liu & Wang 2022, "FastQSL").
+ *
+ * The library traces one magnetic field line per seed through a gridded field,
+ * with trilinear interpolation (Section 2.2, Eq. interp) and adaptive RKF45
+ * stepping (Section 2.3) both ways to the box faces (Section 2.1), integrates the
+ * twist number along it (Section 1, Eq. tw), and forms Method-I Q from the
+ * footpoint mapping of neighbouring seeds (Section 2.1, Eq. D+-2, Eq. D+-3;
+ * Section 1, Eq. Q+- with |det D| replaced by |Bn1/Bn2|).
+ *
+ * Conventions shared by every entry point
+ *   - Every array pointer is a DEVICE pointer on the current HIP device, allocated
+ *     and owned by the caller; the library keeps no reference after the call.
+ *     Struct arguments themselves are host memory and are read during the call.
+ *   - Fields are three node planes Bx, By, Bz of n[0] x n[1] x n[2] values, x
+ *     fastest: node (i,j,k) of a plane is element (k*n[1] + j)*n[0] + i. Node
+ *     (i,j,k) sits at origin + (i,j,k) * spacing (a uniform Cartesian grid).
+ *   - Step sizes and tolerances are in grid spacings (the paper's unit for tol,
+ *     Section 2.3); positions and lengths are in the units of origin/spacing.
+ *   - Box faces are numbered 0 = x-, 1 = x+, 2 = y-, 3 = y+, 4 = z-, 5 = z+.
+ *   - Calls only enqueue work on `stream` (a hipStream_t; NULL = the null stream)
+ *     and return; they never synchronise, never allocate device memory, and issue
+ *     no memset node, so a call can be captured into a HIP graph. Scratch memory
+ *     comes from the caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned),
+ *     sized by the matching *_workspace_size query with the same arguments.
+ *   - Return value: FQ_OK or a negative FQ_E* code (fastqsl_strerror gives text).
+ *     Argument errors are detected before anything is enqueued. Per-line problems
+ *     never fail a call: they set per-line / per-point status bits and NaN outputs.
+ */
+#ifndef FASTQSL_H
+#define FASTQSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define FQ_OK 0
+#define FQ_EINVAL (-1)       /* a null required pointer or an inconsistent argument */
+#define FQ_ENOMEM (-2)       /* workspace smaller than the size query returns */
+#define FQ_EHIP (-3)         /* a HIP launch failed */
+#define FQ_EUNSUPPORTED (-4) /* a valid but unsupported combination */
+
+/* field storage types */
+#define FQ_DT_F32 0
+#define FQ_DT_F64 1
+
+/* arithmetic forms */
+#define FQ_PREC_F32X 0 /* FP32 tracing and interpolation; FP64 Jacobian, Q ratio, Tw sum,
+                          normal fields, and FP64 re-tracing of grazing lines */
+#define FQ_PREC_F64 1  /* every step in FP64 */
+
+/* per-line / per-point status bits */
+#define FQ_ST_OK 0
+#define FQ_ST_OUTSIDE 1     /* seed outside the box: outputs NaN */
+#define FQ_ST_NULLB 2       /* |B| vanished on the line: outputs NaN */
+#define FQ_ST_MAXSTEPS 4    /* trial-step budget exhausted: outputs NaN */
+#define FQ_ST_NONFINITE 8   /* NaN/Inf in the field on the line: outputs NaN */
+#define FQ_ST_ONESIDED 16   /* a one-sided difference entered Q */
+#define FQ_ST_MIXEDFACE 32  /* no neighbour ends on the centre line's faces: Q = NaN */
+#define FQ_ST_EDGE 64       /* a line of the stencil ends within edge_eps of a box edge */
+#define FQ_ST_ROTATED 128   /* S0 rotated perpendicular to B (|Bn0/B| < 0.05, interior S0) */
+
+/* A field: three device planes of n[0]*n[1]*n[2] values of type `dtype`. */
+typedef struct {
+    int64_t n[3];         /* nodes along x, y, z; each >= 2 */
+    double origin[3];     /* position of node (0,0,0) */
+    double spacing[3];    /* node spacing per axis; > 0 */
+    int32_t dtype;        /* FQ_DT_F32 or FQ_DT_F64 */
+    int32_t reserved;
+    const void *b[3];     /* device: Bx, By, Bz planes */
+} fq_field;
+
+/* Tracing parameters (Section 2.3 and the S0 rules of Section 4).
+ * For a line whose seed has field angle |Bn0/B| to S0, the first step is
+ * max(step_perp |Bn0/B|, step_min) (Eq. step) and the per-step error bound is
+ * tol_perp |Bn0/B|^1.5 (Eq. tol), with |Bn0/B| taken no smaller than 0.05 and the
+ * bound no smaller than tol_floor. Zero-valued fields take the documented default. */
+typedef struct {
+    double tol_perp;   /* RKF45 error bound for a line perpendicular to S0 (grid spacings); default 1e-6 */
+    double step_perp;  /* first step for a perpendicular line (grid spacings); default 1 */
+    double step_min;   /* smallest first step (grid spacings); default 0.05 */
+    double tol_floor;  /* smallest error bound used (grid spacings); default 16 ulp(1) of the form */
+    double edge_eps;   /* an end this close to a box edge (units of origin/spacing) sets FQ_ST_EDGE; default 1e-5 */
+    int64_t max_steps; /* trial steps per half line; default 200000 */
+    int32_t precision; /* FQ_PREC_F32X (default) or FQ_PREC_F64 */
+    int32_t want_tw;   /* nonzero: integrate Tw (the curl planes are built) */
+    int32_t block;     /* threads per block of the tracer: 64, 128, 192 or 256; 0 = 256 */
+    int32_t waves_per_cu; /* resident waves per CU the tracer's grid is sized for; 0 = the most that fit */
+    double graze;      /* FQ_PREC_F32X only: a line whose field makes an angle |Bn/B| below this
+                          with S0 at its seed or with the face at either end (such lines turn
+                          FP32 rounding into large footpoint errors) is traced again in FP64,
+                          as is any line the FP32 pass could not finish; default 0.05,
+                          negative = no FP64 pass */
+    uint64_t *stats;   /* device, optional: 5 counters ADDED to by the tracer — trial steps,
+                          accepted steps, cell fetches, half lines traced, half lines traced
+                          again in FP64 (NULL = not collected) */
+} fq_params;
+
+/* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,
+ * u and v orthonormal. Map points are stored i fastest. */
+typedef struct {
+    double origin[3];
+    double u[3];
+    double v[3];
+    int64_t nu, nv;
+    double du, dv;
+} fq_plane;
+
+/* 3-D seeds at voxel centres origin + (i,j,k) spacing (i fastest). S0 of each
+ * voxel is the z plane through it; its stencil neighbours are (i+-1, j, k) and
+ * (i, j+-1, k). */
+typedef struct {
+    double origin[3];
+    double spacing[3];
+    int64_t n[3];
+} fq_voxels;
+
+/* Per-line outputs, n entries each (end_b/end_f are n x 3); any pointer may be
+ * NULL. The backward half runs against B, the forward half along it. */
+typedef struct {
+    double *end_b, *end_f;   /* end points of the backward / forward halves */
+    int8_t *face_b, *face_f; /* their box faces (-1 when the half failed) */
+    double *bn_b, *bn_f;     /* B . e_axis(face) at the ends, FP64 */
+    double *bn0;             /* B . normal at the seed, FP64 */
+    double *tw;              /* whole-line twist number */
+    double *length;          /* whole-line length */
+    uint16_t *status;        /* FQ_ST_* bits of the line */
+} fq_lines;
+
+/* Per-point map outputs; any pointer may be NULL. */
+typedef struct {
+    double *q;          /* squashing factor (NaN where undefined) */
+    double *tw;         /* twist number of the point's line */
+    double *length;     /* length of the point's line */
+    uint16_t *status;   /* FQ_ST_* bits of the point */
+    fq_lines lines;     /* the point's own line (NULL members skipped) */
+} fq_map;
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_trace — trace n seeds (device, n x 3 doubles) both ways to the box
+ * (Section 2.1, Eq. rb; Section 2.2; Section 2.3) and integrate Tw along each line
+ * (Section 1, Eq. tw). normal (host, 3 doubles; NULL = +z) defines Bn0 and the
+ * Eq. step / Eq. tol scaling of each line.
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_trace_workspace_size(const fq_field *f, int64_t n, const fq_params *p);
+int fastqsl_trace(const fq_field *f, const double *seeds, int64_t n, const double *normal,
+                  const fq_params *p, const fq_lines *out, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_q2d — Q, Tw and length maps on 2-D seed grids (Section 2.1 Method I,
+ * Eq. D+-2, Eq. D+-3; Section 1, Eq. Q+-, Eq. tw). njobs >= 1 independent
+ * (field, plane, map) triples are traced in ONE persistent launch sharing one line
+ * queue, so cubes and seed grids of uneven sizes keep the GPU full. fields,
+ * planes and maps are host arrays of njobs entries; map pointers are device
+ * pointers of nu*nv entries. S0 on a box face is used as is; on an interior plane
+ * S0 is rotated perpendicular to B where |Bn0/B| < 0.05 (Section 4).
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_q2d_workspace_size(const fq_field *fields, const fq_plane *planes, int njobs,
+                                  const fq_params *p);
+int fastqsl_q2d(const fq_field *fields, const fq_plane *planes, int njobs, const fq_params *p,
+                const fq_map *maps, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_q3d — Q, Tw and length at voxel centres (Section 1, Eq. qline: one line
+ * per voxel, its Q assigned to the voxel), with S0 rotated perpendicular to B
+ * where |Bz/B| < 0.05 and four extra lines traced there (Section 4).
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_q3d_workspace_size(const fq_field *f, const fq_voxels *v, const fq_params *p);
+int fastqsl_q3d(const fq_field *f, const fq_voxels *v, const fq_params *p, const fq_map *map,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_backward — reverse-mode derivative of a q2d map on one field with
+ * respect to the field's node values: given dL/dQ, dL/dTw (nu*nv doubles each)
+ * and dL/d end_b, dL/d end_f (nu*nv x 3 doubles each) — device arrays, any may
+ * be NULL — and the same inputs as the forward call, ADD dL/dBx, dL/dBy, dL/dBz
+ * to gb[0..2] (device float64 planes shaped like the field). Lines are re-traced
+ * forward with their step sequence recorded, and the adjoint is taken back
+ * through the accepted steps (discrete adjoint, step sizes held fixed),
+ * recomputed in segments of `segment` accepted steps from checkpoints kept in
+ * the workspace. Form FQ_PREC_F64 only.
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_backward_workspace_size(const fq_field *f, const fq_plane *pl,
+                                       const fq_params *p, int segment);
+int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
+                     const double *dq, const double *dtw, const double *dend_b,
+                     const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Text of a return code (static storage). */
+const char *fastqsl_strerror(int code);
+
+/* Library version string (static storage). */
+const char *fastqsl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTQSL_H */

@@ -285,6 +285,36 @@ static int land(const line_ctx *L, const double y[5], int a, double plane, doubl
     return 0;
 }
 
+/* inside the closed cell along every axis except `skip` (-1: none) */
+static int inside_cell(const line_ctx *L, const double r[3], int skip)
+{
+    for (int a = 0; a < 3; a++)
+        if (a != skip && (r[a] > face_hi(L->f, L->c, a) || r[a] < face_lo(L->f, L->c, a)))
+            return 0;
+    return 1;
+}
+
+/* First parameter value in (0, t) at which the step y -> y1 (slopes dy0 at the
+ * start) leaves the closed cell along an axis other than `skip`, judged at the RK4
+ * half step and at 15 points of the cubic Hermite interpolant; 0 if none. */
+static double excursion(const line_ctx *L, const double y[5], const double dy0[5],
+                        const double y1[5], double t, int skip)
+{
+    double mid[5], dy1[5];
+    if (rk4(L, y, 0.5 * t, mid) == 0 && !inside_cell(L, mid, skip)) return 0.5 * t;
+    if (rhs(L, y1, dy1)) return 0.0;
+    for (int k = 1; k < 16; k++) {
+        double th = k / 16.0, th2 = th * th, th3 = th2 * th;
+        double h00 = 2 * th3 - 3 * th2 + 1, h10 = th3 - 2 * th2 + th;
+        double h01 = -2 * th3 + 3 * th2, h11 = th3 - th2;
+        double r[3];
+        for (int a = 0; a < 3; a++)
+            r[a] = h00 * y[a] + h10 * t * dy0[a] + h01 * y1[a] + h11 * t * dy1[a];
+        if (!inside_cell(L, r, skip)) return th * t;
+    }
+    return 0.0;
+}
+
 typedef struct {
     double end[3];
     int face;
@@ -374,6 +404,15 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
             else if (y1[a] < face_lo(f, L.c, a)) out_axis[a] = -1, any = 1;
         }
         if (!any) {
+            /* the end is inside, but the line may have left the cell and come back
+             * within the step: look at the half step and at points of the cubic
+             * Hermite interpolant of the step; if one is outside, retry with the step
+             * cut at the first such point */
+            double t_out = excursion(&L, y, dy, y1, h, -1);
+            if (t_out > 0.0) {
+                h = t_out;
+                continue;
+            }
             memcpy(y, y1, sizeof y);
             res->nsteps++;
             double s = (err > 0.0) ? 0.9 * pow(o->tol / err, 0.2) : 4.0;
@@ -399,6 +438,15 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
                 a_best = a;
                 memcpy(y_best, ya, sizeof ya);
                 y_best[a] = plane;
+            }
+        }
+        /* the shortened step must not leave the cell along another axis on the way
+         * (a brief excursion over a neighbouring face): cut it there instead */
+        {
+            double t_out = excursion(&L, y, dy, y_best, t_best, a_best);
+            if (t_out > 0.0) {
+                h = t_out;
+                continue;
             }
         }
         /* keep the landed point in the closed cell (root tolerance only) */

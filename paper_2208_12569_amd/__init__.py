@@ -1,0 +1,248 @@
+"""MI355X field-line tracer for the squashing factor Q and the twist number Tw.
+
+Python binding of libfastqsl.so (include/fastqsl.h). This layer only marshals
+arguments: PyTorch provides device memory and the stream, and every step of the
+computation runs in the library's HIP kernels. There is no CPU fallback; calls fail
+if the library is missing or no GPU is present.
+
+Fields are torch tensors of shape (3, nz, ny, nx) (Bx, By, Bz planes, x fastest),
+float32 or float64, on the current CUDA/HIP device. `grid` is any object with
+`origin` and `spacing` 3-sequences (node (i,j,k) at origin + (i,j,k)*spacing).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    FQ_PREC_F32X,
+    FQ_PREC_F64,
+    ST_EDGE,
+    ST_FATAL,
+    ST_MAXSTEPS,
+    ST_MIXEDFACE,
+    ST_NONFINITE,
+    ST_NULLB,
+    ST_ONESIDED,
+    ST_OUTSIDE,
+    ST_ROTATED,
+)
+
+
+@dataclass
+class Params:
+    """Tracing parameters (zero = library default; see fq_params in fastqsl.h)."""
+
+    tol_perp: float = 0.0
+    step_perp: float = 0.0
+    step_min: float = 0.0
+    tol_floor: float = 0.0
+    edge_eps: float = 0.0
+    max_steps: int = 0
+    precision: int = FQ_PREC_F32X
+    want_tw: bool = True
+    block: int = 0
+    waves_per_cu: int = 0
+    graze: float = 0.0
+    stats: object = None  # optional CUDA int64 tensor of 5 counters (added to)
+
+    def c(self) -> _lib.fq_params:
+        p = _lib.fq_params()
+        p.tol_perp = self.tol_perp
+        p.step_perp = self.step_perp
+        p.step_min = self.step_min
+        p.tol_floor = self.tol_floor
+        p.edge_eps = self.edge_eps
+        p.max_steps = int(self.max_steps)
+        p.precision = int(self.precision)
+        p.want_tw = 1 if self.want_tw else 0
+        p.block = int(self.block)
+        p.waves_per_cu = int(self.waves_per_cu)
+        p.graze = float(self.graze)
+        p.stats = self.stats.data_ptr() if self.stats is not None else None
+        return p
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2208_12569_amd needs a GPU (no CPU fallback)")
+    return torch
+
+
+def _stream(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _field(B, grid) -> _lib.fq_field:
+    torch = _torch()
+    if B.dim() != 4 or B.shape[0] != 3 or not B.is_cuda:
+        raise ValueError("B must be a CUDA tensor of shape (3, nz, ny, nx)")
+    if B.dtype not in (torch.float32, torch.float64):
+        raise ValueError("B must be float32 or float64")
+    if not B.is_contiguous():
+        raise ValueError("B must be contiguous")
+    f = _lib.fq_field()
+    nz, ny, nx = B.shape[1:]
+    f.n[:] = (nx, ny, nz)
+    f.origin[:] = tuple(float(v) for v in grid.origin)
+    f.spacing[:] = tuple(float(v) for v in grid.spacing)
+    f.dtype = _lib.FQ_DT_F32 if B.dtype == torch.float32 else _lib.FQ_DT_F64
+    for c in range(3):
+        f.b[c] = B[c].data_ptr()
+    return f
+
+
+def _plane(pl) -> _lib.fq_plane:
+    p = _lib.fq_plane()
+    p.origin[:] = tuple(float(v) for v in pl.origin)
+    p.u[:] = tuple(float(v) for v in pl.u)
+    p.v[:] = tuple(float(v) for v in pl.v)
+    p.nu, p.nv = int(pl.nu), int(pl.nv)
+    p.du, p.dv = float(pl.du), float(pl.dv)
+    return p
+
+
+def _voxels(vx) -> _lib.fq_voxels:
+    v = _lib.fq_voxels()
+    v.origin[:] = tuple(float(x) for x in vx.origin)
+    v.spacing[:] = tuple(float(x) for x in vx.spacing)
+    v.n[:] = tuple(int(x) for x in vx.n)
+    return v
+
+
+_LINE_KEYS = ("end_b", "end_f", "face_b", "face_f", "bn_b", "bn_f", "bn0", "tw", "length", "status")
+
+
+def _alloc_lines(n: int, device, keys=_LINE_KEYS):
+    torch = _torch()
+    out = {}
+    for k in keys:
+        if k in ("end_b", "end_f"):
+            out[k] = torch.empty((n, 3), dtype=torch.float64, device=device)
+        elif k in ("face_b", "face_f"):
+            out[k] = torch.empty(n, dtype=torch.int8, device=device)
+        elif k == "status":
+            out[k] = torch.empty(n, dtype=torch.int16, device=device)
+        else:
+            out[k] = torch.empty(n, dtype=torch.float64, device=device)
+    return out
+
+
+def _lines_struct(d: dict) -> _lib.fq_lines:
+    s = _lib.fq_lines()
+    for k in _LINE_KEYS:
+        if k in d:
+            setattr(s, k, d[k].data_ptr())
+    return s
+
+
+def _workspace(nbytes: int, device, ws=None):
+    torch = _torch()
+    if ws is not None and ws.numel() >= nbytes:
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def version() -> str:
+    return _lib.load().fastqsl_version().decode()
+
+
+def trace(B, grid, seeds, normal=(0.0, 0.0, 1.0), params: Optional[Params] = None,
+          stream=None, ws=None) -> dict:
+    """Trace every seed (a CUDA float64 tensor of shape (n, 3)) both ways to the box."""
+    torch = _torch()
+    lib = _lib.load()
+    params = params or Params()
+    f = _field(B, grid)
+    p = params.c()
+    seeds = seeds.to(device=B.device, dtype=torch.float64).contiguous()
+    n = seeds.shape[0]
+    out = _alloc_lines(n, B.device)
+    need = lib.fastqsl_trace_workspace_size(C.byref(f), n, C.byref(p))
+    if need == 0:
+        raise ValueError("invalid field or parameters")
+    w = _workspace(need, B.device, ws)
+    nrm = (C.c_double * 3)(*normal)
+    ls = _lines_struct(out)
+    _lib.check(lib.fastqsl_trace(C.byref(f), seeds.data_ptr(), n, nrm, C.byref(p), C.byref(ls),
+                                 w.data_ptr(), w.numel(), _stream(stream)), "fastqsl_trace")
+    out["_ws"] = w
+    return out
+
+
+def _alloc_map(npts: int, shape, device, want_lines: bool):
+    torch = _torch()
+    m = {"q": torch.empty(shape, dtype=torch.float64, device=device),
+         "tw": torch.empty(shape, dtype=torch.float64, device=device),
+         "length": torch.empty(shape, dtype=torch.float64, device=device),
+         "status": torch.empty(shape, dtype=torch.int16, device=device)}
+    s = _lib.fq_map()
+    s.q = m["q"].data_ptr()
+    s.tw = m["tw"].data_ptr()
+    s.length = m["length"].data_ptr()
+    s.status = m["status"].data_ptr()
+    if want_lines:
+        m["lines"] = _alloc_lines(npts, device)
+        s.lines = _lines_struct(m["lines"])
+    return m, s
+
+
+def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
+              stream=None, ws=None) -> list:
+    """Q/Tw/length maps for several (B, grid, plane) triples in ONE persistent launch."""
+    lib = _lib.load()
+    params = params or Params()
+    n = len(jobs)
+    fields = (_lib.fq_field * n)()
+    planes = (_lib.fq_plane * n)()
+    maps = (_lib.fq_map * n)()
+    outs = []
+    for j, (B, grid, pl) in enumerate(jobs):
+        fields[j] = _field(B, grid)
+        planes[j] = _plane(pl)
+        m, s = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines)
+        maps[j] = s
+        outs.append(m)
+    p = params.c()
+    need = lib.fastqsl_q2d_workspace_size(fields, planes, n, C.byref(p))
+    if need == 0:
+        raise ValueError("invalid field, plane or parameters (or an unsupported combination)")
+    w = _workspace(need, jobs[0][0].device, ws)
+    _lib.check(lib.fastqsl_q2d(fields, planes, n, C.byref(p), maps, w.data_ptr(), w.numel(),
+                               _stream(stream)), "fastqsl_q2d")
+    for m in outs:
+        m["_ws"] = w
+    return outs
+
+
+def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = False,
+        stream=None, ws=None) -> dict:
+    """Q, Tw and length maps on a 2-D seed grid (shape (nv, nu))."""
+    return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws)[0]
+
+
+def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = False,
+        stream=None, ws=None) -> dict:
+    """Q, Tw and length at voxel centres (shape (nz, ny, nx) of the voxel grid)."""
+    lib = _lib.load()
+    params = params or Params()
+    f = _field(B, grid)
+    v = _voxels(voxels)
+    nx, ny, nz = (int(x) for x in voxels.n)
+    m, s = _alloc_map(nx * ny * nz, (nz, ny, nx), B.device, want_lines)
+    p = params.c()
+    need = lib.fastqsl_q3d_workspace_size(C.byref(f), C.byref(v), C.byref(p))
+    if need == 0:
+        raise ValueError("invalid field, voxels or parameters")
+    w = _workspace(need, B.device, ws)
+    _lib.check(lib.fastqsl_q3d(C.byref(f), C.byref(v), C.byref(p), C.byref(s), w.data_ptr(),
+                               w.numel(), _stream(stream)), "fastqsl_q3d")
+    m["_ws"] = w
+    return m

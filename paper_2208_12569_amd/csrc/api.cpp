@@ -1,0 +1,615 @@
+// C-ABI entry points: argument checks, workspace carving and launch sequencing.
+//
+// Every call enqueues, on the caller's stream and into the caller's workspace:
+//   fill (counters)  ->  prep (node records + curl, per field)
+//   -> [classify (rotated-S0 list)] -> store job table -> persistent trace
+//   -> stencil (Q, Tw, length, per-line outputs)
+// The size query and the call carve the workspace with the same code path, so the
+// two can never disagree.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "fq_internal.h"
+
+namespace fq {
+namespace {
+
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+enum SpecKind { SPEC_LIST, SPEC_PLANE, SPEC_VOXELS };
+
+struct Spec {
+    SpecKind kind;
+    const fq_field *f;
+    fq_plane pl;
+    fq_voxels vx;
+    const double *seeds;
+    int64_t nlist;
+    double normal[3];
+    const fq_map *map;        // maps (plane / voxels)
+    const fq_lines *lines;    // list outputs
+};
+
+int64_t nodes_of(const fq_field *f) { return f->n[0] * f->n[1] * f->n[2]; }
+
+int64_t lines_of(const Spec &s)
+{
+    switch (s.kind) {
+    case SPEC_LIST: return s.nlist;
+    case SPEC_PLANE: return s.pl.nu * s.pl.nv;
+    default: return s.vx.n[0] * s.vx.n[1] * s.vx.n[2];
+    }
+}
+
+bool finite3(const double v[3]) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+int check_field(const fq_field *f)
+{
+    if (!f) return FQ_EINVAL;
+    for (int a = 0; a < 3; a++) {
+        if (f->n[a] < 2 || f->n[a] > (int64_t)1 << 30) return FQ_EINVAL;
+        if (!(f->spacing[a] > 0.0) || !isfinite(f->spacing[a])) return FQ_EINVAL;
+        if (!f->b[a]) return FQ_EINVAL;
+    }
+    if (!finite3(f->origin)) return FQ_EINVAL;
+    if (f->dtype != FQ_DT_F32 && f->dtype != FQ_DT_F64) return FQ_EINVAL;
+    if (nodes_of(f) > ((int64_t)1 << 40)) return FQ_EINVAL;
+    return FQ_OK;
+}
+
+int check_plane(const fq_plane *p)
+{
+    if (!p) return FQ_EINVAL;
+    if (p->nu < 1 || p->nv < 1 || (p->nu * p->nv) > ((int64_t)1 << 34)) return FQ_EINVAL;
+    if (!(p->du > 0.0) || !(p->dv > 0.0) || !isfinite(p->du) || !isfinite(p->dv)) return FQ_EINVAL;
+    if (!finite3(p->origin) || !finite3(p->u) || !finite3(p->v)) return FQ_EINVAL;
+    double uu = p->u[0] * p->u[0] + p->u[1] * p->u[1] + p->u[2] * p->u[2];
+    double vv = p->v[0] * p->v[0] + p->v[1] * p->v[1] + p->v[2] * p->v[2];
+    double uv = p->u[0] * p->v[0] + p->u[1] * p->v[1] + p->u[2] * p->v[2];
+    if (fabs(uu - 1.0) > 1e-9 || fabs(vv - 1.0) > 1e-9 || fabs(uv) > 1e-9) return FQ_EINVAL;
+    return FQ_OK;
+}
+
+int check_voxels(const fq_voxels *v)
+{
+    if (!v) return FQ_EINVAL;
+    for (int a = 0; a < 3; a++) {
+        if (v->n[a] < 1) return FQ_EINVAL;
+        if (!(v->spacing[a] > 0.0) || !isfinite(v->spacing[a])) return FQ_EINVAL;
+    }
+    if (v->n[0] * v->n[1] * v->n[2] > ((int64_t)1 << 34)) return FQ_EINVAL;
+    if (!finite3(v->origin)) return FQ_EINVAL;
+    return FQ_OK;
+}
+
+int resolve_params(const fq_params *in, fq_params &p)
+{
+    memset(&p, 0, sizeof p);
+    if (in) p = *in;
+    if (p.precision != FQ_PREC_F32X && p.precision != FQ_PREC_F64) return FQ_EINVAL;
+    if (p.tol_perp < 0 || p.step_perp < 0 || p.step_min < 0 || p.tol_floor < 0 || p.edge_eps < 0 ||
+        p.max_steps < 0)
+        return FQ_EINVAL;
+    if (!isfinite(p.tol_perp) || !isfinite(p.step_perp) || !isfinite(p.step_min) ||
+        !isfinite(p.tol_floor) || !isfinite(p.edge_eps))
+        return FQ_EINVAL;
+    if (p.block != 0 && (p.block < 64 || p.block > 256 || (p.block % 64) != 0)) return FQ_EINVAL;
+    if (p.waves_per_cu < 0) return FQ_EINVAL;
+    if (p.tol_perp == 0) p.tol_perp = 1e-6;
+    if (p.step_perp == 0) p.step_perp = 1.0;
+    if (p.step_min == 0) p.step_min = 0.05;
+    if (p.tol_floor == 0) p.tol_floor = (p.precision == FQ_PREC_F64) ? 1e-14 : 2.384185791015625e-7;
+    if (p.edge_eps == 0) p.edge_eps = 1e-5;
+    if (p.max_steps == 0) p.max_steps = 200000;
+    if (!isfinite(p.graze)) return FQ_EINVAL;
+    if (p.graze == 0) p.graze = 0.05;
+    if (in == nullptr) p.want_tw = 1;
+    return FQ_OK;
+}
+
+// All seeds of the plane on one box face (then S0 is never rotated).
+bool plane_on_face(const fq_plane &pl, const fq_field &f)
+{
+    double n[3] = {pl.u[1] * pl.v[2] - pl.u[2] * pl.v[1], pl.u[2] * pl.v[0] - pl.u[0] * pl.v[2],
+                   pl.u[0] * pl.v[1] - pl.u[1] * pl.v[0]};
+    for (int a = 0; a < 3; a++) {
+        if (fabs(fabs(n[a]) - 1.0) > 1e-12) continue;
+        double lo = f.origin[a], hi = f.origin[a] + (f.n[a] - 1) * f.spacing[a];
+        double tol = 1e-12 * f.spacing[a];
+        if (fabs(pl.origin[a] - lo) <= tol || fabs(pl.origin[a] - hi) <= tol) return true;
+    }
+    return false;
+}
+
+struct SpecWs {
+    size_t nodeA, nodeC, bmax, end, tw, len, face, st;
+    size_t nodeA64, nodeC64;  // FP64 node records for the FP64 pass (FP64 grids only)
+    size_t rot_index, rot, rot_count, r_end, r_tw, r_len, r_face, r_st;
+    bool rotate;
+    int64_t nlines;
+};
+
+HalfRecs recs_at(char *ws, size_t end, size_t tw, size_t len, size_t face, size_t st)
+{
+    HalfRecs r;
+    r.end = (double *)(ws + end);
+    r.tw = (double *)(ws + tw);
+    r.len = (double *)(ws + len);
+    r.face = (int8_t *)(ws + face);
+    r.st = (uint16_t *)(ws + st);
+    return r;
+}
+
+void take_recs(Carve &cv, int64_t n, size_t &end, size_t &tw, size_t &len, size_t &face, size_t &st)
+{
+    end = cv.take((size_t)(2 * n) * 3 * sizeof(double));
+    tw = cv.take((size_t)(2 * n) * sizeof(double));
+    len = cv.take((size_t)(2 * n) * sizeof(double));
+    face = cv.take((size_t)(2 * n));
+    st = cv.take((size_t)(2 * n) * sizeof(uint16_t));
+}
+
+void set_map_geometry(const Spec &s, MapJob &m)
+{
+    const fq_field &f = *s.f;
+    for (int a = 0; a < 3; a++) {
+        m.b[a] = f.b[a];
+        m.n[a] = (int32_t)f.n[a];
+        m.origin[a] = f.origin[a];
+        m.spacing[a] = f.spacing[a];
+    }
+    m.dtype = f.dtype;
+    if (s.kind == SPEC_PLANE) {
+        m.nu = s.pl.nu;
+        m.nv = s.pl.nv;
+        m.nlayers = 1;
+        m.d0 = s.pl.du;
+        m.d1 = s.pl.dv;
+        for (int a = 0; a < 3; a++) {
+            m.p_origin[a] = s.pl.origin[a];
+            m.p_a[a] = s.pl.du * s.pl.u[a];
+            m.p_b[a] = s.pl.dv * s.pl.v[a];
+            m.p_c[a] = 0.0;
+            m.normal[a] = s.normal[a];
+        }
+    } else if (s.kind == SPEC_VOXELS) {
+        m.nu = s.vx.n[0];
+        m.nv = s.vx.n[1];
+        m.nlayers = s.vx.n[2];
+        m.d0 = s.vx.spacing[0];
+        m.d1 = s.vx.spacing[1];
+        for (int a = 0; a < 3; a++) {
+            m.p_origin[a] = s.vx.origin[a];
+            m.p_a[a] = a == 0 ? s.vx.spacing[0] : 0.0;
+            m.p_b[a] = a == 1 ? s.vx.spacing[1] : 0.0;
+            m.p_c[a] = a == 2 ? s.vx.spacing[2] : 0.0;
+            m.normal[a] = s.normal[a];
+        }
+    } else {
+        m.nu = s.nlist;
+        m.nv = 1;
+        m.nlayers = 1;
+        for (int a = 0; a < 3; a++) m.normal[a] = s.normal[a];
+    }
+}
+
+// Carve the workspace and (unless dry) enqueue the whole call.
+int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_bytes, bool dry,
+        size_t *need, hipStream_t stream)
+{
+    const int ns = (int)specs.size();
+    const size_t tsz = P.precision == FQ_PREC_F64 ? 8 : 4;
+    Carve cv;
+    const size_t off_ctr = cv.take(256);  // u64 queue counter, u32 spare
+    std::vector<SpecWs> W(ns);
+    int nrot = 0;
+    for (int i = 0; i < ns; i++) {
+        const Spec &s = specs[i];
+        SpecWs &w = W[i];
+        memset(&w, 0, sizeof w);
+        const int64_t nn = nodes_of(s.f);
+        w.nlines = lines_of(s);
+        w.nodeA = cv.take((size_t)nn * 4 * tsz);
+        w.nodeC = P.want_tw ? cv.take((size_t)nn * 2 * tsz) : 0;
+        w.bmax = cv.take(sizeof(float));
+        take_recs(cv, w.nlines, w.end, w.tw, w.len, w.face, w.st);
+        w.rotate = (s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f));
+        if (w.rotate) {
+            nrot++;
+            w.rot_index = cv.take((size_t)w.nlines * sizeof(int32_t));
+            w.rot = cv.take((size_t)w.nlines * sizeof(RotEntry));
+            w.rot_count = cv.take(sizeof(uint32_t));
+            take_recs(cv, 4 * w.nlines, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
+        }
+    }
+    if (nrot > 1 || (nrot == 1 && ns > 1)) return FQ_EUNSUPPORTED;
+    const int njobs = ns + nrot;
+    const size_t off_jobs = cv.take((size_t)njobs * sizeof(TraceJob));
+    // FP64 pass of the FP32 form: re-trace list, its counter, and FP64 node records
+    // when a field is stored in FP64 (FP32 records of an FP32 field are exact)
+    const bool fixup = P.precision == FQ_PREC_F32X && P.graze > 0;
+    int fix_store = FQ_DT_F32;
+    for (int i = 0; i < ns; i++)
+        if (specs[i].f->dtype == FQ_DT_F64) fix_store = FQ_DT_F64;
+    int64_t all_lines = 0;
+    for (int i = 0; i < ns; i++) all_lines += W[i].nlines * (W[i].rotate ? 5 : 1);
+    size_t off_list = 0, off_lcount = 0, off_jobs64 = 0;
+    if (fixup) {
+        off_list = cv.take((size_t)(2 * all_lines) * sizeof(FixEntry));
+        off_lcount = cv.take(sizeof(uint32_t));
+        if (fix_store == FQ_DT_F64) {
+            off_jobs64 = cv.take((size_t)njobs * sizeof(TraceJob));
+            for (int i = 0; i < ns; i++) {
+                const int64_t nn = nodes_of(specs[i].f);
+                W[i].nodeA64 = cv.take((size_t)nn * 4 * 8);
+                W[i].nodeC64 = P.want_tw ? cv.take((size_t)nn * 2 * 8) : 0;
+            }
+        }
+    }
+    if (need) *need = cv.off;
+    if (dry) return FQ_OK;
+    if (!ws) return FQ_EINVAL;
+    if (ws_bytes < cv.off) return FQ_ENOMEM;
+    if (((uintptr_t)ws & 255) != 0) return FQ_EINVAL;
+
+    hipError_t e = hipSuccess;
+#define FQ_TRY(x)                      \
+    do {                               \
+        e = (x);                       \
+        if (e != hipSuccess) return FQ_EHIP; \
+    } while (0)
+
+    unsigned long long *counter = (unsigned long long *)(ws + off_ctr);
+    FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 4, 0u, stream));
+    for (int i = 0; i < ns; i++) {
+        const Spec &s = specs[i];
+        SpecWs &w = W[i];
+        FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.bmax), 1, 0u, stream));
+        if (w.rotate) FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.rot_count), 1, 0u, stream));
+        FQ_TRY(launch_prep(*s.f, P.precision, P.want_tw, ws + w.nodeA, P.want_tw ? ws + w.nodeC : nullptr,
+                           (float *)(ws + w.bmax), stream));
+        if (fixup && fix_store == FQ_DT_F64)
+            FQ_TRY(launch_prep(*s.f, FQ_PREC_F64, P.want_tw, ws + w.nodeA64,
+                               P.want_tw ? ws + w.nodeC64 : nullptr, (float *)(ws + w.bmax), stream));
+    }
+    // rotated-S0 classification (only for a single map)
+    std::vector<MapJob> maps(ns);
+    for (int i = 0; i < ns; i++) {
+        const Spec &s = specs[i];
+        SpecWs &w = W[i];
+        MapJob &m = maps[i];
+        memset(&m, 0, sizeof m);
+        set_map_geometry(s, m);
+        m.edge_eps = P.edge_eps;
+        m.rec = recs_at(ws, w.end, w.tw, w.len, w.face, w.st);
+        m.nlines = w.nlines;
+        if (s.kind != SPEC_LIST && s.map) m.out = *s.map;
+        if (s.kind == SPEC_LIST && s.lines) m.out.lines = *s.lines;
+        if (w.rotate) {
+            m.rot_index = (const int32_t *)(ws + w.rot_index);
+            m.rot = (const RotEntry *)(ws + w.rot);
+            m.rot_rec = recs_at(ws, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
+            m.rot_nlines = 4 * w.nlines;
+            m.rot_delta = fmin(m.d0, m.d1);
+            FQ_TRY(launch_classify(m, (int32_t *)(ws + w.rot_index), (RotEntry *)(ws + w.rot),
+                                   (uint32_t *)(ws + w.rot_count), w.nlines, stream));
+        }
+    }
+    // job table
+    std::vector<TraceJob> jobs(njobs);
+    int64_t items = 0;
+    int jj = 0;
+    for (int i = 0; i < ns; i++) {
+        const Spec &s = specs[i];
+        SpecWs &w = W[i];
+        TraceJob &J = jobs[jj++];
+        memset(&J, 0, sizeof J);
+        J.nodeA = ws + w.nodeA;
+        J.nodeC = P.want_tw ? ws + w.nodeC : nullptr;
+        J.bmax2 = (const float *)(ws + w.bmax);
+        for (int a = 0; a < 3; a++) {
+            J.n[a] = (int32_t)s.f->n[a];
+            J.origin[a] = s.f->origin[a];
+            J.spacing[a] = s.f->spacing[a];
+            J.normal[a] = s.normal[a];
+        }
+        J.nlines = w.nlines;
+        J.rec = recs_at(ws, w.end, w.tw, w.len, w.face, w.st);
+        for (int a = 0; a < 3; a++) {
+            J.planes.b[a] = s.f->b[a];
+            J.planes.n[a] = (int32_t)s.f->n[a];
+            J.planes.origin[a] = s.f->origin[a];
+            J.planes.spacing[a] = s.f->spacing[a];
+        }
+        J.planes.dtype = s.f->dtype;
+        if (s.kind == SPEC_LIST) {
+            J.kind = SEED_LIST;
+            J.seeds = s.seeds;
+            J.tile[0] = 64, J.tile[1] = 1, J.tile[2] = 1;
+            J.dims[0] = s.nlist, J.dims[1] = 1, J.dims[2] = 1;
+        } else if (s.kind == SPEC_PLANE) {
+            J.kind = SEED_PLANE;
+            J.tile[0] = 8, J.tile[1] = 8, J.tile[2] = 1;
+            J.dims[0] = s.pl.nu, J.dims[1] = s.pl.nv, J.dims[2] = 1;
+            for (int a = 0; a < 3; a++) {
+                J.s_origin[a] = s.pl.origin[a];
+                J.s_a[a] = s.pl.du * s.pl.u[a];
+                J.s_b[a] = s.pl.dv * s.pl.v[a];
+            }
+        } else {
+            J.kind = SEED_VOXELS;
+            J.tile[0] = 4, J.tile[1] = 4, J.tile[2] = 4;
+            for (int a = 0; a < 3; a++) {
+                J.dims[a] = s.vx.n[a];
+                J.s_origin[a] = s.vx.origin[a];
+            }
+            J.s_a[0] = s.vx.spacing[0];
+            J.s_b[1] = s.vx.spacing[1];
+            J.s_c[2] = s.vx.spacing[2];
+        }
+        int64_t tv = 1;
+        for (int a = 0; a < 3; a++) {
+            J.tiles[a] = (J.dims[a] + J.tile[a] - 1) / J.tile[a];
+            tv *= J.tiles[a] * J.tile[a];
+        }
+        J.nitems = tv;
+        J.item_base = items;
+        items += 2 * tv;
+    }
+    TraceParams tp;
+    memset(&tp, 0, sizeof tp);
+    for (int i = 0; i < ns; i++) {
+        if (!W[i].rotate) continue;
+        const SpecWs &w = W[i];
+        TraceJob &J = jobs[jj++];
+        J = jobs[i];
+        J.kind = SEED_ROTATED;
+        J.seeds = nullptr;
+        J.rot = (const RotEntry *)(ws + w.rot);
+        J.rot_count = (const uint32_t *)(ws + w.rot_count);
+        J.rot_delta = maps[i].rot_delta;
+        J.nlines = 4 * w.nlines;
+        J.tile[0] = 64, J.tile[1] = 1, J.tile[2] = 1;
+        J.dims[0] = 4 * w.nlines, J.dims[1] = 1, J.dims[2] = 1;
+        J.tiles[0] = (J.dims[0] + 63) / 64, J.tiles[1] = 1, J.tiles[2] = 1;
+        J.nitems = J.tiles[0] * 64;
+        J.rec = recs_at(ws, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
+        J.item_base = items;
+        tp.dynamic_last = 1;
+    }
+    TraceJob *jobs_dev = (TraceJob *)(ws + off_jobs);
+    for (int j = 0; j < njobs; j++) FQ_TRY(launch_store_job(jobs[j], jobs_dev + j, stream));
+    tp.tol_perp = P.tol_perp;
+    tp.step_perp = P.step_perp;
+    tp.step_min = P.step_min;
+    tp.tol_floor = P.tol_floor;
+    tp.max_steps = P.max_steps;
+    tp.want_tw = P.want_tw;
+    tp.njobs = njobs;
+    tp.stats = (unsigned long long *)P.stats;
+    tp.static_items = items;
+    FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
+                        jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
+    if (fixup) {
+        // FP64 pass over the grazing lines of the FP32 pass
+        FixEntry *list = (FixEntry *)(ws + off_list);
+        uint32_t *lcount = (uint32_t *)(ws + off_lcount);
+        FQ_TRY(launch_fill_u32(lcount, 1, 0u, stream));
+        FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 2, 0u, stream));
+        for (int j = 0; j < njobs; j++)
+            FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, list, lcount, 2 * all_lines,
+                                stream));
+        const TraceJob *fix_jobs = jobs_dev;
+        if (fix_store == FQ_DT_F64) {
+            TraceJob *j64 = (TraceJob *)(ws + off_jobs64);
+            int k = 0;
+            for (int i = 0; i < ns; i++) {
+                TraceJob J = jobs[i];
+                J.nodeA = ws + W[i].nodeA64;
+                J.nodeC = P.want_tw ? ws + W[i].nodeC64 : nullptr;
+                FQ_TRY(launch_store_job(J, j64 + k++, stream));
+            }
+            for (int i = 0; i < ns; i++) {
+                if (!W[i].rotate) continue;
+                TraceJob J = jobs[k];
+                J.nodeA = ws + W[i].nodeA64;
+                J.nodeC = P.want_tw ? ws + W[i].nodeC64 : nullptr;
+                FQ_TRY(launch_store_job(J, j64 + k++, stream));
+            }
+            fix_jobs = j64;
+        }
+        TraceParams fp = tp;
+        fp.list = list;
+        fp.list_count = lcount;
+        fp.list_cap = 2 * all_lines;
+        FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw, fix_jobs, fp, counter, P.block,
+                            P.waves_per_cu, stream));
+    }
+    for (int i = 0; i < ns; i++) {
+        if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));
+        else FQ_TRY(launch_stencil(maps[i], stream));
+    }
+#undef FQ_TRY
+    return FQ_OK;
+}
+
+void plane_normal(const fq_plane &p, double n[3])
+{
+    n[0] = p.u[1] * p.v[2] - p.u[2] * p.v[1];
+    n[1] = p.u[2] * p.v[0] - p.u[0] * p.v[2];
+    n[2] = p.u[0] * p.v[1] - p.u[1] * p.v[0];
+}
+
+int q2d_specs(const fq_field *fields, const fq_plane *planes, int njobs, const fq_map *maps,
+              std::vector<Spec> &specs)
+{
+    if (njobs < 1 || !fields || !planes) return FQ_EINVAL;
+    specs.resize(njobs);
+    for (int j = 0; j < njobs; j++) {
+        int rc = check_field(&fields[j]);
+        if (rc) return rc;
+        if ((rc = check_plane(&planes[j]))) return rc;
+        Spec &s = specs[j];
+        memset(&s, 0, sizeof s);
+        s.kind = SPEC_PLANE;
+        s.f = &fields[j];
+        s.pl = planes[j];
+        plane_normal(planes[j], s.normal);
+        s.map = maps ? &maps[j] : nullptr;
+    }
+    return FQ_OK;
+}
+
+}  // namespace
+}  // namespace fq
+
+using namespace fq;
+
+extern "C" {
+
+const char *fastqsl_version(void) { return "fastqsl-mi355x 0.1 (gfx950)"; }
+
+const char *fastqsl_strerror(int code)
+{
+    switch (code) {
+    case FQ_OK: return "ok";
+    case FQ_EINVAL: return "invalid argument";
+    case FQ_ENOMEM: return "workspace too small";
+    case FQ_EHIP: return "HIP launch failed";
+    case FQ_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown error";
+    }
+}
+
+size_t fastqsl_trace_workspace_size(const fq_field *f, int64_t n, const fq_params *p)
+{
+    fq_params P;
+    if (resolve_params(p, P) || check_field(f) || n < 0) return 0;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_LIST;
+    s.f = f;
+    s.nlist = n;
+    std::vector<Spec> v(1, s);
+    size_t need = 0;
+    run(v, P, nullptr, 0, true, &need, nullptr);
+    return need;
+}
+
+int fastqsl_trace(const fq_field *f, const double *seeds, int64_t n, const double *normal,
+                  const fq_params *p, const fq_lines *out, void *ws, size_t ws_bytes,
+                  void *stream)
+{
+    fq_params P;
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if ((rc = check_field(f))) return rc;
+    if (n < 0 || (n > 0 && !seeds) || !out) return FQ_EINVAL;
+    if (n == 0) return FQ_OK;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_LIST;
+    s.f = f;
+    s.seeds = seeds;
+    s.nlist = n;
+    s.lines = out;
+    if (normal) {
+        double nn = sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
+        if (!(nn > 0.0) || !isfinite(nn)) return FQ_EINVAL;
+        for (int a = 0; a < 3; a++) s.normal[a] = normal[a] / nn;
+    } else {
+        s.normal[2] = 1.0;
+    }
+    std::vector<Spec> v(1, s);
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream);
+}
+
+size_t fastqsl_q2d_workspace_size(const fq_field *fields, const fq_plane *planes, int njobs,
+                                  const fq_params *p)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    if (resolve_params(p, P) || q2d_specs(fields, planes, njobs, nullptr, v)) return 0;
+    size_t need = 0;
+    if (run(v, P, nullptr, 0, true, &need, nullptr)) return 0;
+    return need;
+}
+
+int fastqsl_q2d(const fq_field *fields, const fq_plane *planes, int njobs, const fq_params *p,
+                const fq_map *maps, void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if (!maps) return FQ_EINVAL;
+    std::vector<Spec> v;
+    if ((rc = q2d_specs(fields, planes, njobs, maps, v))) return rc;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream);
+}
+
+size_t fastqsl_q3d_workspace_size(const fq_field *f, const fq_voxels *vx, const fq_params *p)
+{
+    fq_params P;
+    if (resolve_params(p, P) || check_field(f) || check_voxels(vx)) return 0;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_VOXELS;
+    s.f = f;
+    s.vx = *vx;
+    s.normal[2] = 1.0;
+    std::vector<Spec> v(1, s);
+    size_t need = 0;
+    run(v, P, nullptr, 0, true, &need, nullptr);
+    return need;
+}
+
+int fastqsl_q3d(const fq_field *f, const fq_voxels *vx, const fq_params *p, const fq_map *map,
+                void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if ((rc = check_field(f)) || (rc = check_voxels(vx))) return rc;
+    if (!map) return FQ_EINVAL;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_VOXELS;
+    s.f = f;
+    s.vx = *vx;
+    s.normal[2] = 1.0;
+    s.map = map;
+    std::vector<Spec> v(1, s);
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream);
+}
+
+size_t fastqsl_backward_workspace_size(const fq_field *f, const fq_plane *pl, const fq_params *p,
+                                       int segment)
+{
+    (void)f;
+    (void)pl;
+    (void)p;
+    (void)segment;
+    return 0;
+}
+
+int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
+                     const double *dq, const double *dtw, const double *dend_b,
+                     const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    (void)f, (void)pl, (void)p, (void)segment, (void)dq, (void)dtw, (void)dend_b, (void)dend_f;
+    (void)gb, (void)ws, (void)ws_bytes, (void)stream;
+    return FQ_EUNSUPPORTED;
+}
+
+}  // extern "C"

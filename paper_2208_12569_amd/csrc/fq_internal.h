@@ -1,0 +1,128 @@
+// Internal definitions shared by the library's translation units (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fastqsl.h"
+#include "field64.h"
+
+namespace fq {
+
+// How a trace job enumerates its seeds.
+enum SeedKind : int32_t {
+    SEED_LIST = 0,    // explicit device array of n x 3 doubles
+    SEED_PLANE = 1,   // origin + i a + j b   (a = du u, b = dv v)
+    SEED_VOXELS = 2,  // origin + i a + j b + k c (a, b, c along the axes)
+    SEED_ROTATED = 3, // r0 +- delta U, r0 +- delta V of the rotated-S0 list
+};
+
+// One rotated-S0 point: its map index, centre and in-plane unit vectors.
+struct RotEntry {
+    int64_t point;
+    double r0[3];
+    double U[3];
+    double V[3];
+};
+
+// Half-line records written by the tracer. Half 0 runs against B (backward),
+// half 1 along it (forward); record (half, line) is at half * nlines + line.
+struct HalfRecs {
+    double *end;   // 2 * nlines * 3
+    double *tw;    // 2 * nlines
+    double *len;   // 2 * nlines
+    int8_t *face;  // 2 * nlines
+    uint16_t *st;  // 2 * nlines
+};
+
+// One independent tracing job: a prepared field plus a seed set.
+struct TraceJob {
+    const void *nodeA;   // per node (Bx, By, Bz, Jx) in the compute type
+    const void *nodeC;   // per node (Jy, Jz)
+    const float *bmax2;  // max |B|^2 over the nodes (float, written by the prep pass)
+    int32_t n[3];
+    int32_t kind;
+    double origin[3];
+    double spacing[3];
+    // seeds
+    int32_t tile[3];     // seeds per tile along each seed axis (tile volume <= 64)
+    int32_t pad;
+    int64_t dims[3];     // seed grid extents (list: n,1,1; rotated: 4*capacity,1,1)
+    int64_t tiles[3];    // tiles along each seed axis
+    int64_t nitems;      // queue items per half = tiles volume * tile volume
+    int64_t nlines;      // output lines of the job
+    double s_origin[3];
+    double s_a[3], s_b[3], s_c[3];
+    double normal[3];    // S0 normal (Eq. step / Eq. tol scaling)
+    const double *seeds;          // SEED_LIST
+    const RotEntry *rot;          // SEED_ROTATED
+    const uint32_t *rot_count;    // SEED_ROTATED: number of valid entries
+    double rot_delta;             // SEED_ROTATED: distance of the extra seeds
+    HalfRecs rec;
+    int64_t item_base;   // first queue item of the job (items of both halves follow)
+    Planes64 planes;     // the caller's field, for FP64 angles in the grazing test
+};
+
+// One half line to trace again (FP64 pass).
+struct FixEntry {
+    int32_t job;
+    int32_t half;  // 0 backward, 1 forward
+    int64_t line;
+};
+
+struct TraceParams {
+    double tol_perp, step_perp, step_min, tol_floor;
+    int64_t max_steps;
+    int32_t want_tw;
+    int32_t njobs;
+    int64_t static_items;          // queue items of all jobs except a trailing rotated job
+    int32_t dynamic_last;          // 1 if the last job is SEED_ROTATED (items known on device)
+    int32_t pad;
+    unsigned long long *stats;     // optional counters (trials, accepted, fetches, halves, FP64 halves)
+    const FixEntry *list;          // list mode: trace exactly these half lines
+    const uint32_t *list_count;
+    int64_t list_cap;
+};
+
+// Host-side launchers, one per translation unit.
+hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodeA, void *nodeC,
+                       float *bmax2, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
+// prec: compute type (FQ_PREC_F32X = float, FQ_PREC_F64 = double);
+// store: node-record type (FQ_DT_F32 / FQ_DT_F64).
+hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_dev,
+                        const TraceParams &tp, unsigned long long *counter, int block,
+                        int waves_per_cu, hipStream_t s);
+hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
+                        FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s);
+
+// Map assembly (Q stencil) of one layer-structured map.
+struct MapJob {
+    const void *b[3];     // input planes (original dtype) for FP64 B_n
+    int32_t dtype;
+    int32_t n[3];
+    double origin[3], spacing[3];
+    int64_t nu, nv, nlayers;     // points per layer = nu*nv
+    double d0, d1;               // seed spacing along the two S0 axes
+    double normal[3];            // S0 normal
+    double p_origin[3], p_a[3], p_b[3], p_c[3]; // point(i,j,k) = origin + i a + j b + k c
+    int32_t on_face;             // every seed lies on a box face (no rotation)
+    int32_t pad;
+    double edge_eps;
+    HalfRecs rec;                // records of the map's own lines (nlines = points)
+    int64_t nlines;
+    const int32_t *rot_index;    // per point: index in the rotated list or -1 (may be NULL)
+    const RotEntry *rot;
+    HalfRecs rot_rec;            // records of the rotated extras (4 per entry)
+    int64_t rot_nlines;
+    double rot_delta;
+    fq_map out;
+};
+
+hipError_t launch_classify(const MapJob &m, int32_t *rot_index, RotEntry *rot,
+                           uint32_t *rot_count, int64_t rot_capacity, hipStream_t s);
+hipError_t launch_stencil(const MapJob &m, hipStream_t s);
+hipError_t launch_lines_out(const MapJob &m, const double *seeds_list, hipStream_t s);
+
+}  // namespace fq

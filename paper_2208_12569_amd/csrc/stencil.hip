@@ -1,0 +1,370 @@
+// Method-I map assembly in FP64.
+//
+// From the traced half lines, each map point gets the Jacobians of both end maps by
+// differences over its neighbouring seeds and Q = (a^2+b^2+c^2+d^2)/|Bn1/Bn2| with
+// D12 = D20 (D10)^-1 (Section 2.1, Eq. D+-2 and Eq. D+-3; Section 1, Eq. Q+- and
+// Eq. Bn1). Written as Q = ||J2 adj(J1)||_F^2 |Bn1 Bn2| / Bn0^2, which is the same
+// quantity: (D10)^-1 = adj(J1) / |Bn0/Bn1| and |det D12| -> |Bn1/Bn2|.
+//
+// Every normal field Bn0, Bn1, Bn2 is interpolated in FP64 from the caller's planes
+// (the FP64 fix-up of the FP32 form): a near-tangent seed has |Bn0| << |B| and an
+// FP32 value would cost Q its accuracy there.
+//
+// Stencil rule: central differences along an S0 axis where both neighbours end on
+// the centre line's faces at both ends; else a one-sided difference with the
+// neighbour that does (FQ_ST_ONESIDED); else Q = NaN (FQ_ST_MIXEDFACE, the case
+// Code2016 returns NaN for, Section 2.1). For a seed on a box face one half line
+// has zero length and ends at the seed; that end is taken as S1, whatever the
+// polarity, so that seeds on both sides of a polarity inversion line difference the
+// same seed -> far-footpoint map.
+#include <math.h>
+
+#include "fq_internal.h"
+
+namespace fq {
+namespace {
+
+constexpr uint16_t kFatal = FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_MAXSTEPS | FQ_ST_NONFINITE;
+
+__device__ __forceinline__ void field64(const MapJob &m, const double r[3], double B[3])
+{
+    Planes64 P;
+    for (int a = 0; a < 3; a++) {
+        P.b[a] = m.b[a];
+        P.n[a] = m.n[a];
+        P.origin[a] = m.origin[a];
+        P.spacing[a] = m.spacing[a];
+    }
+    P.dtype = m.dtype;
+    interp64(P, r, B);
+}
+
+// One line read back from the half records, with its ends ordered as S1, S2.
+struct Line {
+    double e1[3], e2[3];
+    int f1, f2;
+    uint16_t st;
+    double tw, len;
+    bool swapped;  // S1 is the forward end
+};
+
+__device__ void read_line(const HalfRecs &R, int64_t nlines, int64_t l, Line &L)
+{
+    const int64_t hb = l, hf = nlines + l;
+    const double lb = R.len[hb], lf = R.len[hf];
+    L.st = R.st[hb] | R.st[hf];
+    L.tw = R.tw[hb] + R.tw[hf];
+    L.len = lb + lf;
+    L.swapped = (lf == 0.0 && lb != 0.0);
+    const int64_t s1 = L.swapped ? hf : hb, s2 = L.swapped ? hb : hf;
+    for (int a = 0; a < 3; a++) {
+        L.e1[a] = R.end[3 * s1 + a];
+        L.e2[a] = R.end[3 * s2 + a];
+    }
+    L.f1 = R.face[s1];
+    L.f2 = R.face[s2];
+}
+
+__device__ __forceinline__ void inface(int face, const double e[3], double uv[2])
+{
+    const int a = face >> 1;
+    uv[0] = e[a == 0 ? 1 : 0];
+    uv[1] = e[a == 2 ? 1 : 2];
+}
+
+__device__ bool edge_end(const MapJob &m, int face, const double e[3])
+{
+    if (face < 0) return false;
+    const int a = face >> 1;
+    for (int b = 0; b < 3; b++) {
+        if (b == a) continue;
+        const double lo = m.origin[b], hi = m.origin[b] + (m.n[b] - 1) * m.spacing[b];
+        if (e[b] - lo < m.edge_eps || hi - e[b] < m.edge_eps) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool usable(const Line &c, const Line &o)
+{
+    return !(o.st & kFatal) && o.f1 == c.f1 && o.f2 == c.f2;
+}
+
+// derivatives of (u1, v1) and (u2, v2) along one S0 axis; false if no neighbour fits
+__device__ bool axis_diff(const Line &c, const Line *m, const Line *p, double d, double d1[2],
+                          double d2[2], uint16_t &st)
+{
+    const bool um = m && usable(c, *m), up = p && usable(c, *p);
+    double c1[2], c2[2], a1[2], a2[2], b1[2], b2[2];
+    inface(c.f1, c.e1, c1);
+    inface(c.f2, c.e2, c2);
+    if (um) {
+        inface(m->f1, m->e1, a1);
+        inface(m->f2, m->e2, a2);
+    }
+    if (up) {
+        inface(p->f1, p->e1, b1);
+        inface(p->f2, p->e2, b2);
+    }
+    if (um && up) {
+        const double s = 0.5 / d;
+        for (int q = 0; q < 2; q++) {
+            d1[q] = (b1[q] - a1[q]) * s;
+            d2[q] = (b2[q] - a2[q]) * s;
+        }
+        return true;
+    }
+    if (up || um) {
+        const double s = 1.0 / d;
+        for (int q = 0; q < 2; q++) {
+            d1[q] = up ? (b1[q] - c1[q]) * s : (c1[q] - a1[q]) * s;
+            d2[q] = up ? (b2[q] - c2[q]) * s : (c2[q] - a2[q]) * s;
+        }
+        st |= FQ_ST_ONESIDED;
+        return true;
+    }
+    return false;
+}
+
+// Q from the centre line and its four S0 neighbours (any may be null).
+__device__ double q_of(const MapJob &m, const Line &c, const Line *xm, const Line *xp,
+                       const Line *ym, const Line *yp, double d0, double d1, double bn0,
+                       uint16_t &st)
+{
+    double ax1[2], ax2[2], ay1[2], ay2[2];
+    if (!axis_diff(c, xm, xp, d0, ax1, ax2, st) || !axis_diff(c, ym, yp, d1, ay1, ay2, st)) {
+        st |= FQ_ST_MIXEDFACE;
+        return NAN;
+    }
+    // J1 = [[du1/dx0, du1/dy0], [dv1/dx0, dv1/dy0]], likewise J2
+    const double j00 = ax1[0], j01 = ay1[0], j10 = ax1[1], j11 = ay1[1];
+    const double k00 = ax2[0], k01 = ay2[0], k10 = ax2[1], k11 = ay2[1];
+    // M = J2 adj(J1), adj(J1) = [[j11, -j01], [-j10, j00]]
+    const double m00 = k00 * j11 - k01 * j10;
+    const double m01 = -k00 * j01 + k01 * j00;
+    const double m10 = k10 * j11 - k11 * j10;
+    const double m11 = -k10 * j01 + k11 * j00;
+    double B1[3], B2[3];
+    field64(m, c.e1, B1);
+    field64(m, c.e2, B2);
+    const double bn1 = B1[c.f1 >> 1], bn2 = B2[c.f2 >> 1];
+    const double nrm = m00 * m00 + m01 * m01 + m10 * m10 + m11 * m11;
+    return nrm * fabs(bn1 * bn2) / (bn0 * bn0);
+}
+
+__device__ void point_pos(const MapJob &m, int64_t i, int64_t j, int64_t k, double r[3])
+{
+    for (int a = 0; a < 3; a++)
+        r[a] = m.p_origin[a] + (double)i * m.p_a[a] + (double)j * m.p_b[a] + (double)k * m.p_c[a];
+}
+
+__device__ bool on_box_face(const MapJob &m, const double r[3])
+{
+    for (int a = 0; a < 3; a++) {
+        const double tol = 1e-12 * m.spacing[a];
+        const double lo = m.origin[a], hi = m.origin[a] + (m.n[a] - 1) * m.spacing[a];
+        if (fabs(r[a] - lo) <= tol || fabs(hi - r[a]) <= tol) return true;
+    }
+    return false;
+}
+
+__global__ void classify_kernel(MapJob m, int32_t *rot_index, RotEntry *rot,
+                                uint32_t *rot_count, int64_t capacity)
+{
+    const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        int32_t idx = -1;
+        const int64_t k = pt / lay, r2 = pt - k * lay, j = r2 / m.nu, i = r2 - j * m.nu;
+        double r[3];
+        point_pos(m, i, j, k, r);
+        bool inside = true;
+        for (int a = 0; a < 3; a++) {
+            const double lo = m.origin[a], hi = m.origin[a] + (m.n[a] - 1) * m.spacing[a];
+            if (!(r[a] >= lo && r[a] <= hi)) inside = false;
+        }
+        if (inside && !on_box_face(m, r)) {
+            double B[3];
+            field64(m, r, B);
+            const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            const double bn = B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
+            if (bm > 0.0 && fabs(bn) < 0.05 * bm) {
+                // Section 4: rotate S0 perpendicular to the line
+                const double b[3] = {B[0] / bm, B[1] / bm, B[2] / bm};
+                int a = 0;
+                if (fabs(b[1]) < fabs(b[a])) a = 1;
+                if (fabs(b[2]) < fabs(b[a])) a = 2;
+                double ea[3] = {0.0, 0.0, 0.0};
+                ea[a] = 1.0;
+                double U[3] = {ea[1] * b[2] - ea[2] * b[1], ea[2] * b[0] - ea[0] * b[2],
+                               ea[0] * b[1] - ea[1] * b[0]};
+                const double un = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+                for (int q = 0; q < 3; q++) U[q] /= un;
+                const double V[3] = {b[1] * U[2] - b[2] * U[1], b[2] * U[0] - b[0] * U[2],
+                                     b[0] * U[1] - b[1] * U[0]};
+                const uint32_t slot = atomicAdd(rot_count, 1u);
+                if ((int64_t)slot < capacity) {
+                    RotEntry &e = rot[slot];
+                    e.point = pt;
+                    for (int q = 0; q < 3; q++) {
+                        e.r0[q] = r[q];
+                        e.U[q] = U[q];
+                        e.V[q] = V[q];
+                    }
+                    idx = (int32_t)slot;
+                } else {
+                    idx = -2;  // over capacity: no Q at this point
+                }
+            }
+        }
+        rot_index[pt] = idx;
+    }
+}
+
+__device__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const double seed[3])
+{
+    const int64_t hb = l, hf = m.nlines + l;
+    uint16_t st = m.rec.st[hb] | m.rec.st[hf];
+    double eb[3], ef[3];
+    for (int a = 0; a < 3; a++) {
+        eb[a] = m.rec.end[3 * hb + a];
+        ef[a] = m.rec.end[3 * hf + a];
+    }
+    const int fb = m.rec.face[hb], ff = m.rec.face[hf];
+    if (edge_end(m, fb, eb) || edge_end(m, ff, ef)) st |= FQ_ST_EDGE;
+    const bool bad = (st & kFatal) != 0;
+    if (o.end_b)
+        for (int a = 0; a < 3; a++) o.end_b[3 * l + a] = eb[a];
+    if (o.end_f)
+        for (int a = 0; a < 3; a++) o.end_f[3 * l + a] = ef[a];
+    if (o.face_b) o.face_b[l] = (int8_t)fb;
+    if (o.face_f) o.face_f[l] = (int8_t)ff;
+    if (o.bn_b || o.bn_f || o.bn0) {
+        double B[3];
+        if (o.bn_b) {
+            if (fb >= 0) {
+                field64(m, eb, B);
+                o.bn_b[l] = B[fb >> 1];
+            } else o.bn_b[l] = NAN;
+        }
+        if (o.bn_f) {
+            if (ff >= 0) {
+                field64(m, ef, B);
+                o.bn_f[l] = B[ff >> 1];
+            } else o.bn_f[l] = NAN;
+        }
+        if (o.bn0) {
+            if (st & FQ_ST_OUTSIDE) o.bn0[l] = NAN;
+            else {
+                field64(m, seed, B);
+                o.bn0[l] = B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
+            }
+        }
+    }
+    if (o.tw) o.tw[l] = bad ? NAN : m.rec.tw[hb] + m.rec.tw[hf];
+    if (o.length) o.length[l] = bad ? NAN : m.rec.len[hb] + m.rec.len[hf];
+    if (o.status) o.status[l] = st;
+}
+
+__global__ void stencil_kernel(MapJob m)
+{
+    const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = pt / lay, r2 = pt - k * lay, j = r2 / m.nu, i = r2 - j * m.nu;
+        double r0[3];
+        point_pos(m, i, j, k, r0);
+        Line c;
+        read_line(m.rec, m.nlines, pt, c);
+        uint16_t st = c.st;
+        if (edge_end(m, c.f1, c.e1) || edge_end(m, c.f2, c.e2)) st |= FQ_ST_EDGE;
+        double q = NAN, tw = NAN, len = NAN;
+        if (!(c.st & kFatal)) {
+            tw = c.tw;
+            len = c.len;
+            const int32_t ri = m.rot_index ? m.rot_index[pt] : -1;
+            if (ri >= 0) {
+                Line nb[4];
+                for (int w = 0; w < 4; w++) {
+                    read_line(m.rot_rec, m.rot_nlines, 4 * (int64_t)ri + w, nb[w]);
+                    if (edge_end(m, nb[w].f1, nb[w].e1) || edge_end(m, nb[w].f2, nb[w].e2))
+                        st |= FQ_ST_EDGE;
+                }
+                double B[3];
+                field64(m, r0, B);
+                const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                st |= FQ_ST_ROTATED;
+                q = q_of(m, c, &nb[0], &nb[1], &nb[2], &nb[3], m.rot_delta, m.rot_delta, bm, st);
+            } else if (ri == -2) {
+                st |= FQ_ST_ROTATED | FQ_ST_MIXEDFACE;
+            } else {
+                Line xm, xp, ym, yp;
+                const bool hxm = i > 0, hxp = i < m.nu - 1, hym = j > 0, hyp = j < m.nv - 1;
+                if (hxm) read_line(m.rec, m.nlines, pt - 1, xm);
+                if (hxp) read_line(m.rec, m.nlines, pt + 1, xp);
+                if (hym) read_line(m.rec, m.nlines, pt - m.nu, ym);
+                if (hyp) read_line(m.rec, m.nlines, pt + m.nu, yp);
+                const Line *nbs[4] = {hxm ? &xm : nullptr, hxp ? &xp : nullptr,
+                                      hym ? &ym : nullptr, hyp ? &yp : nullptr};
+                for (int w = 0; w < 4; w++)
+                    if (nbs[w] && (edge_end(m, nbs[w]->f1, nbs[w]->e1) ||
+                                   edge_end(m, nbs[w]->f2, nbs[w]->e2)))
+                        st |= FQ_ST_EDGE;
+                double B[3];
+                field64(m, r0, B);
+                const double bn0 = B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
+                q = q_of(m, c, nbs[0], nbs[1], nbs[2], nbs[3], m.d0, m.d1, bn0, st);
+            }
+        }
+        if (m.out.q) m.out.q[pt] = q;
+        if (m.out.tw) m.out.tw[pt] = tw;
+        if (m.out.length) m.out.length[pt] = len;
+        if (m.out.status) m.out.status[pt] = st;
+        const fq_lines &o = m.out.lines;
+        if (o.end_b || o.end_f || o.face_b || o.face_f || o.bn_b || o.bn_f || o.bn0 || o.tw ||
+            o.length || o.status)
+            write_line(m, o, pt, r0);
+    }
+}
+
+__global__ void lines_kernel(MapJob m, const double *seeds)
+{
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < m.nlines;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const double s[3] = {seeds[3 * l], seeds[3 * l + 1], seeds[3 * l + 2]};
+        write_line(m, m.out.lines, l, s);
+    }
+}
+
+unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_classify(const MapJob &m, int32_t *rot_index, RotEntry *rot,
+                           uint32_t *rot_count, int64_t capacity, hipStream_t s)
+{
+    const int64_t np = m.nu * m.nv * m.nlayers;
+    hipLaunchKernelGGL(classify_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m, rot_index, rot,
+                       rot_count, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_stencil(const MapJob &m, hipStream_t s)
+{
+    const int64_t np = m.nu * m.nv * m.nlayers;
+    hipLaunchKernelGGL(stencil_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_lines_out(const MapJob &m, const double *seeds, hipStream_t s)
+{
+    hipLaunchKernelGGL(lines_kernel, dim3(blocks_for(m.nlines)), dim3(256), 0, s, m, seeds);
+    return hipGetLastError();
+}
+
+}  // namespace fq

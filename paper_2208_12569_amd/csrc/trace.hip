@@ -1,0 +1,433 @@
+// Persistent field-line tracer for gfx950.
+//
+// One lane traces one half line (a seed followed along B or against it) through the
+// trilinear field (Section 2.2, Eq. interp) by adaptive RKF45 steps (Section 2.3,
+// Fehlberg's 4(5) pair) of dr/ds = B/|B| (Section 2.1, Eq. rb), with the twist
+// integrand of Eq. tw (Section 1) and the length as two more ODE components, until
+// the line leaves the box (Section 2.1).
+//
+// Design for CDNA:
+//  * Cell-resident interpolation. Inside one grid cell the trilinear interpolant is
+//    a polynomial; a lane keeps the current cell's 8 monomial coefficients of
+//    B (and of curl B) in VGPRs, so the six RK stages of a step gather nothing.
+//    A cell is fetched once per visit: 8 + 8 vector loads of the node records
+//    written by the prep pass.
+//  * Cell-local coordinates. Position = integer cell + local coordinates in [0,1];
+//    FP32 local coordinates keep an absolute resolution of ~1e-7 grid spacings
+//    anywhere in a cube of any size, so FP32 integration does not lose the
+//    footpoint accuracy to the size of the box.
+//  * Exact face landing. Every step stays inside the closed cell (the interpolant
+//    has a kink on every cell face, which would otherwise cost the integrator its
+//    order). A step that reaches a face is taken with the coordinate normal to that
+//    face as the independent variable, so it ends exactly on the face; the line then
+//    continues in the neighbouring cell, or ends if the face is a box face.
+//  * Persistent lanes and a global queue. Line lengths differ by orders of
+//    magnitude; a lane that finishes pops the next half line from a global counter
+//    (one atomic per wave via a ballot), so waves never idle on their longest line.
+//    Queue items follow 64-seed tiles, so the lanes of a wave start on neighbouring
+//    seeds and read neighbouring cells.
+#include "fq_internal.h"
+#include "trace_core.h"
+
+namespace fq {
+namespace {
+
+template <typename T> struct V4;
+template <> struct V4<float> { using t = float4; };
+template <> struct V4<double> { using t = double4; };
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+// Fetch one cell: 8 corner records (Bx, By, Bz, Jx) + (Jy, Jz) of type S, turned into
+// monomial coefficients of type T.
+template <typename T, typename S, bool TW>
+__device__ __forceinline__ void load_cell(const void *nodeA, const void *nodeC, int nx, int ny,
+                                          int cx, int cy, int cz, T cb[3][8], T cj[3][8])
+{
+    const typename V4<S>::t *A = (const typename V4<S>::t *)nodeA;
+    const typename V2<S>::t *C = (const typename V2<S>::t *)nodeC;
+    const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    const int64_t base = (int64_t)cz * sz + (int64_t)cy * sy + cx;
+    T f[6][8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int64_t o = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0);
+        const typename V4<S>::t a = A[o];
+        f[0][q] = (T)a.x;
+        f[1][q] = (T)a.y;
+        f[2][q] = (T)a.z;
+        f[3][q] = (T)a.w;
+        if (TW) {
+            const typename V2<S>::t c = C[o];
+            f[4][q] = (T)c.x;
+            f[5][q] = (T)c.y;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; m++) coeffs<T>(f[m], cb[m]);
+    if (TW) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) coeffs<T>(f[3 + m], cj[m]);
+    }
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src)
+{
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    lo = __shfl(lo, src);
+    hi = __shfl(hi, src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Lines of a job that exist now (a rotated-S0 job is sized on the device).
+__device__ __forceinline__ int64_t live_lines(const TraceJob &J)
+{
+    if (J.kind != SEED_ROTATED) return J.nlines;
+    // the classify pass counts past its capacity; only stored entries exist
+    const int64_t cnt = 4 * (int64_t)(*J.rot_count);
+    return cnt < J.nlines ? cnt : J.nlines;
+}
+
+// Seed position of a line and the S0 normal used for the Eq. step / Eq. tol scaling
+// (zero for rotated S0, whose normal is along B).
+__device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, double r[3],
+                                             double nrm[3])
+{
+    nrm[0] = J.normal[0];
+    nrm[1] = J.normal[1];
+    nrm[2] = J.normal[2];
+    if (J.kind == SEED_LIST) {
+        r[0] = J.seeds[3 * line + 0];
+        r[1] = J.seeds[3 * line + 1];
+        r[2] = J.seeds[3 * line + 2];
+    } else if (J.kind == SEED_ROTATED) {
+        const RotEntry &e = J.rot[line >> 2];
+        const int which = (int)(line & 3);
+        const double *d = (which < 2) ? e.U : e.V;
+        const double s = (which & 1) ? J.rot_delta : -J.rot_delta;
+        for (int a = 0; a < 3; a++) r[a] = e.r0[a] + s * d[a];
+        nrm[0] = nrm[1] = nrm[2] = 0.0;
+    } else {
+        const int64_t i = line % J.dims[0];
+        const int64_t j = (line / J.dims[0]) % J.dims[1];
+        const int64_t k = line / (J.dims[0] * J.dims[1]);
+        for (int a = 0; a < 3; a++)
+            r[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a] +
+                   (double)k * J.s_c[a];
+    }
+}
+
+// Line of queue item t of a job (items follow 64-seed tiles); -1 for tile holes.
+__device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
+{
+    const int64_t tv = (int64_t)J.tile[0] * J.tile[1] * J.tile[2];
+    const int64_t ti = t / tv, w = t - ti * tv;
+    const int64_t t0 = ti % J.tiles[0];
+    const int64_t t1 = (ti / J.tiles[0]) % J.tiles[1];
+    const int64_t t2 = ti / (J.tiles[0] * J.tiles[1]);
+    const int64_t i = t0 * J.tile[0] + w % J.tile[0];
+    const int64_t j = t1 * J.tile[1] + (w / J.tile[0]) % J.tile[1];
+    const int64_t k = t2 * J.tile[2] + w / ((int64_t)J.tile[0] * J.tile[1]);
+    if (i >= J.dims[0] || j >= J.dims[1] || k >= J.dims[2]) return -1;
+    const int64_t line = (k * J.dims[1] + j) * J.dims[0] + i;
+    return line < live_lines(J) ? line : -1;
+}
+
+template <typename T, typename S, bool TW>
+__global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__ jobs,
+                                                    TraceParams tp,
+                                                    unsigned long long *__restrict__ counter)
+{
+    using N = Num<T>;
+    const int lane = threadIdx.x & 63;
+
+    // queue size
+    int64_t total = tp.static_items;
+    int64_t dyn_items = 0;
+    if (tp.list) {
+        total = (int64_t)(*tp.list_count);
+        if (total > tp.list_cap) total = tp.list_cap;
+    } else if (tp.dynamic_last) {
+        const int64_t lines = live_lines(jobs[tp.njobs - 1]);
+        dyn_items = ((lines + 63) / 64) * 64;
+        total += 2 * dyn_items;
+    }
+
+    // lane state
+    int jb = -1;              // job of the active half line, -1 = idle
+    bool exhausted = false;
+    bool need_load = false;   // the cell changed: fetch its corners before stepping
+    bool fresh = false;       // first step of a half line: set h and tol first
+    int64_t rec = 0;          // record slot of the active half line
+    Lane<T> L{};
+    LaneConst<T> K{};
+    K.max_steps = tp.max_steps;
+    const void *nodeA = nullptr, *nodeC = nullptr;
+    T cb[3][8], cj[3][8];
+    unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
+
+    for (;;) {
+        int fin_st = -1, fin_face = -1;  // set when the active half line ends this round
+
+        // ---- refill idle lanes: one atomic per wave ------------------------------------
+        const bool need = (jb < 0) && !exhausted;
+        const unsigned long long m = __ballot(need);
+        if (m) {
+            const int cnt = __popcll(m);
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+            base = shfl_u64(base, leader);
+            if (need) {
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const int64_t it = (int64_t)(base + (unsigned long long)rank);
+                if (it >= total) {
+                    exhausted = true;
+                } else {
+                    int j;
+                    int64_t line;
+                    bool forward;
+                    if (tp.list) {
+                        const FixEntry e = tp.list[it];
+                        j = e.job;
+                        line = e.line;
+                        forward = e.half != 0;
+                    } else {
+                        j = 0;
+                        while (j + 1 < tp.njobs && it >= jobs[j + 1].item_base) j++;
+                        const TraceJob &J = jobs[j];
+                        const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
+                        const int64_t local = it - J.item_base;
+                        forward = local < nit;
+                        line = line_of_item(J, forward ? local : local - nit);
+                    }
+                    if (line >= 0) {
+                        const TraceJob &J = jobs[j];
+                        double r[3], nrm[3];
+                        seed_of_line(J, line, r, nrm);
+                        jb = j;
+                        nodeA = J.nodeA;
+                        nodeC = J.nodeC;
+                        K.nx = J.n[0];
+                        K.ny = J.n[1];
+                        K.nz = J.n[2];
+                        const double dx = J.spacing[0], dy = J.spacing[1], dz = J.spacing[2];
+                        const double dm = fmin(dx, fmin(dy, dz));
+                        K.rx = (T)(dm / dx);
+                        K.ry = (T)(dm / dy);
+                        K.rz = (T)(dm / dz);
+                        K.twk = (T)(dm / (4.0 * M_PI));
+                        K.bnull2 = (T)((double)N::null_rel * (double)(*J.bmax2));
+                        rec = (forward ? J.nlines : 0) + line;
+                        L.sgn = forward ? T(1) : T(-1);
+                        L.tw = 0.0;
+                        L.len = 0.0;
+                        L.trials = 0;
+                        L.force = -1;
+                        const double g0 = (r[0] - J.origin[0]) / dx, g1 = (r[1] - J.origin[1]) / dy,
+                                     g2 = (r[2] - J.origin[2]) / dz;
+                        if (!(g0 >= 0.0 && g0 <= (double)(K.nx - 1) && g1 >= 0.0 &&
+                              g1 <= (double)(K.ny - 1) && g2 >= 0.0 && g2 <= (double)(K.nz - 1))) {
+                            fin_st = FQ_ST_OUTSIDE;
+                        } else {
+                            L.c0 = min(max((int)floor(g0), 0), K.nx - 2);
+                            L.c1 = min(max((int)floor(g1), 0), K.ny - 2);
+                            L.c2 = min(max((int)floor(g2), 0), K.nz - 2);
+                            L.p0 = (T)(g0 - L.c0);
+                            L.p1 = (T)(g1 - L.c1);
+                            L.p2 = (T)(g2 - L.c2);
+                            need_load = true;
+                            fresh = true;
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---- fetch the cell (the only load site) ----------------------------------------
+        if (jb >= 0 && need_load) {
+            load_cell<T, S, TW>(nodeA, nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            need_load = false;
+            n_fetch++;
+            if (fresh) {
+                // Eq. step and Eq. tol from the field angle |Bn0/B| at the seed
+                fresh = false;
+                const TraceJob &J = jobs[jb];
+                const T bx = poly<T>(cb[0], L.p0, L.p1, L.p2), by = poly<T>(cb[1], L.p0, L.p1, L.p2),
+                        bz = poly<T>(cb[2], L.p0, L.p1, L.p2);
+                const double b2 = (double)bx * bx + (double)by * by + (double)bz * bz;
+                const double bn = (double)bx * J.normal[0] + (double)by * J.normal[1] +
+                                  (double)bz * J.normal[2];
+                double ang = (J.kind == SEED_ROTATED) ? 1.0 : fabs(bn) / sqrt(b2);
+                if (!(ang >= 0.05)) ang = 0.05;  // also catches NaN
+                if (ang > 1.0) ang = 1.0;
+                L.h = (T)fmax(tp.step_perp * ang, tp.step_min);
+                L.tol = (T)fmax(tp.tol_perp * ang * sqrt(ang), tp.tol_floor);
+            }
+        }
+
+        // ---- one trial step -------------------------------------------------------------
+        if (jb >= 0 && fin_st < 0) {
+            n_trial++;
+            lane_iterate<T, TW>(L, cb, cj, K, fin_st, fin_face, need_load, n_acc);
+        }
+
+        // ---- write the record of a finished half line -----------------------------------
+        if (jb >= 0 && fin_st >= 0) {
+            const TraceJob &J = jobs[jb];
+            const bool bad = (fin_st & (FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_MAXSTEPS | FQ_ST_NONFINITE)) != 0;
+            double e0 = NAN, e1 = NAN, e2 = NAN;
+            if (!bad) {
+                e0 = J.origin[0] + ((double)L.c0 + (double)L.p0) * J.spacing[0];
+                e1 = J.origin[1] + ((double)L.c1 + (double)L.p1) * J.spacing[1];
+                e2 = J.origin[2] + ((double)L.c2 + (double)L.p2) * J.spacing[2];
+            }
+            const double dref = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
+            J.rec.end[3 * rec + 0] = e0;
+            J.rec.end[3 * rec + 1] = e1;
+            J.rec.end[3 * rec + 2] = e2;
+            J.rec.tw[rec] = bad ? NAN : (TW ? L.tw : NAN);
+            J.rec.len[rec] = bad ? NAN : L.len * dref;
+            J.rec.face[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
+            J.rec.st[rec] = (uint16_t)fin_st;
+            jb = -1;
+            need_load = false;
+            n_half++;
+        }
+
+        if (__ballot(jb >= 0) == 0 && __ballot(!exhausted) == 0) break;
+    }
+    if (tp.stats) {
+        const bool fix = tp.list != nullptr;
+        unsigned long long v[5] = {n_trial, n_acc, n_fetch, fix ? 0u : n_half, fix ? n_half : 0u};
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            unsigned long long x = v[q];
+            for (int off = 32; off > 0; off >>= 1) {
+                unsigned lo = __shfl_xor((unsigned)x, off), hi = __shfl_xor((unsigned)(x >> 32), off);
+                x += ((unsigned long long)hi << 32) | lo;
+            }
+            if (lane == 0 && x) atomicAdd(tp.stats + q, x);
+        }
+    }
+}
+
+// Lines whose field is nearly tangent to S0 at the seed, or to the face at either
+// end, turn FP32 rounding into large footpoint errors (a height error d of a line
+// meeting a plane at angle a moves its crossing by d/a); they and any line the FP32
+// pass could not finish are listed, both halves, for the FP64 pass.
+__global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double thr,
+                             FixEntry *__restrict__ list, uint32_t *__restrict__ count,
+                             int64_t cap)
+{
+    const TraceJob &J = jobs[job];
+    const int64_t nl = live_lines(J);
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t hb = l, hf = J.nlines + l;
+        const uint16_t sb = J.rec.st[hb], sf = J.rec.st[hf];
+        const uint16_t hard = FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_NONFINITE;
+        if ((sb | sf) & hard) continue;
+        bool redo = ((sb | sf) & FQ_ST_MAXSTEPS) != 0;
+        if (!redo) {
+            double r[3], nrm[3], B[3];
+            if (J.kind != SEED_ROTATED) {
+                seed_of_line(J, l, r, nrm);
+                interp64(J.planes, r, B);
+                const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                const double bn = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+                if (!(fabs(bn) >= thr * bm)) redo = true;
+            }
+            for (int h = 0; h < 2 && !redo; h++) {
+                const int64_t q = h ? hf : hb;
+                const int face = J.rec.face[q];
+                if (face < 0 || J.rec.len[q] == 0.0) continue;
+                const double e[3] = {J.rec.end[3 * q], J.rec.end[3 * q + 1], J.rec.end[3 * q + 2]};
+                interp64(J.planes, e, B);
+                const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                if (!(fabs(B[face >> 1]) >= thr * bm)) redo = true;
+            }
+        }
+        if (redo) {
+            const uint32_t slot = atomicAdd(count, 2u);
+            if ((int64_t)slot + 1 < cap) {
+                list[slot] = FixEntry{job, 0, l};
+                list[slot + 1] = FixEntry{job, 1, l};
+            }
+        }
+    }
+}
+
+template <typename T, typename S>
+const void *kernel_of(int want_tw)
+{
+    return want_tw ? (const void *)trace_kernel<T, S, true> : (const void *)trace_kernel<T, S, false>;
+}
+
+template <typename T, typename S>
+void launch_ts(int want_tw, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
+               const TraceParams &tp, unsigned long long *counter)
+{
+    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, false>), grid, blk, 0, s, jobs, tp, counter);
+}
+
+}  // namespace
+
+hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_dev,
+                        const TraceParams &tp, unsigned long long *counter, int block,
+                        int waves_per_cu, hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    if (ncu <= 0) ncu = 256;
+    if (block <= 0) block = 256;
+    const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
+    if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
+    const void *fn = f64 ? (s64 ? kernel_of<double, double>(want_tw) : kernel_of<double, float>(want_tw))
+                         : kernel_of<float, float>(want_tw);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
+    if (per_cu <= 0) per_cu = 1;
+    if (waves_per_cu > 0) {
+        int want = (waves_per_cu * 64 + block - 1) / block;
+        if (want < per_cu) per_cu = want;
+        if (per_cu < 1) per_cu = 1;
+    }
+    dim3 grid((unsigned)(per_cu * ncu)), blk((unsigned)block);
+    if (!f64) launch_ts<float, float>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    else if (s64) launch_ts<double, double>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    else launch_ts<double, float>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
+                        FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s)
+{
+    int64_t b = (max_lines + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(graze_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, job, thr, list,
+                       count, cap);
+    return hipGetLastError();
+}
+
+namespace {
+// Copies one job descriptor (a kernel argument) into the device job table, so the
+// table lives in the caller's workspace and a captured graph holds no host pointer.
+__global__ void store_job_kernel(TraceJob j, TraceJob *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = j;
+}
+}  // namespace
+
+hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(store_job_kernel, dim3(1), dim3(64), 0, s, j, dst);
+    return hipGetLastError();
+}
+
+}  // namespace fq

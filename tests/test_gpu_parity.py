@@ -1,0 +1,251 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Every case prints what it runs before touching the GPU, so a failing run names it.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Plane, cubic_grid, linear_field
+
+from gpu_util import TOL_TW, compare_maps, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32X, F64 = 0, 1
+ORC_TOL = {"tol": 1e-10}
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2208_12569_amd as m
+
+    m._lib.load()
+    return m
+
+
+def _dev(B):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(B)).cuda()
+
+
+def _run_q2d(fq, B, grid, plane, prec, **kw):
+    import torch
+
+    p = fq.Params(precision=prec, **kw)
+    r = fq.q2d(_dev(B), grid, plane, p, want_lines=True)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.config_c1(0)
+    o = oracle.q2d(w.field, w.grid, w.plane, ORC_TOL)
+    return w, o
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_c1_full_map_parity(fq, c1, prec):
+    """The 128x128 Q/Tw map of the 4-charge 64^3 cube, every point."""
+    w, o = c1
+    _say(f"c1 full map, precision {prec}")
+    g = _run_q2d(fq, w.field, w.grid, w.plane, prec)
+    st = compare_maps(g, o, f"c1-{prec}")
+    print(st)
+    assert st["excluded_frac"] < 0.02
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_ragged_seed_grid_and_fp32_field(fq, prec):
+    """Seed grids that are not multiples of the 8x8 queue tile, on an FP32 cube."""
+    rng = np.random.default_rng(5)
+    g = cubic_grid(40, 36, 30)
+    pos, q = synth.draw_charges(rng, 6)
+    B = synth.charges_field(g, pos, q, dtype=np.float32)
+    ux, uy, _ = g.upper
+    pl = Plane((0.013, 0.021, 0.0), (1, 0, 0), (0, 1, 0), 61, 45, (ux - 0.03) / 61, (uy - 0.05) / 45)
+    _say(f"ragged 61x45 seeds on 40x36x30 fp32, precision {prec}")
+    o = oracle.q2d(B, g, pl, ORC_TOL)
+    r = _run_q2d(fq, B, g, pl, prec)
+    st = compare_maps(r, o, "ragged")
+    print(st)
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_closed_form_fields(fq, prec):
+    """Sheared (Q = 2 + s^2 L^2, Tw closed form), hyperbolic (Q = 2 cosh 2kL) and
+    twisted (Tw = qL / (2 pi sqrt(1 + q^2 rho^2))) fields on the GPU."""
+    g = cubic_grid(17, 17, 17)
+    s, y0 = 0.5, 0.5
+    B = linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1])
+    pl = Plane((0.41, 0.25, 0.0), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.02)
+    _say(f"shear field, precision {prec}")
+    r = _run_q2d(fq, B, g, pl, prec)
+    q = to_np(r["q"])
+    assert np.allclose(q[1:-1, 1:-1], 2 + s * s, rtol=1e-5)
+    y1 = pl.points()[:, 1].reshape(9, 9)
+    tw = -s / (4 * np.pi * np.sqrt(1 + s * s * (y1 - y0) ** 2))
+    assert np.allclose(to_np(r["tw"]), tw, atol=TOL_TW)
+
+    kL = 4.0
+    B = linear_field(g, [[kL, 0, 0], [0, -kL, 0], [0, 0, 0]], [-kL * 0.5, kL * 0.5, 1])
+    d = 1e-4
+    pl = Plane((0.5 + 0.1 * math.exp(-kL) - d, 0.6 - d, 0.0), (1, 0, 0), (0, 1, 0), 3, 3, d, d)
+    _say(f"hyperbolic field, precision {prec}")
+    r = _run_q2d(fq, B, g, pl, prec)
+    qexp = 2 * math.cosh(2 * kL)
+    qg = to_np(r["q"])[1, 1]
+    assert abs(math.log10(qg) / math.log10(qexp) - 1) < 1e-4, (qg, qexp)
+
+    qt = 3 * math.pi
+    B = linear_field(g, [[0, -qt, 0], [qt, 0, 0], [0, 0, 0]], [qt * 0.5, -qt * 0.5, 1.0])
+    pl = Plane((0.53, 0.48, 0.0), (1, 0, 0), (0, 1, 0), 4, 4, 0.01, 0.01)
+    _say(f"twisted field, precision {prec}")
+    r = _run_q2d(fq, B, g, pl, prec)
+    pts = pl.points()
+    rho = np.hypot(pts[:, 0] - 0.5, pts[:, 1] - 0.5)
+    tw = qt / (2 * np.pi * np.sqrt(1 + qt * qt * rho * rho))
+    assert np.allclose(to_np(r["tw"]).ravel(), tw, atol=TOL_TW)
+
+
+def test_status_paths(fq):
+    """Seeds outside the box, a NaN in the field, a null region and the step budget
+    are reported per line, as in the oracle."""
+    import torch
+
+    g = cubic_grid(9, 9, 9)
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    seeds = np.array([[1.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.5, 0.5, 0.1]])
+    _say("status paths: outside seed")
+    r = fq.trace(_dev(B), g, torch.from_numpy(seeds).cuda())
+    torch.cuda.synchronize()
+    st = to_np(r["status"]).astype(np.uint16)
+    assert st[0] & fq.ST_OUTSIDE and st[1] == 0 and st[2] == 0
+    assert math.isnan(to_np(r["tw"])[0])
+    Bn = B.copy()
+    Bn[2, 6, 4, 4] = np.nan
+    _say("status paths: NaN in field")
+    r = fq.trace(_dev(Bn), g, torch.from_numpy(seeds[2:]).cuda())
+    torch.cuda.synchronize()
+    assert to_np(r["status"])[0] & fq.ST_NONFINITE
+    Bz = B.copy()
+    Bz[:, 5:, :, :] = 0.0
+    _say("status paths: null region")
+    r = fq.trace(_dev(Bz), g, torch.from_numpy(seeds[2:]).cuda())
+    torch.cuda.synchronize()
+    assert to_np(r["status"])[0] & fq.ST_NULLB
+    _say("status paths: step budget")
+    r = fq.trace(_dev(B), g, torch.from_numpy(seeds[2:]).cuda(), params=fq.Params(max_steps=1))
+    torch.cuda.synchronize()
+    assert to_np(r["status"])[0] & fq.ST_MAXSTEPS
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_trace_list_matches_oracle(fq, prec):
+    """fastqsl_trace on arbitrary seeds (interior and on faces) against the oracle."""
+    import torch
+
+    w = synth.config_c1(1)
+    rng = np.random.default_rng(11)
+    seeds = np.concatenate([rng.uniform(0.02, 0.98, (300, 3)),
+                            np.c_[rng.uniform(0.05, 0.95, (100, 2)), np.zeros(100)]])
+    _say(f"trace list of 400 seeds, precision {prec}")
+    r = fq.trace(_dev(w.field), w.grid, torch.from_numpy(seeds).cuda(),
+                 params=fq.Params(precision=prec))
+    torch.cuda.synchronize()
+    o = oracle.trace(w.field, w.grid, seeds, opts=ORC_TOL)
+    sg = to_np(r["status"]).astype(np.uint16)
+    ok = ((sg | o["status"]) & (oracle.FATAL | oracle.ORC_EDGE)) == 0
+    assert ok.mean() > 0.9
+    for k in ("end_b", "end_f"):
+        d = np.max(np.abs(to_np(r[k]) - o[k]), axis=1)
+        assert d[ok].max() < 1e-6, (k, d[ok].max())
+    assert np.array_equal(to_np(r["face_b"])[ok], o["face_b"][ok])
+    assert np.abs(to_np(r["tw"])[ok] - o["tw"][ok]).max() < TOL_TW
+    assert np.allclose(to_np(r["length"])[ok], o["len"][ok], rtol=1e-6, atol=1e-7)
+    assert np.allclose(to_np(r["bn0"])[ok], o["bn0"][ok], rtol=1e-12, atol=1e-12)
+    # B_n at an end follows the end point (which agrees to ~1e-7)
+    assert np.allclose(to_np(r["bn_f"])[ok], o["bn_f"][ok], rtol=1e-5, atol=1e-6)
+
+
+def test_batched_equals_single(fq):
+    """Two cubes of different sizes in one persistent launch give bit-identical maps
+    to the same jobs launched alone."""
+    import torch
+
+    jobs = synth.config_c4(3, njobs=2, edge=(40, 72), sides=(64, 96), ncharge=(4, 6))
+    _say("batched 2 jobs")
+    dev = [(_dev(j.field), j.grid, j.plane) for j in jobs]
+    rb = fq.q2d_batch(dev, fq.Params(), want_lines=False)
+    torch.cuda.synchronize()
+    for (B, g, pl), r in zip(dev, rb):
+        r1 = fq.q2d(B, g, pl, fq.Params())
+        torch.cuda.synchronize()
+        a, b = to_np(r["q"]), to_np(r1["q"])
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        assert np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+        assert np.array_equal(to_np(r["tw"]), to_np(r1["tw"]), equal_nan=True)
+
+
+def test_deterministic(fq, c1):
+    w, _ = c1
+    _say("determinism: two runs")
+    a = _run_q2d(fq, w.field, w.grid, w.plane, F32X)
+    b = _run_q2d(fq, w.field, w.grid, w.plane, F32X)
+    assert np.array_equal(to_np(a["q"]), to_np(b["q"]), equal_nan=True)
+    assert np.array_equal(to_np(a["tw"]), to_np(b["tw"]), equal_nan=True)
+
+
+def test_degenerate_inputs(fq):
+    """A 1x1 map (no neighbours: MIXEDFACE), a 2x2x2 cube, an empty trace."""
+    import torch
+
+    g = cubic_grid(2, 2, 2)
+    B = linear_field(g, np.zeros((3, 3)), [0.1, 0.0, 1.0])
+    pl = Plane((0.5, 0.5, 0.0), (1, 0, 0), (0, 1, 0), 1, 1, 0.1, 0.1)
+    _say("1x1 map on a 2x2x2 cube")
+    r = _run_q2d(fq, B, g, pl, F32X)
+    assert to_np(r["status"])[0, 0] & fq.ST_MIXEDFACE
+    assert abs(to_np(r["length"])[0, 0] - math.sqrt(1 + 0.01)) < 1e-6
+    pl = Plane((0.3, 0.3, 0.0), (1, 0, 0), (0, 1, 0), 3, 3, 0.1, 0.1)
+    r = _run_q2d(fq, B, g, pl, F32X)
+    assert abs(to_np(r["q"])[1, 1] - 2.0) < 1e-5
+    _say("empty trace")
+    out = fq.trace(_dev(B), g, torch.zeros((0, 3), dtype=torch.float64).cuda())
+    assert out["status"].numel() == 0
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_q3d_small_matches_oracle(fq, prec):
+    """3-D maps (one line per voxel, rotated S0 where |Bz/B| < 0.05) on a small cube."""
+    import torch
+
+    rng = np.random.default_rng(2)
+    g = cubic_grid(33, 33, 25)
+    pos, q = synth.draw_charges(rng, 6)
+    B = synth.charges_field(g, pos, q)
+    ux, uy, uz = g.upper
+    vx = synth.Voxels((ux / 32, uy / 32, uz / 20), (ux / 16, uy / 16, uz / 10), (15, 15, 9))
+    _say(f"q3d 15x15x9 voxels, precision {prec}")
+    o = oracle.q3d(B, g, vx, ORC_TOL)
+    r = fq.q3d(_dev(B), g, vx, fq.Params(precision=prec), want_lines=True)
+    torch.cuda.synchronize()
+    rot = (o["status"] & oracle.ORC_ROTATED) != 0
+    st = compare_maps(r, o, "q3d")
+    print(st, "rotated points:", int(rot.sum()))
