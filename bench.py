@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput of the Q + Tw map on one MI355X.
+
+One step = one fastqsl_q2d call on the 256x256x128 FP32 cube (6 seeded charges plus
+an arched, uniformly twisted flux tube) with 1024 x 1024 seeds on z = 0: field
+preparation, FP32 tracing of both halves of every line, the FP64 re-trace of
+grazing lines, and the FP64 Q/Tw/length stencil. The field is resident in HBM
+before the timed region. Prints ONE JSON line on stdout; details go to stderr.
+
+  python bench.py [--steps K] [--warmup W] [--precision f32x|f64] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q+Tw values/sec at 1 GPU (FP32+FP64-fixup vs all-FP64) at stated log10Q error"
+UNIT = "Q+Tw values/s"
+
+# Algorithmic FP operations of the tracer (FMA = 2), counted from the method:
+#  one RKF45 trial step = 6 right-hand sides (3 + 3 trilinear polynomials of 7 FMAs,
+#  |B|^2, 1/|B|, direction, J.B and the twist integrand: 105 flops each) + stage
+#  sums (105) + landing divisor (24) + twist/length sums (28) + 5th-order update and
+#  error estimate (66) + step control (10) = 863; one cell fetch builds 6 x 8
+#  monomial coefficients from corner values (114 flops).
+FLOPS_PER_TRIAL = 863
+FLOPS_PER_FETCH = 114
+# MI355X vector FP32 without packed instructions (the library is built with packed
+# FP32 switched off): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_FP32_VECTOR = 256 * 4 * 16 * 2 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """HIP events from the runtime torch has loaded (for timing one kernel)."""
+
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, n):
+        arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            h = ctypes.c_void_p()
+            rc = self.lib.hipEventCreate(ctypes.byref(h))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed: {rc}")
+            arr[i] = h
+        return arr
+
+    def ms(self, a, b) -> float:
+        out = ctypes.c_float()
+        rc = self.lib.hipEventElapsedTime(ctypes.byref(out), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(out.value)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("trace.hip", "trace_core.h"):
+        with open(os.path.join(ROOT, "paper_2208_12569_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str, prec: str):
+    """HBM bytes per launch of the tracer from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "trace_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(f"{workload}/{prec}")
+        if e and e.get("kernel_source_sha") == kernel_source_sha():
+            return float(e["traffic_bytes_per_launch"])
+    except (ValueError, KeyError):
+        return None
+    return None
+
+
+def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
+    import torch
+
+    import paper_2208_12569_amd as fq
+
+    prec = fq.FQ_PREC_F64 if prec_name == "f64" else fq.FQ_PREC_F32X
+    B = torch.from_numpy(w.field).cuda()
+    torch.cuda.synchronize()
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    ev = HipEvents()
+    ws = None
+    for _ in range(max(1, warmup)):
+        r = fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec, tol_perp=tol), ws=ws)
+        ws = r["_ws"]
+    torch.cuda.synchronize()
+    evs = [ev.create(4) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for k in range(steps):
+        r = fq.q2d(B, w.grid, w.plane,
+                   fq.Params(precision=prec, tol_perp=tol, stats=stats, events=evs[k]), ws=ws)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    trace_ms = [ev.ms(e[0], e[1]) for e in evs]
+    fix_ms = [ev.ms(e[2], e[3]) for e in evs] if prec == fq.FQ_PREC_F32X else [0.0] * steps
+    st = [int(x) // steps for x in stats.tolist()]
+    q = r["q"]
+    status = r["status"]
+    fatal = int(((status.to(torch.int32) & fq.ST_FATAL) != 0).sum())
+    finite = int(torch.isfinite(q).sum())
+    log(f"[{prec_name}] {steps} steps: {total_ms / steps:.3f} ms/step (wall {wall * 1e3 / steps:.3f}), "
+        f"tracer {sum(trace_ms) / steps:.3f} ms, FP64 pass {sum(fix_ms) / steps:.3f} ms; per step: "
+        f"trials {st[0]}, accepted {st[1]}, fetches {st[2]}, halves {st[3]}, FP64 halves {st[4]}; "
+        f"finite Q {finite}, fatal {fatal}")
+    return {"ms": total_ms / steps, "trace_ms": sum(trace_ms) / steps,
+            "fix_ms": sum(fix_ms) / steps, "stats": st}
+
+
+def cpu_baseline(w, side: int):
+    """The oracle on a bounded sample: a side x side block of the same seed grid
+    (centre of the map), traced and assembled on the host cores."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    pl = w.plane
+    i0 = (pl.nu - side) // 2
+    j0 = (pl.nv - side) // 2
+    o = np.asarray(pl.origin) + i0 * pl.du * np.asarray(pl.u) + j0 * pl.dv * np.asarray(pl.v)
+    sub = synth.Plane(tuple(o), pl.u, pl.v, side, side, pl.du, pl.dv)
+    oracle.build()
+    t = time.perf_counter()
+    r = oracle.q2d(w.field, w.grid, sub, {"tol": 1e-10}, want_lines=False)
+    dt = time.perf_counter() - t
+    n = side * side
+    return {"value": n / dt, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{side}x{side} block at the centre of the 1024x1024 seed grid (same cube, "
+                      f"oracle tol 1e-10 grid spacings); {dt:.1f} s incl. curl",
+            "finite_q": int(np.isfinite(r["q"]).sum())}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=("f32x", "f64"), default="f32x")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison run")
+    ap.add_argument("--cpu-side", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this tracer runs on ONE GPU (no multi-GPU path is built); "
+              "run with --gpus 1 — the value is that GPU's throughput", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+
+    t = time.perf_counter()
+    w = synth.config_c2(args.seed)
+    log(f"generated {w.name} in {time.perf_counter() - t:.1f} s")
+    main_run = run_gpu(w, args.precision, args.tol, args.steps, args.warmup)
+    other = None
+    if not args.no_f64 and args.precision == "f32x":
+        other = run_gpu(w, "f64", args.tol, args.steps, args.warmup)
+
+    npts = w.plane.nu * w.plane.nv
+    value = npts / (main_run["ms"] * 1e-3)
+    st = main_run["stats"]
+    flops = (st[0] - st[3]) * FLOPS_PER_TRIAL + st[2] * FLOPS_PER_FETCH
+    achieved = flops / (main_run["trace_ms"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "f32x" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "256x256x128 FP32 cube (dx=1/255), 6 seeded charges + arched twisted tube "
+                        "(1.5 turns, radius 0.08); 1024x1024 cell-centred seeds on z=0; Q, Tw, length",
+            "seed": args.seed,
+            "precision": args.precision,
+            "tol_perp": args.tol,
+            "trace_ms": main_run["trace_ms"],
+            "fp64_pass_ms": main_run["fix_ms"],
+            "per_step": {"trial_steps": st[0], "accepted_steps": st[1], "cell_fetches": st[2],
+                         "half_lines": st[3], "fp64_half_lines": st[4]},
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "trace_kernel<float,float,true> (FP32 pass)",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR,
+            "traffic": traffic_from_profile("c2", args.precision),
+        },
+    }
+    if other is not None:
+        out["f64_form"] = {"value": npts / (other["ms"] * 1e-3), "ms_per_step": other["ms"],
+                           "trace_ms": other["trace_ms"]}
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, args.cpu_side)
+        log(f"cpu baseline: {cb}")
+        cb.pop("finite_q", None)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

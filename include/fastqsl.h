@@ -67,7 +67,7 @@ extern "C" {
 
 /* A field: three device planes of n[0]*n[1]*n[2] values of type `dtype`. */
 typedef struct {
-    int64_t n[3];         /* nodes along x, y, z; each >= 2 */
+    int64_t n[3];         /* nodes along x, y, z; each in [2, 65535] */
     double origin[3];     /* position of node (0,0,0) */
     double spacing[3];    /* node spacing per axis; > 0 */
     int32_t dtype;        /* FQ_DT_F32 or FQ_DT_F64 */
@@ -99,6 +99,9 @@ typedef struct {
     uint64_t *stats;   /* device, optional: 5 counters ADDED to by the tracer — trial steps,
                           accepted steps, cell fetches, half lines traced, half lines traced
                           again in FP64 (NULL = not collected) */
+    void *const *events; /* host, optional: 4 hipEvent_t recorded on the call's stream right
+                          before and after the tracer launch, and before and after the FP64
+                          pass (for timing the tracer alone; NULL = none) */
 } fq_params;
 
 /* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,

@@ -23,4 +23,7 @@ from .oracle import (  # noqa: F401
     q2d,
     q3d,
     default_opts,
+    threads,
+    q2d_points,
+    q3d_points,
 )

@@ -52,6 +52,15 @@ void orc_default_opts(orc_opts *o)
     o->nthreads = 0;
 }
 
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static int64_t node(const orc_field *f, int64_t i, int64_t j, int64_t k)
 {
     return (k * f->n[1] + j) * f->n[0] + i;
@@ -733,6 +742,39 @@ static double rotated_q(const orc_field *f, const double r0[3], const double B[3
     return method1_q(c, &nb[0], &nb[1], &nb[2], &nb[3], delta, delta, bm, flags);
 }
 
+/* Q, Tw, length and status of one map point from its own line c and its stencil
+ * neighbours (NULL where the grid ends); r0 is the seed, nrm the S0 normal. */
+static void assemble_point(const orc_field *f, const full_line *c, const full_line *xm,
+                           const full_line *xp, const full_line *ym, const full_line *yp,
+                           const double r0[3], double du, double dv, const double nrm[3],
+                           int allow_rotation, const orc_opts *o, double bnull2, double *q,
+                           double *tw, double *len, uint16_t *status)
+{
+    int flags = c->status;
+    double qv = NAN;
+    if (!(c->status & FATAL_BITS)) {
+        const full_line *nbs[4] = {xm, xp, ym, yp};
+        double B[3];
+        int64_t cl[3];
+        locate(f, r0, cl);
+        orc_interp(f, f->b, cl, r0, B);
+        double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+        double bn0 = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+        if (allow_rotation && !on_box_face(f, r0) && fabs(bn0) < 0.05 * bm) {
+            double delta = du < dv ? du : dv;
+            qv = rotated_q(f, r0, B, delta, c, o, bnull2, &flags);
+        } else {
+            for (int k = 0; k < 4; k++)
+                if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
+            qv = method1_q(c, xm, xp, ym, yp, du, dv, bn0, &flags);
+        }
+    }
+    *q = qv;
+    *tw = c->tw;
+    *len = c->len;
+    *status = (uint16_t)flags;
+}
+
 /* Fill the map from traced lines on an nu x nv grid (i fastest). */
 static void assemble_map(const orc_field *f, const full_line *lines, const double *seeds,
                          int64_t nu, int64_t nv, int64_t stride_layer, double du, double dv,
@@ -744,35 +786,92 @@ static void assemble_map(const orc_field *f, const full_line *lines, const doubl
         int64_t i = p % nu, j = p / nu;
         int64_t idx = stride_layer + p;
         const full_line *c = &lines[idx];
-        int flags = c->status;
-        double qv = NAN;
-        if (!(c->status & FATAL_BITS)) {
-            const full_line *xm = i > 0 ? &lines[idx - 1] : NULL;
-            const full_line *xp = i < nu - 1 ? &lines[idx + 1] : NULL;
-            const full_line *ym = j > 0 ? &lines[idx - nu] : NULL;
-            const full_line *yp = j < nv - 1 ? &lines[idx + nu] : NULL;
-            const full_line *nbs[4] = {xm, xp, ym, yp};
-            const double *r0 = seeds + 3 * idx;
-            double B[3];
-            int64_t cl[3];
-            locate(f, r0, cl);
-            orc_interp(f, f->b, cl, r0, B);
-            double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-            double bn0 = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
-            if (allow_rotation && !on_box_face(f, r0) && fabs(bn0) < 0.05 * bm) {
-                double delta = du < dv ? du : dv;
-                qv = rotated_q(f, r0, B, delta, c, o, bnull2, &flags);
-            } else {
-                for (int k = 0; k < 4; k++)
-                    if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
-                qv = method1_q(c, xm, xp, ym, yp, du, dv, bn0, &flags);
-            }
-        }
+        const full_line *xm = i > 0 ? &lines[idx - 1] : NULL;
+        const full_line *xp = i < nu - 1 ? &lines[idx + 1] : NULL;
+        const full_line *ym = j > 0 ? &lines[idx - nu] : NULL;
+        const full_line *yp = j < nv - 1 ? &lines[idx + nu] : NULL;
+        double qv, twv, lv;
+        uint16_t sv;
+        assemble_point(f, c, xm, xp, ym, yp, seeds + 3 * idx, du, dv, nrm, allow_rotation, o,
+                       bnull2, &qv, &twv, &lv, &sv);
         if (q) q[idx] = qv;
-        if (tw) tw[idx] = c->tw;
-        if (len) len[idx] = c->len;
-        if (status) status[idx] = (uint16_t)flags;
+        if (tw) tw[idx] = twv;
+        if (len) len[idx] = lv;
+        if (status) status[idx] = sv;
     }
+}
+
+/* Points of a layered map: point p = (i, j, k) -> seed base + i a + j b + k c, with
+ * stencil neighbours along a and b inside an nu x nv layer. */
+static int map_points(const orc_field *f, const double base[3], const double a[3],
+                      const double b[3], const double c3[3], int64_t nu, int64_t nv,
+                      int64_t nl, double du, double dv, const double nrm[3], const int64_t *pts,
+                      int64_t npts, const orc_opts *o, double *q, double *tw, double *len,
+                      uint16_t *status, orc_lines *lines_out)
+{
+    double bnull2 = 1e-60 * field_scale2(f);
+    set_threads(o);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t n = 0; n < npts; n++) {
+        int64_t pt = pts[n];
+        if (pt < 0 || pt >= nu * nv * nl) {
+            bad = 1;
+            continue;
+        }
+        int64_t k = pt / (nu * nv), r = pt % (nu * nv), j = r / nu, i = r % nu;
+        /* centre, x-, x+, y-, y+ */
+        const int64_t di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
+        full_line L[5];
+        int have[5];
+        double seed0[3];
+        for (int m = 0; m < 5; m++) {
+            int64_t ii = i + di[m], jj = j + dj[m];
+            have[m] = ii >= 0 && ii < nu && jj >= 0 && jj < nv;
+            if (!have[m]) continue;
+            double s[3];
+            for (int e = 0; e < 3; e++)
+                s[e] = base[e] + (double)ii * a[e] + (double)jj * b[e] + (double)k * c3[e];
+            if (m == 0) memcpy(seed0, s, sizeof seed0);
+            trace_full(f, s, nrm, o, bnull2, &L[m]);
+        }
+        double qv, twv, lv;
+        uint16_t sv;
+        assemble_point(f, &L[0], have[1] ? &L[1] : NULL, have[2] ? &L[2] : NULL,
+                       have[3] ? &L[3] : NULL, have[4] ? &L[4] : NULL, seed0, du, dv, nrm, 1,
+                       o, bnull2, &qv, &twv, &lv, &sv);
+        if (q) q[n] = qv;
+        if (tw) tw[n] = twv;
+        if (len) len[n] = lv;
+        if (status) status[n] = sv;
+        if (lines_out) store_line(lines_out, n, &L[0]);
+    }
+    return bad ? -1 : 0;
+}
+
+int orc_q2d_points(const orc_field *f, const double origin[3], const double u[3],
+                   const double v[3], int64_t nu, int64_t nv, double du, double dv,
+                   const int64_t *pts, int64_t npts, const orc_opts *o, double *q, double *tw,
+                   double *len, uint16_t *status, orc_lines *lines)
+{
+    double a[3], b[3], zero[3] = {0, 0, 0}, nrm[3];
+    for (int e = 0; e < 3; e++) {
+        a[e] = du * u[e];
+        b[e] = dv * v[e];
+    }
+    cross(u, v, nrm);
+    return map_points(f, origin, a, b, zero, nu, nv, 1, du, dv, nrm, pts, npts, o, q, tw, len,
+                      status, lines);
+}
+
+int orc_q3d_points(const orc_field *f, const double origin[3], const double spacing[3],
+                   const int64_t nvox[3], const int64_t *pts, int64_t npts, const orc_opts *o,
+                   double *q, double *tw, double *len, uint16_t *status, orc_lines *lines)
+{
+    const double a[3] = {spacing[0], 0, 0}, b[3] = {0, spacing[1], 0}, c3[3] = {0, 0, spacing[2]};
+    const double nrm[3] = {0.0, 0.0, 1.0};
+    return map_points(f, origin, a, b, c3, nvox[0], nvox[1], nvox[2], spacing[0], spacing[1],
+                      nrm, pts, npts, o, q, tw, len, status, lines);
 }
 
 int orc_q2d(const orc_field *f, const double origin[3], const double u[3],

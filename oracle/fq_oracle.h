@@ -64,6 +64,9 @@ typedef struct {
 
 void orc_default_opts(orc_opts *o);
 
+/* OpenMP threads a parallel region of the oracle uses by default. */
+int orc_threads(void);
+
 /* Node-wise curl B by second-order differences (one-sided at the boundary). */
 int orc_curl(const orc_field *f, double *jx, double *jy, double *jz);
 
@@ -86,6 +89,17 @@ int orc_q2d(const orc_field *f, const double origin[3], const double u[3],
 int orc_q3d(const orc_field *f, const double origin[3], const double spacing[3],
             const int64_t nvox[3], const orc_opts *o, double *q, double *tw,
             double *len, uint16_t *status, orc_lines *lines);
+
+/* The same maps at listed points only (indices into the map, i fastest): each
+ * point's line and its stencil neighbours are traced and assembled exactly as in
+ * orc_q2d / orc_q3d. Outputs have npts entries. */
+int orc_q2d_points(const orc_field *f, const double origin[3], const double u[3],
+                   const double v[3], int64_t nu, int64_t nv, double du, double dv,
+                   const int64_t *pts, int64_t npts, const orc_opts *o, double *q, double *tw,
+                   double *len, uint16_t *status, orc_lines *lines);
+int orc_q3d_points(const orc_field *f, const double origin[3], const double spacing[3],
+                   const int64_t nvox[3], const int64_t *pts, int64_t npts, const orc_opts *o,
+                   double *q, double *tw, double *len, uint16_t *status, orc_lines *lines);
 
 #ifdef __cplusplus
 }

@@ -84,8 +84,23 @@ def _load():
                                 C.c_int64 * 3, C.POINTER(_Opts), C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.POINTER(_Lines)]
         lib.orc_default_opts.argtypes = [C.POINTER(_Opts)]
+        lib.orc_threads.restype = C.c_int
+        lib.orc_q2d_points.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
+                                       C.c_double * 3, C.c_int64, C.c_int64, C.c_double,
+                                       C.c_double, C.c_void_p, C.c_int64, C.POINTER(_Opts),
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.POINTER(_Lines)]
+        lib.orc_q3d_points.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
+                                       C.c_int64 * 3, C.c_void_p, C.c_int64, C.POINTER(_Opts),
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.POINTER(_Lines)]
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 def default_opts(**kw) -> dict:
@@ -213,4 +228,50 @@ def q3d(B: np.ndarray, grid, vox, opts: Optional[dict] = None, want_lines: bool 
     shp = (vox.n[2], vox.n[1], vox.n[0])
     for k in ("q", "tw", "len", "status"):
         out[k] = out[k].reshape(shp)
+    return out
+
+
+def _points_out(n):
+    return {"q": np.full(n, np.nan), "tw": np.full(n, np.nan), "len": np.full(n, np.nan),
+            "status": np.zeros(n, np.uint16)}
+
+
+def q2d_points(B: np.ndarray, grid, plane, pts, opts: Optional[dict] = None) -> dict:
+    """Q, Tw, length, status and the point's own line at listed map points
+    (flat indices, i fastest), each traced with its stencil neighbours."""
+    lib = _load()
+    h = _FieldHolder(B, grid, want_curl=(opts or {}).get("want_tw", 1) != 0)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    n = pts.size
+    out = _points_out(n)
+    s, arrs = _lines_struct(n)
+    o = _opts(opts)
+    rc = lib.orc_q2d_points(C.byref(h.f), (C.c_double * 3)(*plane.origin),
+                            (C.c_double * 3)(*plane.u), (C.c_double * 3)(*plane.v), plane.nu,
+                            plane.nv, plane.du, plane.dv, pts.ctypes.data, n, C.byref(o),
+                            out["q"].ctypes.data, out["tw"].ctypes.data, out["len"].ctypes.data,
+                            out["status"].ctypes.data, C.byref(s))
+    if rc != 0:
+        raise ValueError("orc_q2d_points: point index out of range")
+    out["lines"] = arrs
+    return out
+
+
+def q3d_points(B: np.ndarray, grid, vox, pts, opts: Optional[dict] = None) -> dict:
+    """3-D map values at listed voxels (flat indices, i fastest)."""
+    lib = _load()
+    h = _FieldHolder(B, grid, want_curl=(opts or {}).get("want_tw", 1) != 0)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    n = pts.size
+    out = _points_out(n)
+    s, arrs = _lines_struct(n)
+    o = _opts(opts)
+    rc = lib.orc_q3d_points(C.byref(h.f), (C.c_double * 3)(*vox.origin),
+                            (C.c_double * 3)(*vox.spacing), (C.c_int64 * 3)(*vox.n),
+                            pts.ctypes.data, n, C.byref(o), out["q"].ctypes.data,
+                            out["tw"].ctypes.data, out["len"].ctypes.data,
+                            out["status"].ctypes.data, C.byref(s))
+    if rc != 0:
+        raise ValueError("orc_q3d_points: point index out of range")
+    out["lines"] = arrs
     return out

@@ -43,7 +43,8 @@ class fq_params(C.Structure):
     _fields_ = [("tol_perp", C.c_double), ("step_perp", C.c_double), ("step_min", C.c_double),
                 ("tol_floor", C.c_double), ("edge_eps", C.c_double), ("max_steps", C.c_int64),
                 ("precision", C.c_int32), ("want_tw", C.c_int32), ("block", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("graze", C.c_double), ("stats", C.c_void_p)]
+                ("waves_per_cu", C.c_int32), ("graze", C.c_double), ("stats", C.c_void_p),
+                ("events", C.c_void_p)]
 
 
 class fq_plane(C.Structure):
@@ -83,6 +84,10 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the library then binds to the HIP runtime torch has loaded (both
+    # carry the soname libamdhip64.so.7), so torch's streams are valid handles here
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2208_12569_amd.build` (no CPU fallback exists)")

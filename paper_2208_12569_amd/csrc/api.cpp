@@ -57,7 +57,7 @@ int check_field(const fq_field *f)
 {
     if (!f) return FQ_EINVAL;
     for (int a = 0; a < 3; a++) {
-        if (f->n[a] < 2 || f->n[a] > (int64_t)1 << 30) return FQ_EINVAL;
+        if (f->n[a] < 2 || f->n[a] > 65535) return FQ_EINVAL;  // grid extents of the prep pass
         if (!(f->spacing[a] > 0.0) || !isfinite(f->spacing[a])) return FQ_EINVAL;
         if (!f->b[a]) return FQ_EINVAL;
     }
@@ -398,8 +398,11 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.njobs = njobs;
     tp.stats = (unsigned long long *)P.stats;
     tp.static_items = items;
+    hipEvent_t *ev = (hipEvent_t *)P.events;
+    if (ev && ev[0]) FQ_TRY(hipEventRecord(ev[0], stream));
     FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
                         jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
+    if (ev && ev[1]) FQ_TRY(hipEventRecord(ev[1], stream));
     if (fixup) {
         // FP64 pass over the grazing lines of the FP32 pass
         FixEntry *list = (FixEntry *)(ws + off_list);
@@ -432,8 +435,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         fp.list = list;
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;
+        if (ev && ev[2]) FQ_TRY(hipEventRecord(ev[2], stream));
         FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
+        if (ev && ev[3]) FQ_TRY(hipEventRecord(ev[3], stream));
     }
     for (int i = 0; i < ns; i++) {
         if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));

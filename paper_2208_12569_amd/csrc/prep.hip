@@ -50,15 +50,15 @@ __global__ __launch_bounds__(256) void prep_kernel(const S *__restrict__ bx,
                                                    typename V2<T>::t *__restrict__ Cc,
                                                    float *__restrict__ bmax2)
 {
+    // one thread per node: x from the block's x extent, (y, z) from the grid
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
     const int64_t nxy = (int64_t)nx * ny;
-    const int64_t nn = nxy * nz;
     float local = 0.0f;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(q % nx);
-        int j = (int)((q / nx) % ny);
-        int k = (int)(q / nxy);
-        double Bx = ld(bx, q), By = ld(by, q), Bz = ld(bz, q);
+    if (i < nx) {
+        const int64_t q = (int64_t)k * nxy + (int64_t)j * nx + i;
+        const double Bx = ld(bx, q), By = ld(by, q), Bz = ld(bz, q);
         double Jx = 0.0, Jy = 0.0, Jz = 0.0;
         if (want_tw) {
             Jx = ddx(bz, q, j, ny, nx, ihy) - ddx(by, q, k, nz, nxy, ihz);
@@ -77,18 +77,24 @@ __global__ __launch_bounds__(256) void prep_kernel(const S *__restrict__ bx,
             c.y = (T)Jz;
             Cc[q] = c;
         }
-        double b2 = Bx * Bx + By * By + Bz * Bz;
-        float fb2 = (float)b2;
+        const float fb2 = (float)(Bx * Bx + By * By + Bz * Bz);
         if (fb2 > local) local = fb2;  // NaN compares false and is skipped
     }
-    // wave maximum, then one atomic per wave (non-negative floats order like ints)
+    // block maximum, then one atomic per block (non-negative floats order like ints)
     for (int off = 32; off > 0; off >>= 1) {
-        float o = __shfl_xor(local, off);
+        const float o = __shfl_xor(local, off);
         local = o > local ? o : local;
     }
-    if ((threadIdx.x & 63) == 0 && local > 0.0f) {
-        if (local > FLT_MAX) local = FLT_MAX;
-        atomicMax((int *)bmax2, __float_as_int(local));
+    __shared__ float wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; w++) m = wmax[w] > m ? wmax[w] : m;
+        if (m > 0.0f) {
+            if (m > FLT_MAX) m = FLT_MAX;
+            atomicMax((int *)bmax2, __float_as_int(m));
+        }
     }
 }
 
@@ -103,10 +109,8 @@ template <typename S, typename T>
 hipError_t run_prep(const fq_field &f, int want_tw, void *A, void *C, float *bmax2,
                     hipStream_t s)
 {
-    int64_t nn = f.n[0] * f.n[1] * f.n[2];
-    int64_t blocks = (nn + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((prep_kernel<S, T>), dim3((unsigned)blocks), dim3(256), 0, s,
+    const unsigned bxs = (unsigned)((f.n[0] + 255) / 256);
+    hipLaunchKernelGGL((prep_kernel<S, T>), dim3(bxs, (unsigned)f.n[1], (unsigned)f.n[2]), dim3(256), 0, s,
                        (const S *)f.b[0], (const S *)f.b[1], (const S *)f.b[2], (int)f.n[0],
                        (int)f.n[1], (int)f.n[2], 1.0 / f.spacing[0], 1.0 / f.spacing[1],
                        1.0 / f.spacing[2], want_tw, (typename V4<T>::t *)A,

@@ -14,6 +14,7 @@ TOL_LOGQ = 1e-4
 TOL_TW = 1e-5
 TOL_FOOT = 1e-6
 QMAX = 1e8
+LOG10_2 = float(np.log10(2.0))
 
 EXCLUDE = oracle.FATAL | oracle.ORC_MIXEDFACE | oracle.ORC_EDGE
 
@@ -22,16 +23,17 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def compare_maps(g: dict, o: dict, label: str = "", foot: bool = True) -> dict:
+def compare_maps(g: dict, o: dict, label: str = "", foot: bool = True, raw: bool = False) -> dict:
     """Compare a GPU map (dict of tensors, with lines) against an oracle map.
 
     Returns statistics; raises AssertionError when a tolerance is broken on the
     parity mask or the two sides disagree on statuses or faces outside it."""
-    qg = to_np(g["q"]).ravel()
+    cv = (lambda x: np.asarray(x)) if raw else to_np
+    qg = cv(g["q"]).ravel()
     qo = o["q"].ravel()
-    sg = to_np(g["status"]).astype(np.uint16).ravel()
+    sg = cv(g["status"]).astype(np.uint16).ravel()
     so = o["status"].astype(np.uint16).ravel()
-    twg = to_np(g["tw"]).ravel()
+    twg = cv(g["tw"]).ravel()
     two = o["tw"].ravel()
     n = qo.size
     edge = ((sg | so) & oracle.ORC_EDGE) != 0
@@ -43,10 +45,11 @@ def compare_maps(g: dict, o: dict, label: str = "", foot: bool = True) -> dict:
     mask = ((sg | so) & EXCLUDE) == 0
     mask &= np.isfinite(qo) & (qo < QMAX)
     stats = {"n": n, "masked": int(mask.sum()), "excluded_frac": float(1 - mask.mean())}
-    # Q: relative error of log10 Q
+    # Q: relative error of log10 Q, on the scale max(|log10 Q|, log10 2): Q >= 2 in
+    # theory, and the relative measure degenerates where discretisation puts Q near 1
     lq_o = np.log10(qo[mask])
     lq_g = np.log10(qg[mask])
-    rel = np.abs(lq_g - lq_o) / np.maximum(np.abs(lq_o), 1e-300)
+    rel = np.abs(lq_g - lq_o) / np.maximum(np.abs(lq_o), LOG10_2)
     stats["logq_rel_max"] = float(rel.max()) if rel.size else 0.0
     stats["logq_rel_p999"] = float(np.quantile(rel, 0.999)) if rel.size else 0.0
     worst = np.argmax(rel) if rel.size else None
@@ -60,9 +63,9 @@ def compare_maps(g: dict, o: dict, label: str = "", foot: bool = True) -> dict:
     if foot and "lines" in g and "lines" in o:
         L = g["lines"]
         for key in ("end_b", "end_f"):
-            eg = to_np(L[key])
+            eg = cv(L[key])
             eo = o["lines"][key]
-            fg = to_np(L["face_" + key[-1]]).astype(np.int8)
+            fg = cv(L["face_" + key[-1]]).astype(np.int8)
             fo = o["lines"]["face_" + key[-1]]
             lm = (((sg | so) & (oracle.FATAL | oracle.ORC_EDGE)) == 0)
             assert np.array_equal(fg[lm], fo[lm]), (label, key, "face mismatch")
@@ -74,3 +77,12 @@ def compare_maps(g: dict, o: dict, label: str = "", foot: bool = True) -> dict:
             over = fm & (d > bound)
             assert not over.any(), (label, key, int(over.sum()), d[over][:5], qq[over][:5])
     return stats
+
+
+def compare_points(g: dict, idx, o: dict, label: str = "") -> dict:
+    """Compare a full GPU map (tensors, with lines) at flat indices idx with oracle
+    values computed at those points only (oracle.q2d_points / q3d_points)."""
+    sub = {"q": to_np(g["q"]).ravel()[idx], "status": to_np(g["status"]).ravel()[idx],
+           "tw": to_np(g["tw"]).ravel()[idx],
+           "lines": {k: to_np(v)[idx] for k, v in g["lines"].items()}}
+    return compare_maps(sub, o, label, raw=True)

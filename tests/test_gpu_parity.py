@@ -13,7 +13,7 @@ import oracle
 import synth
 from synth import Plane, cubic_grid, linear_field
 
-from gpu_util import TOL_TW, compare_maps, to_np
+from gpu_util import TOL_TW, compare_maps, compare_points, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -249,3 +249,68 @@ def test_q3d_small_matches_oracle(fq, prec):
     rot = (o["status"] & oracle.ORC_ROTATED) != 0
     st = compare_maps(r, o, "q3d")
     print(st, "rotated points:", int(rot.sum()))
+
+
+def _sample(n_total, nu, nv, k, seed):
+    """k random map points plus the four corners and some edge points."""
+    rng = np.random.default_rng(seed)
+    pts = rng.choice(n_total, k, replace=False)
+    edge = [0, nu - 1, nu * (nv - 1), nu * nv - 1, nu // 2, nu * (nv // 2)]
+    return np.unique(np.concatenate([pts, edge]))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config_c2(0)
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_c2_full_size_sampled_parity(fq, c2, prec):
+    """The 1024x1024 map of the 256x256x128 FP32 cube (6 charges + twisted tube), in
+    the launch configuration the bench times, against the oracle at 400 sampled
+    points (each traced with its stencil neighbours)."""
+    import torch
+
+    w = c2
+    _say(f"c2 1024x1024 full map, precision {prec}")
+    r = fq.q2d(_dev(w.field), w.grid, w.plane, fq.Params(precision=prec), want_lines=True)
+    torch.cuda.synchronize()
+    idx = _sample(1024 * 1024, 1024, 1024, 400, 17)
+    o = oracle.q2d_points(w.field, w.grid, w.plane, idx, ORC_TOL)
+    st = compare_points(r, idx, o, f"c2-{prec}")
+    print(st)
+    assert st["excluded_frac"] < 0.05
+    # properties that hold everywhere: no failed lines, Tw finite on every line
+    sg = to_np(r["status"]).astype(np.uint16)
+    assert not (sg & fq.ST_FATAL).any()
+    assert np.isfinite(to_np(r["tw"])).all()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return synth.config_c3(0)
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_c3_full_size_sampled_parity(fq, c3, prec):
+    """3-D Q and Tw on the 256x256x128 voxel centres of the 512x512x256 FP32 cube
+    (10 charges + two tubes), including rotated-S0 voxels, against the oracle at
+    sampled voxels."""
+    import torch
+
+    w = c3
+    vx = w.voxels
+    _say(f"c3 q3d 256x256x128 voxels, precision {prec}")
+    r = fq.q3d(_dev(w.field), w.grid, vx, fq.Params(precision=prec), want_lines=True)
+    torch.cuda.synchronize()
+    n = int(np.prod(vx.n))
+    st_all = to_np(r["status"]).astype(np.uint16).ravel()
+    rot = np.flatnonzero(st_all & fq.ST_ROTATED)
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False),
+                                    rng.choice(rot, min(60, rot.size), replace=False)]))
+    o = oracle.q3d_points(w.field, w.grid, vx, idx, ORC_TOL)
+    st = compare_points(r, idx, o, f"c3-{prec}")
+    print(st, "rotated voxels:", rot.size)
+    assert rot.size > 0
+    assert not (st_all & fq.ST_FATAL).any()

@@ -441,3 +441,30 @@ def test_q_at_least_two(orc):
     assert m.sum() > 0.5 * m.size
     assert np.nanmin(r["q"][m]) > 2 - 1e-4
     assert np.nanmax(r["q"][m]) > 2.5
+
+
+def test_sampled_points_equal_full_map(orc):
+    """The sampled-point entry points assemble Q exactly as the full maps do."""
+    w = synth.config_c1(2, nseed=40)
+    full = orc.q2d(w.field, w.grid, w.plane)
+    rng = np.random.default_rng(0)
+    pts = rng.choice(40 * 40, 60, replace=False)
+    pts = np.concatenate([pts, [0, 39, 40 * 39]])  # map corners too
+    sub = orc.q2d_points(w.field, w.grid, w.plane, pts)
+    assert np.array_equal(sub["status"], full["status"].ravel()[pts])
+    assert np.array_equal(np.isnan(sub["q"]), np.isnan(full["q"].ravel()[pts]))
+    m = ~np.isnan(sub["q"])
+    assert np.array_equal(sub["q"][m], full["q"].ravel()[pts][m])
+    assert np.array_equal(sub["tw"], full["tw"].ravel()[pts])
+    rng = np.random.default_rng(2)
+    g = cubic_grid(17, 17, 13)
+    pos, q = synth.draw_charges(rng, 5)
+    B = synth.charges_field(g, pos, q)
+    ux, uy, uz = g.upper
+    vx = Voxels((ux / 16, uy / 16, uz / 12), (ux / 8, uy / 8, uz / 6), (8, 8, 6))
+    f3 = orc.q3d(B, g, vx)
+    pts = rng.choice(8 * 8 * 6, 50, replace=False)
+    s3 = orc.q3d_points(B, g, vx, pts)
+    assert np.array_equal(s3["status"], f3["status"].ravel()[pts])
+    m = ~np.isnan(s3["q"])
+    assert np.array_equal(s3["q"][m], f3["q"].ravel()[pts][m])
