@@ -203,6 +203,8 @@ void set_map_geometry(const Spec &s, MapJob &m)
     }
 }
 
+void set_job_constants(TraceJob &J);
+
 // Carve the workspace and (unless dry) enqueue the whole call.
 int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_bytes, bool dry,
         size_t *need, hipStream_t stream)
@@ -363,6 +365,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             tv *= J.tiles[a] * J.tile[a];
         }
         J.nitems = tv;
+        set_job_constants(J);
         J.item_base = items;
         items += 2 * tv;
     }
@@ -383,6 +386,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         J.dims[0] = 4 * w.nlines, J.dims[1] = 1, J.dims[2] = 1;
         J.tiles[0] = (J.dims[0] + 63) / 64, J.tiles[1] = 1, J.tiles[2] = 1;
         J.nitems = J.tiles[0] * 64;
+        set_job_constants(J);
         J.rec = recs_at(ws, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
         J.item_base = items;
         tp.dynamic_last = 1;
@@ -446,6 +450,18 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
 #undef FQ_TRY
     return FQ_OK;
+}
+
+// Constants the tracer would otherwise recompute per half line.
+void set_job_constants(TraceJob &J)
+{
+    const double dm = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
+    for (int a = 0; a < 3; a++) J.rscale[a] = (float)(dm / J.spacing[a]);
+    J.twk = (float)(dm / (4.0 * M_PI));
+    J.dref = dm;
+    for (int a = 0; a < 3; a++) J.inv_spacing[a] = 1.0 / J.spacing[a];
+    J.inv_t0 = 1.0 / (double)J.tiles[0];
+    J.inv_t1 = 1.0 / (double)J.tiles[1];
 }
 
 void plane_normal(const fq_plane &p, double n[3])

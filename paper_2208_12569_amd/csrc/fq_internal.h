@@ -61,6 +61,12 @@ struct TraceJob {
     HalfRecs rec;
     int64_t item_base;   // first queue item of the job (items of both halves follow)
     Planes64 planes;     // the caller's field, for FP64 angles in the grazing test
+    // precomputed per-job constants of the tracer
+    float rscale[3];     // reference length / spacing per axis
+    float twk;           // reference length / (4 pi)
+    double dref;         // reference length (smallest spacing)
+    double inv_spacing[3];
+    double inv_t0, inv_t1; // 1 / tiles[0], 1 / tiles[1] (tile decode)
 };
 
 // One half line to trace again (FP64 pass).

@@ -39,14 +39,30 @@ template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
+// Pointers read from the job table are generic; marking them as global memory
+// (address space 1) makes the compiler emit global instead of flat loads/stores.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FQ_GLOBAL __attribute__((address_space(1)))
+#else
+#define FQ_GLOBAL
+#endif
+template <typename P> __device__ __forceinline__ FQ_GLOBAL P *gptr(P *p)
+{
+    return (FQ_GLOBAL P *)p;
+}
+template <typename P> __device__ __forceinline__ const FQ_GLOBAL P *gptr(const P *p)
+{
+    return (const FQ_GLOBAL P *)p;
+}
+
 // Fetch one cell: 8 corner records (Bx, By, Bz, Jx) + (Jy, Jz) of type S, turned into
 // monomial coefficients of type T.
 template <typename T, typename S, bool TW>
 __device__ __forceinline__ void load_cell(const void *nodeA, const void *nodeC, int nx, int ny,
                                           int cx, int cy, int cz, T cb[3][8], T cj[3][8])
 {
-    const typename V4<S>::t *A = (const typename V4<S>::t *)nodeA;
-    const typename V2<S>::t *C = (const typename V2<S>::t *)nodeC;
+    const FQ_GLOBAL typename V4<S>::t *A = gptr((const typename V4<S>::t *)nodeA);
+    const FQ_GLOBAL typename V2<S>::t *C = gptr((const typename V2<S>::t *)nodeC);
     const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
     const int64_t base = (int64_t)cz * sz + (int64_t)cy * sy + cx;
     T f[6][8];
@@ -98,11 +114,12 @@ __device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, do
     nrm[1] = J.normal[1];
     nrm[2] = J.normal[2];
     if (J.kind == SEED_LIST) {
-        r[0] = J.seeds[3 * line + 0];
-        r[1] = J.seeds[3 * line + 1];
-        r[2] = J.seeds[3 * line + 2];
+        const FQ_GLOBAL double *sd = gptr(J.seeds);
+        r[0] = sd[3 * line + 0];
+        r[1] = sd[3 * line + 1];
+        r[2] = sd[3 * line + 2];
     } else if (J.kind == SEED_ROTATED) {
-        const RotEntry &e = J.rot[line >> 2];
+        const FQ_GLOBAL RotEntry &e = gptr(J.rot)[line >> 2];
         const int which = (int)(line & 3);
         const double *d = (which < 2) ? e.U : e.V;
         const double s = (which & 1) ? J.rot_delta : -J.rot_delta;
@@ -118,23 +135,50 @@ __device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, do
     }
 }
 
-// Line of queue item t of a job (items follow 64-seed tiles); -1 for tile holes.
-__device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
+// floor(n / d) for 0 <= n < 2^31 with a precomputed 1/d (one FP64 multiply and
+// an exact integer correction)
+__device__ __forceinline__ int64_t fdiv(int64_t n, int64_t d, double inv_d, int64_t &rem)
 {
-    const int64_t tv = (int64_t)J.tile[0] * J.tile[1] * J.tile[2];
-    const int64_t ti = t / tv, w = t - ti * tv;
-    const int64_t t0 = ti % J.tiles[0];
-    const int64_t t1 = (ti / J.tiles[0]) % J.tiles[1];
-    const int64_t t2 = ti / (J.tiles[0] * J.tiles[1]);
-    const int64_t i = t0 * J.tile[0] + w % J.tile[0];
-    const int64_t j = t1 * J.tile[1] + (w / J.tile[0]) % J.tile[1];
-    const int64_t k = t2 * J.tile[2] + w / ((int64_t)J.tile[0] * J.tile[1]);
-    if (i >= J.dims[0] || j >= J.dims[1] || k >= J.dims[2]) return -1;
-    const int64_t line = (k * J.dims[1] + j) * J.dims[0] + i;
-    return line < live_lines(J) ? line : -1;
+    int64_t q = (int64_t)((double)n * inv_d);
+    int64_t r = n - q * d;
+    if (r < 0) {
+        q--;
+        r += d;
+    } else if (r >= d) {
+        q++;
+        r -= d;
+    }
+    rem = r;
+    return q;
 }
 
-template <typename T, typename S, bool TW>
+// Line of queue item t of a job; -1 for tile holes. Plane seeds come in 8x8 tiles,
+// voxels in 4x4x4 tiles (64 neighbouring seeds per wave), lists in order.
+__device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
+{
+    if (J.kind == SEED_LIST || J.kind == SEED_ROTATED) return t < live_lines(J) ? t : -1;
+    const int64_t ti = t >> 6;
+    const int w = (int)(t & 63);
+    int64_t r0, i, j, k;
+    const int64_t q0 = fdiv(ti, J.tiles[0], J.inv_t0, r0);
+    if (J.kind == SEED_PLANE) {
+        i = r0 * 8 + (w & 7);
+        j = q0 * 8 + (w >> 3);
+        k = 0;
+    } else {
+        int64_t r1;
+        const int64_t q1 = fdiv(q0, J.tiles[1], J.inv_t1, r1);
+        i = r0 * 4 + (w & 3);
+        j = r1 * 4 + ((w >> 2) & 3);
+        k = q1 * 4 + (w >> 4);
+    }
+    if (i >= J.dims[0] || j >= J.dims[1] || k >= J.dims[2]) return -1;
+    return (k * J.dims[1] + j) * J.dims[0] + i;
+}
+
+// UNI: a single job without a rotated-S0 companion, so every job constant is
+// uniform across the grid (kept in scalar registers).
+template <typename T, typename S, bool TW, bool UNI>
 __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
@@ -148,7 +192,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
     if (tp.list) {
         total = (int64_t)(*tp.list_count);
         if (total > tp.list_cap) total = tp.list_cap;
-    } else if (tp.dynamic_last) {
+    } else if (!UNI && tp.dynamic_last) {
         const int64_t lines = live_lines(jobs[tp.njobs - 1]);
         dyn_items = ((lines + 63) / 64) * 64;
         total += 2 * dyn_items;
@@ -164,6 +208,19 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
     LaneConst<T> K{};
     K.max_steps = tp.max_steps;
     const void *nodeA = nullptr, *nodeC = nullptr;
+    if (UNI) {
+        const TraceJob &J0 = jobs[0];
+        nodeA = J0.nodeA;
+        nodeC = J0.nodeC;
+        K.nx = J0.n[0];
+        K.ny = J0.n[1];
+        K.nz = J0.n[2];
+        K.rx = (T)J0.rscale[0];
+        K.ry = (T)J0.rscale[1];
+        K.rz = (T)J0.rscale[2];
+        K.twk = (T)J0.twk;
+        K.bnull2 = (T)((double)N::null_rel * (double)(*J0.bmax2));
+    }
     T cb[3][8], cj[3][8];
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
 
@@ -185,17 +242,17 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
                 if (it >= total) {
                     exhausted = true;
                 } else {
-                    int j;
+                    int j = 0;
                     int64_t line;
                     bool forward;
                     if (tp.list) {
-                        const FixEntry e = tp.list[it];
-                        j = e.job;
+                        const FixEntry e = gptr(tp.list)[it];
+                        j = UNI ? 0 : e.job;
                         line = e.line;
                         forward = e.half != 0;
                     } else {
-                        j = 0;
-                        while (j + 1 < tp.njobs && it >= jobs[j + 1].item_base) j++;
+                        if (!UNI)
+                            while (j + 1 < tp.njobs && it >= jobs[j + 1].item_base) j++;
                         const TraceJob &J = jobs[j];
                         const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
                         const int64_t local = it - J.item_base;
@@ -207,26 +264,27 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
                         double r[3], nrm[3];
                         seed_of_line(J, line, r, nrm);
                         jb = j;
-                        nodeA = J.nodeA;
-                        nodeC = J.nodeC;
-                        K.nx = J.n[0];
-                        K.ny = J.n[1];
-                        K.nz = J.n[2];
-                        const double dx = J.spacing[0], dy = J.spacing[1], dz = J.spacing[2];
-                        const double dm = fmin(dx, fmin(dy, dz));
-                        K.rx = (T)(dm / dx);
-                        K.ry = (T)(dm / dy);
-                        K.rz = (T)(dm / dz);
-                        K.twk = (T)(dm / (4.0 * M_PI));
-                        K.bnull2 = (T)((double)N::null_rel * (double)(*J.bmax2));
+                        if (!UNI) {
+                            nodeA = J.nodeA;
+                            nodeC = J.nodeC;
+                            K.nx = J.n[0];
+                            K.ny = J.n[1];
+                            K.nz = J.n[2];
+                            K.rx = (T)J.rscale[0];
+                            K.ry = (T)J.rscale[1];
+                            K.rz = (T)J.rscale[2];
+                            K.twk = (T)J.twk;
+                            K.bnull2 = (T)((double)N::null_rel * (double)(*J.bmax2));
+                        }
                         rec = (forward ? J.nlines : 0) + line;
                         L.sgn = forward ? T(1) : T(-1);
                         L.tw = 0.0;
                         L.len = 0.0;
                         L.trials = 0;
                         L.force = -1;
-                        const double g0 = (r[0] - J.origin[0]) / dx, g1 = (r[1] - J.origin[1]) / dy,
-                                     g2 = (r[2] - J.origin[2]) / dz;
+                        const double g0 = (r[0] - J.origin[0]) * J.inv_spacing[0],
+                                     g1 = (r[1] - J.origin[1]) * J.inv_spacing[1],
+                                     g2 = (r[2] - J.origin[2]) * J.inv_spacing[2];
                         if (!(g0 >= 0.0 && g0 <= (double)(K.nx - 1) && g1 >= 0.0 &&
                               g1 <= (double)(K.ny - 1) && g2 >= 0.0 && g2 <= (double)(K.nz - 1))) {
                             fin_st = FQ_ST_OUTSIDE;
@@ -253,17 +311,18 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
             if (fresh) {
                 // Eq. step and Eq. tol from the field angle |Bn0/B| at the seed
                 fresh = false;
-                const TraceJob &J = jobs[jb];
-                const T bx = poly<T>(cb[0], L.p0, L.p1, L.p2), by = poly<T>(cb[1], L.p0, L.p1, L.p2),
-                        bz = poly<T>(cb[2], L.p0, L.p1, L.p2);
-                const double b2 = (double)bx * bx + (double)by * by + (double)bz * bz;
-                const double bn = (double)bx * J.normal[0] + (double)by * J.normal[1] +
-                                  (double)bz * J.normal[2];
-                double ang = (J.kind == SEED_ROTATED) ? 1.0 : fabs(bn) / sqrt(b2);
-                if (!(ang >= 0.05)) ang = 0.05;  // also catches NaN
-                if (ang > 1.0) ang = 1.0;
-                L.h = (T)fmax(tp.step_perp * ang, tp.step_min);
-                L.tol = (T)fmax(tp.tol_perp * ang * sqrt(ang), tp.tol_floor);
+                const TraceJob &J = jobs[UNI ? 0 : jb];
+                const float bx = (float)poly<T>(cb[0], L.p0, L.p1, L.p2);
+                const float by = (float)poly<T>(cb[1], L.p0, L.p1, L.p2);
+                const float bz = (float)poly<T>(cb[2], L.p0, L.p1, L.p2);
+                const float b2 = bx * bx + by * by + bz * bz;
+                const float bn = bx * (float)J.normal[0] + by * (float)J.normal[1] +
+                                 bz * (float)J.normal[2];
+                float ang = (J.kind == SEED_ROTATED) ? 1.0f : fabsf(bn) * Num<float>::rsq(b2);
+                if (!(ang >= 0.05f)) ang = 0.05f;  // also catches NaN
+                if (ang > 1.0f) ang = 1.0f;
+                L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
+                L.tol = (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
             }
         }
 
@@ -275,7 +334,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
 
         // ---- write the record of a finished half line -----------------------------------
         if (jb >= 0 && fin_st >= 0) {
-            const TraceJob &J = jobs[jb];
+            const TraceJob &J = jobs[UNI ? 0 : jb];
             const bool bad = (fin_st & (FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_MAXSTEPS | FQ_ST_NONFINITE)) != 0;
             double e0 = NAN, e1 = NAN, e2 = NAN;
             if (!bad) {
@@ -283,14 +342,14 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
                 e1 = J.origin[1] + ((double)L.c1 + (double)L.p1) * J.spacing[1];
                 e2 = J.origin[2] + ((double)L.c2 + (double)L.p2) * J.spacing[2];
             }
-            const double dref = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
-            J.rec.end[3 * rec + 0] = e0;
-            J.rec.end[3 * rec + 1] = e1;
-            J.rec.end[3 * rec + 2] = e2;
-            J.rec.tw[rec] = bad ? NAN : (TW ? L.tw : NAN);
-            J.rec.len[rec] = bad ? NAN : L.len * dref;
-            J.rec.face[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
-            J.rec.st[rec] = (uint16_t)fin_st;
+            FQ_GLOBAL double *ge = gptr(J.rec.end);
+            ge[3 * rec + 0] = e0;
+            ge[3 * rec + 1] = e1;
+            ge[3 * rec + 2] = e2;
+            gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
+            gptr(J.rec.len)[rec] = bad ? NAN : L.len * J.dref;
+            gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
+            gptr(J.rec.st)[rec] = (uint16_t)fin_st;
             jb = -1;
             need_load = false;
             n_half++;
@@ -359,18 +418,19 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
     }
 }
 
-template <typename T, typename S>
+template <typename T, typename S, bool UNI>
 const void *kernel_of(int want_tw)
 {
-    return want_tw ? (const void *)trace_kernel<T, S, true> : (const void *)trace_kernel<T, S, false>;
+    return want_tw ? (const void *)trace_kernel<T, S, true, UNI>
+                   : (const void *)trace_kernel<T, S, false, UNI>;
 }
 
-template <typename T, typename S>
+template <typename T, typename S, bool UNI>
 void launch_ts(int want_tw, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
                const TraceParams &tp, unsigned long long *counter)
 {
-    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true>), grid, blk, 0, s, jobs, tp, counter);
-    else hipLaunchKernelGGL((trace_kernel<T, S, false>), grid, blk, 0, s, jobs, tp, counter);
+    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true, UNI>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, false, UNI>), grid, blk, 0, s, jobs, tp, counter);
 }
 
 }  // namespace
@@ -387,8 +447,11 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
     if (block <= 0) block = 256;
     const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
     if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
-    const void *fn = f64 ? (s64 ? kernel_of<double, double>(want_tw) : kernel_of<double, float>(want_tw))
-                         : kernel_of<float, float>(want_tw);
+    const bool uni = tp.njobs == 1 && !tp.dynamic_last;
+    const void *fn;
+    if (!f64) fn = uni ? kernel_of<float, float, true>(want_tw) : kernel_of<float, float, false>(want_tw);
+    else if (s64) fn = uni ? kernel_of<double, double, true>(want_tw) : kernel_of<double, double, false>(want_tw);
+    else fn = uni ? kernel_of<double, float, true>(want_tw) : kernel_of<double, float, false>(want_tw);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
     if (per_cu <= 0) per_cu = 1;
@@ -398,9 +461,16 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
         if (per_cu < 1) per_cu = 1;
     }
     dim3 grid((unsigned)(per_cu * ncu)), blk((unsigned)block);
-    if (!f64) launch_ts<float, float>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-    else if (s64) launch_ts<double, double>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-    else launch_ts<double, float>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    if (!f64) {
+        if (uni) launch_ts<float, float, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<float, float, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    } else if (s64) {
+        if (uni) launch_ts<double, double, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, double, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    } else {
+        if (uni) launch_ts<double, float, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, float, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+    }
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ template <> struct Num<float> {
     static __host__ __device__ __forceinline__ float rsq(float x)
     {
 #if defined(__HIP_DEVICE_COMPILE__)
-        return __frsqrt_rn(x);
+        return __builtin_amdgcn_rsqf(x);
 #else
         return 1.0f / sqrtf(x);
 #endif
@@ -63,12 +63,14 @@ template <> struct Num<double> {
     static constexpr double hmin = 1e-12;
 };
 
-__host__ __device__ __forceinline__ float pow02(float x)
+// x^(1/10) for the step controller, which works on squared errors (accuracy of a
+// few ulp is plenty: it only scales the next trial step)
+__host__ __device__ __forceinline__ float pow01(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __powf(x, 0.2f);
+    return __builtin_amdgcn_exp2f(0.1f * __builtin_amdgcn_logf(x));
 #else
-    return powf(x, 0.2f);
+    return powf(x, 0.1f);
 #endif
 }
 
@@ -205,14 +207,17 @@ __host__ __device__ __forceinline__ bool carry(int &c, T &p, int n)
 template <typename T>
 __host__ __device__ __forceinline__ int excursion(int axis, T p, T s1, T D, T ov)
 {
-    const T s2 = D - s1;  // x(t) = p + s1 t + s2 t^2, t in [0,1]
+    // x(t) = p + s1 t + s2 t^2 on t in [0,1]; an interior extremum needs s1 s2 < 0 and
+    // t* = -s1 / (2 s2) < 1, and lies at x* = p - s1^2 / (4 s2). Written without
+    // divisions: with a = |s2| the conditions are |s1| < 2a and, for a maximum
+    // (s2 < 0), s1^2 > 4a (1 + ov - p); for a minimum, s1^2 > 4a (p + ov).
+    const T s2 = D - s1;
     if (!(s1 * s2 < T(0))) return -1;
-    const T tm = -s1 / (T(2) * s2);
-    if (!(tm > T(0) && tm < T(1))) return -1;
-    const T xm = p - s1 * s1 / (T(4) * s2);
-    if (xm > T(1) + ov) return 2 * axis + 1;
-    if (xm < -ov) return 2 * axis;
-    return -1;
+    const T a = fabs(s2);
+    if (!(fabs(s1) < T(2) * a)) return -1;
+    const T s1s = s1 * s1, a4 = T(4) * a;
+    if (s2 < T(0)) return s1s > a4 * (T(1) + ov - p) ? 2 * axis + 1 : -1;
+    return s1s > a4 * (p + ov) ? 2 * axis : -1;
 }
 
 // One trial step. On return: fin_st >= 0 if the half line ended (status bits,
@@ -262,15 +267,15 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         T t_exit = T(FLT_MAX);
         int a_star = -1;
         if (fabs(f0) > tau) {
-            const T t = (f0 > 0 ? (T(1) - L.p0) : -L.p0) / f0;
+            const T t = (f0 > 0 ? (T(1) - L.p0) : -L.p0) * N::rcp(f0);
             if (t < t_exit) t_exit = t, a_star = 0;
         }
         if (fabs(f1) > tau) {
-            const T t = (f1 > 0 ? (T(1) - L.p1) : -L.p1) / f1;
+            const T t = (f1 > 0 ? (T(1) - L.p1) : -L.p1) * N::rcp(f1);
             if (t < t_exit) t_exit = t, a_star = 1;
         }
         if (fabs(f2) > tau) {
-            const T t = (f2 > 0 ? (T(1) - L.p2) : -L.p2) / f2;
+            const T t = (f2 > 0 ? (T(1) - L.p2) : -L.p2) * N::rcp(f2);
             if (t < t_exit) t_exit = t, a_star = 2;
         }
         int axis = L.h >= t_exit ? a_star : -1;
@@ -369,9 +374,10 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             fin_st = kNull;
             return;
         }
-        const T err = sqrt(N::fma_(e[0], e[0], N::fma_(e[1], e[1], e[2] * e[2])));
+        const T err2 = N::fma_(e[0], e[0], N::fma_(e[1], e[1], e[2] * e[2]));
+        const T tol2 = L.tol * L.tol;
         const T s_step = H * ig0;  // arc length of the step, reference lengths
-        if (!ok || !finite_(err)) {
+        if (!ok || !finite_(err2)) {
             if (axis < 0) {
                 fin_st = kNonFinite;  // a NaN/Inf in the field
             } else {
@@ -384,13 +390,14 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             }
             return;
         }
-        if (err > L.tol) {  // reject: shrink and retry from the same point
-            const float fac = fmaxf(0.9f * pow02((float)(L.tol / err)), 0.1f);
+        if (err2 > tol2) {  // reject: shrink and retry from the same point
+            const float fac = fmaxf(0.9f * pow01((float)tol2 * Num<float>::rcp((float)err2)), 0.1f);
             L.h = mx((axis >= 0 ? mn(L.h, fabs(s_step)) : L.h) * (T)fac, N::hmin);
             ev(axis >= 0 ? EV_REJECT_LAND : EV_REJECT_ARC);
             return;
         }
-        const float grow = err > T(0) ? fminf(0.9f * pow02((float)(L.tol / err)), 5.0f) : 5.0f;
+        const float grow = err2 > T(0) ? fminf(0.9f * pow01((float)tol2 * Num<float>::rcp((float)err2)), 5.0f)
+                                       : 5.0f;
         T n0 = L.p0 + dyv[0], n1 = L.p1 + dyv[1], n2 = L.p2 + dyv[2];
         const T ov = N::ov;
         // a brief excursion over a face inside the step (the end may be back inside)
