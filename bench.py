@@ -139,6 +139,65 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
             "fix_ms": sum(fix_ms) / steps, "stats": st}
 
 
+def run_batch(seed: int, steps: int, warmup: int):
+    """The uneven batch: 16 seeded cubes (edges 64-384, FP32, 4-12 charges, seed grids
+    128^2-1024^2 on z = 0) in one persistent launch, captured in a HIP graph with
+    autotuned launch parameters; against the same jobs run one call each."""
+    import torch
+
+    import paper_2208_12569_amd as fq
+    from paper_2208_12569_amd.graph import Q2DGraph
+    from paper_2208_12569_amd.tune import tune_launch
+    from synth.torch_fields import config_c4_torch
+
+    t = time.perf_counter()
+    ws_ = config_c4_torch(seed)
+    jobs = [(w.field, w.grid, w.plane) for w in ws_]
+    torch.cuda.synchronize()
+    log(f"generated the 16-cube batch on the GPU in {time.perf_counter() - t:.1f} s")
+    npts = sum(w.plane.nu * w.plane.nv for w in ws_)
+    params, table = tune_launch(jobs, fq.Params(), reps=2)
+    log(f"batch tuner: block {params.block}, waves/CU {params.waves_per_cu}; "
+        + ", ".join(f"{k}: {v:.2f} ms" for k, v in sorted(table.items())))
+    g = Q2DGraph(jobs, params)
+    for _ in range(max(1, warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    # each job alone: one call per job, same parameters, median of 3
+    alone = 0.0
+    for j in jobs:
+        need = fq.q2d_workspace_size([j], params)
+        wsb = torch.empty(need, dtype=torch.uint8, device="cuda")
+        outs = fq.alloc_q2d_outputs([j])
+        fq.q2d_batch_into([j], outs, wsb, params)
+        tt = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fq.q2d_batch_into([j], outs, wsb, params)
+            e1.record()
+            e1.synchronize()
+            tt.append(e0.elapsed_time(e1))
+        alone += sorted(tt)[1]
+        del wsb, outs
+    log(f"[batch] {ms:.3f} ms per graph replay of 16 jobs ({npts} values); one call per job: "
+        f"{alone:.3f} ms")
+    return {"workload": "16 seeded cubes, edges U{64..384} (FP32, 4-12 charges), seed grids "
+                        "U{128,256,512,1024}^2 on z=0, one persistent launch in a HIP graph",
+            "value": npts / (ms * 1e-3), "unit": UNIT, "ms_per_batch": ms, "values": npts,
+            "one_call_per_job_ms": alone, "batching_gain": alone / ms,
+            "params": {"block": params.block, "waves_per_cu": params.waves_per_cu}}
+
+
 def cpu_baseline(w, side: int):
     """The oracle on a bounded sample: a side x side block of the same seed grid
     (centre of the map), traced and assembled on the host cores."""
@@ -174,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--cpu-side", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this tracer runs on ONE GPU (no multi-GPU path is built); "
@@ -232,6 +292,8 @@ def main():
     if other is not None:
         out["f64_form"] = {"value": npts / (other["ms"] * 1e-3), "ms_per_step": other["ms"],
                            "trace_ms": other["trace_ms"]}
+    if not args.no_batch:
+        out["batch"] = run_batch(args.seed, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, args.cpu_side)
         log(f"cpu baseline: {cb}")

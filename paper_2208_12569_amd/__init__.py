@@ -196,29 +196,71 @@ def _alloc_map(npts: int, shape, device, want_lines: bool):
     return m, s
 
 
-def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
-              stream=None, ws=None) -> list:
-    """Q/Tw/length maps for several (B, grid, plane) triples in ONE persistent launch."""
+def _batch_args(jobs, params: Params, outs: list):
+    n = len(jobs)
+    fields = (_lib.fq_field * n)()
+    planes = (_lib.fq_plane * n)()
+    maps = (_lib.fq_map * n)()
+    for j, (B, grid, pl) in enumerate(jobs):
+        fields[j] = _field(B, grid)
+        planes[j] = _plane(pl)
+        m = outs[j]
+        s = _lib.fq_map()
+        s.q = m["q"].data_ptr()
+        s.tw = m["tw"].data_ptr()
+        s.length = m["length"].data_ptr()
+        s.status = m["status"].data_ptr()
+        if "lines" in m:
+            s.lines = _lines_struct(m["lines"])
+        maps[j] = s
+    return fields, planes, maps, params.c()
+
+
+def q2d_workspace_size(jobs: Sequence, params: Optional[Params] = None) -> int:
+    """Workspace bytes fastqsl_q2d needs for these (B, grid, plane) jobs."""
     lib = _lib.load()
     params = params or Params()
     n = len(jobs)
     fields = (_lib.fq_field * n)()
     planes = (_lib.fq_plane * n)()
-    maps = (_lib.fq_map * n)()
-    outs = []
     for j, (B, grid, pl) in enumerate(jobs):
         fields[j] = _field(B, grid)
         planes[j] = _plane(pl)
-        m, s = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines)
-        maps[j] = s
-        outs.append(m)
     p = params.c()
     need = lib.fastqsl_q2d_workspace_size(fields, planes, n, C.byref(p))
     if need == 0:
         raise ValueError("invalid field, plane or parameters (or an unsupported combination)")
+    return int(need)
+
+
+def alloc_q2d_outputs(jobs: Sequence, want_lines: bool = False) -> list:
+    """Output maps for q2d_batch_into (one dict of CUDA tensors per job)."""
+    outs = []
+    for B, grid, pl in jobs:
+        m, _ = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines)
+        outs.append(m)
+    return outs
+
+
+def q2d_batch_into(jobs: Sequence, outs: list, ws, params: Optional[Params] = None,
+                   stream=None) -> None:
+    """fastqsl_q2d on preallocated outputs and workspace: no allocation, no
+    synchronisation, so the call can be captured into a HIP graph."""
+    lib = _lib.load()
+    params = params or Params()
+    fields, planes, maps, p = _batch_args(jobs, params, outs)
+    _lib.check(lib.fastqsl_q2d(fields, planes, len(jobs), C.byref(p), maps, ws.data_ptr(),
+                               ws.numel(), _stream(stream)), "fastqsl_q2d")
+
+
+def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
+              stream=None, ws=None) -> list:
+    """Q/Tw/length maps for several (B, grid, plane) triples in ONE persistent launch."""
+    params = params or Params()
+    need = q2d_workspace_size(jobs, params)
     w = _workspace(need, jobs[0][0].device, ws)
-    _lib.check(lib.fastqsl_q2d(fields, planes, n, C.byref(p), maps, w.data_ptr(), w.numel(),
-                               _stream(stream)), "fastqsl_q2d")
+    outs = alloc_q2d_outputs(jobs, want_lines)
+    q2d_batch_into(jobs, outs, w, params, stream)
     for m in outs:
         m["_ws"] = w
     return outs

@@ -1,0 +1,139 @@
+"""Autotuner for the tracer's launch shape and step-control tolerance.
+
+The tracer keeps one half line per lane and refills idle lanes with one atomic per
+wave, so its launch has two free knobs: the block size and the resident waves per
+CU the persistent grid is sized for (fewer waves trade latency hiding for cache
+footprint). The step-control tolerance tol_perp trades accuracy for steps. The
+tuner times the candidates on the caller's own jobs with HIP events and, for the
+tolerance, accepts only values whose maps stay within a fraction of the accuracy
+bar (relative 1e-4 on log10 Q where Q < 1e8, 1e-5 on Tw, 1e-6 box units on
+footpoints, growing as sqrt(Q/1e4) above Q = 1e4) against the all-FP64 form run at
+a much tighter tolerance on the same GPU.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+from . import (FQ_PREC_F64, ST_EDGE, ST_FATAL, ST_MIXEDFACE, Params, _torch,
+               alloc_q2d_outputs, q2d_batch_into, q2d_workspace_size)
+
+BAR_LOGQ = 1e-4
+BAR_TW = 1e-5
+BAR_FOOT = 1e-6
+
+_CACHE: dict = {}
+
+
+def _key(jobs, params: Params):
+    return (tuple((tuple(B.shape), str(B.dtype), pl.nu, pl.nv) for B, _, pl in jobs),
+            params.precision, params.want_tw)
+
+
+def _timed(jobs, params: Params, outs, ws, reps: int) -> float:
+    """Median device time (ms) of `reps` calls on the current stream."""
+    torch = _torch()
+    q2d_batch_into(jobs, outs, ws, params)  # warm
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        q2d_batch_into(jobs, outs, ws, params)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune_launch(jobs: Sequence, params: Optional[Params] = None, blocks=(64, 128, 256),
+                waves=(0, 4, 8, 12), reps: int = 3) -> tuple:
+    """Pick (block, waves_per_cu) by timing; returns (Params, {(block, waves): ms})."""
+    torch = _torch()
+    params = params or Params()
+    jobs = list(jobs)
+    base = dataclasses.replace(params, stats=None, events=None)
+    need = q2d_workspace_size(jobs, base)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=jobs[0][0].device)
+    outs = alloc_q2d_outputs(jobs)
+    table = {}
+    for b in blocks:
+        for w in waves:
+            cand = dataclasses.replace(base, block=b, waves_per_cu=w)
+            table[(b, w)] = _timed(jobs, cand, outs, ws, reps)
+    best = min(table, key=table.get)
+    return dataclasses.replace(params, block=best[0], waves_per_cu=best[1]), table
+
+
+def map_errors(test: dict, ref: dict) -> dict:
+    """Errors of one q2d map (with lines) against a reference map, on the points
+    where both succeed, no stencil line ends near a box edge and Q < 1e8."""
+    torch = _torch()
+    st_t = test["status"].to(torch.int32)
+    st_r = ref["status"].to(torch.int32)
+    bad = ST_FATAL | ST_MIXEDFACE | ST_EDGE
+    qr, qt = ref["q"], test["q"]
+    mask = (((st_t | st_r) & bad) == 0) & torch.isfinite(qr) & torch.isfinite(qt) & (qr < 1e8)
+    out = {"points": int(mask.sum()), "status_mismatch": int(((st_t != st_r) & (((st_t | st_r) & ST_EDGE) == 0)).sum())}
+    if out["points"] == 0:
+        return dict(out, logq=math.inf, tw=math.inf, foot=math.inf)
+    lr = torch.log10(qr[mask])
+    lt = torch.log10(qt[mask])
+    out["logq"] = float((torch.abs(lt - lr) / torch.clamp(torch.abs(lr), min=math.log10(2.0))).max())
+    out["tw"] = float(torch.abs(test["tw"][mask] - ref["tw"][mask]).max())
+    foot = 0.0
+    if "lines" in test and "lines" in ref:
+        scale = torch.clamp(torch.sqrt(qr / 1e4), min=1.0)[mask]
+        for k in ("end_b", "end_f"):
+            d = torch.abs(test["lines"][k] - ref["lines"][k]).amax(dim=-1).reshape(qr.shape)
+            foot = max(foot, float((d[mask] / scale).max()))
+    out["foot"] = foot
+    return out
+
+
+def tune_tol(jobs: Sequence, params: Optional[Params] = None,
+             tols=(1e-5, 3e-6, 1e-6), ref_tol: float = 1e-9, margin: float = 0.5,
+             reps: int = 3) -> tuple:
+    """Loosest-and-fastest tol_perp whose maps stay within margin x the bar against
+    the all-FP64 form at ref_tol; returns (Params, report)."""
+    torch = _torch()
+    params = params or Params()
+    jobs = list(jobs)
+    base = dataclasses.replace(params, stats=None, events=None)
+    ref_p = dataclasses.replace(base, precision=FQ_PREC_F64, tol_perp=ref_tol)
+    need = max(q2d_workspace_size(jobs, base), q2d_workspace_size(jobs, ref_p))
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=jobs[0][0].device)
+    ref = alloc_q2d_outputs(jobs, want_lines=True)
+    q2d_batch_into(jobs, ref, ws, ref_p)
+    test = alloc_q2d_outputs(jobs, want_lines=True)
+    report = {}
+    for t in tols:
+        cand = dataclasses.replace(base, tol_perp=t)
+        ms = _timed(jobs, cand, test, ws, reps)
+        errs = [map_errors(a, b) for a, b in zip(test, ref)]
+        worst = {k: max(e[k] for e in errs) for k in ("logq", "tw", "foot", "status_mismatch")}
+        ok = (worst["logq"] <= margin * BAR_LOGQ and worst["tw"] <= margin * BAR_TW
+              and worst["foot"] <= margin * BAR_FOOT)
+        report[t] = dict(worst, ms=ms, ok=ok)
+    good = [t for t in tols if report[t]["ok"]]
+    if not good:
+        return dataclasses.replace(params, tol_perp=min(tols)), report
+    best = min(good, key=lambda t: report[t]["ms"])
+    return dataclasses.replace(params, tol_perp=best), report
+
+
+def autotune(jobs: Sequence, params: Optional[Params] = None, tune_tolerance: bool = False,
+             **kw) -> Params:
+    """Tuned Params for these jobs (cached per shapes, precision and Tw flag)."""
+    params = params or Params()
+    key = _key(jobs, params) + (tune_tolerance,)
+    if key in _CACHE:
+        return dataclasses.replace(params, **_CACHE[key])
+    p, _ = tune_launch(jobs, params, **{k: v for k, v in kw.items() if k in ("blocks", "waves", "reps")})
+    if tune_tolerance:
+        p, _ = tune_tol(jobs, p, **{k: v for k, v in kw.items() if k in ("tols", "ref_tol", "margin")})
+    _CACHE[key] = {"block": p.block, "waves_per_cu": p.waves_per_cu, "tol_perp": p.tol_perp}
+    return p

@@ -304,23 +304,32 @@ def config_c3(seed: int = 0, nvox=(256, 256, 128)) -> Workload:
                     meta={"charges": (pos, q), "tube_q": qt})
 
 
+def c4_specs(seed: int = 0, njobs: int = 16, edge=(64, 384), sides=(128, 256, 512, 1024),
+             ncharge=(4, 12)) -> list:
+    """The draws of the uneven batch: per cube (name, edge E, charge positions,
+    strengths, seed-grid side)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(njobs):
+        E = int(rng.integers(edge[0], edge[1] + 1))
+        nc = int(rng.integers(ncharge[0], ncharge[1] + 1))
+        side = int(rng.choice(np.asarray(sides)))
+        pos, q = draw_charges(rng, nc)
+        out.append((f"c4_job{j}_E{E}_S{side}", E, pos, q, side))
+    return out
+
+
 def config_c4(seed: int = 0, njobs: int = 16, edge=(64, 384), sides=(128, 256, 512, 1024),
               ncharge=(4, 12)) -> List[Workload]:
     """Uneven batch: per cube an edge E ~ U{64..384} (cubic, dx = 1/(E-1)), float32,
     U{4..12} seeded charges, and a seed-grid side drawn from {128, 256, 512, 1024}
     on z = 0."""
-    rng = np.random.default_rng(seed)
     jobs = []
-    for j in range(njobs):
-        E = int(rng.integers(edge[0], edge[1] + 1))
-        nc = int(rng.integers(ncharge[0], ncharge[1] + 1))
-        side = int(rng.choice(np.asarray(sides)))
+    for name, E, pos, q, side in c4_specs(seed, njobs, edge, sides, ncharge):
         g = cubic_grid(E, E, E)
-        pos, q = draw_charges(rng, nc)
         B = np.zeros((3,) + g.shape, dtype=np.float32)
         charges_field(g, pos, q, dtype=np.float32, out=B)
-        jobs.append(Workload(f"c4_job{j}_E{E}_S{side}", g, B, plane=plane_z0(side),
-                             meta={"charges": (pos, q)}))
+        jobs.append(Workload(name, g, B, plane=plane_z0(side), meta={"charges": (pos, q)}))
     return jobs
 
 
