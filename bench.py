@@ -198,6 +198,60 @@ def run_batch(seed: int, steps: int, warmup: int):
             "params": {"block": params.block, "waves_per_cu": params.waves_per_cu}}
 
 
+def run_adjoint(seed: int, steps: int, warmup: int):
+    """The adjoint workload: the 256x256 map of a 128x128x96 FP32 cube from 8 point
+    charges, and the gradient of a log10 Q + footpoint loss against a target map
+    with respect to the node values (all-FP64 form, checkpoints every 32 accepted
+    steps): one forward map plus one fastqsl_backward call per step."""
+    import torch
+
+    import paper_2208_12569_amd as fq
+    import synth
+    from synth.torch_fields import charges_field_torch
+
+    w, target = synth.config_c5(seed)
+    g, pl = w.grid, w.plane
+    pos, q = w.meta["charges"]
+    B = charges_field_torch(g, pos, q, torch.float32, "cuda")
+    tB = charges_field_torch(g, *target["charges"], torch.float32, "cuda")
+    p = fq.Params(precision=fq.FQ_PREC_F64)
+    tq = fq.q2d(tB, g, pl, p)["q"]
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    gb = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
+
+    def step(st=None):
+        r = fq.q2d(B, g, pl, p, want_lines=True)
+        qq = r["q"]
+        m = torch.isfinite(qq) & torch.isfinite(tq) & (qq < 1e8) & (tq < 1e8)
+        lq = torch.log10(torch.where(m, qq, torch.ones_like(qq)))
+        lt = torch.log10(torch.where(m, tq, torch.ones_like(tq)))
+        dq = torch.where(m, 2.0 * (lq - lt) / (qq * math.log(10.0)), torch.zeros_like(qq)) / m.sum()
+        gb.zero_()
+        fq.backward(B, g, pl, fq.Params(precision=fq.FQ_PREC_F64, stats=st), 32, dq=dq.reshape(-1),
+                    gb=gb)
+
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step(stats)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    st = [int(x) // steps for x in stats.tolist()]
+    npts = pl.nu * pl.nv
+    log(f"[adjoint] {ms:.3f} ms per map + gradient; half lines differentiated {st[0]}, "
+        f"accepted steps reversed {st[1]}, replay mismatches {st[2]}")
+    return {"workload": "128x128x96 FP32 cube, 8 point charges, 256x256 seeds on z=0; forward "
+                        "map + dL/dB of a log10 Q loss vs a target map (FP64, checkpoint every "
+                        "32 accepted steps)",
+            "value": npts / (ms * 1e-3), "unit": "map points with gradient/s", "ms_per_step": ms,
+            "half_lines": st[0], "steps_reversed": st[1], "replay_mismatches": st[2]}
+
+
 def cpu_baseline(w, side: int):
     """The oracle on a bounded sample: a side x side block of the same seed grid
     (centre of the map), traced and assembled on the host cores."""
@@ -234,6 +288,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--cpu-side", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this tracer runs on ONE GPU (no multi-GPU path is built); "
@@ -294,6 +349,8 @@ def main():
                            "trace_ms": other["trace_ms"]}
     if not args.no_batch:
         out["batch"] = run_batch(args.seed, args.steps, args.warmup)
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, args.cpu_side)
         log(f"cpu baseline: {cb}")

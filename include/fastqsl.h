@@ -179,15 +179,35 @@ int fastqsl_q3d(const fq_field *f, const fq_voxels *v, const fq_params *p, const
                 void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
- * fastqsl_backward — reverse-mode derivative of a q2d map on one field with
- * respect to the field's node values: given dL/dQ, dL/dTw (nu*nv doubles each)
- * and dL/d end_b, dL/d end_f (nu*nv x 3 doubles each) — device arrays, any may
- * be NULL — and the same inputs as the forward call, ADD dL/dBx, dL/dBy, dL/dBz
- * to gb[0..2] (device float64 planes shaped like the field). Lines are re-traced
- * forward with their step sequence recorded, and the adjoint is taken back
- * through the accepted steps (discrete adjoint, step sizes held fixed),
- * recomputed in segments of `segment` accepted steps from checkpoints kept in
- * the workspace. Form FQ_PREC_F64 only.
+ * fastqsl_backward — reverse-mode derivative of one q2d map with respect to the
+ * field's node values. Not an operation of the paper: it differentiates the map of
+ * fastqsl_q2d (Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of
+ * Eq. tw) so that a field model can be fitted to target maps.
+ *   f, pl, p   the same inputs as the forward call; p->precision must be
+ *              FQ_PREC_F64 and the seed plane must lie on a box face (no rotated
+ *              S0), else FQ_EUNSUPPORTED. Use the forward call's parameters: the
+ *              lines are traced again with them.
+ *   segment    accepted steps between checkpoints, 1..4096.
+ *   dq, dtw    dL/dQ and dL/dTw, nu*nv device doubles each (map order), or NULL;
+ *   dend_b, dend_f  dL/d(end points), nu*nv x 3 device doubles each, or NULL.
+ *              Non-finite entries and points with a failed line are ignored;
+ *              points whose Q is NaN contribute no dL/dQ.
+ *   gb         three device double planes shaped like the field: dL/dBx, dL/dBy,
+ *              dL/dBz are ADDED to them.
+ *   ws         caller workspace of fastqsl_backward_workspace_size() bytes (256-byte
+ *              aligned). It holds a pool of 2 + ceil(2048/segment) checkpoints of
+ *              64 bytes per half line (shared by all half lines: room for 2048
+ *              accepted steps per half line on average), per-half adjoints, node
+ *              gradients and replay buffers.
+ * The lines are traced again with the lane state kept every `segment` accepted
+ * steps; each segment is then replayed from its checkpoint with the same stepping
+ * code and its accepted steps are differentiated last to first (the discrete
+ * adjoint with the step lengths held fixed). A half line that finds the pool
+ * exhausted is dropped (it contributes nothing). If p->stats is set, stats[0..3]
+ * get the half lines differentiated, the accepted steps reversed, the replays that
+ * failed to reproduce the forward pass (expected 0) and the half lines with a
+ * nonzero adjoint that were dropped (expected 0).
+ * Asynchronous on `stream`; allocates nothing.
  * ------------------------------------------------------------------------------- */
 size_t fastqsl_backward_workspace_size(const fq_field *f, const fq_plane *pl,
                                        const fq_params *p, int segment);

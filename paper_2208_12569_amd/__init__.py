@@ -13,6 +13,7 @@ float32 or float64, on the current CUDA/HIP device. `grid` is any object with
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -290,3 +291,55 @@ def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = Fal
                                w.numel(), _stream(stream)), "fastqsl_q3d")
     m["_ws"] = w
     return m
+
+
+def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32, dq=None, dtw=None,
+             dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
+    """Reverse-mode derivative of the q2d map of (B, grid, plane) with respect to the
+    field's node values (fastqsl_backward; all-FP64 form, seed plane on a box face).
+
+    dq, dtw: CUDA float64 tensors of nu*nv values (dL/dQ, dL/dTw), dend_b, dend_f:
+    nu*nv x 3 (dL/d end points); any may be None. The result is ADDED into gb, a
+    CUDA float64 tensor shaped like B (allocated as zeros if None), and returned.
+    Lines are re-traced with checkpoints every `segment` accepted steps."""
+    torch = _torch()
+    lib = _lib.load()
+    params = params or Params(precision=FQ_PREC_F64)
+    if params.precision != FQ_PREC_F64:
+        raise ValueError("the derivative is taken in the all-FP64 form (precision=FQ_PREC_F64)")
+    f = _field(B, grid)
+    pl = _plane(plane)
+    p = params.c()
+    if gb is None:
+        gb = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
+    if gb.dtype != torch.float64 or gb.shape != B.shape or not gb.is_contiguous():
+        raise ValueError("gb must be a contiguous float64 tensor shaped like B")
+    npts = plane.nu * plane.nv
+
+    def arg(t, shape):
+        if t is None:
+            return None, None
+        t = t.to(device=B.device, dtype=torch.float64).contiguous()
+        if t.numel() != math.prod(shape):
+            raise ValueError(f"gradient of shape {tuple(t.shape)} does not fit {shape}")
+        return t, t.data_ptr()
+
+    dq_t, dq_p = arg(dq, (npts,))
+    dtw_t, dtw_p = arg(dtw, (npts,))
+    db_t, db_p = arg(dend_b, (npts, 3))
+    df_t, df_p = arg(dend_f, (npts, 3))
+    need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
+    if need == 0:
+        raise ValueError("invalid or unsupported backward call (FP64 form, plane on a box face, "
+                         "1 <= segment <= 4096)")
+    w = _workspace(need, B.device, ws)
+    g3 = (C.c_void_p * 3)(gb[0].data_ptr(), gb[1].data_ptr(), gb[2].data_ptr())
+    _lib.check(lib.fastqsl_backward(C.byref(f), C.byref(pl), C.byref(p), int(segment), dq_p, dtw_p,
+                                    db_p, df_p, g3, w.data_ptr(), w.numel(), _stream(stream)),
+               "fastqsl_backward")
+    if stream is not None:
+        # temporaries freed here stay reserved until the caller's stream is done
+        for t in (dq_t, dtw_t, db_t, df_t, w):
+            if t is not None:
+                t.record_stream(stream)
+    return gb

@@ -1,0 +1,646 @@
+// Reverse-mode derivative of a Q/Tw map with respect to the field's node values.
+//
+// The map is a composition: node values -> (curl by differences) -> cell
+// polynomials -> traced half lines (ends, Tw) -> Method-I stencil (Q, Section 2.1
+// Eq. D+-2 / D+-3, Section 1 Eq. Q+-) with the normal fields Bn0, Bn1, Bn2
+// interpolated from the nodes. Its adjoint runs the other way:
+//   map_backward   dL/dQ, dL/dTw, dL/d(ends) -> dL/d(end of every half line),
+//                  dL/d(Tw of every half line), and dL/dB at the nodes through
+//                  the trilinear Bn0, Bn1, Bn2;
+//   trace_backward the discrete adjoint of every accepted RKF45 step of a half
+//                  line, last to first, with the step lengths held fixed: the
+//                  forward pass kept the lane state every `seg` accepted steps
+//                  (chained per half line in one checkpoint pool),
+//                  and each segment is replayed from its checkpoint with the same
+//                  stepping code (bit-identical), its accepted steps recorded, and
+//                  then swept in reverse; gradients with respect to the 8 corner
+//                  values of B and curl B of each cell go to the nodes;
+//   grad_planes    adds dL/dB of the nodes and the transpose of the curl
+//                  differences applied to dL/d(curl B) into the caller's planes.
+// All of it is FP64.
+#include <math.h>
+
+#include "fq_internal.h"
+#include "stencil_dev.h"
+#include "trace_core.h"
+#include "trace_dev.h"
+
+namespace fq {
+namespace {
+
+using namespace dev;
+using namespace sten;
+
+// ----------------------------------------------------------------------------------
+// Trilinear weights of the caller's planes at a physical point (the cell choice of
+// the FP64 interpolation), and their derivatives along x, y, z.
+struct Tri {
+    int64_t node[8];
+    double w[8];
+    double dw[8][3];
+};
+
+__device__ void tri_of(const MapJob &m, const double r[3], Tri &t)
+{
+    int c[3];
+    double u[3];
+    for (int a = 0; a < 3; a++) {
+        const double g = (r[a] - m.origin[a]) / m.spacing[a];
+        int ci = (int)floor(g);
+        ci = ci < 0 ? 0 : (ci > m.n[a] - 2 ? m.n[a] - 2 : ci);
+        c[a] = ci;
+        u[a] = g - ci;
+    }
+    const int64_t sy = m.n[0], sz = (int64_t)m.n[0] * m.n[1];
+    const int64_t base = c[2] * sz + c[1] * sy + c[0];
+    for (int q = 0; q < 8; q++) {
+        const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+        const double wx = ix ? u[0] : 1.0 - u[0], wy = iy ? u[1] : 1.0 - u[1],
+                     wz = iz ? u[2] : 1.0 - u[2];
+        const double sx = ix ? 1.0 : -1.0, syy = iy ? 1.0 : -1.0, szz = iz ? 1.0 : -1.0;
+        t.node[q] = base + ix + iy * sy + iz * sz;
+        t.w[q] = wx * wy * wz;
+        t.dw[q][0] = sx * wy * wz / m.spacing[0];
+        t.dw[q][1] = wx * syy * wz / m.spacing[1];
+        t.dw[q][2] = wx * wy * szz / m.spacing[2];
+    }
+}
+
+__device__ __forceinline__ double plane_at(const MapJob &m, int comp, int64_t o)
+{
+    return m.dtype == FQ_DT_F32 ? (double)((const float *)m.b[comp])[o]
+                                : ((const double *)m.b[comp])[o];
+}
+
+// d B_comp / d r at the point of t
+__device__ void grad_comp(const MapJob &m, const Tri &t, int comp, double g[3])
+{
+    g[0] = g[1] = g[2] = 0.0;
+    for (int q = 0; q < 8; q++) {
+        const double v = plane_at(m, comp, t.node[q]);
+        g[0] += t.dw[q][0] * v;
+        g[1] += t.dw[q][1] * v;
+        g[2] += t.dw[q][2] * v;
+    }
+}
+
+// adjoint of the two in-face coordinates of an end (face f) -> end point adjoint
+__device__ __forceinline__ void inface_adj(int face, const double ub[2], double eb[3])
+{
+    const int a = face >> 1;
+    eb[a == 0 ? 1 : 0] += ub[0];
+    eb[a == 2 ? 1 : 2] += ub[1];
+}
+
+__device__ __forceinline__ void add3(double *dst, const double v[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (v[a] != 0.0) atomicAdd(dst + a, v[a]);
+}
+
+// End adjoints of one line of the stencil, kept in S1 / S2 order.
+struct LineAdj {
+    double e1[3], e2[3];
+};
+
+// Adjoint of the derivatives along one S0 axis (d1 of (u1,v1), d2 of (u2,v2)) onto
+// the in-face coordinates of the lines the difference used.
+__device__ void axis_adj(int rule, const Line &c, const Line *m, const Line *p, double d,
+                         const double d1b[2], const double d2b[2], LineAdj &cb, LineAdj &mb,
+                         LineAdj &pb)
+{
+    double s_p = 0.0, s_m = 0.0, s_c = 0.0;
+    if (rule == RULE_CENTRAL) s_p = 0.5 / d, s_m = -0.5 / d;
+    else if (rule == RULE_PLUS) s_p = 1.0 / d, s_c = -1.0 / d;
+    else s_c = 1.0 / d, s_m = -1.0 / d;
+    double u1[2], u2[2];
+    if (s_p != 0.0) {
+        u1[0] = s_p * d1b[0], u1[1] = s_p * d1b[1];
+        u2[0] = s_p * d2b[0], u2[1] = s_p * d2b[1];
+        inface_adj(p->f1, u1, pb.e1);
+        inface_adj(p->f2, u2, pb.e2);
+    }
+    if (s_m != 0.0) {
+        u1[0] = s_m * d1b[0], u1[1] = s_m * d1b[1];
+        u2[0] = s_m * d2b[0], u2[1] = s_m * d2b[1];
+        inface_adj(m->f1, u1, mb.e1);
+        inface_adj(m->f2, u2, mb.e2);
+    }
+    if (s_c != 0.0) {
+        u1[0] = s_c * d1b[0], u1[1] = s_c * d1b[1];
+        u2[0] = s_c * d2b[0], u2[1] = s_c * d2b[1];
+        inface_adj(c.f1, u1, cb.e1);
+        inface_adj(c.f2, u2, cb.e2);
+    }
+}
+
+// S1 / S2 end adjoints of line l -> the half records
+__device__ void push_line(const MapJob &m, int64_t l, const Line &L, const LineAdj &a,
+                          double *lam_end)
+{
+    const int64_t hb = l, hf = m.nlines + l;
+    const int64_t s1 = L.swapped ? hf : hb, s2 = L.swapped ? hb : hf;
+    add3(lam_end + 3 * s1, a.e1);
+    add3(lam_end + 3 * s2, a.e2);
+}
+
+__device__ void bn_adj(const MapJob &m, const double r[3], int comp, double gbn, double eb[3],
+                       double *gnode, int64_t nn)
+{
+    Tri t;
+    tri_of(m, r, t);
+    if (eb) {
+        double g[3];
+        grad_comp(m, t, comp, g);
+        for (int a = 0; a < 3; a++) eb[a] += gbn * g[a];
+    }
+    for (int q = 0; q < 8; q++) atomicAdd(gnode + comp * nn + t.node[q], gbn * t.w[q]);
+}
+
+__global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
+                                    const double *__restrict__ dtw,
+                                    const double *__restrict__ dend_b,
+                                    const double *__restrict__ dend_f, double *lam_end,
+                                    double *lam_tw, double *gnode)
+{
+    const int64_t np = m.nu * m.nv;
+    const int64_t nn = (int64_t)m.n[0] * m.n[1] * m.n[2];
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = pt / m.nu, i = pt - j * m.nu;
+        Line c;
+        read_line(m.rec, m.nlines, pt, c);
+        if (c.st & kFatal) continue;
+        const int64_t hb = pt, hf = m.nlines + pt;
+        // Tw of the point is the sum of its two halves
+        if (dtw && isfinite(dtw[pt])) {
+            lam_tw[hb] = dtw[pt];
+            lam_tw[hf] = dtw[pt];
+        }
+        if (dend_b) {
+            const double v[3] = {dend_b[3 * pt], dend_b[3 * pt + 1], dend_b[3 * pt + 2]};
+            if (isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])) add3(lam_end + 3 * hb, v);
+        }
+        if (dend_f) {
+            const double v[3] = {dend_f[3 * pt], dend_f[3 * pt + 1], dend_f[3 * pt + 2]};
+            if (isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])) add3(lam_end + 3 * hf, v);
+        }
+        if (!dq) continue;
+        const double gq = dq[pt];
+        if (!(gq != 0.0) || !isfinite(gq)) continue;
+        Line xm, xp, ym, yp;
+        const bool hxm = i > 0, hxp = i < m.nu - 1, hym = j > 0, hyp = j < m.nv - 1;
+        if (hxm) read_line(m.rec, m.nlines, pt - 1, xm);
+        if (hxp) read_line(m.rec, m.nlines, pt + 1, xp);
+        if (hym) read_line(m.rec, m.nlines, pt - m.nu, ym);
+        if (hyp) read_line(m.rec, m.nlines, pt + m.nu, yp);
+        const Line *pxm = hxm ? &xm : nullptr, *pxp = hxp ? &xp : nullptr;
+        const Line *pym = hym ? &ym : nullptr, *pyp = hyp ? &yp : nullptr;
+        const int rx = axis_rule(c, pxm, pxp), ry = axis_rule(c, pym, pyp);
+        if (rx == RULE_NONE || ry == RULE_NONE) continue;  // Q = NaN there
+        uint16_t st = 0;
+        double ax1[2], ax2[2], ay1[2], ay2[2];
+        axis_diff(c, pxm, pxp, m.d0, ax1, ax2, st);
+        axis_diff(c, pym, pyp, m.d1, ay1, ay2, st);
+        const double j00 = ax1[0], j01 = ay1[0], j10 = ax1[1], j11 = ay1[1];
+        const double k00 = ax2[0], k01 = ay2[0], k10 = ax2[1], k11 = ay2[1];
+        const double m00 = k00 * j11 - k01 * j10;
+        const double m01 = -k00 * j01 + k01 * j00;
+        const double m10 = k10 * j11 - k11 * j10;
+        const double m11 = -k10 * j01 + k11 * j00;
+        double r0[3], B0[3], B1[3], B2[3];
+        point_pos(m, i, j, 0, r0);
+        field64(m, r0, B0);
+        field64(m, c.e1, B1);
+        field64(m, c.e2, B2);
+        const double bn0 = B0[0] * m.normal[0] + B0[1] * m.normal[1] + B0[2] * m.normal[2];
+        const int a1 = c.f1 >> 1, a2 = c.f2 >> 1;
+        const double bn1 = B1[a1], bn2 = B2[a2];
+        const double nrm = m00 * m00 + m01 * m01 + m10 * m10 + m11 * m11;
+        const double A = fabs(bn1 * bn2) / (bn0 * bn0);
+        const double Q = nrm * A;
+        if (!isfinite(Q) || !(bn1 != 0.0) || !(bn2 != 0.0)) continue;
+        // Q = ||M||^2 A, M = J2 adj(J1)
+        const double s = 2.0 * gq * A;
+        const double M00 = s * m00, M01 = s * m01, M10 = s * m10, M11 = s * m11;
+        const double kb00 = M00 * j11 - M01 * j01, kb01 = -M00 * j10 + M01 * j00;
+        const double kb10 = M10 * j11 - M11 * j01, kb11 = -M10 * j10 + M11 * j00;
+        const double jb00 = M01 * k01 + M11 * k11, jb01 = -M01 * k00 - M11 * k10;
+        const double jb10 = -M00 * k01 - M10 * k11, jb11 = M00 * k00 + M10 * k10;
+        LineAdj ca = {}, xma = {}, xpa = {}, yma = {}, ypa = {};
+        {
+            const double d1b[2] = {jb00, jb10}, d2b[2] = {kb00, kb10};
+            axis_adj(rx, c, pxm, pxp, m.d0, d1b, d2b, ca, xma, xpa);
+        }
+        {
+            const double d1b[2] = {jb01, jb11}, d2b[2] = {kb01, kb11};
+            axis_adj(ry, c, pym, pyp, m.d1, d1b, d2b, ca, yma, ypa);
+        }
+        // the normal fields: Q ~ |Bn1 Bn2| / Bn0^2
+        bn_adj(m, c.e1, a1, gq * Q / bn1, ca.e1, gnode, nn);
+        bn_adj(m, c.e2, a2, gq * Q / bn2, ca.e2, gnode, nn);
+        const double gb0 = -2.0 * gq * Q / bn0;
+        for (int comp = 0; comp < 3; comp++)
+            if (m.normal[comp] != 0.0) bn_adj(m, r0, comp, gb0 * m.normal[comp], nullptr, gnode, nn);
+        push_line(m, pt, c, ca, lam_end);
+        if (rx != RULE_PLUS) push_line(m, pt - 1, xm, xma, lam_end);
+        if (rx != RULE_MINUS) push_line(m, pt + 1, xp, xpa, lam_end);
+        if (ry != RULE_PLUS) push_line(m, pt - m.nu, ym, yma, lam_end);
+        if (ry != RULE_MINUS) push_line(m, pt + m.nu, yp, ypa, lam_end);
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Discrete adjoint of one accepted RKF45 step (FP64).
+
+// value and gradient (local coordinates) of P(u,v,w) in monomial form
+__device__ __forceinline__ void poly_grad(const double c[8], double u, double v, double w,
+                                          double g[3])
+{
+    g[0] = c[1] + c[4] * v + c[5] * w + c[7] * v * w;
+    g[1] = c[2] + c[4] * u + c[6] * w + c[7] * u * w;
+    g[2] = c[3] + c[5] * u + c[6] * v + c[7] * u * v;
+}
+
+__device__ __forceinline__ double tri_w(int q, double u, double v, double w)
+{
+    return ((q & 1) ? u : 1.0 - u) * ((q & 2) ? v : 1.0 - v) * ((q & 4) ? w : 1.0 - w);
+}
+
+// Fehlberg 4(5), fifth-order weights (the tableau the forward step uses)
+__constant__ double kA[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+__constant__ double kB[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0,
+                             2.0 / 55.0};
+
+// The accepted step maps local position p to p' (a plain step of arc length H, or a
+// landing with the axis coordinate as the independent variable, H = face - p_axis)
+// and adds H * sum b_s G_s / g_s to Tw (G = twk (J.B)/|B|^2, g = 1 or dp_axis/ds).
+// Given lam = dL/dp' and ltw = dL/dTw, returns lam = dL/dp and adds dL/d(corner
+// values) of B and curl B to gB, gJ.
+template <bool TW>
+__device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const StepRec &sr,
+                             const LaneConst<double> &K, double sgn, double lam[3], double ltw,
+                             double gB[3][8], double gJ[3][8])
+{
+    const double R[3] = {K.rx, K.ry, K.rz};
+    const double p[3] = {sr.p0, sr.p1, sr.p2};
+    const double H = sr.H;
+    const int ax = sr.axis;
+    double y[6][3], k[6][3], G[6], g[6];
+    for (int st = 0; st < 6; st++) {
+        for (int q = 0; q < 3; q++) {
+            double acc = 0.0;
+            for (int jj = 0; jj < st; jj++) acc += kA[st][jj] * k[jj][q];
+            y[st][q] = p[q] + H * acc;
+        }
+        double B[3], J[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; c++) B[c] = poly<double>(cb[c], y[st][0], y[st][1], y[st][2]);
+        if (TW)
+            for (int c = 0; c < 3; c++) J[c] = poly<double>(cj[c], y[st][0], y[st][1], y[st][2]);
+        const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        const double inv = 1.0 / sqrt(b2);
+        double F[3];
+        for (int c = 0; c < 3; c++) F[c] = sgn * inv * B[c] * R[c];
+        G[st] = TW ? K.twk * (J[0] * B[0] + J[1] * B[1] + J[2] * B[2]) * inv * inv : 0.0;
+        g[st] = ax >= 0 ? F[ax] : 1.0;
+        for (int c = 0; c < 3; c++) k[st][c] = F[c] / g[st];
+    }
+    // adjoint of the outputs that depend on the step: the landing axis ends exactly
+    // on its face, and a coordinate clamped to a box face is constant
+    const int cell[3] = {sr.c0, sr.c1, sr.c2};
+    const int nmax[3] = {K.nx - 2, K.ny - 2, K.nz - 2};
+    double lo[3];
+    for (int q = 0; q < 3; q++) {
+        double dy = 0.0;
+        for (int st = 0; st < 6; st++) dy += kB[st] * k[st][q];
+        const double nq = p[q] + H * dy;
+        const bool clamped = (nq > 1.0 && cell[q] == nmax[q]) || (nq < 0.0 && cell[q] == 0);
+        lo[q] = (q == ax || clamped) ? 0.0 : lam[q];
+    }
+    double mu[6][3];
+    double dH = 0.0;
+    for (int st = 0; st < 6; st++) {
+        for (int q = 0; q < 3; q++) mu[st][q] = H * kB[st] * lo[q];
+        dH += kB[st] * (k[st][0] * lo[0] + k[st][1] * lo[1] + k[st][2] * lo[2]);
+        if (TW) dH += ltw * kB[st] * G[st] / g[st];
+    }
+    double ln[3] = {lo[0], lo[1], lo[2]};
+    for (int st = 5; st >= 0; st--) {
+        const double u = y[st][0], v = y[st][1], w = y[st][2];
+        double B[3], J[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; c++) B[c] = poly<double>(cb[c], u, v, w);
+        if (TW)
+            for (int c = 0; c < 3; c++) J[c] = poly<double>(cj[c], u, v, w);
+        const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        const double inv = 1.0 / sqrt(b2);
+        const double tau = TW ? H * kB[st] * ltw : 0.0;
+        double Fb[3], Gb;
+        if (ax >= 0) {
+            const double ig = 1.0 / g[st];
+            const double mk = mu[st][0] * k[st][0] + mu[st][1] * k[st][1] + mu[st][2] * k[st][2];
+            for (int c = 0; c < 3; c++) Fb[c] = mu[st][c] * ig;
+            Gb = tau * ig;
+            Fb[ax] += -mk * ig - tau * G[st] * ig * ig;
+        } else {
+            for (int c = 0; c < 3; c++) Fb[c] = mu[st][c];
+            Gb = tau;
+        }
+        // F = sgn R (B / |B|)
+        double d[3], db[3];
+        for (int c = 0; c < 3; c++) {
+            d[c] = B[c] * inv;
+            db[c] = sgn * R[c] * Fb[c];
+        }
+        const double dd = db[0] * d[0] + db[1] * d[1] + db[2] * d[2];
+        double Bb[3], Jb[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; c++) Bb[c] = (db[c] - dd * d[c]) * inv;
+        if (TW && Gb != 0.0) {
+            // G = twk (J.B) / |B|^2
+            const double i2 = inv * inv;
+            const double jb = J[0] * B[0] + J[1] * B[1] + J[2] * B[2];
+            for (int c = 0; c < 3; c++) {
+                Jb[c] = K.twk * Gb * B[c] * i2;
+                Bb[c] += K.twk * Gb * (J[c] * i2 - 2.0 * jb * i2 * i2 * B[c]);
+            }
+        }
+        double yb[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; c++) {
+            double gr[3];
+            poly_grad(cb[c], u, v, w, gr);
+            for (int a = 0; a < 3; a++) yb[a] += Bb[c] * gr[a];
+            if (TW) {
+                poly_grad(cj[c], u, v, w, gr);
+                for (int a = 0; a < 3; a++) yb[a] += Jb[c] * gr[a];
+            }
+        }
+        for (int q = 0; q < 8; q++) {
+            const double wq = tri_w(q, u, v, w);
+            for (int c = 0; c < 3; c++) {
+                gB[c][q] += Bb[c] * wq;
+                if (TW) gJ[c][q] += Jb[c] * wq;
+            }
+        }
+        for (int a = 0; a < 3; a++) ln[a] += yb[a];
+        for (int jj = 0; jj < st; jj++) {
+            for (int a = 0; a < 3; a++) mu[jj][a] += H * kA[st][jj] * yb[a];
+            dH += kA[st][jj] * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
+        }
+    }
+    if (ax >= 0) ln[ax] -= dH;  // H = face - p_axis
+    for (int a = 0; a < 3; a++) lam[a] = ln[a];
+}
+
+// Captures the accepted step of a replayed trial.
+struct Capture {
+    int *axis;
+    double *H;
+    __device__ __forceinline__ void operator()(int) const {}
+    template <typename T> __device__ __forceinline__ void accepted(int a, T h) const
+    {
+        *axis = a;
+        *H = (double)h;
+    }
+};
+
+template <bool TW>
+__device__ void flush_cell(double *gnode, int64_t nn, int nx, int ny, int c0, int c1, int c2,
+                           double gB[3][8], double gJ[3][8])
+{
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t base = (int64_t)c2 * sz + (int64_t)c1 * sy + c0;
+    for (int q = 0; q < 8; q++) {
+        const int64_t o = base + (q & 1) + ((q >> 1) & 1) * sy + ((q >> 2) & 1) * sz;
+        for (int c = 0; c < 3; c++) {
+            if (gB[c][q] != 0.0) atomicAdd(gnode + c * nn + o, gB[c][q]);
+            gB[c][q] = 0.0;
+            if (TW) {
+                if (gJ[c][q] != 0.0) atomicAdd(gnode + (3 + c) * nn + o, gJ[c][q]);
+                gJ[c][q] = 0.0;
+            }
+        }
+    }
+}
+
+template <typename S, bool TW>
+__global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__restrict__ jobs,
+                                                            BwdParams bp)
+{
+    const TraceJob &J = jobs[0];
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= bp.nslots) return;
+    StepRec *buf = bp.buf + slot * bp.seg;
+    LaneConst<double> K;
+    K.nx = J.n[0];
+    K.ny = J.n[1];
+    K.nz = J.n[2];
+    K.rx = (double)J.rscale[0];
+    K.ry = (double)J.rscale[1];
+    K.rz = (double)J.rscale[2];
+    K.twk = (double)J.twk;
+    K.bnull2 = (double)Num<double>::null_rel * (double)(*J.bmax2);
+    K.max_steps = bp.max_steps;
+    const int64_t nn = (int64_t)K.nx * K.ny * K.nz;
+    unsigned long long n_half = 0, n_steps = 0, n_bad = 0, n_drop = 0;
+    double cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
+    for (int c = 0; c < 3; c++)
+        for (int q = 0; q < 8; q++) gB[c][q] = gJ[c][q] = 0.0;
+    for (;;) {
+        const unsigned long long hq = atomicAdd(bp.counter, 1ull);
+        if (hq >= (unsigned long long)bp.nhalves) break;
+        const int64_t h = (int64_t)hq;
+        double lam[3];
+        for (int a = 0; a < 3; a++) lam[a] = bp.lam_end[3 * h + a] * J.spacing[a];
+        const double ltw = TW ? bp.lam_tw[h] : 0.0;
+        if (lam[0] == 0.0 && lam[1] == 0.0 && lam[2] == 0.0 && ltw == 0.0) continue;
+        const uint16_t st = J.rec.st[h];
+        const int nck = bp.tape_n[h], nacc = bp.tape_acc[h];
+        if (st & kFatal) {
+            n_drop++;  // a line the forward map has but this pass could not keep
+            continue;
+        }
+        if (nck <= 0 || nacc <= 0) continue;  // no step taken (a seed on its exit face)
+        const double sgn = h >= J.nlines ? 1.0 : -1.0;
+        n_half++;
+        bool bad = false;
+        int slot = bp.tape_last[h], next = -1, ck = nck - 1;
+        for (; slot >= 0 && ck >= 0 && !bad; ck--) {
+            // replay the segment from its checkpoint
+            const Ckpt cp = bp.tape[slot];
+            Lane<double> L;
+            L.c0 = cp.c0, L.c1 = cp.c1, L.c2 = cp.c2;
+            L.p0 = cp.p0, L.p1 = cp.p1, L.p2 = cp.p2;
+            L.h = cp.h, L.tol = cp.tol, L.sgn = sgn;
+            L.tw = 0.0, L.len = 0.0;
+            L.trials = cp.trials;
+            L.force = cp.force;
+            const bool last = ck == nck - 1;
+            const int target = last ? nacc - ck * bp.seg : bp.seg;
+            if (target < 0 || target > bp.seg || (target == 0 && !last)) {
+                bad = true;
+                break;
+            }
+            load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            int nrec = 0;
+            unsigned acc = 0;
+            int cap_axis = -1;
+            double cap_H = 0.0;
+            const Capture capture{&cap_axis, &cap_H};
+            for (;;) {
+                if (nrec == target && !last) break;
+                StepRec pre;
+                pre.p0 = L.p0, pre.p1 = L.p1, pre.p2 = L.p2;
+                pre.c0 = L.c0, pre.c1 = L.c1, pre.c2 = L.c2;
+                int fin_st = -1, fin_face = -1;
+                bool need_load = false;
+                const unsigned before = acc;
+                lane_iterate<double, TW, Capture>(L, cb, cj, K, fin_st, fin_face, need_load, acc,
+                                                   capture);
+                if (acc != before) {
+                    if (nrec >= target) {
+                        bad = true;
+                        break;
+                    }
+                    pre.H = cap_H;
+                    pre.axis = cap_axis;
+                    buf[nrec++] = pre;
+                }
+                if (fin_st >= 0) {
+                    if (fin_st != 0 || nrec != target || !last) bad = true;
+                    break;
+                }
+                if (need_load)
+                    load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            }
+            if (!bad && !last) {
+                const Ckpt nx = bp.tape[next];
+                if (nx.c0 != L.c0 || nx.c1 != L.c1 || nx.c2 != L.c2 || nx.p0 != L.p0 ||
+                    nx.p1 != L.p1 || nx.p2 != L.p2 || nx.h != L.h)
+                    bad = true;
+            }
+            if (bad) break;
+            // reverse sweep over the segment
+            int cc0 = -1, cc1 = -1, cc2 = -1;
+            for (int r = nrec - 1; r >= 0; r--) {
+                const StepRec sr = buf[r];
+                if (sr.c0 != cc0 || sr.c1 != cc1 || sr.c2 != cc2) {
+                    if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                    cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
+                    load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+                }
+                step_adjoint<TW>(cb, cj, sr, K, sgn, lam, ltw, gB, gJ);
+                n_steps++;
+            }
+            if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+            next = slot;
+            slot = cp.prev;
+        }
+        if (!bad && (ck != -1 || slot != -1)) bad = true;  // the chain and the count disagree
+        if (bad) n_bad++;
+    }
+    if (bp.stats) {
+        if (n_half) atomicAdd(bp.stats + 0, n_half);
+        if (n_steps) atomicAdd(bp.stats + 1, n_steps);
+        if (n_bad) atomicAdd(bp.stats + 2, n_bad);
+        if (n_drop) atomicAdd(bp.stats + 3, n_drop);
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Weight of the value at index n in the derivative at index m along one axis of N
+// nodes: the second-order differences of the prep pass (central inside, one-sided
+// on the boundary nodes, a plain difference when N < 3).
+__device__ __forceinline__ double dcoef(int m, int n, int N, double ih)
+{
+    if (N < 3) return n == 1 ? ih : (n == 0 ? -ih : 0.0);
+    if (m == 0) return n == 0 ? -1.5 * ih : (n == 1 ? 2.0 * ih : (n == 2 ? -0.5 * ih : 0.0));
+    if (m == N - 1)
+        return n == N - 1 ? 1.5 * ih : (n == N - 2 ? -2.0 * ih : (n == N - 3 ? 0.5 * ih : 0.0));
+    return n == m + 1 ? 0.5 * ih : (n == m - 1 ? -0.5 * ih : 0.0);
+}
+
+// (D_axis)^T g at node (i, j, k): sum over the nodes m whose difference uses it
+__device__ double dT(const double *g, int axis, int i, int j, int k, int nx, int ny, int nz,
+                     double ih)
+{
+    const int N = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    const int n = axis == 0 ? i : (axis == 1 ? j : k);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)nx : (int64_t)nx * ny);
+    const int64_t q = ((int64_t)k * ny + j) * nx + i;
+    double acc = 0.0;
+    const int lo = N < 3 ? 0 : n - 2, hi = N < 3 ? N - 1 : n + 2;
+    for (int m = lo; m <= hi; m++) {
+        if (m < 0 || m >= N) continue;
+        const double c = dcoef(m, n, N, ih);
+        if (c != 0.0) acc += c * g[q + (int64_t)(m - n) * stride];
+    }
+    return acc;
+}
+
+__global__ void grad_planes_kernel(int nx, int ny, int nz, double ihx, double ihy, double ihz,
+                                   const double *__restrict__ gnode, int want_tw, double *gx,
+                                   double *gy, double *gz)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
+    if (i >= nx) return;
+    const int64_t nn = (int64_t)nx * ny * nz;
+    const int64_t q = ((int64_t)k * ny + j) * nx + i;
+    double bx = gnode[q], by = gnode[nn + q], bz = gnode[2 * nn + q];
+    if (want_tw) {
+        // J = (dBz/dy - dBy/dz, dBx/dz - dBz/dx, dBy/dx - dBx/dy)
+        const double *gjx = gnode + 3 * nn, *gjy = gnode + 4 * nn, *gjz = gnode + 5 * nn;
+        bx += dT(gjy, 2, i, j, k, nx, ny, nz, ihz) - dT(gjz, 1, i, j, k, nx, ny, nz, ihy);
+        by += dT(gjz, 0, i, j, k, nx, ny, nz, ihx) - dT(gjx, 2, i, j, k, nx, ny, nz, ihz);
+        bz += dT(gjx, 1, i, j, k, nx, ny, nz, ihy) - dT(gjy, 0, i, j, k, nx, ny, nz, ihx);
+    }
+    gx[q] += bx;
+    gy[q] += by;
+    gz[q] += bz;
+}
+
+}  // namespace
+
+hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *dtw,
+                               const double *dend_b, const double *dend_f, double *lam_end,
+                               double *lam_tw, double *gnode, hipStream_t s)
+{
+    const int64_t np = m.nu * m.nv;
+    int64_t b = (np + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(map_backward_kernel, dim3((unsigned)b), dim3(256), 0, s, m, dq, dtw, dend_b,
+                       dend_f, lam_end, lam_tw, gnode);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,
+                                 const BwdParams &bp, hipStream_t s)
+{
+    const dim3 grid((unsigned)((bp.nslots + 63) / 64)), blk(64);
+    if (store == FQ_DT_F64) {
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<double, true>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<double, false>), grid, blk, 0, s, job_dev, bp);
+    } else {
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<float, true>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<float, false>), grid, blk, 0, s, job_dev, bp);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_planes(const fq_field &f, const double *gnode, int want_tw,
+                              double *const gb[3], hipStream_t s)
+{
+    const unsigned bxs = (unsigned)((f.n[0] + 255) / 256);
+    hipLaunchKernelGGL(grad_planes_kernel, dim3(bxs, (unsigned)f.n[1], (unsigned)f.n[2]), dim3(256),
+                       0, s, (int)f.n[0], (int)f.n[1], (int)f.n[2], 1.0 / f.spacing[0],
+                       1.0 / f.spacing[1], 1.0 / f.spacing[2], gnode, want_tw, gb[0], gb[1], gb[2]);
+    return hipGetLastError();
+}
+
+}  // namespace fq

@@ -205,9 +205,19 @@ void set_map_geometry(const Spec &s, MapJob &m)
 
 void set_job_constants(TraceJob &J);
 
-// Carve the workspace and (unless dry) enqueue the whole call.
+// The reverse-mode call of one q2d map: its output adjoints, the gradient planes and
+// the checkpoint layout.
+struct BwdSpec {
+    int seg;                 // accepted steps between checkpoints
+    int64_t pool;            // checkpoints in the pool
+    const double *dq, *dtw, *dend_b, *dend_f;
+    double *const *gb;
+};
+
+// Carve the workspace and (unless dry) enqueue the whole call. With bwd, the trace
+// keeps checkpoints and the map is differentiated instead of written.
 int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_bytes, bool dry,
-        size_t *need, hipStream_t stream)
+        size_t *need, hipStream_t stream, const BwdSpec *bwd = nullptr)
 {
     const int ns = (int)specs.size();
     const size_t tsz = P.precision == FQ_PREC_F64 ? 8 : 4;
@@ -257,6 +267,24 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                 W[i].nodeC64 = P.want_tw ? cv.take((size_t)nn * 2 * 8) : 0;
             }
         }
+    }
+    // adjoint: checkpoints, per-half adjoints, node gradients and replay buffers
+    size_t off_tape = 0, off_tl = 0, off_tn = 0, off_ta = 0, off_lam = 0, off_ltw = 0, off_gnode = 0;
+    size_t off_buf = 0;
+    int64_t bwd_halves = 0, bwd_nodes = 0;
+    if (bwd) {
+        if (ns != 1 || nrot != 0 || specs[0].kind != SPEC_PLANE || P.precision != FQ_PREC_F64)
+            return FQ_EUNSUPPORTED;
+        bwd_halves = 2 * W[0].nlines;
+        bwd_nodes = nodes_of(specs[0].f);
+        off_tape = cv.take((size_t)bwd->pool * sizeof(Ckpt));
+        off_tl = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        off_tn = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        off_ta = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        off_lam = cv.take((size_t)bwd_halves * 3 * sizeof(double));
+        off_ltw = cv.take((size_t)bwd_halves * sizeof(double));
+        off_gnode = cv.take((size_t)bwd_nodes * (P.want_tw ? 6 : 3) * sizeof(double));
+        off_buf = cv.take((size_t)kBwdSlots * (size_t)bwd->seg * sizeof(StepRec));
     }
     if (need) *need = cv.off;
     if (dry) return FQ_OK;
@@ -400,8 +428,18 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.max_steps = P.max_steps;
     tp.want_tw = P.want_tw;
     tp.njobs = njobs;
-    tp.stats = (unsigned long long *)P.stats;
+    tp.stats = bwd ? nullptr : (unsigned long long *)P.stats;
     tp.static_items = items;
+    if (bwd) {
+        tp.tape = (Ckpt *)(ws + off_tape);
+        tp.pool_ctr = (unsigned long long *)(ws + off_ctr + 128);
+        tp.tape_last = (int32_t *)(ws + off_tl);
+        tp.tape_n = (int32_t *)(ws + off_tn);
+        tp.tape_acc = (int32_t *)(ws + off_ta);
+        tp.seg = bwd->seg;
+        tp.pool_cap = bwd->pool;
+        FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr + 128), 2, 0u, stream));
+    }
     hipEvent_t *ev = (hipEvent_t *)P.events;
     if (ev && ev[0]) FQ_TRY(hipEventRecord(ev[0], stream));
     FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
@@ -443,6 +481,37 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
         if (ev && ev[3]) FQ_TRY(hipEventRecord(ev[3], stream));
+    }
+    if (bwd) {
+        double *lam_end = (double *)(ws + off_lam), *lam_tw = (double *)(ws + off_ltw);
+        double *gnode = (double *)(ws + off_gnode);
+        FQ_TRY(launch_fill_u32((uint32_t *)lam_end, bwd_halves * 6, 0u, stream));
+        FQ_TRY(launch_fill_u32((uint32_t *)lam_tw, bwd_halves * 2, 0u, stream));
+        FQ_TRY(launch_fill_u32((uint32_t *)gnode, bwd_nodes * (P.want_tw ? 12 : 6), 0u, stream));
+        FQ_TRY(launch_map_backward(maps[0], bwd->dq, P.want_tw ? bwd->dtw : nullptr, bwd->dend_b,
+                                   bwd->dend_f, lam_end, lam_tw, gnode, stream));
+        unsigned long long *bctr = (unsigned long long *)(ws + off_ctr + 64);
+        FQ_TRY(launch_fill_u32((uint32_t *)bctr, 2, 0u, stream));
+        BwdParams bp;
+        memset(&bp, 0, sizeof bp);
+        bp.tape = tp.tape;
+        bp.tape_last = tp.tape_last;
+        bp.tape_n = tp.tape_n;
+        bp.tape_acc = tp.tape_acc;
+        bp.seg = tp.seg;
+        bp.nhalves = bwd_halves;
+        bp.lam_end = lam_end;
+        bp.lam_tw = lam_tw;
+        bp.gnode = gnode;
+        bp.buf = (StepRec *)(ws + off_buf);
+        bp.nslots = kBwdSlots;
+        bp.counter = bctr;
+        bp.stats = (unsigned long long *)P.stats;
+        bp.max_steps = P.max_steps;
+        bp.want_tw = P.want_tw;
+        FQ_TRY(launch_trace_backward(FQ_DT_F64, P.want_tw, jobs_dev, bp, stream));
+        FQ_TRY(launch_grad_planes(*specs[0].f, gnode, P.want_tw, bwd->gb, stream));
+        return FQ_OK;
     }
     for (int i = 0; i < ns; i++) {
         if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));
@@ -488,6 +557,29 @@ int q2d_specs(const fq_field *fields, const fq_plane *planes, int njobs, const f
         plane_normal(planes[j], s.normal);
         s.map = maps ? &maps[j] : nullptr;
     }
+    return FQ_OK;
+}
+
+// Checkpoint pool of the adjoint's forward pass: room for 2048 accepted steps per
+// half line on average (plus the first checkpoint and a partial segment).
+constexpr int64_t kBwdPoolSteps = 2048;
+
+int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
+              fq_params &P, std::vector<Spec> &v, BwdSpec &b)
+{
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if (P.precision != FQ_PREC_F64) return FQ_EUNSUPPORTED;
+    if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
+    if (segment < 1 || segment > 4096) return FQ_EINVAL;
+    if (!plane_on_face(*pl, *f)) return FQ_EUNSUPPORTED;
+    if (P.max_steps > INT32_MAX) return FQ_EINVAL;
+    if ((rc = q2d_specs(f, pl, 1, nullptr, v))) return rc;
+    memset(&b, 0, sizeof b);
+    b.seg = segment;
+    const int64_t halves = 2 * pl->nu * pl->nv;
+    b.pool = halves * (2 + (kBwdPoolSteps + segment - 1) / segment);
+    if (b.pool > INT32_MAX) return FQ_EINVAL;
     return FQ_OK;
 }
 
@@ -616,11 +708,13 @@ int fastqsl_q3d(const fq_field *f, const fq_voxels *vx, const fq_params *p, cons
 size_t fastqsl_backward_workspace_size(const fq_field *f, const fq_plane *pl, const fq_params *p,
                                        int segment)
 {
-    (void)f;
-    (void)pl;
-    (void)p;
-    (void)segment;
-    return 0;
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    if (bwd_setup(f, pl, p, segment, P, v, b)) return 0;
+    size_t need = 0;
+    if (run(v, P, nullptr, 0, true, &need, nullptr, &b)) return 0;
+    return need;
 }
 
 int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
@@ -628,9 +722,18 @@ int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, 
                      const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
                      void *stream)
 {
-    (void)f, (void)pl, (void)p, (void)segment, (void)dq, (void)dtw, (void)dend_b, (void)dend_f;
-    (void)gb, (void)ws, (void)ws_bytes, (void)stream;
-    return FQ_EUNSUPPORTED;
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup(f, pl, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!gb || !gb[0] || !gb[1] || !gb[2]) return FQ_EINVAL;
+    b.dq = dq;
+    b.dtw = dtw;
+    b.dend_b = dend_b;
+    b.dend_f = dend_f;
+    b.gb = gb;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
 }
 
 }  // extern "C"

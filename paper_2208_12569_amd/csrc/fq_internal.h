@@ -76,6 +76,24 @@ struct FixEntry {
     int64_t line;
 };
 
+// Lane state at a checkpoint of the adjoint's forward pass (64 bytes): enough to
+// replay the half line from there exactly. Checkpoints come from one pool; those of
+// a half line are chained from its last one backwards.
+struct Ckpt {
+    double p0, p1, p2, h, tol;
+    int32_t c0, c1, c2, force;
+    int32_t trials;
+    int32_t prev;  // pool slot of the previous checkpoint of the half line, -1 = none
+};
+
+// One accepted step found by a replay, for the reverse sweep (48 bytes).
+struct StepRec {
+    double p0, p1, p2;  // local position before the step
+    double H;           // step length in the independent variable
+    int32_t c0, c1, c2;
+    int32_t axis;       // landing axis, -1 for a plain step
+};
+
 struct TraceParams {
     double tol_perp, step_perp, step_min, tol_floor;
     int64_t max_steps;
@@ -88,6 +106,33 @@ struct TraceParams {
     const FixEntry *list;          // list mode: trace exactly these half lines
     const uint32_t *list_count;
     int64_t list_cap;
+    // adjoint forward pass (FP64, single job): checkpoints every `seg` accepted steps
+    Ckpt *tape;                    // checkpoint pool of pool_cap entries
+    unsigned long long *pool_ctr;  // next free pool slot
+    int32_t *tape_last;            // per half record: pool slot of its last checkpoint
+    int32_t *tape_n;               // per half record: checkpoints stored
+    int32_t *tape_acc;             // per half record: accepted steps
+    int32_t seg;
+    int32_t pad2;
+    int64_t pool_cap;
+};
+
+// Reverse sweep over the traced half lines of one job.
+struct BwdParams {
+    const Ckpt *tape;
+    const int32_t *tape_last, *tape_n, *tape_acc;
+    int32_t seg, pad0;
+    int64_t nhalves;               // 2 * nlines
+    const double *lam_end;         // per half: dL/d(end point), 3 doubles
+    const double *lam_tw;          // per half: dL/d(Tw of the half)
+    double *gnode;                 // 6 planes over the nodes: dL/d(Bx, By, Bz, Jx, Jy, Jz)
+    StepRec *buf;                  // nslots * seg replay records
+    int64_t nslots;                // lanes of the reverse kernel
+    unsigned long long *counter;   // queue
+    unsigned long long *stats;     // optional: halves, steps, replay mismatches, dropped halves
+    int64_t max_steps;
+    int32_t want_tw;
+    int32_t pad;
 };
 
 // Host-side launchers, one per translation unit.
@@ -125,6 +170,16 @@ struct MapJob {
     double rot_delta;
     fq_map out;
 };
+
+// Adjoint (adjoint.hip).
+hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *dtw,
+                               const double *dend_b, const double *dend_f, double *lam_end,
+                               double *lam_tw, double *gnode, hipStream_t s);
+hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,
+                                 const BwdParams &bp, hipStream_t s);
+hipError_t launch_grad_planes(const fq_field &f, const double *gnode, int want_tw,
+                              double *const gb[3], hipStream_t s);
+constexpr int64_t kBwdSlots = 32768;  // lanes of the reverse kernel
 
 hipError_t launch_classify(const MapJob &m, int32_t *rot_index, RotEntry *rot,
                            uint32_t *rot_count, int64_t rot_capacity, hipStream_t s);

@@ -28,157 +28,41 @@
 //    seeds and read neighbouring cells.
 #include "fq_internal.h"
 #include "trace_core.h"
+#include "trace_dev.h"
 
 namespace fq {
 namespace {
 
-template <typename T> struct V4;
-template <> struct V4<float> { using t = float4; };
-template <> struct V4<double> { using t = double4; };
-template <typename T> struct V2;
-template <> struct V2<float> { using t = float2; };
-template <> struct V2<double> { using t = double2; };
-
-// Pointers read from the job table are generic; marking them as global memory
-// (address space 1) makes the compiler emit global instead of flat loads/stores.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define FQ_GLOBAL __attribute__((address_space(1)))
-#else
-#define FQ_GLOBAL
-#endif
-template <typename P> __device__ __forceinline__ FQ_GLOBAL P *gptr(P *p)
-{
-    return (FQ_GLOBAL P *)p;
-}
-template <typename P> __device__ __forceinline__ const FQ_GLOBAL P *gptr(const P *p)
-{
-    return (const FQ_GLOBAL P *)p;
-}
-
-// Fetch one cell: 8 corner records (Bx, By, Bz, Jx) + (Jy, Jz) of type S, turned into
-// monomial coefficients of type T.
-template <typename T, typename S, bool TW>
-__device__ __forceinline__ void load_cell(const void *nodeA, const void *nodeC, int nx, int ny,
-                                          int cx, int cy, int cz, T cb[3][8], T cj[3][8])
-{
-    const FQ_GLOBAL typename V4<S>::t *A = gptr((const typename V4<S>::t *)nodeA);
-    const FQ_GLOBAL typename V2<S>::t *C = gptr((const typename V2<S>::t *)nodeC);
-    const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
-    const int64_t base = (int64_t)cz * sz + (int64_t)cy * sy + cx;
-    T f[6][8];
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-        const int64_t o = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0);
-        const typename V4<S>::t a = A[o];
-        f[0][q] = (T)a.x;
-        f[1][q] = (T)a.y;
-        f[2][q] = (T)a.z;
-        f[3][q] = (T)a.w;
-        if (TW) {
-            const typename V2<S>::t c = C[o];
-            f[4][q] = (T)c.x;
-            f[5][q] = (T)c.y;
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 3; m++) coeffs<T>(f[m], cb[m]);
-    if (TW) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) coeffs<T>(f[3 + m], cj[m]);
-    }
-}
-
-__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src)
-{
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-    lo = __shfl(lo, src);
-    hi = __shfl(hi, src);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-// Lines of a job that exist now (a rotated-S0 job is sized on the device).
-__device__ __forceinline__ int64_t live_lines(const TraceJob &J)
-{
-    if (J.kind != SEED_ROTATED) return J.nlines;
-    // the classify pass counts past its capacity; only stored entries exist
-    const int64_t cnt = 4 * (int64_t)(*J.rot_count);
-    return cnt < J.nlines ? cnt : J.nlines;
-}
-
-// Seed position of a line and the S0 normal used for the Eq. step / Eq. tol scaling
-// (zero for rotated S0, whose normal is along B).
-__device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, double r[3],
-                                             double nrm[3])
-{
-    nrm[0] = J.normal[0];
-    nrm[1] = J.normal[1];
-    nrm[2] = J.normal[2];
-    if (J.kind == SEED_LIST) {
-        const FQ_GLOBAL double *sd = gptr(J.seeds);
-        r[0] = sd[3 * line + 0];
-        r[1] = sd[3 * line + 1];
-        r[2] = sd[3 * line + 2];
-    } else if (J.kind == SEED_ROTATED) {
-        const FQ_GLOBAL RotEntry &e = gptr(J.rot)[line >> 2];
-        const int which = (int)(line & 3);
-        const double *d = (which < 2) ? e.U : e.V;
-        const double s = (which & 1) ? J.rot_delta : -J.rot_delta;
-        for (int a = 0; a < 3; a++) r[a] = e.r0[a] + s * d[a];
-        nrm[0] = nrm[1] = nrm[2] = 0.0;
-    } else {
-        const int64_t i = line % J.dims[0];
-        const int64_t j = (line / J.dims[0]) % J.dims[1];
-        const int64_t k = line / (J.dims[0] * J.dims[1]);
-        for (int a = 0; a < 3; a++)
-            r[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a] +
-                   (double)k * J.s_c[a];
-    }
-}
-
-// floor(n / d) for 0 <= n < 2^31 with a precomputed 1/d (one FP64 multiply and
-// an exact integer correction)
-__device__ __forceinline__ int64_t fdiv(int64_t n, int64_t d, double inv_d, int64_t &rem)
-{
-    int64_t q = (int64_t)((double)n * inv_d);
-    int64_t r = n - q * d;
-    if (r < 0) {
-        q--;
-        r += d;
-    } else if (r >= d) {
-        q++;
-        r -= d;
-    }
-    rem = r;
-    return q;
-}
-
-// Line of queue item t of a job; -1 for tile holes. Plane seeds come in 8x8 tiles,
-// voxels in 4x4x4 tiles (64 neighbouring seeds per wave), lists in order.
-__device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
-{
-    if (J.kind == SEED_LIST || J.kind == SEED_ROTATED) return t < live_lines(J) ? t : -1;
-    const int64_t ti = t >> 6;
-    const int w = (int)(t & 63);
-    int64_t r0, i, j, k;
-    const int64_t q0 = fdiv(ti, J.tiles[0], J.inv_t0, r0);
-    if (J.kind == SEED_PLANE) {
-        i = r0 * 8 + (w & 7);
-        j = q0 * 8 + (w >> 3);
-        k = 0;
-    } else {
-        int64_t r1;
-        const int64_t q1 = fdiv(q0, J.tiles[1], J.inv_t1, r1);
-        i = r0 * 4 + (w & 3);
-        j = r1 * 4 + ((w >> 2) & 3);
-        k = q1 * 4 + (w >> 4);
-    }
-    if (i >= J.dims[0] || j >= J.dims[1] || k >= J.dims[2]) return -1;
-    return (k * J.dims[1] + j) * J.dims[0] + i;
-}
+using namespace dev;
 
 // UNI: a single job without a rotated-S0 companion, so every job constant is
 // uniform across the grid (kept in scalar registers).
-template <typename T, typename S, bool TW, bool UNI>
+// TAPE: the adjoint's forward pass (FP64, single job), which also stores the lane
+// state at the start of every half line and after every tp.seg accepted steps.
+template <typename T, typename S, bool TW, bool UNI, bool TAPE>
+__device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, const Lane<T> &L)
+{
+    if (!TAPE) return true;
+    const unsigned long long slot = atomicAdd(tp.pool_ctr, 1ull);
+    if (slot >= (unsigned long long)tp.pool_cap) return false;  // the pool is exhausted
+    Ckpt c;
+    c.p0 = (double)L.p0;
+    c.p1 = (double)L.p1;
+    c.p2 = (double)L.p2;
+    c.h = (double)L.h;
+    c.tol = (double)L.tol;
+    c.c0 = L.c0;
+    c.c1 = L.c1;
+    c.c2 = L.c2;
+    c.force = L.force;
+    c.trials = (int32_t)L.trials;
+    c.prev = last;
+    gptr(tp.tape)[slot] = c;
+    last = (int)slot;
+    return true;
+}
+
+template <typename T, typename S, bool TW, bool UNI, bool TAPE>
 __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
@@ -223,6 +107,8 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
     }
     T cb[3][8], cj[3][8];
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
+    int acc_half = 0, nck = 0;  // TAPE: accepted steps and checkpoints of the half line
+    int last_ck = -1;           // TAPE: pool slot of the last checkpoint
 
     for (;;) {
         int fin_st = -1, fin_face = -1;  // set when the active half line ends this round
@@ -282,6 +168,9 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
                         L.len = 0.0;
                         L.trials = 0;
                         L.force = -1;
+                        acc_half = 0;
+                        nck = 0;
+                        last_ck = -1;
                         const double g0 = (r[0] - J.origin[0]) * J.inv_spacing[0],
                                      g1 = (r[1] - J.origin[1]) * J.inv_spacing[1],
                                      g2 = (r[2] - J.origin[2]) * J.inv_spacing[2];
@@ -323,13 +212,29 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
                 if (ang > 1.0f) ang = 1.0f;
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
                 L.tol = (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
+                if (TAPE) {
+                    if (store_ckpt<T, S, TW, UNI, TAPE>(tp, last_ck, L)) nck++;
+                    else fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
+                }
             }
         }
 
         // ---- one trial step -------------------------------------------------------------
         if (jb >= 0 && fin_st < 0) {
             n_trial++;
+            const unsigned acc_before = n_acc;
             lane_iterate<T, TW>(L, cb, cj, K, fin_st, fin_face, need_load, n_acc);
+            if (TAPE && n_acc != acc_before) {
+                acc_half++;
+                if (fin_st < 0 && acc_half % tp.seg == 0) {
+                    if (store_ckpt<T, S, TW, UNI, TAPE>(tp, last_ck, L)) {
+                        nck++;
+                    } else {
+                        fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
+                        fin_face = -1;
+                    }
+                }
+            }
         }
 
         // ---- write the record of a finished half line -----------------------------------
@@ -350,6 +255,11 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__
             gptr(J.rec.len)[rec] = bad ? NAN : L.len * J.dref;
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
+            if (TAPE) {
+                gptr(tp.tape_last)[rec] = last_ck;
+                gptr(tp.tape_n)[rec] = nck;
+                gptr(tp.tape_acc)[rec] = acc_half;
+            }
             jb = -1;
             need_load = false;
             n_half++;
@@ -421,16 +331,16 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
 template <typename T, typename S, bool UNI>
 const void *kernel_of(int want_tw)
 {
-    return want_tw ? (const void *)trace_kernel<T, S, true, UNI>
-                   : (const void *)trace_kernel<T, S, false, UNI>;
+    return want_tw ? (const void *)trace_kernel<T, S, true, UNI, false>
+                   : (const void *)trace_kernel<T, S, false, UNI, false>;
 }
 
-template <typename T, typename S, bool UNI>
+template <typename T, typename S, bool UNI, bool TAPE>
 void launch_ts(int want_tw, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
                const TraceParams &tp, unsigned long long *counter)
 {
-    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true, UNI>), grid, blk, 0, s, jobs, tp, counter);
-    else hipLaunchKernelGGL((trace_kernel<T, S, false, UNI>), grid, blk, 0, s, jobs, tp, counter);
+    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, false, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
 }
 
 }  // namespace
@@ -448,6 +358,14 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
     const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
     if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
     const bool uni = tp.njobs == 1 && !tp.dynamic_last;
+    if (tp.tape) {
+        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list
+        if (!f64 || !uni || tp.list || tp.seg < 1) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)(2 * ncu)), blk(256);
+        if (s64) launch_ts<double, double, true, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, float, true, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        return hipGetLastError();
+    }
     const void *fn;
     if (!f64) fn = uni ? kernel_of<float, float, true>(want_tw) : kernel_of<float, float, false>(want_tw);
     else if (s64) fn = uni ? kernel_of<double, double, true>(want_tw) : kernel_of<double, double, false>(want_tw);
@@ -462,14 +380,14 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
     }
     dim3 grid((unsigned)(per_cu * ncu)), blk((unsigned)block);
     if (!f64) {
-        if (uni) launch_ts<float, float, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<float, float, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<float, float, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<float, float, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
     } else if (s64) {
-        if (uni) launch_ts<double, double, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, double, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<double, double, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, double, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
     } else {
-        if (uni) launch_ts<double, float, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, float, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<double, float, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, float, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
     }
     return hipGetLastError();
 }

@@ -175,6 +175,10 @@ enum Ev : int {
 
 struct NoEvents {
     __host__ __device__ __forceinline__ void operator()(int) const {}
+    // an accepted step: landing axis (-1 for a plain step) and its signed length in
+    // the independent variable (arc length for a plain step, the axis coordinate
+    // for a landing)
+    template <typename T> __host__ __device__ __forceinline__ void accepted(int, T) const {}
 };
 
 // Carry a coordinate that left [0,1] by a small amount into the neighbouring cell
@@ -422,6 +426,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                 L.len += (double)(H * slen);
                 L.h = mn(L.h * (T)grow, T(4));
                 n_acc++;
+                ev.accepted(-1, H);
                 ev(EV_ACCEPT_ARC);
             } else {
                 // the line curved out of the cell before the straight-line guess: land
@@ -462,6 +467,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         L.len += (double)(H * slen);
         L.h = mn(fabs(s_step) * (T)grow, T(4));
         n_acc++;
+        ev.accepted(axis, H);
         ev(EV_ACCEPT_LAND);
         // carry small overshoots of the other coordinates (a crossing near an edge)
         bool moved = false;

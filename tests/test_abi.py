@@ -173,3 +173,36 @@ def test_python_layer_fails_loudly_without_gpu():
 
     with pytest.raises(RuntimeError, match="GPU"):
         fq.q2d(torch.zeros(3, 4, 4, 4), None, None)
+
+
+def test_backward_workspace_query(lib):
+    """The adjoint is taken in the all-FP64 form on a seed plane on a box face; its
+    workspace holds a pool of 2 + ceil(2048/segment) checkpoints of 64 bytes per half
+    line."""
+    from paper_2208_12569_amd import _lib
+
+    f = _fake_field()
+    pl = _plane(nu=64)
+    p = _lib.fq_params()
+    p.want_tw = 1
+    p.precision = _lib.FQ_PREC_F32X
+    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32) == 0
+    p.precision = _lib.FQ_PREC_F64
+    for seg in (0, -1, 5000):
+        assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), seg) == 0
+    inner = _plane(nu=64, z=0.5)
+    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(inner), C.byref(p), 32) == 0
+    n32 = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32)
+    halves = 2 * 64 * 64
+    slots = 32768  # lanes of the reverse kernel, each with `segment` 48-byte step records
+    assert n32 >= halves * (2048 // 32 + 2) * 64 + slots * 32 * 48
+    n64 = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 64)
+    assert n64 >= halves * (2048 // 64 + 2) * 64 + slots * 64 * 48
+    p.max_steps = 1 << 40
+    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32) == 0
+    p.max_steps = 0
+    # the call itself validates the gradient planes before touching the device
+    gb = (C.c_void_p * 3)(None, None, None)
+    rc = lib.fastqsl_backward(C.byref(f), C.byref(pl), C.byref(p), 32, None, None, None, None, gb,
+                              None, 0, None)
+    assert rc == _lib.FQ_EINVAL

@@ -1,0 +1,414 @@
+"""The adjoint (fastqsl_backward and the QTwMap autograd function) on the GPU.
+
+Pins: closed-form derivatives of the sheared and hyperbolic linear fields
+(dQ/ds = 2 s L^2, dTw/ds, dx2/ds = (y1 - y0) L; dQ/dk = 4 L sinh 2kL), central
+finite differences of the GPU forward on charge fields, and finite differences of
+the FP64 oracle as an independent reference gradient. Every case prints what it
+runs before touching the GPU.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Plane, cubic_grid, linear_field
+
+pytestmark = pytest.mark.gpu
+
+F64 = 1
+TOL = 1e-10
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2208_12569_amd as m
+
+    m._lib.load()
+    return m
+
+
+def _dev(B):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(B)).cuda()
+
+
+def _grad(fq, B, g, pl, stats=None, segment=32, **kw):
+    import torch
+
+    p = fq.Params(precision=F64, tol_perp=TOL, stats=stats)
+    gb = fq.backward(B, g, pl, p, segment, **kw)
+    torch.cuda.synchronize()
+    return gb.cpu().numpy()
+
+
+def test_shear_closed_form_derivatives(fq):
+    """B = (s (y - y0), 0, 1) on the unit cube: Q = 2 + s^2 L^2 on every interior point,
+    Tw = -s L / (4 pi sqrt(1 + s^2 (y1-y0)^2)), x2 = x1 + s (y1 - y0) L. The adjoint's
+    dL/dB contracted with dB/ds gives the s-derivatives of all three."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    s, y0, L = 0.5, 0.5, 1.0
+    B = _dev(linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1]))
+    pl = Plane((0.41, 0.25, 0.0), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.02)
+    yy = np.asarray(g.axes()[1])[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[0] = np.broadcast_to(yy - y0, g.shape)
+    npts = 81
+    interior = np.zeros((9, 9))
+    interior[1:-1, 1:-1] = 1.0
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say("shear: dQ/ds")
+    gq = _grad(fq, B, g, pl, stats, dq=torch.tensor(interior.ravel(), device="cuda"))
+    want = interior.sum() * 2 * s * L * L
+    got = float((gq * dBds).sum())
+    assert abs(got / want - 1) < 1e-6, (got, want)
+    st = stats.tolist()
+    assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0, st
+    _say("shear: dTw/ds")
+    y1 = pl.points()[:, 1]
+    eta = y1 - y0
+    gt = _grad(fq, B, g, pl, dtw=torch.ones(npts, dtype=torch.float64, device="cuda"))
+    want = float(np.sum(-L / (4 * np.pi) * (1 + s * s * eta * eta) ** -1.5))
+    got = float((gt * dBds).sum())
+    assert abs(got / want - 1) < 1e-6, (got, want)
+    _say("shear: d x2 / ds")
+    de = torch.zeros((npts, 3), dtype=torch.float64, device="cuda")
+    de[:, 0] = 1.0
+    ge = _grad(fq, B, g, pl, dend_f=de)
+    want = float(np.sum(eta * L))
+    got = float((ge * dBds).sum())
+    assert abs(got - want) < 1e-7 * max(1.0, abs(want)), (got, want)
+
+
+def test_hyperbolic_closed_form_derivative(fq):
+    """B = (k (x - xc), -k (y - yc), 1): Q = 2 cosh 2kL, dQ/dk = 4 L sinh 2kL."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    k, L = 1.0, 1.0
+    B = _dev(linear_field(g, [[k, 0, 0], [0, -k, 0], [0, 0, 0]], [-k * 0.5, k * 0.5, 1]))
+    d = 1e-3
+    pl = Plane((0.52 - 2 * d, 0.47 - 2 * d, 0.0), (1, 0, 0), (0, 1, 0), 5, 5, d, d)
+    x, y, _ = np.meshgrid(*g.axes(), indexing="ij")
+    dBdk = np.zeros((3,) + g.shape)
+    dBdk[0] = (x - 0.5).transpose(2, 1, 0)
+    dBdk[1] = -(y - 0.5).transpose(2, 1, 0)
+    w = np.zeros((5, 5))
+    w[1:-1, 1:-1] = 1.0
+    _say("hyperbolic: dQ/dk")
+    gq = _grad(fq, B, g, pl, dq=torch.tensor(w.ravel(), device="cuda"))
+    want = w.sum() * 4 * L * math.sinh(2 * k * L)
+    got = float((gq * dBdk).sum())
+    assert abs(got / want - 1) < 1e-5, (got, want)
+
+
+# ---------------------------------------------------------------------------------
+# charge fields: finite differences of the GPU forward and of the oracle
+
+def _charges(seed, n, device="cuda"):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    pos, q = synth.draw_charges(rng, n)
+    return (torch.tensor(pos, dtype=torch.float64, device=device),
+            torch.tensor(q, dtype=torch.float64, device=device))
+
+
+def _fd_mask(fq, r):
+    """Points whose Q cannot jump under a tiny change of the field: every line of the
+    stencil (and of the neighbours' stencils) ends on the same faces, away from box
+    edges, and Q is moderate."""
+    import torch
+
+    st = r["status"].to(torch.int32)
+    bad = ((st & (fq.ST_FATAL | fq.ST_MIXEDFACE | fq.ST_ONESIDED | fq.ST_EDGE)) != 0)
+    bad |= ~torch.isfinite(r["q"]) | (r["q"] > 1e4)
+    pad = torch.nn.functional.pad(bad.float()[None, None], (1, 1, 1, 1), value=1.0)[0, 0]
+    dil = bad.float()
+    dil = torch.maximum(dil, pad[:-2, 1:-1])
+    dil = torch.maximum(dil, pad[2:, 1:-1])
+    dil = torch.maximum(dil, pad[1:-1, :-2])
+    dil = torch.maximum(dil, pad[1:-1, 2:])
+    return dil == 0
+
+
+def _loss_fn(fq, g, pl, mask, wq, wt, we):
+    """A smooth loss of the map: weighted log10 Q, Tw and both end points on the mask."""
+    import torch
+
+    from paper_2208_12569_amd.autograd import qtw_map
+
+    def loss(B):
+        q, tw, eb, ef, st = qtw_map(B, g, pl, fq.Params(precision=F64, tol_perp=TOL), 8)
+        m = mask
+        lq = torch.log10(torch.where(m, q, torch.ones_like(q)))
+        val = (wq * lq * m).sum() + (wt * torch.where(m, tw, torch.zeros_like(tw))).sum()
+        e = torch.where(m[..., None], eb + ef, torch.zeros_like(eb))
+        return val + (we * e).sum()
+
+    return loss
+
+
+def test_charge_field_gradient_matches_finite_differences(fq):
+    """dL/d(charge positions and strengths) of a map loss (log10 Q, Tw, end points)
+    through the field model and QTwMap, against central differences of the GPU
+    forward, on a 48x48x32 cube with 6 charges and 32x32 seeds."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    g = cubic_grid(48, 48, 32)
+    pl = synth.plane_z0(32)
+    pos0, q0 = _charges(7, 6)
+    theta0 = torch.cat([pos0.ravel(), q0]).detach()
+
+    def field(theta):
+        return charges_field_torch(g, theta[:18].view(6, 3), theta[18:], torch.float64, "cuda")
+
+    _say("charge field: base map")
+    r = fq.q2d(field(theta0), g, pl, fq.Params(precision=F64, tol_perp=TOL))
+    mask = _fd_mask(fq, r)
+    assert mask.float().mean() > 0.3
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    wq = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    wt = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    we = torch.randn((32, 32, 3), generator=gen, device="cuda", dtype=torch.float64)
+    loss = _loss_fn(fq, g, pl, mask, wq, wt, we)
+    theta = theta0.clone().requires_grad_(True)
+    _say("charge field: adjoint")
+    L0 = loss(field(theta))
+    L0.backward()
+    grad = theta.grad.detach().cpu().numpy()
+    fd = np.zeros_like(grad)
+    for i in range(theta0.numel()):
+        h = 1e-6 * max(1.0, abs(float(theta0[i])))
+        tp = theta0.clone()
+        tm = theta0.clone()
+        tp[i] += h
+        tm[i] -= h
+        with torch.no_grad():
+            fd[i] = (float(loss(field(tp))) - float(loss(field(tm)))) / (2 * h)
+    scale = np.abs(fd).max()
+    err = np.abs(grad - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+    print("grad", grad, "fd", fd, "rel err", err)
+    assert err.max() < 1e-4, (err.max(), int(np.argmax(err)))
+
+
+def test_segment_length_does_not_change_the_gradient(fq):
+    """Checkpointing every 1, 5 or 32 accepted steps replays the same steps: the node
+    gradients agree to rounding, and no replay diverges from its forward pass."""
+    import torch
+
+    g = cubic_grid(40, 40, 28)
+    pos, q = synth.draw_charges(np.random.default_rng(11), 5)
+    B = _dev(synth.charges_field(g, pos, q))
+    pl = synth.plane_z0(24)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    dq = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    dtw = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    de = torch.randn((24 * 24, 3), generator=gen, device="cuda", dtype=torch.float64)
+    out = []
+    for seg in (1, 5, 32):
+        _say(f"segment {seg}")
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+        gb = _grad(fq, B, g, pl, stats, segment=seg, dq=dq, dtw=dtw, dend_b=de, dend_f=de)
+        st = stats.tolist()
+        assert st[2] == 0 and st[3] == 0, st
+        out.append((gb, st))
+    ref = out[0][0]
+    for gb, st in out[1:]:
+        assert st[:2] == out[0][1][:2]
+        assert np.allclose(gb, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_gradient_matches_oracle_finite_differences(fq):
+    """Reference gradient: central differences of the FP64 oracle's Q at 12 points
+    for three charge parameters, against the adjoint of the sum of those Q values."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    g = cubic_grid(40, 40, 28)
+    pl = synth.plane_z0(24)
+    rng = np.random.default_rng(19)
+    pos, q = synth.draw_charges(rng, 4)
+    _say("oracle reference gradient: base map")
+    B0 = synth.charges_field(g, pos, q)
+    r = fq.q2d(_dev(B0), g, pl, fq.Params(precision=F64, tol_perp=TOL))
+    mask = _fd_mask(fq, r).cpu().numpy().ravel()
+    idx = np.sort(rng.choice(np.flatnonzero(mask), 12, replace=False))
+    dq = torch.zeros(24 * 24, dtype=torch.float64, device="cuda")
+    dq[torch.tensor(idx, device="cuda")] = 1.0
+    theta0 = np.concatenate([pos.ravel(), q])
+    theta = torch.tensor(theta0, device="cuda", requires_grad=True)
+    Bt = charges_field_torch(g, theta[:12].view(4, 3), theta[12:], torch.float64, "cuda")
+    _say("oracle reference gradient: adjoint")
+    gb = fq.backward(Bt.detach(), g, pl, fq.Params(precision=F64, tol_perp=TOL), 16, dq=dq)
+    Bt.backward(gb)
+    grad = theta.grad.cpu().numpy()
+    for i in (0, 5, 13):  # x of charge 0, z of charge 1, strength of charge 1
+        h = 1e-5 * max(1.0, abs(float(theta0[i])))
+        vals = []
+        for sgn in (1, -1):
+            th = theta0.copy()
+            th[i] += sgn * h
+            Bh = synth.charges_field(g, th[:12].reshape(4, 3), th[12:])
+            o = oracle.q2d_points(Bh, g, pl, idx, {"tol": 1e-11})
+            vals.append(float(np.sum(o["q"])))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(i, grad[i], fd)
+        assert abs(grad[i] - fd) <= 1e-4 * max(abs(fd), 1e-3), (i, grad[i], fd)
+
+
+def _c5_loss(fq, g, pl, tgt, mask_q, mask_e):
+    """The fitting loss: mean over mask_q of (log10 Q - log10 Q_target)^2 plus the mean
+    over mask_e of the squared distance between matching end points."""
+    import torch
+
+    from paper_2208_12569_amd.autograd import qtw_map
+
+    nq = mask_q.sum().clamp(min=1)
+    ne = mask_e.sum().clamp(min=1)
+
+    def loss(B):
+        q, tw, eb, ef, st = qtw_map(B, g, pl, fq.Params(precision=F64, tol_perp=TOL), 32)
+        lq = torch.log10(torch.where(mask_q, q, torch.ones_like(q)))
+        lt = torch.log10(torch.where(mask_q, tgt["q"], torch.ones_like(q)))
+        e = ((eb - tgt["eb"]) ** 2).sum(-1) + ((ef - tgt["ef"]) ** 2).sum(-1)
+        return (((lq - lt) ** 2) * mask_q).sum() / nq + torch.where(mask_e, e, torch.zeros_like(e)).sum() / ne
+
+    return loss
+
+
+def test_c5_fit_gradient(fq):
+    """The adjoint workload: a 128x128x96 FP32 cube from 8 charges with learnable
+    positions and strengths, a target map from 8 other charges, the log10 Q and
+    footpoint loss over 256x256 seeds, checkpoints every 32 accepted steps. The
+    gradient with respect to all 32 charge parameters and to 64 node values matches
+    central differences of the GPU forward, and a few gradient steps lower the loss."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    w, target = synth.config_c5(0)
+    g, pl = w.grid, w.plane
+    pos, q = w.meta["charges"]
+    tpos, tq = target["charges"]
+    _say("c5: target and base maps")
+
+    def field(theta, dtype=torch.float32):
+        return charges_field_torch(g, theta[:24].view(8, 3), theta[24:], dtype, "cuda")
+
+    theta0 = torch.tensor(np.concatenate([pos.ravel(), q]), device="cuda")
+    tB = charges_field_torch(g, tpos, tq, torch.float32, "cuda")
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    rt = fq.q2d(tB, g, pl, p, want_lines=True)
+    r0 = fq.q2d(field(theta0), g, pl, p, want_lines=True)
+    shape = (256, 256)
+    tgt = {"q": rt["q"], "eb": rt["lines"]["end_b"].view(*shape, 3),
+           "ef": rt["lines"]["end_f"].view(*shape, 3)}
+    ok = _fd_mask(fq, r0) & _fd_mask(fq, rt)
+    same = ((r0["lines"]["face_b"] == rt["lines"]["face_b"]) &
+            (r0["lines"]["face_f"] == rt["lines"]["face_f"])).view(shape)
+    mask_q, mask_e = ok, ok & same
+    assert mask_q.float().mean() > 0.2 and mask_e.float().mean() > 0.05
+    loss = _c5_loss(fq, g, pl, tgt, mask_q, mask_e)
+
+    # the charge parameters are checked on the unrounded (FP64) cube: differences of
+    # an FP32-rounded field would be dominated by its rounding for weak parameters
+    _say("c5: adjoint gradient with respect to the charges")
+    f64 = torch.float64
+    theta = theta0.clone().requires_grad_(True)
+    L0 = loss(field(theta, f64))
+    L0.backward()
+    grad = theta.grad.detach().cpu().numpy()
+    t0 = theta0.cpu().numpy()
+    # small steps: the log10 Q term is strongly curved, and larger steps let a few end
+    # points cross a box edge (a jump of Q at the points that use them)
+    fd = np.zeros(32)
+    for i in range(32):
+        h = 1e-6 * max(1.0, abs(t0[i]))
+        tp, tm = theta0.clone(), theta0.clone()
+        tp[i] += h
+        tm[i] -= h
+        with torch.no_grad():
+            fd[i] = (float(loss(field(tp, f64))) - float(loss(field(tm, f64)))) / (2 * h)
+    # relative error, floored at 1% of the largest component (some parameters' Q and
+    # footpoint terms nearly cancel)
+    scale = np.abs(fd).max()
+    err = np.abs(grad - fd) / np.maximum(np.abs(fd), 1e-2 * scale)
+    print("c5 charge params: max rel err", err.max(), "grad", grad[:4], "fd", fd[:4])
+    assert err.max() < 1e-3, (err.max(), int(np.argmax(err)))
+
+    _say("c5: adjoint gradient with respect to the FP32 node values")
+    B = field(theta0).requires_grad_(True)
+    loss(B).backward()
+    gB = B.grad.detach().double()
+    with torch.no_grad():
+        B0 = field(theta0)
+    flat = gB.abs().flatten()
+    top = torch.topk(flat, 2000).indices.cpu().numpy()
+    rng = np.random.default_rng(29)
+    nodes = np.concatenate([rng.choice(top, 32, replace=False), rng.choice(flat.numel(), 32, replace=False)])
+    gnodes = gB.flatten()[torch.tensor(nodes, device="cuda")].cpu().numpy()
+    fdn = np.zeros(len(nodes))
+    for t, n in enumerate(nodes):
+        v = float(B0.flatten()[n])
+        h = 1e-4 * max(abs(v), 1e-2)
+        Bp, Bm = B0.clone(), B0.clone()
+        Bp.view(-1)[n] = v + h
+        Bm.view(-1)[n] = v - h
+        dh = float(Bp.view(-1)[n].double() - Bm.view(-1)[n].double())
+        with torch.no_grad():
+            fdn[t] = (float(loss(Bp)) - float(loss(Bm))) / dh
+    nscale = np.abs(fdn).max()
+    nerr = np.abs(gnodes - fdn) / np.maximum(np.abs(fdn), 1e-2 * nscale)
+    print("c5 nodes: max rel err", nerr.max())
+    assert nerr.max() < 1e-2, (nerr.max(), gnodes[np.argmax(nerr)], fdn[np.argmax(nerr)])
+
+    _say("c5: gradient steps")
+    # the fitting loss proper: its masks follow the current map (points whose Q is NaN,
+    # failed or above 1e8 on either side are left out; footpoints count where both
+    # maps end on the same faces)
+    bad = fq.ST_FATAL | fq.ST_MIXEDFACE
+    tvalid = torch.isfinite(rt["q"]) & (rt["q"] < 1e8) & ((rt["status"].to(torch.int32) & bad) == 0)
+    from paper_2208_12569_amd.autograd import qtw_map
+
+    def fit_loss(B):
+        qq, tw, eb, ef, st = qtw_map(B, g, pl, fq.Params(precision=F64), 32)
+        m = tvalid & torch.isfinite(qq) & (qq < 1e8) & ((st.to(torch.int32) & bad) == 0)
+        lq = torch.log10(torch.where(m, qq, torch.ones_like(qq)))
+        lt = torch.log10(torch.where(m, rt["q"], torch.ones_like(qq)))
+        me = (m & same)[..., None]
+        db = torch.where(me, eb, tgt["eb"]) - tgt["eb"]
+        df = torch.where(me, ef, tgt["ef"]) - tgt["ef"]
+        e = (db ** 2).sum(-1) + (df ** 2).sum(-1)
+        return (((lq - lt) ** 2) * m).sum() / m.sum().clamp(min=1) + e.sum() / me.sum().clamp(min=1)
+
+    theta = theta0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([theta], lr=1e-3)
+    losses = []
+    for _ in range(4):
+        opt.zero_grad()
+        L = fit_loss(field(theta))
+        L.backward()
+        assert torch.isfinite(theta.grad).all()
+        opt.step()
+        losses.append(float(L.detach()))
+    print("c5 losses", losses)
+    assert all(np.isfinite(losses)) and losses[-1] < losses[0]
