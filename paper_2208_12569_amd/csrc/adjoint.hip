@@ -283,10 +283,12 @@ __constant__ double kB[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 5643
 // and adds H * sum b_s G_s / g_s to Tw (G = twk (J.B)/|B|^2, g = 1 or dp_axis/ds).
 // Given lam = dL/dp' and ltw = dL/dTw, returns lam = dL/dp and adds dL/d(corner
 // values) of B and curl B to gB, gJ.
+// endb: for the last accepted step of a half line, the axis of the box face the line
+// ends on (-1 otherwise).
 template <bool TW>
 __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const StepRec &sr,
-                             const LaneConst<double> &K, double sgn, double lam[3], double ltw,
-                             double gB[3][8], double gJ[3][8])
+                             const LaneConst<double> &K, double sgn, int endb, double lam[3],
+                             double ltw, double gB[3][8], double gJ[3][8])
 {
     const double R[3] = {K.rx, K.ry, K.rz};
     const double p[3] = {sr.p0, sr.p1, sr.p2};
@@ -311,17 +313,42 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
         g[st] = ax >= 0 ? F[ax] : 1.0;
         for (int c = 0; c < 3; c++) k[st][c] = F[c] / g[st];
     }
-    // adjoint of the outputs that depend on the step: the landing axis ends exactly
-    // on its face, and a coordinate clamped to a box face is constant
-    const int cell[3] = {sr.c0, sr.c1, sr.c2};
-    const int nmax[3] = {K.nx - 2, K.ny - 2, K.nz - 2};
+    // Adjoint of the outputs that depend on the step. A landing coordinate ends
+    // exactly on its face. When the step puts the line on the box face b it ends on
+    // without landing on it (the last step of the line landed on another face or was
+    // a plain step, with b exactly on the face or clamped onto it), that box face is
+    // the end constraint: the landing (if any) is incidental, the step length is held
+    // fixed, and the end moves along the line's direction onto the face,
+    // p_end = p* - k (p*_b - face_b) / k_b, whose adjoint is taken here.
     double lo[3];
-    for (int q = 0; q < 3; q++) {
-        double dy = 0.0;
-        for (int st = 0; st < 6; st++) dy += kB[st] * k[st][q];
-        const double nq = p[q] + H * dy;
-        const bool clamped = (nq > 1.0 && cell[q] == nmax[q]) || (nq < 0.0 && cell[q] == 0);
-        lo[q] = (q == ax || clamped) ? 0.0 : lam[q];
+    int b = -1;
+    if (endb >= 0 && endb != ax) b = endb;
+    else if (endb < 0 && sr.clamp) b = (sr.clamp & 1) ? 0 : ((sr.clamp & 2) ? 1 : 2);
+    const bool onbox = b >= 0;
+    if (!onbox) {
+        for (int q = 0; q < 3; q++) lo[q] = q == ax ? 0.0 : lam[q];
+    } else {
+        double pe[3];
+        for (int q = 0; q < 3; q++) {
+            double dy = 0.0;
+            for (int st = 0; st < 6; st++) dy += kB[st] * k[st][q];
+            pe[q] = p[q] + H * dy;
+        }
+        // direction F and twist integrand G at the end: moving the end by dt along the
+        // line moves p by F dt and Tw by G dt, with dt = -(p*_b - face_b) / F_b
+        double Be[3], Je[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; c++) Be[c] = poly<double>(cb[c], pe[0], pe[1], pe[2]);
+        if (TW)
+            for (int c = 0; c < 3; c++) Je[c] = poly<double>(cj[c], pe[0], pe[1], pe[2]);
+        const double be2 = Be[0] * Be[0] + Be[1] * Be[1] + Be[2] * Be[2];
+        const double inve = 1.0 / sqrt(be2);
+        double Fe[3];
+        for (int c = 0; c < 3; c++) Fe[c] = sgn * inve * Be[c] * R[c];
+        double s_ = 0.0;
+        for (int q = 0; q < 3; q++)
+            if (q != b) s_ += lam[q] * Fe[q];
+        if (TW) s_ += ltw * K.twk * (Je[0] * Be[0] + Je[1] * Be[1] + Je[2] * Be[2]) * inve * inve;
+        for (int q = 0; q < 3; q++) lo[q] = q == b ? -s_ / Fe[b] : lam[q];
     }
     double mu[6][3];
     double dH = 0.0;
@@ -392,7 +419,7 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
             dH += kA[st][jj] * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
         }
     }
-    if (ax >= 0) ln[ax] -= dH;  // H = face - p_axis
+    if (ax >= 0 && !onbox) ln[ax] -= dH;  // H = face - p_axis
     for (int a = 0; a < 3; a++) lam[a] = ln[a];
 }
 
@@ -400,11 +427,13 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
 struct Capture {
     int *axis;
     double *H;
+    int *clamp;
     __device__ __forceinline__ void operator()(int) const {}
-    template <typename T> __device__ __forceinline__ void accepted(int a, T h) const
+    template <typename T> __device__ __forceinline__ void accepted(int a, T h, int cl) const
     {
         *axis = a;
         *H = (double)h;
+        *clamp = cl;
     }
 };
 
@@ -456,6 +485,10 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
         const int64_t h = (int64_t)hq;
         double lam[3];
         for (int a = 0; a < 3; a++) lam[a] = bp.lam_end[3 * h + a] * J.spacing[a];
+        // the end lies on its box face: only its in-face coordinates can move
+        const int fe = J.rec.face[h];
+        if (fe >= 0) lam[fe >> 1] = 0.0;
+        const int endax = fe >= 0 ? (fe >> 1) : -1;
         const double ltw = TW ? bp.lam_tw[h] : 0.0;
         if (lam[0] == 0.0 && lam[1] == 0.0 && lam[2] == 0.0 && ltw == 0.0) continue;
         const uint16_t st = J.rec.st[h];
@@ -488,9 +521,9 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             int nrec = 0;
             unsigned acc = 0;
-            int cap_axis = -1;
+            int cap_axis = -1, cap_clamp = 0;
             double cap_H = 0.0;
-            const Capture capture{&cap_axis, &cap_H};
+            const Capture capture{&cap_axis, &cap_H, &cap_clamp};
             for (;;) {
                 if (nrec == target && !last) break;
                 StepRec pre;
@@ -508,6 +541,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     }
                     pre.H = cap_H;
                     pre.axis = cap_axis;
+                    pre.clamp = cap_clamp;
                     buf[nrec++] = pre;
                 }
                 if (fin_st >= 0) {
@@ -533,7 +567,8 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
                     load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
                 }
-                step_adjoint<TW>(cb, cj, sr, K, sgn, lam, ltw, gB, gJ);
+                const int endb = (last && r == nrec - 1) ? endax : -1;
+                step_adjoint<TW>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
                 n_steps++;
             }
             if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);

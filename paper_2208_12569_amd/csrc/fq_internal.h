@@ -86,12 +86,14 @@ struct Ckpt {
     int32_t prev;  // pool slot of the previous checkpoint of the half line, -1 = none
 };
 
-// One accepted step found by a replay, for the reverse sweep (48 bytes).
+// One accepted step found by a replay, for the reverse sweep (56 bytes).
 struct StepRec {
     double p0, p1, p2;  // local position before the step
     double H;           // step length in the independent variable
     int32_t c0, c1, c2;
     int32_t axis;       // landing axis, -1 for a plain step
+    int32_t clamp;      // bit q: coordinate q was clamped onto a box face
+    int32_t pad;
 };
 
 struct TraceParams {

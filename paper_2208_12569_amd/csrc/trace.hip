@@ -62,8 +62,10 @@ __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, con
     return true;
 }
 
+// The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
+// (the latency of cell fetches is then hidden by more waves).
 template <typename T, typename S, bool TW, bool UNI, bool TAPE>
-__global__ __launch_bounds__(256) void trace_kernel(const TraceJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
 {

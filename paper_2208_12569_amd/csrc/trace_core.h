@@ -54,8 +54,33 @@ template <> struct Num<double> {
     {
         return __builtin_fma(a, b, c);
     }
-    static __host__ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-    static __host__ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    // 1/sqrt(x) and 1/x: the hardware estimates refined by Newton-Raphson iterations
+    // (two each, to within a few ulp of FP64) instead of the IEEE division and square
+    // root sequences. Arguments are positive normal |B|^2 values and direction
+    // components bounded away from zero by the callers.
+    static __host__ __device__ __forceinline__ double rsq(double x)
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        double y = __builtin_amdgcn_rsq(x);
+        const double hx = 0.5 * x;
+        y = y * __builtin_fma(-hx * y, y, 1.5);
+        y = y * __builtin_fma(-hx * y, y, 1.5);
+        return y;
+#else
+        return 1.0 / sqrt(x);
+#endif
+    }
+    static __host__ __device__ __forceinline__ double rcp(double x)
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        double y = __builtin_amdgcn_rcp(x);
+        y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+        y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+        return y;
+#else
+        return 1.0 / x;
+#endif
+    }
     static constexpr double ov = 1e-9;
     static constexpr double tau = 1e-9;
     static constexpr double null_rel = 1e-60;
@@ -175,16 +200,18 @@ enum Ev : int {
 
 struct NoEvents {
     __host__ __device__ __forceinline__ void operator()(int) const {}
-    // an accepted step: landing axis (-1 for a plain step) and its signed length in
-    // the independent variable (arc length for a plain step, the axis coordinate
-    // for a landing)
-    template <typename T> __host__ __device__ __forceinline__ void accepted(int, T) const {}
+    // an accepted step: landing axis (-1 for a plain step), its signed length in the
+    // independent variable (arc length for a plain step, the axis coordinate for a
+    // landing) and the coordinates (bit q) it left past a box face and that were
+    // clamped onto it
+    template <typename T> __host__ __device__ __forceinline__ void accepted(int, T, int) const {}
 };
 
 // Carry a coordinate that left [0,1] by a small amount into the neighbouring cell
-// (on a box face it is clamped to the face). Returns true if the cell changed.
+// (on a box face it is clamped to the face, and `bit` is set in `clamped`). Returns
+// true if the cell changed.
 template <typename T>
-__host__ __device__ __forceinline__ bool carry(int &c, T &p, int n)
+__host__ __device__ __forceinline__ bool carry(int &c, T &p, int n, int &clamped, int bit)
 {
     if (p > T(1)) {
         if (c < n - 2) {
@@ -193,6 +220,7 @@ __host__ __device__ __forceinline__ bool carry(int &c, T &p, int n)
             return true;
         }
         p = T(1);
+        clamped |= bit;
     } else if (p < T(0)) {
         if (c > 0) {
             c--;
@@ -200,6 +228,7 @@ __host__ __device__ __forceinline__ bool carry(int &c, T &p, int n)
             return true;
         }
         p = T(0);
+        clamped |= bit;
     }
     return false;
 }
@@ -344,8 +373,13 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                 y[q] = N::fma_(H, acc, q == 0 ? L.p0 : (q == 1 ? L.p1 : L.p2));
             }
             T g0s, g1s, g2s, gts, b2s;
-            rhs<T, TW>(cb, cj, y[0], y[1], y[2], L.sgn, K.rx, K.ry, K.rz, K.twk, g0s, g1s, g2s, gts,
-                       b2s);
+            // the twist integrand of stage 1 has weight zero in the fifth-order sum
+            if (st == 1)
+                rhs<T, false>(cb, cj, y[0], y[1], y[2], L.sgn, K.rx, K.ry, K.rz, K.twk, g0s, g1s, g2s,
+                              gts, b2s);
+            else
+                rhs<T, TW>(cb, cj, y[0], y[1], y[2], L.sgn, K.rx, K.ry, K.rz, K.twk, g0s, g1s, g2s,
+                           gts, b2s);
             b2min = mn(b2min, b2s);
             if (!finite_(b2s)) ok = false;
             T g = T(1);
@@ -361,7 +395,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             k[st][1] = g1s * ig;
             k[st][2] = g2s * ig;
             const T bs = st == 2 ? B2 : st == 3 ? B3 : st == 4 ? B4 : st == 5 ? B5 : T(0);
-            stw = N::fma_(bs, gts * ig, stw);
+            if (st != 1) stw = N::fma_(bs, gts * ig, stw);
             slen = N::fma_(bs, ig, slen);
         }
         T dyv[3], e[3];
@@ -418,15 +452,16 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                 L.p0 = n0;
                 L.p1 = n1;
                 L.p2 = n2;
-                bool moved = carry(L.c0, L.p0, K.nx);
-                moved |= carry(L.c1, L.p1, K.ny);
-                moved |= carry(L.c2, L.p2, K.nz);
+                int cl = 0;
+                bool moved = carry(L.c0, L.p0, K.nx, cl, 1);
+                moved |= carry(L.c1, L.p1, K.ny, cl, 2);
+                moved |= carry(L.c2, L.p2, K.nz, cl, 4);
                 if (moved) need_load = true;
                 L.tw += (double)(H * stw);
                 L.len += (double)(H * slen);
                 L.h = mn(L.h * (T)grow, T(4));
                 n_acc++;
-                ev.accepted(-1, H);
+                ev.accepted(-1, H, cl);
                 ev(EV_ACCEPT_ARC);
             } else {
                 // the line curved out of the cell before the straight-line guess: land
@@ -467,14 +502,15 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         L.len += (double)(H * slen);
         L.h = mn(fabs(s_step) * (T)grow, T(4));
         n_acc++;
-        ev.accepted(axis, H);
-        ev(EV_ACCEPT_LAND);
         // carry small overshoots of the other coordinates (a crossing near an edge)
         bool moved = false;
-        if (axis != 0) moved |= carry(L.c0, L.p0, K.nx);
-        if (axis != 1) moved |= carry(L.c1, L.p1, K.ny);
-        if (axis != 2) moved |= carry(L.c2, L.p2, K.nz);
+        int cl = 0;
+        if (axis != 0) moved |= carry(L.c0, L.p0, K.nx, cl, 1);
+        if (axis != 1) moved |= carry(L.c1, L.p1, K.ny, cl, 2);
+        if (axis != 2) moved |= carry(L.c2, L.p2, K.nz, cl, 4);
         if (moved) need_load = true;
+        ev.accepted(axis, H, cl);
+        ev(EV_ACCEPT_LAND);
         xa = axis;
         xd = d;
     }

@@ -76,9 +76,19 @@ def test_shear_closed_form_derivatives(fq):
     gq = _grad(fq, B, g, pl, stats, dq=torch.tensor(interior.ravel(), device="cuda"))
     want = interior.sum() * 2 * s * L * L
     got = float((gq * dBds).sum())
-    assert abs(got / want - 1) < 1e-6, (got, want)
     st = stats.tolist()
+    print("shear dQ/ds", got, want, "stats", st)
     assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0, st
+    assert abs(got / want - 1) < 1e-6, (got, want)
+    # every point on its own, including lines that end where a cell face meets the
+    # top face (an end reached by landing on the cell face while the top coordinate
+    # is clamped onto the box face)
+    _say("shear: dQ/ds point by point")
+    for pt in np.flatnonzero(interior.ravel()):
+        dq = torch.zeros(npts, dtype=torch.float64, device="cuda")
+        dq[int(pt)] = 1.0
+        g1 = float((_grad(fq, B, g, pl, dq=dq) * dBds).sum())
+        assert abs(g1 - 2 * s * L * L) < 1e-6, (int(pt), g1)
     _say("shear: dTw/ds")
     y1 = pl.points()[:, 1]
     eta = y1 - y0
