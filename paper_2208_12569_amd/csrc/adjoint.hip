@@ -518,7 +518,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                 bad = true;
                 break;
             }
-            load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             int nrec = 0;
             unsigned acc = 0;
             int cap_axis = -1, cap_clamp = 0;
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     break;
                 }
                 if (need_load)
-                    load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                    load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             }
             if (!bad && !last) {
                 const Ckpt nx = bp.tape[next];
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                 if (sr.c0 != cc0 || sr.c1 != cc1 || sr.c2 != cc2) {
                     if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
                     cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
-                    load_cell<double, S, TW>(J.nodeA, J.nodeC, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+                    load_cell<double, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
                 }
                 const int endb = (last && r == nrec - 1) ? endax : -1;
                 step_adjoint<TW>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);

@@ -132,8 +132,8 @@ bool plane_on_face(const fq_plane &pl, const fq_field &f)
 }
 
 struct SpecWs {
-    size_t nodeA, nodeC, bmax, end, tw, len, face, st;
-    size_t nodeA64, nodeC64;  // FP64 node records for the FP64 pass (FP64 grids only)
+    size_t nodes, bmax, end, tw, len, face, st;
+    size_t nodes64;  // FP64 node records for the FP64 pass (FP64 grids only)
     size_t rot_index, rot, rot_count, r_end, r_tw, r_len, r_face, r_st;
     bool rotate;
     int64_t nlines;
@@ -231,8 +231,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         memset(&w, 0, sizeof w);
         const int64_t nn = nodes_of(s.f);
         w.nlines = lines_of(s);
-        w.nodeA = cv.take((size_t)nn * 4 * tsz);
-        w.nodeC = P.want_tw ? cv.take((size_t)nn * 2 * tsz) : 0;
+        w.nodes = cv.take((size_t)nn * (P.want_tw ? 8 : 4) * tsz);
         w.bmax = cv.take(sizeof(float));
         take_recs(cv, w.nlines, w.end, w.tw, w.len, w.face, w.st);
         w.rotate = (s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f));
@@ -263,8 +262,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             off_jobs64 = cv.take((size_t)njobs * sizeof(TraceJob));
             for (int i = 0; i < ns; i++) {
                 const int64_t nn = nodes_of(specs[i].f);
-                W[i].nodeA64 = cv.take((size_t)nn * 4 * 8);
-                W[i].nodeC64 = P.want_tw ? cv.take((size_t)nn * 2 * 8) : 0;
+                W[i].nodes64 = cv.take((size_t)nn * (P.want_tw ? 8 : 4) * 8);
             }
         }
     }
@@ -306,11 +304,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         SpecWs &w = W[i];
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.bmax), 1, 0u, stream));
         if (w.rotate) FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.rot_count), 1, 0u, stream));
-        FQ_TRY(launch_prep(*s.f, P.precision, P.want_tw, ws + w.nodeA, P.want_tw ? ws + w.nodeC : nullptr,
-                           (float *)(ws + w.bmax), stream));
+        FQ_TRY(launch_prep(*s.f, P.precision, P.want_tw, ws + w.nodes, (float *)(ws + w.bmax), stream));
         if (fixup && fix_store == FQ_DT_F64)
-            FQ_TRY(launch_prep(*s.f, FQ_PREC_F64, P.want_tw, ws + w.nodeA64,
-                               P.want_tw ? ws + w.nodeC64 : nullptr, (float *)(ws + w.bmax), stream));
+            FQ_TRY(launch_prep(*s.f, FQ_PREC_F64, P.want_tw, ws + w.nodes64, (float *)(ws + w.bmax),
+                               stream));
     }
     // rotated-S0 classification (only for a single map)
     std::vector<MapJob> maps(ns);
@@ -344,8 +341,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         SpecWs &w = W[i];
         TraceJob &J = jobs[jj++];
         memset(&J, 0, sizeof J);
-        J.nodeA = ws + w.nodeA;
-        J.nodeC = P.want_tw ? ws + w.nodeC : nullptr;
+        J.nodes = ws + w.nodes;
         J.bmax2 = (const float *)(ws + w.bmax);
         for (int a = 0; a < 3; a++) {
             J.n[a] = (int32_t)s.f->n[a];
@@ -460,15 +456,13 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             int k = 0;
             for (int i = 0; i < ns; i++) {
                 TraceJob J = jobs[i];
-                J.nodeA = ws + W[i].nodeA64;
-                J.nodeC = P.want_tw ? ws + W[i].nodeC64 : nullptr;
+                J.nodes = ws + W[i].nodes64;
                 FQ_TRY(launch_store_job(J, j64 + k++, stream));
             }
             for (int i = 0; i < ns; i++) {
                 if (!W[i].rotate) continue;
                 TraceJob J = jobs[k];
-                J.nodeA = ws + W[i].nodeA64;
-                J.nodeC = P.want_tw ? ws + W[i].nodeC64 : nullptr;
+                J.nodes = ws + W[i].nodes64;
                 FQ_TRY(launch_store_job(J, j64 + k++, stream));
             }
             fix_jobs = j64;

@@ -37,8 +37,8 @@ struct HalfRecs {
 
 // One independent tracing job: a prepared field plus a seed set.
 struct TraceJob {
-    const void *nodeA;   // per node (Bx, By, Bz, Jx) in the compute type
-    const void *nodeC;   // per node (Jy, Jz)
+    const void *nodes;   // node records in the compute type: (Bx, By, Bz, Jx, Jy, Jz, 0, 0)
+                         // with the twist integrand, else (Bx, By, Bz, 0)
     const float *bmax2;  // max |B|^2 over the nodes (float, written by the prep pass)
     int32_t n[3];
     int32_t kind;
@@ -138,8 +138,8 @@ struct BwdParams {
 };
 
 // Host-side launchers, one per translation unit.
-hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodeA, void *nodeC,
-                       float *bmax2, hipStream_t s);
+hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodes, float *bmax2,
+                       hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 // prec: compute type (FQ_PREC_F32X = float, FQ_PREC_F64 = double);

@@ -93,11 +93,10 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
     Lane<T> L{};
     LaneConst<T> K{};
     K.max_steps = tp.max_steps;
-    const void *nodeA = nullptr, *nodeC = nullptr;
+    const void *nodes = nullptr;
     if (UNI) {
         const TraceJob &J0 = jobs[0];
-        nodeA = J0.nodeA;
-        nodeC = J0.nodeC;
+        nodes = J0.nodes;
         K.nx = J0.n[0];
         K.ny = J0.n[1];
         K.nz = J0.n[2];
@@ -153,8 +152,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
                         seed_of_line(J, line, r, nrm);
                         jb = j;
                         if (!UNI) {
-                            nodeA = J.nodeA;
-                            nodeC = J.nodeC;
+                            nodes = J.nodes;
                             K.nx = J.n[0];
                             K.ny = J.n[1];
                             K.nz = J.n[2];
@@ -196,7 +194,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
 
         // ---- fetch the cell (the only load site) ----------------------------------------
         if (jb >= 0 && need_load) {
-            load_cell<T, S, TW>(nodeA, nodeC, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            load_cell<T, S, TW>(nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             need_load = false;
             n_fetch++;
             if (fresh) {

@@ -11,9 +11,6 @@ namespace dev {
 template <typename T> struct V4;
 template <> struct V4<float> { using t = float4; };
 template <> struct V4<double> { using t = double4; };
-template <typename T> struct V2;
-template <> struct V2<float> { using t = float2; };
-template <> struct V2<double> { using t = double2; };
 
 // Pointers read from the job table are generic; marking them as global memory
 // (address space 1) makes the compiler emit global instead of flat loads/stores.
@@ -31,27 +28,28 @@ template <typename P> __device__ __forceinline__ const FQ_GLOBAL P *gptr(const P
     return (const FQ_GLOBAL P *)p;
 }
 
-// Fetch one cell: 8 corner records (Bx, By, Bz, Jx) + (Jy, Jz) of type S, turned into
-// monomial coefficients of type T.
+// Fetch one cell: 8 corner records of type S, turned into monomial coefficients of
+// type T. With the twist integrand a node record is 8 values (Bx, By, Bz, Jx | Jy, Jz,
+// 0, 0): both halves of a corner come from one 32-byte (FP32) record, so a cell
+// touches about 5 cache lines; without it a record is (Bx, By, Bz, 0).
 template <typename T, typename S, bool TW>
-__device__ __forceinline__ void load_cell(const void *nodeA, const void *nodeC, int nx, int ny,
-                                          int cx, int cy, int cz, T cb[3][8], T cj[3][8])
+__device__ __forceinline__ void load_cell(const void *nodes, int nx, int ny, int cx, int cy,
+                                          int cz, T cb[3][8], T cj[3][8])
 {
-    const FQ_GLOBAL typename V4<S>::t *A = gptr((const typename V4<S>::t *)nodeA);
-    const FQ_GLOBAL typename V2<S>::t *C = gptr((const typename V2<S>::t *)nodeC);
+    const FQ_GLOBAL typename V4<S>::t *A = gptr((const typename V4<S>::t *)nodes);
     const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
     const int64_t base = (int64_t)cz * sz + (int64_t)cy * sy + cx;
     T f[6][8];
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int64_t o = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0);
-        const typename V4<S>::t a = A[o];
+        const typename V4<S>::t a = A[TW ? 2 * o : o];
         f[0][q] = (T)a.x;
         f[1][q] = (T)a.y;
         f[2][q] = (T)a.z;
         f[3][q] = (T)a.w;
         if (TW) {
-            const typename V2<S>::t c = C[o];
+            const typename V4<S>::t c = A[2 * o + 1];
             f[4][q] = (T)c.x;
             f[5][q] = (T)c.y;
         }
