@@ -91,10 +91,11 @@ typedef struct {
     int32_t want_tw;   /* nonzero: integrate Tw (the curl planes are built) */
     int32_t block;     /* threads per block of the tracer: 64, 128, 192 or 256; 0 = 256 */
     int32_t waves_per_cu; /* resident waves per CU the tracer's grid is sized for; 0 = the most that fit */
-    double graze;      /* FQ_PREC_F32X only: a line whose field makes an angle |Bn/B| below this
-                          with S0 at its seed or with the face at either end (such lines turn
-                          FP32 rounding into large footpoint errors) is traced again in FP64,
-                          as is any line the FP32 pass could not finish; default 0.05,
+    double graze;      /* FQ_PREC_F32X only: both halves of a line whose field makes an angle
+                          |Bn/B| below this with S0 at its seed, and a half line whose field
+                          makes such an angle with the face it ends on (these turn FP32
+                          rounding into large footpoint errors), are traced again in FP64,
+                          as is any half line the FP32 pass could not finish; default 0.05,
                           negative = no FP64 pass */
     uint64_t *stats;   /* device, optional: 5 counters ADDED to by the tracer — trial steps,
                           accepted steps, cell fetches, half lines traced, half lines traced

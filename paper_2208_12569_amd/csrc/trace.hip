@@ -282,10 +282,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
     }
 }
 
-// Lines whose field is nearly tangent to S0 at the seed, or to the face at either
-// end, turn FP32 rounding into large footpoint errors (a height error d of a line
-// meeting a plane at angle a moves its crossing by d/a); they and any line the FP32
-// pass could not finish are listed, both halves, for the FP64 pass.
+// Lines whose field is nearly tangent to S0 at the seed, or half lines whose field
+// is nearly tangent to the face they end on, turn FP32 rounding into large footpoint
+// errors (a height error d of a line meeting a plane at angle a moves its crossing
+// by d/a); those half lines, and any the FP32 pass could not finish, are listed for
+// the FP64 pass.
 __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double thr,
                              FixEntry *__restrict__ list, uint32_t *__restrict__ count,
                              int64_t cap)
@@ -298,31 +299,33 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
         const uint16_t sb = J.rec.st[hb], sf = J.rec.st[hf];
         const uint16_t hard = FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_NONFINITE;
         if ((sb | sf) & hard) continue;
-        bool redo = ((sb | sf) & FQ_ST_MAXSTEPS) != 0;
-        if (!redo) {
+        // a half line is traced again if the FP32 pass could not finish it, if the
+        // seed is grazing (both halves then stepped at the tolerance floor), or if
+        // its own end is grazing (the footpoint error is amplified at its own end only)
+        bool seed_graze = false;
+        if (J.kind != SEED_ROTATED) {
             double r[3], nrm[3], B[3];
-            if (J.kind != SEED_ROTATED) {
-                seed_of_line(J, l, r, nrm);
-                interp64(J.planes, r, B);
-                const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-                const double bn = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
-                if (!(fabs(bn) >= thr * bm)) redo = true;
-            }
-            for (int h = 0; h < 2 && !redo; h++) {
-                const int64_t q = h ? hf : hb;
-                const int face = J.rec.face[q];
-                if (face < 0 || J.rec.len[q] == 0.0) continue;
+            seed_of_line(J, l, r, nrm);
+            interp64(J.planes, r, B);
+            const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            const double bn = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+            seed_graze = !(fabs(bn) >= thr * bm);
+        }
+        for (int h = 0; h < 2; h++) {
+            const int64_t q = h ? hf : hb;
+            if (J.rec.len[q] == 0.0) continue;  // ends at its seed: nothing to improve
+            bool redo = seed_graze || (J.rec.st[q] & FQ_ST_MAXSTEPS) != 0;
+            const int face = J.rec.face[q];
+            if (!redo && face >= 0) {
                 const double e[3] = {J.rec.end[3 * q], J.rec.end[3 * q + 1], J.rec.end[3 * q + 2]};
+                double B[3];
                 interp64(J.planes, e, B);
                 const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-                if (!(fabs(B[face >> 1]) >= thr * bm)) redo = true;
+                redo = !(fabs(B[face >> 1]) >= thr * bm);
             }
-        }
-        if (redo) {
-            const uint32_t slot = atomicAdd(count, 2u);
-            if ((int64_t)slot + 1 < cap) {
-                list[slot] = FixEntry{job, 0, l};
-                list[slot + 1] = FixEntry{job, 1, l};
+            if (redo) {
+                const uint32_t slot = atomicAdd(count, 1u);
+                if ((int64_t)slot < cap) list[slot] = FixEntry{job, h, l};
             }
         }
     }
