@@ -331,7 +331,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "trace_kernel<float,float,true> (FP32 pass)",
+            "kernel": "trace_kernel<float, float, 1, true, false> (FP32 pass)",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",

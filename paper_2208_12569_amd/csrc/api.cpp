@@ -133,6 +133,7 @@ bool plane_on_face(const fq_plane &pl, const fq_field &f)
 
 struct SpecWs {
     size_t nodes, bmax, end, tw, len, face, st;
+    size_t tile_order, tile_bucket, tile_counts;  // plane jobs
     size_t nodes64;  // FP64 node records for the FP64 pass (FP64 grids only)
     size_t rot_index, rot, rot_count, r_end, r_tw, r_len, r_face, r_st;
     bool rotate;
@@ -234,6 +235,12 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         w.nodes = cv.take((size_t)nn * (P.want_tw ? 8 : 4) * tsz);
         w.bmax = cv.take(sizeof(float));
         take_recs(cv, w.nlines, w.end, w.tw, w.len, w.face, w.st);
+        if (s.kind == SPEC_PLANE) {
+            const int64_t ntiles = ((s.pl.nu + 7) / 8) * ((s.pl.nv + 7) / 8);
+            w.tile_order = cv.take((size_t)ntiles * sizeof(int32_t));
+            w.tile_bucket = cv.take((size_t)ntiles * sizeof(int32_t));
+            w.tile_counts = cv.take(256 * sizeof(uint32_t));
+        }
         w.rotate = (s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f));
         if (w.rotate) {
             nrot++;
@@ -392,6 +399,11 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         set_job_constants(J);
         J.item_base = items;
         items += 2 * tv;
+        if (s.kind == SPEC_PLANE) {
+            J.tile_order = (const int32_t *)(ws + w.tile_order);
+            FQ_TRY(launch_tile_order(J, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
+                                     (int32_t *)(ws + w.tile_order), stream));
+        }
     }
     TraceParams tp;
     memset(&tp, 0, sizeof tp);
@@ -401,6 +413,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         TraceJob &J = jobs[jj++];
         J = jobs[i];
         J.kind = SEED_ROTATED;
+        J.tile_order = nullptr;
         J.seeds = nullptr;
         J.rot = (const RotEntry *)(ws + w.rot);
         J.rot_count = (const uint32_t *)(ws + w.rot_count);
@@ -472,7 +485,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;
         if (ev && ev[2]) FQ_TRY(hipEventRecord(ev[2], stream));
-        FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw, fix_jobs, fp, counter, P.block,
+        // positions only: the twist integral is not sensitive to the end angle, so the
+        // FP32 pass's Tw is kept and the latency-bound FP64 pass skips the curl
+        FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw ? 2 : 0, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
         if (ev && ev[3]) FQ_TRY(hipEventRecord(ev[3], stream));
     }

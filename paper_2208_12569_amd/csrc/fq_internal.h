@@ -60,6 +60,7 @@ struct TraceJob {
     double rot_delta;             // SEED_ROTATED: distance of the extra seeds
     HalfRecs rec;
     int64_t item_base;   // first queue item of the job (items of both halves follow)
+    const int32_t *tile_order;  // plane jobs: tiles in the order they are traced (may be NULL)
     Planes64 planes;     // the caller's field, for FP64 angles in the grazing test
     // precomputed per-job constants of the tracer
     float rscale[3];     // reference length / spacing per axis
@@ -143,10 +144,16 @@ hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodes, fl
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 // prec: compute type (FQ_PREC_F32X = float, FQ_PREC_F64 = double);
-// store: node-record type (FQ_DT_F32 / FQ_DT_F64).
-hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_dev,
+// store: node-record type (FQ_DT_F32 / FQ_DT_F64);
+// twm: 0 = no twist, 1 = twist, 2 = positions only on twist-layout records, keeping the
+// twist already in the records (the FP64 re-trace).
+hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
                         const TraceParams &tp, unsigned long long *counter, int block,
                         int waves_per_cu, hipStream_t s);
+// Order the tiles of a plane job (J: its host copy, bmax2 and planes valid on the
+// device): bucket (tiles), counts (256), order (tiles) are workspace arrays.
+hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *counts,
+                             int32_t *order, hipStream_t s);
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s);
 

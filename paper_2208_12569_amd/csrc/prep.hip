@@ -48,27 +48,29 @@ __global__ __launch_bounds__(256) void prep_kernel(const S *__restrict__ bx,
                                                    typename V4<T>::t *__restrict__ A,
                                                    float *__restrict__ bmax2)
 {
-    // one thread per node: x from the block's x extent, (y, z) from the grid
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    const int k = blockIdx.z;
+    // a block takes 256-node pieces of x rows in turn (few blocks, so the maximum
+    // of |B|^2 costs one atomic per block)
+    const int bxs = (nx + 255) / 256;
+    const int64_t pieces = (int64_t)bxs * ny * nz;
     const int64_t nxy = (int64_t)nx * ny;
     float local = 0.0f;
-    if (i < nx) {
+    for (int64_t piece = blockIdx.x; piece < pieces; piece += gridDim.x) {
+        const int64_t row = piece / bxs;
+        const int i = (int)(piece - row * bxs) * 256 + (int)threadIdx.x;
+        const int k = (int)(row / ny);
+        const int j = (int)(row - (int64_t)k * ny);
+        if (i >= nx) continue;
         const int64_t q = (int64_t)k * nxy + (int64_t)j * nx + i;
         const double Bx = ld(bx, q), By = ld(by, q), Bz = ld(bz, q);
-        double Jx = 0.0, Jy = 0.0, Jz = 0.0;
-        if (want_tw) {
-            Jx = ddx(bz, q, j, ny, nx, ihy) - ddx(by, q, k, nz, nxy, ihz);
-            Jy = ddx(bx, q, k, nz, nxy, ihz) - ddx(bz, q, i, nx, 1, ihx);
-            Jz = ddx(by, q, i, nx, 1, ihx) - ddx(bx, q, j, ny, nx, ihy);
-        }
         typename V4<T>::t a;
         a.x = (T)Bx;
         a.y = (T)By;
         a.z = (T)Bz;
-        a.w = (T)Jx;
         if (want_tw) {
+            const double Jx = ddx(bz, q, j, ny, nx, ihy) - ddx(by, q, k, nz, nxy, ihz);
+            const double Jy = ddx(bx, q, k, nz, nxy, ihz) - ddx(bz, q, i, nx, 1, ihx);
+            const double Jz = ddx(by, q, i, nx, 1, ihx) - ddx(bx, q, j, ny, nx, ihy);
+            a.w = (T)Jx;
             typename V4<T>::t c;
             c.x = (T)Jy;
             c.y = (T)Jz;
@@ -77,6 +79,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const S *__restrict__ bx,
             A[2 * q] = a;
             A[2 * q + 1] = c;
         } else {
+            a.w = (T)0;
             A[q] = a;
         }
         const float fb2 = (float)(Bx * Bx + By * By + Bz * Bz);
@@ -110,8 +113,9 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
 template <typename S, typename T>
 hipError_t run_prep(const fq_field &f, int want_tw, void *A, float *bmax2, hipStream_t s)
 {
-    const unsigned bxs = (unsigned)((f.n[0] + 255) / 256);
-    hipLaunchKernelGGL((prep_kernel<S, T>), dim3(bxs, (unsigned)f.n[1], (unsigned)f.n[2]), dim3(256), 0, s,
+    const int64_t pieces = ((f.n[0] + 255) / 256) * f.n[1] * f.n[2];
+    const unsigned blocks = (unsigned)(pieces < 4096 ? pieces : 4096);
+    hipLaunchKernelGGL((prep_kernel<S, T>), dim3(blocks), dim3(256), 0, s,
                        (const S *)f.b[0], (const S *)f.b[1], (const S *)f.b[2], (int)f.n[0],
                        (int)f.n[1], (int)f.n[2], 1.0 / f.spacing[0], 1.0 / f.spacing[1],
                        1.0 / f.spacing[2], want_tw, (typename V4<T>::t *)A, bmax2);

@@ -39,7 +39,7 @@ using namespace dev;
 // uniform across the grid (kept in scalar registers).
 // TAPE: the adjoint's forward pass (FP64, single job), which also stores the lane
 // state at the start of every half line and after every tp.seg accepted steps.
-template <typename T, typename S, bool TW, bool UNI, bool TAPE>
+template <typename T, int TWM, bool UNI, bool TAPE>
 __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, const Lane<T> &L)
 {
     if (!TAPE) return true;
@@ -62,14 +62,17 @@ __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, con
     return true;
 }
 
+// TWM: 0 = no twist (narrow records), 1 = twist, 2 = positions only on wide records
+// (the FP64 re-trace, which keeps the twist of the first pass).
 // The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
 // (the latency of cell fetches is then hidden by more waves).
-template <typename T, typename S, bool TW, bool UNI, bool TAPE>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
+template <typename T, typename S, int TWM, bool UNI, bool TAPE>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
 {
     using N = Num<T>;
+    constexpr bool TW = TWM == 1;
     const int lane = threadIdx.x & 63;
 
     // queue size
@@ -143,8 +146,15 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
                         const TraceJob &J = jobs[j];
                         const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
                         const int64_t local = it - J.item_base;
-                        forward = local < nit;
-                        line = line_of_item(J, forward ? local : local - nit);
+                        if (J.kind == SEED_PLANE || J.kind == SEED_VOXELS) {
+                            // the forward and backward halves of a tile follow each
+                            // other, so long lines of either direction start early
+                            forward = ((local >> 6) & 1) == 0;
+                            line = line_of_item(J, ((local >> 7) << 6) | (local & 63));
+                        } else {
+                            forward = local < nit;
+                            line = line_of_item(J, forward ? local : local - nit);
+                        }
                     }
                     if (line >= 0) {
                         const TraceJob &J = jobs[j];
@@ -194,7 +204,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
 
         // ---- fetch the cell (the only load site) ----------------------------------------
         if (jb >= 0 && need_load) {
-            load_cell<T, S, TW>(nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            load_cell<T, S, TW, TWM != 0>(nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             need_load = false;
             n_fetch++;
             if (fresh) {
@@ -213,7 +223,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
                 L.tol = (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
                 if (TAPE) {
-                    if (store_ckpt<T, S, TW, UNI, TAPE>(tp, last_ck, L)) nck++;
+                    if (store_ckpt<T, TWM, UNI, TAPE>(tp, last_ck, L)) nck++;
                     else fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
                 }
             }
@@ -227,7 +237,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
             if (TAPE && n_acc != acc_before) {
                 acc_half++;
                 if (fin_st < 0 && acc_half % tp.seg == 0) {
-                    if (store_ckpt<T, S, TW, UNI, TAPE>(tp, last_ck, L)) {
+                    if (store_ckpt<T, TWM, UNI, TAPE>(tp, last_ck, L)) {
                         nck++;
                     } else {
                         fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TW && UNI) ? 3 : 1) void tr
             ge[3 * rec + 0] = e0;
             ge[3 * rec + 1] = e1;
             ge[3 * rec + 2] = e2;
-            gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
+            if (TWM != 2) gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
             gptr(J.rec.len)[rec] = bad ? NAN : L.len * J.dref;
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
@@ -332,23 +342,100 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
 }
 
 template <typename T, typename S, bool UNI>
-const void *kernel_of(int want_tw)
+const void *kernel_of(int twm)
 {
-    return want_tw ? (const void *)trace_kernel<T, S, true, UNI, false>
-                   : (const void *)trace_kernel<T, S, false, UNI, false>;
+    return twm == 1 ? (const void *)trace_kernel<T, S, 1, UNI, false>
+                    : twm == 2 ? (const void *)trace_kernel<T, S, 2, UNI, false>
+                               : (const void *)trace_kernel<T, S, 0, UNI, false>;
 }
 
 template <typename T, typename S, bool UNI, bool TAPE>
-void launch_ts(int want_tw, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
+void launch_ts(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
                const TraceParams &tp, unsigned long long *counter)
 {
-    if (want_tw) hipLaunchKernelGGL((trace_kernel<T, S, true, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
-    else hipLaunchKernelGGL((trace_kernel<T, S, false, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
+    if (twm == 1) hipLaunchKernelGGL((trace_kernel<T, S, 1, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
+    else if (twm == 2 && !TAPE) hipLaunchKernelGGL((trace_kernel<T, S, 2, UNI, false>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, 0, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
+}
+
+__global__ void fill_counts_kernel(uint32_t *counts)
+{
+    counts[threadIdx.x] = 0u;
+}
+
+// Tile order of a plane job: long lines start early, so the last ones to finish are
+// short. A tile's key is the largest |Bn0| of its seeds relative to max |B| (lines
+// rooted in strong normal field reach far), bucketed on a log scale; tiles are
+// placed bucket by bucket, largest keys first (the order inside a bucket does not
+// matter: every line's result is independent of when it is traced).
+__global__ void tile_key_kernel(TraceJob J, int32_t *__restrict__ bucket,
+                                uint32_t *__restrict__ counts)
+{
+    const int64_t ntiles = J.tiles[0] * J.tiles[1];
+    const double bmax = sqrt((double)*J.bmax2);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ty = t / J.tiles[0], tx = t - ty * J.tiles[0];
+        double key = 0.0;
+        for (int w = 0; w < 64; w++) {
+            const int64_t i = tx * 8 + (w & 7), j = ty * 8 + (w >> 3);
+            if (i >= J.dims[0] || j >= J.dims[1]) continue;
+            double r[3], B[3];
+            for (int a = 0; a < 3; a++) r[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
+            interp64(J.planes, r, B);
+            const double bn = fabs(B[0] * J.normal[0] + B[1] * J.normal[1] + B[2] * J.normal[2]);
+            key = bn > key ? bn : key;
+        }
+        int b = 255;
+        if (key > 0.0 && bmax > 0.0) {
+            const double lg = -16.0 * log2(key / bmax);
+            b = lg < 0.0 ? 0 : (lg > 255.0 ? 255 : (int)lg);
+        }
+        bucket[t] = b;
+        atomicAdd(counts + b, 1u);
+    }
+}
+
+__global__ void tile_scan_kernel(uint32_t *counts)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < 256; b++) {
+            const uint32_t c = counts[b];
+            counts[b] = acc;
+            acc += c;
+        }
+    }
+}
+
+__global__ void tile_place_kernel(int64_t ntiles, const int32_t *__restrict__ bucket,
+                                  uint32_t *__restrict__ offsets, int32_t *__restrict__ order)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t pos = atomicAdd(offsets + bucket[t], 1u);
+        order[pos] = (int32_t)t;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_dev,
+hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *counts,
+                             int32_t *order, hipStream_t s)
+{
+    const int64_t ntiles = J.tiles[0] * J.tiles[1];
+    int64_t b = (ntiles + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(fill_counts_kernel, dim3(1), dim3(256), 0, s, counts);
+    hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, J, bucket, counts);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(64), 0, s, counts);
+    hipLaunchKernelGGL(tile_place_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts,
+                       order);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
                         const TraceParams &tp, unsigned long long *counter, int block,
                         int waves_per_cu, hipStream_t s)
 {
@@ -365,14 +452,14 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
         // the adjoint's forward pass: FP64, one job, no FP64 re-trace list
         if (!f64 || !uni || tp.list || tp.seg < 1) return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
-        if (s64) launch_ts<double, double, true, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, float, true, true>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
         return hipGetLastError();
     }
     const void *fn;
-    if (!f64) fn = uni ? kernel_of<float, float, true>(want_tw) : kernel_of<float, float, false>(want_tw);
-    else if (s64) fn = uni ? kernel_of<double, double, true>(want_tw) : kernel_of<double, double, false>(want_tw);
-    else fn = uni ? kernel_of<double, float, true>(want_tw) : kernel_of<double, float, false>(want_tw);
+    if (!f64) fn = uni ? kernel_of<float, float, true>(twm) : kernel_of<float, float, false>(twm);
+    else if (s64) fn = uni ? kernel_of<double, double, true>(twm) : kernel_of<double, double, false>(twm);
+    else fn = uni ? kernel_of<double, float, true>(twm) : kernel_of<double, float, false>(twm);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
     if (per_cu <= 0) per_cu = 1;
@@ -383,14 +470,14 @@ hipError_t launch_trace(int prec, int store, int want_tw, const TraceJob *jobs_d
     }
     dim3 grid((unsigned)(per_cu * ncu)), blk((unsigned)block);
     if (!f64) {
-        if (uni) launch_ts<float, float, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<float, float, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<float, float, true, false>(twm, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<float, float, false, false>(twm, grid, blk, s, jobs_dev, tp, counter);
     } else if (s64) {
-        if (uni) launch_ts<double, double, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, double, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<double, double, true, false>(twm, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, double, false, false>(twm, grid, blk, s, jobs_dev, tp, counter);
     } else {
-        if (uni) launch_ts<double, float, true, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, float, false, false>(want_tw, grid, blk, s, jobs_dev, tp, counter);
+        if (uni) launch_ts<double, float, true, false>(twm, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<double, float, false, false>(twm, grid, blk, s, jobs_dev, tp, counter);
     }
     return hipGetLastError();
 }

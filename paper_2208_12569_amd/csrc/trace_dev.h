@@ -29,10 +29,10 @@ template <typename P> __device__ __forceinline__ const FQ_GLOBAL P *gptr(const P
 }
 
 // Fetch one cell: 8 corner records of type S, turned into monomial coefficients of
-// type T. With the twist integrand a node record is 8 values (Bx, By, Bz, Jx | Jy, Jz,
-// 0, 0): both halves of a corner come from one 32-byte (FP32) record, so a cell
-// touches about 5 cache lines; without it a record is (Bx, By, Bz, 0).
-template <typename T, typename S, bool TW>
+// type T. WIDE records hold 8 values (Bx, By, Bz, Jx | Jy, Jz, 0, 0): both halves of a
+// corner come from one 32-byte (FP32) record, so a cell touches about 5 cache lines;
+// narrow records are (Bx, By, Bz, 0). TW: build the curl coefficients too.
+template <typename T, typename S, bool TW, bool WIDE = TW>
 __device__ __forceinline__ void load_cell(const void *nodes, int nx, int ny, int cx, int cy,
                                           int cz, T cb[3][8], T cj[3][8])
 {
@@ -43,7 +43,7 @@ __device__ __forceinline__ void load_cell(const void *nodes, int nx, int ny, int
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int64_t o = base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0);
-        const typename V4<S>::t a = A[TW ? 2 * o : o];
+        const typename V4<S>::t a = A[WIDE ? 2 * o : o];
         f[0][q] = (T)a.x;
         f[1][q] = (T)a.y;
         f[2][q] = (T)a.z;
@@ -127,11 +127,13 @@ __device__ __forceinline__ int64_t fdiv(int64_t n, int64_t d, double inv_d, int6
 }
 
 // Line of queue item t of a job; -1 for tile holes. Plane seeds come in 8x8 tiles,
-// voxels in 4x4x4 tiles (64 neighbouring seeds per wave), lists in order.
+// voxels in 4x4x4 tiles (64 neighbouring seeds per wave), lists in order. Tiles are
+// taken in the job's tile order when it has one.
 __device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
 {
     if (J.kind == SEED_LIST || J.kind == SEED_ROTATED) return t < live_lines(J) ? t : -1;
-    const int64_t ti = t >> 6;
+    int64_t ti = t >> 6;
+    if (J.tile_order) ti = gptr(J.tile_order)[ti];
     const int w = (int)(t & 63);
     int64_t r0, i, j, k;
     const int64_t q0 = fdiv(ti, J.tiles[0], J.inv_t0, r0);

@@ -18,7 +18,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
-TRACER = "trace_kernel<float, float, true, true, false>"
+TRACER = "trace_kernel<float, float, 1, true, false>"
 
 
 def kernel_source_sha() -> str:
