@@ -12,6 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfastqsl.so")
+# the gather microbenchmark (the tracer's cell fetches without its arithmetic)
+GATHER_LIB = os.path.join(HERE, "libfqgather.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "prep.hip", "trace.hip", "stencil.hip", "adjoint.hip"]
@@ -54,8 +56,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    gobj = _compile("gatherbench.hip")
+    tmp = GATHER_LIB + ".tmp"
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, gobj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, GATHER_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {GATHER_LIB}")
     return LIB
 
 

@@ -1,0 +1,91 @@
+// Gather microbenchmark: the tracer's cell fetches without its arithmetic.
+//
+// Every lane walks from cell to neighbouring cell through a node-record array laid
+// out as the tracer's (8 FP32 values per node: B and curl B), fetching the 8 corner
+// records of each cell with the same 16 vector loads. The next cell depends on the
+// values just loaded (one fetch in flight per lane, as in the tracer, where the next
+// cell follows from the field), and the walks look like field lines: a persistent
+// direction biased upwards, the lanes of a wave starting on neighbouring cells of the
+// bottom face. The rate of fetches x 192 useful bytes (24 values of B and curl B at 8
+// corners) is the gather roofline the tracer is measured against.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+__device__ __forceinline__ uint32_t mix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restrict__ rec, int nx,
+                                                          int ny, int nz, int steps, uint32_t seed,
+                                                          float *__restrict__ sink)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = g >> 6;
+    // a wave starts on a 2 x 2 patch of bottom cells; patches tile the bottom face
+    const int px = (nx - 1) / 2, py = (ny - 1) / 2;
+    const int64_t patch = (wave * 7919) % ((int64_t)px * py);
+    int cx = (int)(patch % px) * 2 + (lane & 1);
+    int cy = (int)(patch / px) * 2 + ((lane >> 1) & 1);
+    int cz = 0;
+    uint32_t r = mix((uint32_t)g ^ seed);
+    // persistent direction: weights for x, y and an upward-biased z (in 1/256)
+    int wx = (int)(r & 127), wy = (int)((r >> 7) & 127), wz = 64 + (int)((r >> 14) & 127);
+    int sxn = (r >> 21) & 1 ? 1 : -1, syn = (r >> 22) & 1 ? 1 : -1, szn = 1;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    float acc = 0.0f;
+    for (int s = 0; s < steps; s++) {
+        const int64_t base = (int64_t)cz * sz + (int64_t)cy * sy + cx;
+        float v = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int64_t o = base + ((q & 1) ? 1 : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0);
+            const float4 a = rec[2 * o];
+            const float4 c = rec[2 * o + 1];
+            v += a.x + a.y + a.z + a.w + c.x + c.y;
+        }
+        acc += v;
+        // next cell: an axis drawn with the lane's weights, perturbed by the data
+        r = mix(r ^ __float_as_uint(v));
+        const int pick = (int)(r % (uint32_t)(wx + wy + wz));
+        if (pick < wx) {
+            cx += sxn;
+            if (cx < 0 || cx > nx - 2) { sxn = -sxn; cx += 2 * sxn; }
+        } else if (pick < wx + wy) {
+            cy += syn;
+            if (cy < 0 || cy > ny - 2) { syn = -syn; cy += 2 * syn; }
+        } else {
+            cz += szn;
+            if (cz < 0 || cz > nz - 2) { szn = -szn; cz += 2 * szn; }
+        }
+        cx = cx < 0 ? 0 : (cx > nx - 2 ? nx - 2 : cx);
+        cy = cy < 0 ? 0 : (cy > ny - 2 ? ny - 2 : cy);
+        cz = cz < 0 ? 0 : (cz > nz - 2 ? nz - 2 : cz);
+    }
+    sink[g] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+// records: nx*ny*nz nodes x 8 floats (device); lanes = blocks * 256; steps per lane.
+// Asynchronous on `stream`; returns a hipError_t code.
+int fqgb_walk(const void *records, int nx, int ny, int nz, int steps, int blocks, uint32_t seed,
+              float *sink, void *stream)
+{
+    if (!records || !sink || nx < 3 || ny < 3 || nz < 3 || steps < 1 || blocks < 1) return 1;
+    hipLaunchKernelGGL(gather_walk_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const float4 *)records, nx, ny, nz, steps, seed, sink);
+    return (int)hipGetLastError();
+}
+
+}  // extern "C"
