@@ -500,7 +500,9 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         L.p2 = axis == 2 ? (d > 0 ? T(1) : T(0)) : n2;
         L.tw += (double)(H * stw);
         L.len += (double)(H * slen);
-        L.h = mn(fabs(s_step) * (T)grow, T(4));
+        // a landing is cut short by the face, not by the error bound: unless the error
+        // asks for a smaller step, keep the step the controller had before the cut
+        L.h = grow >= 1.0f ? mn(mx(fabs(s_step) * (T)grow, L.h), T(4)) : fabs(s_step) * (T)grow;
         n_acc++;
         // carry small overshoots of the other coordinates (a crossing near an edge)
         bool moved = false;
