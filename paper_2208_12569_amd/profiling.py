@@ -31,7 +31,7 @@ def kernel_source_sha() -> str:
 
 
 def _short(name: str) -> str:
-    name = name.replace("fq::(anonymous namespace)::", "")
+    name = name.replace("fq::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
     if name.startswith("void "):
         name = name[5:]
     return name.split("(")[0] if "(" in name and "<" not in name.split("(")[0] else name[:110]
