@@ -449,6 +449,32 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
                 y_best[a] = plane;
             }
         }
+        /* A face crossed and crossed back within the trial step leaves its end inside
+         * along that axis, so the landing above may have found a later face: the
+         * landed point then lies beyond that face by more than the root tolerance.
+         * The line left through it first; land on it instead (each pass shortens the
+         * step, so this ends). */
+        for (int pass = 0; pass < 8; pass++) {
+            int a_out = -1;
+            double plane = 0.0;
+            for (int a = 0; a < 3 && a_out < 0; a++) {
+                if (a == a_best) continue;
+                double slack = 1e-12 * f->spacing[a];
+                if (y_best[a] > face_hi(f, L.c, a) + slack) a_out = a, plane = face_hi(f, L.c, a);
+                else if (y_best[a] < face_lo(f, L.c, a) - slack) a_out = a, plane = face_lo(f, L.c, a);
+            }
+            if (a_out < 0) break;
+            double ya[5], ta;
+            memcpy(ya, y_best, sizeof ya);
+            if ((st = land(&L, y, a_out, plane, t_best, y_best[a_out] - plane, ya, &ta))) {
+                res->status = st;
+                return;
+            }
+            t_best = ta;
+            a_best = a_out;
+            memcpy(y_best, ya, sizeof ya);
+            y_best[a_out] = plane;
+        }
         /* the shortened step must not leave the cell along another axis on the way
          * (a brief excursion over a neighbouring face): cut it there instead */
         {

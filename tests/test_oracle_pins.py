@@ -183,6 +183,31 @@ def test_p5_twisted_field_tw(orc):
     assert abs(e[1] - (yc + rho[4] * math.sin(ang))) < 1e-9
 
 
+@pytest.mark.parametrize("delta", [1e-5, 1e-6])
+def test_p9_line_grazing_a_face_before_landing(orc, delta):
+    """B = (1, 0, a(x - x0)): the lines are parabolas z = z_top + a (x - x0)^2 / 2 in
+    the plane y = const (Eq. rb). The apex rises delta above the cell face z = 1/2,
+    and the line crosses that face a distance eps before an x face, then crosses it
+    back within the same trial step. The cell-by-cell integration must treat the
+    z face as the first face crossed; taking the x face instead moves the line by
+    about sqrt(2 delta) eps. Both ends must match the closed form."""
+    g = cubic_grid(17, 17, 17)
+    a, zf = -1.0, 0.5
+    s = math.sqrt(2 * delta / -a)
+    for xf in (0.5, 0.5625):
+        for eps in (1e-5, 1e-4, 1e-3):
+            x0 = xf - eps + s
+            B = linear_field(g, [[0, 0, 0], [0, 0, 0], [a, 0, 0]], [1.0, 0.0, -a * x0])
+            xs, ys = 0.05, 0.53
+            zs = zf + delta + 0.5 * a * (xs - x0) ** 2
+            L = orc.trace(B, g, np.array([[xs, ys, zs]]))
+            assert L["face_f"][0] == 1 and L["face_b"][0] == 0
+            for key, xe in (("end_f", 1.0), ("end_b", 0.0)):
+                ze = zf + delta + 0.5 * a * (xe - x0) ** 2
+                e = L[key][0]
+                assert np.max(np.abs(e - [xe, ys, ze])) < 1e-11, (xf, eps, key, e)
+
+
 # --------------------------------------------------------------------------------------
 # invariances of Q on a charge field (Section 1, Section 2.1)
 # --------------------------------------------------------------------------------------
