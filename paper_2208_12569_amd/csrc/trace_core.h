@@ -253,6 +253,17 @@ __host__ __device__ __forceinline__ int excursion(int axis, T p, T s1, T D, T ov
     return s1s > a4 * (p + ov) ? 2 * axis : -1;
 }
 
+// Face code of a box face that a step ended past (coordinate n of cell c on an axis
+// of `nodes` nodes, face codes lo and lo + 1) while the line heads out through it
+// with direction component d steeper than gmin; -1 if none.
+template <typename T>
+__host__ __device__ __forceinline__ int box_past(T n, int c, int nodes, T d, int lo)
+{
+    if (c == 0 && n < T(0) && d < -Num<T>::gmin) return lo;
+    if (c == nodes - 2 && n > T(1) && d > Num<T>::gmin) return lo + 1;
+    return -1;
+}
+
 // One trial step. On return: fin_st >= 0 if the half line ended (status bits,
 // fin_face = exit face or -1), need_load if the cell changed. n_acc counts
 // accepted steps.
@@ -438,13 +449,24 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                                        : 5.0f;
         T n0 = L.p0 + dyv[0], n1 = L.p1 + dyv[1], n2 = L.p2 + dyv[2];
         const T ov = N::ov;
+        // Past a box face the line ends on that face, and clamping an overshoot d onto
+        // it moves the end by d over the line's slope to the face: a first-order
+        // error, not the second-order kink error of an interior face. So a step that
+        // ends past a box face the line heads out through steeply enough to land on
+        // keeps no overshoot: it lands on that face instead (`bp`, its face code). A
+        // line tangent to the box face, or turning back, keeps the allowance (a
+        // landing there would not converge). The start direction is k1 times g0.
+        int bp = -1;
+        if (axis != 0) bp = box_past(n0, L.c0, K.nx, k[0][0] * g0, 0);
+        if (bp < 0 && axis != 1) bp = box_past(n1, L.c1, K.ny, k[0][1] * g0, 2);
+        if (bp < 0 && axis != 2) bp = box_past(n2, L.c2, K.nz, k[0][2] * g0, 4);
         // a brief excursion over a face inside the step (the end may be back inside)
         int xf = -1;
         if (axis != 0) xf = excursion(0, L.p0, H * k[0][0], dyv[0], ov);
         if (xf < 0 && axis != 1) xf = excursion(1, L.p1, H * k[0][1], dyv[1], ov);
         if (xf < 0 && axis != 2) xf = excursion(2, L.p2, H * k[0][2], dyv[2], ov);
         if (axis < 0) {
-            if (xf < 0 && n0 >= -ov && n0 <= T(1) + ov && n1 >= -ov && n1 <= T(1) + ov &&
+            if (xf < 0 && bp < 0 && n0 >= -ov && n0 <= T(1) + ov && n1 >= -ov && n1 <= T(1) + ov &&
                 n2 >= -ov && n2 <= T(1) + ov) {
                 // inside, or past a face by at most ov: a step straddling a face by d
                 // errs by O(d^2), so keep it and carry the overshoot into the
@@ -481,8 +503,9 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             }
             return;
         }
-        // landing step: the other coordinates must still be within ov of the cell
-        int fb = xf;
+        // landing step: the other coordinates must still be within ov of the cell, and
+        // not past a box face the line heads out through
+        int fb = bp >= 0 ? bp : xf;
         if (axis != 0 && (n0 < -ov || n0 > T(1) + ov)) fb = n0 > T(1) ? 1 : 0;
         if (axis != 1 && (n1 < -ov || n1 > T(1) + ov)) fb = n1 > T(1) ? 3 : 2;
         if (axis != 2 && (n2 < -ov || n2 > T(1) + ov)) fb = n2 > T(1) ? 5 : 4;

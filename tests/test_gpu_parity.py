@@ -124,6 +124,34 @@ def test_closed_form_fields(fq, prec):
     assert np.allclose(to_np(r["tw"]).ravel(), tw, atol=TOL_TW)
 
 
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_end_on_box_face_just_before_a_cell_face(fq, prec):
+    """B = (1, 0, -(x - x0)): from the apex (x0, y, m^2/2) the lines are parabolas that
+    leave through the bottom face at x0 +- m with slope m (Eq. rb). With the forward
+    exit a distance eps before an x face, a step aimed at the x face ends just below
+    the box; clamping that end onto z = 0 would move it by up to eps. The ends must
+    match the closed form. Slopes of 0.08 and 0.2 keep the ends out of the FP64
+    re-trace, so the F32X form checks the FP32 pass itself."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    _say(f"box-face ends near x faces, precision {prec}")
+    for xf in (0.4375, 0.5625):
+        for eps in (1e-6, 3e-6, 6e-6, 2e-5):
+            for m in (0.08, 0.2):
+                x0 = xf - eps - m
+                B = linear_field(g, [[0, 0, 0], [0, 0, 0], [-1, 0, 0]], [1.0, 0.0, x0])
+                seeds = np.array([[x0, 0.53, m * m / 2]])
+                r = fq.trace(_dev(B), g, torch.from_numpy(seeds).cuda(), normal=(1.0, 0.0, 0.0),
+                             params=fq.Params(precision=prec))
+                torch.cuda.synchronize()
+                assert int(to_np(r["status"])[0]) == 0
+                assert int(to_np(r["face_f"])[0]) == 4 and int(to_np(r["face_b"])[0]) == 4
+                for key, xe in (("end_f", x0 + m), ("end_b", x0 - m)):
+                    e = to_np(r[key])[0]
+                    assert np.max(np.abs(e - [xe, 0.53, 0.0])) < 1e-7, (xf, eps, m, key, e)
+
+
 def test_status_paths(fq):
     """Seeds outside the box, a NaN in the field, a null region and the step budget
     are reported per line, as in the oracle."""
