@@ -323,28 +323,43 @@ def cpu_baseline(w, side: int):
             "finite_q": int(np.isfinite(r["q"]).sum()), "_map": r, "_at": (i0, j0, side)}
 
 
-def accuracy(gmap: dict, orc: dict, at, w) -> dict:
-    """Errors of a GPU map against the oracle on the oracle's block, away from the
-    block's border (where the block's own stencil is one-sided), on points where both
-    succeed, no stencil line ends near a box edge and Q < 1e8: relative error of
-    log10 Q on the scale max(|log10 Q|, log10 2), and the absolute error of Tw.
-    Also stated over the points whose seed is not on a polarity inversion line
-    (|Bn0/B| >= 1e-3): Q divides by Bn0^2, so where Bn0 vanishes a footpoint error
-    dr moves Q by about |grad Bn| dr / |Bn| and no tolerance controls it."""
+def err_stats(qg, twg, sg, qo, two, so, cond=None) -> dict:
+    """Errors of GPU values against the oracle's on the points where both succeed, no
+    stencil line ends near a box edge and Q < 1e8: relative error of log10 Q on the
+    scale max(|log10 Q|, log10 2) (max, 99.9th percentile, count over 1e-4), and the
+    absolute error of Tw. With `cond`, also the maximum over the points it selects."""
     import numpy as np
 
     import paper_2208_12569_amd as fq
 
-    i0, j0, side = at
-    sl = (slice(j0 + 1, j0 + side - 1), slice(i0 + 1, i0 + side - 1))
-    qg = gmap["q"][sl]
-    twg = gmap["tw"][sl]
-    sg = gmap["status"][sl]
-    qo = orc["q"].reshape(side, side)[1:-1, 1:-1]
-    two = orc["tw"].reshape(side, side)[1:-1, 1:-1]
-    so = orc["status"].reshape(side, side)[1:-1, 1:-1].astype(np.uint16)
+    sg = sg.astype(np.uint16)
+    so = so.astype(np.uint16)
     bad = fq.ST_FATAL | fq.ST_MIXEDFACE | fq.ST_EDGE
     m = (((sg | so) & bad) == 0) & np.isfinite(qo) & np.isfinite(qg) & (qo < 1e8)
+    lo = np.log10(np.where(m, qo, 1.0))
+    lg = np.log10(np.where(m, qg, 1.0))
+    rel = np.where(m, np.abs(lg - lo) / np.maximum(np.abs(lo), np.log10(2.0)), 0.0)
+    tw_ok = (((sg | so) & fq.ST_FATAL) == 0) & np.isfinite(two) & np.isfinite(twg)
+    out = {"points": int(m.sum()), "logq_rel_max": float(rel[m].max()),
+           "logq_rel_p999": float(np.quantile(rel[m], 0.999)),
+           "points_over_1e-4": int((rel > 1e-4).sum()),
+           "tw_abs_max": float(np.abs(twg[tw_ok] - two[tw_ok]).max())}
+    if cond is not None:
+        out["_cond_max"] = float(rel[m & cond].max())
+        out["_cond_excluded"] = int((m & ~cond).sum())
+    return out
+
+
+def accuracy(gmap: dict, orc: dict, at, w) -> dict:
+    """Errors of a GPU map against the oracle on the oracle's block, away from the
+    block's border (where the block's own stencil is one-sided). Also stated over the
+    points whose seed is not on a polarity inversion line (|Bn0/B| >= 1e-3): Q
+    divides by Bn0^2, so where Bn0 vanishes a footpoint error dr moves Q by about
+    |grad Bn| dr / |Bn| and no tolerance controls it."""
+    import numpy as np
+
+    i0, j0, side = at
+    sl = (slice(j0 + 1, j0 + side - 1), slice(i0 + 1, i0 + side - 1))
     # field angle at the seeds (z = 0 nodes: bilinear in x and y)
     pts = w.plane.points().reshape(w.plane.nv, w.plane.nu, 3)[sl]
     g = w.grid
@@ -354,18 +369,98 @@ def accuracy(gmap: dict, orc: dict, at, w) -> dict:
     B0 = [(P[jj, ii] * (1 - u) * (1 - v) + P[jj, ii + 1] * u * (1 - v) + P[jj + 1, ii] * (1 - u) * v
            + P[jj + 1, ii + 1] * u * v) for P in (w.field[0, 0], w.field[1, 0], w.field[2, 0])]
     ang = np.abs(B0[2]) / np.sqrt(B0[0] ** 2 + B0[1] ** 2 + B0[2] ** 2)
-    lo = np.log10(np.where(m, qo, 1.0))
-    lg = np.log10(np.where(m, qg, 1.0))
-    rel = np.where(m, np.abs(lg - lo) / np.maximum(np.abs(lo), np.log10(2.0)), 0.0)
-    cond = m & (ang >= 1e-3)
-    tw_ok = (((sg | so) & fq.ST_FATAL) == 0) & np.isfinite(two)
-    return {"points": int(m.sum()), "logq_rel_max": float(rel[m].max()),
-            "logq_rel_p999": float(np.quantile(rel[m], 0.999)),
-            "points_over_1e-4": int((rel > 1e-4).sum()),
-            "logq_rel_max_seed_angle_ge_1e-3": float(rel[cond].max()),
-            "seeds_on_pil_excluded": int((m & ~cond).sum()),
-            "tw_abs_max": float(np.abs(twg[tw_ok] - two[tw_ok]).max()),
-            "against": "the oracle (FP64, tol 1e-10) on the CPU-baseline block"}
+    r = err_stats(gmap["q"][sl], gmap["tw"][sl], gmap["status"][sl],
+                  orc["q"].reshape(side, side)[1:-1, 1:-1],
+                  orc["tw"].reshape(side, side)[1:-1, 1:-1],
+                  orc["status"].reshape(side, side)[1:-1, 1:-1], cond=ang >= 1e-3)
+    r["logq_rel_max_seed_angle_ge_1e-3"] = r.pop("_cond_max")
+    r["seeds_on_pil_excluded"] = r.pop("_cond_excluded")
+    r["against"] = "the oracle (FP64, tol 1e-10) on the CPU-baseline block"
+    return r
+
+
+def run_q3d(seed: int, steps: int, warmup: int, sample: int = 3000):
+    """The 3-D map: Q, Tw and length at the 256x256x128 voxel centres of the
+    512x512x256 FP32 cube (10 seeded charges, two arched tubes of opposite
+    handedness). Voxels where |Bz/B| < 0.05 turn S0 perpendicular to B and trace 4
+    extra lines. Both forms: the first call and the mean of `steps` warm calls.
+    Keeps the values at sampled voxels (random ones and rotated ones) for the
+    oracle comparison of the CPU-baseline leg."""
+    import numpy as np
+    import torch
+
+    import paper_2208_12569_amd as fq
+    from synth.torch_fields import config_c3_torch
+
+    t = time.perf_counter()
+    w = config_c3_torch(seed)
+    torch.cuda.synchronize()
+    log(f"generated {w.name} on the GPU in {time.perf_counter() - t:.1f} s")
+    vx = w.voxels
+    n = int(np.prod(vx.n))
+    out = {"workload": "512x512x256 FP32 cube (dx=1/511), 10 seeded charges + 2 arched tubes "
+                       "(1.5 turns, opposite handedness); Q, Tw, length at 256x256x128 voxel "
+                       "centres, S0 turned perpendicular to B where |Bz/B| < 0.05",
+           "unit": UNIT, "voxels": n}
+    keep = {}
+    for name, prec in (("f32x", fq.FQ_PREC_F32X), ("f64", fq.FQ_PREC_F64)):
+        p = fq.Params(precision=prec)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        r = fq.q3d(w.field, w.grid, vx, p)
+        c1.record()
+        c1.synchronize()
+        first = c0.elapsed_time(c1)
+        ws = r["_ws"]
+        for _ in range(max(0, warmup - 1)):
+            r = fq.q3d(w.field, w.grid, vx, p, ws=ws)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            r = fq.q3d(w.field, w.grid, vx, p, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = {"value": n / (ms * 1e-3), "ms_per_map": ms, "first_call_ms": first}
+        keep[name] = {k: r[k].cpu().numpy().ravel() for k in ("q", "tw", "status")}
+        log(f"[q3d {name}] {ms:.3f} ms per map (first call {first:.3f} ms)")
+        del ws, r
+    st = keep["f32x"]["status"].astype(np.uint16)
+    rot = np.flatnonzero(st & fq.ST_ROTATED)
+    out["rotated_voxels"] = int(rot.size)
+    out["rotated_fraction"] = rot.size / n
+    out["lines_traced"] = n + 4 * int(rot.size)
+    rng = np.random.default_rng(29)
+    idx = np.unique(np.concatenate([rng.choice(n, sample, replace=False),
+                                    rng.choice(rot, min(sample // 10, rot.size), replace=False)]))
+    out["_sample"] = (w, idx, {k: {c: v[idx] for c, v in d.items()} for k, d in keep.items()})
+    return out
+
+
+def q3d_accuracy(w, idx, gvals) -> dict:
+    """The oracle at the sampled voxels (FP64, tol 1e-10 grid spacings) against both
+    forms, and the oracle's rate on that sample."""
+    import numpy as np
+
+    import oracle
+
+    Bh = w.field.cpu().numpy()
+    t = time.perf_counter()
+    o = oracle.q3d_points(Bh, w.grid, w.voxels, idx, {"tol": 1e-10})
+    dt = time.perf_counter() - t
+    import paper_2208_12569_amd as fq
+
+    nrot = int(((gvals["f32x"]["status"].astype(np.uint16) & fq.ST_ROTATED) != 0).sum())
+    res = {"sample": f"{idx.size} voxels drawn at random, plus rotated-S0 voxels drawn apart "
+                     f"({nrot} rotated in all)",
+           "oracle_values_per_s": idx.size / dt, "oracle_cores": oracle.threads()}
+    for k, g in gvals.items():
+        res[k] = err_stats(g["q"], g["tw"], g["status"], np.asarray(o["q"]).ravel(),
+                           np.asarray(o["tw"]).ravel(), np.asarray(o["status"]).ravel())
+    return res
 
 
 def main():
@@ -381,6 +476,9 @@ def main():
     ap.add_argument("--cpu-side", type=int, default=512)
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint run")
+    ap.add_argument("--no-q3d", action="store_true", help="skip the 3-D map run")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the runs of the same workload drawn with the two other seeds")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with one 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -454,10 +552,24 @@ def main():
     if other is not None:
         out["f64_form"] = {"value": npts / (other["ms"] * 1e-3), "ms_per_step": other["ms"],
                            "trace_ms": other["trace_ms"]}
+    if not args.no_seeds:
+        # the same workload drawn with the two other seeds (the value above is seed's)
+        seeds = {}
+        for sd in [x for x in (0, 1, 2) if x != args.seed][:2]:
+            ws_ = synth.config_c2(sd)
+            rr = run_gpu(ws_, args.precision, args.tol, args.steps, args.warmup)
+            seeds[str(sd)] = {"value": npts / (rr["ms"] * 1e-3), "ms_per_step": rr["ms"],
+                              "trial_steps": rr["stats"][0]}
+            del ws_, rr
+        out["config"]["other_seeds"] = seeds
     if not args.no_batch:
         out["batch"] = run_batch(args.seed, args.steps, args.warmup)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
+    q3d_sample = None
+    if not args.no_q3d:
+        out["q3d"] = run_q3d(args.seed, args.steps, args.warmup)
+        q3d_sample = out["q3d"].pop("_sample")
     if args.calib_copy:
         import torch
 
@@ -477,6 +589,9 @@ def main():
         if other is not None:
             out["accuracy"]["f64"] = accuracy(other["map"], orc_map, at, w)
         log(f"accuracy: {out['accuracy']}")
+        if q3d_sample is not None:
+            out["q3d"]["accuracy"] = q3d_accuracy(*q3d_sample)
+            log(f"q3d accuracy: {out['q3d']['accuracy']}")
     print(json.dumps(out), flush=True)
 
 

@@ -284,22 +284,32 @@ def config_c2(seed: int = 0, nseed: int = 1024) -> Workload:
                     plane=plane_z0(nseed), meta={"charges": (pos, q), "tube_q": qt})
 
 
+def c3_spec(seed: int = 0, nvox=(256, 256, 128)):
+    """The draws and geometry of C3: (grid, charge positions, strengths, tubes as
+    (centre, R0, a, B0, q, plane_normal), voxels, twist rate)."""
+    rng = np.random.default_rng(seed)
+    g = cubic_grid(512, 512, 256)
+    pos, q = draw_charges(rng, 10)
+    qt = tube_q_for_turns(0.2, -0.08, 1.5)
+    tubes = [((0.5, 0.35, -0.08), 0.2, 0.08, 1.0, qt, 1),
+             ((0.65, 0.5, -0.08), 0.2, 0.08, 1.0, -qt, 0)]
+    ux, uy, uz = g.upper
+    sp = (ux / nvox[0], uy / nvox[1], uz / nvox[2])
+    vox = Voxels((0.5 * sp[0], 0.5 * sp[1], 0.5 * sp[2]), sp, tuple(nvox))
+    return g, pos, q, tubes, vox, qt
+
+
 def config_c3(seed: int = 0, nvox=(256, 256, 128)) -> Workload:
     """512x512x256 nodes (dx = 1/511), float32: 10 seeded charges plus two arched
     tubes of opposite handedness (R0 = 0.2, centre 0.08 below z = 0, radius 0.08,
     1.5 turns; one in plane y = 0.35 along x, one in plane x = 0.65 along y);
-    3-D maps on the 256x256x128 voxel centres."""
-    rng = np.random.default_rng(seed)
-    g = cubic_grid(512, 512, 256)
-    pos, q = draw_charges(rng, 10)
+    3-D maps on the 256x256x128 voxel centres. The charge field and each tube are
+    rounded to float32 separately and summed in float32."""
+    g, pos, q, tubes, vox, qt = c3_spec(seed, nvox)
     B = np.zeros((3,) + g.shape, dtype=np.float32)
     charges_field(g, pos, q, dtype=np.float32, out=B)
-    qt = tube_q_for_turns(0.2, -0.08, 1.5)
-    B += tube_field(g, (0.5, 0.35, -0.08), 0.2, 0.08, 1.0, qt, plane_normal=1).astype(np.float32)
-    B += tube_field(g, (0.65, 0.5, -0.08), 0.2, 0.08, 1.0, -qt, plane_normal=0).astype(np.float32)
-    ux, uy, uz = g.upper
-    sp = (ux / nvox[0], uy / nvox[1], uz / nvox[2])
-    vox = Voxels((0.5 * sp[0], 0.5 * sp[1], 0.5 * sp[2]), sp, tuple(nvox))
+    for c, R0, a, B0, qq, n in tubes:
+        B += tube_field(g, c, R0, a, B0, qq, plane_normal=n).astype(np.float32)
     return Workload("c3_charges10_tubes2_512x512x256", g, B, voxels=vox,
                     meta={"charges": (pos, q), "tube_q": qt})
 

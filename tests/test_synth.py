@@ -40,3 +40,15 @@ def test_c4_draws_are_deterministic():
         assert np.array_equal(x[2], y[2]) and np.array_equal(x[3], y[3])
         assert 64 <= x[1] <= 384 and x[4] in (128, 256, 512, 1024)
         assert 4 <= len(x[3]) <= 12 and abs(x[3].sum()) < 1e-12
+
+
+def test_torch_tube_field_equals_numpy():
+    from synth.torch_fields import tube_field_torch
+
+    g = synth.cubic_grid(41, 37, 23)
+    qt = synth.fields.tube_q_for_turns(0.2, -0.08, 1.5)
+    for n, c in ((1, (0.5, 0.35, -0.08)), (0, (0.65, 0.5, -0.08))):
+        a = synth.fields.tube_field(g, c, 0.2, 0.08, 1.0, qt, plane_normal=n, chunk=5)
+        b = tube_field_torch(g, c, 0.2, 0.08, 1.0, qt, n, "cpu", chunk=6).numpy()
+        assert np.abs(a - b).max() <= 1e-14 * max(np.abs(a).max(), 1.0)
+        assert np.array_equal(a.astype(np.float32), b.astype(np.float32))
