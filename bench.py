@@ -148,7 +148,8 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
     return {"ms": total_ms / steps, "trace_ms": sum(trace_ms) / steps,
             "fix_ms": sum(fix_ms) / steps, "stats": st, "stats32": st32, "first_ms": first_ms,
             "map": {"q": r["q"].cpu().numpy(), "tw": r["tw"].cpu().numpy(),
-                    "status": r["status"].cpu().numpy().astype("uint16")}}
+                    "status": r["status"].cpu().numpy().astype("uint16")},
+            "params": fq.Params(precision=prec, tol_perp=tol)}
 
 
 def gather_roofline(nodes: int, nx: int, ny: int, nz: int, walk_steps: int = 400):
@@ -314,7 +315,7 @@ def cpu_baseline(w, side: int):
     sub = synth.Plane(tuple(o), pl.u, pl.v, side, side, pl.du, pl.dv)
     oracle.build()
     t = time.perf_counter()
-    r = oracle.q2d(w.field, w.grid, sub, {"tol": 1e-10}, want_lines=False)
+    r = oracle.q2d(w.field, w.grid, sub, {"tol": 1e-10}, want_lines=True)
     dt = time.perf_counter() - t
     n = side * side
     return {"value": n / dt, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
@@ -348,6 +349,47 @@ def err_stats(qg, twg, sg, qo, two, so, cond=None) -> dict:
         out["_cond_max"] = float(rel[m & cond].max())
         out["_cond_excluded"] = int((m & ~cond).sum())
     return out
+
+
+def block_ends(w, params, at):
+    """End points of both halves of every line of the oracle's block, from one more
+    call of the timed form (the timed runs keep no lines)."""
+    import numpy as np
+    import torch
+
+    import paper_2208_12569_amd as fq
+
+    i0, j0, side = at
+    B = torch.from_numpy(w.field).cuda()
+    r = fq.q2d(B, w.grid, w.plane, params, want_lines=True)
+    torch.cuda.synchronize()
+    out = {}
+    for k in ("end_b", "end_f"):
+        e = r["lines"][k].reshape(w.plane.nv, w.plane.nu, 3)[j0:j0 + side, i0:i0 + side]
+        out[k] = e.cpu().numpy().reshape(-1, 3)
+    return out
+
+
+def foot_stats(ends: dict, orc: dict, side: int) -> dict:
+    """Footpoint errors (box units, max over both ends of a line) on the block's
+    interior, against the bound 1e-6 where Q < 1e4 and 1e-6 sqrt(Q/1e4) above (the map
+    stretches a line's error by about sqrt(Q))."""
+    import numpy as np
+
+    import paper_2208_12569_amd as fq
+
+    d = np.zeros(side * side)
+    for k in ("end_b", "end_f"):
+        d = np.maximum(d, np.abs(ends[k] - orc["lines"][k]).max(axis=1))
+    qo = orc["q"].ravel()
+    st = orc["status"].ravel().astype(np.uint16)
+    keep = ((st & (fq.ST_FATAL | fq.ST_EDGE)) == 0) & np.isfinite(qo) & (qo < 1e8)
+    inner = np.zeros((side, side), bool)
+    inner[1:-1, 1:-1] = True
+    keep &= inner.ravel() & np.isfinite(d)
+    bound = 1e-6 * np.maximum(1.0, np.sqrt(qo / 1e4))
+    return {"foot_max": float(d[keep].max()), "foot_over_bound": int((d[keep] > bound[keep]).sum()),
+            "foot_max_over_bound": float((d[keep] / bound[keep]).max())}
 
 
 def accuracy(gmap: dict, orc: dict, at, w) -> dict:
@@ -586,8 +628,11 @@ def main():
         out["cpu_baseline"] = cb
         # the accuracy the throughput is stated at
         out["accuracy"] = {args.precision: accuracy(main_run["map"], orc_map, at, w)}
+        out["accuracy"][args.precision].update(
+            foot_stats(block_ends(w, main_run["params"], at), orc_map, at[2]))
         if other is not None:
             out["accuracy"]["f64"] = accuracy(other["map"], orc_map, at, w)
+            out["accuracy"]["f64"].update(foot_stats(block_ends(w, other["params"], at), orc_map, at[2]))
         log(f"accuracy: {out['accuracy']}")
         if q3d_sample is not None:
             out["q3d"]["accuracy"] = q3d_accuracy(*q3d_sample)

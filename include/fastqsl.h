@@ -103,6 +103,11 @@ typedef struct {
     void *const *events; /* host, optional: 4 hipEvent_t recorded on the call's stream right
                           before and after the tracer launch, and before and after the FP64
                           pass (for timing the tracer alone; NULL = none) */
+    double qfix;       /* FQ_PREC_F32X maps only: a line whose own map point has Q above this
+                          after the FP32 pass is traced again in FP64 too, and Q is formed
+                          again (the map amplifies a line's FP32 rounding by about sqrt(Q));
+                          default 300, negative = off. Lines of a call with no Q output, and
+                          the extra lines of rotated S0, are not selected this way */
 } fq_params;
 
 /* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,

@@ -48,6 +48,7 @@ class Params:
     block: int = 0
     waves_per_cu: int = 0
     graze: float = 0.0
+    qfix: float = 0.0
     stats: object = None  # optional CUDA int64 tensor of 5 counters (added to)
     events: object = None  # optional ctypes array of 4 hipEvent_t handles
 
@@ -64,6 +65,7 @@ class Params:
         p.block = int(self.block)
         p.waves_per_cu = int(self.waves_per_cu)
         p.graze = float(self.graze)
+        p.qfix = float(self.qfix)
         p.stats = self.stats.data_ptr() if self.stats is not None else None
         p.events = C.cast(self.events, C.c_void_p) if self.events is not None else None
         return p

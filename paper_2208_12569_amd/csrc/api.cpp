@@ -113,6 +113,8 @@ int resolve_params(const fq_params *in, fq_params &p)
     if (p.max_steps == 0) p.max_steps = 200000;
     if (!isfinite(p.graze)) return FQ_EINVAL;
     if (p.graze == 0) p.graze = 0.05;
+    if (!isfinite(p.qfix)) return FQ_EINVAL;
+    if (p.qfix == 0) p.qfix = 300.0;
     if (in == nullptr) p.want_tw = 1;
     return FQ_OK;
 }
@@ -455,14 +457,26 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                         jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
     if (ev && ev[1]) FQ_TRY(hipEventRecord(ev[1], stream));
     if (fixup) {
-        // FP64 pass over the grazing lines of the FP32 pass
+        // FP64 pass over the grazing lines of the FP32 pass, and over the lines whose
+        // map point has a large Q by the FP32 pass (formed here first)
+        const bool qsel = P.qfix > 0;
+        if (qsel)
+            for (int i = 0; i < ns; i++) {
+                if (specs[i].kind == SPEC_LIST || !maps[i].out.q) continue;
+                MapJob mq = maps[i];  // Q only: the final pass writes every output
+                memset(&mq.out, 0, sizeof mq.out);
+                mq.out.q = maps[i].out.q;
+                FQ_TRY(launch_stencil(mq, stream));
+            }
         FixEntry *list = (FixEntry *)(ws + off_list);
         uint32_t *lcount = (uint32_t *)(ws + off_lcount);
         FQ_TRY(launch_fill_u32(lcount, 1, 0u, stream));
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 2, 0u, stream));
-        for (int j = 0; j < njobs; j++)
-            FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, list, lcount, 2 * all_lines,
-                                stream));
+        for (int j = 0; j < njobs; j++) {
+            const double *qmap = (qsel && j < ns && specs[j].kind != SPEC_LIST) ? maps[j].out.q : nullptr;
+            FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, qmap, P.qfix, list, lcount,
+                                2 * all_lines, stream));
+        }
         const TraceJob *fix_jobs = jobs_dev;
         if (fix_store == FQ_DT_F64) {
             TraceJob *j64 = (TraceJob *)(ws + off_jobs64);

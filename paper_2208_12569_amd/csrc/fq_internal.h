@@ -155,6 +155,7 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
 hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *counts,
                              int32_t *order, hipStream_t s);
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
+                        const double *qmap, double qthr,
                         FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s);
 
 // Map assembly (Q stencil) of one layer-structured map.

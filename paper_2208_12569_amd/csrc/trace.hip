@@ -296,8 +296,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
 // is nearly tangent to the face they end on, turn FP32 rounding into large footpoint
 // errors (a height error d of a line meeting a plane at angle a moves its crossing
 // by d/a); those half lines, and any the FP32 pass could not finish, are listed for
-// the FP64 pass.
+// the FP64 pass. So are both halves of a line whose own map point (qmap, the Q the
+// FP32 pass gives; one point per line of a plane or voxel job) has Q above qthr: the
+// map stretches a line's rounding error by about sqrt(Q).
 __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double thr,
+                             const double *__restrict__ qmap, double qthr,
                              FixEntry *__restrict__ list, uint32_t *__restrict__ count,
                              int64_t cap)
 {
@@ -321,6 +324,8 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
             const double bn = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
             seed_graze = !(fabs(bn) >= thr * bm);
         }
+        if (qmap && (J.kind == SEED_PLANE || J.kind == SEED_VOXELS) && l < J.nlines && qmap[l] > qthr)
+            seed_graze = true;
         for (int h = 0; h < 2; h++) {
             const int64_t q = h ? hf : hb;
             if (J.rec.len[q] == 0.0) continue;  // ends at its seed: nothing to improve
@@ -488,13 +493,14 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
 }
 
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
-                        FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s)
+                        const double *qmap, double qthr, FixEntry *list, uint32_t *count,
+                        int64_t cap, hipStream_t s)
 {
     int64_t b = (max_lines + 255) / 256;
     if (b < 1) b = 1;
     if (b > 65536) b = 65536;
-    hipLaunchKernelGGL(graze_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, job, thr, list,
-                       count, cap);
+    hipLaunchKernelGGL(graze_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, job, thr, qmap,
+                       qthr, list, count, cap);
     return hipGetLastError();
 }
 

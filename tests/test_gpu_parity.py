@@ -314,6 +314,37 @@ def test_c2_full_size_sampled_parity(fq, c2, prec):
     assert np.isfinite(to_np(r["tw"])).all()
 
 
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_c2_high_q_points_parity(fq, prec):
+    """The same workload drawn with seed 1, whose map has a wide high-Q region, where
+    the map stretches each line's rounding by about sqrt(Q). Against the oracle: the
+    200 lines whose ends move most between this form and an FP64 map at a 1000x
+    tighter tolerance (the GPU map only picks the points; the oracle gives the
+    values), the 100 largest-Q points and 100 random ones, footpoints included. In
+    the F32X form, lines whose point has Q > 300 are re-traced in FP64."""
+    import torch
+
+    w = synth.config_c2(1)
+    B = _dev(w.field)
+    _say(f"c2 seed 1 high-Q points, precision {prec}")
+    r = fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec), want_lines=True)
+    ref = fq.q2d(B, w.grid, w.plane, fq.Params(precision=F64, tol_perp=1e-9), want_lines=True)
+    torch.cuda.synchronize()
+    d = np.zeros(1024 * 1024)
+    for k in ("end_b", "end_f"):
+        d = np.maximum(d, np.abs(to_np(r["lines"][k]) - to_np(ref["lines"][k])).max(axis=1))
+    d = np.where(np.isfinite(d), d, 0.0)
+    q = to_np(r["q"]).ravel()
+    qs = np.where(np.isfinite(q) & (q < 1e8), q, 0.0)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([np.argsort(-d)[:200], np.argsort(-qs)[:100],
+                                    rng.choice(q.size, 100, replace=False)]))
+    o = oracle.q2d_points(w.field, w.grid, w.plane, idx, ORC_TOL)
+    st = compare_points(r, idx, o, f"c2-seed1-highq-{prec}")
+    print(st, "largest end shift:", float(d.max()), "largest Q:", float(qs.max()))
+    assert qs.max() > 1e4
+
+
 @pytest.fixture(scope="module")
 def c3():
     return synth.config_c3(0)
