@@ -369,38 +369,66 @@ __global__ void fill_counts_kernel(uint32_t *counts)
 }
 
 // Tile order of a plane job: long lines start early, so the last ones to finish are
-// short. A tile's key is the largest |Bn0| of its seeds relative to max |B| (lines
-// rooted in strong normal field reach far; sampled at five seeds of the tile),
-// bucketed on a log scale; tiles are
-// placed bucket by bucket, largest keys first (the order inside a bucket does not
-// matter: every line's result is independent of when it is traced).
-__global__ void tile_key_kernel(TraceJob J, int32_t *__restrict__ bucket,
-                                uint32_t *__restrict__ counts)
+// short. A tile's key is the length of the longest of ten coarse half lines: its four
+// corner seeds and a central one, traced both ways with Heun steps of four grid
+// spacings (at most 256) on the FP64 trilinear field. Half lines are the queue's
+// items, so the longest half decides when a tile's work ends; the key is the step
+// count, and tiles are placed longest first (the order inside a key does not matter:
+// every line's result is independent of when it is traced).
+constexpr int kCoarseCells = 4, kCoarseSteps = 256;
+
+__global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
 {
     const int64_t ntiles = J.tiles[0] * J.tiles[1];
-    const double bmax = sqrt((double)*J.bmax2);
+    const double dmin = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
+    const double h = kCoarseCells * dmin;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = J.origin[a];
+        hi[a] = J.origin[a] + (double)(J.n[a] - 1) * J.spacing[a];
+    }
+    const int sw[5] = {0, 7, 56, 63, 36};
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 10 * ntiles;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = k / 10;
+        const int q = (int)(k - 10 * t);
+        const double sgn = (q & 1) ? -1.0 : 1.0;
+        const int64_t ty = t / J.tiles[0], tx = t - ty * J.tiles[0];
+        const int w = sw[q >> 1];
+        int64_t i = tx * 8 + (w & 7), j = ty * 8 + (w >> 3);
+        i = i < J.dims[0] ? i : J.dims[0] - 1;
+        j = j < J.dims[1] ? j : J.dims[1] - 1;
+        double p[3];
+        for (int a = 0; a < 3; a++) p[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
+        int n = 0;
+        for (; n < kCoarseSteps; n++) {
+            double B[3], pm[3], B2[3];
+            interp64(J.planes, p, B);
+            const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            if (!(bm > 0.0) || !isfinite(bm)) break;
+            for (int a = 0; a < 3; a++) pm[a] = fmin(fmax(p[a] + 0.5 * h * sgn * B[a] / bm, lo[a]), hi[a]);
+            interp64(J.planes, pm, B2);
+            const double bm2 = sqrt(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
+            if (!(bm2 > 0.0) || !isfinite(bm2)) break;
+            bool inside = true;
+            for (int a = 0; a < 3; a++) {
+                p[a] += h * sgn * B2[a] / bm2;
+                inside = inside && p[a] >= lo[a] && p[a] <= hi[a];
+            }
+            if (!inside) break;
+        }
+        atomicMax(len + t, n);
+    }
+}
+
+// Key -> bucket, longest first (bucket 0), and the bucket counts for the placement.
+__global__ void tile_key_kernel(int64_t ntiles, int32_t *__restrict__ bucket,
+                                uint32_t *__restrict__ counts)
+{
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ty = t / J.tiles[0], tx = t - ty * J.tiles[0];
-        double key = 0.0;
-        // the four corner seeds and a central one of the 8 x 8 tile
-        const int sw[5] = {0, 7, 56, 63, 36};
-        for (int q = 0; q < 5; q++) {
-            const int w = sw[q];
-            int64_t i = tx * 8 + (w & 7), j = ty * 8 + (w >> 3);
-            i = i < J.dims[0] ? i : J.dims[0] - 1;
-            j = j < J.dims[1] ? j : J.dims[1] - 1;
-            double r[3], B[3];
-            for (int a = 0; a < 3; a++) r[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
-            interp64(J.planes, r, B);
-            const double bn = fabs(B[0] * J.normal[0] + B[1] * J.normal[1] + B[2] * J.normal[2]);
-            key = bn > key ? bn : key;
-        }
-        int b = 255;
-        if (key > 0.0 && bmax > 0.0) {
-            const double lg = -16.0 * log2(key / bmax);
-            b = lg < 0.0 ? 0 : (lg > 255.0 ? 255 : (int)lg);
-        }
+        const int32_t n = bucket[t];
+        const int b = 255 - (n < 0 ? 0 : (n > 255 ? 255 : n));
         bucket[t] = b;
         atomicAdd(counts + b, 1u);
     }
@@ -438,7 +466,12 @@ hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *count
     if (b < 1) b = 1;
     if (b > 4096) b = 4096;
     hipLaunchKernelGGL(fill_counts_kernel, dim3(1), dim3(256), 0, s, counts);
-    hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, J, bucket, counts);
+    hipError_t e = launch_fill_u32((uint32_t *)bucket, ntiles, 0u, s);
+    if (e != hipSuccess) return e;
+    int64_t bl = (10 * ntiles + 255) / 256;
+    if (bl > 65536) bl = 65536;
+    hipLaunchKernelGGL(tile_len_kernel, dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+    hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(64), 0, s, counts);
     hipLaunchKernelGGL(tile_place_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts,
                        order);
