@@ -421,17 +421,23 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
     }
 }
 
-// Key -> bucket, longest first (bucket 0), and the bucket counts for the placement.
+// Key -> bucket, longest first (bucket 0), and the bucket counts for the placement
+// (a block histogram in LDS first: many tiles share a bucket). Blocks of 256.
 __global__ void tile_key_kernel(int64_t ntiles, int32_t *__restrict__ bucket,
                                 uint32_t *__restrict__ counts)
 {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int32_t n = bucket[t];
         const int b = 255 - (n < 0 ? 0 : (n > 255 ? 255 : n));
         bucket[t] = b;
-        atomicAdd(counts + b, 1u);
+        atomicAdd(hist + b, 1u);
     }
+    __syncthreads();
+    if (hist[threadIdx.x]) atomicAdd(counts + threadIdx.x, hist[threadIdx.x]);
 }
 
 __global__ void tile_scan_kernel(uint32_t *counts)
@@ -446,13 +452,25 @@ __global__ void tile_scan_kernel(uint32_t *counts)
     }
 }
 
+// Each block ranks its tiles inside their buckets in LDS and takes one range per
+// bucket from the global offsets. Blocks of 256; every thread runs the same number
+// of rounds (the barriers are uniform).
 __global__ void tile_place_kernel(int64_t ntiles, const int32_t *__restrict__ bucket,
                                   uint32_t *__restrict__ offsets, int32_t *__restrict__ order)
 {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t pos = atomicAdd(offsets + bucket[t], 1u);
-        order[pos] = (int32_t)t;
+    __shared__ uint32_t hist[256], base[256];
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < ntiles;
+         t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        const int b = t < ntiles ? bucket[t] : -1;
+        const uint32_t r = b >= 0 ? atomicAdd(hist + b, 1u) : 0u;
+        __syncthreads();
+        if (hist[threadIdx.x]) base[threadIdx.x] = atomicAdd(offsets + threadIdx.x, hist[threadIdx.x]);
+        __syncthreads();
+        if (b >= 0) order[base[b] + r] = (int32_t)t;
+        __syncthreads();
     }
 }
 
