@@ -155,36 +155,45 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
 def gather_roofline(nodes: int, nx: int, ny: int, nz: int, walk_steps: int = 400):
     """Sustained rate of the tracer's cell fetches (8 corner records of B and curl B,
     16 vector loads) along field-line-like walks with no arithmetic, on a record
-    array of the same size and layout; the best over 1-4 resident blocks per CU."""
+    array of the same size and layout; the best over 1-4 resident blocks per CU, for
+    incoherent walks (each lane its own moves) and coherent ones (the lanes of a wave
+    on an 8 x 8 patch of cells, taking the same moves). Returns (coherent, incoherent)
+    rates in useful bytes per second."""
     import torch
 
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2208_12569_amd", "libfqgather.so"))
     lib.fqgb_walk.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                              ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+                              ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p]
     rec = torch.rand((nodes, 8), dtype=torch.float32, device="cuda")
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    best = 0.0
-    rates = {}
-    for per_cu in (1, 2, 3, 4):
-        blocks = ncu * per_cu
-        sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
-        stream = torch.cuda.current_stream().cuda_stream
-        rc = lib.fqgb_walk(rec.data_ptr(), nx, ny, nz, walk_steps, blocks, 1, sink.data_ptr(), stream)
-        if rc != 0:
-            raise RuntimeError(f"gather microbenchmark launch failed: {rc}")
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        lib.fqgb_walk(rec.data_ptr(), nx, ny, nz, walk_steps, blocks, 2, sink.data_ptr(), stream)
-        b.record()
-        b.synchronize()
-        ms = a.elapsed_time(b)
-        rate = blocks * 256 * walk_steps * 192 / (ms * 1e-3)
-        rates[per_cu * 4] = rate / 1e9
-        best = max(best, rate)
-    log("gather microbenchmark (GB/s of useful gathered bytes by resident waves per CU): "
-        + ", ".join(f"{k}: {v:.0f}" for k, v in rates.items()))
-    return best
+    out = []
+    for coherent in (1, 0):
+        best = 0.0
+        rates = {}
+        for per_cu in (1, 2, 3, 4):
+            blocks = ncu * per_cu
+            sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+            stream = torch.cuda.current_stream().cuda_stream
+            rc = lib.fqgb_walk(rec.data_ptr(), nx, ny, nz, walk_steps, blocks, 1, coherent,
+                               sink.data_ptr(), stream)
+            if rc != 0:
+                raise RuntimeError(f"gather microbenchmark launch failed: {rc}")
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            lib.fqgb_walk(rec.data_ptr(), nx, ny, nz, walk_steps, blocks, 2, coherent,
+                          sink.data_ptr(), stream)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            rate = blocks * 256 * walk_steps * 192 / (ms * 1e-3)
+            rates[per_cu * 4] = rate / 1e9
+            best = max(best, rate)
+        log(f"gather microbenchmark, {'coherent' if coherent else 'incoherent'} walks (GB/s of useful "
+            "gathered bytes by resident waves per CU): " + ", ".join(f"{k}: {v:.0f}" for k, v in rates.items()))
+        out.append(best)
+    return out[0], out[1]
 
 
 def run_batch(seed: int, steps: int, warmup: int):
@@ -585,12 +594,15 @@ def main():
     # the gather roofline: algorithmic gathered bytes of the tracer (192 B of B and
     # curl B per cell fetch) per second, against the microbenchmark's sustained rate
     g = w.grid
-    micro = gather_roofline(g.nx * g.ny * g.nz, g.nx, g.ny, g.nz)
+    micro, micro_inc = gather_roofline(g.nx * g.ny * g.nz, g.nx, g.ny, g.nz)
     gathered = s32[2] * 192 / (main_run["trace_ms"] * 1e-3)
     out["gather_roofline"] = {"achieved": gathered / 1e9, "peak": micro / 1e9, "unit": "GB/s",
-                              "frac": gathered / micro,
+                              "frac": gathered / micro, "incoherent_walks": micro_inc / 1e9,
                               "note": "cell fetches x 192 B / tracer time, against the same "
-                                      "fetches along field-line-like walks with no arithmetic"}
+                                      "fetches along field-line-like walks with no arithmetic "
+                                      "whose 64 lanes per wave move together (neighbouring "
+                                      "lines); walks whose lanes move apart reach "
+                                      "incoherent_walks"}
     if other is not None:
         out["f64_form"] = {"value": npts / (other["ms"] * 1e-3), "ms_per_step": other["ms"],
                            "trace_ms": other["trace_ms"]}

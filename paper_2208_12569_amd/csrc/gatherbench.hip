@@ -6,8 +6,11 @@
 // values just loaded (one fetch in flight per lane, as in the tracer, where the next
 // cell follows from the field), and the walks look like field lines: a persistent
 // direction biased upwards, the lanes of a wave starting on neighbouring cells of the
-// bottom face. The rate of fetches x 192 useful bytes (24 values of B and curl B at 8
-// corners) is the gather roofline the tracer is measured against.
+// bottom face. Two kinds of walk: incoherent (each lane draws its own moves, from a
+// 2 x 2 patch of start cells) and coherent (the 64 lanes of a wave start on an 8 x 8
+// patch and take the same moves, as neighbouring field lines do before they part).
+// The rate of fetches x 192 useful bytes (24 values of B and curl B at 8 corners) is
+// the gather roofline the tracer is measured against.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,18 +28,20 @@ __device__ __forceinline__ uint32_t mix(uint32_t x)
 
 __global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restrict__ rec, int nx,
                                                           int ny, int nz, int steps, uint32_t seed,
-                                                          float *__restrict__ sink)
+                                                          int coherent, float *__restrict__ sink)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t wave = g >> 6;
-    // a wave starts on a 2 x 2 patch of bottom cells; patches tile the bottom face
-    const int px = (nx - 1) / 2, py = (ny - 1) / 2;
+    // a wave starts on a 2 x 2 (incoherent) or 8 x 8 (coherent) patch of bottom cells;
+    // patches tile the bottom face
+    const int side = coherent ? 8 : 2;
+    const int px = (nx - 1) / side, py = (ny - 1) / side;
     const int64_t patch = (wave * 7919) % ((int64_t)px * py);
-    int cx = (int)(patch % px) * 2 + (lane & 1);
-    int cy = (int)(patch / px) * 2 + ((lane >> 1) & 1);
+    int cx = (int)(patch % px) * side + (coherent ? (lane & 7) : (lane & 1));
+    int cy = (int)(patch / px) * side + (coherent ? (lane >> 3) : ((lane >> 1) & 1));
     int cz = 0;
-    uint32_t r = mix((uint32_t)g ^ seed);
+    uint32_t r = mix((uint32_t)(coherent ? wave : g) ^ seed);
     // persistent direction: weights for x, y and an upward-biased z (in 1/256)
     int wx = (int)(r & 127), wy = (int)((r >> 7) & 127), wz = 64 + (int)((r >> 14) & 127);
     int sxn = (r >> 21) & 1 ? 1 : -1, syn = (r >> 22) & 1 ? 1 : -1, szn = 1;
@@ -53,8 +58,9 @@ __global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restri
             v += a.x + a.y + a.z + a.w + c.x + c.y;
         }
         acc += v;
-        // next cell: an axis drawn with the lane's weights, perturbed by the data
-        r = mix(r ^ __float_as_uint(v));
+        // next cell: an axis drawn with the lane's weights, perturbed by the data (the
+        // first lane's, in a coherent walk)
+        r = mix(r ^ __float_as_uint(coherent ? __shfl(v, 0) : v));
         const int pick = (int)(r % (uint32_t)(wx + wy + wz));
         if (pick < wx) {
             cx += sxn;
@@ -77,14 +83,15 @@ __global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restri
 
 extern "C" {
 
-// records: nx*ny*nz nodes x 8 floats (device); lanes = blocks * 256; steps per lane.
-// Asynchronous on `stream`; returns a hipError_t code.
+// records: nx*ny*nz nodes x 8 floats (device); lanes = blocks * 256; steps per lane;
+// coherent: nonzero for the coherent walk. Asynchronous on `stream`; returns a
+// hipError_t code.
 int fqgb_walk(const void *records, int nx, int ny, int nz, int steps, int blocks, uint32_t seed,
-              float *sink, void *stream)
+              int coherent, float *sink, void *stream)
 {
-    if (!records || !sink || nx < 3 || ny < 3 || nz < 3 || steps < 1 || blocks < 1) return 1;
+    if (!records || !sink || nx < 17 || ny < 17 || nz < 3 || steps < 1 || blocks < 1) return 1;
     hipLaunchKernelGGL(gather_walk_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                       (const float4 *)records, nx, ny, nz, steps, seed, sink);
+                       (const float4 *)records, nx, ny, nz, steps, seed, coherent, sink);
     return (int)hipGetLastError();
 }
 
