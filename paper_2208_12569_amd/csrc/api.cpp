@@ -9,6 +9,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "fq_internal.h"
@@ -399,12 +400,26 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         }
         J.nitems = tv;
         set_job_constants(J);
-        J.item_base = items;
-        items += 2 * tv;
         if (s.kind == SPEC_PLANE) {
             J.tile_order = (const int32_t *)(ws + w.tile_order);
             FQ_TRY(launch_tile_order(J, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
                                      (int32_t *)(ws + w.tile_order), stream));
+        }
+    }
+    // queue ranges of the main jobs, largest cube first: its lines reach farthest, so
+    // they start early (inside a job, plane tiles follow their own length order)
+    {
+        std::vector<int> perm(ns);
+        for (int i = 0; i < ns; i++) perm[i] = i;
+        auto edge = [&](int i) {
+            const int64_t *n = specs[i].f->n;
+            return n[0] > n[1] ? (n[0] > n[2] ? n[0] : n[2]) : (n[1] > n[2] ? n[1] : n[2]);
+        };
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return edge(x) > edge(y); });
+        for (int k = 0; k < ns; k++) {
+            TraceJob &J = jobs[perm[k]];
+            J.item_base = items;
+            items += 2 * J.nitems;
         }
     }
     TraceParams tp;

@@ -141,8 +141,12 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
                         line = e.line;
                         forward = e.half != 0;
                     } else {
+                        // the job whose range of items holds it (the ranges need not
+                        // follow the job table's order; a dynamic last job takes the rest)
                         if (!UNI)
-                            while (j + 1 < tp.njobs && it >= jobs[j + 1].item_base) j++;
+                            while (j + 1 < tp.njobs &&
+                                   !(it >= jobs[j].item_base && it < jobs[j].item_base + 2 * jobs[j].nitems))
+                                j++;
                         const TraceJob &J = jobs[j];
                         const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
                         const int64_t local = it - J.item_base;
