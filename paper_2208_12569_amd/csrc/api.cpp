@@ -402,7 +402,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         set_job_constants(J);
         if (s.kind == SPEC_PLANE) {
             J.tile_order = (const int32_t *)(ws + w.tile_order);
-            FQ_TRY(launch_tile_order(J, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
+            FQ_TRY(launch_tile_order(J, P.precision, P.want_tw, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
                                      (int32_t *)(ws + w.tile_order), stream));
         }
     }

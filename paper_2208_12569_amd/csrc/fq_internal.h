@@ -150,9 +150,10 @@ hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
                         const TraceParams &tp, unsigned long long *counter, int block,
                         int waves_per_cu, hipStream_t s);
-// Order the tiles of a plane job (J: its host copy, bmax2 and planes valid on the
-// device): bucket (tiles), counts (256), order (tiles) are workspace arrays.
-hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *counts,
+// Order the tiles of a plane job (J: its host copy; its node records, written by
+// the prep pass for precision prec and want_tw, valid on the device): bucket (tiles),
+// counts (256), order (tiles) are workspace arrays.
+hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *bucket, uint32_t *counts,
                              int32_t *order, hipStream_t s);
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr,

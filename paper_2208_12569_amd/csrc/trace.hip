@@ -375,53 +375,89 @@ __global__ void fill_counts_kernel(uint32_t *counts)
 // Tile order of a plane job: long lines start early, so the last ones to finish are
 // short. A tile's key is the length of the longest of ten coarse half lines: its four
 // corner seeds and a central one, traced both ways with Heun steps of four grid
-// spacings (at most 256) on the FP64 trilinear field. Half lines are the queue's
-// items, so the longest half decides when a tile's work ends; the key is the step
-// count, and tiles are placed longest first (the order inside a key does not matter:
-// every line's result is independent of when it is traced).
+// spacings (at most 256), in FP32 on the tracer's own node records (B in the first
+// four values of a record of type R; 8-wide records when WIDE). Half lines are the
+// queue's items, so the longest half decides when a tile's work ends; the key is the
+// step count, and tiles are placed longest first (the order inside a key does not
+// matter: every line's result is independent of when it is traced).
 constexpr int kCoarseCells = 4, kCoarseSteps = 256;
 
+// B at grid coordinates g (clamped into the grid) from the node records.
+template <typename R, bool WIDE>
+__device__ __forceinline__ void coarse_field(const typename V4<R>::t *__restrict__ A, const int n[3],
+                                             const float g[3], float B[3])
+{
+    int c[3];
+    float t[3];
+    for (int a = 0; a < 3; a++) {
+        const float x = fminf(fmaxf(g[a], 0.0f), (float)(n[a] - 1));
+        int ci = (int)floorf(x);
+        ci = ci > n[a] - 2 ? n[a] - 2 : ci;
+        c[a] = ci;
+        t[a] = x - (float)ci;
+    }
+    const int64_t sy = n[0], sz = (int64_t)n[0] * n[1];
+    const int64_t base = (int64_t)c[2] * sz + (int64_t)c[1] * sy + c[0];
+    B[0] = B[1] = B[2] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+        const float w = (ix ? t[0] : 1.0f - t[0]) * (iy ? t[1] : 1.0f - t[1]) * (iz ? t[2] : 1.0f - t[2]);
+        const int64_t o = base + ix + iy * sy + iz * sz;
+        const typename V4<R>::t v = A[WIDE ? 2 * o : o];
+        B[0] = fmaf(w, (float)v.x, B[0]);
+        B[1] = fmaf(w, (float)v.y, B[1]);
+        B[2] = fmaf(w, (float)v.z, B[2]);
+    }
+}
+
+template <typename R, bool WIDE>
 __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
 {
+    const typename V4<R>::t *A = gptr((const typename V4<R>::t *)J.nodes);
     const int64_t ntiles = J.tiles[0] * J.tiles[1];
     const double dmin = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
-    const double h = kCoarseCells * dmin;
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; a++) {
-        lo[a] = J.origin[a];
-        hi[a] = J.origin[a] + (double)(J.n[a] - 1) * J.spacing[a];
-    }
+    const int n[3] = {J.n[0], J.n[1], J.n[2]};
+    float hs[3];  // a coarse step along a unit direction, in grid units per axis
+    for (int a = 0; a < 3; a++) hs[a] = (float)(kCoarseCells * dmin / J.spacing[a]);
     const int sw[5] = {0, 7, 56, 63, 36};
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 10 * ntiles;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = k / 10;
         const int q = (int)(k - 10 * t);
-        const double sgn = (q & 1) ? -1.0 : 1.0;
+        const float sgn = (q & 1) ? -1.0f : 1.0f;
         const int64_t ty = t / J.tiles[0], tx = t - ty * J.tiles[0];
         const int w = sw[q >> 1];
         int64_t i = tx * 8 + (w & 7), j = ty * 8 + (w >> 3);
         i = i < J.dims[0] ? i : J.dims[0] - 1;
         j = j < J.dims[1] ? j : J.dims[1] - 1;
-        double p[3];
-        for (int a = 0; a < 3; a++) p[a] = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
-        int n = 0;
-        for (; n < kCoarseSteps; n++) {
-            double B[3], pm[3], B2[3];
-            interp64(J.planes, p, B);
-            const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-            if (!(bm > 0.0) || !isfinite(bm)) break;
-            for (int a = 0; a < 3; a++) pm[a] = fmin(fmax(p[a] + 0.5 * h * sgn * B[a] / bm, lo[a]), hi[a]);
-            interp64(J.planes, pm, B2);
-            const double bm2 = sqrt(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
-            if (!(bm2 > 0.0) || !isfinite(bm2)) break;
-            bool inside = true;
-            for (int a = 0; a < 3; a++) {
-                p[a] += h * sgn * B2[a] / bm2;
-                inside = inside && p[a] >= lo[a] && p[a] <= hi[a];
-            }
-            if (!inside) break;
+        float g[3];
+        bool inside = true;
+        for (int a = 0; a < 3; a++) {
+            const double r = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
+            g[a] = (float)((r - J.origin[a]) * J.inv_spacing[a]);
+            inside = inside && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
         }
-        atomicMax(len + t, n);
+        int m = 0;
+        if (inside) {
+            for (; m < kCoarseSteps; m++) {
+                float B[3], gm[3], B2[3];
+                coarse_field<R, WIDE>(A, n, g, B);
+                const float bm = sqrtf(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                if (!(bm > 0.0f) || !isfinite(bm)) break;
+                for (int a = 0; a < 3; a++) gm[a] = g[a] + 0.5f * sgn * hs[a] * B[a] / bm;
+                coarse_field<R, WIDE>(A, n, gm, B2);
+                const float bm2 = sqrtf(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
+                if (!(bm2 > 0.0f) || !isfinite(bm2)) break;
+                bool in = true;
+                for (int a = 0; a < 3; a++) {
+                    g[a] += sgn * hs[a] * B2[a] / bm2;
+                    in = in && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
+                }
+                if (!in) break;
+            }
+        }
+        atomicMax(len + t, m);
     }
 }
 
@@ -480,8 +516,8 @@ __global__ void tile_place_kernel(int64_t ntiles, const int32_t *__restrict__ bu
 
 }  // namespace
 
-hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *counts,
-                             int32_t *order, hipStream_t s)
+hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *bucket,
+                             uint32_t *counts, int32_t *order, hipStream_t s)
 {
     const int64_t ntiles = J.tiles[0] * J.tiles[1];
     int64_t b = (ntiles + 255) / 256;
@@ -492,7 +528,14 @@ hipError_t launch_tile_order(const TraceJob &J, int32_t *bucket, uint32_t *count
     if (e != hipSuccess) return e;
     int64_t bl = (10 * ntiles + 255) / 256;
     if (bl > 65536) bl = 65536;
-    hipLaunchKernelGGL(tile_len_kernel, dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+    // the node records the prep pass wrote: FP64 values for the all-FP64 form
+    if (prec == FQ_PREC_F64) {
+        if (want_tw) hipLaunchKernelGGL((tile_len_kernel<double, true>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+        else hipLaunchKernelGGL((tile_len_kernel<double, false>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+    } else {
+        if (want_tw) hipLaunchKernelGGL((tile_len_kernel<float, true>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+        else hipLaunchKernelGGL((tile_len_kernel<float, false>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
+    }
     hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(64), 0, s, counts);
     hipLaunchKernelGGL(tile_place_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts,
