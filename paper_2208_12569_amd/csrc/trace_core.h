@@ -54,18 +54,16 @@ template <> struct Num<double> {
     {
         return __builtin_fma(a, b, c);
     }
-    // 1/sqrt(x) and 1/x: the hardware estimates refined by Newton-Raphson iterations
-    // (two each, to within a few ulp of FP64) instead of the IEEE division and square
-    // root sequences. Arguments are positive normal |B|^2 values and direction
-    // components bounded away from zero by the callers.
+    // 1/sqrt(x) and 1/x: the hardware estimates (relative error about 5e-8) refined
+    // by one Newton-Raphson iteration each (to about 5e-15 relative, measured on
+    // gfx950) instead of the IEEE division and square root sequences. Arguments are
+    // positive normal |B|^2 values and direction components bounded away from zero
+    // by the callers.
     static __host__ __device__ __forceinline__ double rsq(double x)
     {
 #if defined(__HIP_DEVICE_COMPILE__)
-        double y = __builtin_amdgcn_rsq(x);
-        const double hx = 0.5 * x;
-        y = y * __builtin_fma(-hx * y, y, 1.5);
-        y = y * __builtin_fma(-hx * y, y, 1.5);
-        return y;
+        const double y = __builtin_amdgcn_rsq(x);
+        return y * __builtin_fma(-0.5 * x * y, y, 1.5);
 #else
         return 1.0 / sqrt(x);
 #endif
@@ -73,10 +71,8 @@ template <> struct Num<double> {
     static __host__ __device__ __forceinline__ double rcp(double x)
     {
 #if defined(__HIP_DEVICE_COMPILE__)
-        double y = __builtin_amdgcn_rcp(x);
-        y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
-        y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
-        return y;
+        const double y = __builtin_amdgcn_rcp(x);
+        return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
 #else
         return 1.0 / x;
 #endif
