@@ -87,9 +87,12 @@ __device__ void grad_comp(const MapJob &m, const Tri &t, int comp, double g[3])
 // adjoint of the two in-face coordinates of an end (face f) -> end point adjoint
 __device__ __forceinline__ void inface_adj(int face, const double ub[2], double eb[3])
 {
+    // by selects: an index computed at run time would put eb in scratch memory
     const int a = face >> 1;
-    eb[a == 0 ? 1 : 0] += ub[0];
-    eb[a == 2 ? 1 : 2] += ub[1];
+    if (a == 0) eb[1] += ub[0];
+    else eb[0] += ub[0];
+    if (a == 2) eb[1] += ub[1];
+    else eb[2] += ub[1];
 }
 
 __device__ __forceinline__ void add3(double *dst, const double v[3])
@@ -105,7 +108,7 @@ struct LineAdj {
 
 // Adjoint of the derivatives along one S0 axis (d1 of (u1,v1), d2 of (u2,v2)) onto
 // the in-face coordinates of the lines the difference used.
-__device__ void axis_adj(int rule, const Line &c, const Line *m, const Line *p, double d,
+__device__ __forceinline__ void axis_adj(int rule, const Line &c, const Nb &m, const Nb &p, double d,
                          const double d1b[2], const double d2b[2], LineAdj &cb, LineAdj &mb,
                          LineAdj &pb)
 {
@@ -117,14 +120,14 @@ __device__ void axis_adj(int rule, const Line &c, const Line *m, const Line *p, 
     if (s_p != 0.0) {
         u1[0] = s_p * d1b[0], u1[1] = s_p * d1b[1];
         u2[0] = s_p * d2b[0], u2[1] = s_p * d2b[1];
-        inface_adj(p->f1, u1, pb.e1);
-        inface_adj(p->f2, u2, pb.e2);
+        inface_adj(p.f1, u1, pb.e1);
+        inface_adj(p.f2, u2, pb.e2);
     }
     if (s_m != 0.0) {
         u1[0] = s_m * d1b[0], u1[1] = s_m * d1b[1];
         u2[0] = s_m * d2b[0], u2[1] = s_m * d2b[1];
-        inface_adj(m->f1, u1, mb.e1);
-        inface_adj(m->f2, u2, mb.e2);
+        inface_adj(m.f1, u1, mb.e1);
+        inface_adj(m.f2, u2, mb.e2);
     }
     if (s_c != 0.0) {
         u1[0] = s_c * d1b[0], u1[1] = s_c * d1b[1];
@@ -135,11 +138,11 @@ __device__ void axis_adj(int rule, const Line &c, const Line *m, const Line *p, 
 }
 
 // S1 / S2 end adjoints of line l -> the half records
-__device__ void push_line(const MapJob &m, int64_t l, const Line &L, const LineAdj &a,
-                          double *lam_end)
+__device__ __forceinline__ void push_line(const MapJob &m, int64_t l, bool swapped, const LineAdj &a,
+                                          double *lam_end)
 {
     const int64_t hb = l, hf = m.nlines + l;
-    const int64_t s1 = L.swapped ? hf : hb, s2 = L.swapped ? hb : hf;
+    const int64_t s1 = swapped ? hf : hb, s2 = swapped ? hb : hf;
     add3(lam_end + 3 * s1, a.e1);
     add3(lam_end + 3 * s2, a.e2);
 }
@@ -157,7 +160,7 @@ __device__ void bn_adj(const MapJob &m, const double r[3], int comp, double gbn,
     for (int q = 0; q < 8; q++) atomicAdd(gnode + comp * nn + t.node[q], gbn * t.w[q]);
 }
 
-__global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
+__global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const double *__restrict__ dq,
                                     const double *__restrict__ dtw,
                                     const double *__restrict__ dend_b,
                                     const double *__restrict__ dend_f, double *lam_end,
@@ -188,20 +191,21 @@ __global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
         if (!dq) continue;
         const double gq = dq[pt];
         if (!(gq != 0.0) || !isfinite(gq)) continue;
-        Line xm, xp, ym, yp;
         const bool hxm = i > 0, hxp = i < m.nu - 1, hym = j > 0, hyp = j < m.nv - 1;
-        if (hxm) read_line(m.rec, m.nlines, pt - 1, xm);
-        if (hxp) read_line(m.rec, m.nlines, pt + 1, xp);
-        if (hym) read_line(m.rec, m.nlines, pt - m.nu, ym);
-        if (hyp) read_line(m.rec, m.nlines, pt + m.nu, yp);
-        const Line *pxm = hxm ? &xm : nullptr, *pxp = hxp ? &xp : nullptr;
-        const Line *pym = hym ? &ym : nullptr, *pyp = hyp ? &yp : nullptr;
-        const int rx = axis_rule(c, pxm, pxp), ry = axis_rule(c, pym, pyp);
+        // a missing neighbour reads the centre's own record (never used)
+        const Nb xm = read_nb(m, m.rec, m.nlines, hxm ? pt - 1 : pt);
+        const Nb xp = read_nb(m, m.rec, m.nlines, hxp ? pt + 1 : pt);
+        const Nb ym = read_nb(m, m.rec, m.nlines, hym ? pt - m.nu : pt);
+        const Nb yp = read_nb(m, m.rec, m.nlines, hyp ? pt + m.nu : pt);
+        const int rx = axis_rule(c, xm, hxm, xp, hxp), ry = axis_rule(c, ym, hym, yp, hyp);
         if (rx == RULE_NONE || ry == RULE_NONE) continue;  // Q = NaN there
         uint16_t st = 0;
+        double c1[2], c2[2];
+        inface(c.f1, c.e1, c1);
+        inface(c.f2, c.e2, c2);
         double ax1[2], ax2[2], ay1[2], ay2[2];
-        axis_diff(c, pxm, pxp, m.d0, ax1, ax2, st);
-        axis_diff(c, pym, pyp, m.d1, ay1, ay2, st);
+        axis_diff(rx, c1, c2, xm, xp, m.d0, ax1, ax2, st);
+        axis_diff(ry, c1, c2, ym, yp, m.d1, ay1, ay2, st);
         const double j00 = ax1[0], j01 = ay1[0], j10 = ax1[1], j11 = ay1[1];
         const double k00 = ax2[0], k01 = ay2[0], k10 = ax2[1], k11 = ay2[1];
         const double m00 = k00 * j11 - k01 * j10;
@@ -215,7 +219,7 @@ __global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
         field64(m, c.e2, B2);
         const double bn0 = B0[0] * m.normal[0] + B0[1] * m.normal[1] + B0[2] * m.normal[2];
         const int a1 = c.f1 >> 1, a2 = c.f2 >> 1;
-        const double bn1 = B1[a1], bn2 = B2[a2];
+        const double bn1 = comp3(B1, a1), bn2 = comp3(B2, a2);
         const double nrm = m00 * m00 + m01 * m01 + m10 * m10 + m11 * m11;
         const double A = fabs(bn1 * bn2) / (bn0 * bn0);
         const double Q = nrm * A;
@@ -230,11 +234,11 @@ __global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
         LineAdj ca = {}, xma = {}, xpa = {}, yma = {}, ypa = {};
         {
             const double d1b[2] = {jb00, jb10}, d2b[2] = {kb00, kb10};
-            axis_adj(rx, c, pxm, pxp, m.d0, d1b, d2b, ca, xma, xpa);
+            axis_adj(rx, c, xm, xp, m.d0, d1b, d2b, ca, xma, xpa);
         }
         {
             const double d1b[2] = {jb01, jb11}, d2b[2] = {kb01, kb11};
-            axis_adj(ry, c, pym, pyp, m.d1, d1b, d2b, ca, yma, ypa);
+            axis_adj(ry, c, ym, yp, m.d1, d1b, d2b, ca, yma, ypa);
         }
         // the normal fields: Q ~ |Bn1 Bn2| / Bn0^2
         bn_adj(m, c.e1, a1, gq * Q / bn1, ca.e1, gnode, nn);
@@ -242,11 +246,11 @@ __global__ void map_backward_kernel(MapJob m, const double *__restrict__ dq,
         const double gb0 = -2.0 * gq * Q / bn0;
         for (int comp = 0; comp < 3; comp++)
             if (m.normal[comp] != 0.0) bn_adj(m, r0, comp, gb0 * m.normal[comp], nullptr, gnode, nn);
-        push_line(m, pt, c, ca, lam_end);
-        if (rx != RULE_PLUS) push_line(m, pt - 1, xm, xma, lam_end);
-        if (rx != RULE_MINUS) push_line(m, pt + 1, xp, xpa, lam_end);
-        if (ry != RULE_PLUS) push_line(m, pt - m.nu, ym, yma, lam_end);
-        if (ry != RULE_MINUS) push_line(m, pt + m.nu, yp, ypa, lam_end);
+        push_line(m, pt, c.swapped, ca, lam_end);
+        if (rx != RULE_PLUS) push_line(m, pt - 1, xm.swapped, xma, lam_end);
+        if (rx != RULE_MINUS) push_line(m, pt + 1, xp.swapped, xpa, lam_end);
+        if (ry != RULE_PLUS) push_line(m, pt - m.nu, ym.swapped, yma, lam_end);
+        if (ry != RULE_MINUS) push_line(m, pt + m.nu, yp.swapped, ypa, lam_end);
     }
 }
 

@@ -27,16 +27,24 @@ namespace {
 
 using namespace sten;
 
-// Q from the centre line and its four S0 neighbours (any may be null).
-__device__ double q_of(const MapJob &m, const Line &c, const Line *xm, const Line *xp,
-                       const Line *ym, const Line *yp, double d0, double d1, double bn0,
-                       uint16_t &st)
+// Q from the centre line and its four S0 neighbours (present flags hxm..hyp).
+__device__ __forceinline__ double q_nb(const MapJob &m, const Line &c, const Nb &xm, bool hxm,
+                                       const Nb &xp, bool hxp, const Nb &ym, bool hym, const Nb &yp,
+                                       bool hyp, double d0, double d1, double bn0, uint16_t &st)
 {
+    double c1[2], c2[2];
+    inface(c.f1, c.e1, c1);
+    inface(c.f2, c.e2, c2);
+    // axis by axis, so that a one-sided x difference is flagged also where y fails
     double ax1[2], ax2[2], ay1[2], ay2[2];
-    if (!axis_diff(c, xm, xp, d0, ax1, ax2, st) || !axis_diff(c, ym, yp, d1, ay1, ay2, st)) {
+    const int rx = axis_rule(c, xm, hxm, xp, hxp);
+    if (rx != RULE_NONE) axis_diff(rx, c1, c2, xm, xp, d0, ax1, ax2, st);
+    const int ry = rx == RULE_NONE ? RULE_NONE : axis_rule(c, ym, hym, yp, hyp);
+    if (ry == RULE_NONE) {
         st |= FQ_ST_MIXEDFACE;
         return NAN;
     }
+    axis_diff(ry, c1, c2, ym, yp, d1, ay1, ay2, st);
     // J1 = [[du1/dx0, du1/dy0], [dv1/dx0, dv1/dy0]], likewise J2
     const double j00 = ax1[0], j01 = ay1[0], j10 = ax1[1], j11 = ay1[1];
     const double k00 = ax2[0], k01 = ay2[0], k10 = ax2[1], k11 = ay2[1];
@@ -48,12 +56,12 @@ __device__ double q_of(const MapJob &m, const Line &c, const Line *xm, const Lin
     double B1[3], B2[3];
     field64(m, c.e1, B1);
     field64(m, c.e2, B2);
-    const double bn1 = B1[c.f1 >> 1], bn2 = B2[c.f2 >> 1];
+    const double bn1 = comp3(B1, c.f1 >> 1), bn2 = comp3(B2, c.f2 >> 1);
     const double nrm = m00 * m00 + m01 * m01 + m10 * m10 + m11 * m11;
     return nrm * fabs(bn1 * bn2) / (bn0 * bn0);
 }
 
-__device__ bool on_box_face(const MapJob &m, const double r[3])
+__device__ __forceinline__ bool on_box_face(const MapJob &m, const double r[3])
 {
     for (int a = 0; a < 3; a++) {
         const double tol = 1e-12 * m.spacing[a];
@@ -116,7 +124,7 @@ __global__ void classify_kernel(MapJob m, int32_t *rot_index, RotEntry *rot,
     }
 }
 
-__device__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const double seed[3])
+__device__ __forceinline__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const double seed[3])
 {
     const int64_t hb = l, hf = m.nlines + l;
     uint16_t st = m.rec.st[hb] | m.rec.st[hf];
@@ -139,13 +147,13 @@ __device__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const 
         if (o.bn_b) {
             if (fb >= 0) {
                 field64(m, eb, B);
-                o.bn_b[l] = B[fb >> 1];
+                o.bn_b[l] = comp3(B, fb >> 1);
             } else o.bn_b[l] = NAN;
         }
         if (o.bn_f) {
             if (ff >= 0) {
                 field64(m, ef, B);
-                o.bn_f[l] = B[ff >> 1];
+                o.bn_f[l] = comp3(B, ff >> 1);
             } else o.bn_f[l] = NAN;
         }
         if (o.bn0) {
@@ -161,7 +169,7 @@ __device__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const 
     if (o.status) o.status[l] = st;
 }
 
-__global__ void stencil_kernel(MapJob m)
+__global__ __launch_bounds__(256) void stencil_kernel(MapJob m)
 {
     const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
     for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
@@ -179,36 +187,32 @@ __global__ void stencil_kernel(MapJob m)
             len = c.len;
             const int32_t ri = m.rot_index ? m.rot_index[pt] : -1;
             if (ri >= 0) {
-                Line nb[4];
-                for (int w = 0; w < 4; w++) {
-                    read_line(m.rot_rec, m.rot_nlines, 4 * (int64_t)ri + w, nb[w]);
-                    if (edge_end(m, nb[w].f1, nb[w].e1) || edge_end(m, nb[w].f2, nb[w].e2))
-                        st |= FQ_ST_EDGE;
-                }
+                const int64_t r4 = 4 * (int64_t)ri;
+                const Nb n0 = read_nb(m, m.rot_rec, m.rot_nlines, r4 + 0);
+                const Nb n1 = read_nb(m, m.rot_rec, m.rot_nlines, r4 + 1);
+                const Nb n2 = read_nb(m, m.rot_rec, m.rot_nlines, r4 + 2);
+                const Nb n3 = read_nb(m, m.rot_rec, m.rot_nlines, r4 + 3);
+                if (n0.edge || n1.edge || n2.edge || n3.edge) st |= FQ_ST_EDGE;
                 double B[3];
                 field64(m, r0, B);
                 const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
                 st |= FQ_ST_ROTATED;
-                q = q_of(m, c, &nb[0], &nb[1], &nb[2], &nb[3], m.rot_delta, m.rot_delta, bm, st);
+                q = q_nb(m, c, n0, true, n1, true, n2, true, n3, true, m.rot_delta, m.rot_delta, bm, st);
             } else if (ri == -2) {
                 st |= FQ_ST_ROTATED | FQ_ST_MIXEDFACE;
             } else {
-                Line xm, xp, ym, yp;
                 const bool hxm = i > 0, hxp = i < m.nu - 1, hym = j > 0, hyp = j < m.nv - 1;
-                if (hxm) read_line(m.rec, m.nlines, pt - 1, xm);
-                if (hxp) read_line(m.rec, m.nlines, pt + 1, xp);
-                if (hym) read_line(m.rec, m.nlines, pt - m.nu, ym);
-                if (hyp) read_line(m.rec, m.nlines, pt + m.nu, yp);
-                const Line *nbs[4] = {hxm ? &xm : nullptr, hxp ? &xp : nullptr,
-                                      hym ? &ym : nullptr, hyp ? &yp : nullptr};
-                for (int w = 0; w < 4; w++)
-                    if (nbs[w] && (edge_end(m, nbs[w]->f1, nbs[w]->e1) ||
-                                   edge_end(m, nbs[w]->f2, nbs[w]->e2)))
-                        st |= FQ_ST_EDGE;
+                // a missing neighbour reads the centre's own record (never used)
+                const Nb xm = read_nb(m, m.rec, m.nlines, hxm ? pt - 1 : pt);
+                const Nb xp = read_nb(m, m.rec, m.nlines, hxp ? pt + 1 : pt);
+                const Nb ym = read_nb(m, m.rec, m.nlines, hym ? pt - m.nu : pt);
+                const Nb yp = read_nb(m, m.rec, m.nlines, hyp ? pt + m.nu : pt);
+                if ((hxm && xm.edge) || (hxp && xp.edge) || (hym && ym.edge) || (hyp && yp.edge))
+                    st |= FQ_ST_EDGE;
                 double B[3];
                 field64(m, r0, B);
                 const double bn0 = B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
-                q = q_of(m, c, nbs[0], nbs[1], nbs[2], nbs[3], m.d0, m.d1, bn0, st);
+                q = q_nb(m, c, xm, hxm, xp, hxp, ym, hym, yp, hyp, m.d0, m.d1, bn0, st);
             }
         }
         if (m.out.q) m.out.q[pt] = q;

@@ -51,11 +51,19 @@ __device__ __forceinline__ void read_line(const HalfRecs &R, int64_t nlines, int
     L.f2 = R.face[s2];
 }
 
+// (selects between fixed elements: an index computed at run time would put the
+// caller's arrays in scratch memory)
 __device__ __forceinline__ void inface(int face, const double e[3], double uv[2])
 {
     const int a = face >> 1;
-    uv[0] = e[a == 0 ? 1 : 0];
-    uv[1] = e[a == 2 ? 1 : 2];
+    uv[0] = a == 0 ? e[1] : e[0];
+    uv[1] = a == 2 ? e[1] : e[2];
+}
+
+// component a (0, 1, 2) of v, by selects
+__device__ __forceinline__ double comp3(const double v[3], int a)
+{
+    return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
 }
 
 __device__ __forceinline__ bool edge_end(const MapJob &m, int face, const double e[3])
@@ -70,57 +78,71 @@ __device__ __forceinline__ bool edge_end(const MapJob &m, int face, const double
     return false;
 }
 
-__device__ __forceinline__ bool usable(const Line &c, const Line &o)
+// A neighbour line as the stencil needs it: the in-face coordinates of its S1 and S2
+// ends, their faces, its status, which half is S1 and whether an end lies near a box
+// edge. Kept small so that a point and its four neighbours stay in registers.
+struct Nb {
+    double u1[2], u2[2];
+    int f1, f2;
+    uint16_t st;
+    bool swapped, edge;
+};
+
+__device__ __forceinline__ Nb read_nb(const MapJob &m, const HalfRecs &R, int64_t nlines, int64_t l)
 {
-    return !(o.st & kFatal) && o.f1 == c.f1 && o.f2 == c.f2;
+    Line L;
+    read_line(R, nlines, l, L);
+    Nb n;
+    inface(L.f1, L.e1, n.u1);
+    inface(L.f2, L.e2, n.u2);
+    n.f1 = L.f1;
+    n.f2 = L.f2;
+    n.st = L.st;
+    n.swapped = L.swapped;
+    n.edge = edge_end(m, L.f1, L.e1) || edge_end(m, L.f2, L.e2);
+    return n;
 }
 
 // Which difference an S0 axis takes: central where both neighbours end on the
 // centre line's faces at both ends, else one-sided with the neighbour that does.
 enum AxisRule { RULE_NONE = 0, RULE_CENTRAL, RULE_PLUS, RULE_MINUS };
 
-__device__ __forceinline__ int axis_rule(const Line &c, const Line *m, const Line *p)
+__device__ __forceinline__ bool usable(const Line &c, const Nb &o, bool present)
 {
-    const bool um = m && usable(c, *m), up = p && usable(c, *p);
+    return present && !(o.st & kFatal) && o.f1 == c.f1 && o.f2 == c.f2;
+}
+
+// mn / pn: the neighbours on the minus / plus side, hm / hp: whether they exist
+__device__ __forceinline__ int axis_rule(const Line &c, const Nb &mn, bool hm, const Nb &pn, bool hp)
+{
+    const bool um = usable(c, mn, hm), up = usable(c, pn, hp);
     if (um && up) return RULE_CENTRAL;
     if (up) return RULE_PLUS;
     if (um) return RULE_MINUS;
     return RULE_NONE;
 }
 
-// derivatives of (u1, v1) and (u2, v2) along one S0 axis; false if no neighbour fits
-__device__ __forceinline__ bool axis_diff(const Line &c, const Line *m, const Line *p, double d, double d1[2],
-                          double d2[2], uint16_t &st)
+// derivatives of (u1, v1) and (u2, v2) along one S0 axis by the given rule (not
+// RULE_NONE); c1, c2: the centre line's in-face coordinates
+__device__ __forceinline__ void axis_diff(int rule, const double c1[2], const double c2[2],
+                                          const Nb &mn, const Nb &pn, double d, double d1[2],
+                                          double d2[2], uint16_t &st)
 {
-    const int rule = axis_rule(c, m, p);
-    if (rule == RULE_NONE) return false;
-    double c1[2], c2[2], a1[2], a2[2], b1[2], b2[2];
-    inface(c.f1, c.e1, c1);
-    inface(c.f2, c.e2, c2);
-    if (rule != RULE_PLUS) {
-        inface(m->f1, m->e1, a1);
-        inface(m->f2, m->e2, a2);
-    }
-    if (rule != RULE_MINUS) {
-        inface(p->f1, p->e1, b1);
-        inface(p->f2, p->e2, b2);
-    }
     if (rule == RULE_CENTRAL) {
         const double s = 0.5 / d;
         for (int q = 0; q < 2; q++) {
-            d1[q] = (b1[q] - a1[q]) * s;
-            d2[q] = (b2[q] - a2[q]) * s;
+            d1[q] = (pn.u1[q] - mn.u1[q]) * s;
+            d2[q] = (pn.u2[q] - mn.u2[q]) * s;
         }
-        return true;
+        return;
     }
     const bool up = rule == RULE_PLUS;
     const double s = 1.0 / d;
     for (int q = 0; q < 2; q++) {
-        d1[q] = up ? (b1[q] - c1[q]) * s : (c1[q] - a1[q]) * s;
-        d2[q] = up ? (b2[q] - c2[q]) * s : (c2[q] - a2[q]) * s;
+        d1[q] = up ? (pn.u1[q] - c1[q]) * s : (c1[q] - mn.u1[q]) * s;
+        d2[q] = up ? (pn.u2[q] - c2[q]) * s : (c2[q] - mn.u2[q]) * s;
     }
     st |= FQ_ST_ONESIDED;
-    return true;
 }
 
 __device__ __forceinline__ void point_pos(const MapJob &m, int64_t i, int64_t j, int64_t k, double r[3])
