@@ -62,6 +62,12 @@ __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, con
     return true;
 }
 
+// A wave refills its idle lanes only once at least this many are idle (or none is
+// busy): the refill code runs for the whole wave, so refilling one lane at a time
+// would run it on almost every round. FP64 steps cost more, so idle lanes cost more
+// there and the threshold is lower.
+template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 8; }
+
 // TWM: 0 = no twist (narrow records), 1 = twist, 2 = positions only on wide records
 // (the FP64 re-trace, which keeps the twist of the first pass).
 // The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
@@ -119,7 +125,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
 
         // ---- refill idle lanes: one atomic per wave ------------------------------------
         const bool need = (jb < 0) && !exhausted;
-        const unsigned long long m = __ballot(need);
+        unsigned long long m = __ballot(need);
+        if (m && __popcll(m) < refill_min<T>() && __ballot(jb >= 0) != 0) m = 0;
         if (m) {
             const int cnt = __popcll(m);
             const int leader = __ffsll((long long)m) - 1;
