@@ -483,32 +483,51 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
     double cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
     for (int c = 0; c < 3; c++)
         for (int q = 0; q < 8; q++) gB[c][q] = gJ[c][q] = 0.0;
+    // A lane reverses its half line one segment per round and takes the next half
+    // line as soon as its own is done, so the lanes of a wave stay busy while their
+    // half lines differ in length (a segment costs about the same everywhere).
+    int64_t h = -1;       // the lane's half line, -1 = none
+    bool drained = false; // the queue is empty
+    double lam[3] = {0.0, 0.0, 0.0}, ltw = 0.0, sgn = 1.0;
+    int endax = -1, ckslot = -1, next = -1, ck = -1, nck = 0, nacc = 0;
+    bool bad = false;
     for (;;) {
-        const unsigned long long hq = atomicAdd(bp.counter, 1ull);
-        if (hq >= (unsigned long long)bp.nhalves) break;
-        const int64_t h = (int64_t)hq;
-        double lam[3];
-        for (int a = 0; a < 3; a++) lam[a] = bp.lam_end[3 * h + a] * J.spacing[a];
-        // the end lies on its box face: only its in-face coordinates can move
-        const int fe = J.rec.face[h];
-        if (fe >= 0) lam[fe >> 1] = 0.0;
-        const int endax = fe >= 0 ? (fe >> 1) : -1;
-        const double ltw = TW ? bp.lam_tw[h] : 0.0;
-        if (lam[0] == 0.0 && lam[1] == 0.0 && lam[2] == 0.0 && ltw == 0.0) continue;
-        const uint16_t st = J.rec.st[h];
-        const int nck = bp.tape_n[h], nacc = bp.tape_acc[h];
-        if (st & kFatal) {
-            n_drop++;  // a line the forward map has but this pass could not keep
-            continue;
+        while (h < 0 && !drained) {
+            const unsigned long long hq = atomicAdd(bp.counter, 1ull);
+            if (hq >= (unsigned long long)bp.nhalves) {
+                drained = true;
+                break;
+            }
+            // long half lines first: they set the end of the launch
+            const int64_t hh = bp.order ? (int64_t)bp.order[hq] : (int64_t)hq;
+            for (int a = 0; a < 3; a++) lam[a] = bp.lam_end[3 * hh + a] * J.spacing[a];
+            // the end lies on its box face: only its in-face coordinates can move
+            const int fe = J.rec.face[hh];
+            if (fe >= 0) lam[fe >> 1] = 0.0;
+            endax = fe >= 0 ? (fe >> 1) : -1;
+            ltw = TW ? bp.lam_tw[hh] : 0.0;
+            if (lam[0] == 0.0 && lam[1] == 0.0 && lam[2] == 0.0 && ltw == 0.0) continue;
+            const uint16_t st = J.rec.st[hh];
+            nck = bp.tape_n[hh];
+            nacc = bp.tape_acc[hh];
+            if (st & kFatal) {
+                n_drop++;  // a line the forward map has but this pass could not keep
+                continue;
+            }
+            if (nck <= 0 || nacc <= 0) continue;  // no step taken (a seed on its exit face)
+            sgn = hh >= J.nlines ? 1.0 : -1.0;
+            n_half++;
+            bad = false;
+            ckslot = bp.tape_last[hh];
+            next = -1;
+            ck = nck - 1;
+            h = hh;
         }
-        if (nck <= 0 || nacc <= 0) continue;  // no step taken (a seed on its exit face)
-        const double sgn = h >= J.nlines ? 1.0 : -1.0;
-        n_half++;
-        bool bad = false;
-        int slot = bp.tape_last[h], next = -1, ck = nck - 1;
-        for (; slot >= 0 && ck >= 0 && !bad; ck--) {
+        if (__ballot(h >= 0) == 0) break;  // every lane is drained
+        if (h < 0) continue;
+        {
             // replay the segment from its checkpoint
-            const Ckpt cp = bp.tape[slot];
+            const Ckpt cp = bp.tape[ckslot];
             Lane<double> L;
             L.c0 = cp.c0, L.c1 = cp.c1, L.c2 = cp.c2;
             L.p0 = cp.p0, L.p1 = cp.p1, L.p2 = cp.p2;
@@ -518,69 +537,73 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             L.force = cp.force;
             const bool last = ck == nck - 1;
             const int target = last ? nacc - ck * bp.seg : bp.seg;
-            if (target < 0 || target > bp.seg || (target == 0 && !last)) {
-                bad = true;
-                break;
-            }
-            load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+            if (target < 0 || target > bp.seg || (target == 0 && !last)) bad = true;
             int nrec = 0;
-            unsigned acc = 0;
-            int cap_axis = -1, cap_clamp = 0;
-            double cap_H = 0.0;
-            const Capture capture{&cap_axis, &cap_H, &cap_clamp};
-            for (;;) {
-                if (nrec == target && !last) break;
-                StepRec pre;
-                pre.p0 = L.p0, pre.p1 = L.p1, pre.p2 = L.p2;
-                pre.c0 = L.c0, pre.c1 = L.c1, pre.c2 = L.c2;
-                int fin_st = -1, fin_face = -1;
-                bool need_load = false;
-                const unsigned before = acc;
-                lane_iterate<double, TW, Capture>(L, cb, cj, K, fin_st, fin_face, need_load, acc,
-                                                   capture);
-                if (acc != before) {
-                    if (nrec >= target) {
-                        bad = true;
+            if (!bad) {
+                load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                unsigned acc = 0;
+                int cap_axis = -1, cap_clamp = 0;
+                double cap_H = 0.0;
+                const Capture capture{&cap_axis, &cap_H, &cap_clamp};
+                for (;;) {
+                    if (nrec == target && !last) break;
+                    StepRec pre;
+                    pre.p0 = L.p0, pre.p1 = L.p1, pre.p2 = L.p2;
+                    pre.c0 = L.c0, pre.c1 = L.c1, pre.c2 = L.c2;
+                    int fin_st = -1, fin_face = -1;
+                    bool need_load = false;
+                    const unsigned before = acc;
+                    lane_iterate<double, TW, Capture>(L, cb, cj, K, fin_st, fin_face, need_load, acc,
+                                                       capture);
+                    if (acc != before) {
+                        if (nrec >= target) {
+                            bad = true;
+                            break;
+                        }
+                        pre.H = cap_H;
+                        pre.axis = cap_axis;
+                        pre.clamp = cap_clamp;
+                        buf[nrec++] = pre;
+                    }
+                    if (fin_st >= 0) {
+                        if (fin_st != 0 || nrec != target || !last) bad = true;
                         break;
                     }
-                    pre.H = cap_H;
-                    pre.axis = cap_axis;
-                    pre.clamp = cap_clamp;
-                    buf[nrec++] = pre;
+                    if (need_load)
+                        load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
                 }
-                if (fin_st >= 0) {
-                    if (fin_st != 0 || nrec != target || !last) bad = true;
-                    break;
+                if (!bad && !last) {
+                    const Ckpt nx = bp.tape[next];
+                    if (nx.c0 != L.c0 || nx.c1 != L.c1 || nx.c2 != L.c2 || nx.p0 != L.p0 ||
+                        nx.p1 != L.p1 || nx.p2 != L.p2 || nx.h != L.h)
+                        bad = true;
                 }
-                if (need_load)
-                    load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             }
-            if (!bad && !last) {
-                const Ckpt nx = bp.tape[next];
-                if (nx.c0 != L.c0 || nx.c1 != L.c1 || nx.c2 != L.c2 || nx.p0 != L.p0 ||
-                    nx.p1 != L.p1 || nx.p2 != L.p2 || nx.h != L.h)
-                    bad = true;
-            }
-            if (bad) break;
-            // reverse sweep over the segment
-            int cc0 = -1, cc1 = -1, cc2 = -1;
-            for (int r = nrec - 1; r >= 0; r--) {
-                const StepRec sr = buf[r];
-                if (sr.c0 != cc0 || sr.c1 != cc1 || sr.c2 != cc2) {
-                    if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
-                    cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
-                    load_cell<double, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+            if (!bad) {
+                // reverse sweep over the segment
+                int cc0 = -1, cc1 = -1, cc2 = -1;
+                for (int r = nrec - 1; r >= 0; r--) {
+                    const StepRec sr = buf[r];
+                    if (sr.c0 != cc0 || sr.c1 != cc1 || sr.c2 != cc2) {
+                        if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                        cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
+                        load_cell<double, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+                    }
+                    const int endb = (last && r == nrec - 1) ? endax : -1;
+                    step_adjoint<TW>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
+                    n_steps++;
                 }
-                const int endb = (last && r == nrec - 1) ? endax : -1;
-                step_adjoint<TW>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
-                n_steps++;
+                if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                next = ckslot;
+                ckslot = cp.prev;
+                ck--;
             }
-            if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
-            next = slot;
-            slot = cp.prev;
         }
-        if (!bad && (ck != -1 || slot != -1)) bad = true;  // the chain and the count disagree
-        if (bad) n_bad++;
+        if (bad || ckslot < 0 || ck < 0) {
+            if (!bad && (ck != -1 || ckslot != -1)) bad = true;  // the chain and the count disagree
+            if (bad) n_bad++;
+            h = -1;
+        }
     }
     if (bp.stats) {
         if (n_half) atomicAdd(bp.stats + 0, n_half);
@@ -656,6 +679,32 @@ hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *
     hipLaunchKernelGGL(map_backward_kernel, dim3((unsigned)b), dim3(256), 0, s, m, dq, dtw, dend_b,
                        dend_f, lam_end, lam_tw, gnode);
     return hipGetLastError();
+}
+
+namespace {
+
+__global__ void bwd_key_kernel(const int32_t *__restrict__ tape_acc, int64_t n,
+                               int32_t *__restrict__ key)
+{
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n;
+         h += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = tape_acc[h];
+        key[h] = a <= 0 ? 0 : (a >= 1020 ? 255 : a >> 2);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bwd_order(const int32_t *tape_acc, int64_t nhalves, int32_t *key,
+                            uint32_t *counts, int32_t *order, hipStream_t s)
+{
+    int64_t b = (nhalves + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(bwd_key_kernel, dim3((unsigned)b), dim3(256), 0, s, tape_acc, nhalves, key);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bucket_order(nhalves, key, counts, order, s);
 }
 
 hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,

@@ -278,7 +278,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     // adjoint: checkpoints, per-half adjoints, node gradients and replay buffers
     size_t off_tape = 0, off_tl = 0, off_tn = 0, off_ta = 0, off_lam = 0, off_ltw = 0, off_gnode = 0;
-    size_t off_buf = 0;
+    size_t off_buf = 0, off_bkey = 0, off_border = 0, off_bcnt = 0;
     int64_t bwd_halves = 0, bwd_nodes = 0;
     if (bwd) {
         if (ns != 1 || nrot != 0 || specs[0].kind != SPEC_PLANE || P.precision != FQ_PREC_F64)
@@ -293,6 +293,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         off_ltw = cv.take((size_t)bwd_halves * sizeof(double));
         off_gnode = cv.take((size_t)bwd_nodes * (P.want_tw ? 6 : 3) * sizeof(double));
         off_buf = cv.take((size_t)kBwdSlots * (size_t)bwd->seg * sizeof(StepRec));
+        off_bkey = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        off_border = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        off_bcnt = cv.take(256 * sizeof(uint32_t));
     }
     if (need) *need = cv.off;
     if (dry) return FQ_OK;
@@ -544,6 +547,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         bp.buf = (StepRec *)(ws + off_buf);
         bp.nslots = kBwdSlots;
         bp.counter = bctr;
+        int32_t *border = (int32_t *)(ws + off_border);
+        FQ_TRY(launch_bwd_order(tp.tape_acc, bwd_halves, (int32_t *)(ws + off_bkey),
+                                (uint32_t *)(ws + off_bcnt), border, stream));
+        bp.order = border;
         bp.stats = (unsigned long long *)P.stats;
         bp.max_steps = P.max_steps;
         bp.want_tw = P.want_tw;

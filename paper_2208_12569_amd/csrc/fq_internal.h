@@ -132,6 +132,7 @@ struct BwdParams {
     StepRec *buf;                  // nslots * seg replay records
     int64_t nslots;                // lanes of the reverse kernel
     unsigned long long *counter;   // queue
+    const int32_t *order;          // the half lines in queue order (longest first)
     unsigned long long *stats;     // optional: halves, steps, replay mismatches, dropped halves
     int64_t max_steps;
     int32_t want_tw;
@@ -150,6 +151,10 @@ hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
                         const TraceParams &tp, unsigned long long *counter, int block,
                         int waves_per_cu, hipStream_t s);
+// Order n items longest first: key (n values, 0..255 = longest; overwritten with the
+// bucket), counts (256), order (n: the item indices in queue order) are workspace.
+hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_t *order,
+                               hipStream_t s);
 // Order the tiles of a plane job (J: its host copy; its node records, written by
 // the prep pass for precision prec and want_tw, valid on the device): bucket (tiles),
 // counts (256), order (tiles) are workspace arrays.
@@ -186,6 +191,10 @@ struct MapJob {
 hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *dtw,
                                const double *dend_b, const double *dend_f, double *lam_end,
                                double *lam_tw, double *gnode, hipStream_t s);
+// Queue order of the reverse kernel: half lines by their accepted steps, most first
+// (key, counts, order: workspace of nhalves, 256 and nhalves entries).
+hipError_t launch_bwd_order(const int32_t *tape_acc, int64_t nhalves, int32_t *key,
+                            uint32_t *counts, int32_t *order, hipStream_t s);
 hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,
                                  const BwdParams &bp, hipStream_t s);
 hipError_t launch_grad_planes(const fq_field &f, const double *gnode, int want_tw,

@@ -527,10 +527,6 @@ hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *
                              uint32_t *counts, int32_t *order, hipStream_t s)
 {
     const int64_t ntiles = J.tiles[0] * J.tiles[1];
-    int64_t b = (ntiles + 255) / 256;
-    if (b < 1) b = 1;
-    if (b > 4096) b = 4096;
-    hipLaunchKernelGGL(fill_counts_kernel, dim3(1), dim3(256), 0, s, counts);
     hipError_t e = launch_fill_u32((uint32_t *)bucket, ntiles, 0u, s);
     if (e != hipSuccess) return e;
     int64_t bl = (10 * ntiles + 255) / 256;
@@ -543,10 +539,21 @@ hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *
         if (want_tw) hipLaunchKernelGGL((tile_len_kernel<float, true>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
         else hipLaunchKernelGGL((tile_len_kernel<float, false>), dim3((unsigned)bl), dim3(256), 0, s, J, bucket);
     }
-    hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bucket_order(ntiles, bucket, counts, order, s);
+}
+
+hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_t *order,
+                               hipStream_t s)
+{
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(fill_counts_kernel, dim3(1), dim3(256), 0, s, counts);
+    hipLaunchKernelGGL(tile_key_kernel, dim3((unsigned)b), dim3(256), 0, s, n, key, counts);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(64), 0, s, counts);
-    hipLaunchKernelGGL(tile_place_kernel, dim3((unsigned)b), dim3(256), 0, s, ntiles, bucket, counts,
-                       order);
+    hipLaunchKernelGGL(tile_place_kernel, dim3((unsigned)b), dim3(256), 0, s, n, key, counts, order);
     return hipGetLastError();
 }
 
