@@ -48,13 +48,18 @@ __global__ __launch_bounds__(256) void prep_kernel(const S *__restrict__ bx,
                                                    typename V4<T>::t *__restrict__ A,
                                                    float *__restrict__ bmax2)
 {
-    // a block takes 256-node pieces of x rows in turn (few blocks, so the maximum
-    // of |B|^2 costs one atomic per block)
+    // a block takes a contiguous range of 256-node pieces of x rows (few blocks, so
+    // the maximum of |B|^2 costs one atomic per block): the rows next to a row in y
+    // are its own block's, and those next to it in z belong to blocks a fixed
+    // distance away in the grid, which run at the same time on the same XCD, so the
+    // neighbour reads of the curl differences mostly hit L2
     const int bxs = (nx + 255) / 256;
     const int64_t pieces = (int64_t)bxs * ny * nz;
     const int64_t nxy = (int64_t)nx * ny;
+    const int64_t per = (pieces + gridDim.x - 1) / gridDim.x;
+    const int64_t p_end = min(pieces, ((int64_t)blockIdx.x + 1) * per);
     float local = 0.0f;
-    for (int64_t piece = blockIdx.x; piece < pieces; piece += gridDim.x) {
+    for (int64_t piece = (int64_t)blockIdx.x * per; piece < p_end; piece++) {
         const int64_t row = piece / bxs;
         const int i = (int)(piece - row * bxs) * 256 + (int)threadIdx.x;
         const int k = (int)(row / ny);
