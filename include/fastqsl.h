@@ -204,7 +204,8 @@ int fastqsl_q3d(const fq_field *f, const fq_voxels *v, const fq_params *p, const
  *              aligned). It holds a pool of 2 + ceil(2048/segment) checkpoints of
  *              64 bytes per half line (shared by all half lines: room for 2048
  *              accepted steps per half line on average), per-half adjoints, node
- *              gradients and replay buffers.
+ *              gradients, replay buffers and the reverse pass's queue order (half
+ *              lines by accepted steps, most first).
  * The lines are traced again with the lane state kept every `segment` accepted
  * steps; each segment is then replayed from its checkpoint with the same stepping
  * code and its accepted steps are differentiated last to first (the discrete
