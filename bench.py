@@ -114,18 +114,24 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
         ws = r["_ws"]
     torch.cuda.synchronize()
     evs = [ev.create(4) for _ in range(steps)]
+    # one event between consecutive calls: per-call times for the median
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
+    marks[0].record()
     for k in range(steps):
         r = fq.q2d(B, w.grid, w.plane,
                    fq.Params(precision=prec, tol_perp=tol, stats=stats, events=evs[k]), ws=ws)
+        marks[k + 1].record()
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
+    call_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    median_ms = (call_ms[(steps - 1) // 2] + call_ms[steps // 2]) / 2.0
     trace_ms = [ev.ms(e[0], e[1]) for e in evs]
     fix_ms = [ev.ms(e[2], e[3]) for e in evs] if prec == fq.FQ_PREC_F32X else [0.0] * steps
     st = [int(x) // steps for x in stats.tolist()]
@@ -145,7 +151,7 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
         f"tracer {sum(trace_ms) / steps:.3f} ms, FP64 pass {sum(fix_ms) / steps:.3f} ms; per step: "
         f"trials {st[0]}, accepted {st[1]}, fetches {st[2]}, halves {st[3]}, FP64 halves {st[4]}; "
         f"finite Q {finite}, fatal {fatal}")
-    return {"ms": total_ms / steps, "trace_ms": sum(trace_ms) / steps,
+    return {"ms": total_ms / steps, "median_ms": median_ms, "trace_ms": sum(trace_ms) / steps,
             "fix_ms": sum(fix_ms) / steps, "stats": st, "stats32": st32, "first_ms": first_ms,
             "map": {"q": r["q"].cpu().numpy(), "tw": r["tw"].cpu().numpy(),
                     "status": r["status"].cpu().numpy().astype("uint16")},
@@ -577,6 +583,7 @@ def main():
             "trace_ms": main_run["trace_ms"],
             "fp64_pass_ms": main_run["fix_ms"],
             "first_call_ms": main_run["first_ms"],
+            "median_ms_per_step": main_run["median_ms"],
             "per_step": {"trial_steps": st[0], "accepted_steps": st[1], "cell_fetches": st[2],
                          "half_lines": st[3], "fp64_half_lines": st[4]},
             "fp32_pass": {"trial_steps": s32[0], "accepted_steps": s32[1], "cell_fetches": s32[2]},
