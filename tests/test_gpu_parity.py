@@ -231,6 +231,31 @@ def test_batched_equals_single(fq):
         assert np.array_equal(to_np(r["tw"]), to_np(r1["tw"]), equal_nan=True)
 
 
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_batch_with_a_job_smaller_than_a_refill(fq, prec):
+    """A job of 12 half lines (fewer than the idle lanes a wave waits for before it
+    refills, in FP32; about that many in FP64) next to two larger cubes in one
+    launch: every job's map equals the job launched alone, bit for bit."""
+    import torch
+
+    jobs = synth.config_c4(5, njobs=2, edge=(40, 72), sides=(64, 96), ncharge=(4, 6))
+    dev = [(_dev(j.field), j.grid, j.plane) for j in jobs]
+    g = jobs[0].grid
+    tiny = Plane((0.4, 0.45, 0.0), (1, 0, 0), (0, 1, 0), 2, 3, 0.01, 0.01)
+    dev.append((dev[0][0], g, tiny))
+    _say(f"batch with a 2x3 job, precision {prec}")
+    rb = fq.q2d_batch(dev, fq.Params(precision=prec), want_lines=False)
+    torch.cuda.synchronize()
+    assert to_np(rb[2]["q"]).shape == (3, 2)
+    for (B, gg, pl), r in zip(dev, rb):
+        r1 = fq.q2d(B, gg, pl, fq.Params(precision=prec))
+        torch.cuda.synchronize()
+        for k in ("q", "tw", "length"):
+            assert np.array_equal(to_np(r[k]), to_np(r1[k]), equal_nan=True), k
+        assert np.array_equal(to_np(r["status"]), to_np(r1["status"]))
+    assert np.isfinite(to_np(rb[2]["length"])).all()
+
+
 def test_deterministic(fq, c1):
     w, _ = c1
     _say("determinism: two runs")
