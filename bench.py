@@ -202,6 +202,37 @@ def gather_roofline(nodes: int, nx: int, ny: int, nz: int, walk_steps: int = 400
     return out[0], out[1]
 
 
+def valu_fma_rate(iters: int = 20000):
+    """Sustained FP32 FMA rate of the chip's vector units (unpacked, as the library
+    is built): 8 independent FMA chains per lane, the best over 1-8 resident blocks
+    per CU. Returns FLOP/s."""
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2208_12569_amd", "libfqgather.so"))
+    lib.fqgb_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = torch.cuda.current_stream().cuda_stream
+    best = 0.0
+    rates = {}
+    for per_cu in (1, 2, 4, 8):
+        blocks = ncu * per_cu
+        sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+        if lib.fqgb_fma(iters, blocks, sink.data_ptr(), stream) != 0:
+            raise RuntimeError("FMA microbenchmark launch failed")
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        lib.fqgb_fma(iters, blocks, sink.data_ptr(), stream)
+        b.record()
+        b.synchronize()
+        rate = blocks * 256 * iters * 16 / (a.elapsed_time(b) * 1e-3)
+        rates[per_cu * 4] = rate / 1e12
+        best = max(best, rate)
+    log("FP32 FMA microbenchmark (TFLOP/s by resident waves per CU): "
+        + ", ".join(f"{k}: {v:.1f}" for k, v in rates.items()))
+    return best
+
+
 def run_batch(seed: int, steps: int, warmup: int):
     """The uneven batch: 16 seeded cubes (edges 64-384, FP32, 4-12 charges, seed grids
     128^2-1024^2 on z = 0) in one persistent launch, captured in a HIP graph with
@@ -610,6 +641,11 @@ def main():
                                       "whose 64 lanes per wave move together (neighbouring "
                                       "lines); walks whose lanes move apart reach "
                                       "incoherent_walks"}
+    # the ALU roofline's peak is derived from the unit counts; a FMA microbenchmark
+    # gives the sustained rate of the same (unpacked) instructions beside it
+    fma = valu_fma_rate()
+    out["roofline"]["measured_fma_peak"] = fma / 1e12
+    out["roofline"]["frac_of_measured"] = achieved / fma
     if other is not None:
         out["f64_form"] = {"value": npts / (other["ms"] * 1e-3), "ms_per_step": other["ms"],
                            "trace_ms": other["trace_ms"]}

@@ -10,7 +10,8 @@
 // 2 x 2 patch of start cells) and coherent (the 64 lanes of a wave start on an 8 x 8
 // patch and take the same moves, as neighbouring field lines do before they part).
 // The rate of fetches x 192 useful bytes (24 values of B and curl B at 8 corners) is
-// the gather roofline the tracer is measured against.
+// the gather roofline the tracer is measured against. A second kernel measures the FP32 FMA
+// rate, the arithmetic ceiling of the same lanes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -79,6 +80,27 @@ __global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restri
     sink[g] = acc;
 }
 
+// FP32 FMA rate: each lane runs `iters` rounds of 8 independent FMA chains, enough
+// independent work to cover the FMA latency; the sum is stored so that the chains
+// stay. Built like the library (packed FP32 instructions off): one FMA per lane per
+// instruction.
+__global__ __launch_bounds__(256) void fma_kernel(int iters, float a, float b, float *__restrict__ sink)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float x[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) x[q] = (float)threadIdx.x * 1e-3f + (float)q;
+#pragma unroll 4
+    for (int i = 0; i < iters; i++) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) x[q] = fmaf(x[q], a, b);
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; q++) acc += x[q];
+    sink[g] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -92,6 +114,17 @@ int fqgb_walk(const void *records, int nx, int ny, int nz, int steps, int blocks
     if (!records || !sink || nx < 17 || ny < 17 || nz < 3 || steps < 1 || blocks < 1) return 1;
     hipLaunchKernelGGL(gather_walk_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        (const float4 *)records, nx, ny, nz, steps, seed, coherent, sink);
+    return (int)hipGetLastError();
+}
+
+// FMA chains: lanes = blocks * 256, each `iters` x 8 FMAs (16 flops per round);
+// sink: blocks * 256 floats (device). Asynchronous on `stream`; returns a hipError_t
+// code.
+int fqgb_fma(int iters, int blocks, float *sink, void *stream)
+{
+    if (!sink || iters < 1 || blocks < 1) return 1;
+    hipLaunchKernelGGL(fma_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, iters,
+                       0.999999f, 1e-7f, sink);
     return (int)hipGetLastError();
 }
 
