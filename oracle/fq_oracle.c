@@ -29,6 +29,17 @@
  *     differences over neighbouring seeds, D12 = D20 (D10)^-1 with the inverse
  *     written as in Eq. D+-3, and Q = (a^2+b^2+c^2+d^2)/|Bn1/Bn2| (Section 1,
  *     Eq. Q+- with |det D| replaced by the normal-field ratio).
+ *
+ * How it is pinned (CPU tests, against facts other than itself): exact curl on
+ * quadratic fields; trilinear values against an independent interpolator; closed
+ * forms of the mapping, Q and Tw in uniform, tilted, sheared, hyperbolic and
+ * twisted fields; lines crossing a cell face and back within one step; interior
+ * seed planes against the direct S1 -> S2 map; Q(x1,y1) = Q(x2,y2); flux
+ * conservation of the difference Jacobian; B -> -B and mirror symmetries; the
+ * paper's quadrupole example (Section 3.2); end points against an independent
+ * high-order integrator. Parity unpinned: Q and Tw of the charge and flux-tube
+ * benchmark fields themselves, which have no closed form (covered only through
+ * the invariances above).
  */
 #include "fq_oracle.h"
 
