@@ -296,7 +296,8 @@ def run_adjoint(seed: int, steps: int, warmup: int):
     """The adjoint workload: the 256x256 map of a 128x128x96 FP32 cube from 8 point
     charges, and the gradient of a log10 Q + footpoint loss against a target map
     with respect to the node values (all-FP64 form, checkpoints every 32 accepted
-    steps): one forward map plus one fastqsl_backward call per step."""
+    steps): per step, the map traced once with its checkpoints kept
+    (fastqsl_q2d_record), the loss, and the reverse pass (fastqsl_backward_recorded)."""
     import torch
 
     import paper_2208_12569_amd as fq
@@ -312,17 +313,19 @@ def run_adjoint(seed: int, steps: int, warmup: int):
     tq = fq.q2d(tB, g, pl, p)["q"]
     stats = torch.zeros(5, dtype=torch.int64, device="cuda")
     gb = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
+    ws = [None]  # the record's workspace, reused from step to step
 
     def step(st=None):
-        r = fq.q2d(B, g, pl, p, want_lines=True)
+        r = fq.q2d_record(B, g, pl, p, 32, ws=ws[0])
+        ws[0] = r["_ws"]
         qq = r["q"]
         m = torch.isfinite(qq) & torch.isfinite(tq) & (qq < 1e8) & (tq < 1e8)
         lq = torch.log10(torch.where(m, qq, torch.ones_like(qq)))
         lt = torch.log10(torch.where(m, tq, torch.ones_like(tq)))
         dq = torch.where(m, 2.0 * (lq - lt) / (qq * math.log(10.0)), torch.zeros_like(qq)) / m.sum()
         gb.zero_()
-        fq.backward(B, g, pl, fq.Params(precision=fq.FQ_PREC_F64, stats=st), 32, dq=dq.reshape(-1),
-                    gb=gb)
+        fq.backward_recorded(B, g, pl, r, fq.Params(precision=fq.FQ_PREC_F64, stats=st), 32,
+                             dq=dq.reshape(-1), gb=gb)
 
     for _ in range(max(1, warmup)):
         step()
@@ -340,8 +343,8 @@ def run_adjoint(seed: int, steps: int, warmup: int):
     log(f"[adjoint] {ms:.3f} ms per map + gradient; half lines differentiated {st[0]}, "
         f"accepted steps reversed {st[1]}, replay mismatches {st[2]}")
     return {"workload": "128x128x96 FP32 cube, 8 point charges, 256x256 seeds on z=0; forward "
-                        "map + dL/dB of a log10 Q loss vs a target map (FP64, checkpoint every "
-                        "32 accepted steps)",
+                        "map traced once with checkpoints + dL/dB of a log10 Q loss vs a target "
+                        "map (FP64, checkpoint every 32 accepted steps)",
             "value": npts / (ms * 1e-3), "unit": "map points with gradient/s", "ms_per_step": ms,
             "half_lines": st[0], "steps_reversed": st[1], "replay_mismatches": st[2]}
 

@@ -223,6 +223,30 @@ int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, 
                      const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
                      void *stream);
 
+/* ---------------------------------------------------------------------------------
+ * fastqsl_q2d_record, fastqsl_backward_recorded — fastqsl_backward in two calls, for
+ * callers that need the map before they know its gradient (a training step: map,
+ * loss, then derivative). The lines are traced once.
+ *   fastqsl_q2d_record: the checkpointed forward pass of fastqsl_backward, and the
+ *     map of fastqsl_q2d (all-FP64 form) written to `map` (as fastqsl_q2d does,
+ *     Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of Eq. tw).
+ *   fastqsl_backward_recorded: the reverse pass of fastqsl_backward (same argument
+ *     meanings), reading the checkpoints and half-line records the record call left
+ *     in `ws`.
+ * Both take f, pl, p and segment as fastqsl_backward does and the workspace of
+ * fastqsl_backward_workspace_size(); the reverse call must get the same inputs and
+ * a workspace that nothing else wrote since the record call, on the same stream (or
+ * after it). A record call may be followed by any number of reverse calls. Errors
+ * as fastqsl_backward; the map's points follow fastqsl_q2d. Asynchronous on
+ * `stream`; allocate nothing.
+ * ------------------------------------------------------------------------------- */
+int fastqsl_q2d_record(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
+                       const fq_map *map, void *ws, size_t ws_bytes, void *stream);
+int fastqsl_backward_recorded(const fq_field *f, const fq_plane *pl, const fq_params *p,
+                              int segment, const double *dq, const double *dtw,
+                              const double *dend_b, const double *dend_f, double *const gb[3],
+                              void *ws, size_t ws_bytes, void *stream);
+
 /* Text of a return code (static storage). */
 const char *fastqsl_strerror(int code);
 

@@ -295,16 +295,7 @@ def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = Fal
     return m
 
 
-def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32, dq=None, dtw=None,
-             dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
-    """Reverse-mode derivative of the q2d map of (B, grid, plane) with respect to the
-    field's node values (fastqsl_backward; all-FP64 form, seed plane on a box face).
-
-    dq, dtw: CUDA float64 tensors of nu*nv values (dL/dQ, dL/dTw), dend_b, dend_f:
-    nu*nv x 3 (dL/d end points); any may be None. The result is ADDED into gb, a
-    CUDA float64 tensor shaped like B (allocated as zeros if None), and returned.
-    Lines are re-traced with checkpoints every `segment` accepted steps."""
-    torch = _torch()
+def _bwd_prepare(B, grid, plane, params: Optional[Params], segment: int):
     lib = _lib.load()
     params = params or Params(precision=FQ_PREC_F64)
     if params.precision != FQ_PREC_F64:
@@ -312,6 +303,16 @@ def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32,
     f = _field(B, grid)
     pl = _plane(plane)
     p = params.c()
+    need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
+    if need == 0:
+        raise ValueError("invalid or unsupported backward call (FP64 form, plane on a box face, "
+                         "1 <= segment <= 4096)")
+    return lib, f, pl, p, need
+
+
+def _bwd_reverse(name, B, grid, plane, params, segment, dq, dtw, dend_b, dend_f, gb, stream, ws):
+    torch = _torch()
+    lib, f, pl, p, need = _bwd_prepare(B, grid, plane, params, segment)
     if gb is None:
         gb = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
     if gb.dtype != torch.float64 or gb.shape != B.shape or not gb.is_contiguous():
@@ -330,18 +331,51 @@ def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32,
     dtw_t, dtw_p = arg(dtw, (npts,))
     db_t, db_p = arg(dend_b, (npts, 3))
     df_t, df_p = arg(dend_f, (npts, 3))
-    need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
-    if need == 0:
-        raise ValueError("invalid or unsupported backward call (FP64 form, plane on a box face, "
-                         "1 <= segment <= 4096)")
+    if name == "fastqsl_backward_recorded" and (ws is None or ws.numel() < need):
+        raise ValueError("the record does not belong to these inputs (workspace too small)")
     w = _workspace(need, B.device, ws)
     g3 = (C.c_void_p * 3)(gb[0].data_ptr(), gb[1].data_ptr(), gb[2].data_ptr())
-    _lib.check(lib.fastqsl_backward(C.byref(f), C.byref(pl), C.byref(p), int(segment), dq_p, dtw_p,
-                                    db_p, df_p, g3, w.data_ptr(), w.numel(), _stream(stream)),
-               "fastqsl_backward")
+    _lib.check(getattr(lib, name)(C.byref(f), C.byref(pl), C.byref(p), int(segment), dq_p, dtw_p,
+                                  db_p, df_p, g3, w.data_ptr(), w.numel(), _stream(stream)), name)
     if stream is not None:
         # temporaries freed here stay reserved until the caller's stream is done
         for t in (dq_t, dtw_t, db_t, df_t, w):
             if t is not None:
                 t.record_stream(stream)
     return gb
+
+
+def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32, dq=None, dtw=None,
+             dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
+    """Reverse-mode derivative of the q2d map of (B, grid, plane) with respect to the
+    field's node values (fastqsl_backward; all-FP64 form, seed plane on a box face).
+
+    dq, dtw: CUDA float64 tensors of nu*nv values (dL/dQ, dL/dTw), dend_b, dend_f:
+    nu*nv x 3 (dL/d end points); any may be None. The result is ADDED into gb, a
+    CUDA float64 tensor shaped like B (allocated as zeros if None), and returned.
+    Lines are re-traced with checkpoints every `segment` accepted steps."""
+    return _bwd_reverse("fastqsl_backward", B, grid, plane, params, segment, dq, dtw, dend_b,
+                        dend_f, gb, stream, ws)
+
+
+def q2d_record(B, grid, plane, params: Optional[Params] = None, segment: int = 32,
+               want_lines: bool = False, stream=None, ws=None) -> dict:
+    """The all-FP64 q2d map of (B, grid, plane), traced once with the checkpoints of
+    its derivative kept (fastqsl_q2d_record). The returned dict holds the map and,
+    under "_ws", the workspace to hand to backward_recorded (which must not be
+    written by anything else in between)."""
+    lib, f, pl, p, need = _bwd_prepare(B, grid, plane, params, segment)
+    w = _workspace(need, B.device, ws)
+    m, s = _alloc_map(plane.nu * plane.nv, (plane.nv, plane.nu), B.device, want_lines)
+    _lib.check(lib.fastqsl_q2d_record(C.byref(f), C.byref(pl), C.byref(p), int(segment), C.byref(s),
+                                      w.data_ptr(), w.numel(), _stream(stream)), "fastqsl_q2d_record")
+    m["_ws"] = w
+    return m
+
+
+def backward_recorded(B, grid, plane, rec: dict, params: Optional[Params] = None, segment: int = 32,
+                      dq=None, dtw=None, dend_b=None, dend_f=None, gb=None, stream=None):
+    """backward() of a map that q2d_record produced (same B, grid, plane, params and
+    segment; rec: its result), without tracing the lines again (fastqsl_backward_recorded)."""
+    return _bwd_reverse("fastqsl_backward_recorded", B, grid, plane, params, segment, dq, dtw,
+                        dend_b, dend_f, gb, stream, rec["_ws"])

@@ -73,6 +73,7 @@ EXPORTS = [
     "fastqsl_q2d_workspace_size", "fastqsl_q2d",
     "fastqsl_q3d_workspace_size", "fastqsl_q3d",
     "fastqsl_backward_workspace_size", "fastqsl_backward",
+    "fastqsl_q2d_record", "fastqsl_backward_recorded",
     "fastqsl_strerror", "fastqsl_version",
 ]
 
@@ -115,6 +116,11 @@ def load():
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p * 3, C.c_void_p, C.c_size_t, C.c_void_p]
     lib.fastqsl_backward.restype = C.c_int
+    lib.fastqsl_q2d_record.argtypes = [P(fq_field), P(fq_plane), P(fq_params), C.c_int, P(fq_map),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.fastqsl_q2d_record.restype = C.c_int
+    lib.fastqsl_backward_recorded.argtypes = lib.fastqsl_backward.argtypes
+    lib.fastqsl_backward_recorded.restype = C.c_int
     lib.fastqsl_strerror.argtypes = [C.c_int]
     lib.fastqsl_strerror.restype = C.c_char_p
     lib.fastqsl_version.argtypes = []

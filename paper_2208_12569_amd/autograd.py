@@ -1,9 +1,10 @@
 """Q/Tw maps as a differentiable torch operation.
 
 QTwMap.apply(B, grid, plane, params, segment) returns the q2d map (Q, Tw, backward
-and forward end points, status) of the all-FP64 form; its backward runs
-fastqsl_backward, the hand-written adjoint of the tracer and the Q stencil, and
-returns dL/dB. Composed with a field model written in torch (for instance point
+and forward end points, status) of the all-FP64 form, traced once with the
+checkpoints of its derivative kept (fastqsl_q2d_record); its backward runs the
+hand-written adjoint of the tracer and the Q stencil on them
+(fastqsl_backward_recorded) and returns dL/dB. Composed with a field model written in torch (for instance point
 charges -> node values), autograd then yields the gradient with respect to the
 model's parameters, so the model can be fitted to target maps.
 """
@@ -12,7 +13,7 @@ from __future__ import annotations
 
 import torch
 
-from . import FQ_PREC_F64, Params, backward, q2d
+from . import FQ_PREC_F64, Params, backward_recorded, q2d_record
 
 
 class QTwMap(torch.autograd.Function):
@@ -21,12 +22,13 @@ class QTwMap(torch.autograd.Function):
         params = params or Params(precision=FQ_PREC_F64)
         if params.precision != FQ_PREC_F64:
             raise ValueError("QTwMap differentiates the all-FP64 form")
-        r = q2d(B.detach(), grid, plane, params, want_lines=True)
+        r = q2d_record(B.detach(), grid, plane, params, segment, want_lines=True)
         shape = (plane.nv, plane.nu)
         eb = r["lines"]["end_b"].view(*shape, 3)
         ef = r["lines"]["end_f"].view(*shape, 3)
         ctx.save_for_backward(B)
         ctx.grid, ctx.plane, ctx.params, ctx.segment = grid, plane, params, segment
+        ctx.rec = r  # the workspace with the checkpoints, read by the backward pass
         st = r["status"]
         ctx.mark_non_differentiable(st)
         return r["q"], r["tw"], eb, ef, st
@@ -34,11 +36,11 @@ class QTwMap(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gq, gtw, geb, gef, _gst):
         (B,) = ctx.saved_tensors
-        gb = backward(B.detach(), ctx.grid, ctx.plane, ctx.params, ctx.segment,
-                      dq=None if gq is None else gq.reshape(-1),
-                      dtw=None if gtw is None else gtw.reshape(-1),
-                      dend_b=None if geb is None else geb.reshape(-1, 3),
-                      dend_f=None if gef is None else gef.reshape(-1, 3))
+        gb = backward_recorded(B.detach(), ctx.grid, ctx.plane, ctx.rec, ctx.params, ctx.segment,
+                               dq=None if gq is None else gq.reshape(-1),
+                               dtw=None if gtw is None else gtw.reshape(-1),
+                               dend_b=None if geb is None else geb.reshape(-1, 3),
+                               dend_f=None if gef is None else gef.reshape(-1, 3))
         return gb.to(B.dtype), None, None, None, None
 
 

@@ -212,6 +212,10 @@ void set_job_constants(TraceJob &J);
 // The reverse-mode call of one q2d map: its output adjoints, the gradient planes and
 // the checkpoint layout.
 struct BwdSpec {
+    // 0: checkpointed forward pass, then the reverse pass (no map written);
+    // 1: checkpointed forward pass and the map (a later phase 2 reverses it);
+    // 2: the reverse pass of a workspace that phase 1 filled
+    int phase;
     int seg;                 // accepted steps between checkpoints
     int64_t pool;            // checkpoints in the pool
     const double *dq, *dtw, *dend_b, *dend_f;
@@ -219,7 +223,8 @@ struct BwdSpec {
 };
 
 // Carve the workspace and (unless dry) enqueue the whole call. With bwd, the trace
-// keeps checkpoints and the map is differentiated instead of written.
+// keeps checkpoints and the map is differentiated instead of written, or (phases 1
+// and 2) the two halves of that are enqueued by separate calls on one workspace.
 int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_bytes, bool dry,
         size_t *need, hipStream_t stream, const BwdSpec *bwd = nullptr)
 {
@@ -310,9 +315,13 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         if (e != hipSuccess) return FQ_EHIP; \
     } while (0)
 
+    // the kernels of the forward pass (all but the reverse of a recorded forward pass)
+    // and of the reverse pass
+    const bool fwd = !bwd || bwd->phase != 2;
+    const bool rev = bwd && bwd->phase != 1;
     unsigned long long *counter = (unsigned long long *)(ws + off_ctr);
-    FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 4, 0u, stream));
-    for (int i = 0; i < ns; i++) {
+    if (fwd) FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 4, 0u, stream));
+    for (int i = 0; i < ns && fwd; i++) {
         const Spec &s = specs[i];
         SpecWs &w = W[i];
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.bmax), 1, 0u, stream));
@@ -405,8 +414,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         set_job_constants(J);
         if (s.kind == SPEC_PLANE) {
             J.tile_order = (const int32_t *)(ws + w.tile_order);
-            FQ_TRY(launch_tile_order(J, P.precision, P.want_tw, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
-                                     (int32_t *)(ws + w.tile_order), stream));
+            if (fwd)
+                FQ_TRY(launch_tile_order(J, P.precision, P.want_tw, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
+                                         (int32_t *)(ws + w.tile_order), stream));
         }
     }
     // queue ranges of the main jobs, largest cube first: its lines reach farthest, so
@@ -449,7 +459,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         tp.dynamic_last = 1;
     }
     TraceJob *jobs_dev = (TraceJob *)(ws + off_jobs);
-    for (int j = 0; j < njobs; j++) FQ_TRY(launch_store_job(jobs[j], jobs_dev + j, stream));
+    for (int j = 0; j < njobs && fwd; j++) FQ_TRY(launch_store_job(jobs[j], jobs_dev + j, stream));
     tp.tol_perp = P.tol_perp;
     tp.step_perp = P.step_perp;
     tp.step_min = P.step_min;
@@ -467,12 +477,13 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         tp.tape_acc = (int32_t *)(ws + off_ta);
         tp.seg = bwd->seg;
         tp.pool_cap = bwd->pool;
-        FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr + 128), 2, 0u, stream));
+        if (fwd) FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr + 128), 2, 0u, stream));
     }
-    hipEvent_t *ev = (hipEvent_t *)P.events;
+    hipEvent_t *ev = fwd ? (hipEvent_t *)P.events : nullptr;
     if (ev && ev[0]) FQ_TRY(hipEventRecord(ev[0], stream));
-    FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
-                        jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
+    if (fwd)
+        FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
+                            jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
     if (ev && ev[1]) FQ_TRY(hipEventRecord(ev[1], stream));
     if (fixup) {
         // FP64 pass over the grazing lines of the FP32 pass, and over the lines whose
@@ -523,7 +534,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                             P.waves_per_cu, stream));
         if (ev && ev[3]) FQ_TRY(hipEventRecord(ev[3], stream));
     }
-    if (bwd) {
+    if (rev) {
         double *lam_end = (double *)(ws + off_lam), *lam_tw = (double *)(ws + off_ltw);
         double *gnode = (double *)(ws + off_gnode);
         FQ_TRY(launch_fill_u32((uint32_t *)lam_end, bwd_halves * 6, 0u, stream));
@@ -778,6 +789,40 @@ int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, 
     b.dend_b = dend_b;
     b.dend_f = dend_f;
     b.gb = gb;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
+}
+
+int fastqsl_q2d_record(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
+                       const fq_map *map, void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup(f, pl, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!map) return FQ_EINVAL;
+    v[0].map = map;
+    b.phase = 1;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
+}
+
+int fastqsl_backward_recorded(const fq_field *f, const fq_plane *pl, const fq_params *p,
+                              int segment, const double *dq, const double *dtw,
+                              const double *dend_b, const double *dend_f, double *const gb[3],
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup(f, pl, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!gb || !gb[0] || !gb[1] || !gb[2]) return FQ_EINVAL;
+    b.dq = dq;
+    b.dtw = dtw;
+    b.dend_b = dend_b;
+    b.dend_f = dend_f;
+    b.gb = gb;
+    b.phase = 2;
     return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
 }
 

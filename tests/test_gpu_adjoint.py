@@ -246,6 +246,44 @@ def test_segment_length_does_not_change_the_gradient(fq):
         assert np.allclose(gb, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
 
 
+def test_recorded_forward_and_reverse_match_the_one_call_form(fq):
+    """fastqsl_q2d_record writes the all-FP64 map of fastqsl_q2d bit for bit, and
+    fastqsl_backward_recorded on its workspace (twice in a row) gives the gradient of
+    fastqsl_backward to rounding, with no replay diverging from its forward pass."""
+    import torch
+
+    g = cubic_grid(40, 40, 28)
+    pos, q = synth.draw_charges(np.random.default_rng(13), 5)
+    B = _dev(synth.charges_field(g, pos, q))
+    pl = synth.plane_z0(24)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    dq = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    dtw = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    de = torch.randn((24 * 24, 3), generator=gen, device="cuda", dtype=torch.float64)
+    _say("record + reverse vs q2d + backward")
+    rec = fq.q2d_record(B, g, pl, p, 16, want_lines=True)
+    ref_map = fq.q2d(B, g, pl, p, want_lines=True)
+    torch.cuda.synchronize()
+    for k in ("q", "tw", "length", "status"):
+        assert np.array_equal(rec[k].cpu().numpy(), ref_map[k].cpu().numpy(), equal_nan=True), k
+    for k in ("end_b", "end_f"):
+        assert np.array_equal(rec["lines"][k].cpu().numpy(), ref_map["lines"][k].cpu().numpy(),
+                              equal_nan=True), k
+    ref = _grad(fq, B, g, pl, segment=16, dq=dq, dtw=dtw, dend_b=de, dend_f=de)
+    for rep in range(2):
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+        pr = fq.Params(precision=F64, tol_perp=TOL, stats=stats)
+        gb = fq.backward_recorded(B, g, pl, rec, pr, 16, dq=dq, dtw=dtw, dend_b=de, dend_f=de)
+        torch.cuda.synchronize()
+        st = stats.tolist()
+        assert st[0] > 0 and st[2] == 0 and st[3] == 0, (rep, st)
+        gb = gb.cpu().numpy()
+        assert np.allclose(gb, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max()), rep
+    with pytest.raises(ValueError):
+        fq.backward_recorded(B, g, synth.plane_z0(48), rec, p, 16, dq=None)
+
+
 def test_gradient_matches_oracle_finite_differences(fq):
     """Reference gradient: central differences of the FP64 oracle's Q at 12 points
     for three charge parameters, against the adjoint of the sum of those Q values."""
