@@ -483,7 +483,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
     double cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
     for (int c = 0; c < 3; c++)
         for (int q = 0; q < 8; q++) gB[c][q] = gJ[c][q] = 0.0;
-    // A lane reverses its half line one segment per round and takes the next half
+    // A lane reverses its half line one segment per iteration and takes the next half
     // line as soon as its own is done, so the lanes of a wave stay busy while their
     // half lines differ in length (a segment costs about the same everywhere).
     int64_t h = -1;       // the lane's half line, -1 = none

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void gather_walk_kernel(const float4 *__restri
     sink[g] = acc;
 }
 
-// FP32 FMA rate: each lane runs `iters` rounds of 8 independent FMA chains, enough
+// FP32 FMA rate: each lane runs `iters` iterations of 8 independent FMA chains, enough
 // independent work to cover the FMA latency; the sum is stored so that the chains
 // stay. Built like the library (packed FP32 instructions off): one FMA per lane per
 // instruction.
@@ -117,7 +117,7 @@ int fqgb_walk(const void *records, int nx, int ny, int nz, int steps, int blocks
     return (int)hipGetLastError();
 }
 
-// FMA chains: lanes = blocks * 256, each `iters` x 8 FMAs (16 flops per round);
+// FMA chains: lanes = blocks * 256, each `iters` x 8 FMAs (16 flops per iteration);
 // sink: blocks * 256 floats (device). Asynchronous on `stream`; returns a hipError_t
 // code.
 int fqgb_fma(int iters, int blocks, float *sink, void *stream)

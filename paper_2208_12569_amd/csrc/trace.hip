@@ -64,7 +64,7 @@ __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, con
 
 // A wave refills its idle lanes only once at least this many are idle (or none is
 // busy): the refill code runs for the whole wave, so refilling one lane at a time
-// would run it on almost every round. FP64 steps cost more, so idle lanes cost more
+// would run it on almost every iteration. FP64 steps cost more, so idle lanes cost more
 // there and the threshold is lower.
 template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 8; }
 
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
     int last_ck = -1;           // TAPE: pool slot of the last checkpoint
 
     for (;;) {
-        int fin_st = -1, fin_face = -1;  // set when the active half line ends this round
+        int fin_st = -1, fin_face = -1;  // set when the active half line ends this iteration
 
         // ---- refill idle lanes: one atomic per wave ------------------------------------
         const bool need = (jb < 0) && !exhausted;
@@ -501,7 +501,7 @@ __global__ void tile_scan_kernel(uint32_t *counts)
 
 // Each block ranks its tiles inside their buckets in LDS and takes one range per
 // bucket from the global offsets. Blocks of 256; every thread runs the same number
-// of rounds (the barriers are uniform).
+// of iterations (the barriers are uniform).
 __global__ void tile_place_kernel(int64_t ntiles, const int32_t *__restrict__ bucket,
                                   uint32_t *__restrict__ offsets, int32_t *__restrict__ order)
 {
