@@ -33,8 +33,13 @@
  * How it is pinned (CPU tests, against facts other than itself): exact curl on
  * quadratic fields; trilinear values against an independent interpolator; closed
  * forms of the mapping, Q and Tw in uniform, tilted, sheared, hyperbolic and
- * twisted fields; lines crossing a cell face and back within one step; interior
- * seed planes against the direct S1 -> S2 map; Q(x1,y1) = Q(x2,y2); flux
+ * twisted fields; lines crossing a cell face and back within one step; Q = 2 on
+ * arcades over a polarity inversion line of the seed face, down to seeds 1e-8 from
+ * it (grazing landings); interior seed planes against the direct S1 -> S2 map;
+ * the rotated S0 of 3-D maps against the closed form of an oblique sheared field,
+ * including a voxel with Bz = 0; voxels of two layers of a 3-D map on one line
+ * (same Tw and length; Q in the ratio that the interpolant's divergence along
+ * the line fixes, computed independently); Q(x1,y1) = Q(x2,y2); flux
  * conservation of the difference Jacobian; B -> -B and mirror symmetries; the
  * paper's quadrupole example (Section 3.2); end points against an independent
  * high-order integrator. Parity unpinned: Q and Tw of the charge and flux-tube
@@ -271,23 +276,29 @@ static int rk4_doubled(const line_ctx *L, const double y[5], double t, double ou
 
 /* Length t in (0, t_hi] at which the step from y ends on the plane
  * coordinate[a] = plane; g(0) and g(t_hi) must bracket the root. Illinois-modified
- * regula falsi on g(t) = Phi(y, t)[a] - plane. */
+ * regula falsi on g(t) = Phi(y, t)[a] - plane.
+ *
+ * The iteration stops on the width of the bracket in arc length, not on the size
+ * of g: the line moves at unit speed, so a bracket of width w bounds the error of
+ * the landed point by w whatever the angle between the line and the plane. (A stop
+ * on |g| below a fixed height lets a line that grazes the plane at angle alpha land
+ * up to height/alpha away from the crossing; near a polarity inversion line on a
+ * box face that error reaches the seed's own distance from the inversion line.) */
 static int land(const line_ctx *L, const double y[5], int a, double plane, double t_hi,
                 double g_hi, double out[5], double *t_out)
 {
     double ta = 0.0, ga = y[a] - plane;
     double tb = t_hi, gb = g_hi;
     double err, t = t_hi;
-    double tiny = 1e-13 * L->f->spacing[a];
     int side = 0, st;
     double cur[5];
     memcpy(cur, out, sizeof cur);
-    for (int it = 0; it < 200; it++) {
+    for (int it = 0; it < 400; it++) {
         t = (ta * gb - tb * ga) / (gb - ga);
         if (!(t > ta && t < tb)) t = 0.5 * (ta + tb);
         if ((st = rk4_doubled(L, y, t, cur, &err))) return st;
         double gt = cur[a] - plane;
-        if (fabs(gt) <= tiny || (tb - ta) <= 1e-15 * t_hi) break;
+        if (gt == 0.0 || (tb - ta) <= 1e-15 * t_hi) break;
         if ((gt > 0) == (gb > 0)) {
             tb = t;
             gb = gt;

@@ -493,3 +493,239 @@ def test_sampled_points_equal_full_map(orc):
     assert np.array_equal(s3["status"], f3["status"].ravel()[pts])
     m = ~np.isnan(s3["q"])
     assert np.array_equal(s3["q"][m], f3["q"].ravel()[pts][m])
+
+
+# --------------------------------------------------------------------------------------
+# landing at grazing incidence: a polarity inversion line on the seed face
+# --------------------------------------------------------------------------------------
+
+
+def _arcade(g, x0):
+    """B = (1, 0, -(x - x0)): arcades over the polarity inversion line x = x0 of the
+    bottom face. A line from (x1, y1, 0) is the parabola z = ((x1-x0)^2 - (x-x0)^2)/2
+    and comes back to z = 0 at x2 = 2 x0 - x1, y2 = y1, where Bn = x1 - x0 = -Bn0
+    (Eq. rb)."""
+    return linear_field(g, [[0, 0, 0], [0, 0, 0], [-1, 0, 0]], [1.0, 0.0, x0])
+
+
+@pytest.mark.parametrize("dist", [1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
+def test_pil_arcade_q_is_two(orc, dist):
+    """Seeds on both sides of a polarity inversion line of the bottom face. The
+    zero-length half is S1 (the seed), so both sides map seed -> far footpoint by
+    x2 = 2 x0 - x1: a linear map with |Bn2/Bn0| = 1, hence Q = 2 exactly
+    (Section 1, Eq. Q+-; Q >= 2). The far footpoint is met at the angle of the seed,
+    which is |x1 - x0| at most: an end that is not converged on the crossing itself
+    (rather than on the height above the face) moves Bn2, so Q, by a relative
+    error/dist. Both ends must sit on the closed form."""
+    g = cubic_grid(17, 17, 17)
+    x0 = 0.5 + 1e-4 * math.pi
+    B = _arcade(g, x0)
+    d = 7e-4  # stencil spacing: neighbours stay off the inversion line
+    for sgn in (-1.0, 1.0):
+        xc = x0 + sgn * dist
+        pl = Plane((xc - d, 0.5 - d, 0.0), (1, 0, 0), (0, 1, 0), 3, 3, d, d)
+        r = orc.q2d(B, g, pl)
+        assert r["status"][1, 1] == 0
+        assert abs(r["q"][1, 1] - 2.0) < 1e-9, (sgn * dist, r["q"][1, 1])
+        L = r["lines"]
+        seeds = pl.points()
+        far = np.where((L["face_f"] == 4)[:, None] & (np.abs(L["end_f"] - seeds).sum(1) > 0)[:, None],
+                       L["end_f"], L["end_b"])
+        assert np.max(np.abs(far[:, 0] - (2 * x0 - seeds[:, 0]))) < 1e-13
+        assert np.max(np.abs(far[:, 1] - seeds[:, 1])) < 1e-14
+
+
+def test_pil_arcade_map_straddling_the_pil(orc):
+    """A 40 x 3 map across the inversion line with one seed 1e-9 from it: every point
+    with central differences has Q = 2 to rounding (none drops below 2 - O(delta^2))."""
+    g = cubic_grid(17, 17, 17)
+    x0 = 0.5 + 1e-4 * math.pi
+    B = _arcade(g, x0)
+    d = 1.37e-3
+    n = 40
+    ox = x0 + 1e-9 - 20 * d
+    pl = Plane((ox, 0.5 - d, 0.0), (1, 0, 0), (0, 1, 0), n, 3, d, d)
+    r = orc.q2d(B, g, pl)
+    q = r["q"][1, 1:-1]
+    st = r["status"][1, 1:-1]
+    assert np.all(st == 0)
+    assert np.max(np.abs(q - 2.0)) < 1e-8, np.max(np.abs(q - 2.0))
+
+
+# --------------------------------------------------------------------------------------
+# 3-D maps: rotated S0 (Section 4) and B . grad Q = 0 (Section 1, Eq. qline)
+# --------------------------------------------------------------------------------------
+
+
+def _sheared_oblique(g, s, y0, by=0.3):
+    """B = (1, by, s (y - y0)): y = y1 + by (x - x1) and z picks up
+    s (y1 - y0)(x - x1) + s by (x - x1)^2 / 2, so between the faces x = 0 and x = 1
+    (S1, S2 with Bn = Bx = 1) the map is (y, z) -> (y + by, z + s (y - y0) + s by / 2):
+    Jacobian [[1, 0], [s, 1]] and Q = 2 + s^2 (Section 1, Eq. Q+-)."""
+    return linear_field(g, [[0, 0, 0], [0, 0, 0], [0, s, 0]], [1.0, by, -s * y0])
+
+
+def test_rotated_s0_closed_form(orc):
+    """Voxels of a 3-D map where |Bz/B| < 0.05 take S0 perpendicular to B with four
+    extra lines (Section 4); elsewhere S0 is the voxel's z plane. Q is a property of
+    the line (Eq. qline), so both must give 2 + s^2. A voxel with Bz = 0 has no
+    usable z-plane stencil at all: only the rotated S0 gives Q there."""
+    g = cubic_grid(17, 17, 17)
+    s, y0 = 0.5, 0.4
+    B = _sheared_oblique(g, s, y0)
+    dv = 1e-4
+    opts = {"tol": 1e-12}
+    seen_rot = seen_plain = 0
+    for yc in (y0, y0 + 0.003, y0 - 0.02, y0 + 0.08, y0 - 0.12, y0 + 0.2):
+        vx = Voxels((0.45 - dv, yc - dv, 0.5), (dv, dv, 0.01), (3, 3, 1))
+        r = orc.q3d(B, g, vx, opts)
+        q, st = r["q"][0, 1, 1], r["status"][0, 1, 1]
+        rot = abs(s * (yc - y0)) < 0.05 * math.sqrt(1 + 0.09 + (s * (yc - y0)) ** 2)
+        assert bool(st & orc.ORC_ROTATED) == rot, (yc, st)
+        assert (int(st) & ~orc.ORC_ROTATED) == 0, (yc, st)
+        assert abs(q - (2 + s * s)) < 1e-6, (yc, q)
+        seen_rot += rot
+        seen_plain += not rot
+    assert seen_rot >= 3 and seen_plain >= 2
+
+
+def _interp_div(B, g, r):
+    """Trilinear B and the divergence of the trilinear interpolant at r (numpy; the
+    cell's corner values weighted by Eq. interp / w0 / w1 and by their derivatives)."""
+    n = (g.nx, g.ny, g.nz)
+    c, t = [], []
+    for a in range(3):
+        x = (r[a] - g.origin[a]) / g.spacing[a]
+        i = min(max(int(math.floor(x)), 0), n[a] - 2)
+        c.append(i)
+        t.append(x - i)
+    i, j, k = c
+    cube = B[:, k:k + 2, j:j + 2, i:i + 2]
+    wx, wy, wz = (np.array([1 - t[0], t[0]]), np.array([1 - t[1], t[1]]),
+                  np.array([1 - t[2], t[2]]))
+    d = np.array([-1.0, 1.0])
+    val = np.einsum("czyx,z,y,x->c", cube, wz, wy, wx)
+    div = (np.einsum("zyx,z,y,x->", cube[0], wz, wy, d) / g.spacing[0] +
+           np.einsum("zyx,z,y,x->", cube[1], wz, d, wx) / g.spacing[1] +
+           np.einsum("zyx,z,y,x->", cube[2], d, wy, wx) / g.spacing[2])
+    return val, div
+
+
+def _div_integral(B, g, p0, z_end):
+    """Integral of div(B)/|B| ds along the line from p0 (following B) up to the plane
+    z = z_end, by scipy's DOP853 on the trilinear interpolant (independent of the
+    oracle's integrator)."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(s, y):
+        b, dv = _interp_div(B, g, y[:3])
+        bm = np.linalg.norm(b)
+        return np.concatenate([b / bm, [dv / bm]])
+
+    def hit(s, y):
+        return y[2] - z_end
+
+    hit.terminal = True
+    sol = solve_ivp(rhs, (0.0, 5.0), np.concatenate([p0, [0.0]]), method="DOP853",
+                    rtol=1e-11, atol=1e-13, events=hit)
+    assert sol.status == 1
+    return sol.y[3, -1], sol.y[:3, -1]
+
+
+def _line_lattice(p0, p1, z0, z1, step):
+    """A voxel lattice of two layers (z0, z1) with a voxel centre on p0 and one on p1
+    (p1 - p0 is a whole number of x and y spacings near `step`); returns the voxels
+    and the flat indices of the two centres."""
+    dx, dy = p1[0] - p0[0], p1[1] - p0[1]
+    mx_, my_ = max(1, int(round(abs(dx) / step))), max(1, int(round(abs(dy) / step)))
+    sx, sy = abs(dx) / mx_, abs(dy) / my_
+    lo = np.minimum(p0, p1)
+    origin = (lo[0] - sx, lo[1] - sy, z0)
+    nx_, ny_ = mx_ + 3, my_ + 3
+    vx = Voxels(origin, (sx, sy, z1 - z0), (nx_, ny_, 2))
+    i0, j0 = int(round((p0[0] - origin[0]) / sx)), int(round((p0[1] - origin[1]) / sy))
+    i1, j1 = int(round((p1[0] - origin[0]) / sx)), int(round((p1[1] - origin[1]) / sy))
+    a, b = j0 * nx_ + i0, (ny_ + j1) * nx_ + i1
+    pts = vx.points()
+    assert np.max(np.abs(pts[a] - p0)) < 1e-12 and np.max(np.abs(pts[b] - p1)) < 1e-12
+    return vx, a, b
+
+
+def _lines_through_two_layers(orc, B, g, k0, k1, candidates, opts):
+    """Seeds p0 on the plane half a cell above node plane k0 whose forward lines rise
+    through node plane k1, and their crossing points p1 there: the same line traced
+    in the sub-box below plane k1 (trilinear interpolation is local to a cell, so
+    the sub-box holds the same interpolated field) ends on p1."""
+    z0, z1 = g.spacing[2] * (k0 + 0.5), g.spacing[2] * k1
+    gs = synth.Grid(g.nx, g.ny, k1 + 1, g.origin, g.spacing)
+    sub = np.ascontiguousarray(B[:, : k1 + 1])
+    out = []
+    for (x, y) in candidates:
+        p0 = np.array([x, y, z0])
+        L = orc.trace(sub, gs, p0[None, :], opts=opts)
+        if L["face_f"][0] == 5:
+            out.append((p0, L["end_f"][0]))
+    return z0, z1, out
+
+
+def test_p9_voxels_on_one_line_share_tw_length_and_q(orc):
+    """B . grad Q = 0 (Section 1, Eq. qline) on a 3-D map whose voxel lattice puts
+    two voxels of different layers on one field line. They must get the same Tw and
+    length (one line). Their Q comes from Method I through two different S0 planes
+    with |det D| replaced by the normal-field ratio (Eq. D+-3, Eq. Bn1), which
+    assumes that flux is conserved along the line. The trilinear interpolant of a
+    divergence-free field is not exactly divergence-free, and flux along a thin
+    tube grows as exp(int div B / |B| ds), so the two values must differ by exactly
+    Q(p0) / Q(p1) = exp(2 int_{p0}^{p1} div B / |B| ds) (up to the O(delta^2) error
+    of the differences); the integral is computed independently with scipy."""
+    bad = orc.FATAL | orc.ORC_MIXEDFACE | orc.ORC_EDGE | orc.ORC_ONESIDED
+    rng = np.random.default_rng(11)
+    g = cubic_grid(33, 33, 33)
+    pos, qq = synth.draw_charges(rng, 4)
+    B = synth.charges_field(g, pos, qq)
+    opts = {"tol": 1e-12}
+    z0, z1, pairs = _lines_through_two_layers(
+        orc, B, g, 8, 12, ((0.41, 0.47), (0.36, 0.61), (0.62, 0.58)), opts)
+    assert len(pairs) >= 2
+    checked = 0
+    for p0, p1 in pairs:
+        I, end = _div_integral(B, g, p0, z1)
+        assert np.max(np.abs(end - p1)) < 1e-8  # the same line
+        # the full-map entry point on a coarse lattice (delta ~ 2e-3)
+        vx, a, b = _line_lattice(p0, p1, z0, z1, 2e-3)
+        r = orc.q3d(B, g, vx, opts)
+        q, tw, ln, st = (r[k].ravel() for k in ("q", "tw", "len", "status"))
+        if (st[a] | st[b]) & bad:
+            continue
+        assert abs(tw[a] - tw[b]) < 1e-9 and abs(ln[a] - ln[b]) < 1e-9
+        assert abs(math.log(q[a] / q[b]) - 2 * I) < 1.5e-3
+        m = (st & bad) == 0
+        assert np.nanmin(q[m]) > 2 - 1e-3  # Q >= 2 - O(delta^2)
+        # sampled points on a fine lattice (delta ~ 2.5e-4): the O(delta^2) part shrinks
+        vx, a, b = _line_lattice(p0, p1, z0, z1, 2.5e-4)
+        r = orc.q3d_points(B, g, vx, np.array([a, b]), opts)
+        assert not (r["status"] & bad).any()
+        assert abs(math.log(r["q"][0] / r["q"][1]) - 2 * I) < 3e-5, (r["q"], I)
+        checked += 1
+    assert checked >= 2
+
+
+def test_p9_solenoidal_interpolant_q_is_a_line_invariant(orc):
+    """With a field whose trilinear interpolant is exactly divergence-free, Method I
+    through any S0 on the line gives one Q: voxels of two layers on one line agree
+    to the O(delta^2) error of the differences (Section 1, Eq. qline)."""
+    bad = orc.FATAL | orc.ORC_MIXEDFACE | orc.ORC_EDGE | orc.ORC_ONESIDED
+    g = cubic_grid(9, 9, 9)
+    B = _multilinear_solenoidal(g)
+    opts = {"tol": 1e-12}
+    z0, z1, pairs = _lines_through_two_layers(
+        orc, B, g, 2, 5, ((0.47, 0.52), (0.3, 0.6), (0.6, 0.35)), opts)
+    assert len(pairs) >= 2
+    for p0, p1 in pairs:
+        vx, a, b = _line_lattice(p0, p1, z0, z1, 1e-3)
+        r = orc.q3d(B, g, vx, opts)
+        q, tw, ln, st = (r[k].ravel() for k in ("q", "tw", "len", "status"))
+        assert not ((st[a] | st[b]) & bad)
+        assert abs(tw[a] - tw[b]) < 1e-10 and abs(ln[a] - ln[b]) < 1e-10
+        assert abs(q[a] / q[b] - 1) < 1e-5, (q[a], q[b])
+        assert q[a] > 2.05  # a non-trivial map
