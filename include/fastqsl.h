@@ -64,6 +64,9 @@ extern "C" {
 #define FQ_ST_MIXEDFACE 32  /* no neighbour ends on the centre line's faces: Q = NaN */
 #define FQ_ST_EDGE 64       /* a line of the stencil ends within edge_eps of a box edge */
 #define FQ_ST_ROTATED 128   /* S0 rotated perpendicular to B (|Bn0/B| < 0.05, interior S0) */
+#define FQ_ST_NOTAPE 256    /* adjoint calls only: the checkpoint pool ran out before this line
+                               was traced (set with FQ_ST_MAXSTEPS; the line has no outputs
+                               and no derivative; raise fq_params.tape_steps) */
 
 /* A field: three device planes of n[0]*n[1]*n[2] values of type `dtype`. */
 typedef struct {
@@ -78,13 +81,17 @@ typedef struct {
 /* Tracing parameters (Section 2.3 and the S0 rules of Section 4).
  * For a line whose seed has field angle |Bn0/B| to S0, the first step is
  * max(step_perp |Bn0/B|, step_min) (Eq. step) and the per-step error bound is
- * tol_perp |Bn0/B|^1.5 (Eq. tol), with |Bn0/B| taken no smaller than 0.05 and the
- * bound no smaller than tol_floor. Zero-valued fields take the documented default. */
+ * tol_perp |Bn0/B|^1.5 (Eq. tol), with |Bn0/B| taken no smaller than 0.05 for a
+ * seed inside the box (S0 is rotated below that) and no smaller than 1e-9 for a
+ * seed on a box face, and the bound no smaller than tol_floor. Zero-valued fields
+ * take the documented default. */
 typedef struct {
     double tol_perp;   /* RKF45 error bound for a line perpendicular to S0 (grid spacings); default 1e-6 */
     double step_perp;  /* first step for a perpendicular line (grid spacings); default 1 */
     double step_min;   /* smallest first step (grid spacings); default 0.05 */
-    double tol_floor;  /* smallest error bound used (grid spacings); default 16 ulp(1) of the form */
+    double tol_floor;  /* smallest error bound used (grid spacings); default 16 ulp(1) of FP32
+                          in the F32X form (whose FP64 pass takes the FP64 default, 1e-14,
+                          unless a larger floor is given) and 1e-14 in the F64 form */
     double edge_eps;   /* an end this close to a box edge (units of origin/spacing) sets FQ_ST_EDGE; default 1e-5 */
     int64_t max_steps; /* trial steps per half line; default 200000 */
     int32_t precision; /* FQ_PREC_F32X (default) or FQ_PREC_F64 */
@@ -103,11 +110,15 @@ typedef struct {
     void *const *events; /* host, optional: 4 hipEvent_t recorded on the call's stream right
                           before and after the tracer launch, and before and after the FP64
                           pass (for timing the tracer alone; NULL = none) */
-    double qfix;       /* FQ_PREC_F32X maps only: a line whose own map point has Q above this
-                          after the FP32 pass is traced again in FP64 too, and Q is formed
-                          again (the map amplifies a line's FP32 rounding by about sqrt(Q));
-                          default 300, negative = off. Lines of a call with no Q output, and
-                          the extra lines of rotated S0, are not selected this way */
+    double qfix;       /* FQ_PREC_F32X maps only: a line whose map point has Q above this
+                          after the FP32 pass is traced again in FP64 too (for a rotated S0,
+                          its four extra lines as well), and Q is formed again (the map
+                          amplifies a line's FP32 rounding by about sqrt(Q)); default 300,
+                          negative = off. Lines of a call with no Q output are not selected
+                          this way */
+    int64_t tape_steps; /* adjoint calls only: accepted steps per half line, on average over
+                          the map, that the checkpoint pool has room for; default 2048. A half
+                          line that finds the pool full gets FQ_ST_NOTAPE | FQ_ST_MAXSTEPS */
 } fq_params;
 
 /* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,
@@ -201,19 +212,21 @@ int fastqsl_q3d(const fq_field *f, const fq_voxels *v, const fq_params *p, const
  *   gb         three device double planes shaped like the field: dL/dBx, dL/dBy,
  *              dL/dBz are ADDED to them.
  *   ws         caller workspace of fastqsl_backward_workspace_size() bytes (256-byte
- *              aligned). It holds a pool of 2 + ceil(2048/segment) checkpoints of
- *              64 bytes per half line (shared by all half lines: room for 2048
- *              accepted steps per half line on average), per-half adjoints, node
- *              gradients, replay buffers and the reverse pass's queue order (half
- *              lines by accepted steps, most first).
+ *              aligned). It holds a pool of 2 + ceil(p->tape_steps/segment)
+ *              checkpoints of 64 bytes per half line (shared by all half lines: room
+ *              for p->tape_steps accepted steps per half line on average), per-half
+ *              adjoints, node gradients, replay buffers and the reverse pass's queue
+ *              order (half lines by accepted steps, most first).
  * The lines are traced again with the lane state kept every `segment` accepted
  * steps; each segment is then replayed from its checkpoint with the same stepping
  * code and its accepted steps are differentiated last to first (the discrete
  * adjoint with the step lengths held fixed). A half line that finds the pool
- * exhausted is dropped (it contributes nothing). If p->stats is set, stats[0..3]
- * get the half lines differentiated, the accepted steps reversed, the replays that
- * failed to reproduce the forward pass (expected 0) and the half lines with a
- * nonzero adjoint that were dropped (expected 0).
+ * exhausted is not traced further: it ends with FQ_ST_NOTAPE | FQ_ST_MAXSTEPS, so
+ * its point has no outputs and contributes nothing; fastqsl_q2d_record reports
+ * those points in the map's status. If p->stats is set, stats[0..3] get the half
+ * lines differentiated, the accepted steps reversed, the replays that failed to
+ * reproduce the forward pass (expected 0) and the half lines with a nonzero
+ * adjoint that were dropped (expected 0).
  * Asynchronous on `stream`; allocates nothing.
  * ------------------------------------------------------------------------------- */
 size_t fastqsl_backward_workspace_size(const fq_field *f, const fq_plane *pl,

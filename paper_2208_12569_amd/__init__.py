@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     ST_MAXSTEPS,
     ST_MIXEDFACE,
     ST_NONFINITE,
+    ST_NOTAPE,
     ST_NULLB,
     ST_ONESIDED,
     ST_OUTSIDE,
@@ -49,6 +50,7 @@ class Params:
     waves_per_cu: int = 0
     graze: float = 0.0
     qfix: float = 0.0
+    tape_steps: int = 0  # adjoint calls: checkpoint pool room in accepted steps per half line
     stats: object = None  # optional CUDA int64 tensor of 5 counters (added to)
     events: object = None  # optional ctypes array of 4 hipEvent_t handles
 
@@ -66,6 +68,7 @@ class Params:
         p.waves_per_cu = int(self.waves_per_cu)
         p.graze = float(self.graze)
         p.qfix = float(self.qfix)
+        p.tape_steps = int(self.tape_steps)
         p.stats = self.stats.data_ptr() if self.stats is not None else None
         p.events = C.cast(self.events, C.c_void_p) if self.events is not None else None
         return p

@@ -31,6 +31,7 @@ ST_ONESIDED = 16
 ST_MIXEDFACE = 32
 ST_EDGE = 64
 ST_ROTATED = 128
+ST_NOTAPE = 256
 ST_FATAL = ST_OUTSIDE | ST_NULLB | ST_MAXSTEPS | ST_NONFINITE
 
 
@@ -44,7 +45,7 @@ class fq_params(C.Structure):
                 ("tol_floor", C.c_double), ("edge_eps", C.c_double), ("max_steps", C.c_int64),
                 ("precision", C.c_int32), ("want_tw", C.c_int32), ("block", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("graze", C.c_double), ("stats", C.c_void_p),
-                ("events", C.c_void_p), ("qfix", C.c_double)]
+                ("events", C.c_void_p), ("qfix", C.c_double), ("tape_steps", C.c_int64)]
 
 
 class fq_plane(C.Structure):

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import torch
 
-from . import FQ_PREC_F64, Params, backward_recorded, q2d_record
+from . import FQ_PREC_F64, ST_NOTAPE, Params, backward_recorded, q2d_record
 
 
 class QTwMap(torch.autograd.Function):
@@ -30,6 +30,9 @@ class QTwMap(torch.autograd.Function):
         ctx.grid, ctx.plane, ctx.params, ctx.segment = grid, plane, params, segment
         ctx.rec = r  # the workspace with the checkpoints, read by the backward pass
         st = r["status"]
+        if bool(((st.to(torch.int32) & ST_NOTAPE) != 0).any()):
+            raise RuntimeError("the adjoint's checkpoint pool ran out: raise params.tape_steps "
+                               "(accepted steps per half line the pool holds on average)")
         ctx.mark_non_differentiable(st)
         return r["q"], r["tw"], eb, ef, st
 

@@ -93,6 +93,10 @@ int check_voxels(const fq_voxels *v)
     return FQ_OK;
 }
 
+// Default error-bound floors (grid spacings): 16 ulp(1) of FP32 and about 70 ulp(1)
+// of FP64.
+constexpr double kFloor32 = 2.384185791015625e-7, kFloor64 = 1e-14;
+
 int resolve_params(const fq_params *in, fq_params &p)
 {
     memset(&p, 0, sizeof p);
@@ -109,13 +113,15 @@ int resolve_params(const fq_params *in, fq_params &p)
     if (p.tol_perp == 0) p.tol_perp = 1e-6;
     if (p.step_perp == 0) p.step_perp = 1.0;
     if (p.step_min == 0) p.step_min = 0.05;
-    if (p.tol_floor == 0) p.tol_floor = (p.precision == FQ_PREC_F64) ? 1e-14 : 2.384185791015625e-7;
+    if (p.tol_floor == 0) p.tol_floor = (p.precision == FQ_PREC_F64) ? kFloor64 : kFloor32;
     if (p.edge_eps == 0) p.edge_eps = 1e-5;
     if (p.max_steps == 0) p.max_steps = 200000;
     if (!isfinite(p.graze)) return FQ_EINVAL;
     if (p.graze == 0) p.graze = 0.05;
     if (!isfinite(p.qfix)) return FQ_EINVAL;
     if (p.qfix == 0) p.qfix = 300.0;
+    if (p.tape_steps < 0) return FQ_EINVAL;
+    if (p.tape_steps == 0) p.tape_steps = 2048;
     if (in == nullptr) p.want_tw = 1;
     return FQ_OK;
 }
@@ -231,7 +237,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     const int ns = (int)specs.size();
     const size_t tsz = P.precision == FQ_PREC_F64 ? 8 : 4;
     Carve cv;
-    const size_t off_ctr = cv.take(256);  // u64 queue counter, u32 spare
+    // queue counters: +0 the tracer (u64, u32 spare), +64 the reverse pass, +128 the
+    // checkpoint pool, +192 the FP64 pass over half lines that need their twist
+    const size_t off_ctr = cv.take(256);
     std::vector<SpecWs> W(ns);
     int nrot = 0;
     for (int i = 0; i < ns; i++) {
@@ -272,7 +280,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     size_t off_list = 0, off_lcount = 0, off_jobs64 = 0;
     if (fixup) {
         off_list = cv.take((size_t)(2 * all_lines) * sizeof(FixEntry));
-        off_lcount = cv.take(sizeof(uint32_t));
+        off_lcount = cv.take(2 * sizeof(uint32_t));  // positions-only and twist lists
         if (fix_store == FQ_DT_F64) {
             off_jobs64 = cv.take((size_t)njobs * sizeof(TraceJob));
             for (int i = 0; i < ns; i++) {
@@ -499,12 +507,15 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             }
         FixEntry *list = (FixEntry *)(ws + off_list);
         uint32_t *lcount = (uint32_t *)(ws + off_lcount);
-        FQ_TRY(launch_fill_u32(lcount, 1, 0u, stream));
+        FQ_TRY(launch_fill_u32(lcount, 2, 0u, stream));
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 2, 0u, stream));
         for (int j = 0; j < njobs; j++) {
-            const double *qmap = (qsel && j < ns && specs[j].kind != SPEC_LIST) ? maps[j].out.q : nullptr;
+            // the spec whose map decides the Q rule: a main job's own, or for the
+            // rotated-S0 job (only with a single spec) the map of spec 0
+            const int sp = j < ns ? j : 0;
+            const double *qmap = (qsel && specs[sp].kind != SPEC_LIST) ? maps[sp].out.q : nullptr;
             FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, qmap, P.qfix, list, lcount,
-                                2 * all_lines, stream));
+                                lcount + 1, 2 * all_lines, stream));
         }
         const TraceJob *fix_jobs = jobs_dev;
         if (fix_store == FQ_DT_F64) {
@@ -527,11 +538,24 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         fp.list = list;
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;
+        // the FP64 pass is held to the FP64 floor unless the caller set a larger one
+        fp.tol_floor = P.tol_floor == kFloor32 ? kFloor64 : P.tol_floor;
         if (ev && ev[2]) FQ_TRY(hipEventRecord(ev[2], stream));
         // positions only: the twist integral is not sensitive to the end angle, so the
         // FP32 pass's Tw is kept and the latency-bound FP64 pass skips the curl
         FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw ? 2 : 0, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
+        if (P.want_tw) {
+            // half lines the FP32 pass could not finish have no twist yet: trace those
+            // (usually none) with the twist integrand, on a queue counter of their own
+            TraceParams ft = fp;
+            ft.list_count = lcount + 1;
+            ft.list_rev = 1;
+            unsigned long long *c2 = (unsigned long long *)(ws + off_ctr + 192);
+            FQ_TRY(launch_fill_u32((uint32_t *)c2, 2, 0u, stream));
+            FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, 1, fix_jobs, ft, c2, P.block, P.waves_per_cu,
+                                stream));
+        }
         if (ev && ev[3]) FQ_TRY(hipEventRecord(ev[3], stream));
     }
     if (rev) {
@@ -616,10 +640,6 @@ int q2d_specs(const fq_field *fields, const fq_plane *planes, int njobs, const f
     return FQ_OK;
 }
 
-// Checkpoint pool of the adjoint's forward pass: room for 2048 accepted steps per
-// half line on average (plus the first checkpoint and a partial segment).
-constexpr int64_t kBwdPoolSteps = 2048;
-
 int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
               fq_params &P, std::vector<Spec> &v, BwdSpec &b)
 {
@@ -633,8 +653,11 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
     if ((rc = q2d_specs(f, pl, 1, nullptr, v))) return rc;
     memset(&b, 0, sizeof b);
     b.seg = segment;
+    // checkpoint pool: room for tape_steps accepted steps per half line on average
+    // (plus the first checkpoint and a partial segment)
     const int64_t halves = 2 * pl->nu * pl->nv;
-    b.pool = halves * (2 + (kBwdPoolSteps + segment - 1) / segment);
+    if (P.tape_steps > ((int64_t)1 << 40)) return FQ_EINVAL;
+    b.pool = halves * (2 + (P.tape_steps + segment - 1) / segment);
     if (b.pool > INT32_MAX) return FQ_EINVAL;
     return FQ_OK;
 }

@@ -109,6 +109,8 @@ struct TraceParams {
     const FixEntry *list;          // list mode: trace exactly these half lines
     const uint32_t *list_count;
     int64_t list_cap;
+    int32_t list_rev;              // list mode: entry k sits at list[list_cap - 1 - k]
+    int32_t pad3;
     // adjoint forward pass (FP64, single job): checkpoints every `seg` accepted steps
     Ckpt *tape;                    // checkpoint pool of pool_cap entries
     unsigned long long *pool_ctr;  // next free pool slot
@@ -160,9 +162,14 @@ hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_
 // counts (256), order (tiles) are workspace arrays.
 hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *bucket, uint32_t *counts,
                              int32_t *order, hipStream_t s);
+// Lists the half lines of job `job` that the FP64 pass traces again: positions only
+// at list[0, *count) and, for half lines the FP32 pass could not finish (whose twist
+// is then missing too), with the twist at list[cap - 1 - k] for k < *count_tw.
+// qmap: the job's map after the FP32 pass (the map of the job's main points for a
+// rotated-S0 job), or NULL.
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
-                        const double *qmap, double qthr,
-                        FixEntry *list, uint32_t *count, int64_t cap, hipStream_t s);
+                        const double *qmap, double qthr, FixEntry *list, uint32_t *count,
+                        uint32_t *count_tw, int64_t cap, hipStream_t s);
 
 // Map assembly (Q stencil) of one layer-structured map.
 struct MapJob {

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
                     int64_t line;
                     bool forward;
                     if (tp.list) {
-                        const FixEntry e = gptr(tp.list)[it];
+                        const FixEntry e = gptr(tp.list)[tp.list_rev ? tp.list_cap - 1 - it : it];
                         j = UNI ? 0 : e.job;
                         line = e.line;
                         forward = e.half != 0;
@@ -228,14 +228,24 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
                 const float b2 = bx * bx + by * by + bz * bz;
                 const float bn = bx * (float)J.normal[0] + by * (float)J.normal[1] +
                                  bz * (float)J.normal[2];
+                // |Bn0/B| is taken no smaller than 0.05 where S0 is interior (the map
+                // rotates S0 perpendicular to B below that), but on a box face, where
+                // S0 is the physical S1, the angle itself scales the bound: near a
+                // polarity inversion line Bn at the far end is as small as the seed's
+                // distance from that line, so the far footpoint must be found to a
+                // small fraction of it, which the ang^1.5 of Eq. tol provides
+                const bool on_face = (L.c0 == 0 && L.p0 == T(0)) || (L.c0 == K.nx - 2 && L.p0 == T(1)) ||
+                                     (L.c1 == 0 && L.p1 == T(0)) || (L.c1 == K.ny - 2 && L.p1 == T(1)) ||
+                                     (L.c2 == 0 && L.p2 == T(0)) || (L.c2 == K.nz - 2 && L.p2 == T(1));
+                const float amin = on_face ? 1e-9f : 0.05f;
                 float ang = (J.kind == SEED_ROTATED) ? 1.0f : fabsf(bn) * Num<float>::rsq(b2);
-                if (!(ang >= 0.05f)) ang = 0.05f;  // also catches NaN
+                if (!(ang >= amin)) ang = amin;  // also catches NaN
                 if (ang > 1.0f) ang = 1.0f;
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
                 L.tol = (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
                 if (TAPE) {
                     if (store_ckpt<T, TWM, UNI, TAPE>(tp, last_ck, L)) nck++;
-                    else fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
+                    else fin_st = FQ_ST_MAXSTEPS | FQ_ST_NOTAPE;  // no checkpoint space
                 }
             }
         }
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
                     if (store_ckpt<T, TWM, UNI, TAPE>(tp, last_ck, L)) {
                         nck++;
                     } else {
-                        fin_st = FQ_ST_MAXSTEPS;  // no checkpoint space: the line is dropped
+                        fin_st = FQ_ST_MAXSTEPS | FQ_ST_NOTAPE;  // no checkpoint space
                         fin_face = -1;
                     }
                 }
@@ -263,7 +273,16 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
             const TraceJob &J = jobs[UNI ? 0 : jb];
             const bool bad = (fin_st & (FQ_ST_OUTSIDE | FQ_ST_NULLB | FQ_ST_MAXSTEPS | FQ_ST_NONFINITE)) != 0;
             double e0 = NAN, e1 = NAN, e2 = NAN;
-            if (!bad) {
+            if (!bad && L.len == 0.0) {
+                // no step taken (a seed on a box face heading out of the box): the
+                // half line ends exactly at its seed, not at the seed's position as
+                // rounded into local coordinates of the compute type
+                double r[3], nrm[3];
+                seed_of_line(J, rec >= J.nlines ? rec - J.nlines : rec, r, nrm);
+                e0 = r[0];
+                e1 = r[1];
+                e2 = r[2];
+            } else if (!bad) {
                 e0 = J.origin[0] + ((double)L.c0 + (double)L.p0) * J.spacing[0];
                 e1 = J.origin[1] + ((double)L.c1 + (double)L.p1) * J.spacing[1];
                 e2 = J.origin[2] + ((double)L.c2 + (double)L.p2) * J.spacing[2];
@@ -307,13 +326,16 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
 // is nearly tangent to the face they end on, turn FP32 rounding into large footpoint
 // errors (a height error d of a line meeting a plane at angle a moves its crossing
 // by d/a); those half lines, and any the FP32 pass could not finish, are listed for
-// the FP64 pass. So are both halves of a line whose own map point (qmap, the Q the
-// FP32 pass gives; one point per line of a plane or voxel job) has Q above qthr: the
-// map stretches a line's rounding error by about sqrt(Q).
+// the FP64 pass. So are both halves of a line whose map point (qmap, the Q the FP32
+// pass gives: one point per line of a plane or voxel job; for the four lines of a
+// rotated-S0 entry, the entry's point) has Q above qthr: the map stretches a line's
+// rounding error by about sqrt(Q). Half lines the FP32 pass could not finish have no
+// twist either: they go to the second list (from the top of the array down), which
+// is traced with the twist integrand.
 __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double thr,
                              const double *__restrict__ qmap, double qthr,
                              FixEntry *__restrict__ list, uint32_t *__restrict__ count,
-                             int64_t cap)
+                             uint32_t *__restrict__ count_tw, int64_t cap)
 {
     const TraceJob &J = jobs[job];
     const int64_t nl = live_lines(J);
@@ -335,21 +357,28 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
             const double bn = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
             seed_graze = !(fabs(bn) >= thr * bm);
         }
-        if (qmap && (J.kind == SEED_PLANE || J.kind == SEED_VOXELS) && l < J.nlines && qmap[l] > qthr)
-            seed_graze = true;
+        if (qmap) {
+            if ((J.kind == SEED_PLANE || J.kind == SEED_VOXELS) && l < J.nlines && qmap[l] > qthr)
+                seed_graze = true;
+            if (J.kind == SEED_ROTATED && qmap[J.rot[l >> 2].point] > qthr) seed_graze = true;
+        }
         for (int h = 0; h < 2; h++) {
             const int64_t q = h ? hf : hb;
             if (J.rec.len[q] == 0.0) continue;  // ends at its seed: nothing to improve
-            bool redo = seed_graze || (J.rec.st[q] & FQ_ST_MAXSTEPS) != 0;
+            const bool unfinished = (J.rec.st[q] & FQ_ST_MAXSTEPS) != 0;
+            bool redo = seed_graze;
             const int face = J.rec.face[q];
-            if (!redo && face >= 0) {
+            if (!redo && !unfinished && face >= 0) {
                 const double e[3] = {J.rec.end[3 * q], J.rec.end[3 * q + 1], J.rec.end[3 * q + 2]};
                 double B[3];
                 interp64(J.planes, e, B);
                 const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
                 redo = !(fabs(B[face >> 1]) >= thr * bm);
             }
-            if (redo) {
+            if (unfinished) {
+                const uint32_t k = atomicAdd(count_tw, 1u);
+                if ((int64_t)k < cap) list[cap - 1 - k] = FixEntry{job, h, l};
+            } else if (redo) {
                 const uint32_t slot = atomicAdd(count, 1u);
                 if ((int64_t)slot < cap) list[slot] = FixEntry{job, h, l};
             }
@@ -606,13 +635,13 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
 
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr, FixEntry *list, uint32_t *count,
-                        int64_t cap, hipStream_t s)
+                        uint32_t *count_tw, int64_t cap, hipStream_t s)
 {
     int64_t b = (max_lines + 255) / 256;
     if (b < 1) b = 1;
     if (b > 65536) b = 65536;
     hipLaunchKernelGGL(graze_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, job, thr, qmap,
-                       qthr, list, count, cap);
+                       qthr, list, count, count_tw, cap);
     return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 //
 // One call of lane_iterate() makes one trial step of one half line inside its
 // current grid cell; the caller owns the cell coefficients and refetches them when
-// the call reports a cell change. The same function runs in the GPU kernel and,
-// compiled for the host, in CPU replays of single lines.
+// the call reports a cell change. The same function runs in the tracer kernel and
+// in the adjoint's replays of recorded segments (which capture the accepted steps
+// through the event sink).
 //
 // Method: RKF45 (Fehlberg's 4(5) pair, fifth-order solution kept; Section 2.3) on
 // dr/ds = B/|B| (Section 2.1, Eq. rb) with the Eq. tw integrand (Section 1) and the
@@ -180,7 +181,7 @@ template <typename T> struct LaneConst {
     int64_t max_steps;
 };
 
-// Why a trial ended (for CPU replays; the GPU build ignores it).
+// Why a trial ended (an event sink may record it; the tracer ignores it).
 enum Ev : int {
     EV_CROSS = 0,     // moved to the next cell through the face it sat on
     EV_NOLAND,        // a landing was not possible yet: plain step next
@@ -250,13 +251,18 @@ __host__ __device__ __forceinline__ int excursion(int axis, T p, T s1, T D, T ov
 }
 
 // Face code of a box face that a step ended past (coordinate n of cell c on an axis
-// of `nodes` nodes, face codes lo and lo + 1) while the line heads out through it
-// with direction component d steeper than gmin; -1 if none.
+// of `nodes` nodes, face codes lo and lo + 1) while the line crosses it: its
+// direction component heads out through the face more steeply than gmin at the
+// start of the step (d0) or at its end (d1); -1 if none. Only a line tangent to
+// the face at both ends keeps the overshoot allowance: a line that turns over
+// within the step and leaves at a small angle alpha would otherwise be clamped
+// onto the face up to ov / alpha away from its crossing (near a polarity
+// inversion line on a box face, alpha is the seed's distance from that line).
 template <typename T>
-__host__ __device__ __forceinline__ int box_past(T n, int c, int nodes, T d, int lo)
+__host__ __device__ __forceinline__ int box_past(T n, int c, int nodes, T d0, T d1, int lo)
 {
-    if (c == 0 && n < T(0) && d < -Num<T>::gmin) return lo;
-    if (c == nodes - 2 && n > T(1) && d > Num<T>::gmin) return lo + 1;
+    if (c == 0 && n < T(0) && (d0 < -Num<T>::gmin || d1 < -Num<T>::gmin)) return lo;
+    if (c == nodes - 2 && n > T(1) && (d0 > Num<T>::gmin || d1 > Num<T>::gmin)) return lo + 1;
     return -1;
 }
 
@@ -448,14 +454,18 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         // Past a box face the line ends on that face, and clamping an overshoot d onto
         // it moves the end by d over the line's slope to the face: a first-order
         // error, not the second-order kink error of an interior face. So a step that
-        // ends past a box face the line heads out through steeply enough to land on
-        // keeps no overshoot: it lands on that face instead (`bp`, its face code). A
-        // line tangent to the box face, or turning back, keeps the allowance (a
-        // landing there would not converge). The start direction is k1 times g0.
+        // ends past a box face the line crosses keeps no overshoot: it lands on that
+        // face instead (`bp`, its face code), or, where the line is not heading out
+        // steeply enough at the step's start to take the face coordinate as the
+        // independent variable, approaches it with shorter plain steps first. Only
+        // a line tangent to the box face at both ends of the step keeps the
+        // allowance. The start direction is k1 times g0; stage 5 sits at the end
+        // of the step, so k5 times g0 stands for the end direction (its sign is
+        // exact, its size is scaled by that stage's own g on a landing).
         int bp = -1;
-        if (axis != 0) bp = box_past(n0, L.c0, K.nx, k[0][0] * g0, 0);
-        if (bp < 0 && axis != 1) bp = box_past(n1, L.c1, K.ny, k[0][1] * g0, 2);
-        if (bp < 0 && axis != 2) bp = box_past(n2, L.c2, K.nz, k[0][2] * g0, 4);
+        if (axis != 0) bp = box_past(n0, L.c0, K.nx, k[0][0] * g0, k[4][0] * g0, 0);
+        if (bp < 0 && axis != 1) bp = box_past(n1, L.c1, K.ny, k[0][1] * g0, k[4][1] * g0, 2);
+        if (bp < 0 && axis != 2) bp = box_past(n2, L.c2, K.nz, k[0][2] * g0, k[4][2] * g0, 4);
         // a brief excursion over a face inside the step (the end may be back inside)
         int xf = -1;
         if (axis != 0) xf = excursion(0, L.p0, H * k[0][0], dyv[0], ov);

@@ -27,9 +27,34 @@ BAR_FOOT = 1e-6
 _CACHE: dict = {}
 
 
+class NoToleranceMeetsBar(RuntimeError):
+    """No candidate tol_perp kept the maps within the accuracy bar; `report` holds
+    the errors and times of every candidate."""
+
+    def __init__(self, report: dict):
+        super().__init__("no candidate tolerance keeps the maps within the accuracy bar: "
+                         + ", ".join(f"{t:g}: logq {r['logq']:.2e} tw {r['tw']:.2e} "
+                                     f"foot {r['foot']:.2e}" for t, r in report.items()))
+        self.report = report
+
+
 def _key(jobs, params: Params):
+    """Launch shapes are timed per job shapes, precision and Tw flag."""
     return (tuple((tuple(B.shape), str(B.dtype), pl.nu, pl.nv) for B, _, pl in jobs),
             params.precision, params.want_tw)
+
+
+def _field_key(jobs):
+    """A fingerprint of the field values and seed planes: an accepted tolerance holds
+    for the fields it was checked on, not for every field of the same shape."""
+    torch = _torch()
+    out = []
+    for B, grid, pl in jobs:
+        x = B.to(torch.float64)
+        out.append((float(x.sum()), float((x * x).sum()), float(x.abs().amax()),
+                    tuple(float(v) for v in grid.origin), tuple(float(v) for v in grid.spacing),
+                    tuple(float(v) for v in pl.origin), float(pl.du), float(pl.dv)))
+    return tuple(out)
 
 
 def _timed(jobs, params: Params, outs, ws, reps: int) -> float:
@@ -98,7 +123,8 @@ def tune_tol(jobs: Sequence, params: Optional[Params] = None,
              tols=(1e-5, 3e-6, 1e-6), ref_tol: float = 1e-9, margin: float = 0.5,
              reps: int = 3) -> tuple:
     """Loosest-and-fastest tol_perp whose maps stay within margin x the bar against
-    the all-FP64 form at ref_tol; returns (Params, report)."""
+    the all-FP64 form at ref_tol; returns (Params, report). Raises
+    NoToleranceMeetsBar (with the report) when no candidate does."""
     torch = _torch()
     params = params or Params()
     jobs = list(jobs)
@@ -120,20 +146,26 @@ def tune_tol(jobs: Sequence, params: Optional[Params] = None,
         report[t] = dict(worst, ms=ms, ok=ok)
     good = [t for t in tols if report[t]["ok"]]
     if not good:
-        return dataclasses.replace(params, tol_perp=min(tols)), report
+        raise NoToleranceMeetsBar(report)
     best = min(good, key=lambda t: report[t]["ms"])
     return dataclasses.replace(params, tol_perp=best), report
 
 
 def autotune(jobs: Sequence, params: Optional[Params] = None, tune_tolerance: bool = False,
              **kw) -> Params:
-    """Tuned Params for these jobs (cached per shapes, precision and Tw flag)."""
+    """Tuned Params for these jobs. The launch shape is cached per job shapes,
+    precision and Tw flag; a tuned tolerance additionally per field values and seed
+    planes (it was checked against the bar on those fields only). A tolerance search
+    that finds no candidate within the bar raises NoToleranceMeetsBar and caches
+    nothing."""
     params = params or Params()
-    key = _key(jobs, params) + (tune_tolerance,)
+    key = _key(jobs, params) + ((_field_key(jobs),) if tune_tolerance else ())
     if key in _CACHE:
         return dataclasses.replace(params, **_CACHE[key])
     p, _ = tune_launch(jobs, params, **{k: v for k, v in kw.items() if k in ("blocks", "waves", "reps")})
+    fields = {"block": p.block, "waves_per_cu": p.waves_per_cu}
     if tune_tolerance:
         p, _ = tune_tol(jobs, p, **{k: v for k, v in kw.items() if k in ("tols", "ref_tol", "margin")})
-    _CACHE[key] = {"block": p.block, "waves_per_cu": p.waves_per_cu, "tol_perp": p.tol_perp}
+        fields["tol_perp"] = p.tol_perp
+    _CACHE[key] = fields
     return p

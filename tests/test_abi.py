@@ -47,7 +47,7 @@ def test_struct_sizes_match_header_layout(lib):
 
     # int64[3] + double[3] + double[3] + int32 + int32 + ptr[3]
     assert C.sizeof(_lib.fq_field) == 24 + 24 + 24 + 8 + 24
-    assert C.sizeof(_lib.fq_params) == 5 * 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8
+    assert C.sizeof(_lib.fq_params) == 5 * 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8
     assert C.sizeof(_lib.fq_plane) == 9 * 8 + 16 + 16
     assert C.sizeof(_lib.fq_voxels) == 9 * 8
     assert C.sizeof(_lib.fq_lines) == 10 * 8
@@ -206,3 +206,35 @@ def test_backward_workspace_query(lib):
     rc = lib.fastqsl_backward(C.byref(f), C.byref(pl), C.byref(p), 32, None, None, None, None, gb,
                               None, 0, None)
     assert rc == _lib.FQ_EINVAL
+
+
+def test_ctypes_layout_matches_compiled_header(tmp_path):
+    """Every field of every struct of the header sits at the same offset in the
+    binding's ctypes structs as in the C compiler's layout of the header."""
+    import subprocess
+
+    from paper_2208_12569_amd import _lib
+
+    structs = {"fq_field": _lib.fq_field, "fq_params": _lib.fq_params, "fq_plane": _lib.fq_plane,
+               "fq_voxels": _lib.fq_voxels, "fq_lines": _lib.fq_lines, "fq_map": _lib.fq_map}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fastqsl.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fld, _ in cls._fields_:
+            lines.append(f'printf("{name} {fld} %zu\\n", offsetof({name}, {fld}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    seen = 0
+    for row in out:
+        if not row:
+            continue
+        name, fld, val = row.split()
+        cls = structs[name]
+        want = C.sizeof(cls) if fld == "size" else getattr(cls, fld).offset
+        assert int(val) == want, (name, fld, int(val), want)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())

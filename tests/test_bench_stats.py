@@ -26,10 +26,6 @@ def test_logq_error_counts_only_comparable_points():
     assert e["logq_rel_max"] == pytest.approx(8e-4 / 4.0)
     assert e["points_over_1e-4"] == 1
     assert e["tw_abs_max"] == pytest.approx(3e-6)
-    cond = np.array([True, True, True, True, True, True, False])
-    e = bench.err_stats(qg, twg, sg, qo, two, so, cond=cond)
-    assert e["_cond_max"] == pytest.approx(5e-5)
-    assert e["_cond_excluded"] == 1
     assert 1e-6 / np.log10(2.0) <= e["logq_rel_p999"] <= 2e-4
 
 

@@ -1,0 +1,188 @@
+"""Closed forms on the GPU (through the C-ABI), in both arithmetic forms: Q = 2 on
+arcades over a polarity inversion line of the seed face, the rotated S0 of 3-D maps
+against the closed form of an oblique sheared field, and two voxels of one field
+line in a 3-D map (B . grad Q = 0 under the flux substitution of Eq. D+-3).
+
+Every case prints what it runs before touching the GPU, so a failing run names it.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Plane, cubic_grid
+
+from gpu_util import LOG10_2, TOL_LOGQ, compare_maps, to_np
+from test_oracle_pins import (_arcade, _div_integral, _line_lattice,
+                              _lines_through_two_layers, _sheared_oblique)
+
+pytestmark = pytest.mark.gpu
+
+F32X, F64 = 0, 1
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2208_12569_amd as m
+
+    m._lib.load()
+    return m
+
+
+def _dev(B):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(B)).cuda()
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_pil_arcade_q_is_two(fq, prec):
+    """B = (1, 0, -(x - x0)) on an FP64 cube: seeds 1e-3 ... 1e-8 from the polarity
+    inversion line x = x0 of the bottom face, on both sides. The far footpoint is
+    x2 = 2 x0 - x1 (met at the seed's own small angle) and Q = 2 exactly (Section 1,
+    Eq. Q+-). Q within the log10 Q bar, and the far footpoint within 1e-12 of the
+    closed form relative to the seed's distance from the line (Bn2 = x1 - x0 sets
+    Q through |Bn2/Bn0|)."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    x0 = 0.5 + 1e-4 * math.pi
+    B = _dev(_arcade(g, x0))
+    d = 7e-4
+    for dist in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        for sgn in (-1.0, 1.0):
+            xc = x0 + sgn * dist
+            pl = Plane((xc - d, 0.5 - d, 0.0), (1, 0, 0), (0, 1, 0), 3, 3, d, d)
+            _say(f"arcade seed {sgn * dist:+.0e} from the inversion line, precision {prec}")
+            r = fq.q2d(B, g, pl, fq.Params(precision=prec), want_lines=True)
+            torch.cuda.synchronize()
+            q = float(to_np(r["q"])[1, 1])
+            st = int(to_np(r["status"])[1, 1])
+            assert st == 0, (dist, st)
+            assert abs(math.log10(q) - LOG10_2) / LOG10_2 <= TOL_LOGQ, (sgn * dist, q)
+            L = {k: to_np(v) for k, v in r["lines"].items()}
+            c = 4  # the centre line; its far end is the end away from the seed
+            seed = pl.points()[c]
+            far = max((L["end_b"][c], L["end_f"][c]), key=lambda e: abs(e[0] - seed[0]))
+            err = abs(far[0] - (2 * x0 - xc))
+            assert err <= 1e-5 * dist, (sgn * dist, far, err)
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_rotated_s0_closed_form(fq, prec):
+    """3-D map of B = (1, 0.3, s (y - y0)) (x faces as S1, S2; Q = 2 + s^2): voxels
+    where |Bz/B| < 0.05 take S0 perpendicular to B with four extra lines
+    (Section 4), the others their z plane; one voxel has Bz = 0, where only the
+    rotated S0 gives Q. The map from the rotated seeds is quadratic, so central
+    differences are exact and delta can be large enough for FP32 positions."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    s, y0 = 0.5, 0.4
+    B = _dev(_sheared_oblique(g, s, y0))
+    dv = 2e-3
+    seen_rot = 0
+    for yc in (y0, y0 + 0.003, y0 - 0.02, y0 + 0.08, y0 - 0.12, y0 + 0.2):
+        vx = synth.Voxels((0.45 - dv, yc - dv, 0.5), (dv, dv, 0.01), (3, 3, 1))
+        _say(f"rotated S0 closed form at y - y0 = {yc - y0:+.3f}, precision {prec}")
+        r = fq.q3d(B, g, vx, fq.Params(precision=prec))
+        torch.cuda.synchronize()
+        q = float(to_np(r["q"])[0, 1, 1])
+        st = int(to_np(r["status"])[0, 1, 1])
+        rot = abs(s * (yc - y0)) < 0.05 * math.sqrt(1 + 0.09 + (s * (yc - y0)) ** 2)
+        assert bool(st & fq.ST_ROTATED) == rot, (yc, st)
+        assert (st & ~fq.ST_ROTATED) == 0, (yc, st)
+        lq = math.log10(2 + s * s)
+        assert abs(math.log10(q) - lq) / lq <= TOL_LOGQ, (yc, q)
+        seen_rot += rot
+    assert seen_rot >= 3
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_q3d_voxels_on_one_line(fq, prec):
+    """A 3-D map of a 4-charge field on a voxel lattice that puts two voxels of
+    different layers on one field line (Section 1, Eq. qline). Against the oracle on
+    the whole lattice (parity mask and tolerances as everywhere), and the two voxels
+    share Tw and length, with Q in the ratio exp(2 int div B/|B| ds) that the
+    interpolant's divergence along the line fixes (computed with scipy)."""
+    import torch
+
+    bad = oracle.FATAL | oracle.ORC_MIXEDFACE | oracle.ORC_EDGE | oracle.ORC_ONESIDED
+    rng = np.random.default_rng(11)
+    g = cubic_grid(33, 33, 33)
+    pos, qq = synth.draw_charges(rng, 4)
+    Bh = synth.charges_field(g, pos, qq)
+    opts = {"tol": 1e-12}
+    z0, z1, pairs = _lines_through_two_layers(oracle, Bh, g, 8, 12,
+                                              ((0.41, 0.47), (0.36, 0.61)), opts)
+    assert len(pairs) == 2
+    B = _dev(Bh)
+    for p0, p1 in pairs:
+        I, _ = _div_integral(Bh, g, p0, z1)
+        vx, a, b = _line_lattice(p0, p1, z0, z1, 2e-3)
+        _say(f"q3d lattice {vx.n} on the line from {p0}, precision {prec}")
+        # a tight bound: on this coarse 33^3 grid the default one (in grid spacings)
+        # leaves footpoint errors near the 1e-6 box-unit bar
+        r = fq.q3d(B, g, vx, fq.Params(precision=prec, tol_perp=1e-8), want_lines=True)
+        torch.cuda.synchronize()
+        o = oracle.q3d(Bh, g, vx, {"tol": 1e-10})
+        print(compare_maps(r, o, f"q3d-line-{prec}"))
+        q = to_np(r["q"]).ravel()
+        tw = to_np(r["tw"]).ravel()
+        ln = to_np(r["length"]).ravel()
+        st = to_np(r["status"]).astype(np.uint16).ravel()
+        assert not ((st[a] | st[b]) & bad)
+        assert abs(tw[a] - tw[b]) < 1e-5 and abs(ln[a] - ln[b]) < 1e-6
+        assert abs(math.log(q[a] / q[b]) - 2 * I) < 1.5e-3
+
+
+def test_fp32_unfinished_half_gets_its_twist_in_the_fp64_pass(fq):
+    """A half line that runs out of trial steps in the FP32 pass but not in FP64 (the
+    step budget set between the two passes' trial counts for that half, read from
+    the counters) is finished by the FP64 pass, with its twist: Tw finite, status
+    clear, and equal to the all-FP64 line's Tw."""
+    import torch
+
+    w = synth.config_c1(0)
+    B = _dev(w.field)
+    g = w.grid
+    rng = np.random.default_rng(3)
+    cand = np.c_[rng.uniform(0.3, 0.7, (64, 2)), np.zeros(64)]
+    chosen = None
+    for s in cand:
+        seed = torch.from_numpy(s[None, :].copy()).cuda()
+        c32 = torch.zeros(5, dtype=torch.int64, device="cuda")
+        call = torch.zeros(5, dtype=torch.int64, device="cuda")
+        _say(f"trial counts of the seed {s} in both passes")
+        fq.trace(B, g, seed, params=fq.Params(graze=-1.0, stats=c32))
+        fq.trace(B, g, seed, params=fq.Params(graze=1.0, stats=call))
+        torch.cuda.synchronize()
+        t32, t64 = int(c32[0]), int(call[0]) - int(c32[0])
+        if int(call[4]) == 1 and t32 > t64 + 2:
+            chosen = (seed, t64)
+            break
+    assert chosen is not None, "no seed needs more FP32 than FP64 trials"
+    seed, t64 = chosen
+    st = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say(f"budget {t64 + 1} trials: FP32 pass runs out, FP64 pass finishes")
+    r = fq.trace(B, g, seed, params=fq.Params(max_steps=t64 + 1, stats=st))
+    ref = fq.trace(B, g, seed, params=fq.Params(precision=F64))
+    torch.cuda.synchronize()
+    assert int(st[4]) == 1  # traced again in FP64
+    assert int(to_np(r["status"])[0]) == 0
+    tw = float(to_np(r["tw"])[0])
+    assert math.isfinite(tw)
+    assert abs(tw - float(to_np(ref["tw"])[0])) < 1e-7
