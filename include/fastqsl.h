@@ -260,6 +260,22 @@ int fastqsl_backward_recorded(const fq_field *f, const fq_plane *pl, const fq_pa
                               const double *dend_b, const double *dend_f, double *const gb[3],
                               void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------------
+ * fastqsl_q2d_static — fastqsl_q2d for callers that cannot allocate device memory
+ * (code under HIP graph capture that must not allocate, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments and results as fastqsl_q2d,
+ * without the workspace: the scratch is the library's own device array of
+ * fastqsl_static_scratch_bytes() (64 MiB), one per GPU, held from the library's
+ * load until the process ends. Calls whose fastqsl_q2d_workspace_size exceeds it
+ * return FQ_ENOMEM (use fastqsl_q2d with a caller workspace); invalid arguments
+ * return FQ_EINVAL. The call allocates nothing and clears the counters it uses
+ * itself; calls that overlap on one GPU (two streams or threads) share that
+ * GPU's array and race.
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_static_scratch_bytes(void);
+int fastqsl_q2d_static(const fq_field *fields, const fq_plane *planes, int njobs,
+                       const fq_params *p, const fq_map *maps, void *stream);
+
 /* Text of a return code (static storage). */
 const char *fastqsl_strerror(int code);
 

@@ -278,6 +278,27 @@ def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = Fals
     return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws)[0]
 
 
+def q2d_static(jobs: Sequence, params: Optional[Params] = None, outs: Optional[list] = None,
+               want_lines: bool = False, stream=None) -> list:
+    """fastqsl_q2d_static: the maps of q2d_batch with the library's own device
+    scratch (no workspace is allocated; outputs are, unless `outs` from
+    alloc_q2d_outputs is given). Raises if the jobs need more scratch than
+    fastqsl_static_scratch_bytes()."""
+    lib = _lib.load()
+    params = params or Params()
+    jobs = list(jobs)
+    if outs is None:
+        outs = alloc_q2d_outputs(jobs, want_lines)
+    f, pl, m, p = _batch_args(jobs, params, outs)
+    _lib.check(lib.fastqsl_q2d_static(f, pl, len(jobs), C.byref(p), m, _stream(stream)),
+               "fastqsl_q2d_static")
+    return outs
+
+
+def static_scratch_bytes() -> int:
+    return int(_lib.load().fastqsl_static_scratch_bytes())
+
+
 def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = False,
         stream=None, ws=None) -> dict:
     """Q, Tw and length at voxel centres (shape (nz, ny, nx) of the voxel grid)."""

@@ -76,6 +76,7 @@ EXPORTS = [
     "fastqsl_backward_workspace_size", "fastqsl_backward",
     "fastqsl_q2d_record", "fastqsl_backward_recorded",
     "fastqsl_strerror", "fastqsl_version",
+    "fastqsl_static_scratch_bytes", "fastqsl_q2d_static",
 ]
 
 _lib = None
@@ -122,6 +123,11 @@ def load():
     lib.fastqsl_q2d_record.restype = C.c_int
     lib.fastqsl_backward_recorded.argtypes = lib.fastqsl_backward.argtypes
     lib.fastqsl_backward_recorded.restype = C.c_int
+    lib.fastqsl_static_scratch_bytes.argtypes = []
+    lib.fastqsl_static_scratch_bytes.restype = C.c_size_t
+    lib.fastqsl_q2d_static.argtypes = [P(fq_field), P(fq_plane), C.c_int, P(fq_params), P(fq_map),
+                                       C.c_void_p]
+    lib.fastqsl_q2d_static.restype = C.c_int
     lib.fastqsl_strerror.argtypes = [C.c_int]
     lib.fastqsl_strerror.restype = C.c_char_p
     lib.fastqsl_version.argtypes = []

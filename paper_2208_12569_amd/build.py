@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libfastqsl.so")
 GATHER_LIB = os.path.join(HERE, "libfqgather.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "prep.hip", "trace.hip", "stencil.hip", "adjoint.hip"]
+SOURCES = ["api.cpp", "prep.hip", "trace.hip", "stencil.hip", "adjoint.hip", "static_ws.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
