@@ -26,4 +26,5 @@ from .oracle import (  # noqa: F401
     threads,
     q2d_points,
     q3d_points,
+    method2,
 )

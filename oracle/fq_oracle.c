@@ -204,15 +204,59 @@ static int in_box(const orc_field *f, const double r[3])
  * y = (x, y, z, Tw, l);  dy/ds = (sigma B/|B|, (curl B . B)/(4 pi |B|^2), 1)
  * ---------------------------------------------------------------------------- */
 
+/* State of a line: y = (x, y, z, Tw, l) for Method I, followed by the two tangent
+ * vectors U, V of Method II (Section 2.1, Eq. rb2): NY components in all. */
+#define NY 11
+
 typedef struct {
     const orc_field *f;
     int64_t c[3];
     int sigma;
     int want_tw;
     double bnull2; /* |B|^2 below this counts as a null */
+    int nq;        /* components integrated: 5 (Method I) or NY (Method II) */
+    int way;       /* Method II: 1 = node array of grad(B/B) (gb), 2 = offset differences */
+    const double *const *gb; /* way 1: the 9 planes d(B_i/B)/dx_j, plane 3 i + j */
 } line_ctx;
 
-static int rhs(const line_ctx *L, const double y[5], double dy[5])
+/* The unit vector B/|B| of the current cell's interpolant at r. */
+static int unit_b(const line_ctx *L, const double r[3], double b[3])
+{
+    double B[3];
+    orc_interp(L->f, L->f->b, L->c, r, B);
+    double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    if (!isfinite(bm)) return ORC_NONFINITE;
+    if (bm * bm <= L->bnull2) return ORC_NULLB;
+    for (int a = 0; a < 3; a++) b[a] = B[a] / bm;
+    return 0;
+}
+
+/* The Jacobian g[i][j] = d(B_i/B)/dx_j at r (Section 4, Eq. grad_B and the text
+ * around it): way 1 interpolates the node array (Eq. interp in the current cell);
+ * way 2 takes central differences of B/B at r +- 0.001 grid spacings along each
+ * axis, on the current cell's interpolant. */
+static int grad_b(const line_ctx *L, const double r[3], double g[3][3])
+{
+    if (L->way == 1) {
+        for (int i = 0; i < 3; i++) {
+            const double *const p[3] = {L->gb[3 * i], L->gb[3 * i + 1], L->gb[3 * i + 2]};
+            orc_interp(L->f, p, L->c, r, g[i]);
+        }
+        return 0;
+    }
+    for (int j = 0; j < 3; j++) {
+        double h = 1e-3 * L->f->spacing[j];
+        double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]}, bp[3], bm[3];
+        rp[j] += h;
+        rm[j] -= h;
+        int st;
+        if ((st = unit_b(L, rp, bp)) || (st = unit_b(L, rm, bm))) return st;
+        for (int i = 0; i < 3; i++) g[i][j] = (bp[i] - bm[i]) / (2.0 * h);
+    }
+    return 0;
+}
+
+static int rhs(const line_ctx *L, const double y[NY], double dy[NY])
 {
     double B[3];
     orc_interp(L->f, L->f->b, L->c, y, B);
@@ -230,39 +274,59 @@ static int rhs(const line_ctx *L, const double y[5], double dy[5])
         dy[3] = jb / (4.0 * M_PI * b2);
     }
     dy[4] = 1.0;
+    if (L->nq > 5) {
+        /* Eq. rb2: dU/ds = (U . grad)(B/B), the same for V, along the direction the
+         * half line runs (sigma) */
+        double g[3][3];
+        int st = grad_b(L, y, g);
+        if (st) return st;
+        for (int i = 0; i < 3; i++) {
+            double du = 0.0, dv = 0.0;
+            for (int j = 0; j < 3; j++) {
+                du += g[i][j] * y[5 + j];
+                dv += g[i][j] * y[8 + j];
+            }
+            dy[5 + i] = (double)L->sigma * du;
+            dy[8 + i] = (double)L->sigma * dv;
+        }
+        for (int q = 5; q < NY; q++)
+            if (!isfinite(dy[q])) return ORC_NONFINITE;
+    }
     return 0;
 }
 
 /* one classic RK4 step of length t */
-static int rk4(const line_ctx *L, const double y[5], double t, double out[5])
+static int rk4(const line_ctx *L, const double y[NY], double t, double out[NY])
 {
-    double k1[5], k2[5], k3[5], k4[5], z[5];
-    int st;
+    double k1[NY], k2[NY], k3[NY], k4[NY], z[NY];
+    int st, n = L->nq;
     if ((st = rhs(L, y, k1))) return st;
-    for (int q = 0; q < 5; q++) z[q] = y[q] + 0.5 * t * k1[q];
+    for (int q = 0; q < n; q++) z[q] = y[q] + 0.5 * t * k1[q];
     if ((st = rhs(L, z, k2))) return st;
-    for (int q = 0; q < 5; q++) z[q] = y[q] + 0.5 * t * k2[q];
+    for (int q = 0; q < n; q++) z[q] = y[q] + 0.5 * t * k2[q];
     if ((st = rhs(L, z, k3))) return st;
-    for (int q = 0; q < 5; q++) z[q] = y[q] + t * k3[q];
+    for (int q = 0; q < n; q++) z[q] = y[q] + t * k3[q];
     if ((st = rhs(L, z, k4))) return st;
-    for (int q = 0; q < 5; q++)
+    for (int q = 0; q < n; q++)
         out[q] = y[q] + t / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    for (int q = n; q < NY; q++) out[q] = y[q];
     return 0;
 }
 
 /* Step doubling: one step of t against two of t/2. The difference estimates the
  * error (divided by 2^4 - 1); Richardson extrapolation gives the returned state.
- * err is the position part in grid spacings. */
-static int rk4_doubled(const line_ctx *L, const double y[5], double t, double out[5],
+ * err is the position part in grid spacings; for Method II the tangent vectors'
+ * parts, relative to their size (at least 1), join it. */
+static int rk4_doubled(const line_ctx *L, const double y[NY], double t, double out[NY],
                        double *err)
 {
-    double one[5], half[5], two[5];
+    double one[NY], half[NY], two[NY];
     int st;
     if ((st = rk4(L, y, t, one))) return st;
     if ((st = rk4(L, y, 0.5 * t, half))) return st;
     if ((st = rk4(L, half, 0.5 * t, two))) return st;
     double e2 = 0.0;
-    for (int q = 0; q < 5; q++) {
+    for (int q = 0; q < NY; q++) {
         double d = (two[q] - one[q]) / 15.0;
         out[q] = two[q] + d;
         if (q < 3) {
@@ -270,6 +334,15 @@ static int rk4_doubled(const line_ctx *L, const double y[5], double t, double ou
             e2 += g * g;
         }
     }
+    if (L->nq > 5)
+        for (int v = 5; v < NY; v += 3) {
+            double m = sqrt(y[v] * y[v] + y[v + 1] * y[v + 1] + y[v + 2] * y[v + 2]);
+            if (m < 1.0) m = 1.0;
+            for (int q = v; q < v + 3; q++) {
+                double d = (two[q] - one[q]) / 15.0 / m;
+                e2 += d * d;
+            }
+        }
     *err = sqrt(e2);
     return 0;
 }
@@ -284,14 +357,14 @@ static int rk4_doubled(const line_ctx *L, const double y[5], double t, double ou
  * on |g| below a fixed height lets a line that grazes the plane at angle alpha land
  * up to height/alpha away from the crossing; near a polarity inversion line on a
  * box face that error reaches the seed's own distance from the inversion line.) */
-static int land(const line_ctx *L, const double y[5], int a, double plane, double t_hi,
-                double g_hi, double out[5], double *t_out)
+static int land(const line_ctx *L, const double y[NY], int a, double plane, double t_hi,
+                double g_hi, double out[NY], double *t_out)
 {
     double ta = 0.0, ga = y[a] - plane;
     double tb = t_hi, gb = g_hi;
     double err, t = t_hi;
     int side = 0, st;
-    double cur[5];
+    double cur[NY];
     memcpy(cur, out, sizeof cur);
     for (int it = 0; it < 400; it++) {
         t = (ta * gb - tb * ga) / (gb - ga);
@@ -328,10 +401,10 @@ static int inside_cell(const line_ctx *L, const double r[3], int skip)
 /* First parameter value in (0, t) at which the step y -> y1 (slopes dy0 at the
  * start) leaves the closed cell along an axis other than `skip`, judged at the RK4
  * half step and at 15 points of the cubic Hermite interpolant; 0 if none. */
-static double excursion(const line_ctx *L, const double y[5], const double dy0[5],
-                        const double y1[5], double t, int skip)
+static double excursion(const line_ctx *L, const double y[NY], const double dy0[NY],
+                        const double y1[NY], double t, int skip)
 {
-    double mid[5], dy1[5];
+    double mid[NY], dy1[NY];
     if (rk4(L, y, 0.5 * t, mid) == 0 && !inside_cell(L, mid, skip)) return 0.5 * t;
     if (rhs(L, y1, dy1)) return 0.0;
     for (int k = 1; k < 16; k++) {
@@ -353,22 +426,40 @@ typedef struct {
     double tw, len;
     int status;
     int64_t nsteps;
+    double U[3], V[3]; /* Method II: the tangent vectors at the end */
 } half_line;
 
-/* Trace one half line (direction sigma) from seed until it leaves the box. */
-static void trace_half(const orc_field *f, const double seed[3], int sigma, const orc_opts *o,
-                       double bnull2, half_line *res)
+/* Method II inputs of a half line: how grad(B/B) is taken and the tangent vectors
+ * at the seed. */
+typedef struct {
+    int way;
+    const double *const *gb;
+    double U0[3], V0[3];
+} m2_ctx;
+
+/* Trace one half line (direction sigma) from seed until it leaves the box; with m2,
+ * the tangent vectors of Method II ride along (Eq. rb2). */
+static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
+                           const orc_opts *o, double bnull2, const m2_ctx *m2, half_line *res)
 {
     line_ctx L;
     L.f = f;
     L.sigma = sigma;
     L.want_tw = o->want_tw;
     L.bnull2 = bnull2;
+    L.nq = m2 ? NY : 5;
+    L.way = m2 ? m2->way : 0;
+    L.gb = m2 ? m2->gb : NULL;
     double dmin = f->spacing[0];
     if (f->spacing[1] < dmin) dmin = f->spacing[1];
     if (f->spacing[2] < dmin) dmin = f->spacing[2];
 
-    double y[5] = {seed[0], seed[1], seed[2], 0.0, 0.0};
+    double y[NY] = {seed[0], seed[1], seed[2], 0.0, 0.0};
+    for (int a = 0; a < 3; a++) {
+        y[5 + a] = m2 ? m2->U0[a] : 0.0;
+        y[8 + a] = m2 ? m2->V0[a] : 0.0;
+        res->U[a] = res->V[a] = NAN;
+    }
     res->face = -1;
     res->status = 0;
     res->nsteps = 0;
@@ -390,7 +481,7 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
         }
         /* a point on a face of its cell, heading out through that face, moves to
          * the neighbouring cell; if there is none the line has left the box */
-        double dy[5];
+        double dy[NY];
         int st = rhs(&L, y, dy);
         if (st) {
             res->status = st;
@@ -414,11 +505,15 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
             res->bn = B[exit_face / 2];
             res->tw = y[3];
             res->len = y[4];
+            for (int a = 0; a < 3; a++) {
+                res->U[a] = y[5 + a];
+                res->V[a] = y[8 + a];
+            }
             return;
         }
 
         /* trial step within the current cell's polynomial */
-        double y1[5], err;
+        double y1[NY], err;
         if ((st = rk4_doubled(&L, y, h, y1, &err))) {
             res->status = st;
             return;
@@ -453,12 +548,12 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
         }
         /* the step leaves the cell: shorten it to end on the first face crossed
          * (ties go to the lower axis) */
-        double t_best = h, y_best[5];
+        double t_best = h, y_best[NY];
         int a_best = -1;
         for (int a = 0; a < 3; a++) {
             if (!out_axis[a]) continue;
             double plane = out_axis[a] > 0 ? face_hi(f, L.c, a) : face_lo(f, L.c, a);
-            double ya[5], ta;
+            double ya[NY], ta;
             memcpy(ya, y1, sizeof ya);
             if ((st = land(&L, y, a, plane, h, y1[a] - plane, ya, &ta))) {
                 res->status = st;
@@ -486,7 +581,7 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
                 else if (y_best[a] < face_lo(f, L.c, a) - slack) a_out = a, plane = face_lo(f, L.c, a);
             }
             if (a_out < 0) break;
-            double ya[5], ta;
+            double ya[NY], ta;
             memcpy(ya, y_best, sizeof ya);
             if ((st = land(&L, y, a_out, plane, t_best, y_best[a_out] - plane, ya, &ta))) {
                 res->status = st;
@@ -516,6 +611,12 @@ static void trace_half(const orc_field *f, const double seed[3], int sigma, cons
         memcpy(y, y_best, sizeof y);
         res->nsteps++;
     }
+}
+
+static void trace_half(const orc_field *f, const double seed[3], int sigma, const orc_opts *o,
+                       double bnull2, half_line *res)
+{
+    trace_half_gen(f, seed, sigma, o, bnull2, NULL, res);
 }
 
 /* in-face coordinates of an end point on face `face`: the two other axes, in
@@ -989,5 +1090,174 @@ int orc_q3d(const orc_field *f, const double origin[3], const double spacing[3],
         for (int64_t i = 0; i < n; i++) store_line(lines_out, i, &lines[i]);
     free(seeds);
     free(lines);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * Method II (Section 2.1, Eq. rb2 and Eq. q_scott)
+ * ---------------------------------------------------------------------------- */
+
+/* Components of the node array of grad(B/B) (Section 4, Eq. grad_B): plane 3 i + j
+ * holds d(B_i/B)/dx_j at every node, by the same second-order differences as the
+ * curl (central inside, one-sided on boundary nodes), applied to B/B. */
+static int grad_b_planes(const orc_field *f, double *planes[9])
+{
+    int64_t nn = f->n[0] * f->n[1] * f->n[2];
+    double *u[3];
+    for (int a = 0; a < 3; a++) {
+        u[a] = (double *)malloc((size_t)nn * sizeof(double));
+        if (!u[a]) {
+            for (int b = 0; b < a; b++) free(u[b]);
+            return -2;
+        }
+    }
+    for (int64_t q = 0; q < nn; q++) {
+        double bm = sqrt(f->b[0][q] * f->b[0][q] + f->b[1][q] * f->b[1][q] + f->b[2][q] * f->b[2][q]);
+        for (int a = 0; a < 3; a++) u[a][q] = bm > 0.0 ? f->b[a][q] / bm : 0.0;
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < f->n[2]; k++)
+        for (int64_t j = 0; j < f->n[1]; j++)
+            for (int64_t i = 0; i < f->n[0]; i++) {
+                int64_t q = node(f, i, j, k);
+                for (int c = 0; c < 3; c++)
+                    for (int ax = 0; ax < 3; ax++)
+                        planes[3 * c + ax][q] = deriv(f, u[c], ax, i, j, k);
+            }
+    for (int a = 0; a < 3; a++) free(u[a]);
+    return 0;
+}
+
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* The two ends' tangent vectors moved onto their end planes along B:
+ * W~ = W - (W . n) / (B . n) B, with n the plane's normal. */
+static void project_along_b(const double W[3], const double n[3], const double B[3], double out[3])
+{
+    double s = dot3(W, n) / dot3(B, n);
+    for (int a = 0; a < 3; a++) out[a] = W[a] - s * B[a];
+}
+
+/* Eq. q_scott's numerator for projected tangent vectors (U1, V1) and (U2, V2). */
+static double scott_num(const double U1[3], const double V1[3], const double U2[3],
+                        const double V2[3])
+{
+    return dot3(U1, U1) * dot3(V2, V2) + dot3(U2, U2) * dot3(V1, V1) -
+           2.0 * dot3(U1, V1) * dot3(U2, V2);
+}
+
+int orc_method2(const orc_field *f, const double *seeds, int64_t n, int way, const orc_opts *o,
+                double *q, double *qperp, double *tw, double *len, uint16_t *status,
+                orc_lines *out)
+{
+    if (way != 1 && way != 2) return -1;
+    double *gp[9] = {NULL};
+    if (way == 1) {
+        int64_t nn = f->n[0] * f->n[1] * f->n[2];
+        for (int a = 0; a < 9; a++) {
+            gp[a] = (double *)malloc((size_t)nn * sizeof(double));
+            if (!gp[a]) {
+                for (int b = 0; b < a; b++) free(gp[b]);
+                return -2;
+            }
+        }
+        if (grad_b_planes(f, gp)) {
+            for (int a = 0; a < 9; a++) free(gp[a]);
+            return -2;
+        }
+    }
+    double bnull2 = 1e-60 * field_scale2(f);
+    set_threads(o);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        const double *r0 = seeds + 3 * i;
+        full_line r;
+        memset(&r, 0, sizeof r);
+        double qv = NAN, qp = NAN;
+        int flags = 0;
+        half_line hb, hf;
+        if (!in_box(f, r0)) {
+            flags = ORC_OUTSIDE;
+            hb.face = hf.face = -1;
+        } else {
+            /* S0 perpendicular to B at the seed (Section 4: Method II always takes the
+             * perpendicular S0), U and V orthonormal in it: U = e_a x b / |..| with e_a
+             * the axis least aligned with b, V = b x U */
+            int64_t c[3];
+            double B0[3];
+            locate(f, r0, c);
+            orc_interp(f, f->b, c, r0, B0);
+            double bm0 = sqrt(dot3(B0, B0));
+            m2_ctx m;
+            m.way = way;
+            m.gb = (const double *const *)gp;
+            if (!(bm0 * bm0 > bnull2)) {
+                flags = ORC_NULLB;
+                hb.face = hf.face = -1;
+            } else {
+                double bh[3] = {B0[0] / bm0, B0[1] / bm0, B0[2] / bm0};
+                int a = 0;
+                for (int k = 1; k < 3; k++)
+                    if (fabs(bh[k]) < fabs(bh[a])) a = k;
+                double ea[3] = {0, 0, 0};
+                ea[a] = 1.0;
+                cross(ea, bh, m.U0);
+                double um = sqrt(dot3(m.U0, m.U0));
+                for (int k = 0; k < 3; k++) m.U0[k] /= um;
+                cross(bh, m.U0, m.V0);
+                trace_half_gen(f, r0, -1, o, bnull2, &m, &hb);
+                trace_half_gen(f, r0, +1, o, bnull2, &m, &hf);
+                flags = hb.status | hf.status;
+                if (!(flags & FATAL_BITS)) {
+                    /* Eq. q_scott with S1, S2 the faces the line ends on ... */
+                    double n1[3] = {0, 0, 0}, n2[3] = {0, 0, 0}, B1[3], B2[3];
+                    int64_t c1[3], c2[3];
+                    n1[hb.face / 2] = 1.0;
+                    n2[hf.face / 2] = 1.0;
+                    locate(f, hb.end, c1);
+                    locate(f, hf.end, c2);
+                    orc_interp(f, f->b, c1, hb.end, B1);
+                    orc_interp(f, f->b, c2, hf.end, B2);
+                    double U1[3], V1[3], U2[3], V2[3];
+                    project_along_b(hb.U, n1, B1, U1);
+                    project_along_b(hb.V, n1, B1, V1);
+                    project_along_b(hf.U, n2, B2, U2);
+                    project_along_b(hf.V, n2, B2, V2);
+                    qv = scott_num(U1, V1, U2, V2) * fabs(dot3(B1, n1) * dot3(B2, n2)) /
+                         (bm0 * bm0);
+                    /* ... and with S1, S2 perpendicular to B at the ends (Q_perp) */
+                    double b1m = sqrt(dot3(B1, B1)), b2m = sqrt(dot3(B2, B2));
+                    double t1[3] = {B1[0] / b1m, B1[1] / b1m, B1[2] / b1m};
+                    double t2[3] = {B2[0] / b2m, B2[1] / b2m, B2[2] / b2m};
+                    project_along_b(hb.U, t1, B1, U1);
+                    project_along_b(hb.V, t1, B1, V1);
+                    project_along_b(hf.U, t2, B2, U2);
+                    project_along_b(hf.V, t2, B2, V2);
+                    qp = scott_num(U1, V1, U2, V2) * b1m * b2m / (bm0 * bm0);
+                }
+                if (near_edge(f, hb.face, hb.end, o->edge_eps) ||
+                    near_edge(f, hf.face, hf.end, o->edge_eps))
+                    flags |= ORC_EDGE;
+            }
+        }
+        if (q) q[i] = qv;
+        if (qperp) qperp[i] = qp;
+        int fatal = (flags & FATAL_BITS) != 0;
+        if (tw) tw[i] = (fatal || !o->want_tw) ? NAN : hb.tw + hf.tw;
+        if (len) len[i] = fatal ? NAN : hb.len + hf.len;
+        if (status) status[i] = (uint16_t)flags;
+        if (out) {
+            if (out->end_b) memcpy(out->end_b + 3 * i, fatal ? (double[3]){NAN, NAN, NAN} : hb.end, 3 * sizeof(double));
+            if (out->end_f) memcpy(out->end_f + 3 * i, fatal ? (double[3]){NAN, NAN, NAN} : hf.end, 3 * sizeof(double));
+            if (out->face_b) out->face_b[i] = (int8_t)(fatal ? -1 : hb.face);
+            if (out->face_f) out->face_f[i] = (int8_t)(fatal ? -1 : hf.face);
+            if (out->status) out->status[i] = (uint16_t)flags;
+        }
+        (void)r;
+    }
+    for (int a = 0; a < 9; a++) free(gp[a]);
     return 0;
 }

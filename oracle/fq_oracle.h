@@ -101,6 +101,18 @@ int orc_q3d_points(const orc_field *f, const double origin[3], const double spac
                    const int64_t nvox[3], const int64_t *pts, int64_t npts, const orc_opts *o,
                    double *q, double *tw, double *len, uint16_t *status, orc_lines *lines);
 
+/* Method II (Scott 2017; Section 2.1, Eq. rb2, Eq. q_scott) at n seeds: S0 is
+ * perpendicular to B at each seed with orthonormal U, V in it; r, U and V are
+ * traced both ways (dU/ds = (U . grad)(B/B)); q gets Q with S1, S2 the faces the
+ * line ends on and qperp gets Q_perp with S1, S2 perpendicular to B at the ends.
+ * way 1: grad(B/B) interpolated from node values by second-order differences
+ * (Eq. grad_B); way 2: central differences of B/B at +-0.001 grid spacings on the
+ * current cell's interpolant. Outputs (n entries; any may be NULL) as orc_q2d's;
+ * lines gets end_b/end_f/face_b/face_f/status. */
+int orc_method2(const orc_field *f, const double *seeds, int64_t n, int way, const orc_opts *o,
+                double *q, double *qperp, double *tw, double *len, uint16_t *status,
+                orc_lines *lines);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,9 @@ def _load():
         lib.orc_q3d.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
                                 C.c_int64 * 3, C.POINTER(_Opts), C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.POINTER(_Lines)]
+        lib.orc_method2.argtypes = [C.POINTER(_Field), C.c_void_p, C.c_int64, C.c_int,
+                                    C.POINTER(_Opts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.POINTER(_Lines)]
         lib.orc_default_opts.argtypes = [C.POINTER(_Opts)]
         lib.orc_threads.restype = C.c_int
         lib.orc_q2d_points.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
@@ -273,5 +276,27 @@ def q3d_points(B: np.ndarray, grid, vox, pts, opts: Optional[dict] = None) -> di
                             out["status"].ctypes.data, C.byref(s))
     if rc != 0:
         raise ValueError("orc_q3d_points: point index out of range")
+    out["lines"] = arrs
+    return out
+
+
+def method2(B: np.ndarray, grid, seeds: np.ndarray, way: int = 2,
+            opts: Optional[dict] = None) -> dict:
+    """Method II at every seed (n x 3): Q (S1, S2 = the faces the line ends on),
+    Q_perp (S1, S2 perpendicular to B), Tw, length, status and the ends. way 1 takes
+    grad(B/B) from node values, way 2 from offset differences."""
+    lib = _load()
+    h = _FieldHolder(B, grid, want_curl=(opts or {}).get("want_tw", 1) != 0)
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
+    n = seeds.shape[0]
+    out = {"q": np.full(n, np.nan), "qperp": np.full(n, np.nan), "tw": np.full(n, np.nan),
+           "len": np.full(n, np.nan), "status": np.zeros(n, np.uint16)}
+    s, arrs = _lines_struct(n)
+    o = _opts(opts)
+    rc = lib.orc_method2(C.byref(h.f), seeds.ctypes.data, n, int(way), C.byref(o),
+                         out["q"].ctypes.data, out["qperp"].ctypes.data, out["tw"].ctypes.data,
+                         out["len"].ctypes.data, out["status"].ctypes.data, C.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_method2 failed: {rc}")
     out["lines"] = arrs
     return out

@@ -729,3 +729,95 @@ def test_p9_solenoidal_interpolant_q_is_a_line_invariant(orc):
         assert abs(tw[a] - tw[b]) < 1e-10 and abs(ln[a] - ln[b]) < 1e-10
         assert abs(q[a] / q[b] - 1) < 1e-5, (q[a], q[b])
         assert q[a] > 2.05  # a non-trivial map
+
+
+# --------------------------------------------------------------------------------------
+# Method II (Section 2.1, Eq. rb2, Eq. q_scott): Q and Q_perp from tangent vectors
+# --------------------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("way", [1, 2])
+def test_m2_uniform_and_tilted_fields(orc, way):
+    """Uniform B: Q = Q_perp = 2. Tilted uniform B = (bx, 0, bz) from the bottom to
+    the side face x+: Q = r + 1/r with r = bz/bx (the projection effect of S1, S2 on
+    the faces), while Q_perp = 2: planes perpendicular to B remove it (Section 2.1)."""
+    g = cubic_grid(17, 17, 17)
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    r = orc.method2(B, g, np.array([[0.3, 0.4, 0.0], [0.5, 0.5, 0.5]]), way)
+    assert np.all(r["status"] == 0)
+    assert np.allclose(r["q"], 2.0, atol=1e-12) and np.allclose(r["qperp"], 2.0, atol=1e-12)
+    bx, bz = 2.0, 1.0
+    B = linear_field(g, np.zeros((3, 3)), [bx, 0, bz])
+    r = orc.method2(B, g, np.array([[0.7, 0.5, 0.0], [0.8, 0.3, 0.0]]), way)
+    assert np.all(r["lines"]["face_f"] == 1)
+    assert np.allclose(r["q"], bz / bx + bx / bz, rtol=1e-10)
+    assert np.allclose(r["qperp"], 2.0, rtol=1e-10)
+
+
+def test_m2_sheared_field(orc):
+    """B = (s (y - y0), 0, 1): the lines are straight, x2 = x1 + s (y1 - y0) L, so
+    Q = 2 + s^2 L^2 with S1, S2 on the faces; along a line U and V stay
+    perpendicular to B with dV/ds = s / (1 + a^2) e1 (a = s (y1 - y0), e1 the
+    in-plane unit vector perpendicular to B), which gives
+    Q_perp = 2 + s^2 L^2 / (1 + a^2) (Eq. rb2, Eq. q_scott). Way 2 differentiates
+    the exact interpolant (to its 1e-3-cell offsets); way 1's node differences of
+    B/B converge at second order in the grid spacing."""
+    s, y0 = 0.5, 0.5
+    ys = np.array([0.3, 0.5, 0.7])
+    seeds = np.c_[np.full(3, 0.45), ys, np.zeros(3)]
+    a = s * (ys - y0)
+    q_exp = 2 + s * s
+    qp_exp = 2 + s * s / (1 + a * a)
+    errs = []
+    for n in (17, 33):
+        g = cubic_grid(n, n, n)
+        B = linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1])
+        r2 = orc.method2(B, g, seeds, 2)
+        assert np.allclose(r2["q"], q_exp, rtol=1e-8)
+        assert np.allclose(r2["qperp"], qp_exp, rtol=1e-8)
+        r1 = orc.method2(B, g, seeds, 1)
+        errs.append(max(np.abs(r1["q"] / q_exp - 1).max(), np.abs(r1["qperp"] / qp_exp - 1).max()))
+    assert errs[1] < 2e-4 and 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_m2_hyperbolic_field(orc):
+    """B = (k(x - xc), -k(y - yc), 1): Q = 2 cosh(2 kL) (Eq. Q+-, Eq. q_scott); way 1
+    converges to it at second order in the grid spacing."""
+    kL = 2.0
+    seeds = np.array([[0.5 + 0.05 * math.exp(-kL), 0.52, 0.0]])
+    q_exp = 2 * math.cosh(2 * kL)
+    errs = []
+    for n in (17, 33, 65):
+        g = cubic_grid(n, n, n)
+        B = linear_field(g, [[kL, 0, 0], [0, -kL, 0], [0, 0, 0]], [-kL * 0.5, kL * 0.5, 1])
+        r = orc.method2(B, g, seeds, 2)
+        assert abs(r["q"][0] / q_exp - 1) < 1e-7
+        errs.append(abs(orc.method2(B, g, seeds, 1)["q"][0] / q_exp - 1))
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
+
+
+def test_m2_agrees_with_method1_at_the_same_seeds(orc):
+    """Both methods give the Q of one map (Eq. q_scott is equivalent to Eq. Q+-,
+    Section 2.1). At seeds on the bottom face Method I's S0 (the face) and Method II's
+    (perpendicular to B) pass through the same point, so the flux substitution
+    treats them alike, and Method II with offset differences matches Method I's
+    differences over delta = 1e-4 to their O(delta^2) and O(offset^2) errors. The
+    results do not depend on the sign of B."""
+    rng = np.random.default_rng(7)
+    g = cubic_grid(33, 33, 33)
+    pos, qq = synth.draw_charges(rng, 4)
+    B = synth.charges_field(g, pos, qq)
+    d = 1e-4
+    pts = np.c_[np.random.default_rng(1).uniform(0.2, 0.8, (30, 2)), np.zeros(30)]
+    qi = []
+    for p in pts:
+        r = orc.q2d(B, g, _plane(p, d), {"tol": 1e-12})
+        qi.append(r["q"][1, 1] if r["status"][1, 1] == 0 else np.nan)
+    qi = np.array(qi)
+    r2 = orc.method2(B, g, pts, 2, {"tol": 1e-12})
+    ok = np.isfinite(qi) & (r2["status"] == 0) & (qi < 1e3)
+    assert ok.sum() >= 25 and np.nanmax(qi[ok]) > 10
+    assert np.max(np.abs(r2["q"][ok] / qi[ok] - 1)) < 1e-3
+    rn = orc.method2(-B, g, pts, 2, {"tol": 1e-12})
+    assert np.allclose(rn["q"][ok], r2["q"][ok], rtol=1e-8)
+    assert np.allclose(rn["qperp"][ok], r2["qperp"][ok], rtol=1e-8)
