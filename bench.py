@@ -585,6 +585,8 @@ def main():
                     help="skip the runs of the same workload drawn with the two other seeds")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with one 1 GiB device copy (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--q3d-only", action="store_true",
+                    help="run only the 3-D map of the 512x512x256 cube (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this tracer runs on ONE GPU (no multi-GPU path is built); "
@@ -592,6 +594,19 @@ def main():
         sys.exit(2)
 
     import synth
+
+    if args.q3d_only:
+        r = run_q3d(args.seed, args.steps, args.warmup)
+        r.pop("_sample")
+        if args.calib_copy:
+            import torch
+
+            x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+            y = torch.empty_like(x)
+            y.copy_(x)
+            torch.cuda.synchronize()
+        print(json.dumps({"q3d": r}), flush=True)
+        return
 
     t = time.perf_counter()
     w = synth.config_c2(args.seed)
@@ -639,7 +654,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "trace_kernel<float, float, 1, true, false> (FP32 pass)",
+            "kernel": "trace_kernel<float, float, 1, true, false, 0, false> (FP32 pass)",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",

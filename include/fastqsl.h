@@ -54,6 +54,19 @@ extern "C" {
                           normal fields, and FP64 re-tracing of grazing lines */
 #define FQ_PREC_F64 1  /* every step in FP64 */
 
+/* integration schemes (Section 2.3) */
+#define FQ_SCHEME_RKF45 0  /* adaptive Fehlberg 4(5): error bound tol_perp |Bn0/B|^1.5 (Eq. tol) */
+#define FQ_SCHEME_RK4 1    /* classic RK4 with the fixed step max(step_perp |Bn0/B|, step_min) */
+#define FQ_SCHEME_RK4_38 2 /* Kutta's 3/8-rule RK4 with that fixed step */
+
+/* how Q is formed (Section 2.1) */
+#define FQ_METHOD_I 0  /* neighbour differences of the footpoint mapping through S0 (Eq. D+-2,
+                          Eq. D+-3, Eq. Q+-) */
+#define FQ_METHOD_II 1 /* tangent vectors U, V traced with the line from S0 perpendicular to B
+                          (Eq. rb2), Q and Q_perp by Eq. q_scott; grad(B/B) analytic on the
+                          cell's interpolant (the offset differences of Section 4 taken to a
+                          vanishing offset) */
+
 /* per-line / per-point status bits */
 #define FQ_ST_OK 0
 #define FQ_ST_OUTSIDE 1     /* seed outside the box: outputs NaN */
@@ -119,6 +132,15 @@ typedef struct {
     int64_t tape_steps; /* adjoint calls only: accepted steps per half line, on average over
                           the map, that the checkpoint pool has room for; default 2048. A half
                           line that finds the pool full gets FQ_ST_NOTAPE | FQ_ST_MAXSTEPS */
+    int32_t scheme;    /* FQ_SCHEME_RKF45 (default), FQ_SCHEME_RK4 or FQ_SCHEME_RK4_38. Every
+                          step stays in one grid cell and ends on the cell face it reaches, in
+                          every scheme; a fixed-step scheme takes its step (Eq. step) between
+                          faces. The adjoint calls take RKF45 only (else FQ_EUNSUPPORTED) */
+    int32_t method;    /* maps: FQ_METHOD_I (default) or FQ_METHOD_II. Method II traces one line
+                          per map point (no stencil neighbours, no rotated S0), with Eq. step /
+                          Eq. tol at |Bn0/B| = 1 (its S0 is perpendicular to B), RKF45 only, and
+                          in the F32X form without the FP64 passes (FP32 tracing; FP64 end
+                          fields and Q); the adjoint calls take Method I only */
 } fq_params;
 
 /* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,
@@ -159,6 +181,8 @@ typedef struct {
     double *length;     /* length of the point's line */
     uint16_t *status;   /* FQ_ST_* bits of the point */
     fq_lines lines;     /* the point's own line (NULL members skipped) */
+    double *qperp;      /* Method II only: Q_perp, with S1, S2 perpendicular to B at the
+                           ends (Section 2.1); left untouched by Method I */
 } fq_map;
 
 /* ---------------------------------------------------------------------------------

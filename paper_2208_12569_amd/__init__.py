@@ -21,6 +21,11 @@ from . import _lib
 from ._lib import (  # noqa: F401
     FQ_PREC_F32X,
     FQ_PREC_F64,
+    FQ_METHOD_I,
+    FQ_METHOD_II,
+    FQ_SCHEME_RK4,
+    FQ_SCHEME_RK4_38,
+    FQ_SCHEME_RKF45,
     ST_EDGE,
     ST_FATAL,
     ST_MAXSTEPS,
@@ -51,6 +56,8 @@ class Params:
     graze: float = 0.0
     qfix: float = 0.0
     tape_steps: int = 0  # adjoint calls: checkpoint pool room in accepted steps per half line
+    scheme: int = FQ_SCHEME_RKF45
+    method: int = FQ_METHOD_I  # maps: FQ_METHOD_II adds Q_perp ("qperp")
     stats: object = None  # optional CUDA int64 tensor of 5 counters (added to)
     events: object = None  # optional ctypes array of 4 hipEvent_t handles
 
@@ -69,6 +76,8 @@ class Params:
         p.graze = float(self.graze)
         p.qfix = float(self.qfix)
         p.tape_steps = int(self.tape_steps)
+        p.scheme = int(self.scheme)
+        p.method = int(self.method)
         p.stats = self.stats.data_ptr() if self.stats is not None else None
         p.events = C.cast(self.events, C.c_void_p) if self.events is not None else None
         return p
@@ -185,7 +194,7 @@ def trace(B, grid, seeds, normal=(0.0, 0.0, 1.0), params: Optional[Params] = Non
     return out
 
 
-def _alloc_map(npts: int, shape, device, want_lines: bool):
+def _alloc_map(npts: int, shape, device, want_lines: bool, qperp: bool = False):
     torch = _torch()
     m = {"q": torch.empty(shape, dtype=torch.float64, device=device),
          "tw": torch.empty(shape, dtype=torch.float64, device=device),
@@ -196,6 +205,9 @@ def _alloc_map(npts: int, shape, device, want_lines: bool):
     s.tw = m["tw"].data_ptr()
     s.length = m["length"].data_ptr()
     s.status = m["status"].data_ptr()
+    if qperp:
+        m["qperp"] = torch.empty(shape, dtype=torch.float64, device=device)
+        s.qperp = m["qperp"].data_ptr()
     if want_lines:
         m["lines"] = _alloc_lines(npts, device)
         s.lines = _lines_struct(m["lines"])
@@ -218,6 +230,8 @@ def _batch_args(jobs, params: Params, outs: list):
         s.status = m["status"].data_ptr()
         if "lines" in m:
             s.lines = _lines_struct(m["lines"])
+        if "qperp" in m:
+            s.qperp = m["qperp"].data_ptr()
         maps[j] = s
     return fields, planes, maps, params.c()
 
@@ -239,11 +253,12 @@ def q2d_workspace_size(jobs: Sequence, params: Optional[Params] = None) -> int:
     return int(need)
 
 
-def alloc_q2d_outputs(jobs: Sequence, want_lines: bool = False) -> list:
-    """Output maps for q2d_batch_into (one dict of CUDA tensors per job)."""
+def alloc_q2d_outputs(jobs: Sequence, want_lines: bool = False, qperp: bool = False) -> list:
+    """Output maps for q2d_batch_into (one dict of CUDA tensors per job; with qperp,
+    a Q_perp map too, which Method II fills)."""
     outs = []
     for B, grid, pl in jobs:
-        m, _ = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines)
+        m, _ = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines, qperp)
         outs.append(m)
     return outs
 
@@ -265,7 +280,7 @@ def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool 
     params = params or Params()
     need = q2d_workspace_size(jobs, params)
     w = _workspace(need, jobs[0][0].device, ws)
-    outs = alloc_q2d_outputs(jobs, want_lines)
+    outs = alloc_q2d_outputs(jobs, want_lines, params.method == FQ_METHOD_II)
     q2d_batch_into(jobs, outs, w, params, stream)
     for m in outs:
         m["_ws"] = w
@@ -307,7 +322,8 @@ def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = Fal
     f = _field(B, grid)
     v = _voxels(voxels)
     nx, ny, nz = (int(x) for x in voxels.n)
-    m, s = _alloc_map(nx * ny * nz, (nz, ny, nx), B.device, want_lines)
+    m, s = _alloc_map(nx * ny * nz, (nz, ny, nx), B.device, want_lines,
+                      params.method == FQ_METHOD_II)
     p = params.c()
     need = lib.fastqsl_q3d_workspace_size(C.byref(f), C.byref(v), C.byref(p))
     if need == 0:

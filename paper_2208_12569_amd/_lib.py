@@ -21,6 +21,11 @@ FQ_DT_F32 = 0
 FQ_DT_F64 = 1
 FQ_PREC_F32X = 0
 FQ_PREC_F64 = 1
+FQ_SCHEME_RKF45 = 0
+FQ_SCHEME_RK4 = 1
+FQ_SCHEME_RK4_38 = 2
+FQ_METHOD_I = 0
+FQ_METHOD_II = 1
 
 ST_OK = 0
 ST_OUTSIDE = 1
@@ -45,7 +50,8 @@ class fq_params(C.Structure):
                 ("tol_floor", C.c_double), ("edge_eps", C.c_double), ("max_steps", C.c_int64),
                 ("precision", C.c_int32), ("want_tw", C.c_int32), ("block", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("graze", C.c_double), ("stats", C.c_void_p),
-                ("events", C.c_void_p), ("qfix", C.c_double), ("tape_steps", C.c_int64)]
+                ("events", C.c_void_p), ("qfix", C.c_double), ("tape_steps", C.c_int64),
+                ("scheme", C.c_int32), ("method", C.c_int32)]
 
 
 class fq_plane(C.Structure):
@@ -66,7 +72,7 @@ class fq_lines(C.Structure):
 
 class fq_map(C.Structure):
     _fields_ = [("q", C.c_void_p), ("tw", C.c_void_p), ("length", C.c_void_p),
-                ("status", C.c_void_p), ("lines", fq_lines)]
+                ("status", C.c_void_p), ("lines", fq_lines), ("qperp", C.c_void_p)]
 
 
 EXPORTS = [

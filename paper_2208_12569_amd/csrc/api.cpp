@@ -120,6 +120,8 @@ int resolve_params(const fq_params *in, fq_params &p)
     if (p.graze == 0) p.graze = 0.05;
     if (!isfinite(p.qfix)) return FQ_EINVAL;
     if (p.qfix == 0) p.qfix = 300.0;
+    if (p.scheme < FQ_SCHEME_RKF45 || p.scheme > FQ_SCHEME_RK4_38) return FQ_EINVAL;
+    if (p.method != FQ_METHOD_I && p.method != FQ_METHOD_II) return FQ_EINVAL;
     if (p.tape_steps < 0) return FQ_EINVAL;
     if (p.tape_steps == 0) p.tape_steps = 2048;
     if (in == nullptr) p.want_tw = 1;
@@ -142,6 +144,7 @@ bool plane_on_face(const fq_plane &pl, const fq_field &f)
 
 struct SpecWs {
     size_t nodes, bmax, end, tw, len, face, st;
+    size_t uv;  // Method II: tangent vectors at the half lines' ends
     size_t tile_order, tile_bucket, tile_counts;  // plane jobs
     size_t nodes64;  // FP64 node records for the FP64 pass (FP64 grids only)
     size_t rot_index, rot, rot_count, r_end, r_tw, r_len, r_face, r_st;
@@ -157,6 +160,7 @@ HalfRecs recs_at(char *ws, size_t end, size_t tw, size_t len, size_t face, size_
     r.len = (double *)(ws + len);
     r.face = (int8_t *)(ws + face);
     r.st = (uint16_t *)(ws + st);
+    r.uv = nullptr;
     return r;
 }
 
@@ -236,6 +240,15 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
 {
     const int ns = (int)specs.size();
     const size_t tsz = P.precision == FQ_PREC_F64 ? 8 : 4;
+    // launches are checked with hipGetLastError: an error that an earlier, unrelated
+    // HIP call of the caller left behind is not this call's (a fault still shows, as
+    // the sticky error every later call returns)
+    if (!dry) (void)hipGetLastError();
+    // Method II: maps only (a list of seeds traces plain lines), RKF45, no adjoint
+    bool m2 = P.method == FQ_METHOD_II;
+    for (int i = 0; i < ns; i++)
+        if (specs[i].kind == SPEC_LIST) m2 = false;
+    if (m2 && (P.scheme != FQ_SCHEME_RKF45 || bwd)) return FQ_EUNSUPPORTED;
     Carve cv;
     // queue counters: +0 the tracer (u64, u32 spare), +64 the reverse pass, +128 the
     // checkpoint pool, +192 the FP64 pass over half lines that need their twist
@@ -257,7 +270,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             w.tile_bucket = cv.take((size_t)ntiles * sizeof(int32_t));
             w.tile_counts = cv.take(256 * sizeof(uint32_t));
         }
-        w.rotate = (s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f));
+        if (m2) w.uv = cv.take((size_t)(2 * w.nlines) * 6 * sizeof(double));
+        w.rotate = !m2 && ((s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f)));
         if (w.rotate) {
             nrot++;
             w.rot_index = cv.take((size_t)w.nlines * sizeof(int32_t));
@@ -349,6 +363,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         set_map_geometry(s, m);
         m.edge_eps = P.edge_eps;
         m.rec = recs_at(ws, w.end, w.tw, w.len, w.face, w.st);
+        if (m2) m.rec.uv = (double *)(ws + w.uv);
         m.nlines = w.nlines;
         if (s.kind != SPEC_LIST && s.map) m.out = *s.map;
         if (s.kind == SPEC_LIST && s.lines) m.out.lines = *s.lines;
@@ -381,6 +396,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         }
         J.nlines = w.nlines;
         J.rec = recs_at(ws, w.end, w.tw, w.len, w.face, w.st);
+        if (m2) J.rec.uv = (double *)(ws + w.uv);
         for (int a = 0; a < 3; a++) {
             J.planes.b[a] = s.f->b[a];
             J.planes.n[a] = (int32_t)s.f->n[a];
@@ -472,6 +488,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.step_perp = P.step_perp;
     tp.step_min = P.step_min;
     tp.tol_floor = P.tol_floor;
+    tp.scheme = P.scheme;
+    tp.method = m2 ? FQ_METHOD_II : FQ_METHOD_I;
     tp.max_steps = P.max_steps;
     tp.want_tw = P.want_tw;
     tp.njobs = njobs;
@@ -503,8 +521,12 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                 MapJob mq = maps[i];  // Q only: the final pass writes every output
                 memset(&mq.out, 0, sizeof mq.out);
                 mq.out.q = maps[i].out.q;
-                FQ_TRY(launch_stencil(mq, stream));
+                FQ_TRY(m2 ? launch_m2_map(mq, stream) : launch_stencil(mq, stream));
             }
+        // Method I keeps the FP32 pass's twist and re-traces positions only, then the
+        // half lines that pass could not finish with the twist (split lists); Method
+        // II has no positions-only tracer and re-traces everything in one list
+        const bool split = P.want_tw && !m2;
         FixEntry *list = (FixEntry *)(ws + off_list);
         uint32_t *lcount = (uint32_t *)(ws + off_lcount);
         FQ_TRY(launch_fill_u32(lcount, 2, 0u, stream));
@@ -515,7 +537,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             const int sp = j < ns ? j : 0;
             const double *qmap = (qsel && specs[sp].kind != SPEC_LIST) ? maps[sp].out.q : nullptr;
             FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, qmap, P.qfix, list, lcount,
-                                lcount + 1, 2 * all_lines, stream));
+                                lcount + 1, 2 * all_lines, split, !m2, stream));
         }
         const TraceJob *fix_jobs = jobs_dev;
         if (fix_store == FQ_DT_F64) {
@@ -543,9 +565,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         if (ev && ev[2]) FQ_TRY(hipEventRecord(ev[2], stream));
         // positions only: the twist integral is not sensitive to the end angle, so the
         // FP32 pass's Tw is kept and the latency-bound FP64 pass skips the curl
-        FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, P.want_tw ? 2 : 0, fix_jobs, fp, counter, P.block,
+        const int fix_twm = !P.want_tw ? 0 : (split ? 2 : 1);
+        FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, fix_twm, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
-        if (P.want_tw) {
+        if (split) {
             // half lines the FP32 pass could not finish have no twist yet: trace those
             // (usually none) with the twist integrand, on a queue counter of their own
             TraceParams ft = fp;
@@ -595,6 +618,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     for (int i = 0; i < ns; i++) {
         if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));
+        else if (m2) FQ_TRY(launch_m2_map(maps[i], stream));
         else FQ_TRY(launch_stencil(maps[i], stream));
     }
 #undef FQ_TRY
@@ -645,7 +669,8 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
 {
     int rc = resolve_params(p, P);
     if (rc) return rc;
-    if (P.precision != FQ_PREC_F64) return FQ_EUNSUPPORTED;
+    if (P.precision != FQ_PREC_F64 || P.scheme != FQ_SCHEME_RKF45 || P.method != FQ_METHOD_I)
+        return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;
     if (!plane_on_face(*pl, *f)) return FQ_EUNSUPPORTED;

@@ -33,6 +33,7 @@ struct HalfRecs {
     double *len;   // 2 * nlines
     int8_t *face;  // 2 * nlines
     uint16_t *st;  // 2 * nlines
+    double *uv;    // Method II: 2 * nlines * 6, the tangent vectors U, V at the end (else NULL)
 };
 
 // One independent tracing job: a prepared field plus a seed set.
@@ -110,7 +111,9 @@ struct TraceParams {
     const uint32_t *list_count;
     int64_t list_cap;
     int32_t list_rev;              // list mode: entry k sits at list[list_cap - 1 - k]
-    int32_t pad3;
+    int32_t scheme;                // integration scheme (FQ_SCHEME_*)
+    int32_t method;                // FQ_METHOD_I or FQ_METHOD_II (tangent vectors carried)
+    int32_t pad4;
     // adjoint forward pass (FP64, single job): checkpoints every `seg` accepted steps
     Ckpt *tape;                    // checkpoint pool of pool_cap entries
     unsigned long long *pool_ctr;  // next free pool slot
@@ -162,14 +165,14 @@ hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_
 // counts (256), order (tiles) are workspace arrays.
 hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *bucket, uint32_t *counts,
                              int32_t *order, hipStream_t s);
-// Lists the half lines of job `job` that the FP64 pass traces again: positions only
-// at list[0, *count) and, for half lines the FP32 pass could not finish (whose twist
-// is then missing too), with the twist at list[cap - 1 - k] for k < *count_tw.
+// Lists the half lines of job `job` that the FP64 pass traces again at
+// list[0, *count) and, with split, the half lines the FP32 pass could not finish
+// (whose twist is then missing too) apart at list[cap - 1 - k] for k < *count_tw.
 // qmap: the job's map after the FP32 pass (the map of the job's main points for a
-// rotated-S0 job), or NULL.
+// rotated-S0 job), or NULL. seed_check: also list lines whose seed is grazing.
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr, FixEntry *list, uint32_t *count,
-                        uint32_t *count_tw, int64_t cap, hipStream_t s);
+                        uint32_t *count_tw, int64_t cap, int split, int seed_check, hipStream_t s);
 
 // Map assembly (Q stencil) of one layer-structured map.
 struct MapJob {
@@ -211,6 +214,8 @@ constexpr int64_t kBwdSlots = 32768;  // lanes of the reverse kernel
 hipError_t launch_classify(const MapJob &m, int32_t *rot_index, RotEntry *rot,
                            uint32_t *rot_count, int64_t rot_capacity, hipStream_t s);
 hipError_t launch_stencil(const MapJob &m, hipStream_t s);
+// Method II: Q and Q_perp of every point from its own line's tangent vectors.
+hipError_t launch_m2_map(const MapJob &m, hipStream_t s);
 hipError_t launch_lines_out(const MapJob &m, const double *seeds_list, hipStream_t s);
 
 }  // namespace fq

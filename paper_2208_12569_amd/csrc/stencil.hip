@@ -226,6 +226,88 @@ __global__ __launch_bounds__(256) void stencil_kernel(MapJob m)
     }
 }
 
+// Method II (Section 2.1, Eq. q_scott): the tangent vectors at each end, moved onto
+// the end's plane along B, W~ = W - (W . n) / (B . n) B, give
+// Q = (U1~^2 V2~^2 + U2~^2 V1~^2 - 2 (U1~ . V1~)(U2~ . V2~)) |Bn1 Bn2| / Bn0^2 with S1, S2
+// the faces the line ends on, and Q_perp with n = B/|B| at each end (planes
+// perpendicular to B, Bn = |B|). S0 is perpendicular to B at the seed: Bn0 = |B0|.
+__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ __forceinline__ void along_b(const double W[3], const double n[3], const double B[3],
+                                        double o[3])
+{
+    const double t = dot3(W, n) / dot3(B, n);
+    for (int a = 0; a < 3; a++) o[a] = W[a] - t * B[a];
+}
+
+__device__ __forceinline__ double scott(const double U1[3], const double V1[3], const double U2[3],
+                                        const double V2[3])
+{
+    return dot3(U1, U1) * dot3(V2, V2) + dot3(U2, U2) * dot3(V1, V1) -
+           2.0 * dot3(U1, V1) * dot3(U2, V2);
+}
+
+__global__ __launch_bounds__(256) void m2_map_kernel(MapJob m)
+{
+    const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = pt / lay, r2 = pt - k * lay, j = r2 / m.nu, i = r2 - j * m.nu;
+        double r0[3];
+        point_pos(m, i, j, k, r0);
+        const int64_t hb = pt, hf = m.nlines + pt;
+        uint16_t st = m.rec.st[hb] | m.rec.st[hf];
+        const int fb = m.rec.face[hb], ff = m.rec.face[hf];
+        double eb[3], ef[3];
+        for (int a = 0; a < 3; a++) {
+            eb[a] = m.rec.end[3 * hb + a];
+            ef[a] = m.rec.end[3 * hf + a];
+        }
+        if (edge_end(m, fb, eb) || edge_end(m, ff, ef)) st |= FQ_ST_EDGE;
+        double q = NAN, qp = NAN, tw = NAN, len = NAN;
+        if (!(st & kFatal)) {
+            tw = m.rec.tw[hb] + m.rec.tw[hf];
+            len = m.rec.len[hb] + m.rec.len[hf];
+            const double *w1 = m.rec.uv + 6 * hb, *w2 = m.rec.uv + 6 * hf;
+            const double U1[3] = {w1[0], w1[1], w1[2]}, V1[3] = {w1[3], w1[4], w1[5]};
+            const double U2[3] = {w2[0], w2[1], w2[2]}, V2[3] = {w2[3], w2[4], w2[5]};
+            double B0[3], B1[3], B2[3];
+            field64(m, r0, B0);
+            field64(m, eb, B1);
+            field64(m, ef, B2);
+            const double b00 = dot3(B0, B0);
+            double n1[3] = {0, 0, 0}, n2[3] = {0, 0, 0}, u1[3], v1[3], u2[3], v2[3];
+            n1[fb >> 1] = 1.0;
+            n2[ff >> 1] = 1.0;
+            along_b(U1, n1, B1, u1);
+            along_b(V1, n1, B1, v1);
+            along_b(U2, n2, B2, u2);
+            along_b(V2, n2, B2, v2);
+            q = scott(u1, v1, u2, v2) * fabs(comp3(B1, fb >> 1) * comp3(B2, ff >> 1)) / b00;
+            const double m1 = sqrt(dot3(B1, B1)), m2 = sqrt(dot3(B2, B2));
+            const double t1[3] = {B1[0] / m1, B1[1] / m1, B1[2] / m1};
+            const double t2[3] = {B2[0] / m2, B2[1] / m2, B2[2] / m2};
+            along_b(U1, t1, B1, u1);
+            along_b(V1, t1, B1, v1);
+            along_b(U2, t2, B2, u2);
+            along_b(V2, t2, B2, v2);
+            qp = scott(u1, v1, u2, v2) * m1 * m2 / b00;
+        }
+        if (m.out.q) m.out.q[pt] = q;
+        if (m.out.qperp) m.out.qperp[pt] = qp;
+        if (m.out.tw) m.out.tw[pt] = tw;
+        if (m.out.length) m.out.length[pt] = len;
+        if (m.out.status) m.out.status[pt] = st;
+        const fq_lines &o = m.out.lines;
+        if (o.end_b || o.end_f || o.face_b || o.face_f || o.bn_b || o.bn_f || o.bn0 || o.tw ||
+            o.length || o.status)
+            write_line(m, o, pt, r0);
+    }
+}
+
 __global__ void lines_kernel(MapJob m, const double *seeds)
 {
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < m.nlines;
@@ -258,6 +340,13 @@ hipError_t launch_stencil(const MapJob &m, hipStream_t s)
 {
     const int64_t np = m.nu * m.nv * m.nlayers;
     hipLaunchKernelGGL(stencil_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2_map(const MapJob &m, hipStream_t s)
+{
+    const int64_t np = m.nu * m.nv * m.nlayers;
+    hipLaunchKernelGGL(m2_map_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
 

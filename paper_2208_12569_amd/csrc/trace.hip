@@ -72,8 +72,11 @@ template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 
 // (the FP64 re-trace, which keeps the twist of the first pass).
 // The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
 // (the latency of cell fetches is then hidden by more waves).
-template <typename T, typename S, int TWM, bool UNI, bool TAPE>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
+// SCH: the integration scheme (Scheme in trace_core.h); the adjoint's forward pass
+// (TAPE) uses RKF45 only. M2: Method II, the tangent vectors U, V ride along (their
+// end values go to the records' uv array).
+template <typename T, typename S, int TWM, bool UNI, bool TAPE, int SCH = SCH_RKF45, bool M2 = false>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
 {
@@ -116,6 +119,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
         K.bnull2 = (T)((double)N::null_rel * (double)(*J0.bmax2));
     }
     T cb[3][8], cj[3][8];
+    Tan<T> tn;  // Method II
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
     int acc_half = 0, nck = 0;  // TAPE: accepted steps and checkpoints of the half line
     int last_ck = -1;           // TAPE: pool slot of the last checkpoint
@@ -238,11 +242,38 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
                                      (L.c1 == 0 && L.p1 == T(0)) || (L.c1 == K.ny - 2 && L.p1 == T(1)) ||
                                      (L.c2 == 0 && L.p2 == T(0)) || (L.c2 == K.nz - 2 && L.p2 == T(1));
                 const float amin = on_face ? 1e-9f : 0.05f;
-                float ang = (J.kind == SEED_ROTATED) ? 1.0f : fabsf(bn) * Num<float>::rsq(b2);
+                // Method II's S0 is perpendicular to B: no angle scaling
+                float ang = (J.kind == SEED_ROTATED || M2) ? 1.0f : fabsf(bn) * Num<float>::rsq(b2);
                 if (!(ang >= amin)) ang = amin;  // also catches NaN
                 if (ang > 1.0f) ang = 1.0f;
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
-                L.tol = (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
+                // a fixed-step scheme keeps its step where RKF45 keeps its bound
+                L.tol = SCH != SCH_RKF45 ? L.h : (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
+                if constexpr (M2) {
+                    // S0 perpendicular to B at the seed, U and V orthonormal in it:
+                    // U = e_a x b / |..| with e_a the axis least aligned with b, V = b x U
+                    // (physical units), held in local grid units
+                    using N = Num<T>;
+                    const T Bx = poly<T>(cb[0], L.p0, L.p1, L.p2), By = poly<T>(cb[1], L.p0, L.p1, L.p2),
+                            Bz = poly<T>(cb[2], L.p0, L.p1, L.p2);
+                    const T inv = N::rsq(N::fma_(Bx, Bx, N::fma_(By, By, Bz * Bz)));
+                    const T b[3] = {Bx * inv, By * inv, Bz * inv};
+                    int a = 0;
+                    if (fabs(b[1]) < fabs(b[a])) a = 1;
+                    if (fabs(b[2]) < fabs(b[a])) a = 2;
+                    // e_a x b
+                    T u[3] = {a == 0 ? T(0) : (a == 1 ? b[2] : -b[1]),
+                              a == 0 ? -b[2] : (a == 1 ? T(0) : b[0]),
+                              a == 0 ? b[1] : (a == 1 ? -b[0] : T(0))};
+                    const T iu = N::rsq(N::fma_(u[0], u[0], N::fma_(u[1], u[1], u[2] * u[2])));
+                    for (int q = 0; q < 3; q++) u[q] *= iu;
+                    const T v[3] = {b[1] * u[2] - b[2] * u[1], b[2] * u[0] - b[0] * u[2],
+                                    b[0] * u[1] - b[1] * u[0]};
+                    for (int q = 0; q < 3; q++) {
+                        tn.u[q] = u[q] * (T)J.inv_spacing[q];
+                        tn.v[q] = v[q] * (T)J.inv_spacing[q];
+                    }
+                }
                 if (TAPE) {
                     if (store_ckpt<T, TWM, UNI, TAPE>(tp, last_ck, L)) nck++;
                     else fin_st = FQ_ST_MAXSTEPS | FQ_ST_NOTAPE;  // no checkpoint space
@@ -254,7 +285,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
         if (jb >= 0 && fin_st < 0) {
             n_trial++;
             const unsigned acc_before = n_acc;
-            lane_iterate<T, TW>(L, cb, cj, K, fin_st, fin_face, need_load, n_acc);
+            lane_iterate<T, TW, NoEvents, SCH, M2>(L, cb, cj, K, fin_st, fin_face, need_load, n_acc,
+                                                   NoEvents(), &tn);
             if (TAPE && n_acc != acc_before) {
                 acc_half++;
                 if (fin_st < 0 && acc_half % tp.seg == 0) {
@@ -295,6 +327,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
             gptr(J.rec.len)[rec] = bad ? NAN : L.len * J.dref;
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
+            if constexpr (M2) {
+                FQ_GLOBAL double *uv = gptr(J.rec.uv) + 6 * rec;
+                for (int q = 0; q < 3; q++) {
+                    uv[q] = bad ? NAN : (double)tn.u[q] * J.spacing[q];
+                    uv[3 + q] = bad ? NAN : (double)tn.v[q] * J.spacing[q];
+                }
+            }
             if (TAPE) {
                 gptr(tp.tape_last)[rec] = last_ck;
                 gptr(tp.tape_n)[rec] = nck;
@@ -330,12 +369,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI) ? 3 : 1) v
 // pass gives: one point per line of a plane or voxel job; for the four lines of a
 // rotated-S0 entry, the entry's point) has Q above qthr: the map stretches a line's
 // rounding error by about sqrt(Q). Half lines the FP32 pass could not finish have no
-// twist either: they go to the second list (from the top of the array down), which
-// is traced with the twist integrand.
+// twist either: with split they go to the second list (from the top of the array
+// down), which is traced with the twist integrand after a positions-only pass over
+// the first; without it they join the first list. seed_check: the seed's angle with
+// S0 is tested (Method II's S0 is perpendicular to B and has no such test).
 __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double thr,
                              const double *__restrict__ qmap, double qthr,
                              FixEntry *__restrict__ list, uint32_t *__restrict__ count,
-                             uint32_t *__restrict__ count_tw, int64_t cap)
+                             uint32_t *__restrict__ count_tw, int64_t cap, int split, int seed_check)
 {
     const TraceJob &J = jobs[job];
     const int64_t nl = live_lines(J);
@@ -349,7 +390,7 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
         // seed is grazing (both halves then stepped at the tolerance floor), or if
         // its own end is grazing (the footpoint error is amplified at its own end only)
         bool seed_graze = false;
-        if (J.kind != SEED_ROTATED) {
+        if (seed_check && J.kind != SEED_ROTATED) {
             double r[3], nrm[3], B[3];
             seed_of_line(J, l, r, nrm);
             interp64(J.planes, r, B);
@@ -375,10 +416,10 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
                 const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
                 redo = !(fabs(B[face >> 1]) >= thr * bm);
             }
-            if (unfinished) {
+            if (unfinished && split) {
                 const uint32_t k = atomicAdd(count_tw, 1u);
                 if ((int64_t)k < cap) list[cap - 1 - k] = FixEntry{job, h, l};
-            } else if (redo) {
+            } else if (redo || unfinished) {
                 const uint32_t slot = atomicAdd(count, 1u);
                 if ((int64_t)slot < cap) list[slot] = FixEntry{job, h, l};
             }
@@ -386,21 +427,50 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
     }
 }
 
-template <typename T, typename S, bool UNI>
-const void *kernel_of(int twm)
+template <typename T, typename S, bool UNI, int SCH>
+const void *kernel_of_s(int twm)
 {
-    return twm == 1 ? (const void *)trace_kernel<T, S, 1, UNI, false>
-                    : twm == 2 ? (const void *)trace_kernel<T, S, 2, UNI, false>
-                               : (const void *)trace_kernel<T, S, 0, UNI, false>;
+    return twm == 1 ? (const void *)trace_kernel<T, S, 1, UNI, false, SCH>
+                    : twm == 2 ? (const void *)trace_kernel<T, S, 2, UNI, false, SCH>
+                               : (const void *)trace_kernel<T, S, 0, UNI, false, SCH>;
+}
+
+template <typename T, typename S, bool UNI>
+const void *kernel_of(int twm, int sch, int method)
+{
+    if (method == FQ_METHOD_II)
+        return twm == 1 ? (const void *)trace_kernel<T, S, 1, UNI, false, SCH_RKF45, true>
+                        : (const void *)trace_kernel<T, S, 0, UNI, false, SCH_RKF45, true>;
+    return sch == SCH_RK4 ? kernel_of_s<T, S, UNI, SCH_RK4>(twm)
+                          : sch == SCH_RK4_38 ? kernel_of_s<T, S, UNI, SCH_RK4_38>(twm)
+                                              : kernel_of_s<T, S, UNI, SCH_RKF45>(twm);
+}
+
+template <typename T, typename S, bool UNI, bool TAPE, int SCH>
+void launch_tss(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
+                const TraceParams &tp, unsigned long long *counter)
+{
+    if (twm == 1) hipLaunchKernelGGL((trace_kernel<T, S, 1, UNI, TAPE, SCH>), grid, blk, 0, s, jobs, tp, counter);
+    else if (twm == 2 && !TAPE) hipLaunchKernelGGL((trace_kernel<T, S, 2, UNI, false, SCH>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, 0, UNI, TAPE, SCH>), grid, blk, 0, s, jobs, tp, counter);
+}
+
+template <typename T, typename S, bool UNI>
+void launch_m2(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
+               const TraceParams &tp, unsigned long long *counter)
+{
+    if (twm == 1) hipLaunchKernelGGL((trace_kernel<T, S, 1, UNI, false, SCH_RKF45, true>), grid, blk, 0, s, jobs, tp, counter);
+    else hipLaunchKernelGGL((trace_kernel<T, S, 0, UNI, false, SCH_RKF45, true>), grid, blk, 0, s, jobs, tp, counter);
 }
 
 template <typename T, typename S, bool UNI, bool TAPE>
 void launch_ts(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
                const TraceParams &tp, unsigned long long *counter)
 {
-    if (twm == 1) hipLaunchKernelGGL((trace_kernel<T, S, 1, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
-    else if (twm == 2 && !TAPE) hipLaunchKernelGGL((trace_kernel<T, S, 2, UNI, false>), grid, blk, 0, s, jobs, tp, counter);
-    else hipLaunchKernelGGL((trace_kernel<T, S, 0, UNI, TAPE>), grid, blk, 0, s, jobs, tp, counter);
+    if (!TAPE && tp.method == FQ_METHOD_II) launch_m2<T, S, UNI>(twm, grid, blk, s, jobs, tp, counter);
+    else if (TAPE || tp.scheme == SCH_RKF45) launch_tss<T, S, UNI, TAPE, SCH_RKF45>(twm, grid, blk, s, jobs, tp, counter);
+    else if (tp.scheme == SCH_RK4) launch_tss<T, S, UNI, false, SCH_RK4>(twm, grid, blk, s, jobs, tp, counter);
+    else launch_tss<T, S, UNI, false, SCH_RK4_38>(twm, grid, blk, s, jobs, tp, counter);
 }
 
 __global__ void fill_counts_kernel(uint32_t *counts)
@@ -599,18 +669,21 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
     if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
     const bool uni = tp.njobs == 1 && !tp.dynamic_last;
+    if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
-        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list
-        if (!f64 || !uni || tp.list || tp.seg < 1) return hipErrorInvalidValue;
+        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, RKF45
+        if (!f64 || !uni || tp.list || tp.seg < 1 || tp.scheme != SCH_RKF45) return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
         if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
         else launch_ts<double, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
         return hipGetLastError();
     }
     const void *fn;
-    if (!f64) fn = uni ? kernel_of<float, float, true>(twm) : kernel_of<float, float, false>(twm);
-    else if (s64) fn = uni ? kernel_of<double, double, true>(twm) : kernel_of<double, double, false>(twm);
-    else fn = uni ? kernel_of<double, float, true>(twm) : kernel_of<double, float, false>(twm);
+    const int sch = tp.scheme, mt = tp.method;
+    if (mt == FQ_METHOD_II && (sch != SCH_RKF45 || twm == 2)) return hipErrorInvalidValue;
+    if (!f64) fn = uni ? kernel_of<float, float, true>(twm, sch, mt) : kernel_of<float, float, false>(twm, sch, mt);
+    else if (s64) fn = uni ? kernel_of<double, double, true>(twm, sch, mt) : kernel_of<double, double, false>(twm, sch, mt);
+    else fn = uni ? kernel_of<double, float, true>(twm, sch, mt) : kernel_of<double, float, false>(twm, sch, mt);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
     if (per_cu <= 0) per_cu = 1;
@@ -635,13 +708,13 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
 
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr, FixEntry *list, uint32_t *count,
-                        uint32_t *count_tw, int64_t cap, hipStream_t s)
+                        uint32_t *count_tw, int64_t cap, int split, int seed_check, hipStream_t s)
 {
     int64_t b = (max_lines + 255) / 256;
     if (b < 1) b = 1;
     if (b > 65536) b = 65536;
     hipLaunchKernelGGL(graze_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, job, thr, qmap,
-                       qthr, list, count, count_tw, cap);
+                       qthr, list, count, count_tw, cap, split, seed_check);
     return hipGetLastError();
 }
 

@@ -45,6 +45,10 @@ template <> struct Num<float> {
 #endif
     }
     static constexpr float ov = 1e-5f;        // overshoot of a step past a face that is kept
+    // Method II: the gradient of the trilinear B/B jumps across a cell face, so an
+    // overshoot d kept there moves U and V by d times that jump (first order, where
+    // positions err by d^2): about two ulp of a local coordinate
+    static constexpr float ov_tan = 1.2e-7f;
     static constexpr float tau = 1e-4f;       // |direction component| below this is tangent
     static constexpr float null_rel = 1e-30f; // |B|^2 below null_rel * max|B|^2 is a null
     static constexpr float gmin = 1e-4f;      // smallest usable d(coordinate)/ds on a landing
@@ -79,6 +83,7 @@ template <> struct Num<double> {
 #endif
     }
     static constexpr double ov = 1e-9;
+    static constexpr double ov_tan = 1e-9;
     static constexpr double tau = 1e-9;
     static constexpr double null_rel = 1e-60;
     static constexpr double gmin = 1e-9;
@@ -181,6 +186,52 @@ template <typename T> struct LaneConst {
     int64_t max_steps;
 };
 
+// Method II (Section 2.1, Eq. rb2): the two tangent vectors U, V carried along the
+// line, in local grid units (component a in units of the spacing of axis a), so
+// that dU/ds = J U with J the Jacobian of the local direction field
+// f = sgn R B/|B| (R = diag(rx, ry, rz)) with respect to the local coordinates.
+template <typename T> struct Tan {
+    T u[3], v[3];
+};
+
+// d/du, d/dv, d/dw of the cell polynomial P (see poly).
+template <typename T>
+__host__ __device__ __forceinline__ void dpoly(const T c[8], T u, T v, T w, T &du, T &dv, T &dw)
+{
+    using N = Num<T>;
+    du = N::fma_(v, N::fma_(c[7], w, c[4]), N::fma_(c[5], w, c[1]));
+    dv = N::fma_(u, N::fma_(c[7], w, c[4]), N::fma_(c[6], w, c[2]));
+    dw = N::fma_(u, N::fma_(c[7], v, c[5]), N::fma_(c[6], v, c[3]));
+}
+
+// The rates of U and V at local point (u,v,w), per reference length: J U and J V
+// with J = sgn R (I - b b^T) (dB/dp) / |B| and b = B/|B| (B given, inv = 1/|B|).
+// The gradient of B/B is taken analytically on the cell's interpolant.
+template <typename T>
+__host__ __device__ __forceinline__ void tan_rates(const T cb[3][8], T u, T v, T w, T bx, T by,
+                                                   T bz, T inv, T sgn, T rx, T ry, T rz,
+                                                   const T U[3], const T V[3], T kU[3], T kV[3])
+{
+    using N = Num<T>;
+    T d[3][3];  // d[i][j] = dB_i / dp_j
+#pragma unroll
+    for (int i = 0; i < 3; i++) dpoly<T>(cb[i], u, v, w, d[i][0], d[i][1], d[i][2]);
+    const T b0 = bx * inv, b1 = by * inv, b2 = bz * inv;
+    const T s = sgn * inv;
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        const T *X = m ? V : U;
+        T *K = m ? kV : kU;
+        T g[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) g[i] = N::fma_(d[i][0], X[0], N::fma_(d[i][1], X[1], d[i][2] * X[2]));
+        const T bg = N::fma_(b0, g[0], N::fma_(b1, g[1], b2 * g[2]));
+        K[0] = s * rx * N::fma_(-b0, bg, g[0]);
+        K[1] = s * ry * N::fma_(-b1, bg, g[1]);
+        K[2] = s * rz * N::fma_(-b2, bg, g[2]);
+    }
+}
+
 // Why a trial ended (an event sink may record it; the tracer ignores it).
 enum Ev : int {
     EV_CROSS = 0,     // moved to the next cell through the face it sat on
@@ -269,12 +320,22 @@ __host__ __device__ __forceinline__ int box_past(T n, int c, int nodes, T d0, T 
 // One trial step. On return: fin_st >= 0 if the half line ended (status bits,
 // fin_face = exit face or -1), need_load if the cell changed. n_acc counts
 // accepted steps.
-template <typename T, bool TW, typename EvSink = NoEvents>
+// Integration schemes (Section 2.3). RKF45 is adaptive; the two RK4 rules take a
+// fixed step (L.tol holds it; the error bound is not used), cut short only by cell
+// faces like every step here.
+enum Scheme : int { SCH_RKF45 = 0, SCH_RK4 = 1, SCH_RK4_38 = 2 };
+
+// M2: carry Method II's tangent vectors tn along (RKF45 only).
+template <typename T, bool TW, typename EvSink = NoEvents, int SCH = SCH_RKF45, bool M2 = false>
 __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][8],
                                                       const T cj[3][8], const LaneConst<T> &K,
                                                       int &fin_st, int &fin_face, bool &need_load,
-                                                      unsigned &n_acc, EvSink ev = EvSink())
+                                                      unsigned &n_acc, EvSink ev = EvSink(),
+                                                      Tan<T> *tn = nullptr)
 {
+    static_assert(!M2 || SCH == 0, "Method II is traced with RKF45");
+    constexpr bool FIXED = SCH != SCH_RKF45;
+    constexpr int NS = FIXED ? 4 : 6;  // stages
     using N = Num<T>;
     constexpr int kNull = 2, kMaxSteps = 4, kNonFinite = 8;  // FQ_ST_* bits
     if (++L.trials > K.max_steps) {
@@ -347,8 +408,9 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         const T hs = H >= 0 ? T(1) : T(-1);
         const T ig0 = N::rcp(g0);
 
-        // Fehlberg 4(5). Stage positions need only the position parts of earlier
-        // stages; the twist and length parts go straight into the fifth-order sums.
+        // Fehlberg 4(5), or classic / 3/8-rule RK4 (Kutta). Stage positions need only
+        // the position parts of earlier stages; the twist and length parts go straight
+        // into the weighted sums of the solution.
         constexpr T A10 = T(1.0 / 4.0);
         constexpr T A20 = T(3.0 / 32.0), A21 = T(9.0 / 32.0);
         constexpr T A30 = T(1932.0 / 2197.0), A31 = T(-7200.0 / 2197.0), A32 = T(7296.0 / 2197.0);
@@ -360,20 +422,42 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                     B4 = T(-9.0 / 50.0), B5 = T(2.0 / 55.0);
         constexpr T E0 = T(1.0 / 360.0), E2 = T(-128.0 / 4275.0), E3 = T(-2197.0 / 75240.0),
                     E4 = T(1.0 / 50.0), E5 = T(2.0 / 55.0);
+        // classic RK4: c = (0, 1/2, 1/2, 1), b = (1, 2, 2, 1) / 6;
+        // 3/8 rule: c = (0, 1/3, 2/3, 1), a = (1/3; -1/3, 1; 1, -1, 1), b = (1, 3, 3, 1) / 8
+        constexpr T W0 = SCH == SCH_RK4 ? T(1.0 / 6.0) : SCH == SCH_RK4_38 ? T(1.0 / 8.0) : B0;
         T k[6][3];
         k[0][0] = f0 * ig0;
         k[0][1] = f1 * ig0;
         k[0][2] = f2 * ig0;
-        T stw = B0 * (ft * ig0), slen = B0 * ig0;
+        T ku[M2 ? 6 : 1][3], kv[M2 ? 6 : 1][3];
+        if constexpr (M2) {
+            // the rates at the start need B there; one more evaluation of it
+            const T bx = poly<T>(cb[0], L.p0, L.p1, L.p2), by = poly<T>(cb[1], L.p0, L.p1, L.p2),
+                    bz = poly<T>(cb[2], L.p0, L.p1, L.p2);
+            tan_rates<T>(cb, L.p0, L.p1, L.p2, bx, by, bz, N::rsq(b2), L.sgn, K.rx, K.ry, K.rz,
+                         tn->u, tn->v, ku[0], kv[0]);
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                ku[0][q] *= ig0;
+                kv[0][q] *= ig0;
+            }
+        }
+        T stw = W0 * (ft * ig0), slen = W0 * ig0;
         bool ok = true;
         T b2min = b2;
 #pragma unroll
-        for (int st = 1; st < 6; st++) {
+        for (int st = 1; st < NS; st++) {
             T y[3];
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 T acc;
-                if (st == 1) acc = A10 * k[0][q];
+                if (SCH == SCH_RK4) {
+                    acc = st == 3 ? k[2][q] : T(0.5) * k[st - 1][q];
+                } else if (SCH == SCH_RK4_38) {
+                    if (st == 1) acc = T(1.0 / 3.0) * k[0][q];
+                    else if (st == 2) acc = k[1][q] - T(1.0 / 3.0) * k[0][q];
+                    else acc = (k[0][q] - k[1][q]) + k[2][q];
+                } else if (st == 1) acc = A10 * k[0][q];
                 else if (st == 2) acc = N::fma_(A21, k[1][q], A20 * k[0][q]);
                 else if (st == 3) acc = N::fma_(A32, k[2][q], N::fma_(A31, k[1][q], A30 * k[0][q]));
                 else if (st == 4)
@@ -385,9 +469,35 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                                           N::fma_(A52, k[2][q], N::fma_(A51, k[1][q], A50 * k[0][q]))));
                 y[q] = N::fma_(H, acc, q == 0 ? L.p0 : (q == 1 ? L.p1 : L.p2));
             }
+            T uy[3], vy[3];
+            if constexpr (M2) {
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    T au, av;
+                    if (st == 1) au = A10 * ku[0][q], av = A10 * kv[0][q];
+                    else if (st == 2) {
+                        au = N::fma_(A21, ku[1][q], A20 * ku[0][q]);
+                        av = N::fma_(A21, kv[1][q], A20 * kv[0][q]);
+                    } else if (st == 3) {
+                        au = N::fma_(A32, ku[2][q], N::fma_(A31, ku[1][q], A30 * ku[0][q]));
+                        av = N::fma_(A32, kv[2][q], N::fma_(A31, kv[1][q], A30 * kv[0][q]));
+                    } else if (st == 4) {
+                        au = N::fma_(A43, ku[3][q], N::fma_(A42, ku[2][q], N::fma_(A41, ku[1][q], A40 * ku[0][q])));
+                        av = N::fma_(A43, kv[3][q], N::fma_(A42, kv[2][q], N::fma_(A41, kv[1][q], A40 * kv[0][q])));
+                    } else {
+                        au = N::fma_(A54, ku[4][q], N::fma_(A53, ku[3][q],
+                             N::fma_(A52, ku[2][q], N::fma_(A51, ku[1][q], A50 * ku[0][q]))));
+                        av = N::fma_(A54, kv[4][q], N::fma_(A53, kv[3][q],
+                             N::fma_(A52, kv[2][q], N::fma_(A51, kv[1][q], A50 * kv[0][q]))));
+                    }
+                    uy[q] = N::fma_(H, au, tn->u[q]);
+                    vy[q] = N::fma_(H, av, tn->v[q]);
+                }
+            }
             T g0s, g1s, g2s, gts, b2s;
-            // the twist integrand of stage 1 has weight zero in the fifth-order sum
-            if (st == 1)
+            // the twist integrand of Fehlberg's stage 1 has weight zero in the
+            // fifth-order sum
+            if (!FIXED && st == 1)
                 rhs<T, false>(cb, cj, y[0], y[1], y[2], L.sgn, K.rx, K.ry, K.rz, K.twk, g0s, g1s, g2s,
                               gts, b2s);
             else
@@ -398,7 +508,11 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             T g = T(1);
             if (axis >= 0) {
                 g = sel3(axis, g0s, g1s, g2s);
-                if (!(g * hs > N::gmin)) {
+                // a fixed-step scheme has no error estimate to catch a landing whose
+                // independent variable turns badly within the step (a line meeting
+                // the face at a small angle): it approaches with shorter plain steps
+                // until the face coordinate's rate changes by at most a tenth
+                if (!(g * hs > N::gmin) || (FIXED && fabs(g - g0) > T(0.1) * fabs(g0))) {
                     ok = false;
                     g = g0;
                 }
@@ -407,25 +521,69 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             k[st][0] = g0s * ig;
             k[st][1] = g1s * ig;
             k[st][2] = g2s * ig;
-            const T bs = st == 2 ? B2 : st == 3 ? B3 : st == 4 ? B4 : st == 5 ? B5 : T(0);
-            if (st != 1) stw = N::fma_(bs, gts * ig, stw);
-            slen = N::fma_(bs, ig, slen);
+            if constexpr (M2) {
+                const T bx = poly<T>(cb[0], y[0], y[1], y[2]), by = poly<T>(cb[1], y[0], y[1], y[2]),
+                        bz = poly<T>(cb[2], y[0], y[1], y[2]);
+                tan_rates<T>(cb, y[0], y[1], y[2], bx, by, bz, N::rsq(b2s), L.sgn, K.rx, K.ry, K.rz,
+                             uy, vy, ku[st], kv[st]);
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    ku[st][q] *= ig;
+                    kv[st][q] *= ig;
+                }
+            }
+            T bs;
+            if (SCH == SCH_RK4) bs = st == 3 ? T(1.0 / 6.0) : T(1.0 / 3.0);
+            else if (SCH == SCH_RK4_38) bs = st == 3 ? T(1.0 / 8.0) : T(3.0 / 8.0);
+            else bs = st == 2 ? B2 : st == 3 ? B3 : st == 4 ? B4 : st == 5 ? B5 : T(0);
+            if (FIXED || st != 1) stw = N::fma_(bs, gts * ig, stw);
+            if (FIXED || st != 1) slen = N::fma_(bs, ig, slen);
         }
         T dyv[3], e[3];
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const T acc = N::fma_(B5, k[5][q], N::fma_(B4, k[4][q],
-                          N::fma_(B3, k[3][q], N::fma_(B2, k[2][q], B0 * k[0][q]))));
-            dyv[q] = H * acc;
-            const T ea = N::fma_(E5, k[5][q], N::fma_(E4, k[4][q],
-                         N::fma_(E3, k[3][q], N::fma_(E2, k[2][q], E0 * k[0][q]))));
-            e[q] = H * ea;
+            if (SCH == SCH_RK4) {
+                dyv[q] = H * (T(1.0 / 6.0) * (k[0][q] + k[3][q]) + T(1.0 / 3.0) * (k[1][q] + k[2][q]));
+                e[q] = T(0);
+            } else if (SCH == SCH_RK4_38) {
+                dyv[q] = H * (T(1.0 / 8.0) * (k[0][q] + k[3][q]) + T(3.0 / 8.0) * (k[1][q] + k[2][q]));
+                e[q] = T(0);
+            } else {
+                const T acc = N::fma_(B5, k[5][q], N::fma_(B4, k[4][q],
+                              N::fma_(B3, k[3][q], N::fma_(B2, k[2][q], B0 * k[0][q]))));
+                dyv[q] = H * acc;
+                const T ea = N::fma_(E5, k[5][q], N::fma_(E4, k[4][q],
+                             N::fma_(E3, k[3][q], N::fma_(E2, k[2][q], E0 * k[0][q]))));
+                e[q] = H * ea;
+            }
         }
         if (b2min <= K.bnull2) {
             fin_st = kNull;
             return;
         }
-        const T err2 = N::fma_(e[0], e[0], N::fma_(e[1], e[1], e[2] * e[2]));
+        T err2 = N::fma_(e[0], e[0], N::fma_(e[1], e[1], e[2] * e[2]));
+        T du[3], dvv[3];
+        if constexpr (M2) {
+            // the tangent vectors' errors join the norm relative to their size (at
+            // least one grid unit), as their 5th-order updates are formed
+            T eu2 = T(0), ev2 = T(0);
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                du[q] = H * N::fma_(B5, ku[5][q], N::fma_(B4, ku[4][q],
+                            N::fma_(B3, ku[3][q], N::fma_(B2, ku[2][q], B0 * ku[0][q]))));
+                dvv[q] = H * N::fma_(B5, kv[5][q], N::fma_(B4, kv[4][q],
+                             N::fma_(B3, kv[3][q], N::fma_(B2, kv[2][q], B0 * kv[0][q]))));
+                const T a = H * N::fma_(E5, ku[5][q], N::fma_(E4, ku[4][q],
+                                N::fma_(E3, ku[3][q], N::fma_(E2, ku[2][q], E0 * ku[0][q]))));
+                const T b = H * N::fma_(E5, kv[5][q], N::fma_(E4, kv[4][q],
+                                N::fma_(E3, kv[3][q], N::fma_(E2, kv[2][q], E0 * kv[0][q]))));
+                eu2 = N::fma_(a, a, eu2);
+                ev2 = N::fma_(b, b, ev2);
+            }
+            const T uu = mx(T(1), N::fma_(tn->u[0], tn->u[0], N::fma_(tn->u[1], tn->u[1], tn->u[2] * tn->u[2])));
+            const T vv = mx(T(1), N::fma_(tn->v[0], tn->v[0], N::fma_(tn->v[1], tn->v[1], tn->v[2] * tn->v[2])));
+            err2 = err2 + eu2 * N::rcp(uu) + ev2 * N::rcp(vv);
+        }
         const T tol2 = L.tol * L.tol;
         const T s_step = H * ig0;  // arc length of the step, reference lengths
         if (!ok || !finite_(err2)) {
@@ -441,7 +599,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             }
             return;
         }
-        if (err2 > tol2) {  // reject: shrink and retry from the same point
+        if (!FIXED && err2 > tol2) {  // reject: shrink and retry from the same point
             const float fac = fmaxf(0.9f * pow01((float)tol2 * Num<float>::rcp((float)err2)), 0.1f);
             L.h = mx((axis >= 0 ? mn(L.h, fabs(s_step)) : L.h) * (T)fac, N::hmin);
             ev(axis >= 0 ? EV_REJECT_LAND : EV_REJECT_ARC);
@@ -450,7 +608,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         const float grow = err2 > T(0) ? fminf(0.9f * pow01((float)tol2 * Num<float>::rcp((float)err2)), 5.0f)
                                        : 5.0f;
         T n0 = L.p0 + dyv[0], n1 = L.p1 + dyv[1], n2 = L.p2 + dyv[2];
-        const T ov = N::ov;
+        const T ov = M2 ? N::ov_tan : N::ov;
         // Past a box face the line ends on that face, and clamping an overshoot d onto
         // it moves the end by d over the line's slope to the face: a first-order
         // error, not the second-order kink error of an interior face. So a step that
@@ -462,10 +620,11 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         // allowance. The start direction is k1 times g0; stage 5 sits at the end
         // of the step, so k5 times g0 stands for the end direction (its sign is
         // exact, its size is scaled by that stage's own g on a landing).
+        constexpr int KE = FIXED ? 3 : 4;  // the stage at the end of the step (c = 1)
         int bp = -1;
-        if (axis != 0) bp = box_past(n0, L.c0, K.nx, k[0][0] * g0, k[4][0] * g0, 0);
-        if (bp < 0 && axis != 1) bp = box_past(n1, L.c1, K.ny, k[0][1] * g0, k[4][1] * g0, 2);
-        if (bp < 0 && axis != 2) bp = box_past(n2, L.c2, K.nz, k[0][2] * g0, k[4][2] * g0, 4);
+        if (axis != 0) bp = box_past(n0, L.c0, K.nx, k[0][0] * g0, k[KE][0] * g0, 0);
+        if (bp < 0 && axis != 1) bp = box_past(n1, L.c1, K.ny, k[0][1] * g0, k[KE][1] * g0, 2);
+        if (bp < 0 && axis != 2) bp = box_past(n2, L.c2, K.nz, k[0][2] * g0, k[KE][2] * g0, 4);
         // a brief excursion over a face inside the step (the end may be back inside)
         int xf = -1;
         if (axis != 0) xf = excursion(0, L.p0, H * k[0][0], dyv[0], ov);
@@ -480,6 +639,12 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                 L.p0 = n0;
                 L.p1 = n1;
                 L.p2 = n2;
+                if constexpr (M2)
+#pragma unroll
+                    for (int q = 0; q < 3; q++) {
+                        tn->u[q] += du[q];
+                        tn->v[q] += dvv[q];
+                    }
                 int cl = 0;
                 bool moved = carry(L.c0, L.p0, K.nx, cl, 1);
                 moved |= carry(L.c1, L.p1, K.ny, cl, 2);
@@ -487,7 +652,7 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
                 if (moved) need_load = true;
                 L.tw += (double)(H * stw);
                 L.len += (double)(H * slen);
-                L.h = mn(L.h * (T)grow, T(4));
+                L.h = FIXED ? L.tol : mn(L.h * (T)grow, T(4));
                 n_acc++;
                 ev.accepted(-1, H, cl);
                 ev(EV_ACCEPT_ARC);
@@ -524,6 +689,12 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
             return;
         }
         const int d = hs > 0 ? 1 : -1;
+        if constexpr (M2)
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                tn->u[q] += du[q];
+                tn->v[q] += dvv[q];
+            }
         L.p0 = axis == 0 ? (d > 0 ? T(1) : T(0)) : n0;
         L.p1 = axis == 1 ? (d > 0 ? T(1) : T(0)) : n1;
         L.p2 = axis == 2 ? (d > 0 ? T(1) : T(0)) : n2;
@@ -531,7 +702,8 @@ __host__ __device__ __forceinline__ void lane_iterate(Lane<T> &L, const T cb[3][
         L.len += (double)(H * slen);
         // a landing is cut short by the face, not by the error bound: unless the error
         // asks for a smaller step, keep the step the controller had before the cut
-        L.h = grow >= 1.0f ? mn(mx(fabs(s_step) * (T)grow, L.h), T(4)) : fabs(s_step) * (T)grow;
+        if (FIXED) L.h = L.tol;
+        else L.h = grow >= 1.0f ? mn(mx(fabs(s_step) * (T)grow, L.h), T(4)) : fabs(s_step) * (T)grow;
         n_acc++;
         // carry small overshoots of the other coordinates (a crossing near an edge)
         bool moved = false;

@@ -5,7 +5,9 @@ the same process.
 
   python -m paper_2208_12569_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
   python -m paper_2208_12569_amd.profiling traffic <fetch counter csv> <write counter csv>
-        <out.json> <key> "<command>"
+        <out.json> <key> "<command>" [kernel]
+  python -m paper_2208_12569_amd.profiling l2 <tcc counter csv> <tcp counter csv> <out.md>
+        "<command>" [kernel]
 """
 
 from __future__ import annotations
@@ -18,7 +20,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
-TRACER = "trace_kernel<float, float, 1, true, false>"
+TRACER = "trace_kernel<float, float, 1, true, false, 0, false>"
 
 
 def kernel_source_sha() -> str:
@@ -86,6 +88,43 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str = TRACER) -> dict:
             "fetch_calibration": f_scale, "write_calibration": w_scale}
 
 
+def _mean_counter(path: str, counter: str, kernel: str) -> float:
+    vals = [v for n, v in _counter_rows(path, counter)
+            if kernel in n.replace("fq::(anonymous namespace)::", "")]
+    if not vals:
+        raise ValueError(f"{counter} of {kernel} not found in {path}")
+    return sum(vals) / len(vals)
+
+
+def l2_md(tcc_csv: str, tcp_csv: str, command: str, kernel: str = TRACER,
+          kernel_ms: float = None) -> str:
+    """L2 (TCC) hits, misses and requests of one kernel per launch, the bytes the L2
+    returned (32-byte read sectors) and, with the kernel's duration, the L2 read
+    rate; beside the L1 (TCP) accesses and the requests the L1 sent to the L2."""
+    hit = _mean_counter(tcc_csv, "TCC_HIT_sum", kernel)
+    miss = _mean_counter(tcc_csv, "TCC_MISS_sum", kernel)
+    req = _mean_counter(tcc_csv, "TCC_REQ_sum", kernel)
+    sect = _mean_counter(tcc_csv, "TCC_READ_SECTORS_sum", kernel)
+    tcp_req = _mean_counter(tcp_csv, "TCP_TCC_READ_REQ_sum", kernel)
+    tcp_acc = _mean_counter(tcp_csv, "TCP_TOTAL_CACHE_ACCESSES_sum", kernel)
+    rows = [f"Command: `{command}` (one `--pmc` pass per counter group: "
+            "TCC_HIT_sum TCC_MISS_sum TCC_REQ_sum TCC_READ_SECTORS_sum, then "
+            "TCP_TCC_READ_REQ_sum TCP_TOTAL_CACHE_ACCESSES_sum)", "",
+            f"Kernel: `{kernel}`, per launch (mean over launches):", "",
+            "| counter | value |", "|---|---|",
+            f"| L1 (TCP) cache accesses | {tcp_acc:.4g} |",
+            f"| L1 -> L2 read requests | {tcp_req:.4g} |",
+            f"| L2 (TCC) requests | {req:.4g} |",
+            f"| L2 hits | {hit:.4g} |", f"| L2 misses | {miss:.4g} |",
+            f"| L2 hit rate | {hit / max(hit + miss, 1):.3f} |",
+            f"| L2 read sectors (32 B) | {sect:.4g} |",
+            f"| bytes read from L2 | {sect * 32 / 1e9:.3f} GB |"]
+    if kernel_ms:
+        rows.append(f"| L2 read rate at {kernel_ms:.3f} ms per launch | "
+                    f"{sect * 32 / (kernel_ms * 1e-3) / 1e12:.2f} TB/s |")
+    return "\n".join(rows) + "\n"
+
+
 def main(argv):
     if argv[0] == "stats":
         open(argv[2], "w").write(stats_md(argv[1], argv[3]))
@@ -93,10 +132,14 @@ def main(argv):
         d = {}
         if os.path.exists(argv[3]):
             d = json.load(open(argv[3]))
-        e = traffic(argv[1], argv[2])
+        e = traffic(argv[1], argv[2], *(argv[6:7] or [TRACER]))
         e["command"] = argv[5]
         d[argv[4]] = e
         json.dump(d, open(argv[3], "w"), indent=1)
+    elif argv[0] == "l2":
+        kernel = argv[5] if len(argv) > 5 else TRACER
+        ms = float(argv[6]) if len(argv) > 6 else None
+        open(argv[3], "w").write(l2_md(argv[1], argv[2], argv[4], kernel, ms))
     else:
         raise SystemExit(__doc__)
 

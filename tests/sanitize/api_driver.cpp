@@ -87,6 +87,25 @@ int main()
                 CHECK(fastqsl_q2d(f, pl, nj, &P, m, ws, need, nullptr) == FQ_OK);
                 CHECK(fastqsl_q2d(f, pl, nj, &P, m, ws, need - 1, nullptr) == FQ_ENOMEM);
             }
+            // Method II maps, and the fixed-step schemes
+            fq_params P2 = P;
+            P2.method = FQ_METHOD_II;
+            for (int nj = 1; nj <= 3; nj++) {
+                size_t need = fastqsl_q2d_workspace_size(f, pl, nj, &P2);
+                CHECK(need > 0);
+                CHECK(fastqsl_q2d(f, pl, nj, &P2, m, workspace(need), need, nullptr) == FQ_OK);
+            }
+            P2.scheme = FQ_SCHEME_RK4;
+            CHECK(fastqsl_q2d_workspace_size(f, pl, 1, &P2) == 0);
+            P2.method = FQ_METHOD_I;
+            P2.scheme = FQ_SCHEME_RK4_38;
+            {
+                size_t need = fastqsl_q2d_workspace_size(f, pl, 2, &P2);
+                CHECK(need > 0);
+                CHECK(fastqsl_q2d(f, pl, 2, &P2, m, workspace(need), need, nullptr) == FQ_OK);
+            }
+            P2.scheme = 7;
+            CHECK(fastqsl_q2d_workspace_size(f, pl, 1, &P2) == 0);
             // an interior plane (rotated S0) alone, and in a batch (unsupported)
             fq_plane mid = plane(20, 20, 0.37);
             size_t need = fastqsl_q2d_workspace_size(f, &mid, 1, &P);
@@ -94,7 +113,7 @@ int main()
             CHECK(fastqsl_q2d(f, &mid, 1, &P, m, workspace(need), need, nullptr) == FQ_OK);
             fq_plane two[2] = {mid, pl[1]};
             CHECK(fastqsl_q2d_workspace_size(f, two, 2, &P) == 0);
-            // q3d
+            // q3d (Method I with rotated S0, and Method II)
             fq_voxels vx;
             memset(&vx, 0, sizeof vx);
             vx.n[0] = 11, vx.n[1] = 7, vx.n[2] = 5;
@@ -105,6 +124,13 @@ int main()
             std::vector<uint16_t> s3(11 * 7 * 5);
             fq_map m3 = map_of(q3, t3, s3);
             CHECK(fastqsl_q3d(&f[0], &vx, &P, &m3, workspace(need), need, nullptr) == FQ_OK);
+            {
+                fq_params P3 = P;
+                P3.method = FQ_METHOD_II;
+                size_t n3 = fastqsl_q3d_workspace_size(&f[0], &vx, &P3);
+                CHECK(n3 > 0);
+                CHECK(fastqsl_q3d(&f[0], &vx, &P3, &m3, workspace(n3), n3, nullptr) == FQ_OK);
+            }
             // trace lists, including an empty one
             fq_lines L;
             memset(&L, 0, sizeof L);

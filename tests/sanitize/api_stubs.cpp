@@ -69,7 +69,8 @@ hipError_t launch_tile_order(const TraceJob &J, int, int, int32_t *bucket, uint3
     return launch_bucket_order(J.tiles[0] * J.tiles[1], bucket, counts, order, s);
 }
 hipError_t launch_graze(const TraceJob *jobs, int job, int64_t, double, const double *, double,
-                        FixEntry *list, uint32_t *count, uint32_t *count_tw, int64_t cap, hipStream_t)
+                        FixEntry *list, uint32_t *count, uint32_t *count_tw, int64_t cap, int, int,
+                        hipStream_t)
 {
     in_ws(jobs + job, sizeof(TraceJob), "graze job");
     in_ws(list, (size_t)cap * sizeof(FixEntry), "graze list");
@@ -125,6 +126,13 @@ hipError_t launch_stencil(const MapJob &m, hipStream_t)
     g_calls++;
     return hipSuccess;
 }
+hipError_t launch_m2_map(const MapJob &m, hipStream_t)
+{
+    in_ws(m.rec.st, (size_t)(2 * m.nlines) * 2, "Method II records");
+    in_ws(m.rec.uv, (size_t)(2 * m.nlines) * 48, "Method II tangent vectors");
+    g_calls++;
+    return hipSuccess;
+}
 hipError_t launch_lines_out(const MapJob &m, const double *, hipStream_t)
 {
     in_ws(m.rec.end, (size_t)(2 * m.nlines) * 24, "line records");
@@ -134,5 +142,6 @@ hipError_t launch_lines_out(const MapJob &m, const double *, hipStream_t)
 
 }  // namespace fq
 
-// events are recorded only when the caller passes them; nothing to time here
+// The HIP runtime calls of the host layer: events and the error state, without a GPU.
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipGetLastError() { return hipSuccess; }

@@ -9,7 +9,7 @@ import pytest
 import bench
 from paper_2208_12569_amd import profiling
 
-TRACER = "void fq::(anonymous namespace)::trace_kernel<float, float, 1, true, false>(fq::TraceJob const*)"
+TRACER = "void fq::(anonymous namespace)::trace_kernel<float, float, 1, true, false, 0, false>(fq::TraceJob const*)"
 COPY = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctor_add<float>>"
 
 
@@ -68,7 +68,7 @@ def test_stats_table_is_ordered_by_total_time(tmp_path):
     lines = md.splitlines()
     assert lines[0] == "Command: `rocprofv3 --kernel-trace --stats -- python3 bench.py`"
     rows = [l for l in lines if l.startswith("| ") and not l.startswith("| kernel")]
-    assert rows[0].startswith("| trace_kernel<float, float, 1, true, false>")
+    assert rows[0].startswith("| trace_kernel<float, float, 1, true, false, 0, false>")
     assert "| 8.000 | 4000.0 |" in rows[0]
     assert rows[1].startswith("| stencil_kernel |")
     assert rows[2].startswith("| fill |")
