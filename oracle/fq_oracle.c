@@ -8,7 +8,10 @@
  * What it computes
  *   - The magnetic field at any point is the trilinear interpolant of the node
  *     values (Section 2.2, Eq. interp / w0 / w1). Inside one grid cell this is a
- *     polynomial; across cell faces it is only continuous.
+ *     polynomial; across cell faces it is only continuous. Grids are uniform or
+ *     stretched rectilinear (per axis node coordinates; the cell of a point by
+ *     bisection, Section 2.2), and on a stretched axis derivatives at nodes are
+ *     those of the quadratic through three nodes.
  *   - A field line solves dr/ds = B/|B| (Section 2.1, Eq. rb). The oracle
  *     approximates the exact solution of that ODE in the interpolated field: it
  *     integrates cell by cell with every step confined to one closed cell (the
@@ -36,6 +39,9 @@
  * twisted fields; lines crossing a cell face and back within one step; Q = 2 on
  * arcades over a polarity inversion line of the seed face, down to seeds 1e-8 from
  * it (grazing landings); interior seed planes against the direct S1 -> S2 map;
+ * the linear-field closed forms again on stretched grids (cells up to five times
+ * their neighbours' width), exact curl and scipy's trilinear interpolation there,
+ * seeds on node planes, and explicit uniform nodes against the uniform grid;
  * the rotated S0 of 3-D maps against the closed form of an oblique sheared field,
  * including a voxel with Bz = 0; voxels of two layers of a 3-D map on one line
  * (same Tw and length; Q in the ratio that the interpolant's divergence along
@@ -86,8 +92,38 @@ static int64_t node(const orc_field *f, int64_t i, int64_t j, int64_t k)
  * curl B at the nodes
  * ---------------------------------------------------------------------------- */
 
+/* Position of node i along axis a (Section 2.2: the nodes x_i, y_j, z_k; on a
+ * uniform axis origin + i spacing). */
+static double node_x(const orc_field *f, int a, int64_t i)
+{
+    return f->coord[a] ? f->coord[a][i] : f->origin[a] + (double)i * f->spacing[a];
+}
+
+/* Width of cell c along axis a. */
+static double cell_w(const orc_field *f, int a, int64_t c)
+{
+    return f->coord[a] ? f->coord[a][c + 1] - f->coord[a][c] : f->spacing[a];
+}
+
+/* Mean cell width along axis a (the spacing of a uniform axis). */
+static double mean_w(const orc_field *f, int a)
+{
+    return f->coord[a] ? (f->coord[a][f->n[a] - 1] - f->coord[a][0]) / (double)(f->n[a] - 1)
+                       : f->spacing[a];
+}
+
+/* The derivative at x0 of the quadratic through (x0,p0), (x1,p1), (x2,p2): the
+ * second-order difference on unequal spacings (Lagrange form). */
+static double quad_deriv(double x0, double x1, double x2, double p0, double p1, double p2)
+{
+    return p0 * (2.0 * x0 - x1 - x2) / ((x0 - x1) * (x0 - x2)) +
+           p1 * (x0 - x2) / ((x1 - x0) * (x1 - x2)) + p2 * (x0 - x1) / ((x2 - x0) * (x2 - x1));
+}
+
 /* d p / d axis at node (i,j,k): central second-order differences inside, the
- * one-sided second-order formula (-3 f0 + 4 f1 - f2) / 2h on the boundary nodes. */
+ * one-sided second-order formula (-3 f0 + 4 f1 - f2) / 2h on the boundary nodes.
+ * On a stretched axis, the same three nodes give the derivative of the quadratic
+ * through them (second order on unequal spacings). */
 static double deriv(const orc_field *f, const double *p, int axis, int64_t i, int64_t j,
                     int64_t k)
 {
@@ -99,6 +135,22 @@ static double deriv(const orc_field *f, const double *p, int axis, int64_t i, in
     memcpy(a, idx, sizeof a);
     memcpy(b, idx, sizeof b);
     memcpy(c, idx, sizeof c);
+    if (f->coord[axis]) {
+        const double *x = f->coord[axis];
+        if (n < 3) {
+            a[axis] = 0;
+            b[axis] = 1;
+            return (p[node(f, b[0], b[1], b[2])] - p[node(f, a[0], a[1], a[2])]) / (x[1] - x[0]);
+        }
+        /* the three nodes: this one and its two neighbours, or the two inward ones
+         * on a boundary node */
+        int64_t m1 = m == 0 ? 1 : (m == n - 1 ? n - 2 : m - 1);
+        int64_t m2 = m == 0 ? 2 : (m == n - 1 ? n - 3 : m + 1);
+        b[axis] = m1;
+        c[axis] = m2;
+        return quad_deriv(x[m], x[m1], x[m2], p[node(f, a[0], a[1], a[2])],
+                          p[node(f, b[0], b[1], b[2])], p[node(f, c[0], c[1], c[2])]);
+    }
     if (n < 3) { /* two nodes only: the single first-order difference */
         a[axis] = 0;
         b[axis] = 1;
@@ -146,8 +198,8 @@ void orc_interp(const orc_field *f, const double *const p[3], const int64_t c[3]
 {
     double w[3][2];
     for (int a = 0; a < 3; a++) {
-        double lo = f->origin[a] + (double)c[a] * f->spacing[a];
-        double hi = f->origin[a] + (double)(c[a] + 1) * f->spacing[a];
+        double lo = node_x(f, a, c[a]);
+        double hi = node_x(f, a, c[a] + 1);
         w[a][0] = (hi - r[a]) / (hi - lo); /* omega_{.,0} */
         w[a][1] = 1.0 - w[a][0];           /* omega_{.,1} */
     }
@@ -163,10 +215,22 @@ void orc_interp(const orc_field *f, const double *const p[3], const int64_t c[3]
 }
 
 /* The grid cell holding r: floor((r - origin)/spacing), clamped to [0, n-2] so
- * that a point on an upper box face belongs to the last cell. */
+ * that a point on an upper box face belongs to the last cell; on a stretched axis
+ * the last node at or below r, by bisection (Section 2.2). */
 static void locate(const orc_field *f, const double r[3], int64_t c[3])
 {
     for (int a = 0; a < 3; a++) {
+        if (f->coord[a]) {
+            int64_t lo = 0, hi = f->n[a] - 1; /* x[lo] <= r < x[hi] kept while possible */
+            while (hi - lo > 1) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (f->coord[a][mid] <= r[a]) lo = mid;
+                else hi = mid;
+            }
+            if (lo > f->n[a] - 2) lo = f->n[a] - 2;
+            c[a] = lo;
+            continue;
+        }
         double t = floor((r[a] - f->origin[a]) / f->spacing[a]);
         int64_t i = (int64_t)t;
         if (i < 0) i = 0;
@@ -175,21 +239,30 @@ static void locate(const orc_field *f, const double r[3], int64_t c[3])
     }
 }
 
-static double face_lo(const orc_field *f, const int64_t c[3], int a)
-{
-    return f->origin[a] + (double)c[a] * f->spacing[a];
-}
+static double face_lo(const orc_field *f, const int64_t c[3], int a) { return node_x(f, a, c[a]); }
 
 static double face_hi(const orc_field *f, const int64_t c[3], int a)
 {
-    return f->origin[a] + (double)(c[a] + 1) * f->spacing[a];
+    return node_x(f, a, c[a] + 1);
 }
 
-static double box_lo(const orc_field *f, int a) { return f->origin[a]; }
+static double box_lo(const orc_field *f, int a) { return node_x(f, a, 0); }
 
-static double box_hi(const orc_field *f, int a)
+static double box_hi(const orc_field *f, int a) { return node_x(f, a, f->n[a] - 1); }
+
+/* The smallest cell width of the grid (the reference length of steps). */
+static double min_width(const orc_field *f)
 {
-    return f->origin[a] + (double)(f->n[a] - 1) * f->spacing[a];
+    double d = INFINITY;
+    for (int a = 0; a < 3; a++) {
+        if (!f->coord[a]) {
+            if (f->spacing[a] < d) d = f->spacing[a];
+            continue;
+        }
+        for (int64_t c = 0; c + 1 < f->n[a]; c++)
+            if (cell_w(f, a, c) < d) d = cell_w(f, a, c);
+    }
+    return d;
 }
 
 static int in_box(const orc_field *f, const double r[3])
@@ -245,7 +318,7 @@ static int grad_b(const line_ctx *L, const double r[3], double g[3][3])
         return 0;
     }
     for (int j = 0; j < 3; j++) {
-        double h = 1e-3 * L->f->spacing[j];
+        double h = 1e-3 * cell_w(L->f, j, L->c[j]);
         double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]}, bp[3], bm[3];
         rp[j] += h;
         rm[j] -= h;
@@ -330,7 +403,7 @@ static int rk4_doubled(const line_ctx *L, const double y[NY], double t, double o
         double d = (two[q] - one[q]) / 15.0;
         out[q] = two[q] + d;
         if (q < 3) {
-            double g = d / L->f->spacing[q];
+            double g = d / cell_w(L->f, q, L->c[q]);
             e2 += g * g;
         }
     }
@@ -450,9 +523,7 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
     L.nq = m2 ? NY : 5;
     L.way = m2 ? m2->way : 0;
     L.gb = m2 ? m2->gb : NULL;
-    double dmin = f->spacing[0];
-    if (f->spacing[1] < dmin) dmin = f->spacing[1];
-    if (f->spacing[2] < dmin) dmin = f->spacing[2];
+    double dmin = min_width(f);
 
     double y[NY] = {seed[0], seed[1], seed[2], 0.0, 0.0};
     for (int a = 0; a < 3; a++) {
@@ -576,7 +647,7 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
             double plane = 0.0;
             for (int a = 0; a < 3 && a_out < 0; a++) {
                 if (a == a_best) continue;
-                double slack = 1e-12 * f->spacing[a];
+                double slack = 1e-12 * cell_w(f, a, L.c[a]);
                 if (y_best[a] > face_hi(f, L.c, a) + slack) a_out = a, plane = face_hi(f, L.c, a);
                 else if (y_best[a] < face_lo(f, L.c, a) - slack) a_out = a, plane = face_lo(f, L.c, a);
             }
@@ -853,7 +924,7 @@ static void cross(const double a[3], const double b[3], double o[3])
 static int on_box_face(const orc_field *f, const double r[3])
 {
     for (int a = 0; a < 3; a++) {
-        double tol = 1e-12 * f->spacing[a];
+        double tol = 1e-12 * mean_w(f, a);
         if (fabs(r[a] - box_lo(f, a)) <= tol || fabs(box_hi(f, a) - r[a]) <= tol) return 1;
     }
     return 0;

@@ -8,9 +8,11 @@
  * Conventions
  *   - Field: three node planes Bx, By, Bz of n[0] x n[1] x n[2] float64 values,
  *     x fastest: node (i,j,k) at ((k*n[1] + j)*n[0] + i). Node (i,j,k) sits at
- *     origin + (i,j,k) * spacing (uniform Cartesian grid, Section 2.2).
+ *     origin + (i,j,k) * spacing (uniform Cartesian grid, Section 2.2), or, along
+ *     an axis given by its node coordinates, at those (stretched rectilinear grid).
  *   - Lengths are physical (the units of origin/spacing); tolerances are in grid
- *     spacings (the unit the paper uses for tol, Section 2.3).
+ *     spacings (the unit the paper uses for tol, Section 2.3): on a stretched grid,
+ *     in the widths of the cell the step is taken in.
  *   - Faces of the box: 0 = x-, 1 = x+, 2 = y-, 3 = y+, 4 = z-, 5 = z+.
  */
 #ifndef FQ_ORACLE_H
@@ -39,6 +41,9 @@ typedef struct {
     double spacing[3];
     const double *b[3]; /* Bx, By, Bz node planes */
     const double *j[3]; /* curl B node planes (fill with orc_curl) */
+    const double *coord[3]; /* stretched axes (Section 2.2): the n[a] node positions,
+                               strictly increasing; NULL = uniform (origin + i spacing).
+                               On a stretched axis origin and spacing are not used. */
 } orc_field;
 
 typedef struct {

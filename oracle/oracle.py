@@ -32,6 +32,7 @@ class _Field(C.Structure):
         ("spacing", C.c_double * 3),
         ("b", C.c_void_p * 3),
         ("j", C.c_void_p * 3),
+        ("coord", C.c_void_p * 3),
     ]
 
 
@@ -133,6 +134,10 @@ class _FieldHolder:
         f.n[:] = (nx, ny, nz)
         f.origin[:] = tuple(float(x) for x in grid.origin)
         f.spacing[:] = tuple(float(x) for x in grid.spacing)
+        # stretched axes: node coordinates (kept alive here)
+        self.coord = [grid.coord(a) if hasattr(grid, "coord") else None for a in range(3)]
+        for a in range(3):
+            f.coord[a] = self.coord[a].ctypes.data if self.coord[a] is not None else None
         for c in range(3):
             f.b[c] = self.b[c].ctypes.data
         self.j = [np.zeros_like(self.b[0]) for _ in range(3)]

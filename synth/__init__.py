@@ -10,6 +10,9 @@ from .fields import (  # noqa: F401
     Plane,
     Voxels,
     cubic_grid,
+    geometric_axis,
+    clustered_axis,
+    stretched_grid,
     draw_charges,
     charges_field,
     tube_field,
@@ -17,6 +20,8 @@ from .fields import (  # noqa: F401
     quadrupole_field,
     plane_z0,
     config_c1,
+    config_c1s,
+    config_c2s,
     config_c2,
     config_c3,
     config_c4,

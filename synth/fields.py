@@ -4,7 +4,9 @@ Layout convention used everywhere in this repository: a field is a float array o
 shape (3, nz, ny, nx) holding the Bx, By, Bz node planes, x fastest, so node
 (i, j, k) of component c sits at flat offset ((k * ny + j) * nx + i) of plane c.
 Nodes sit at x_i = origin_x + i * dx (likewise y, z): a uniform Cartesian grid,
-the case the paper's trilinear interpolation (Section 2.2) is written for.
+the case the paper's trilinear interpolation (Section 2.2) is written for; or, on a
+stretched axis, at the given node coordinates x_i (a stretched rectilinear grid,
+which the paper's code also accepts).
 
 Everything here is computed in float64 and cast once at the end; the cast array
 *is* the field that both the oracle and the GPU path see.
@@ -26,13 +28,16 @@ import numpy as np
 
 @dataclass
 class Grid:
-    """Uniform node grid: n = (nx, ny, nz) nodes, node (i,j,k) at origin + (i,j,k)*spacing."""
+    """Node grid: n = (nx, ny, nz) nodes, node (i,j,k) at origin + (i,j,k)*spacing;
+    an axis whose entry of `coords` is an array has its nodes there instead
+    (strictly increasing, n values; origin and spacing then unused on that axis)."""
 
     nx: int
     ny: int
     nz: int
     origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     spacing: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    coords: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -40,18 +45,72 @@ class Grid:
 
     @property
     def upper(self) -> Tuple[float, float, float]:
-        return tuple(o + (n - 1) * d for o, n, d in
-                     zip(self.origin, (self.nx, self.ny, self.nz), self.spacing))
+        return tuple(float(x[-1]) for x in self.axes())
+
+    @property
+    def lower(self) -> Tuple[float, float, float]:
+        return tuple(float(x[0]) for x in self.axes())
+
+    def coord(self, a: int) -> Optional[np.ndarray]:
+        """Node coordinates of a stretched axis a, else None."""
+        if self.coords is None or self.coords[a] is None:
+            return None
+        return np.ascontiguousarray(self.coords[a], dtype=np.float64)
+
+    @property
+    def stretched(self) -> bool:
+        return any(self.coord(a) is not None for a in range(3))
 
     def axes(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-        return tuple(o + d * np.arange(n, dtype=np.float64) for o, n, d in
-                     zip(self.origin, (self.nx, self.ny, self.nz), self.spacing))
+        out = []
+        for a, (o, n, d) in enumerate(zip(self.origin, (self.nx, self.ny, self.nz), self.spacing)):
+            c = self.coord(a)
+            out.append(c if c is not None else o + d * np.arange(n, dtype=np.float64))
+        return tuple(out)
 
 
 def cubic_grid(nx: int, ny: int, nz: int) -> Grid:
     """Cubic cells with spacing 1/(nx-1): the x extent is one box unit."""
     d = 1.0 / (nx - 1)
     return Grid(nx, ny, nz, (0.0, 0.0, 0.0), (d, d, d))
+
+
+def geometric_axis(n: int, lo: float, hi: float, ratio: float) -> np.ndarray:
+    """n nodes from lo to hi whose cell widths grow by `ratio` from one cell to the
+    next (ratio 1: uniform)."""
+    w = ratio ** np.arange(n - 1, dtype=np.float64)
+    x = np.concatenate([[0.0], np.cumsum(w)])
+    x = lo + (hi - lo) * x / x[-1]
+    x[-1] = hi
+    return x
+
+
+def clustered_axis(n: int, lo: float, hi: float, centre: float, strength: float) -> np.ndarray:
+    """n nodes from lo to hi, denser around `centre` (a sinh map of a uniform
+    parameter; strength 0: uniform)."""
+    t = np.linspace(-1.0, 1.0, n)
+    if strength == 0:
+        return lo + (hi - lo) * (t + 1) / 2
+    c = (centre - lo) / (hi - lo) * 2 - 1
+    # x(t) = c + sinh(strength (t - t0)) / sinh(strength) scaled so x(-1) = -1, x(1) = 1
+    a = np.arcsinh((1 + c) * math.sinh(strength)) / strength
+    b = np.arcsinh((1 - c) * math.sinh(strength)) / strength
+    tt = -a + (t + 1) / 2 * (a + b)
+    x = c + np.sinh(strength * tt) / math.sinh(strength)
+    x = lo + (hi - lo) * (x + 1) / 2
+    x[0], x[-1] = lo, hi
+    return x
+
+
+def stretched_grid(x: np.ndarray, y: np.ndarray, z: np.ndarray) -> Grid:
+    """A stretched rectilinear grid with the given node coordinates; origin and
+    spacing hold the first node and the mean cell width of each axis."""
+    ax = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, z)]
+    for v in ax:
+        if v.size < 2 or not np.all(np.diff(v) > 0):
+            raise ValueError("node coordinates must be strictly increasing")
+    return Grid(ax[0].size, ax[1].size, ax[2].size, tuple(float(v[0]) for v in ax),
+                tuple(float((v[-1] - v[0]) / (v.size - 1)) for v in ax), tuple(ax))
 
 
 @dataclass
@@ -268,6 +327,38 @@ def config_c1(seed: int = 0, nseed: int = 128) -> Workload:
     B = charges_field(g, pos, q, dtype=np.float64)
     return Workload("c1_quadrupolar_64", g, B, plane=plane_z0(nseed),
                     meta={"charges": (pos, q)})
+
+
+def config_c1s(seed: int = 0, nseed: int = 128) -> Workload:
+    """C1 on a stretched rectilinear grid: 64 x 64 x 64 nodes on [0,1]^3 with x and y
+    clustered around the box centre (cells 0.67x-1.7x the mean width) and z cells
+    growing by 3% per cell upward (0.35x-2.2x); float64, the same 4 seeded charges,
+    cell-centred 128 x 128 seeds on z = 0."""
+    rng = np.random.default_rng(seed)
+    x = clustered_axis(64, 0.0, 1.0, 0.5, 1.6)
+    z = geometric_axis(64, 0.0, 1.0, 1.03)
+    g = stretched_grid(x, x.copy(), z)
+    pos, q = draw_charges(rng, 4)
+    B = charges_field(g, pos, q, dtype=np.float64)
+    return Workload("c1s_quadrupolar_64_stretched", g, B, plane=plane_z0(nseed),
+                    meta={"charges": (pos, q)})
+
+
+def config_c2s(seed: int = 0, nseed: int = 1024) -> Workload:
+    """C2 on a stretched rectilinear grid of the same node counts and box (256 x 256
+    x 128 nodes on [0,1]^2 x [0, 127/255]): x and y clustered around the box centre
+    (cells 0.67x-1.7x the mean width), z cells growing by 1% per cell upward
+    (0.5x-1.75x); float32, the same charges and tube; 1024 x 1024 seeds on z = 0."""
+    rng = np.random.default_rng(seed)
+    x = clustered_axis(256, 0.0, 1.0, 0.5, 1.6)
+    z = geometric_axis(128, 0.0, 127.0 / 255.0, 1.01)
+    g = stretched_grid(x, x.copy(), z)
+    pos, q = draw_charges(rng, 6)
+    B = charges_field(g, pos, q, dtype=np.float64)
+    qt = tube_q_for_turns(0.25, -0.1, 1.5)
+    B += tube_field(g, (0.5, 0.5, -0.1), 0.25, 0.08, 1.0, qt, plane_normal=1)
+    return Workload("c2s_charges6_tube_256x256x128_stretched", g, B.astype(np.float32),
+                    plane=plane_z0(nseed), meta={"charges": (pos, q), "tube_q": qt})
 
 
 def config_c2(seed: int = 0, nseed: int = 1024) -> Workload:

@@ -821,3 +821,135 @@ def test_m2_agrees_with_method1_at_the_same_seeds(orc):
     rn = orc.method2(-B, g, pts, 2, {"tol": 1e-12})
     assert np.allclose(rn["q"][ok], r2["q"][ok], rtol=1e-8)
     assert np.allclose(rn["qperp"][ok], r2["qperp"][ok], rtol=1e-8)
+
+
+# --------------------------------------------------------------------------------------
+# stretched rectilinear grids (Section 2.2: nodes x_i, y_j, z_k, cell by bisection;
+# Eq. interp / w0 / w1 with the cell's own widths)
+# --------------------------------------------------------------------------------------
+
+
+def _stretched(nx, ny, nz, seed=5, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """Strictly increasing random node coordinates: cell widths drawn in [0.3, 1.7]
+    times the mean, so neighbouring cells differ by up to a factor of five."""
+    rng = np.random.default_rng(seed)
+    ax = []
+    for n, a, b in zip((nx, ny, nz), lo, hi):
+        w = rng.uniform(0.3, 1.7, n - 1)
+        x = np.concatenate([[0.0], np.cumsum(w)])
+        x = a + (b - a) * x / x[-1]
+        x[-1] = b
+        ax.append(x)
+    return synth.stretched_grid(*ax)
+
+
+def test_stretched_curl_exact_for_quadratic_field(orc):
+    """On unequal spacings the three-node difference is the derivative of the
+    quadratic through the nodes: exact for quadratic fields at every node, the
+    boundary ones included (a wrong weight or a uniform-spacing formula fails)."""
+    g = _stretched(7, 8, 9, lo=(0.1, -0.2, 0.3), hi=(1.6, 1.2, 1.5))
+    x, y, z = g.axes()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    B = np.stack([X * Y + 2 * Z * Z - Y, Y * Z - 3 * X * X + X * Z, X * Y * 0.5 + Z * X - Y * Y])
+    J = np.stack([(0.5 * X - 2 * Y) - (Y + X), 4 * Z - (0.5 * Y + Z), (-6 * X + Z) - (X - 1)])
+    assert np.max(np.abs(orc.curl(B, g) - J)) < 1e-10
+
+
+def test_stretched_interp_matches_scipy_trilinear(orc):
+    """Eq. interp / w0 / w1 with each cell's own node coordinates, against scipy's
+    linear RegularGridInterpolator on the same rectilinear grid."""
+    from scipy.interpolate import RegularGridInterpolator
+
+    rng = np.random.default_rng(3)
+    g = _stretched(6, 5, 7, lo=(0.0, 1.0, -1.0), hi=(1.5, 3.0, 0.2))
+    B = rng.standard_normal((3,) + g.shape)
+    x, y, z = g.axes()
+    pts = np.stack([rng.uniform(x[0], x[-1], 60), rng.uniform(y[0], y[-1], 60),
+                    rng.uniform(z[0], z[-1], 60)], axis=1)
+    for c in range(3):
+        f = RegularGridInterpolator((x, y, z), np.transpose(B[c], (2, 1, 0)), method="linear")
+        ref = f(pts)
+        for p, r in zip(pts, ref):
+            cell = [min(int(np.searchsorted(ax, p[a], side="right")) - 1, ax.size - 2)
+                    for a, ax in enumerate((x, y, z))]
+            assert abs(orc.interp(B, g, cell, p)[c] - r) < 1e-12
+
+
+def test_stretched_linear_fields_closed_forms(orc):
+    """A field linear in x, y, z is its own trilinear interpolant on any rectilinear
+    grid, and its curl is exact: the closed forms of P1, P3, P4 and P5 hold on a
+    grid whose neighbouring cells differ by up to five times in width. They then
+    bound the cell lookup, the landings on faces at unequal positions and the
+    error norm in each cell's widths."""
+    g = _stretched(13, 12, 15, seed=7)
+    # P1: identity map, Q = 2, length Lz
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    pl = synth.plane_z0(12)
+    r = orc.q2d(B, g, pl)
+    assert np.all(r["status"] & orc.FATAL == 0)
+    assert np.allclose(r["q"], 2.0, atol=1e-10)
+    assert np.allclose(r["len"], 1.0, atol=1e-12)
+    assert np.allclose(r["lines"]["end_f"][:, :2], pl.points()[:, :2], atol=1e-12)
+    # P3: sheared field, Q = 2 + s^2, Tw = -s / (4 pi sqrt(1 + s^2 (y1 - y0)^2))
+    s, y0 = 0.5, 0.5
+    B = linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1])
+    pl = _plane((0.45, 0.3, 0.0), 0.01, n=5)
+    r = orc.q2d(B, g, pl)
+    seeds = pl.points()
+    y1 = seeds[:, 1]
+    assert np.allclose(r["q"], 2 + s * s, rtol=1e-9)
+    assert np.allclose(r["tw"].ravel(), -s / (4 * np.pi * np.sqrt(1 + s * s * (y1 - y0) ** 2)),
+                       atol=1e-11)
+    assert np.allclose(r["lines"]["end_f"][:, 0], seeds[:, 0] + s * (y1 - y0), atol=1e-11)
+    # P4: hyperbolic field, Q = 2 cosh 2kL
+    kL = 3.0
+    xc = yc = 0.5
+    B = linear_field(g, [[kL, 0, 0], [0, -kL, 0], [0, 0, 0]], [-kL * xc, kL * yc, 1])
+    pl = _plane((xc + 0.2 * math.exp(-kL), yc + 0.1, 0.0), 1e-4, n=3)
+    r = orc.q2d(B, g, pl)
+    assert np.all(r["lines"]["face_f"] == 5)
+    assert abs(r["q"][1, 1] / (2 * math.cosh(2 * kL)) - 1) < 1e-6
+    # P5: twisted field, Tw = qL / (2 pi sqrt(1 + q^2 rho^2)), Q = 2
+    q = 2 * math.pi
+    B0 = 0.7
+    B = linear_field(g, [[0, -q * B0, 0], [q * B0, 0, 0], [0, 0, 0]], [q * B0 * yc, -q * B0 * xc, B0])
+    pl = _plane((xc + 0.05, yc, 0.0), 0.002, n=3)
+    r = orc.q2d(B, g, pl)
+    rho = np.hypot(pl.points()[:, 0] - xc, pl.points()[:, 1] - yc)
+    assert np.allclose(r["tw"].ravel(), q / (2 * np.pi * np.sqrt(1 + q * q * rho * rho)), atol=1e-9)
+    assert abs(r["q"][1, 1] - 2.0) < 1e-6
+
+
+def test_stretched_seeds_on_nodes_and_faces(orc):
+    """Seeds exactly on interior node planes and on the top face of a stretched
+    grid: bisection puts a point on node x_i into cell i (the last cell for the last
+    node), so lines start in the right cell and end where the uniform field sends
+    them, with the length of the box above the seed."""
+    g = _stretched(9, 9, 11, seed=11)
+    x, y, z = g.axes()
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    seeds = np.array([[x[3], y[4], z[2]], [x[0], y[8], z[5]], [x[8], y[0], z[10]],
+                      [0.5 * (x[1] + x[2]), y[7], z[9]]])
+    r = orc.trace(B, g, seeds)
+    # seeds 1 and 2 lie on box faces, so their lines run along box edges (EDGE bit)
+    assert np.all((r["status"] & orc.FATAL) == 0)
+    assert np.allclose(r["end_f"][:, :2], seeds[:, :2], atol=1e-14)
+    assert np.allclose(r["end_f"][:, 2], z[-1], atol=0) and np.allclose(r["end_b"][:, 2], z[0], atol=0)
+    assert np.allclose(r["len"], z[-1] - z[0], atol=1e-12)
+
+
+def test_stretched_with_uniform_nodes_equals_uniform(orc, charge_cube):
+    """A grid whose node coordinates are given explicitly but are uniform is the
+    uniform grid: the stretched code paths give the uniform ones' map (Q, Tw,
+    footpoints) to within the integrators' tolerance."""
+    g, B = charge_cube
+    gs = synth.stretched_grid(*g.axes())
+    pl = _plane((0.4, 0.55, 0.0), 0.01, n=6)
+    ru = orc.q2d(B, g, pl)
+    rs = orc.q2d(B, gs, pl)
+    m = (ru["status"] & orc.FATAL) == 0
+    assert m.all() and np.array_equal(ru["status"], rs["status"])
+    assert np.allclose(rs["q"], ru["q"], rtol=1e-7)
+    assert np.allclose(rs["tw"], ru["tw"], atol=1e-9)
+    for k in ("end_b", "end_f"):
+        assert np.allclose(rs["lines"][k], ru["lines"][k], atol=1e-9)
