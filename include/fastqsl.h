@@ -81,7 +81,19 @@ extern "C" {
                                was traced (set with FQ_ST_MAXSTEPS; the line has no outputs
                                and no derivative; raise fq_params.tape_steps) */
 
-/* A field: three device planes of n[0]*n[1]*n[2] values of type `dtype`. */
+/* A field: three device planes of n[0]*n[1]*n[2] values of type `dtype`, on a
+ * uniform grid (node (i,j,k) at origin + (i,j,k) spacing) or a stretched rectilinear
+ * one (Section 2.2): an axis a with coord[a] set has its nodes at coord[a][0..n[a]-1]
+ * (device, FP64, strictly increasing and finite; read by the call, which copies
+ * nothing). On such an axis origin[a] must be the first node and origin[a] +
+ * (n[a]-1) spacing[a] the last (spacing[a] is the mean cell width: the box extent
+ * stays known to the host). On a stretched grid the per-step error bound is taken in
+ * the widths of the cell the step is in, and the first step of Eq. step is scaled by
+ * the seed cell's width along B (Section 2.3, the scaling of step and tol on
+ * stretched grids). A field whose node coordinates are not strictly increasing and
+ * finite, or do not span the box that origin and spacing give (to 1e-12 of its
+ * extent), gives its lines FQ_ST_NONFINITE. Method II and the adjoint take uniform
+ * grids only (else FQ_EUNSUPPORTED). */
 typedef struct {
     int64_t n[3];         /* nodes along x, y, z; each in [2, 65535] */
     double origin[3];     /* position of node (0,0,0) */
@@ -89,6 +101,8 @@ typedef struct {
     int32_t dtype;        /* FQ_DT_F32 or FQ_DT_F64 */
     int32_t reserved;
     const void *b[3];     /* device: Bx, By, Bz planes */
+    const double *coord[3]; /* device, optional: node coordinates of a stretched axis (NULL =
+                               uniform axis) */
 } fq_field;
 
 /* Tracing parameters (Section 2.3 and the S0 rules of Section 4).

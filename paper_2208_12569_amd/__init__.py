@@ -17,6 +17,8 @@ import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
+
 from . import _lib
 from ._lib import (  # noqa: F401
     FQ_PREC_F32X,
@@ -113,7 +115,38 @@ def _field(B, grid) -> _lib.fq_field:
     f.dtype = _lib.FQ_DT_F32 if B.dtype == torch.float32 else _lib.FQ_DT_F64
     for c in range(3):
         f.b[c] = B[c].data_ptr()
+    for a, t in enumerate(_coords(grid, B.device)):
+        f.coord[a] = t.data_ptr() if t is not None else None
     return f
+
+
+def _coords(grid, device):
+    """Device FP64 node coordinates of a grid's stretched axes (None per uniform
+    axis). A grid may carry them as CUDA tensors already; numpy coordinates are
+    copied once per device and kept on the grid object, so their device memory
+    lives as long as the grid (the library reads them asynchronously, also from
+    captured graphs)."""
+    torch = _torch()
+    coords = getattr(grid, "coords", None)
+    if coords is None:
+        return (None, None, None)
+    cache = grid.__dict__.setdefault("_fq_device_coords", {})
+    out = []
+    for a in range(3):
+        c = coords[a]
+        if c is None:
+            out.append(None)
+            continue
+        if isinstance(c, torch.Tensor) and c.is_cuda:
+            if c.dtype != torch.float64 or not c.is_contiguous() or c.device != device:
+                raise ValueError("device node coordinates must be contiguous float64 on B's device")
+            out.append(c)
+            continue
+        key = (str(device), a)
+        if key not in cache:
+            cache[key] = torch.as_tensor(np.ascontiguousarray(c, dtype=np.float64)).to(device)
+        out.append(cache[key])
+    return tuple(out)
 
 
 def _plane(pl) -> _lib.fq_plane:

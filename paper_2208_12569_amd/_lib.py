@@ -42,7 +42,8 @@ ST_FATAL = ST_OUTSIDE | ST_NULLB | ST_MAXSTEPS | ST_NONFINITE
 
 class fq_field(C.Structure):
     _fields_ = [("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
-                ("dtype", C.c_int32), ("reserved", C.c_int32), ("b", C.c_void_p * 3)]
+                ("dtype", C.c_int32), ("reserved", C.c_int32), ("b", C.c_void_p * 3),
+                ("coord", C.c_void_p * 3)]
 
 
 class fq_params(C.Structure):

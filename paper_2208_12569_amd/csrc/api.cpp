@@ -43,6 +43,8 @@ struct Spec {
 
 int64_t nodes_of(const fq_field *f) { return f->n[0] * f->n[1] * f->n[2]; }
 
+bool stretched(const fq_field *f) { return f->coord[0] || f->coord[1] || f->coord[2]; }
+
 int64_t lines_of(const Spec &s)
 {
     switch (s.kind) {
@@ -59,10 +61,12 @@ int check_field(const fq_field *f)
     if (!f) return FQ_EINVAL;
     for (int a = 0; a < 3; a++) {
         if (f->n[a] < 2 || f->n[a] > 65535) return FQ_EINVAL;  // grid extents of the prep pass
-        if (!(f->spacing[a] > 0.0) || !isfinite(f->spacing[a])) return FQ_EINVAL;
         if (!f->b[a]) return FQ_EINVAL;
+        // on a stretched axis these give the box extent (the geometry pass checks them
+        // against the node coordinates)
+        if (!(f->spacing[a] > 0.0) || !isfinite(f->spacing[a])) return FQ_EINVAL;
+        if (!isfinite(f->origin[a])) return FQ_EINVAL;
     }
-    if (!finite3(f->origin)) return FQ_EINVAL;
     if (f->dtype != FQ_DT_F32 && f->dtype != FQ_DT_F64) return FQ_EINVAL;
     if (nodes_of(f) > ((int64_t)1 << 40)) return FQ_EINVAL;
     return FQ_OK;
@@ -145,6 +149,7 @@ bool plane_on_face(const fq_plane &pl, const fq_field &f)
 struct SpecWs {
     size_t nodes, bmax, end, tw, len, face, st;
     size_t uv;  // Method II: tangent vectors at the half lines' ends
+    size_t iw[3], geo;  // stretched grids: per-cell 1 / width per axis, and the Geo record
     size_t tile_order, tile_bucket, tile_counts;  // plane jobs
     size_t nodes64;  // FP64 node records for the FP64 pass (FP64 grids only)
     size_t rot_index, rot, rot_count, r_end, r_tw, r_len, r_face, r_st;
@@ -181,6 +186,7 @@ void set_map_geometry(const Spec &s, MapJob &m)
         m.n[a] = (int32_t)f.n[a];
         m.origin[a] = f.origin[a];
         m.spacing[a] = f.spacing[a];
+        m.coord[a] = f.coord[a];
     }
     m.dtype = f.dtype;
     if (s.kind == SPEC_PLANE) {
@@ -249,6 +255,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     for (int i = 0; i < ns; i++)
         if (specs[i].kind == SPEC_LIST) m2 = false;
     if (m2 && (P.scheme != FQ_SCHEME_RKF45 || bwd)) return FQ_EUNSUPPORTED;
+    for (int i = 0; i < ns; i++)
+        if (stretched(specs[i].f) && (m2 || bwd)) return FQ_EUNSUPPORTED;
     Carve cv;
     // queue counters: +0 the tracer (u64, u32 spare), +64 the reverse pass, +128 the
     // checkpoint pool, +192 the FP64 pass over half lines that need their twist
@@ -271,6 +279,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             w.tile_counts = cv.take(256 * sizeof(uint32_t));
         }
         if (m2) w.uv = cv.take((size_t)(2 * w.nlines) * 6 * sizeof(double));
+        if (stretched(s.f)) {
+            for (int a = 0; a < 3; a++) w.iw[a] = cv.take((size_t)(s.f->n[a] - 1) * sizeof(double));
+            w.geo = cv.take(sizeof(Geo));
+        }
         w.rotate = !m2 && ((s.kind == SPEC_VOXELS) || (s.kind == SPEC_PLANE && !plane_on_face(s.pl, *s.f)));
         if (w.rotate) {
             nrot++;
@@ -348,6 +360,11 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         SpecWs &w = W[i];
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.bmax), 1, 0u, stream));
         if (w.rotate) FQ_TRY(launch_fill_u32((uint32_t *)(ws + w.rot_count), 1, 0u, stream));
+        if (stretched(s.f)) {
+            double *const iw[3] = {(double *)(ws + w.iw[0]), (double *)(ws + w.iw[1]),
+                                   (double *)(ws + w.iw[2])};
+            FQ_TRY(launch_geometry(*s.f, iw, (Geo *)(ws + w.geo), stream));
+        }
         FQ_TRY(launch_prep(*s.f, P.precision, P.want_tw, ws + w.nodes, (float *)(ws + w.bmax), stream));
         if (fixup && fix_store == FQ_DT_F64)
             FQ_TRY(launch_prep(*s.f, FQ_PREC_F64, P.want_tw, ws + w.nodes64, (float *)(ws + w.bmax),
@@ -402,8 +419,13 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             J.planes.n[a] = (int32_t)s.f->n[a];
             J.planes.origin[a] = s.f->origin[a];
             J.planes.spacing[a] = s.f->spacing[a];
+            J.planes.coord[a] = s.f->coord[a];
         }
         J.planes.dtype = s.f->dtype;
+        if (stretched(s.f)) {
+            for (int a = 0; a < 3; a++) J.iw[a] = (const double *)(ws + w.iw[a]);
+            J.geo = (const Geo *)(ws + w.geo);
+        }
         if (s.kind == SPEC_LIST) {
             J.kind = SEED_LIST;
             J.seeds = s.seeds;
@@ -490,6 +512,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.tol_floor = P.tol_floor;
     tp.scheme = P.scheme;
     tp.method = m2 ? FQ_METHOD_II : FQ_METHOD_I;
+    for (int i = 0; i < ns; i++)
+        if (stretched(specs[i].f)) tp.stretched = 1;
     tp.max_steps = P.max_steps;
     tp.want_tw = P.want_tw;
     tp.njobs = njobs;
@@ -671,6 +695,7 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
     if (rc) return rc;
     if (P.precision != FQ_PREC_F64 || P.scheme != FQ_SCHEME_RKF45 || P.method != FQ_METHOD_I)
         return FQ_EUNSUPPORTED;
+    if (f && stretched(f)) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;
     if (!plane_on_face(*pl, *f)) return FQ_EUNSUPPORTED;

@@ -1,6 +1,7 @@
 // FP64 trilinear interpolation (Section 2.2, Eq. interp) straight from the caller's
 // node planes, for the quantities kept in FP64: the normal fields entering Q and
-// the field angles that send a line to the FP64 pass.
+// the field angles that send a line to the FP64 pass. Uniform and stretched
+// rectilinear grids.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,7 +15,41 @@ struct Planes64 {
     int32_t dtype;  // FQ_DT_F32 / FQ_DT_F64
     int32_t n[3];
     double origin[3], spacing[3];
+    const double *coord[3];  // node coordinates of stretched axes (NULL = uniform axis)
 };
+
+// The cell of a stretched axis holding r: the last of the n nodes x at or below r,
+// kept in [0, n-2] (bisection, Section 2.2). A point below the first node takes cell
+// 0 and one at or above the last node cell n-2 (whose polynomial is then extended).
+__host__ __device__ __forceinline__ int axis_cell(const double *x, int n, double r)
+{
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (x[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Box extent and a typical cell width along axis a of a grid description (Planes64,
+// MapJob: anything with n, origin, spacing and coord).
+template <typename G>
+__host__ __device__ __forceinline__ double axis_lo(const G &g, int a)
+{
+    return g.coord[a] ? g.coord[a][0] : g.origin[a];
+}
+template <typename G>
+__host__ __device__ __forceinline__ double axis_hi(const G &g, int a)
+{
+    return g.coord[a] ? g.coord[a][g.n[a] - 1] : g.origin[a] + (g.n[a] - 1) * g.spacing[a];
+}
+template <typename G>
+__host__ __device__ __forceinline__ double axis_width(const G &g, int a)
+{
+    return g.coord[a] ? (g.coord[a][g.n[a] - 1] - g.coord[a][0]) / (double)(g.n[a] - 1)
+                      : g.spacing[a];
+}
 
 template <typename S>
 __device__ __forceinline__ void interp64_t(const Planes64 &m, const double r[3], double B[3])
@@ -23,6 +58,13 @@ __device__ __forceinline__ void interp64_t(const Planes64 &m, const double r[3],
     int c[3];
     double t[3];
     for (int a = 0; a < 3; a++) {
+        if (m.coord[a]) {
+            const double *x = m.coord[a];
+            const int ci = axis_cell(x, m.n[a], r[a]);
+            c[a] = ci;
+            t[a] = (r[a] - x[ci]) / (x[ci + 1] - x[ci]);
+            continue;
+        }
         const double g = (r[a] - m.origin[a]) / m.spacing[a];
         int ci = (int)floor(g);
         ci = ci < 0 ? 0 : (ci > m.n[a] - 2 ? m.n[a] - 2 : ci);

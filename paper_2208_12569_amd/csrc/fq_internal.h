@@ -36,6 +36,14 @@ struct HalfRecs {
     double *uv;    // Method II: 2 * nlines * 6, the tangent vectors U, V at the end (else NULL)
 };
 
+// Stretched grids: what the geometry pass finds on the device.
+struct Geo {
+    double dref;   // smallest cell width over the three axes (the tracer's length unit)
+    int32_t bad;   // nonzero: node coordinates not strictly increasing and finite, or not
+                   // spanning the box that origin and spacing give
+    int32_t pad;
+};
+
 // One independent tracing job: a prepared field plus a seed set.
 struct TraceJob {
     const void *nodes;   // node records in the compute type: (Bx, By, Bz, Jx, Jy, Jz, 0, 0)
@@ -63,10 +71,15 @@ struct TraceJob {
     int64_t item_base;   // first queue item of the job (items of both halves follow)
     const int32_t *tile_order;  // plane jobs: tiles in the order they are traced (may be NULL)
     Planes64 planes;     // the caller's field, for FP64 angles in the grazing test
+    // stretched grids (NULL on a uniform grid): per-cell 1 / width of every axis (a
+    // uniform axis repeats 1 / spacing) and the grid's reference length; the node
+    // coordinates of the stretched axes themselves are in planes.coord
+    const double *iw[3];
+    const Geo *geo;
     // precomputed per-job constants of the tracer
-    float rscale[3];     // reference length / spacing per axis
-    float twk;           // reference length / (4 pi)
-    double dref;         // reference length (smallest spacing)
+    float rscale[3];     // reference length / spacing per axis (uniform grids)
+    float twk;           // reference length / (4 pi) (uniform grids)
+    double dref;         // reference length (smallest spacing; uniform grids)
     double inv_spacing[3];
     double inv_t0, inv_t1; // 1 / tiles[0], 1 / tiles[1] (tile decode)
 };
@@ -113,7 +126,7 @@ struct TraceParams {
     int32_t list_rev;              // list mode: entry k sits at list[list_cap - 1 - k]
     int32_t scheme;                // integration scheme (FQ_SCHEME_*)
     int32_t method;                // FQ_METHOD_I or FQ_METHOD_II (tangent vectors carried)
-    int32_t pad4;
+    int32_t stretched;             // some job's grid is stretched (multi-job kernels then)
     // adjoint forward pass (FP64, single job): checkpoints every `seg` accepted steps
     Ckpt *tape;                    // checkpoint pool of pool_cap entries
     unsigned long long *pool_ctr;  // next free pool slot
@@ -148,6 +161,16 @@ struct BwdParams {
 hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodes, float *bmax2,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// Stretched grids: the geometry pass (per-cell 1 / width of all three axes into
+// iw[a][0 .. n[a]-2], and *geo).
+struct GeoIn {
+    const double *coord[3];
+    int32_t n[3];
+    int32_t pad;
+    double spacing[3];
+    double origin[3];
+};
+hipError_t launch_geometry(const fq_field &f, double *const iw[3], Geo *geo, hipStream_t s);
 hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 // prec: compute type (FQ_PREC_F32X = float, FQ_PREC_F64 = double);
 // store: node-record type (FQ_DT_F32 / FQ_DT_F64);
@@ -180,6 +203,7 @@ struct MapJob {
     int32_t dtype;
     int32_t n[3];
     double origin[3], spacing[3];
+    const double *coord[3];  // node coordinates of stretched axes (NULL = uniform axis)
     int64_t nu, nv, nlayers;     // points per layer = nu*nv
     double d0, d1;               // seed spacing along the two S0 axes
     double normal[3];            // S0 normal

@@ -64,8 +64,8 @@ __device__ __forceinline__ double q_nb(const MapJob &m, const Line &c, const Nb 
 __device__ __forceinline__ bool on_box_face(const MapJob &m, const double r[3])
 {
     for (int a = 0; a < 3; a++) {
-        const double tol = 1e-12 * m.spacing[a];
-        const double lo = m.origin[a], hi = m.origin[a] + (m.n[a] - 1) * m.spacing[a];
+        const double tol = 1e-12 * axis_width(m, a);
+        const double lo = axis_lo(m, a), hi = axis_hi(m, a);
         if (fabs(r[a] - lo) <= tol || fabs(hi - r[a]) <= tol) return true;
     }
     return false;
@@ -83,7 +83,7 @@ __global__ void classify_kernel(MapJob m, int32_t *rot_index, RotEntry *rot,
         point_pos(m, i, j, k, r);
         bool inside = true;
         for (int a = 0; a < 3; a++) {
-            const double lo = m.origin[a], hi = m.origin[a] + (m.n[a] - 1) * m.spacing[a];
+            const double lo = axis_lo(m, a), hi = axis_hi(m, a);
             if (!(r[a] >= lo && r[a] <= hi)) inside = false;
         }
         if (inside && !on_box_face(m, r)) {

@@ -20,6 +20,7 @@ __device__ __forceinline__ void field64(const MapJob &m, const double r[3], doub
         P.n[a] = m.n[a];
         P.origin[a] = m.origin[a];
         P.spacing[a] = m.spacing[a];
+        P.coord[a] = m.coord[a];
     }
     P.dtype = m.dtype;
     interp64(P, r, B);
@@ -72,7 +73,7 @@ __device__ __forceinline__ bool edge_end(const MapJob &m, int face, const double
     const int a = face >> 1;
     for (int b = 0; b < 3; b++) {
         if (b == a) continue;
-        const double lo = m.origin[b], hi = m.origin[b] + (m.n[b] - 1) * m.spacing[b];
+        const double lo = axis_lo(m, b), hi = axis_hi(m, b);
         if (e[b] - lo < m.edge_eps || hi - e[b] < m.edge_eps) return true;
     }
     return false;

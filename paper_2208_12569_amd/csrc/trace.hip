@@ -118,6 +118,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
         K.twk = (T)J0.twk;
         K.bnull2 = (T)((double)N::null_rel * (double)(*J0.bmax2));
     }
+    // stretched grids (jobs of the multi-job kernels only, which the launcher picks
+    // for them): the per-cell scales follow the lane's cell; the length unit is the
+    // grid's smallest cell width, found on the device
+    bool str = false;
+    double dref_s = 0.0;
     T cb[3][8], cj[3][8];
     Tan<T> tn;  // Method II
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
@@ -186,6 +191,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                             K.rz = (T)J.rscale[2];
                             K.twk = (T)J.twk;
                             K.bnull2 = (T)((double)N::null_rel * (double)(*J.bmax2));
+                            str = J.geo != nullptr;
+                            if (!UNI && str) {
+                                dref_s = J.geo->dref;
+                                K.twk = (T)(dref_s * (0.25 / M_PI));
+                            }
                         }
                         rec = (forward ? J.nlines : 0) + line;
                         L.sgn = forward ? T(1) : T(-1);
@@ -196,21 +206,46 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                         acc_half = 0;
                         nck = 0;
                         last_ck = -1;
-                        const double g0 = (r[0] - J.origin[0]) * J.inv_spacing[0],
-                                     g1 = (r[1] - J.origin[1]) * J.inv_spacing[1],
-                                     g2 = (r[2] - J.origin[2]) * J.inv_spacing[2];
-                        if (!(g0 >= 0.0 && g0 <= (double)(K.nx - 1) && g1 >= 0.0 &&
-                              g1 <= (double)(K.ny - 1) && g2 >= 0.0 && g2 <= (double)(K.nz - 1))) {
-                            fin_st = FQ_ST_OUTSIDE;
-                        } else {
-                            L.c0 = min(max((int)floor(g0), 0), K.nx - 2);
-                            L.c1 = min(max((int)floor(g1), 0), K.ny - 2);
-                            L.c2 = min(max((int)floor(g2), 0), K.nz - 2);
-                            L.p0 = (T)(g0 - L.c0);
-                            L.p1 = (T)(g1 - L.c1);
-                            L.p2 = (T)(g2 - L.c2);
-                            need_load = true;
-                            fresh = true;
+                        if (!UNI && str) {
+                            // stretched: the seed's cell by bisection on each axis
+                            bool in = !J.geo->bad;
+                            for (int a = 0; a < 3; a++) {
+                                const FQ_GLOBAL double *x = gptr(J.planes.coord[a]);
+                                if (x) in = in && r[a] >= x[0] && r[a] <= x[J.n[a] - 1];
+                                else in = in && r[a] >= J.origin[a] &&
+                                          r[a] <= J.origin[a] + (J.n[a] - 1) * J.spacing[a];
+                            }
+                            if (!in) {
+                                fin_st = J.geo->bad ? FQ_ST_NONFINITE : FQ_ST_OUTSIDE;
+                            } else {
+                                double q0, q1, q2;
+                                L.c0 = str_cell(J, 0, r[0], q0);
+                                L.c1 = str_cell(J, 1, r[1], q1);
+                                L.c2 = str_cell(J, 2, r[2], q2);
+                                L.p0 = (T)q0;
+                                L.p1 = (T)q1;
+                                L.p2 = (T)q2;
+                                need_load = true;
+                                fresh = true;
+                            }
+                        }
+                        if (UNI || !str) {
+                            const double g0 = (r[0] - J.origin[0]) * J.inv_spacing[0],
+                                         g1 = (r[1] - J.origin[1]) * J.inv_spacing[1],
+                                         g2 = (r[2] - J.origin[2]) * J.inv_spacing[2];
+                            if (!(g0 >= 0.0 && g0 <= (double)(K.nx - 1) && g1 >= 0.0 &&
+                                  g1 <= (double)(K.ny - 1) && g2 >= 0.0 && g2 <= (double)(K.nz - 1))) {
+                                fin_st = FQ_ST_OUTSIDE;
+                            } else {
+                                L.c0 = min(max((int)floor(g0), 0), K.nx - 2);
+                                L.c1 = min(max((int)floor(g1), 0), K.ny - 2);
+                                L.c2 = min(max((int)floor(g2), 0), K.nz - 2);
+                                L.p0 = (T)(g0 - L.c0);
+                                L.p1 = (T)(g1 - L.c1);
+                                L.p2 = (T)(g2 - L.c2);
+                                need_load = true;
+                                fresh = true;
+                            }
                         }
                     }
                 }
@@ -222,6 +257,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             load_cell<T, S, TW, TWM != 0>(nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             need_load = false;
             n_fetch++;
+            if (!UNI && str) {
+                // stretched grid: this cell's widths scale the direction into local
+                // coordinates (reference length / width per axis)
+                const TraceJob &J = jobs[UNI ? 0 : jb];
+                K.rx = (T)(dref_s * gptr(J.iw[0])[L.c0]);
+                K.ry = (T)(dref_s * gptr(J.iw[1])[L.c1]);
+                K.rz = (T)(dref_s * gptr(J.iw[2])[L.c2]);
+            }
             if (fresh) {
                 // Eq. step and Eq. tol from the field angle |Bn0/B| at the seed
                 fresh = false;
@@ -247,6 +290,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 if (!(ang >= amin)) ang = amin;  // also catches NaN
                 if (ang > 1.0f) ang = 1.0f;
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
+                if (!UNI && str) {
+                    // stretched grid: the first step in units of the seed cell's width
+                    // along B, 1 / |(b_x / dx, b_y / dy, b_z / dz)| (Section 2.3)
+                    const float sx = bx * (float)K.rx, sy = by * (float)K.ry, sz = bz * (float)K.rz;
+                    const float w2 = sx * sx + sy * sy + sz * sz;
+                    if (w2 > 0.0f) L.h = (T)((float)L.h * sqrtf(b2 / w2));
+                }
                 // a fixed-step scheme keeps its step where RKF45 keeps its bound
                 L.tol = SCH != SCH_RKF45 ? L.h : (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
                 if constexpr (M2) {
@@ -314,6 +364,10 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 e0 = r[0];
                 e1 = r[1];
                 e2 = r[2];
+            } else if (!bad && !UNI && str) {
+                e0 = grid_pos(J, 0, L.c0, (double)L.p0);
+                e1 = grid_pos(J, 1, L.c1, (double)L.p1);
+                e2 = grid_pos(J, 2, L.c2, (double)L.p2);
             } else if (!bad) {
                 e0 = J.origin[0] + ((double)L.c0 + (double)L.p0) * J.spacing[0];
                 e1 = J.origin[1] + ((double)L.c1 + (double)L.p1) * J.spacing[1];
@@ -324,7 +378,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             ge[3 * rec + 1] = e1;
             ge[3 * rec + 2] = e2;
             if (TWM != 2) gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
-            gptr(J.rec.len)[rec] = bad ? NAN : L.len * J.dref;
+            gptr(J.rec.len)[rec] = bad ? NAN : L.len * ((!UNI && str) ? dref_s : J.dref);
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
             if constexpr (M2) {
@@ -522,10 +576,18 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
 {
     const typename V4<R>::t *A = gptr((const typename V4<R>::t *)J.nodes);
     const int64_t ntiles = J.tiles[0] * J.tiles[1];
-    const double dmin = fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
+    // stretched grids: grid coordinates run through the cells at their own widths,
+    // so a coarse step's size in grid units follows the cell it starts in
+    const bool str = J.geo != nullptr;
+    const double dmin = str ? J.geo->dref : fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
     const int n[3] = {J.n[0], J.n[1], J.n[2]};
     float hs[3];  // a coarse step along a unit direction, in grid units per axis
     for (int a = 0; a < 3; a++) hs[a] = (float)(kCoarseCells * dmin / J.spacing[a]);
+    auto step_of = [&](int a, float ga) -> float {
+        if (!str) return hs[a];
+        const int c = min(max((int)floorf(ga), 0), n[a] - 2);
+        return (float)(kCoarseCells * dmin * J.iw[a][c]);
+    };
     const int sw[5] = {0, 7, 56, 63, 36};
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 10 * ntiles;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -541,6 +603,14 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
         bool inside = true;
         for (int a = 0; a < 3; a++) {
             const double r = J.s_origin[a] + (double)i * J.s_a[a] + (double)j * J.s_b[a];
+            if (str && J.planes.coord[a]) {
+                const double *x = J.planes.coord[a];
+                inside = inside && r >= x[0] && r <= x[n[a] - 1];
+                double p;
+                const int c = str_cell(J, a, r, p);
+                g[a] = (float)((double)c + p);
+                continue;
+            }
             g[a] = (float)((r - J.origin[a]) * J.inv_spacing[a]);
             inside = inside && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
         }
@@ -551,13 +621,13 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
                 coarse_field<R, WIDE>(A, n, g, B);
                 const float bm = sqrtf(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
                 if (!(bm > 0.0f) || !isfinite(bm)) break;
-                for (int a = 0; a < 3; a++) gm[a] = g[a] + 0.5f * sgn * hs[a] * B[a] / bm;
+                for (int a = 0; a < 3; a++) gm[a] = g[a] + 0.5f * sgn * step_of(a, g[a]) * B[a] / bm;
                 coarse_field<R, WIDE>(A, n, gm, B2);
                 const float bm2 = sqrtf(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
                 if (!(bm2 > 0.0f) || !isfinite(bm2)) break;
                 bool in = true;
                 for (int a = 0; a < 3; a++) {
-                    g[a] += sgn * hs[a] * B2[a] / bm2;
+                    g[a] += sgn * step_of(a, gm[a]) * B2[a] / bm2;
                     in = in && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
                 }
                 if (!in) break;
@@ -668,7 +738,8 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     if (block <= 0) block = 256;
     const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
     if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
-    const bool uni = tp.njobs == 1 && !tp.dynamic_last;
+    // stretched grids take the multi-job kernels, which carry their per-cell scales
+    const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched;
     if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
         // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, RKF45

@@ -109,6 +109,34 @@ __device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, do
     }
 }
 
+// Axis a of a job on a stretched grid: the cell holding coordinate r (bisection in
+// the node coordinates of a stretched axis, Section 2.2; the floor of the grid
+// coordinate on a uniform one) and the local coordinate in it, within [0, 1].
+__device__ __forceinline__ int str_cell(const TraceJob &J, int a, double r, double &p)
+{
+    if (!J.planes.coord[a]) {
+        const double g = (r - J.origin[a]) * J.inv_spacing[a];
+        const int c = min(max((int)floor(g), 0), J.n[a] - 2);
+        p = g - c;
+        return c;
+    }
+    const FQ_GLOBAL double *x = gptr(J.planes.coord[a]);
+    const int c = axis_cell((const double *)x, J.n[a], r);
+    // a point on the cell's upper node (the box's last node) is at exactly 1
+    const double t = r == x[c + 1] ? 1.0 : (r - x[c]) * gptr(J.iw[a])[c];
+    p = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    return c;
+}
+
+// The position along axis a of local coordinate p in cell c of job J's grid.
+__device__ __forceinline__ double grid_pos(const TraceJob &J, int a, int c, double p)
+{
+    const double *x = J.planes.coord[a];
+    if (!x) return J.origin[a] + ((double)c + p) * J.spacing[a];
+    const FQ_GLOBAL double *xg = gptr(x);
+    return xg[c] + p * (xg[c + 1] - xg[c]);
+}
+
 // floor(n / d) for 0 <= n < 2^31 with a precomputed 1/d (one FP64 multiply and
 // an exact integer correction)
 __device__ __forceinline__ int64_t fdiv(int64_t n, int64_t d, double inv_d, int64_t &rem)

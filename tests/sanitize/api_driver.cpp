@@ -131,6 +131,26 @@ int main()
                 CHECK(n3 > 0);
                 CHECK(fastqsl_q3d(&f[0], &vx, &P3, &m3, workspace(n3), n3, nullptr) == FQ_OK);
             }
+            // stretched grids: one stretched axis, and all three, in q2d (alone and in a
+            // batch with a uniform job) and q3d; Method II there is unsupported
+            {
+                fq_field fs[2] = {field(33, 30, 17, dt), field(9, 9, 9, dt)};
+                fs[0].coord[2] = (const double *)fake_dev;
+                for (int all = 0; all < 2; all++) {
+                    if (all) fs[0].coord[0] = fs[0].coord[1] = (const double *)fake_dev;
+                    for (int nj = 1; nj <= 2; nj++) {
+                        size_t ns_ = fastqsl_q2d_workspace_size(fs, pl, nj, &P);
+                        CHECK(ns_ > 0);
+                        CHECK(fastqsl_q2d(fs, pl, nj, &P, m, workspace(ns_), ns_, nullptr) == FQ_OK);
+                    }
+                    size_t n3 = fastqsl_q3d_workspace_size(&fs[0], &vx, &P);
+                    CHECK(n3 > 0);
+                    CHECK(fastqsl_q3d(&fs[0], &vx, &P, &m3, workspace(n3), n3, nullptr) == FQ_OK);
+                    fq_params P4 = P;
+                    P4.method = FQ_METHOD_II;
+                    CHECK(fastqsl_q2d_workspace_size(fs, pl, 1, &P4) == 0);
+                }
+            }
             // trace lists, including an empty one
             fq_lines L;
             memset(&L, 0, sizeof L);
@@ -161,6 +181,9 @@ int main()
                                                 nullptr, gb, ws, need, nullptr) == FQ_OK);
                 CHECK(fastqsl_backward_workspace_size(&f[0], &mid, &P, 32) == 0);
                 CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 0) == 0);
+                fq_field fst = f[0];
+                fst.coord[1] = (const double *)fake_dev;
+                CHECK(fastqsl_backward_workspace_size(&fst, &pl[0], &P, 32) == 0);
                 P.tape_steps = 100000;
                 size_t big = fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 32);
                 CHECK(big > need);

@@ -31,6 +31,13 @@ hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodes, fl
     g_calls++;
     return hipSuccess;
 }
+hipError_t launch_geometry(const fq_field &f, double *const iw[3], Geo *geo, hipStream_t)
+{
+    for (int a = 0; a < 3; a++) in_ws(iw[a], (size_t)(f.n[a] - 1) * sizeof(double), "geometry widths");
+    in_ws(geo, sizeof(Geo), "geometry record");
+    g_calls++;
+    return hipSuccess;
+}
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t, hipStream_t)
 {
     in_ws(p, (size_t)n * 4, "fill");
