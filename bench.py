@@ -98,12 +98,13 @@ def traffic_from_profile(workload: str, prec: str):
     return None
 
 
-def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
+def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int, method: int = 0):
     import torch
 
     import paper_2208_12569_amd as fq
 
     prec = fq.FQ_PREC_F64 if prec_name == "f64" else fq.FQ_PREC_F32X
+    mk = {"method": method}
     B = torch.from_numpy(w.field).cuda()
     torch.cuda.synchronize()
     stats = torch.zeros(5, dtype=torch.int64, device="cuda")
@@ -114,7 +115,7 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
         c0 = torch.cuda.Event(enable_timing=True)
         c1 = torch.cuda.Event(enable_timing=True)
         c0.record()
-        r = fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec, tol_perp=tol), ws=ws)
+        r = fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec, tol_perp=tol, **mk), ws=ws)
         c1.record()
         c1.synchronize()
         if first_ms is None:
@@ -132,7 +133,7 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
     marks[0].record()
     for k in range(steps):
         r = fq.q2d(B, w.grid, w.plane,
-                   fq.Params(precision=prec, tol_perp=tol, stats=stats, events=evs[k]), ws=ws)
+                   fq.Params(precision=prec, tol_perp=tol, stats=stats, events=evs[k], **mk), ws=ws)
         marks[k + 1].record()
     t1.record()
     torch.cuda.synchronize()
@@ -148,7 +149,8 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
     st32 = st
     if prec == fq.FQ_PREC_F32X:
         s32 = torch.zeros(5, dtype=torch.int64, device="cuda")
-        fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec, tol_perp=tol, graze=-1.0, stats=s32), ws=ws)
+        fq.q2d(B, w.grid, w.plane, fq.Params(precision=prec, tol_perp=tol, graze=-1.0, stats=s32, **mk),
+               ws=ws)
         torch.cuda.synchronize()
         st32 = [int(x) for x in s32.tolist()]
     q = r["q"]
@@ -162,8 +164,61 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int):
     return {"ms": total_ms / steps, "median_ms": median_ms, "trace_ms": sum(trace_ms) / steps,
             "fix_ms": sum(fix_ms) / steps, "stats": st, "stats32": st32, "first_ms": first_ms,
             "map": {"q": r["q"].cpu().numpy(), "tw": r["tw"].cpu().numpy(),
-                    "status": r["status"].cpu().numpy().astype("uint16")},
-            "params": fq.Params(precision=prec, tol_perp=tol)}
+                    "status": r["status"].cpu().numpy().astype("uint16"),
+                    **({"qperp": r["qperp"].cpu().numpy()} if "qperp" in r else {})},
+            "params": fq.Params(precision=prec, tol_perp=tol, **mk)}
+
+
+def sampled_accuracy(w, gmaps: dict, k: int = 3000, seed: int = 7, method: int = 0) -> dict:
+    """The oracle (FP64, tol 1e-10) at k interior map points drawn at random against
+    each form's map: Method I through each point's own stencil (q2d_points), Method
+    II through its own line (method2, offset differences of B/B), Q_perp too."""
+    import numpy as np
+
+    import oracle
+
+    pl = w.plane
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(1, pl.nu - 1, k)
+    jj = rng.integers(1, pl.nv - 1, k)
+    idx = np.unique(jj * pl.nu + ii)
+    t = time.perf_counter()
+    if method == 1:
+        o = oracle.method2(w.field, w.grid, pl.points()[idx], 2, {"tol": 1e-10})
+    else:
+        o = oracle.q2d_points(w.field, w.grid, pl, idx, {"tol": 1e-10})
+    dt = time.perf_counter() - t
+    res = {"sample": f"{idx.size} interior map points drawn at random",
+           "oracle_values_per_s": idx.size / dt, "oracle_cores": oracle.threads()}
+    for form, g in gmaps.items():
+        res[form] = err_stats(g["q"].ravel()[idx], g["tw"].ravel()[idx], g["status"].ravel()[idx],
+                              np.asarray(o["q"]).ravel(), np.asarray(o["tw"]).ravel(),
+                              np.asarray(o["status"]).ravel())
+        if method == 1:
+            qp = err_stats(g["qperp"].ravel()[idx], g["tw"].ravel()[idx], g["status"].ravel()[idx],
+                           np.asarray(o["qperp"]).ravel(), np.asarray(o["tw"]).ravel(),
+                           np.asarray(o["status"]).ravel())
+            res[form]["qperp_logq_rel_max"] = qp["logq_rel_max"]
+            res[form]["qperp_points_over_1e-4"] = qp["points_over_1e-4"]
+    return res
+
+
+def run_variant(w, label: str, args, uniform_value: float, method: int = 0) -> dict:
+    """One more workload in both forms, with its sampled accuracy: the stretched C2
+    grid, or Method II on C2."""
+    npts = w.plane.nu * w.plane.nv
+    out = {"workload": label, "unit": UNIT}
+    maps = {}
+    for form in ("f32x", "f64"):
+        r = run_gpu(w, form, args.tol, args.steps, args.warmup, method=method)
+        out[form] = {"value": npts / (r["ms"] * 1e-3), "ms_per_step": r["ms"], "trace_ms": r["trace_ms"],
+                     "fp64_pass_ms": r["fix_ms"], "trial_steps": r["stats"][0],
+                     "vs_uniform_method1": npts / (r["ms"] * 1e-3) / uniform_value[form]}
+        maps[form] = r["map"]
+    if not args.no_cpu_baseline:
+        out["accuracy"] = sampled_accuracy(w, maps, method=method)
+    log(f"{label}: {out}")
+    return out
 
 
 def gather_roofline(nodes: int, nx: int, ny: int, nz: int, walk_steps: int = 400):
@@ -585,6 +640,8 @@ def main():
                     help="skip the runs of the same workload drawn with the two other seeds")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with one 1 GiB device copy (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the stretched-grid and Method II runs of the C2 workload")
     ap.add_argument("--q3d-only", action="store_true",
                     help="run only the 3-D map of the 512x512x256 cube (for profiling it)")
     args = ap.parse_args()
@@ -707,8 +764,17 @@ def main():
                               "trial_steps": rr["stats"][0]}
             del ws_, rr
         out["config"]["other_seeds"] = seeds
-    if not args.no_batch:
-        out["batch"] = run_batch(args.seed, args.steps, args.warmup)
+    if not args.no_variants and args.precision == "f32x" and other is not None:
+        uv = {"f32x": value, "f64": npts / (other["ms"] * 1e-3)}
+        ws_ = synth.config_c2s(args.seed)
+        out["stretched"] = run_variant(
+            ws_, "C2 on a stretched grid of the same node counts (x, y clustered at the centre, "
+                 "cells 0.67x-1.7x the mean width; z cells growing 1% per cell, 0.5x-1.75x); "
+                 "the paper reports 45-80% of its uniform-grid throughput there", args, uv)
+        del ws_
+        out["method2"] = run_variant(
+            w, "C2, Method II (Q, Q_perp and Tw from U, V traced with each line; no "
+               "neighbour lines)", args, uv, method=1)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
     q3d_sample = None
