@@ -71,12 +71,14 @@ template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 
 // TWM: 0 = no twist (narrow records), 1 = twist, 2 = positions only on wide records
 // (the FP64 re-trace, which keeps the twist of the first pass).
 // The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
-// (the latency of cell fetches is then hidden by more waves).
+// (the latency of cell fetches is then hidden by more waves), and the FP32 Method II
+// kernels to two waves per SIMD (a few bytes of spills; at one wave their lone
+// waves took 40% longer than the two-wave form).
 // SCH: the integration scheme (Scheme in trace_core.h); the adjoint's forward pass
 // (TAPE) uses RKF45 only. M2: Method II, the tangent vectors U, V ride along (their
 // end values go to the records' uv array).
 template <typename T, typename S, int TWM, bool UNI, bool TAPE, int SCH = SCH_RKF45, bool M2 = false>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3 : 1) void trace_kernel(const TraceJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3 : ((sizeof(T) == 4 && M2) ? 2 : 1)) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
 {
