@@ -27,4 +27,5 @@ from .oracle import (  # noqa: F401
     q2d_points,
     q3d_points,
     method2,
+    q2d_perp,
 )

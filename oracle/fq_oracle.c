@@ -27,6 +27,9 @@
  *     Eq. tw) is an extra component of the same ODE, curl B being node-wise
  *     second-order differences (the stencil of Eq. grad_B, Section 4) interpolated
  *     like B. The line length is another component.
+ *   - Q_perp (S1, S2 perpendicular to B at the ends) by Method I projects the end
+ *     displacements of the same stencil along B onto those planes; the length
+ *     edge map is |grad_S0 length| on the same stencil.
  *   - Q follows Method I (Section 2.1, Eq. D+-2 and Eq. D+-3): the Jacobians of
  *     both end maps with respect to the seed-plane coordinates come from
  *     differences over neighbouring seeds, D12 = D20 (D10)^-1 with the inverse
@@ -42,6 +45,8 @@
  * the linear-field closed forms again on stretched grids (cells up to five times
  * their neighbours' width), exact curl and scipy's trilinear interpolation there,
  * seeds on node planes, and explicit uniform nodes against the uniform grid;
+ * Method I's Q_perp and the length edge map against the uniform, tilted and
+ * sheared closed forms, and Q_perp against Method II's on the charge cube;
  * the rotated S0 of 3-D maps against the closed form of an oblique sheared field,
  * including a voxel with Bz = 0; voxels of two layers of a 3-D map on one line
  * (same Tw and length; Q in the ratio that the interpolant's divergence along
@@ -1159,6 +1164,147 @@ int orc_q3d(const orc_field *f, const double origin[3], const double spacing[3],
                      nrm, 1, o, bnull2, q, tw, len, status);
     if (lines_out)
         for (int64_t i = 0; i < n; i++) store_line(lines_out, i, &lines[i]);
+    free(seeds);
+    free(lines);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * Method I with S1, S2 perpendicular to B at the ends (Q_perp, Section 2.1), and the
+ * field-line length edge map
+ * ---------------------------------------------------------------------------- */
+
+/* One S0 axis of the 3-D end Jacobians: derivatives of the S1 and S2 end points with
+ * respect to the seed coordinate along the axis, by the stencil rule of
+ * axis_jacobian (central where both neighbours end on the centre line's faces,
+ * else one-sided), and the same derivative of the line length. Returns 0 if no
+ * neighbour is usable. */
+static int axis_jacobian3(const full_line *c, const full_line *m, const full_line *p,
+                          double delta, double j1[3], double j2[3], double *dl)
+{
+    ends12 ec = order_ends(c);
+    ends12 em = m ? order_ends(m) : ec, ep = p ? order_ends(p) : ec;
+    int okm = m && !(m->status & FATAL_BITS) && em.f1 == ec.f1 && em.f2 == ec.f2;
+    int okp = p && !(p->status & FATAL_BITS) && ep.f1 == ec.f1 && ep.f2 == ec.f2;
+    const full_line *lo = okm ? m : c, *hi = okp ? p : c;
+    ends12 el = okm ? em : ec, eh = okp ? ep : ec;
+    if (!okm && !okp) return 0;
+    double span = (okm && okp) ? 2.0 * delta : delta;
+    for (int q = 0; q < 3; q++) {
+        j1[q] = (eh.e1[q] - el.e1[q]) / span;
+        j2[q] = (eh.e2[q] - el.e2[q]) / span;
+    }
+    *dl = (hi->len - lo->len) / span;
+    return 1;
+}
+
+static double dot3(const double a[3], const double b[3]);
+
+/* v minus its component along the unit vector b. */
+static void perp_to(const double v[3], const double b[3], double out[3])
+{
+    double t = v[0] * b[0] + v[1] * b[1] + v[2] * b[2];
+    for (int q = 0; q < 3; q++) out[q] = v[q] - t * b[q];
+}
+
+/* Q_perp at a point (Section 2.1: S1, S2 rotated perpendicular to the line at its
+ * ends). The end displacements of neighbouring lines, projected along B onto the
+ * planes perpendicular to B at the ends, give the maps from S0 to S1_perp and to
+ * S2_perp, with Gram matrices G1, G2 (2 x 2). The map S1_perp -> S2_perp has squared
+ * norm tr(G1^-1 G2); its determinant is |B1/B2| (flux through perpendicular
+ * sections), and the inverse of G1 is written, as in Eq. D+-3, with its determinant
+ * from the flux through S0: det G1 = (Bn0/|B1|)^2. So Q_perp = tr(adj(G1) G2)
+ * |B1| |B2| / Bn0^2. Also |grad_S0 length| (the length edge map). */
+static void method1_perp(const orc_field *f, const full_line *c, const full_line *xm,
+                         const full_line *xp, const full_line *ym, const full_line *yp,
+                         double d0, double d1, double bn0, double *qperp, double *fledge,
+                         int *flags)
+{
+    double j1x[3], j2x[3], j1y[3], j2y[3], dlx, dly;
+    *qperp = *fledge = NAN;
+    if (!axis_jacobian3(c, xm, xp, d0, j1x, j2x, &dlx) ||
+        !axis_jacobian3(c, ym, yp, d1, j1y, j2y, &dly)) {
+        *flags |= ORC_MIXEDFACE;
+        return;
+    }
+    *fledge = sqrt(dlx * dlx + dly * dly);
+    ends12 ec = order_ends(c);
+    double B1[3], B2[3], b1[3], b2[3];
+    int64_t cl[3];
+    locate(f, ec.e1, cl);
+    orc_interp(f, f->b, cl, ec.e1, B1);
+    locate(f, ec.e2, cl);
+    orc_interp(f, f->b, cl, ec.e2, B2);
+    double m1 = sqrt(B1[0] * B1[0] + B1[1] * B1[1] + B1[2] * B1[2]);
+    double m2 = sqrt(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
+    for (int q = 0; q < 3; q++) {
+        b1[q] = B1[q] / m1;
+        b2[q] = B2[q] / m2;
+    }
+    double p1x[3], p1y[3], p2x[3], p2y[3];
+    perp_to(j1x, b1, p1x);
+    perp_to(j1y, b1, p1y);
+    perp_to(j2x, b2, p2x);
+    perp_to(j2y, b2, p2y);
+    /* G1 = [[g11, g12], [g12, g22]], adj(G1) = [[g22, -g12], [-g12, g11]] */
+    double g11 = dot3(p1x, p1x), g12 = dot3(p1x, p1y), g22 = dot3(p1y, p1y);
+    double h11 = dot3(p2x, p2x), h12 = dot3(p2x, p2y), h22 = dot3(p2y, p2y);
+    double tr = g22 * h11 - 2.0 * g12 * h12 + g11 * h22;
+    *qperp = tr * m1 * m2 / (bn0 * bn0);
+}
+
+int orc_q2d_perp(const orc_field *f, const double origin[3], const double u[3],
+                 const double v[3], int64_t nu, int64_t nv, double du, double dv,
+                 const orc_opts *o, double *qperp, double *fledge, uint16_t *status)
+{
+    if (nu < 1 || nv < 1) return -1;
+    set_threads(o);
+    int64_t n = nu * nv;
+    double *seeds = (double *)malloc((size_t)n * 3 * sizeof(double));
+    full_line *lines = (full_line *)malloc((size_t)n * sizeof(full_line));
+    if (!seeds || !lines) {
+        free(seeds);
+        free(lines);
+        return -2;
+    }
+    for (int64_t j = 0; j < nv; j++)
+        for (int64_t i = 0; i < nu; i++)
+            for (int a = 0; a < 3; a++)
+                seeds[3 * (j * nu + i) + a] =
+                    origin[a] + (double)i * du * u[a] + (double)j * dv * v[a];
+    double nrm[3];
+    cross(u, v, nrm);
+    double bnull2 = 1e-60 * field_scale2(f);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) trace_full(f, seeds + 3 * i, nrm, o, bnull2, &lines[i]);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < n; p++) {
+        int64_t i = p % nu, j = p / nu;
+        const full_line *c = &lines[p];
+        const full_line *xm = i > 0 ? &lines[p - 1] : NULL;
+        const full_line *xp = i < nu - 1 ? &lines[p + 1] : NULL;
+        const full_line *ym = j > 0 ? &lines[p - nu] : NULL;
+        const full_line *yp = j < nv - 1 ? &lines[p + nu] : NULL;
+        int flags = c->status;
+        double qp = NAN, fl = NAN;
+        const double *r0 = seeds + 3 * p;
+        if (!(c->status & FATAL_BITS)) {
+            double B[3];
+            int64_t cl[3];
+            locate(f, r0, cl);
+            orc_interp(f, f->b, cl, r0, B);
+            double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            double bn0 = B[0] * nrm[0] + B[1] * nrm[1] + B[2] * nrm[2];
+            const full_line *nbs[4] = {xm, xp, ym, yp};
+            for (int k = 0; k < 4; k++)
+                if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
+            if (!on_box_face(f, r0) && fabs(bn0) < 0.05 * bm) flags |= ORC_ROTATED; /* not formed */
+            else method1_perp(f, c, xm, xp, ym, yp, du, dv, bn0, &qp, &fl, &flags);
+        }
+        if (qperp) qperp[p] = qp;
+        if (fledge) fledge[p] = fl;
+        if (status) status[p] = (uint16_t)flags;
+    }
     free(seeds);
     free(lines);
     return 0;

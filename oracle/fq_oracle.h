@@ -106,6 +106,16 @@ int orc_q3d_points(const orc_field *f, const double origin[3], const double spac
                    const int64_t nvox[3], const int64_t *pts, int64_t npts, const orc_opts *o,
                    double *q, double *tw, double *len, uint16_t *status, orc_lines *lines);
 
+/* Method I with S1, S2 rotated perpendicular to B at the line's ends (Q_perp,
+ * Section 2.1) on the 2-D seed grid of orc_q2d, from the 3-D end displacements of
+ * the same neighbour stencil projected along B onto those planes, and the length
+ * edge map fledge = |grad_S0 length| (neighbour differences of the line lengths).
+ * Points whose S0 would be rotated (interior S0, |Bn0/B| < 0.05) get NaN and
+ * ORC_ROTATED. */
+int orc_q2d_perp(const orc_field *f, const double origin[3], const double u[3],
+                 const double v[3], int64_t nu, int64_t nv, double du, double dv,
+                 const orc_opts *o, double *qperp, double *fledge, uint16_t *status);
+
 /* Method II (Scott 2017; Section 2.1, Eq. rb2, Eq. q_scott) at n seeds: S0 is
  * perpendicular to B at each seed with orthonormal U, V in it; r, U and V are
  * traced both ways (dU/ds = (U . grad)(B/B)); q gets Q with S1, S2 the faces the

@@ -87,6 +87,10 @@ def _load():
         lib.orc_method2.argtypes = [C.POINTER(_Field), C.c_void_p, C.c_int64, C.c_int,
                                     C.POINTER(_Opts), C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.POINTER(_Lines)]
+        lib.orc_q2d_perp.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
+                                     C.c_double * 3, C.c_int64, C.c_int64, C.c_double,
+                                     C.c_double, C.POINTER(_Opts), C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
         lib.orc_default_opts.argtypes = [C.POINTER(_Opts)]
         lib.orc_threads.restype = C.c_int
         lib.orc_q2d_points.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
@@ -282,6 +286,26 @@ def q3d_points(B: np.ndarray, grid, vox, pts, opts: Optional[dict] = None) -> di
     if rc != 0:
         raise ValueError("orc_q3d_points: point index out of range")
     out["lines"] = arrs
+    return out
+
+
+def q2d_perp(B: np.ndarray, grid, plane, opts: Optional[dict] = None) -> dict:
+    """Method I Q_perp (S1, S2 perpendicular to B at the ends) and the length edge map
+    |grad_S0 length| on a 2-D seed grid (shape (nv, nu), u fastest), with statuses."""
+    lib = _load()
+    h = _FieldHolder(B, grid, want_curl=False)
+    n = plane.nu * plane.nv
+    out = {"qperp": np.full(n, np.nan), "fledge": np.full(n, np.nan),
+           "status": np.zeros(n, np.uint16)}
+    o = _opts(dict(opts or {}, want_tw=0))
+    rc = lib.orc_q2d_perp(C.byref(h.f), (C.c_double * 3)(*plane.origin), (C.c_double * 3)(*plane.u),
+                          (C.c_double * 3)(*plane.v), plane.nu, plane.nv, plane.du, plane.dv,
+                          C.byref(o), out["qperp"].ctypes.data, out["fledge"].ctypes.data,
+                          out["status"].ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_q2d_perp failed: {rc}")
+    for k in out:
+        out[k] = out[k].reshape(plane.nv, plane.nu)
     return out
 
 

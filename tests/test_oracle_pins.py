@@ -953,3 +953,56 @@ def test_stretched_with_uniform_nodes_equals_uniform(orc, charge_cube):
     assert np.allclose(rs["tw"], ru["tw"], atol=1e-9)
     for k in ("end_b", "end_f"):
         assert np.allclose(rs["lines"][k], ru["lines"][k], atol=1e-9)
+
+
+# --------------------------------------------------------------------------------------
+# Method I with S1, S2 perpendicular to B (Q_perp, Section 2.1) and the length edge map
+# --------------------------------------------------------------------------------------
+
+
+def test_perp_uniform_and_tilted_fields(orc):
+    """Uniform field: Q_perp = 2 and no length edge. Tilted uniform field ending on the
+    side face x+: Q = r + 1/r there (the projection effect of the face, Section 2.1)
+    but Q_perp = 2, and the length (1 - x1) |B| / bx changes at |B| / bx per unit x1."""
+    g = cubic_grid(11, 11, 11)
+    B = linear_field(g, np.zeros((3, 3)), [0, 0, 1])
+    r = orc.q2d_perp(B, g, synth.plane_z0(8))
+    assert np.allclose(r["qperp"], 2.0, atol=1e-12) and np.allclose(r["fledge"], 0.0, atol=1e-12)
+    bx, bz = 2.0, 1.0
+    B = linear_field(g, np.zeros((3, 3)), [bx, 0, bz])
+    pl = synth.plane_z0(20)
+    r = orc.q2d_perp(B, g, pl)
+    o = orc.q2d(B, g, pl)
+    side = (o["lines"]["face_f"] == 1).reshape(20, 20)
+    inner = side & ((r["status"] & (orc.ORC_ONESIDED | orc.ORC_MIXEDFACE)) == 0)
+    assert inner.sum() > 20
+    assert np.allclose(o["q"][inner], bz / bx + bx / bz, rtol=1e-9)
+    assert np.allclose(r["qperp"][inner], 2.0, rtol=1e-9)
+    assert np.allclose(r["fledge"][inner], math.hypot(bx, bz) / bx, rtol=1e-9)
+
+
+def test_perp_sheared_field(orc):
+    """B = (s(y - y0), 0, 1): Q_perp = 2 + s^2 / (1 + a^2), a = s(y1 - y0) (the closed
+    form Method II gives too), and the length sqrt(1 + a^2) has |grad| =
+    s |a| / sqrt(1 + a^2) (central differences inside the seed grid)."""
+    g = cubic_grid(11, 11, 11)
+    s, y0 = 0.5, 0.5
+    B = linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1])
+    pl = _plane((0.45, 0.27, 0.0), 0.01, n=5)
+    r = orc.q2d_perp(B, g, pl)
+    a = (s * (pl.points()[:, 1] - y0)).reshape(5, 5)
+    assert np.allclose(r["qperp"], 2 + s * s / (1 + a * a), rtol=1e-10)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose(r["fledge"][inner], (np.abs(s * a) / np.sqrt(1 + a * a))[inner], atol=1e-6)
+
+
+def test_perp_agrees_with_method2(orc):
+    """On the 4-charge cube Method I's Q_perp (neighbour differences, d = 1e-4) and
+    Method II's (tangent vectors) agree to the stencil's O(d^2) error: two
+    independent ways to the same Q_perp."""
+    w = synth.config_c1(0)
+    for centre in ((0.37, 0.52), (0.61, 0.44), (0.5, 0.3)):
+        pl = _plane((centre[0], centre[1], 0.0), 1e-4, n=3)
+        r = orc.q2d_perp(w.field, w.grid, pl, {"tol": 1e-12})
+        m = orc.method2(w.field, w.grid, pl.points()[4:5], 2, {"tol": 1e-12})
+        assert abs(r["qperp"][1, 1] / m["qperp"][0] - 1) < 1e-4, (centre, r["qperp"][1, 1], m["qperp"][0])
