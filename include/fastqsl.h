@@ -195,8 +195,15 @@ typedef struct {
     double *length;     /* length of the point's line */
     uint16_t *status;   /* FQ_ST_* bits of the point */
     fq_lines lines;     /* the point's own line (NULL members skipped) */
-    double *qperp;      /* Method II only: Q_perp, with S1, S2 perpendicular to B at the
-                           ends (Section 2.1); left untouched by Method I */
+    double *qperp;      /* Q_perp, with S1, S2 perpendicular to B at the ends (Section 2.1).
+                           Method II: from U, V. Method I (2-D maps; 3-D maps leave it
+                           untouched): the end displacements of Q's neighbour stencil,
+                           projected along B onto the planes perpendicular to B at the
+                           ends; NaN where S0 is rotated */
+    double *fledge;     /* 2-D maps (3-D maps leave it untouched): the length edge map,
+                           |grad_S0 length| by the neighbour differences of Q's stencil
+                           (dimensionless; large where neighbouring lines part, as at
+                           QSLs); NaN where no neighbour is usable or S0 is rotated */
 } fq_map;
 
 /* ---------------------------------------------------------------------------------

@@ -227,7 +227,8 @@ def trace(B, grid, seeds, normal=(0.0, 0.0, 1.0), params: Optional[Params] = Non
     return out
 
 
-def _alloc_map(npts: int, shape, device, want_lines: bool, qperp: bool = False):
+def _alloc_map(npts: int, shape, device, want_lines: bool, qperp: bool = False,
+               fledge: bool = False):
     torch = _torch()
     m = {"q": torch.empty(shape, dtype=torch.float64, device=device),
          "tw": torch.empty(shape, dtype=torch.float64, device=device),
@@ -241,6 +242,9 @@ def _alloc_map(npts: int, shape, device, want_lines: bool, qperp: bool = False):
     if qperp:
         m["qperp"] = torch.empty(shape, dtype=torch.float64, device=device)
         s.qperp = m["qperp"].data_ptr()
+    if fledge:
+        m["fledge"] = torch.empty(shape, dtype=torch.float64, device=device)
+        s.fledge = m["fledge"].data_ptr()
     if want_lines:
         m["lines"] = _alloc_lines(npts, device)
         s.lines = _lines_struct(m["lines"])
@@ -265,6 +269,8 @@ def _batch_args(jobs, params: Params, outs: list):
             s.lines = _lines_struct(m["lines"])
         if "qperp" in m:
             s.qperp = m["qperp"].data_ptr()
+        if "fledge" in m:
+            s.fledge = m["fledge"].data_ptr()
         maps[j] = s
     return fields, planes, maps, params.c()
 
@@ -286,12 +292,13 @@ def q2d_workspace_size(jobs: Sequence, params: Optional[Params] = None) -> int:
     return int(need)
 
 
-def alloc_q2d_outputs(jobs: Sequence, want_lines: bool = False, qperp: bool = False) -> list:
+def alloc_q2d_outputs(jobs: Sequence, want_lines: bool = False, qperp: bool = False,
+                      fledge: bool = False) -> list:
     """Output maps for q2d_batch_into (one dict of CUDA tensors per job; with qperp,
-    a Q_perp map too, which Method II fills)."""
+    a Q_perp map too; with fledge, the length edge map)."""
     outs = []
     for B, grid, pl in jobs:
-        m, _ = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines, qperp)
+        m, _ = _alloc_map(pl.nu * pl.nv, (pl.nv, pl.nu), B.device, want_lines, qperp, fledge)
         outs.append(m)
     return outs
 
@@ -308,12 +315,14 @@ def q2d_batch_into(jobs: Sequence, outs: list, ws, params: Optional[Params] = No
 
 
 def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
-              stream=None, ws=None) -> list:
-    """Q/Tw/length maps for several (B, grid, plane) triples in ONE persistent launch."""
+              stream=None, ws=None, perp: bool = False) -> list:
+    """Q/Tw/length maps for several (B, grid, plane) triples in ONE persistent launch.
+    perp: also Q_perp ("qperp"; Method II always gives it) and the length edge map
+    ("fledge")."""
     params = params or Params()
     need = q2d_workspace_size(jobs, params)
     w = _workspace(need, jobs[0][0].device, ws)
-    outs = alloc_q2d_outputs(jobs, want_lines, params.method == FQ_METHOD_II)
+    outs = alloc_q2d_outputs(jobs, want_lines, perp or params.method == FQ_METHOD_II, perp)
     q2d_batch_into(jobs, outs, w, params, stream)
     for m in outs:
         m["_ws"] = w
@@ -321,9 +330,10 @@ def q2d_batch(jobs: Sequence, params: Optional[Params] = None, want_lines: bool 
 
 
 def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = False,
-        stream=None, ws=None) -> dict:
-    """Q, Tw and length maps on a 2-D seed grid (shape (nv, nu))."""
-    return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws)[0]
+        stream=None, ws=None, perp: bool = False) -> dict:
+    """Q, Tw and length maps on a 2-D seed grid (shape (nv, nu)); perp: Q_perp and the
+    length edge map too."""
+    return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws, perp)[0]
 
 
 def q2d_static(jobs: Sequence, params: Optional[Params] = None, outs: Optional[list] = None,

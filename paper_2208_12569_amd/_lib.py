@@ -73,7 +73,8 @@ class fq_lines(C.Structure):
 
 class fq_map(C.Structure):
     _fields_ = [("q", C.c_void_p), ("tw", C.c_void_p), ("length", C.c_void_p),
-                ("status", C.c_void_p), ("lines", fq_lines), ("qperp", C.c_void_p)]
+                ("status", C.c_void_p), ("lines", fq_lines), ("qperp", C.c_void_p),
+                ("fledge", C.c_void_p)]
 
 
 EXPORTS = [

@@ -644,6 +644,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));
         else if (m2) FQ_TRY(launch_m2_map(maps[i], stream));
         else FQ_TRY(launch_stencil(maps[i], stream));
+        // Q_perp by Method I (plane maps) and the length edge map (plane maps, both
+        // methods)
+        if (specs[i].kind == SPEC_PLANE && (maps[i].out.fledge || (!m2 && maps[i].out.qperp)))
+            FQ_TRY(launch_perp_map(maps[i], !m2, stream));
     }
 #undef FQ_TRY
     return FQ_OK;

@@ -240,6 +240,9 @@ hipError_t launch_classify(const MapJob &m, int32_t *rot_index, RotEntry *rot,
 hipError_t launch_stencil(const MapJob &m, hipStream_t s);
 // Method II: Q and Q_perp of every point from its own line's tangent vectors.
 hipError_t launch_m2_map(const MapJob &m, hipStream_t s);
+// Method I Q_perp (S1, S2 perpendicular to B at the ends; want_qperp) and the length
+// edge map |grad_S0 length| of a map, from its lines' records and stencil.
+hipError_t launch_perp_map(const MapJob &m, int want_qperp, hipStream_t s);
 hipError_t launch_lines_out(const MapJob &m, const double *seeds_list, hipStream_t s);
 
 }  // namespace fq

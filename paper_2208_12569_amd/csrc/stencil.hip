@@ -308,6 +308,91 @@ __global__ __launch_bounds__(256) void m2_map_kernel(MapJob m)
     }
 }
 
+// Method I with S1, S2 perpendicular to B at the ends (Q_perp, Section 2.1), and the
+// length edge map |grad_S0 length|, on one layer of a map: the 3-D end displacements
+// of the point's stencil (the neighbour rule of Q: central where both neighbours end
+// on the centre line's faces, else one-sided), projected along B onto the planes
+// perpendicular to B at the ends. With P1, P2 the projected 3 x 2 Jacobians and
+// G = P^T P, the map between the perpendicular sections has squared norm
+// tr(G1^-1 G2) and determinant |B1 / B2|; det G1 = (Bn0 / |B1|)^2 from the flux
+// through S0 (as Eq. D+-3 does for Q), so Q_perp = tr(adj(G1) G2) |B1| |B2| / Bn0^2.
+// Points whose S0 is rotated get NaN. want_qperp = 0: the length edge map only
+// (Method II forms its own Q_perp).
+
+// One S0 axis: the S1 and S2 end displacements and the length change per unit seed
+// coordinate, from the usable neighbours at pt - stride (if hm) and pt + stride (if
+// hp). False when neither is usable.
+__device__ __forceinline__ bool axis_diff3(const MapJob &m, const Line &c, int64_t pt, int64_t stride,
+                                           bool hm, bool hp, double delta, double j1[3], double j2[3],
+                                           double &dl)
+{
+    Line lm, lp;
+    bool okm = false, okp = false;
+    if (hm) {
+        read_line(m.rec, m.nlines, pt - stride, lm);
+        okm = !(lm.st & kFatal) && lm.f1 == c.f1 && lm.f2 == c.f2;
+    }
+    if (hp) {
+        read_line(m.rec, m.nlines, pt + stride, lp);
+        okp = !(lp.st & kFatal) && lp.f1 == c.f1 && lp.f2 == c.f2;
+    }
+    if (!okm && !okp) return false;
+    const Line &lo = okm ? lm : c, &hi = okp ? lp : c;
+    const double inv = 1.0 / ((okm && okp) ? 2.0 * delta : delta);
+    for (int a = 0; a < 3; a++) {
+        j1[a] = (hi.e1[a] - lo.e1[a]) * inv;
+        j2[a] = (hi.e2[a] - lo.e2[a]) * inv;
+    }
+    dl = (hi.len - lo.len) * inv;
+    return true;
+}
+
+// v minus its component along the unit vector t
+__device__ __forceinline__ void perp3(double v[3], const double t[3])
+{
+    const double d = v[0] * t[0] + v[1] * t[1] + v[2] * t[2];
+    for (int a = 0; a < 3; a++) v[a] -= d * t[a];
+}
+
+__global__ __launch_bounds__(256) void perp_kernel(MapJob m, int want_qperp)
+{
+    const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = pt / lay, r2 = pt - k * lay, j = r2 / m.nu, i = r2 - j * m.nu;
+        Line c;
+        read_line(m.rec, m.nlines, pt, c);
+        double qp = NAN, fl = NAN;
+        const int32_t ri = m.rot_index ? m.rot_index[pt] : -1;
+        double jx1[3], jx2[3], jy1[3], jy2[3], dlx, dly;
+        if (!(c.st & kFatal) && ri == -1 &&
+            axis_diff3(m, c, pt, 1, i > 0, i < m.nu - 1, m.d0, jx1, jx2, dlx) &&
+            axis_diff3(m, c, pt, m.nu, j > 0, j < m.nv - 1, m.d1, jy1, jy2, dly)) {
+            fl = sqrt(dlx * dlx + dly * dly);
+            if (want_qperp) {
+                double r0[3], B0[3], B1[3], B2[3];
+                point_pos(m, i, j, k, r0);
+                field64(m, r0, B0);
+                field64(m, c.e1, B1);
+                field64(m, c.e2, B2);
+                const double bn0 = B0[0] * m.normal[0] + B0[1] * m.normal[1] + B0[2] * m.normal[2];
+                const double m1 = sqrt(dot3(B1, B1)), m2 = sqrt(dot3(B2, B2));
+                const double t1[3] = {B1[0] / m1, B1[1] / m1, B1[2] / m1};
+                const double t2[3] = {B2[0] / m2, B2[1] / m2, B2[2] / m2};
+                perp3(jx1, t1);
+                perp3(jy1, t1);
+                perp3(jx2, t2);
+                perp3(jy2, t2);
+                const double g11 = dot3(jx1, jx1), g12 = dot3(jx1, jy1), g22 = dot3(jy1, jy1);
+                const double h11 = dot3(jx2, jx2), h12 = dot3(jx2, jy2), h22 = dot3(jy2, jy2);
+                qp = (g22 * h11 - 2.0 * g12 * h12 + g11 * h22) * m1 * m2 / (bn0 * bn0);
+            }
+        }
+        if (want_qperp && m.out.qperp) m.out.qperp[pt] = qp;
+        if (m.out.fledge) m.out.fledge[pt] = fl;
+    }
+}
+
 __global__ void lines_kernel(MapJob m, const double *seeds)
 {
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < m.nlines;
@@ -347,6 +432,13 @@ hipError_t launch_m2_map(const MapJob &m, hipStream_t s)
 {
     const int64_t np = m.nu * m.nv * m.nlayers;
     hipLaunchKernelGGL(m2_map_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_perp_map(const MapJob &m, int want_qperp, hipStream_t s)
+{
+    const int64_t np = m.nu * m.nv * m.nlayers;
+    hipLaunchKernelGGL(perp_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m, want_qperp);
     return hipGetLastError();
 }
 

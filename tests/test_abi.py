@@ -51,7 +51,7 @@ def test_struct_sizes_match_header_layout(lib):
     assert C.sizeof(_lib.fq_plane) == 9 * 8 + 16 + 16
     assert C.sizeof(_lib.fq_voxels) == 9 * 8
     assert C.sizeof(_lib.fq_lines) == 10 * 8
-    assert C.sizeof(_lib.fq_map) == 4 * 8 + 10 * 8 + 8
+    assert C.sizeof(_lib.fq_map) == 4 * 8 + 10 * 8 + 8 + 8
 
 
 def _fake_field(n=(64, 64, 64), dtype=0):
