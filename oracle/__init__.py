@@ -28,4 +28,6 @@ from .oracle import (  # noqa: F401
     q3d_points,
     method2,
     q2d_perp,
+    qcyl,
+    ORC_FACE_CYL,
 )

@@ -27,6 +27,10 @@
  *     Eq. tw) is an extra component of the same ODE, curl B being node-wise
  *     second-order differences (the stencil of Eq. grad_B, Section 4) interpolated
  *     like B. The line length is another component.
+ *   - On a cylindrical mapping surface (Section 3's x^2 + y^2 = 1 example) lines
+ *     run inside the cylinder and end where they meet it again (the crossing found
+ *     like a face landing, on the root of phi = r^2 - R^2); Q by Method I on the
+ *     surface coordinates (R theta, z).
  *   - Q_perp (S1, S2 perpendicular to B at the ends) by Method I projects the end
  *     displacements of the same stencil along B onto those planes; the length
  *     edge map is |grad_S0 length| on the same stencil.
@@ -46,7 +50,10 @@
  * their neighbours' width), exact curl and scipy's trilinear interpolation there,
  * seeds on node planes, and explicit uniform nodes against the uniform grid;
  * Method I's Q_perp and the length edge map against the uniform, tilted and
- * sheared closed forms, and Q_perp against Method II's on the charge cube;
+ * sheared closed forms, and Q_perp against Method II's on the charge cube; the
+ * cylindrical mapping surface against the paper's B = (x, -y, 0) example (Q = 2,
+ * theta2 = pi/2 - theta1, hyperbola arc lengths by scipy) and a tilted uniform
+ * field (Q = 2 + 4 bz^2 sin^2 theta1, across the wrap of theta);
  * the rotated S0 of 3-D maps against the closed form of an oblique sheared field,
  * including a voxel with Bz = 0; voxels of two layers of a 3-D map on one line
  * (same Tw and length; Q in the ratio that the interpolant's divergence along
@@ -467,6 +474,57 @@ static int land(const line_ctx *L, const double y[NY], int a, double plane, doub
     return 0;
 }
 
+/* The cylindrical mapping surface (axis along z): phi < 0 inside, phi = 0 on it. */
+static double cyl_phi(const orc_cyl *c, const double y[3])
+{
+    double dx = y[0] - c->xc, dy = y[1] - c->yc;
+    return dx * dx + dy * dy - c->r * c->r;
+}
+
+/* Outward unit normal of the cylinder through the point y (radial direction). */
+static void cyl_normal(const orc_cyl *c, const double y[3], double n[3])
+{
+    double dx = y[0] - c->xc, dy = y[1] - c->yc, m = sqrt(dx * dx + dy * dy);
+    n[0] = dx / m;
+    n[1] = dy / m;
+    n[2] = 0.0;
+}
+
+/* Length t in (0, t_hi] at which the step from y (inside, phi < 0) reaches the
+ * cylinder, phi(Phi(y, t_hi)) = g_hi >= 0: the same Illinois iteration and stop
+ * on the bracket's width in arc length as land(). */
+static int land_cyl(const line_ctx *L, const orc_cyl *c, const double y[NY], double t_hi,
+                    double g_hi, double out[NY], double *t_out)
+{
+    double ta = 0.0, ga = cyl_phi(c, y);
+    double tb = t_hi, gb = g_hi;
+    double err, t = t_hi;
+    int side = 0, st;
+    double cur[NY];
+    memcpy(cur, out, sizeof cur);
+    for (int it = 0; it < 400; it++) {
+        t = (ta * gb - tb * ga) / (gb - ga);
+        if (!(t > ta && t < tb)) t = 0.5 * (ta + tb);
+        if ((st = rk4_doubled(L, y, t, cur, &err))) return st;
+        double gt = cyl_phi(c, cur);
+        if (gt == 0.0 || (tb - ta) <= 1e-15 * t_hi) break;
+        if ((gt > 0) == (gb > 0)) {
+            tb = t;
+            gb = gt;
+            if (side == 1) ga *= 0.5;
+            side = 1;
+        } else {
+            ta = t;
+            ga = gt;
+            if (side == -1) gb *= 0.5;
+            side = -1;
+        }
+    }
+    memcpy(out, cur, sizeof cur);
+    *t_out = t;
+    return 0;
+}
+
 /* inside the closed cell along every axis except `skip` (-1: none) */
 static int inside_cell(const line_ctx *L, const double r[3], int skip)
 {
@@ -517,8 +575,13 @@ typedef struct {
 
 /* Trace one half line (direction sigma) from seed until it leaves the box; with m2,
  * the tangent vectors of Method II ride along (Eq. rb2). */
+/* With cyl, the line runs inside the cylinder (and the box) only: a half whose
+ * direction at the seed (on the cylinder) points out of it ends at its seed, and a
+ * half that reaches the cylinder again ends there (face ORC_FACE_CYL, bn = B . the
+ * outward normal). */
 static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
-                           const orc_opts *o, double bnull2, const m2_ctx *m2, half_line *res)
+                           const orc_opts *o, double bnull2, const m2_ctx *m2,
+                           const orc_cyl *cyl, half_line *res)
 {
     line_ctx L;
     L.f = f;
@@ -547,6 +610,31 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
         return;
     }
     locate(f, seed, L.c);
+    /* the end of the half on the cylinder at y (its cell L.c) */
+#define CYL_END(yy)                                                                        \
+    do {                                                                                   \
+        double B_[3], n_[3];                                                               \
+        orc_interp(f, f->b, L.c, (yy), B_);                                                \
+        cyl_normal(cyl, (yy), n_);                                                         \
+        memcpy(res->end, (yy), 3 * sizeof(double));                                        \
+        res->face = ORC_FACE_CYL;                                                          \
+        res->bn = B_[0] * n_[0] + B_[1] * n_[1] + B_[2] * n_[2];                           \
+        res->tw = (yy)[3];                                                                 \
+        res->len = (yy)[4];                                                                \
+        for (int a_ = 0; a_ < 3; a_++) {                                                   \
+            res->U[a_] = (yy)[5 + a_];                                                     \
+            res->V[a_] = (yy)[8 + a_];                                                     \
+        }                                                                                  \
+    } while (0)
+    if (cyl) {
+        double B[3], n[3];
+        orc_interp(f, f->b, L.c, seed, B);
+        cyl_normal(cyl, seed, n);
+        if (sigma * (B[0] * n[0] + B[1] * n[1] + B[2] * n[2]) >= 0.0) {
+            CYL_END(y);
+            return;
+        }
+    }
     double h = o->h0 * dmin;
     const double hmax = o->hmax * dmin;
     int64_t trials = 0;
@@ -614,6 +702,19 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
             if (t_out > 0.0) {
                 h = t_out;
                 continue;
+            }
+            if (cyl && cyl_phi(cyl, y1) > 0.0) {
+                /* the step leaves the cylinder: end on it */
+                double yc_[NY], tc;
+                memcpy(yc_, y1, sizeof yc_);
+                if (cyl_phi(cyl, y) < 0.0 &&
+                    (st = land_cyl(&L, cyl, y, h, cyl_phi(cyl, y1), yc_, &tc))) {
+                    res->status = st;
+                    return;
+                }
+                if (!(cyl_phi(cyl, y) < 0.0)) memcpy(yc_, y, sizeof yc_);
+                CYL_END(yc_);
+                return;
             }
             memcpy(y, y1, sizeof y);
             res->nsteps++;
@@ -684,16 +785,25 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
             if (y_best[a] < lo) y_best[a] = lo;
             if (y_best[a] > hi) y_best[a] = hi;
         }
+        if (cyl && cyl_phi(cyl, y_best) > 0.0) {
+            /* the line meets the cylinder before this cell face: end on it */
+            double yc_[NY], tc;
+            memcpy(yc_, y_best, sizeof yc_);
+            if (cyl_phi(cyl, y) < 0.0 &&
+                (st = land_cyl(&L, cyl, y, t_best, cyl_phi(cyl, y_best), yc_, &tc))) {
+                res->status = st;
+                return;
+            }
+            if (!(cyl_phi(cyl, y) < 0.0)) memcpy(yc_, y, sizeof yc_);
+            CYL_END(yc_);
+            return;
+        }
         memcpy(y, y_best, sizeof y);
         res->nsteps++;
     }
+#undef CYL_END
 }
 
-static void trace_half(const orc_field *f, const double seed[3], int sigma, const orc_opts *o,
-                       double bnull2, half_line *res)
-{
-    trace_half_gen(f, seed, sigma, o, bnull2, NULL, res);
-}
 
 /* in-face coordinates of an end point on face `face`: the two other axes, in
  * increasing axis order */
@@ -704,9 +814,32 @@ static void inface(int face, const double e[3], double uv[2])
         if (b != a) uv[m++] = e[b];
 }
 
+/* In-surface coordinates of an end: in-face ones on a box face, (r theta, z) on the
+ * cylinder (arc length around the axis from the +x direction, and height). */
+static void surf_uv(const orc_cyl *cyl, int face, const double e[3], double uv[2])
+{
+    if (face != ORC_FACE_CYL) {
+        inface(face, e, uv);
+        return;
+    }
+    uv[0] = cyl->r * atan2(e[1] - cyl->yc, e[0] - cyl->xc);
+    uv[1] = e[2];
+}
+
+/* The arc length u shifted by whole turns to lie within half a turn of ref. */
+static double unwrap(const orc_cyl *cyl, double u, double ref)
+{
+    double turn = 2.0 * M_PI * cyl->r;
+    while (u - ref > 0.5 * turn) u -= turn;
+    while (ref - u > 0.5 * turn) u += turn;
+    return u;
+}
+
 static int near_edge(const orc_field *f, int face, const double e[3], double eps)
 {
     if (face < 0) return 0;
+    /* the cylinder (inside the box in x and y) meets only the z faces */
+    if (face == ORC_FACE_CYL) return e[2] - box_lo(f, 2) < eps || box_hi(f, 2) - e[2] < eps;
     int a = face / 2;
     for (int b = 0; b < 3; b++) {
         if (b == a) continue;
@@ -762,12 +895,14 @@ static ends12 order_ends(const full_line *l)
     return r;
 }
 
-static void trace_full(const orc_field *f, const double seed[3], const double nrm[3],
-                       const orc_opts *o, double bnull2, full_line *r)
+/* Both halves from seed; with cyl, inside that cylinder (the S0 normal at the seed
+ * is then the cylinder's). */
+static void trace_full_gen(const orc_field *f, const double seed[3], const double nrm[3],
+                           const orc_cyl *cyl, const orc_opts *o, double bnull2, full_line *r)
 {
     half_line hb, hf;
-    trace_half(f, seed, -1, o, bnull2, &hb);
-    trace_half(f, seed, +1, o, bnull2, &hf);
+    trace_half_gen(f, seed, -1, o, bnull2, NULL, cyl, &hb);
+    trace_half_gen(f, seed, +1, o, bnull2, NULL, cyl, &hf);
     memcpy(r->end_b, hb.end, sizeof r->end_b);
     memcpy(r->end_f, hf.end, sizeof r->end_f);
     r->face_b = hb.face;
@@ -793,6 +928,12 @@ static void trace_full(const orc_field *f, const double seed[3], const double nr
     if (near_edge(f, r->face_b, r->end_b, o->edge_eps) ||
         near_edge(f, r->face_f, r->end_f, o->edge_eps))
         r->status |= ORC_EDGE;
+}
+
+static void trace_full(const orc_field *f, const double seed[3], const double nrm[3],
+                       const orc_opts *o, double bnull2, full_line *r)
+{
+    trace_full_gen(f, seed, nrm, NULL, o, bnull2, r);
 }
 
 static void store_line(orc_lines *out, int64_t i, const full_line *r)
@@ -847,22 +988,28 @@ int orc_trace(const orc_field *f, const double *seeds, int64_t n, const double *
  * minus/plus neighbours (NULL where the grid ends). Returns 0 if no usable
  * neighbour exists. */
 static int axis_jacobian(const full_line *c, const full_line *m, const full_line *p,
-                         double delta, double d1[2], double d2[2], int *flags)
+                         double delta, double d1[2], double d2[2], int *flags,
+                         const orc_cyl *cyl)
 {
     ends12 ec = order_ends(c);
     ends12 em = m ? order_ends(m) : ec, ep = p ? order_ends(p) : ec;
     int okm = m && !(m->status & FATAL_BITS) && em.f1 == ec.f1 && em.f2 == ec.f2;
     int okp = p && !(p->status & FATAL_BITS) && ep.f1 == ec.f1 && ep.f2 == ec.f2;
     double c1[2], c2[2], m1[2], m2[2], p1[2], p2[2];
-    inface(ec.f1, ec.e1, c1);
-    inface(ec.f2, ec.e2, c2);
+    surf_uv(cyl, ec.f1, ec.e1, c1);
+    surf_uv(cyl, ec.f2, ec.e2, c2);
     if (okm) {
-        inface(em.f1, em.e1, m1);
-        inface(em.f2, em.e2, m2);
+        surf_uv(cyl, em.f1, em.e1, m1);
+        surf_uv(cyl, em.f2, em.e2, m2);
+        /* on the cylinder, arc lengths of neighbours are taken on the centre's branch */
+        if (ec.f1 == ORC_FACE_CYL) m1[0] = unwrap(cyl, m1[0], c1[0]);
+        if (ec.f2 == ORC_FACE_CYL) m2[0] = unwrap(cyl, m2[0], c2[0]);
     }
     if (okp) {
-        inface(ep.f1, ep.e1, p1);
-        inface(ep.f2, ep.e2, p2);
+        surf_uv(cyl, ep.f1, ep.e1, p1);
+        surf_uv(cyl, ep.f2, ep.e2, p2);
+        if (ec.f1 == ORC_FACE_CYL) p1[0] = unwrap(cyl, p1[0], c1[0]);
+        if (ec.f2 == ORC_FACE_CYL) p2[0] = unwrap(cyl, p2[0], c2[0]);
     }
     if (okm && okp) {
         for (int q = 0; q < 2; q++) {
@@ -894,11 +1041,11 @@ static int axis_jacobian(const full_line *c, const full_line *m, const full_line
  * spacings d0, d1. Eq. D+-2 and Eq. D+-3, then Eq. Q+- with |det D| -> |Bn1/Bn2|. */
 static double method1_q(const full_line *c, const full_line *xm, const full_line *xp,
                         const full_line *ym, const full_line *yp, double d0, double d1,
-                        double bn0, int *flags)
+                        double bn0, int *flags, const orc_cyl *cyl)
 {
     double d1x[2], d2x[2], d1y[2], d2y[2];
-    if (!axis_jacobian(c, xm, xp, d0, d1x, d2x, flags) ||
-        !axis_jacobian(c, ym, yp, d1, d1y, d2y, flags)) {
+    if (!axis_jacobian(c, xm, xp, d0, d1x, d2x, flags, cyl) ||
+        !axis_jacobian(c, ym, yp, d1, d1y, d2y, flags, cyl)) {
         *flags |= ORC_MIXEDFACE;
         return NAN;
     }
@@ -964,7 +1111,7 @@ static double rotated_q(const orc_field *f, const double r0[3], const double B[3
             if (nb[2 * ax + sgn].status & ORC_EDGE) *flags |= ORC_EDGE;
         }
     *flags |= ORC_ROTATED;
-    return method1_q(c, &nb[0], &nb[1], &nb[2], &nb[3], delta, delta, bm, flags);
+    return method1_q(c, &nb[0], &nb[1], &nb[2], &nb[3], delta, delta, bm, flags, NULL);
 }
 
 /* Q, Tw, length and status of one map point from its own line c and its stencil
@@ -991,7 +1138,7 @@ static void assemble_point(const orc_field *f, const full_line *c, const full_li
         } else {
             for (int k = 0; k < 4; k++)
                 if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
-            qv = method1_q(c, xm, xp, ym, yp, du, dv, bn0, &flags);
+            qv = method1_q(c, xm, xp, ym, yp, du, dv, bn0, &flags, NULL);
         }
     }
     *q = qv;
@@ -1164,6 +1311,70 @@ int orc_q3d(const orc_field *f, const double origin[3], const double spacing[3],
                      nrm, 1, o, bnull2, q, tw, len, status);
     if (lines_out)
         for (int64_t i = 0; i < n; i++) store_line(lines_out, i, &lines[i]);
+    free(seeds);
+    free(lines);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * A cylindrical mapping surface (Section 3, the x^2 + y^2 = 1 example)
+ * ---------------------------------------------------------------------------- */
+
+int orc_qcyl(const orc_field *f, const orc_cyl *cyl, double theta0, double dtheta,
+             int64_t ntheta, double z0, double dz, int64_t nz, const orc_opts *o, double *q,
+             double *tw, double *len, uint16_t *status, orc_lines *lines_out)
+{
+    if (ntheta < 1 || nz < 1 || !(cyl->r > 0.0)) return -1;
+    set_threads(o);
+    int64_t n = ntheta * nz;
+    double *seeds = (double *)malloc((size_t)n * 3 * sizeof(double));
+    full_line *lines = (full_line *)malloc((size_t)n * sizeof(full_line));
+    if (!seeds || !lines) {
+        free(seeds);
+        free(lines);
+        return -2;
+    }
+    for (int64_t j = 0; j < nz; j++)
+        for (int64_t i = 0; i < ntheta; i++) {
+            double th = theta0 + (double)i * dtheta;
+            double *s3 = seeds + 3 * (j * ntheta + i);
+            s3[0] = cyl->xc + cyl->r * cos(th);
+            s3[1] = cyl->yc + cyl->r * sin(th);
+            s3[2] = z0 + (double)j * dz;
+        }
+    double bnull2 = 1e-60 * field_scale2(f);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        double nrm[3];
+        cyl_normal(cyl, seeds + 3 * i, nrm);
+        trace_full_gen(f, seeds + 3 * i, nrm, cyl, o, bnull2, &lines[i]);
+    }
+    /* Method I on S0 = the cylinder (coordinates r theta, z; neighbours along theta
+     * and z), S1 = the seed's own end, S2 = where the line meets the cylinder again
+     * (or a box face) */
+    double d0 = cyl->r * dtheta;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < n; p++) {
+        int64_t i = p % ntheta, j = p / ntheta;
+        const full_line *c = &lines[p];
+        const full_line *xm = i > 0 ? &lines[p - 1] : NULL;
+        const full_line *xp = i < ntheta - 1 ? &lines[p + 1] : NULL;
+        const full_line *ym = j > 0 ? &lines[p - ntheta] : NULL;
+        const full_line *yp = j < nz - 1 ? &lines[p + ntheta] : NULL;
+        int flags = c->status;
+        double qv = NAN;
+        if (!(c->status & FATAL_BITS)) {
+            const full_line *nbs[4] = {xm, xp, ym, yp};
+            for (int k = 0; k < 4; k++)
+                if (nbs[k] && (nbs[k]->status & ORC_EDGE)) flags |= ORC_EDGE;
+            qv = method1_q(c, xm, xp, ym, yp, d0, dz, c->bn0, &flags, cyl);
+        }
+        if (q) q[p] = qv;
+        if (tw) tw[p] = c->tw;
+        if (len) len[p] = c->len;
+        if (status) status[p] = (uint16_t)flags;
+        if (lines_out) store_line(lines_out, p, c);
+    }
     free(seeds);
     free(lines);
     return 0;
@@ -1425,8 +1636,8 @@ int orc_method2(const orc_field *f, const double *seeds, int64_t n, int way, con
                 double um = sqrt(dot3(m.U0, m.U0));
                 for (int k = 0; k < 3; k++) m.U0[k] /= um;
                 cross(bh, m.U0, m.V0);
-                trace_half_gen(f, r0, -1, o, bnull2, &m, &hb);
-                trace_half_gen(f, r0, +1, o, bnull2, &m, &hf);
+                trace_half_gen(f, r0, -1, o, bnull2, &m, NULL, &hb);
+                trace_half_gen(f, r0, +1, o, bnull2, &m, NULL, &hf);
                 flags = hb.status | hf.status;
                 if (!(flags & FATAL_BITS)) {
                     /* Eq. q_scott with S1, S2 the faces the line ends on ... */

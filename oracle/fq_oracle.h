@@ -46,6 +46,14 @@ typedef struct {
                                On a stretched axis origin and spacing are not used. */
 } orc_field;
 
+/* face id of an end on the cylindrical mapping surface (orc_qcyl) */
+#define ORC_FACE_CYL 6
+
+/* A cylindrical mapping surface: axis along z through (xc, yc), radius r. */
+typedef struct {
+    double xc, yc, r;
+} orc_cyl;
+
 typedef struct {
     double tol;       /* per-step error bound, grid spacings */
     double h0;        /* first trial step, grid spacings */
@@ -105,6 +113,19 @@ int orc_q2d_points(const orc_field *f, const double origin[3], const double u[3]
 int orc_q3d_points(const orc_field *f, const double origin[3], const double spacing[3],
                    const int64_t nvox[3], const int64_t *pts, int64_t npts, const orc_opts *o,
                    double *q, double *tw, double *len, uint16_t *status, orc_lines *lines);
+
+/* Method I on a cylindrical mapping surface (Section 3, the x^2 + y^2 = 1 example):
+ * seeds at (xc + r cos theta, yc + r sin theta, z), theta = theta0 + i dtheta
+ * (i < ntheta, fastest), z = z0 + j dz. Lines run inside the cylinder only: the
+ * half whose direction points out of the cylinder ends at its seed, the other ends
+ * where it meets the cylinder again (face ORC_FACE_CYL) or leaves the box. S0, S1
+ * and S2 are the cylinder, with coordinates (r theta, z) and normal fields along the
+ * outward normal; Q by Eq. D+-2, D+-3 and Q+- on the (theta, z) stencil. The
+ * cylinder must lie inside the box in x and y. Outputs as orc_q2d's; bn0 in lines
+ * is B . the outward normal at the seed. */
+int orc_qcyl(const orc_field *f, const orc_cyl *cyl, double theta0, double dtheta,
+             int64_t ntheta, double z0, double dz, int64_t nz, const orc_opts *o, double *q,
+             double *tw, double *len, uint16_t *status, orc_lines *lines);
 
 /* Method I with S1, S2 rotated perpendicular to B at the line's ends (Q_perp,
  * Section 2.1) on the 2-D seed grid of orc_q2d, from the 3-D end displacements of

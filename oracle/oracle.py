@@ -36,6 +36,13 @@ class _Field(C.Structure):
     ]
 
 
+class _Cyl(C.Structure):
+    _fields_ = [("xc", C.c_double), ("yc", C.c_double), ("r", C.c_double)]
+
+
+ORC_FACE_CYL = 6
+
+
 class _Opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double),
@@ -91,6 +98,9 @@ def _load():
                                      C.c_double * 3, C.c_int64, C.c_int64, C.c_double,
                                      C.c_double, C.POINTER(_Opts), C.c_void_p, C.c_void_p,
                                      C.c_void_p]
+        lib.orc_qcyl.argtypes = [C.POINTER(_Field), C.POINTER(_Cyl), C.c_double, C.c_double,
+                                 C.c_int64, C.c_double, C.c_double, C.c_int64, C.POINTER(_Opts),
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.orc_default_opts.argtypes = [C.POINTER(_Opts)]
         lib.orc_threads.restype = C.c_int
         lib.orc_q2d_points.argtypes = [C.POINTER(_Field), C.c_double * 3, C.c_double * 3,
@@ -285,6 +295,29 @@ def q3d_points(B: np.ndarray, grid, vox, pts, opts: Optional[dict] = None) -> di
                             out["status"].ctypes.data, C.byref(s))
     if rc != 0:
         raise ValueError("orc_q3d_points: point index out of range")
+    out["lines"] = arrs
+    return out
+
+
+def qcyl(B: np.ndarray, grid, cyl, opts: Optional[dict] = None) -> dict:
+    """Q, Tw, length, status (shape (nz, ntheta), theta fastest) and lines on a
+    cylindrical mapping surface; `cyl` has centre (xc, yc), r, theta0, dtheta, ntheta,
+    z0, dz, nz (synth.Cylinder)."""
+    lib = _load()
+    h = _FieldHolder(B, grid, want_curl=(opts or {}).get("want_tw", 1) != 0)
+    n = cyl.ntheta * cyl.nz
+    out = {"q": np.full(n, np.nan), "tw": np.full(n, np.nan), "len": np.full(n, np.nan),
+           "status": np.zeros(n, np.uint16)}
+    s, arrs = _lines_struct(n)
+    c = _Cyl(float(cyl.centre[0]), float(cyl.centre[1]), float(cyl.r))
+    rc = lib.orc_qcyl(C.byref(h.f), C.byref(c), float(cyl.theta0), float(cyl.dtheta), int(cyl.ntheta),
+                      float(cyl.z0), float(cyl.dz), int(cyl.nz), C.byref(_opts(opts)),
+                      out["q"].ctypes.data, out["tw"].ctypes.data, out["len"].ctypes.data,
+                      out["status"].ctypes.data, C.byref(s))
+    if rc != 0:
+        raise RuntimeError(f"orc_qcyl failed: {rc}")
+    for k in ("q", "tw", "len", "status"):
+        out[k] = out[k].reshape(cyl.nz, cyl.ntheta)
     out["lines"] = arrs
     return out
 

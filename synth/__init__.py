@@ -8,6 +8,7 @@ the CPU oracle (``oracle/``) and in the HIP library (``paper_2208_12569_amd/``).
 from .fields import (  # noqa: F401
     Grid,
     Plane,
+    Cylinder,
     Voxels,
     cubic_grid,
     geometric_axis,

@@ -114,6 +114,29 @@ def stretched_grid(x: np.ndarray, y: np.ndarray, z: np.ndarray) -> Grid:
 
 
 @dataclass
+class Cylinder:
+    """Seeds on a cylindrical mapping surface (axis along z through `centre`, radius
+    r): seed (i, j) = (xc + r cos(theta0 + i dtheta), yc + r sin(theta0 + i dtheta),
+    z0 + j dz), i < ntheta (fastest), j < nz."""
+
+    centre: Tuple[float, float]
+    r: float
+    theta0: float
+    dtheta: float
+    ntheta: int
+    z0: float
+    dz: float
+    nz: int
+
+    def points(self) -> np.ndarray:
+        th = self.theta0 + self.dtheta * np.arange(self.ntheta)
+        z = self.z0 + self.dz * np.arange(self.nz)
+        Z, TH = np.meshgrid(z, th, indexing="ij")
+        return np.stack([self.centre[0] + self.r * np.cos(TH), self.centre[1] + self.r * np.sin(TH), Z],
+                        axis=-1).reshape(-1, 3)
+
+
+@dataclass
 class Plane:
     """A 2-D seed grid: seed (i, j) = origin + i*du*u + j*dv*v, i < nu, j < nv.
 

@@ -1006,3 +1006,72 @@ def test_perp_agrees_with_method2(orc):
         r = orc.q2d_perp(w.field, w.grid, pl, {"tol": 1e-12})
         m = orc.method2(w.field, w.grid, pl.points()[4:5], 2, {"tol": 1e-12})
         assert abs(r["qperp"][1, 1] / m["qperp"][0] - 1) < 1e-4, (centre, r["qperp"][1, 1], m["qperp"][0])
+
+
+# --------------------------------------------------------------------------------------
+# a cylindrical mapping surface (Section 3: B = (x, -y, 0) with S1, S2 on x^2 + y^2 = 1)
+# --------------------------------------------------------------------------------------
+
+
+def _cyl_box():
+    return synth.Grid(31, 31, 11, (-1.5, -1.5, 0.0), (0.1, 0.1, 0.1))
+
+
+def test_cylinder_paper_example(orc):
+    """B = (x, -y, 0), mapping surface x^2 + y^2 = 1: for 0 < theta < pi/2 the line
+    inside the cylinder maps theta1 -> pi/2 - theta1 at the same z, so Q = 2
+    (Section 3); Tw = 0 (curl-free); the length is the arc of the hyperbola
+    x y = sin(2 theta1) / 2 between the two crossings (integrated here by scipy);
+    the half pointing out of the cylinder ends at its seed."""
+    from scipy.integrate import quad
+
+    g = _cyl_box()
+    B = linear_field(g, [[1, 0, 0], [0, -1, 0], [0, 0, 0]], [0, 0, 0])
+    cyl = synth.Cylinder((0.0, 0.0), 1.0, 0.1, 0.05, 27, 0.2, 0.1, 5)
+    r = orc.qcyl(B, g, cyl, {"tol": 1e-10})
+    th = cyl.theta0 + cyl.dtheta * np.arange(cyl.ntheta)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.all(r["status"][inner] == 0)
+    assert np.allclose(r["q"][inner], 2.0, rtol=1e-9)
+    assert np.allclose(r["tw"], 0.0, atol=1e-12)
+    L = r["lines"]
+    fb = L["face_b"].reshape(cyl.nz, cyl.ntheta)
+    ff = L["face_f"].reshape(cyl.nz, cyl.ntheta)
+    assert np.all(fb == orc.ORC_FACE_CYL) and np.all(ff == orc.ORC_FACE_CYL)
+    # B . n = cos 2 theta: below pi/4 the forward half leaves at once, above it the backward one
+    eb = L["end_b"].reshape(cyl.nz, cyl.ntheta, 3)
+    ef = L["end_f"].reshape(cyl.nz, cyl.ntheta, 3)
+    seeds = cyl.points().reshape(cyl.nz, cyl.ntheta, 3)
+    far = np.where((th < math.pi / 4)[None, :, None], eb, ef)
+    near = np.where((th < math.pi / 4)[None, :, None], ef, eb)
+    assert np.allclose(near, seeds, atol=0)
+    assert np.allclose(np.arctan2(far[..., 1], far[..., 0]), math.pi / 2 - th[None, :], atol=1e-10)
+    assert np.allclose(far[..., 2], seeds[..., 2], atol=1e-12)
+    for k in (0, 5, 20):
+        c = 0.5 * math.sin(2 * th[k])
+        x1, x2 = sorted((math.cos(th[k]), math.sin(th[k])))
+        arc = quad(lambda x: math.sqrt(1 + c * c / x ** 4), x1, x2, epsabs=1e-13)[0]
+        assert abs(r["len"][2, k] - arc) < 1e-9
+
+
+def test_cylinder_tilted_uniform_field(orc):
+    """B = (1, 0, bz) through the cylinder: a line from theta1 (pi/2 < theta1 < 3pi/2,
+    where B points inward) crosses to pi - theta1 and rises 2 bz |cos theta1|, so on
+    (r theta, z) coordinates D = [[-1, 0], [2 bz sin theta1, 1]], |Bn1/Bn2| = 1 and
+    Q = 2 + 4 bz^2 sin^2 theta1 (the central difference over theta1 +- dtheta gives
+    that entry times sin(dtheta)/dtheta exactly); the length is 2 |cos theta1|
+    sqrt(1 + bz^2). The seed row straddles theta = pi, where the arc-length
+    coordinate wraps."""
+    g = _cyl_box()
+    bz = 0.3
+    B = linear_field(g, np.zeros((3, 3)), [1.0, 0.0, bz])
+    cyl = synth.Cylinder((0.0, 0.0), 1.0, 2.0, 0.04, 56, 0.1, 0.02, 4)
+    r = orc.qcyl(B, g, cyl, {"tol": 1e-11})
+    th = cyl.theta0 + cyl.dtheta * np.arange(cyl.ntheta)
+    inner = (slice(1, -1), slice(1, -1))
+    c = 2 * bz * np.sin(th) * math.sin(cyl.dtheta) / cyl.dtheta
+    qexp = np.broadcast_to(2 + c * c, r["q"].shape)
+    assert np.all(r["status"][inner] == 0)
+    assert np.allclose(r["q"][inner], qexp[inner], rtol=1e-7)
+    lexp = np.broadcast_to(2 * np.abs(np.cos(th)) * math.sqrt(1 + bz * bz), r["len"].shape)
+    assert np.allclose(r["len"], lexp, atol=1e-10)
