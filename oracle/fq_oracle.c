@@ -502,6 +502,23 @@ static int land_cyl(const line_ctx *L, const orc_cyl *c, const double y[NY], dou
     int side = 0, st;
     double cur[NY];
     memcpy(cur, out, sizeof cur);
+    if (!(ga < 0.0)) {
+        /* a step from the cylinder itself (a seed, phi = 0 to rounding) that ends
+         * outside it: the line went inside first (its direction points inward), so
+         * the crossing sought is the far root; bracket it with an inside point of
+         * the step, halving back towards its start */
+        double tt = t_hi;
+        for (int k = 0; k < 60 && !(ga < 0.0); k++) {
+            tt *= 0.5;
+            if ((st = rk4_doubled(L, y, tt, cur, &err))) return st;
+            if (cyl_phi(c, cur) < 0.0) ta = tt, ga = cyl_phi(c, cur);
+        }
+        if (!(ga < 0.0)) {
+            memcpy(out, y, sizeof cur);  /* never inside: the line ends at its start */
+            *t_out = 0.0;
+            return 0;
+        }
+    }
     for (int it = 0; it < 400; it++) {
         t = (ta * gb - tb * ga) / (gb - ga);
         if (!(t > ta && t < tb)) t = 0.5 * (ta + tb);
@@ -707,12 +724,10 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
                 /* the step leaves the cylinder: end on it */
                 double yc_[NY], tc;
                 memcpy(yc_, y1, sizeof yc_);
-                if (cyl_phi(cyl, y) < 0.0 &&
-                    (st = land_cyl(&L, cyl, y, h, cyl_phi(cyl, y1), yc_, &tc))) {
+                if ((st = land_cyl(&L, cyl, y, h, cyl_phi(cyl, y1), yc_, &tc))) {
                     res->status = st;
                     return;
                 }
-                if (!(cyl_phi(cyl, y) < 0.0)) memcpy(yc_, y, sizeof yc_);
                 CYL_END(yc_);
                 return;
             }
@@ -789,12 +804,10 @@ static void trace_half_gen(const orc_field *f, const double seed[3], int sigma,
             /* the line meets the cylinder before this cell face: end on it */
             double yc_[NY], tc;
             memcpy(yc_, y_best, sizeof yc_);
-            if (cyl_phi(cyl, y) < 0.0 &&
-                (st = land_cyl(&L, cyl, y, t_best, cyl_phi(cyl, y_best), yc_, &tc))) {
+            if ((st = land_cyl(&L, cyl, y, t_best, cyl_phi(cyl, y_best), yc_, &tc))) {
                 res->status = st;
                 return;
             }
-            if (!(cyl_phi(cyl, y) < 0.0)) memcpy(yc_, y, sizeof yc_);
             CYL_END(yc_);
             return;
         }

@@ -1075,3 +1075,24 @@ def test_cylinder_tilted_uniform_field(orc):
     assert np.allclose(r["q"][inner], qexp[inner], rtol=1e-7)
     lexp = np.broadcast_to(2 * np.abs(np.cos(th)) * math.sqrt(1 + bz * bz), r["len"].shape)
     assert np.allclose(r["len"], lexp, atol=1e-10)
+
+
+def test_cylinder_short_chords_near_tangency(orc):
+    """B = (1, 0, 0) with seeds just past theta = pi/2, where B barely points into
+    the cylinder: the chords to pi - theta1 are far shorter than a first step (2
+    |cos theta1| down to 2e-6), so the far crossing is bracketed from the surface
+    itself; ends and lengths as the closed form gives them. At a grazing angle a the
+    crossing is conditioned by phi's rounding, about 1e-16 / (2 a) along the line."""
+    g = _cyl_box()
+    B = linear_field(g, np.zeros((3, 3)), [1.0, 0.0, 0.0])
+    for d in (1e-2, 1e-4, 1e-6):
+        cyl = synth.Cylinder((0.0, 0.0), 1.0, math.pi / 2 + d, d / 4, 3, 0.5, 0.1, 3)
+        r = orc.qcyl(B, g, cyl, {"tol": 1e-12})
+        th = cyl.theta0 + cyl.dtheta * np.arange(3)
+        eb = r["lines"]["end_b"].reshape(3, 3, 3)
+        ef = r["lines"]["end_f"].reshape(3, 3, 3)
+        # B . n = cos theta < 0: the forward half runs inside, the backward one ends at once
+        assert np.allclose(eb, cyl.points().reshape(3, 3, 3), atol=0)
+        tol = 1e-13 + 4e-16 / d
+        assert np.allclose(np.arctan2(ef[..., 1], ef[..., 0]), math.pi - th[None, :], rtol=0, atol=tol)
+        assert np.allclose(r["len"], np.broadcast_to(2 * np.abs(np.cos(th)), (3, 3)), rtol=0, atol=2 * tol)
