@@ -176,6 +176,25 @@ typedef struct {
     int64_t n[3];
 } fq_voxels;
 
+/* A cylindrical mapping surface (Section 3: the x^2 + y^2 = 1 example): axis along z
+ * through `centre`, radius `radius`, inside the box in x and y. Map point (i, j),
+ * i < ntheta fastest, is the seed (xc + R cos(t), yc + R sin(t), z) with t = theta0 +
+ * i dtheta and z = z0 + j dz. Lines run inside the cylinder (and the box): the half
+ * whose direction at the seed points out of the cylinder ends at its seed, the other
+ * ends where it meets the cylinder again (face FQ_FACE_CYL) or leaves the box. S0, S1
+ * and S2 are the cylinder, with coordinates (R theta, z) and normal fields along its
+ * outward normal; Q by Method I (Eq. D+-2, D+-3, Q+-) on the (theta, z) stencil. */
+typedef struct {
+    double centre[2];
+    double radius;
+    double theta0, dtheta;
+    int64_t ntheta;
+    double z0, dz;
+    int64_t nz;
+} fq_cylinder;
+
+#define FQ_FACE_CYL 6 /* face id of an end on a cylindrical mapping surface */
+
 /* Per-line outputs, n entries each (end_b/end_f are n x 3); any pointer may be
  * NULL. The backward half runs against B, the forward half along it. */
 typedef struct {
@@ -239,6 +258,20 @@ int fastqsl_q2d(const fq_field *fields, const fq_plane *planes, int njobs, const
 size_t fastqsl_q3d_workspace_size(const fq_field *f, const fq_voxels *v, const fq_params *p);
 int fastqsl_q3d(const fq_field *f, const fq_voxels *v, const fq_params *p, const fq_map *map,
                 void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_qcyl — Q, Tw and length on a cylindrical mapping surface (Section 3's
+ * x^2 + y^2 = 1 example; Section 2.1's choice of S1, S2): the map of fq_cylinder,
+ * ntheta x nz points (theta fastest), by Method I. Both forms; RKF45 only (else
+ * FQ_EUNSUPPORTED); map->qperp and map->fledge are left untouched. Lines are
+ * reported as for fastqsl_q2d, with bn0 = B . the outward normal at the seed and
+ * face FQ_FACE_CYL for ends on the cylinder (bn_b/bn_f then along its outward
+ * normal). Errors: FQ_EINVAL for a cylinder that is empty, has a radius that is not
+ * positive and finite, or leaves the box in x or y.
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_qcyl_workspace_size(const fq_field *f, const fq_cylinder *c, const fq_params *p);
+int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, const fq_map *map,
+                 void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * fastqsl_backward — reverse-mode derivative of one q2d map with respect to the

@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     FQ_PREC_F64,
     FQ_METHOD_I,
     FQ_METHOD_II,
+    FQ_FACE_CYL,
     FQ_SCHEME_RK4,
     FQ_SCHEME_RK4_38,
     FQ_SCHEME_RKF45,
@@ -374,6 +375,30 @@ def q3d(B, grid, voxels, params: Optional[Params] = None, want_lines: bool = Fal
     w = _workspace(need, B.device, ws)
     _lib.check(lib.fastqsl_q3d(C.byref(f), C.byref(v), C.byref(p), C.byref(s), w.data_ptr(),
                                w.numel(), _stream(stream)), "fastqsl_q3d")
+    m["_ws"] = w
+    return m
+
+
+def qcyl(B, grid, cyl, params: Optional[Params] = None, want_lines: bool = False,
+         stream=None, ws=None) -> dict:
+    """Q, Tw and length on a cylindrical mapping surface (shape (nz, ntheta), theta
+    fastest); `cyl` has centre, r, theta0, dtheta, ntheta, z0, dz, nz."""
+    lib = _lib.load()
+    params = params or Params()
+    f = _field(B, grid)
+    c = _lib.fq_cylinder()
+    c.centre[:] = (float(cyl.centre[0]), float(cyl.centre[1]))
+    c.radius = float(cyl.r)
+    c.theta0, c.dtheta, c.ntheta = float(cyl.theta0), float(cyl.dtheta), int(cyl.ntheta)
+    c.z0, c.dz, c.nz = float(cyl.z0), float(cyl.dz), int(cyl.nz)
+    m, s = _alloc_map(c.ntheta * c.nz, (c.nz, c.ntheta), B.device, want_lines)
+    p = params.c()
+    need = lib.fastqsl_qcyl_workspace_size(C.byref(f), C.byref(c), C.byref(p))
+    if need == 0:
+        raise ValueError("invalid field, cylinder or parameters (or an unsupported combination)")
+    w = _workspace(need, B.device, ws)
+    _lib.check(lib.fastqsl_qcyl(C.byref(f), C.byref(c), C.byref(p), C.byref(s), w.data_ptr(),
+                                w.numel(), _stream(stream)), "fastqsl_qcyl")
     m["_ws"] = w
     return m
 

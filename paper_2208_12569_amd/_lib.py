@@ -64,6 +64,15 @@ class fq_voxels(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("spacing", C.c_double * 3), ("n", C.c_int64 * 3)]
 
 
+class fq_cylinder(C.Structure):
+    _fields_ = [("centre", C.c_double * 2), ("radius", C.c_double), ("theta0", C.c_double),
+                ("dtheta", C.c_double), ("ntheta", C.c_int64), ("z0", C.c_double),
+                ("dz", C.c_double), ("nz", C.c_int64)]
+
+
+FQ_FACE_CYL = 6
+
+
 class fq_lines(C.Structure):
     _fields_ = [("end_b", C.c_void_p), ("end_f", C.c_void_p), ("face_b", C.c_void_p),
                 ("face_f", C.c_void_p), ("bn_b", C.c_void_p), ("bn_f", C.c_void_p),
@@ -81,6 +90,7 @@ EXPORTS = [
     "fastqsl_trace_workspace_size", "fastqsl_trace",
     "fastqsl_q2d_workspace_size", "fastqsl_q2d",
     "fastqsl_q3d_workspace_size", "fastqsl_q3d",
+    "fastqsl_qcyl_workspace_size", "fastqsl_qcyl",
     "fastqsl_backward_workspace_size", "fastqsl_backward",
     "fastqsl_q2d_record", "fastqsl_backward_recorded",
     "fastqsl_strerror", "fastqsl_version",
@@ -119,6 +129,11 @@ def load():
     lib.fastqsl_q3d.argtypes = [P(fq_field), P(fq_voxels), P(fq_params), P(fq_map), C.c_void_p,
                                 C.c_size_t, C.c_void_p]
     lib.fastqsl_q3d.restype = C.c_int
+    lib.fastqsl_qcyl_workspace_size.argtypes = [P(fq_field), P(fq_cylinder), P(fq_params)]
+    lib.fastqsl_qcyl_workspace_size.restype = C.c_size_t
+    lib.fastqsl_qcyl.argtypes = [P(fq_field), P(fq_cylinder), P(fq_params), P(fq_map), C.c_void_p,
+                                 C.c_size_t, C.c_void_p]
+    lib.fastqsl_qcyl.restype = C.c_int
     lib.fastqsl_backward_workspace_size.argtypes = [P(fq_field), P(fq_plane), P(fq_params),
                                                     C.c_int]
     lib.fastqsl_backward_workspace_size.restype = C.c_size_t

@@ -27,13 +27,14 @@ struct Carve {
     }
 };
 
-enum SpecKind { SPEC_LIST, SPEC_PLANE, SPEC_VOXELS };
+enum SpecKind { SPEC_LIST, SPEC_PLANE, SPEC_VOXELS, SPEC_CYL };
 
 struct Spec {
     SpecKind kind;
     const fq_field *f;
     fq_plane pl;
     fq_voxels vx;
+    fq_cylinder cy;
     const double *seeds;
     int64_t nlist;
     double normal[3];
@@ -50,6 +51,7 @@ int64_t lines_of(const Spec &s)
     switch (s.kind) {
     case SPEC_LIST: return s.nlist;
     case SPEC_PLANE: return s.pl.nu * s.pl.nv;
+    case SPEC_CYL: return s.cy.ntheta * s.cy.nz;
     default: return s.vx.n[0] * s.vx.n[1] * s.vx.n[2];
     }
 }
@@ -82,6 +84,22 @@ int check_plane(const fq_plane *p)
     double vv = p->v[0] * p->v[0] + p->v[1] * p->v[1] + p->v[2] * p->v[2];
     double uv = p->u[0] * p->v[0] + p->u[1] * p->v[1] + p->u[2] * p->v[2];
     if (fabs(uu - 1.0) > 1e-9 || fabs(vv - 1.0) > 1e-9 || fabs(uv) > 1e-9) return FQ_EINVAL;
+    return FQ_OK;
+}
+
+// A cylinder map: points, radius, steps; the cylinder inside the box in x and y.
+int check_cylinder(const fq_cylinder *c, const fq_field *f)
+{
+    if (!c) return FQ_EINVAL;
+    if (c->ntheta < 1 || c->nz < 1 || c->ntheta * c->nz > ((int64_t)1 << 34)) return FQ_EINVAL;
+    if (!(c->radius > 0.0) || !isfinite(c->radius)) return FQ_EINVAL;
+    if (!isfinite(c->theta0) || !isfinite(c->dtheta) || !isfinite(c->z0) || !isfinite(c->dz) ||
+        !isfinite(c->centre[0]) || !isfinite(c->centre[1]))
+        return FQ_EINVAL;
+    for (int a = 0; a < 2; a++) {
+        const double lo = f->origin[a], hi = f->origin[a] + (f->n[a] - 1) * f->spacing[a];
+        if (!(c->centre[a] - c->radius >= lo && c->centre[a] + c->radius <= hi)) return FQ_EINVAL;
+    }
     return FQ_OK;
 }
 
@@ -215,6 +233,21 @@ void set_map_geometry(const Spec &s, MapJob &m)
             m.p_c[a] = a == 2 ? s.vx.spacing[2] : 0.0;
             m.normal[a] = s.normal[a];
         }
+    } else if (s.kind == SPEC_CYL) {
+        // points (theta, z): theta0 + i dtheta, z0 + j dz on the cylinder
+        m.nu = s.cy.ntheta;
+        m.nv = s.cy.nz;
+        m.nlayers = 1;
+        m.d0 = s.cy.radius * s.cy.dtheta;
+        m.d1 = s.cy.dz;
+        m.is_cyl = 1;
+        m.cyl[0] = s.cy.centre[0];
+        m.cyl[1] = s.cy.centre[1];
+        m.cyl[2] = s.cy.radius;
+        m.p_origin[0] = s.cy.theta0;
+        m.p_a[0] = s.cy.dtheta;
+        m.p_origin[1] = s.cy.z0;
+        m.p_b[1] = s.cy.dz;
     } else {
         m.nu = s.nlist;
         m.nv = 1;
@@ -255,6 +288,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     for (int i = 0; i < ns; i++)
         if (specs[i].kind == SPEC_LIST) m2 = false;
     if (m2 && (P.scheme != FQ_SCHEME_RKF45 || bwd)) return FQ_EUNSUPPORTED;
+    for (int i = 0; i < ns; i++)
+        if (specs[i].kind == SPEC_CYL && (m2 || bwd || P.scheme != FQ_SCHEME_RKF45)) return FQ_EUNSUPPORTED;
     for (int i = 0; i < ns; i++)
         if (stretched(specs[i].f) && (m2 || bwd)) return FQ_EUNSUPPORTED;
     Carve cv;
@@ -440,6 +475,17 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                 J.s_a[a] = s.pl.du * s.pl.u[a];
                 J.s_b[a] = s.pl.dv * s.pl.v[a];
             }
+        } else if (s.kind == SPEC_CYL) {
+            J.kind = SEED_CYL;
+            J.tile[0] = 8, J.tile[1] = 8, J.tile[2] = 1;
+            J.dims[0] = s.cy.ntheta, J.dims[1] = s.cy.nz, J.dims[2] = 1;
+            J.cyl[0] = s.cy.centre[0];
+            J.cyl[1] = s.cy.centre[1];
+            J.cyl[2] = s.cy.radius;
+            J.s_origin[0] = s.cy.theta0;
+            J.s_a[0] = s.cy.dtheta;
+            J.s_origin[1] = s.cy.z0;
+            J.s_b[1] = s.cy.dz;
         } else {
             J.kind = SEED_VOXELS;
             J.tile[0] = 4, J.tile[1] = 4, J.tile[2] = 4;
@@ -512,8 +558,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.tol_floor = P.tol_floor;
     tp.scheme = P.scheme;
     tp.method = m2 ? FQ_METHOD_II : FQ_METHOD_I;
-    for (int i = 0; i < ns; i++)
+    for (int i = 0; i < ns; i++) {
         if (stretched(specs[i].f)) tp.stretched = 1;
+        if (specs[i].kind == SPEC_CYL) tp.cyl = 1;
+    }
     tp.max_steps = P.max_steps;
     tp.want_tw = P.want_tw;
     tp.njobs = njobs;
@@ -545,7 +593,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                 MapJob mq = maps[i];  // Q only: the final pass writes every output
                 memset(&mq.out, 0, sizeof mq.out);
                 mq.out.q = maps[i].out.q;
-                FQ_TRY(m2 ? launch_m2_map(mq, stream) : launch_stencil(mq, stream));
+                FQ_TRY(specs[i].kind == SPEC_CYL ? launch_cyl_map(mq, stream)
+                       : m2                     ? launch_m2_map(mq, stream)
+                                                : launch_stencil(mq, stream));
             }
         // Method I keeps the FP32 pass's twist and re-traces positions only, then the
         // half lines that pass could not finish with the twist (split lists); Method
@@ -642,6 +692,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     for (int i = 0; i < ns; i++) {
         if (specs[i].kind == SPEC_LIST) FQ_TRY(launch_lines_out(maps[i], specs[i].seeds, stream));
+        else if (specs[i].kind == SPEC_CYL) FQ_TRY(launch_cyl_map(maps[i], stream));
         else if (m2) FQ_TRY(launch_m2_map(maps[i], stream));
         else FQ_TRY(launch_stencil(maps[i], stream));
         // Q_perp by Method I (plane maps) and the length edge map (plane maps, both
@@ -833,6 +884,39 @@ int fastqsl_q3d(const fq_field *f, const fq_voxels *vx, const fq_params *p, cons
     s.f = f;
     s.vx = *vx;
     s.normal[2] = 1.0;
+    s.map = map;
+    std::vector<Spec> v(1, s);
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream);
+}
+
+size_t fastqsl_qcyl_workspace_size(const fq_field *f, const fq_cylinder *c, const fq_params *p)
+{
+    fq_params P;
+    if (resolve_params(p, P) || check_field(f) || check_cylinder(c, f)) return 0;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_CYL;
+    s.f = f;
+    s.cy = *c;
+    std::vector<Spec> v(1, s);
+    size_t need = 0;
+    if (run(v, P, nullptr, 0, true, &need, nullptr)) return 0;
+    return need;
+}
+
+int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, const fq_map *map,
+                 void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if ((rc = check_field(f)) || (rc = check_cylinder(c, f))) return rc;
+    if (!map) return FQ_EINVAL;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_CYL;
+    s.f = f;
+    s.cy = *c;
     s.map = map;
     std::vector<Spec> v(1, s);
     return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream);

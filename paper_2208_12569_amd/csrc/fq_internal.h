@@ -15,7 +15,11 @@ enum SeedKind : int32_t {
     SEED_PLANE = 1,   // origin + i a + j b   (a = du u, b = dv v)
     SEED_VOXELS = 2,  // origin + i a + j b + k c (a, b, c along the axes)
     SEED_ROTATED = 3, // r0 +- delta U, r0 +- delta V of the rotated-S0 list
+    SEED_CYL = 4,     // (xc + R cos(t0 + i dt), yc + R sin(t0 + i dt), z0 + j dz)
 };
+
+// face id of a half line that ends on a cylindrical mapping surface
+constexpr int kFaceCyl = FQ_FACE_CYL;
 
 // One rotated-S0 point: its map index, centre and in-plane unit vectors.
 struct RotEntry {
@@ -63,6 +67,8 @@ struct TraceJob {
     double s_origin[3];
     double s_a[3], s_b[3], s_c[3];
     double normal[3];    // S0 normal (Eq. step / Eq. tol scaling)
+    double cyl[3];       // SEED_CYL: axis (xc, yc) and radius R; seeds use s_origin[0] = t0,
+                         // s_a[0] = dt, s_origin[1] = z0, s_b[1] = dz; lines run inside it
     const double *seeds;          // SEED_LIST
     const RotEntry *rot;          // SEED_ROTATED
     const uint32_t *rot_count;    // SEED_ROTATED: number of valid entries
@@ -118,7 +124,8 @@ struct TraceParams {
     int32_t njobs;
     int64_t static_items;          // queue items of all jobs except a trailing rotated job
     int32_t dynamic_last;          // 1 if the last job is SEED_ROTATED (items known on device)
-    int32_t pad;
+    int32_t cyl;                   // some job runs inside a cylindrical mapping surface
+                                   // (multi-job kernels then)
     unsigned long long *stats;     // optional counters (trials, accepted, fetches, halves, FP64 halves)
     const FixEntry *list;          // list mode: trace exactly these half lines
     const uint32_t *list_count;
@@ -209,7 +216,8 @@ struct MapJob {
     double normal[3];            // S0 normal
     double p_origin[3], p_a[3], p_b[3], p_c[3]; // point(i,j,k) = origin + i a + j b + k c
     int32_t on_face;             // every seed lies on a box face (no rotation)
-    int32_t pad;
+    int32_t is_cyl;              // a cylinder map: points (theta, z), S0 = S1 = S2 = the cylinder
+    double cyl[3];               // its axis (xc, yc) and radius
     double edge_eps;
     HalfRecs rec;                // records of the map's own lines (nlines = points)
     int64_t nlines;
@@ -243,6 +251,8 @@ hipError_t launch_m2_map(const MapJob &m, hipStream_t s);
 // Method I Q_perp (S1, S2 perpendicular to B at the ends; want_qperp) and the length
 // edge map |grad_S0 length| of a map, from its lines' records and stencil.
 hipError_t launch_perp_map(const MapJob &m, int want_qperp, hipStream_t s);
+// Method I Q of a cylinder map (surface coordinates on the cylinder).
+hipError_t launch_cyl_map(const MapJob &m, hipStream_t s);
 hipError_t launch_lines_out(const MapJob &m, const double *seeds_list, hipStream_t s);
 
 }  // namespace fq

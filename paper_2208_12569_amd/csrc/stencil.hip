@@ -124,6 +124,17 @@ __global__ void classify_kernel(MapJob m, int32_t *rot_index, RotEntry *rot,
     }
 }
 
+// The normal field at an end on `face`: the face's axis component, or on a
+// cylindrical mapping surface the component along its outward normal.
+__device__ __forceinline__ double end_bn(const MapJob &m, int face, const double e[3], const double B[3])
+{
+    if (face == kFaceCyl) {
+        const double dx = e[0] - m.cyl[0], dy = e[1] - m.cyl[1];
+        return (B[0] * dx + B[1] * dy) / sqrt(dx * dx + dy * dy);
+    }
+    return comp3(B, face >> 1);
+}
+
 __device__ __forceinline__ void write_line(const MapJob &m, const fq_lines &o, int64_t l, const double seed[3])
 {
     const int64_t hb = l, hf = m.nlines + l;
@@ -147,20 +158,21 @@ __device__ __forceinline__ void write_line(const MapJob &m, const fq_lines &o, i
         if (o.bn_b) {
             if (fb >= 0) {
                 field64(m, eb, B);
-                o.bn_b[l] = comp3(B, fb >> 1);
+                o.bn_b[l] = end_bn(m, fb, eb, B);
             } else o.bn_b[l] = NAN;
         }
         if (o.bn_f) {
             if (ff >= 0) {
                 field64(m, ef, B);
-                o.bn_f[l] = comp3(B, ff >> 1);
+                o.bn_f[l] = end_bn(m, ff, ef, B);
             } else o.bn_f[l] = NAN;
         }
         if (o.bn0) {
             if (st & FQ_ST_OUTSIDE) o.bn0[l] = NAN;
             else {
                 field64(m, seed, B);
-                o.bn0[l] = B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
+                o.bn0[l] = m.is_cyl ? end_bn(m, kFaceCyl, seed, B)
+                                    : B[0] * m.normal[0] + B[1] * m.normal[1] + B[2] * m.normal[2];
             }
         }
     }
@@ -393,6 +405,111 @@ __global__ __launch_bounds__(256) void perp_kernel(MapJob m, int want_qperp)
     }
 }
 
+// Method I on a cylindrical mapping surface (Section 3's x^2 + y^2 = 1 example): the
+// point's stencil along theta and z, end coordinates (R theta, z) on the cylinder
+// (arc lengths taken on the centre line's branch) or in-face ones on a box face,
+// and Eq. D+-2, D+-3, Q+- with normal fields along the cylinder's outward normal.
+__device__ __forceinline__ void cyl_uv(const MapJob &m, int face, const double e[3], double uv[2])
+{
+    if (face == kFaceCyl) {
+        uv[0] = m.cyl[2] * atan2(e[1] - m.cyl[1], e[0] - m.cyl[0]);
+        uv[1] = e[2];
+    } else {
+        inface(face, e, uv);
+    }
+}
+
+__device__ __forceinline__ double unwrap(const MapJob &m, double u, double ref)
+{
+    const double turn = 2.0 * M_PI * m.cyl[2];
+    return u - turn * rint((u - ref) / turn);
+}
+
+// One stencil axis: derivatives of the S1 and S2 end coordinates per unit seed
+// coordinate from the usable neighbours at pt -+ stride (central, else one-sided).
+__device__ __forceinline__ bool cyl_axis(const MapJob &m, const Line &c, int64_t pt, int64_t stride,
+                                         bool hm, bool hp, double delta, double d1[2], double d2[2],
+                                         uint16_t &st)
+{
+    Line lm, lp;
+    bool okm = false, okp = false;
+    if (hm) {
+        read_line(m.rec, m.nlines, pt - stride, lm);
+        okm = !(lm.st & kFatal) && lm.f1 == c.f1 && lm.f2 == c.f2;
+        if (edge_end(m, lm.f1, lm.e1) || edge_end(m, lm.f2, lm.e2)) st |= FQ_ST_EDGE;
+    }
+    if (hp) {
+        read_line(m.rec, m.nlines, pt + stride, lp);
+        okp = !(lp.st & kFatal) && lp.f1 == c.f1 && lp.f2 == c.f2;
+        if (edge_end(m, lp.f1, lp.e1) || edge_end(m, lp.f2, lp.e2)) st |= FQ_ST_EDGE;
+    }
+    if (!okm && !okp) return false;
+    if (!(okm && okp)) st |= FQ_ST_ONESIDED;
+    const Line &lo = okm ? lm : c, &hi = okp ? lp : c;
+    double c1[2], c2[2], l1[2], l2[2], h1[2], h2[2];
+    cyl_uv(m, c.f1, c.e1, c1);
+    cyl_uv(m, c.f2, c.e2, c2);
+    cyl_uv(m, lo.f1, lo.e1, l1);
+    cyl_uv(m, lo.f2, lo.e2, l2);
+    cyl_uv(m, hi.f1, hi.e1, h1);
+    cyl_uv(m, hi.f2, hi.e2, h2);
+    if (c.f1 == kFaceCyl) l1[0] = unwrap(m, l1[0], c1[0]), h1[0] = unwrap(m, h1[0], c1[0]);
+    if (c.f2 == kFaceCyl) l2[0] = unwrap(m, l2[0], c2[0]), h2[0] = unwrap(m, h2[0], c2[0]);
+    const double inv = 1.0 / ((okm && okp) ? 2.0 * delta : delta);
+    for (int q = 0; q < 2; q++) {
+        d1[q] = (h1[q] - l1[q]) * inv;
+        d2[q] = (h2[q] - l2[q]) * inv;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void cyl_map_kernel(MapJob m)
+{
+    const int64_t np = m.nu * m.nv;
+    for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
+         pt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = pt / m.nu, i = pt - j * m.nu;
+        const double t = m.p_origin[0] + (double)i * m.p_a[0];
+        const double r0[3] = {m.cyl[0] + m.cyl[2] * cos(t), m.cyl[1] + m.cyl[2] * sin(t),
+                              m.p_origin[1] + (double)j * m.p_b[1]};
+        Line c;
+        read_line(m.rec, m.nlines, pt, c);
+        uint16_t st = c.st;
+        if (edge_end(m, c.f1, c.e1) || edge_end(m, c.f2, c.e2)) st |= FQ_ST_EDGE;
+        double q = NAN, tw = NAN, len = NAN;
+        if (!(c.st & kFatal)) {
+            tw = c.tw;
+            len = c.len;
+            double d1x[2], d2x[2], d1y[2], d2y[2];
+            if (cyl_axis(m, c, pt, 1, i > 0, i < m.nu - 1, m.d0, d1x, d2x, st) &&
+                cyl_axis(m, c, pt, m.nu, j > 0, j < m.nv - 1, m.d1, d1y, d2y, st)) {
+                double B0[3], B1[3], B2[3];
+                field64(m, r0, B0);
+                field64(m, c.e1, B1);
+                field64(m, c.e2, B2);
+                const double bn0 = end_bn(m, kFaceCyl, r0, B0);
+                const double bn1 = end_bn(m, c.f1, c.e1, B1), bn2 = end_bn(m, c.f2, c.e2, B2);
+                // Eq. D+-3: (D10)^-1 = adj(D10) / |Bn0/Bn1|; Eq. D+-2: D12 = D20 (D10)^-1
+                const double s = fabs(bn0 / bn1);
+                const double i00 = d1y[1] / s, i01 = -d1y[0] / s, i10 = -d1x[1] / s, i11 = d1x[0] / s;
+                const double a = d2x[0] * i00 + d2y[0] * i10, b = d2x[0] * i01 + d2y[0] * i11;
+                const double cc = d2x[1] * i00 + d2y[1] * i10, d = d2x[1] * i01 + d2y[1] * i11;
+                q = (a * a + b * b + cc * cc + d * d) / fabs(bn1 / bn2);
+            } else {
+                st |= FQ_ST_MIXEDFACE;
+            }
+        }
+        if (m.out.q) m.out.q[pt] = q;
+        if (m.out.tw) m.out.tw[pt] = tw;
+        if (m.out.length) m.out.length[pt] = len;
+        if (m.out.status) m.out.status[pt] = st;
+        const fq_lines &o = m.out.lines;
+        if (o.end_b || o.end_f || o.face_b || o.face_f || o.bn_b || o.bn_f || o.bn0 || o.tw ||
+            o.length || o.status)
+            write_line(m, o, pt, r0);
+    }
+}
+
 __global__ void lines_kernel(MapJob m, const double *seeds)
 {
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < m.nlines;
@@ -439,6 +556,12 @@ hipError_t launch_perp_map(const MapJob &m, int want_qperp, hipStream_t s)
 {
     const int64_t np = m.nu * m.nv * m.nlayers;
     hipLaunchKernelGGL(perp_kernel, dim3(blocks_for(np)), dim3(256), 0, s, m, want_qperp);
+    return hipGetLastError();
+}
+
+hipError_t launch_cyl_map(const MapJob &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(cyl_map_kernel, dim3(blocks_for(m.nu * m.nv)), dim3(256), 0, s, m);
     return hipGetLastError();
 }
 

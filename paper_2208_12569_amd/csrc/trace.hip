@@ -62,6 +62,11 @@ __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, con
     return true;
 }
 
+// A line inside a cylindrical mapping surface ends on it once the surface is this
+// close (reference lengths): its last straight step then errs by about the square of
+// this, below the rounding of the compute type's local coordinates.
+template <typename T> constexpr double kCylEnd() { return sizeof(T) == 4 ? 1e-5 : 1e-10; }
+
 // A wave refills its idle lanes only once at least this many are idle (or none is
 // busy): the refill code runs for the whole wave, so refilling one lane at a time
 // would run it on almost every iteration. FP64 steps cost more, so idle lanes cost more
@@ -84,6 +89,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
 {
     using N = Num<T>;
     constexpr bool TW = TWM == 1;
+    // cylindrical mapping surfaces: the multi-job Method I kernels only
+    constexpr bool CYLK = !UNI && !M2 && !TAPE;
     const int lane = threadIdx.x & 63;
 
     // queue size
@@ -125,6 +132,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
     // grid's smallest cell width, found on the device
     bool str = false;
     double dref_s = 0.0;
+    // cylindrical mapping surfaces (multi-job kernels only, as stretched grids): the
+    // lane's job runs inside the cylinder; the state before the trial step (a step
+    // that leaves the cylinder is taken again, shorter) and phi = r^2 - R^2 there
+    bool cylj = false;
+    int sv_c0 = 0, sv_c1 = 0, sv_c2 = 0;
+    T sv_p0 = T(0), sv_p1 = T(0), sv_p2 = T(0);
+    double sv_tw = 0.0, sv_len = 0.0, cphi = 0.0;
     T cb[3][8], cj[3][8];
     Tan<T> tn;  // Method II
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
@@ -168,7 +182,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                         const TraceJob &J = jobs[j];
                         const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
                         const int64_t local = it - J.item_base;
-                        if (J.kind == SEED_PLANE || J.kind == SEED_VOXELS) {
+                        if (J.kind == SEED_PLANE || J.kind == SEED_VOXELS || J.kind == SEED_CYL) {
                             // the forward and backward halves of a tile follow each
                             // other, so long lines of either direction start early
                             forward = ((local >> 6) & 1) == 0;
@@ -181,7 +195,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                     if (line >= 0) {
                         const TraceJob &J = jobs[j];
                         double r[3], nrm[3];
-                        seed_of_line(J, line, r, nrm);
+                        seed_of_line<CYLK>(J, line, r, nrm);
                         jb = j;
                         if (!UNI) {
                             nodes = J.nodes;
@@ -193,6 +207,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                             K.rz = (T)J.rscale[2];
                             K.twk = (T)J.twk;
                             K.bnull2 = (T)((double)N::null_rel * (double)(*J.bmax2));
+                            cylj = J.kind == SEED_CYL;
+                            cphi = 0.0;
                             str = J.geo != nullptr;
                             if (!UNI && str) {
                                 dref_s = J.geo->dref;
@@ -275,8 +291,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 const float by = (float)poly<T>(cb[1], L.p0, L.p1, L.p2);
                 const float bz = (float)poly<T>(cb[2], L.p0, L.p1, L.p2);
                 const float b2 = bx * bx + by * by + bz * bz;
-                const float bn = bx * (float)J.normal[0] + by * (float)J.normal[1] +
-                                 bz * (float)J.normal[2];
+                float n0 = (float)J.normal[0], n1 = (float)J.normal[1], n2 = (float)J.normal[2];
+                if (CYLK && cylj) {
+                    // S0 is the cylinder: its outward normal at the seed
+                    n0 = (float)((grid_pos(J, 0, L.c0, (double)L.p0) - J.cyl[0]) / J.cyl[2]);
+                    n1 = (float)((grid_pos(J, 1, L.c1, (double)L.p1) - J.cyl[1]) / J.cyl[2]);
+                    n2 = 0.0f;
+                }
+                const float bn = bx * n0 + by * n1 + bz * n2;
                 // |Bn0/B| is taken no smaller than 0.05 where S0 is interior (the map
                 // rotates S0 perpendicular to B below that), but on a box face, where
                 // S0 is the physical S1, the angle itself scales the bound: near a
@@ -301,6 +323,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 }
                 // a fixed-step scheme keeps its step where RKF45 keeps its bound
                 L.tol = SCH != SCH_RKF45 ? L.h : (T)fmax(tp.tol_perp * (double)(ang * sqrtf(ang)), tp.tol_floor);
+                if (CYLK && cylj && !((float)L.sgn * bn < 0.0f)) {
+                    // heading out of (or along) the cylinder: the half ends at its seed
+                    fin_st = 0;
+                    fin_face = kFaceCyl;
+                }
                 if constexpr (M2) {
                     // S0 perpendicular to B at the seed, U and V orthonormal in it:
                     // U = e_a x b / |..| with e_a the axis least aligned with b, V = b x U
@@ -337,8 +364,59 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
         if (jb >= 0 && fin_st < 0) {
             n_trial++;
             const unsigned acc_before = n_acc;
+            if (CYLK && cylj) {
+                sv_c0 = L.c0, sv_c1 = L.c1, sv_c2 = L.c2;
+                sv_p0 = L.p0, sv_p1 = L.p1, sv_p2 = L.p2;
+                sv_tw = L.tw, sv_len = L.len;
+            }
             lane_iterate<T, TW, NoEvents, SCH, M2>(L, cb, cj, K, fin_st, fin_face, need_load, n_acc,
                                                    NoEvents(), &tn);
+            if (CYLK && cylj && fin_st < 0 && n_acc != acc_before) {
+                // Inside a cylindrical mapping surface: a step that ends outside it is
+                // taken again from its start, shorter (the secant estimate of where phi
+                // = r^2 - R^2 changes sign, undershot); near the surface the steps are
+                // held short of it, and within kCylEnd reference lengths the line
+                // ends on it with one straight step.
+                const TraceJob &J = jobs[jb];
+                const double dl = str ? dref_s : J.dref;
+                const double x = grid_pos(J, 0, L.c0, (double)L.p0), y = grid_pos(J, 1, L.c1, (double)L.p1),
+                             z = grid_pos(J, 2, L.c2, (double)L.p2);
+                const double dx = x - J.cyl[0], dy = y - J.cyl[1];
+                const double phi = dx * dx + dy * dy - J.cyl[2] * J.cyl[2];
+                if (phi > 0.0) {
+                    const double H = L.len - sv_len;
+                    const double tsec = H * (-cphi) / (phi - cphi);
+                    if (L.c0 != sv_c0 || L.c1 != sv_c1 || L.c2 != sv_c2) need_load = true;
+                    L.c0 = sv_c0, L.c1 = sv_c1, L.c2 = sv_c2;
+                    L.p0 = sv_p0, L.p1 = sv_p1, L.p2 = sv_p2;
+                    L.tw = sv_tw, L.len = sv_len;
+                    L.force = -1;
+                    L.h = (T)fmax(fmin(0.9 * tsec, 0.5 * H), (double)N::hmin);
+                } else {
+                    cphi = phi;
+                    const double r[3] = {x, y, z};
+                    double B[3];
+                    interp64(J.planes, r, B);
+                    const double sg = (double)L.sgn / sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                    const double ux = sg * B[0], uy = sg * B[1], uz = sg * B[2];
+                    const double b1 = dx * ux + dy * uy;  // half of d phi / ds
+                    if (b1 > 0.0) {
+                        const double est = -phi / (2.0 * b1);
+                        if (est <= kCylEnd<T>() * dl) {
+                            // phi + 2 b1 t + (ux^2 + uy^2) t^2 = 0, its root t >= 0
+                            const double t = -phi / (b1 + sqrt(b1 * b1 - (ux * ux + uy * uy) * phi));
+                            L.p0 += (T)(t * ux * inv_width(J, 0, L.c0));
+                            L.p1 += (T)(t * uy * inv_width(J, 1, L.c1));
+                            L.p2 += (T)(t * uz * inv_width(J, 2, L.c2));
+                            L.len += t / dl;
+                            fin_st = 0;
+                            fin_face = kFaceCyl;
+                        } else if ((double)L.h * dl > 0.9 * est) {
+                            L.h = (T)(0.9 * est / dl);
+                        }
+                    }
+                }
+            }
             if (TAPE && n_acc != acc_before) {
                 acc_half++;
                 if (fin_st < 0 && acc_half % tp.seg == 0) {
@@ -362,7 +440,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 // half line ends exactly at its seed, not at the seed's position as
                 // rounded into local coordinates of the compute type
                 double r[3], nrm[3];
-                seed_of_line(J, rec >= J.nlines ? rec - J.nlines : rec, r, nrm);
+                seed_of_line<CYLK>(J, rec >= J.nlines ? rec - J.nlines : rec, r, nrm);
                 e0 = r[0];
                 e1 = r[1];
                 e2 = r[2];
@@ -455,7 +533,8 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
             seed_graze = !(fabs(bn) >= thr * bm);
         }
         if (qmap) {
-            if ((J.kind == SEED_PLANE || J.kind == SEED_VOXELS) && l < J.nlines && qmap[l] > qthr)
+            if ((J.kind == SEED_PLANE || J.kind == SEED_VOXELS || J.kind == SEED_CYL) && l < J.nlines &&
+                qmap[l] > qthr)
                 seed_graze = true;
             if (J.kind == SEED_ROTATED && qmap[J.rot[l >> 2].point] > qthr) seed_graze = true;
         }
@@ -470,7 +549,15 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
                 double B[3];
                 interp64(J.planes, e, B);
                 const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-                redo = !(fabs(B[face >> 1]) >= thr * bm);
+                double bnf;
+                if (face == kFaceCyl) {
+                    // an end on a cylindrical mapping surface: along its outward normal
+                    const double dx = e[0] - J.cyl[0], dy = e[1] - J.cyl[1];
+                    bnf = (B[0] * dx + B[1] * dy) / sqrt(dx * dx + dy * dy);
+                } else {
+                    bnf = face == 0 || face == 1 ? B[0] : (face == 2 || face == 3 ? B[1] : B[2]);
+                }
+                redo = !(fabs(bnf) >= thr * bm);
             }
             if (unfinished && split) {
                 const uint32_t k = atomicAdd(count_tw, 1u);
@@ -741,7 +828,7 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     const bool f64 = prec == FQ_PREC_F64, s64 = store == FQ_DT_F64;
     if (!f64 && s64) return hipErrorInvalidValue;  // FP32 arithmetic reads FP32 records only
     // stretched grids take the multi-job kernels, which carry their per-cell scales
-    const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched;
+    const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched && !tp.cyl;
     if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
         // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, RKF45

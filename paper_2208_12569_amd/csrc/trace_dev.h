@@ -80,7 +80,9 @@ __device__ __forceinline__ int64_t live_lines(const TraceJob &J)
 }
 
 // Seed position of a line and the S0 normal used for the Eq. step / Eq. tol scaling
-// (zero for rotated S0, whose normal is along B).
+// (zero for rotated S0, whose normal is along B). CYL: cylinder jobs may occur (the
+// kernels that never see them leave out their trigonometry).
+template <bool CYL = true>
 __device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, double r[3],
                                              double nrm[3])
 {
@@ -99,6 +101,17 @@ __device__ __forceinline__ void seed_of_line(const TraceJob &J, int64_t line, do
         const double s = (which & 1) ? J.rot_delta : -J.rot_delta;
         for (int a = 0; a < 3; a++) r[a] = e.r0[a] + s * d[a];
         nrm[0] = nrm[1] = nrm[2] = 0.0;
+    } else if (CYL && J.kind == SEED_CYL) {
+        // a seed on the cylinder; the S0 normal is its outward normal there
+        const int64_t i = line % J.dims[0], j = line / J.dims[0];
+        const double t = J.s_origin[0] + (double)i * J.s_a[0];
+        const double ct = cos(t), st = sin(t);
+        r[0] = J.cyl[0] + J.cyl[2] * ct;
+        r[1] = J.cyl[1] + J.cyl[2] * st;
+        r[2] = J.s_origin[1] + (double)j * J.s_b[1];
+        nrm[0] = ct;
+        nrm[1] = st;
+        nrm[2] = 0.0;
     } else {
         const int64_t i = line % J.dims[0];
         const int64_t j = (line / J.dims[0]) % J.dims[1];
@@ -126,6 +139,12 @@ __device__ __forceinline__ int str_cell(const TraceJob &J, int a, double r, doub
     const double t = r == x[c + 1] ? 1.0 : (r - x[c]) * gptr(J.iw[a])[c];
     p = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     return c;
+}
+
+// 1 / the width of cell c along axis a of job J's grid.
+__device__ __forceinline__ double inv_width(const TraceJob &J, int a, int c)
+{
+    return J.iw[a] ? gptr(J.iw[a])[c] : J.inv_spacing[a];
 }
 
 // The position along axis a of local coordinate p in cell c of job J's grid.
@@ -165,7 +184,7 @@ __device__ __forceinline__ int64_t line_of_item(const TraceJob &J, int64_t t)
     const int w = (int)(t & 63);
     int64_t r0, i, j, k;
     const int64_t q0 = fdiv(ti, J.tiles[0], J.inv_t0, r0);
-    if (J.kind == SEED_PLANE) {
+    if (J.kind == SEED_PLANE || J.kind == SEED_CYL) {
         i = r0 * 8 + (w & 7);
         j = q0 * 8 + (w >> 3);
         k = 0;

@@ -151,6 +151,29 @@ int main()
                     CHECK(fastqsl_q2d_workspace_size(fs, pl, 1, &P4) == 0);
                 }
             }
+            // cylinder maps (RKF45, Method I only; the cylinder inside the box in x, y)
+            {
+                fq_cylinder cy;
+                memset(&cy, 0, sizeof cy);
+                cy.centre[0] = 0.5, cy.centre[1] = 0.5, cy.radius = 0.3;
+                cy.theta0 = 0.1, cy.dtheta = 0.05, cy.ntheta = 37, cy.z0 = 0.1, cy.dz = 0.05, cy.nz = 5;
+                std::vector<double> qc(37 * 5), tc(37 * 5);
+                std::vector<uint16_t> sc(37 * 5);
+                fq_map mc = map_of(qc, tc, sc);
+                size_t nc = fastqsl_qcyl_workspace_size(&f[0], &cy, &P);
+                CHECK(nc > 0);
+                CHECK(fastqsl_qcyl(&f[0], &cy, &P, &mc, workspace(nc), nc, nullptr) == FQ_OK);
+                CHECK(fastqsl_qcyl(&f[0], &cy, &P, &mc, workspace(nc), nc - 1, nullptr) == FQ_ENOMEM);
+                fq_params P5 = P;
+                P5.method = FQ_METHOD_II;
+                CHECK(fastqsl_qcyl_workspace_size(&f[0], &cy, &P5) == 0);
+                P5 = P;
+                P5.scheme = FQ_SCHEME_RK4;
+                CHECK(fastqsl_qcyl_workspace_size(&f[0], &cy, &P5) == 0);
+                cy.radius = 0.6;  // leaves the box in x
+                CHECK(fastqsl_qcyl_workspace_size(&f[0], &cy, &P) == 0);
+                CHECK(fastqsl_qcyl(&f[0], &cy, &P, &mc, workspace(nc), nc, nullptr) == FQ_EINVAL);
+            }
             // trace lists, including an empty one
             fq_lines L;
             memset(&L, 0, sizeof L);

@@ -140,6 +140,12 @@ hipError_t launch_m2_map(const MapJob &m, hipStream_t)
     g_calls++;
     return hipSuccess;
 }
+hipError_t launch_cyl_map(const MapJob &m, hipStream_t)
+{
+    in_ws(m.rec.end, (size_t)(2 * m.nlines) * 24, "line records");
+    g_calls++;
+    return hipSuccess;
+}
 hipError_t launch_perp_map(const MapJob &m, int, hipStream_t)
 {
     in_ws(m.rec.end, (size_t)(2 * m.nlines) * 24, "line records");
