@@ -243,7 +243,8 @@ int fastqsl_trace(const fq_field *f, const double *seeds, int64_t n, const doubl
  * queue, so cubes and seed grids of uneven sizes keep the GPU full. fields,
  * planes and maps are host arrays of njobs entries; map pointers are device
  * pointers of nu*nv entries. S0 on a box face is used as is; on an interior plane
- * S0 is rotated perpendicular to B where |Bn0/B| < 0.05 (Section 4).
+ * S0 is rotated perpendicular to B where |Bn0/B| < 0.05 (Section 4); a batch may
+ * mix both kinds.
  * ------------------------------------------------------------------------------- */
 size_t fastqsl_q2d_workspace_size(const fq_field *fields, const fq_plane *planes, int njobs,
                                   const fq_params *p);

@@ -327,9 +327,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             take_recs(cv, 4 * w.nlines, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
         }
     }
-    if (nrot > 1 || (nrot == 1 && ns > 1)) return FQ_EUNSUPPORTED;
     const int njobs = ns + nrot;
     const size_t off_jobs = cv.take((size_t)njobs * sizeof(TraceJob));
+    // the queue's size once the rotated-S0 jobs are counted (device)
+    const size_t off_total = cv.take(sizeof(int64_t));
     // FP64 pass of the FP32 form: re-trace list, its counter, and FP64 node records
     // when a field is stored in FP64 (FP32 records of an FP32 field are exact)
     const bool fixup = P.precision == FQ_PREC_F32X && P.graze > 0;
@@ -405,7 +406,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             FQ_TRY(launch_prep(*s.f, FQ_PREC_F64, P.want_tw, ws + w.nodes64, (float *)(ws + w.bmax),
                                stream));
     }
-    // rotated-S0 classification (only for a single map)
+    // rotated-S0 classification (each map with an interior S0)
     std::vector<MapJob> maps(ns);
     for (int i = 0; i < ns; i++) {
         const Spec &s = specs[i];
@@ -529,9 +530,11 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     TraceParams tp;
     memset(&tp, 0, sizeof tp);
+    std::vector<int> rot_spec;  // the spec of each rotated-S0 job (jobs ns, ns + 1, ...)
     for (int i = 0; i < ns; i++) {
         if (!W[i].rotate) continue;
         const SpecWs &w = W[i];
+        rot_spec.push_back(i);
         TraceJob &J = jobs[jj++];
         J = jobs[i];
         J.kind = SEED_ROTATED;
@@ -552,6 +555,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     TraceJob *jobs_dev = (TraceJob *)(ws + off_jobs);
     for (int j = 0; j < njobs && fwd; j++) FQ_TRY(launch_store_job(jobs[j], jobs_dev + j, stream));
+    if (nrot > 0 && fwd)
+        FQ_TRY(launch_rot_ranges(jobs_dev, ns, nrot, items, (int64_t *)(ws + off_total), stream));
+    tp.total_dev = (const int64_t *)(ws + off_total);
     tp.tol_perp = P.tol_perp;
     tp.step_perp = P.step_perp;
     tp.step_min = P.step_min;
@@ -607,8 +613,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr), 2, 0u, stream));
         for (int j = 0; j < njobs; j++) {
             // the spec whose map decides the Q rule: a main job's own, or for the
-            // rotated-S0 job (only with a single spec) the map of spec 0
-            const int sp = j < ns ? j : 0;
+            // rotated-S0 job the map of the spec it belongs to
+            const int sp = j < ns ? j : rot_spec[j - ns];
             const double *qmap = (qsel && specs[sp].kind != SPEC_LIST) ? maps[sp].out.q : nullptr;
             FQ_TRY(launch_graze(jobs_dev, j, jobs[j].nlines, P.graze, qmap, P.qfix, list, lcount,
                                 lcount + 1, 2 * all_lines, split, !m2, stream));

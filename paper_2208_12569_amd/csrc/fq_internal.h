@@ -122,8 +122,11 @@ struct TraceParams {
     int64_t max_steps;
     int32_t want_tw;
     int32_t njobs;
-    int64_t static_items;          // queue items of all jobs except a trailing rotated job
-    int32_t dynamic_last;          // 1 if the last job is SEED_ROTATED (items known on device)
+    int64_t static_items;          // queue items of the main jobs (before the rotated ones)
+    int32_t dynamic_last;          // 1 if rotated-S0 jobs follow the main jobs: their item
+                                   // ranges and the queue's size (*total_dev) are set on
+                                   // the device once the classify passes have counted them
+    const int64_t *total_dev;
     int32_t cyl;                   // some job runs inside a cylindrical mapping surface
                                    // (multi-job kernels then)
     unsigned long long *stats;     // optional counters (trials, accepted, fetches, halves, FP64 halves)
@@ -168,6 +171,11 @@ struct BwdParams {
 hipError_t launch_prep(const fq_field &f, int prec, int want_tw, void *nodes, float *bmax2,
                        hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// The queue ranges of the rotated-S0 jobs jobs_dev[first .. first + n): items from
+// `base` on, each job's item count its live lines rounded up to a wave, both halves;
+// the queue's end goes to *total.
+hipError_t launch_rot_ranges(TraceJob *jobs_dev, int first, int n, int64_t base, int64_t *total,
+                             hipStream_t s);
 // Stretched grids: the geometry pass (per-cell 1 / width of all three axes into
 // iw[a][0 .. n[a]-2], and *geo).
 struct GeoIn {

@@ -95,14 +95,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
 
     // queue size
     int64_t total = tp.static_items;
-    int64_t dyn_items = 0;
     if (tp.list) {
         total = (int64_t)(*tp.list_count);
         if (total > tp.list_cap) total = tp.list_cap;
     } else if (!UNI && tp.dynamic_last) {
-        const int64_t lines = live_lines(jobs[tp.njobs - 1]);
-        dyn_items = ((lines + 63) / 64) * 64;
-        total += 2 * dyn_items;
+        total = *tp.total_dev;  // with the rotated-S0 jobs, sized on the device
     }
 
     // lane state
@@ -174,13 +171,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                         forward = e.half != 0;
                     } else {
                         // the job whose range of items holds it (the ranges need not
-                        // follow the job table's order; a dynamic last job takes the rest)
+                        // follow the job table's order; rotated-S0 jobs' ranges were set
+                        // on the device)
                         if (!UNI)
                             while (j + 1 < tp.njobs &&
                                    !(it >= jobs[j].item_base && it < jobs[j].item_base + 2 * jobs[j].nitems))
                                 j++;
                         const TraceJob &J = jobs[j];
-                        const int64_t nit = (J.kind == SEED_ROTATED) ? dyn_items : J.nitems;
+                        const int64_t nit = J.nitems;
                         const int64_t local = it - J.item_base;
                         if (J.kind == SEED_PLANE || J.kind == SEED_VOXELS || J.kind == SEED_CYL) {
                             // the forward and backward halves of a tile follow each
@@ -863,6 +861,28 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
         if (uni) launch_ts<double, float, true, false>(twm, grid, blk, s, jobs_dev, tp, counter);
         else launch_ts<double, float, false, false>(twm, grid, blk, s, jobs_dev, tp, counter);
     }
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void rot_ranges_kernel(TraceJob *jobs, int first, int n, int64_t base, int64_t *total)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = first; k < first + n; k++) {
+        TraceJob &J = jobs[k];
+        const int64_t lines = live_lines(J);
+        J.item_base = base;
+        J.nitems = ((lines + 63) / 64) * 64;
+        base += 2 * J.nitems;
+    }
+    *total = base;
+}
+}  // namespace
+
+hipError_t launch_rot_ranges(TraceJob *jobs_dev, int first, int n, int64_t base, int64_t *total,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(rot_ranges_kernel, dim3(1), dim3(64), 0, s, jobs_dev, first, n, base, total);
     return hipGetLastError();
 }
 

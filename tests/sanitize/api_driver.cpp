@@ -111,8 +111,11 @@ int main()
             size_t need = fastqsl_q2d_workspace_size(f, &mid, 1, &P);
             CHECK(need > 0);
             CHECK(fastqsl_q2d(f, &mid, 1, &P, m, workspace(need), need, nullptr) == FQ_OK);
-            fq_plane two[2] = {mid, pl[1]};
-            CHECK(fastqsl_q2d_workspace_size(f, two, 2, &P) == 0);
+            // interior planes in a batch: two rotated-S0 jobs beside a face plane
+            fq_plane three[3] = {mid, pl[1], plane(11, 9, 0.21)};
+            need = fastqsl_q2d_workspace_size(f, three, 3, &P);
+            CHECK(need > 0);
+            CHECK(fastqsl_q2d(f, three, 3, &P, m, workspace(need), need, nullptr) == FQ_OK);
             // q3d (Method I with rotated S0, and Method II)
             fq_voxels vx;
             memset(&vx, 0, sizeof vx);

@@ -140,6 +140,13 @@ hipError_t launch_m2_map(const MapJob &m, hipStream_t)
     g_calls++;
     return hipSuccess;
 }
+hipError_t launch_rot_ranges(TraceJob *jobs, int first, int n, int64_t, int64_t *total, hipStream_t)
+{
+    in_ws(jobs + first, (size_t)n * sizeof(TraceJob), "rotated jobs");
+    in_ws(total, sizeof(int64_t), "queue total");
+    g_calls++;
+    return hipSuccess;
+}
 hipError_t launch_cyl_map(const MapJob &m, hipStream_t)
 {
     in_ws(m.rec.end, (size_t)(2 * m.nlines) * 24, "line records");

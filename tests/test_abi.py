@@ -153,15 +153,18 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert lib.fastqsl_strerror(_lib.FQ_ENOMEM) == b"workspace too small"
 
 
-def test_interior_planes_in_a_batch_are_unsupported(lib):
+def test_interior_planes_in_a_batch_take_their_rotated_s0_room(lib):
+    """A batch may mix interior and box-face planes; each interior plane adds its
+    rotated-S0 room (four extra lines per point) to the workspace."""
     from paper_2208_12569_amd import _lib
 
     p = _lib.fq_params()
     fs = (_lib.fq_field * 2)(_fake_field(), _fake_field())
-    ps = (_lib.fq_plane * 2)(_plane(z=0.5), _plane())
-    assert lib.fastqsl_q2d_workspace_size(fs, ps, 2, C.byref(p)) == 0
-    ps = (_lib.fq_plane * 2)(_plane(), _plane())
-    assert lib.fastqsl_q2d_workspace_size(fs, ps, 2, C.byref(p)) > 0
+    face = lib.fastqsl_q2d_workspace_size(fs, (_lib.fq_plane * 2)(_plane(), _plane()), 2, C.byref(p))
+    one = lib.fastqsl_q2d_workspace_size(fs, (_lib.fq_plane * 2)(_plane(z=0.5), _plane()), 2, C.byref(p))
+    two = lib.fastqsl_q2d_workspace_size(fs, (_lib.fq_plane * 2)(_plane(z=0.5), _plane(z=0.25)), 2,
+                                         C.byref(p))
+    assert 0 < face < one < two
 
 
 def test_python_layer_fails_loudly_without_gpu():

@@ -437,3 +437,33 @@ def test_c3_full_size_sampled_parity(fq, c3, prec):
     print(st, "rotated voxels:", rot.size)
     assert rot.size > 0
     assert not (st_all & fq.ST_FATAL).any()
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_batch_with_interior_planes_equals_single(fq, prec):
+    """Interior seed planes (rotated S0 where |Bn0/B| < 0.05, four extra lines each)
+    and a box-face plane in one persistent launch: the rotated-S0 jobs' queue ranges
+    are sized on the device, one after another, and every map is bit-identical to
+    the same job launched alone."""
+    import torch
+
+    w = synth.config_c1(0)
+    B = _dev(w.field)
+    planes = [Plane((0.11, 0.13, 0.37), (1, 0, 0), (0, 1, 0), 40, 36, 0.02, 0.02),
+              Plane((0.2, 0.31, 0.21), (1, 0, 0), (0, 0.6, 0.8), 30, 28, 0.02, 0.02),
+              Plane((0.05, 0.05, 0.0), (1, 0, 0), (0, 1, 0), 48, 40, 0.018, 0.02)]
+    _say(f"batch of two interior planes and a face plane, precision {prec}")
+    p = fq.Params(precision=prec)
+    rb = fq.q2d_batch([(B, w.grid, pl) for pl in planes], p, want_lines=False)
+    torch.cuda.synchronize()
+    nrot = 0
+    for pl, r in zip(planes, rb):
+        r1 = fq.q2d(B, w.grid, pl, p)
+        torch.cuda.synchronize()
+        a, b = to_np(r["q"]), to_np(r1["q"])
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        assert np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+        assert np.array_equal(to_np(r["tw"]), to_np(r1["tw"]), equal_nan=True)
+        assert np.array_equal(to_np(r["status"]), to_np(r1["status"]))
+        nrot += int(((to_np(r["status"]).astype(np.uint16) & fq.ST_ROTATED) != 0).sum())
+    assert nrot > 0
