@@ -149,7 +149,9 @@ typedef struct {
     int32_t scheme;    /* FQ_SCHEME_RKF45 (default), FQ_SCHEME_RK4 or FQ_SCHEME_RK4_38. Every
                           step stays in one grid cell and ends on the cell face it reaches, in
                           every scheme; a fixed-step scheme takes its step (Eq. step) between
-                          faces. The adjoint calls take RKF45 only (else FQ_EUNSUPPORTED) */
+                          faces. The adjoint calls take all three: their reverse pass holds
+                          the recorded step lengths fixed, so with a fixed-step scheme the
+                          only state-dependent lengths are those of face landings */
     int32_t method;    /* maps: FQ_METHOD_I (default) or FQ_METHOD_II. Method II traces one line
                           per map point (no stencil neighbours, no rotated S0), with Eq. step /
                           Eq. tol at |Bn0/B| = 1 (its S0 is perpendicular to B), RKF45 only, and
@@ -280,9 +282,10 @@ int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, co
  * fastqsl_q2d (Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of
  * Eq. tw) so that a field model can be fitted to target maps.
  *   f, pl, p   the same inputs as the forward call; p->precision must be
- *              FQ_PREC_F64 and the seed plane must lie on a box face (no rotated
- *              S0), else FQ_EUNSUPPORTED. Use the forward call's parameters: the
- *              lines are traced again with them.
+ *              FQ_PREC_F64, p->method FQ_METHOD_I (any p->scheme) and the seed
+ *              plane must lie on a box face (no rotated S0), else FQ_EUNSUPPORTED.
+ *              Use the forward call's parameters: the lines are traced again with
+ *              them.
  *   segment    accepted steps between checkpoints, 1..4096.
  *   dq, dtw    dL/dQ and dL/dTw, nu*nv device doubles each (map order), or NULL;
  *   dend_b, dend_f  dL/d(end points), nu*nv x 3 device doubles each, or NULL.

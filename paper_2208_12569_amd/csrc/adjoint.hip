@@ -7,7 +7,7 @@
 //   map_backward   dL/dQ, dL/dTw, dL/d(ends) -> dL/d(end of every half line),
 //                  dL/d(Tw of every half line), and dL/dB at the nodes through
 //                  the trilinear Bn0, Bn1, Bn2;
-//   trace_backward the discrete adjoint of every accepted RKF45 step of a half
+//   trace_backward the discrete adjoint of every accepted Runge-Kutta step of a half
 //                  line, last to first, with the step lengths held fixed: the
 //                  forward pass kept the lane state every `seg` accepted steps
 //                  (chained per half line in one checkpoint pool),
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
 }
 
 // ----------------------------------------------------------------------------------
-// Discrete adjoint of one accepted RKF45 step (FP64).
+// Discrete adjoint of one accepted Runge-Kutta step (FP64).
 
 // value and gradient (local coordinates) of P(u,v,w) in monomial form
 __device__ __forceinline__ void poly_grad(const double c[8], double u, double v, double w,
@@ -271,16 +271,31 @@ __device__ __forceinline__ double tri_w(int q, double u, double v, double w)
     return ((q & 1) ? u : 1.0 - u) * ((q & 2) ? v : 1.0 - v) * ((q & 4) ? w : 1.0 - w);
 }
 
-// Fehlberg 4(5), fifth-order weights (the tableau the forward step uses)
-__constant__ double kA[6][5] = {
-    {0.0, 0.0, 0.0, 0.0, 0.0},
-    {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
-    {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
-    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
-    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
-    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
-__constant__ double kB[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0,
-                             2.0 / 55.0};
+// The tableaux the forward step uses, by Scheme: Fehlberg 4(5) with its fifth-order
+// weights; classic RK4; Kutta's 3/8 rule (the two RK4 rules use stages 0-3).
+__constant__ double kA[3][6][5] = {
+    {{0.0, 0.0, 0.0, 0.0, 0.0},
+     {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+     {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+     {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+     {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+     {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}},
+    {{0.0, 0.0, 0.0, 0.0, 0.0},
+     {0.5, 0.0, 0.0, 0.0, 0.0},
+     {0.0, 0.5, 0.0, 0.0, 0.0},
+     {0.0, 0.0, 1.0, 0.0, 0.0},
+     {0.0, 0.0, 0.0, 0.0, 0.0},
+     {0.0, 0.0, 0.0, 0.0, 0.0}},
+    {{0.0, 0.0, 0.0, 0.0, 0.0},
+     {1.0 / 3.0, 0.0, 0.0, 0.0, 0.0},
+     {-1.0 / 3.0, 1.0, 0.0, 0.0, 0.0},
+     {1.0, -1.0, 1.0, 0.0, 0.0},
+     {0.0, 0.0, 0.0, 0.0, 0.0},
+     {0.0, 0.0, 0.0, 0.0, 0.0}}};
+__constant__ double kB[3][6] = {
+    {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0},
+    {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0, 0.0, 0.0},
+    {1.0 / 8.0, 3.0 / 8.0, 3.0 / 8.0, 1.0 / 8.0, 0.0, 0.0}};
 
 // The accepted step maps local position p to p' (a plain step of arc length H, or a
 // landing with the axis coordinate as the independent variable, H = face - p_axis)
@@ -289,20 +304,23 @@ __constant__ double kB[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 5643
 // values) of B and curl B to gB, gJ.
 // endb: for the last accepted step of a half line, the axis of the box face the line
 // ends on (-1 otherwise).
-template <bool TW>
+template <bool TW, int SCH>
 __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const StepRec &sr,
                              const LaneConst<double> &K, double sgn, int endb, double lam[3],
                              double ltw, double gB[3][8], double gJ[3][8])
 {
+    constexpr int NS = SCH == SCH_RKF45 ? 6 : 4;  // stages
+    const double(*A)[5] = kA[SCH];
+    const double *Bw = kB[SCH];
     const double R[3] = {K.rx, K.ry, K.rz};
     const double p[3] = {sr.p0, sr.p1, sr.p2};
     const double H = sr.H;
     const int ax = sr.axis;
     double y[6][3], k[6][3], G[6], g[6];
-    for (int st = 0; st < 6; st++) {
+    for (int st = 0; st < NS; st++) {
         for (int q = 0; q < 3; q++) {
             double acc = 0.0;
-            for (int jj = 0; jj < st; jj++) acc += kA[st][jj] * k[jj][q];
+            for (int jj = 0; jj < st; jj++) acc += A[st][jj] * k[jj][q];
             y[st][q] = p[q] + H * acc;
         }
         double B[3], J[3] = {0.0, 0.0, 0.0};
@@ -335,7 +353,7 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
         double pe[3];
         for (int q = 0; q < 3; q++) {
             double dy = 0.0;
-            for (int st = 0; st < 6; st++) dy += kB[st] * k[st][q];
+            for (int st = 0; st < NS; st++) dy += Bw[st] * k[st][q];
             pe[q] = p[q] + H * dy;
         }
         // direction F and twist integrand G at the end: moving the end by dt along the
@@ -356,13 +374,13 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
     }
     double mu[6][3];
     double dH = 0.0;
-    for (int st = 0; st < 6; st++) {
-        for (int q = 0; q < 3; q++) mu[st][q] = H * kB[st] * lo[q];
-        dH += kB[st] * (k[st][0] * lo[0] + k[st][1] * lo[1] + k[st][2] * lo[2]);
-        if (TW) dH += ltw * kB[st] * G[st] / g[st];
+    for (int st = 0; st < NS; st++) {
+        for (int q = 0; q < 3; q++) mu[st][q] = H * Bw[st] * lo[q];
+        dH += Bw[st] * (k[st][0] * lo[0] + k[st][1] * lo[1] + k[st][2] * lo[2]);
+        if (TW) dH += ltw * Bw[st] * G[st] / g[st];
     }
     double ln[3] = {lo[0], lo[1], lo[2]};
-    for (int st = 5; st >= 0; st--) {
+    for (int st = NS - 1; st >= 0; st--) {
         const double u = y[st][0], v = y[st][1], w = y[st][2];
         double B[3], J[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 3; c++) B[c] = poly<double>(cb[c], u, v, w);
@@ -370,7 +388,7 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
             for (int c = 0; c < 3; c++) J[c] = poly<double>(cj[c], u, v, w);
         const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
         const double inv = 1.0 / sqrt(b2);
-        const double tau = TW ? H * kB[st] * ltw : 0.0;
+        const double tau = TW ? H * Bw[st] * ltw : 0.0;
         double Fb[3], Gb;
         if (ax >= 0) {
             const double ig = 1.0 / g[st];
@@ -419,8 +437,8 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
         }
         for (int a = 0; a < 3; a++) ln[a] += yb[a];
         for (int jj = 0; jj < st; jj++) {
-            for (int a = 0; a < 3; a++) mu[jj][a] += H * kA[st][jj] * yb[a];
-            dH += kA[st][jj] * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
+            for (int a = 0; a < 3; a++) mu[jj][a] += H * A[st][jj] * yb[a];
+            dH += A[st][jj] * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
         }
     }
     if (ax >= 0 && !onbox) ln[ax] -= dH;  // H = face - p_axis
@@ -460,7 +478,7 @@ __device__ void flush_cell(double *gnode, int64_t nn, int nx, int ny, int c0, in
     }
 }
 
-template <typename S, bool TW>
+template <typename S, bool TW, int SCH>
 __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__restrict__ jobs,
                                                             BwdParams bp)
 {
@@ -553,8 +571,8 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     int fin_st = -1, fin_face = -1;
                     bool need_load = false;
                     const unsigned before = acc;
-                    lane_iterate<double, TW, Capture>(L, cb, cj, K, fin_st, fin_face, need_load, acc,
-                                                       capture);
+                    lane_iterate<double, TW, Capture, SCH>(L, cb, cj, K, fin_st, fin_face, need_load,
+                                                            acc, capture);
                     if (acc != before) {
                         if (nrec >= target) {
                             bad = true;
@@ -590,7 +608,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                         load_cell<double, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
                     }
                     const int endb = (last && r == nrec - 1) ? endax : -1;
-                    step_adjoint<TW>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
+                    step_adjoint<TW, SCH>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
                     n_steps++;
                 }
                 if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
@@ -707,17 +725,28 @@ hipError_t launch_bwd_order(const int32_t *tape_acc, int64_t nhalves, int32_t *k
     return launch_bucket_order(nhalves, key, counts, order, s);
 }
 
-hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,
-                                 const BwdParams &bp, hipStream_t s)
+namespace {
+template <int SCH>
+void launch_bwd_s(int store, int want_tw, const TraceJob *job_dev, const BwdParams &bp, hipStream_t s)
 {
     const dim3 grid((unsigned)((bp.nslots + 63) / 64)), blk(64);
     if (store == FQ_DT_F64) {
-        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<double, true>), grid, blk, 0, s, job_dev, bp);
-        else hipLaunchKernelGGL((trace_backward_kernel<double, false>), grid, blk, 0, s, job_dev, bp);
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<double, true, SCH>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<double, false, SCH>), grid, blk, 0, s, job_dev, bp);
     } else {
-        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<float, true>), grid, blk, 0, s, job_dev, bp);
-        else hipLaunchKernelGGL((trace_backward_kernel<float, false>), grid, blk, 0, s, job_dev, bp);
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<float, true, SCH>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<float, false, SCH>), grid, blk, 0, s, job_dev, bp);
     }
+}
+}  // namespace
+
+hipError_t launch_trace_backward(int store, int want_tw, const TraceJob *job_dev,
+                                 const BwdParams &bp, hipStream_t s)
+{
+    if (bp.scheme == SCH_RKF45) launch_bwd_s<SCH_RKF45>(store, want_tw, job_dev, bp, s);
+    else if (bp.scheme == SCH_RK4) launch_bwd_s<SCH_RK4>(store, want_tw, job_dev, bp, s);
+    else if (bp.scheme == SCH_RK4_38) launch_bwd_s<SCH_RK4_38>(store, want_tw, job_dev, bp, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

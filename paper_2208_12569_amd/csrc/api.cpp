@@ -692,6 +692,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         bp.stats = (unsigned long long *)P.stats;
         bp.max_steps = P.max_steps;
         bp.want_tw = P.want_tw;
+        bp.scheme = P.scheme;
         FQ_TRY(launch_trace_backward(FQ_DT_F64, P.want_tw, jobs_dev, bp, stream));
         FQ_TRY(launch_grad_planes(*specs[0].f, gnode, P.want_tw, bwd->gb, stream));
         return FQ_OK;
@@ -754,8 +755,7 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
 {
     int rc = resolve_params(p, P);
     if (rc) return rc;
-    if (P.precision != FQ_PREC_F64 || P.scheme != FQ_SCHEME_RKF45 || P.method != FQ_METHOD_I)
-        return FQ_EUNSUPPORTED;
+    if (P.precision != FQ_PREC_F64 || P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
     if (f && stretched(f)) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;

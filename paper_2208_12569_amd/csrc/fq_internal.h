@@ -164,7 +164,7 @@ struct BwdParams {
     unsigned long long *stats;     // optional: halves, steps, replay mismatches, dropped halves
     int64_t max_steps;
     int32_t want_tw;
-    int32_t pad;
+    int32_t scheme;                // Scheme of the forward pass (trace_core.h)
 };
 
 // Host-side launchers, one per translation unit.

@@ -79,8 +79,8 @@ template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 
 // (the latency of cell fetches is then hidden by more waves), and the FP32 Method II
 // kernels to two waves per SIMD (a few bytes of spills; at one wave their lone
 // waves took 40% longer than the two-wave form).
-// SCH: the integration scheme (Scheme in trace_core.h); the adjoint's forward pass
-// (TAPE) uses RKF45 only. M2: Method II, the tangent vectors U, V ride along (their
+// SCH: the integration scheme (Scheme in trace_core.h), the adjoint's forward pass
+// (TAPE) included. M2: Method II, the tangent vectors U, V ride along (their
 // end values go to the records' uv array).
 template <typename T, typename S, int TWM, bool UNI, bool TAPE, int SCH = SCH_RKF45, bool M2 = false>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3 : ((sizeof(T) == 4 && M2) ? 2 : 1)) void trace_kernel(const TraceJob *__restrict__ jobs,
@@ -609,9 +609,9 @@ void launch_ts(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs
                const TraceParams &tp, unsigned long long *counter)
 {
     if (!TAPE && tp.method == FQ_METHOD_II) launch_m2<T, S, UNI>(twm, grid, blk, s, jobs, tp, counter);
-    else if (TAPE || tp.scheme == SCH_RKF45) launch_tss<T, S, UNI, TAPE, SCH_RKF45>(twm, grid, blk, s, jobs, tp, counter);
-    else if (tp.scheme == SCH_RK4) launch_tss<T, S, UNI, false, SCH_RK4>(twm, grid, blk, s, jobs, tp, counter);
-    else launch_tss<T, S, UNI, false, SCH_RK4_38>(twm, grid, blk, s, jobs, tp, counter);
+    else if (tp.scheme == SCH_RKF45) launch_tss<T, S, UNI, TAPE, SCH_RKF45>(twm, grid, blk, s, jobs, tp, counter);
+    else if (tp.scheme == SCH_RK4) launch_tss<T, S, UNI, TAPE, SCH_RK4>(twm, grid, blk, s, jobs, tp, counter);
+    else launch_tss<T, S, UNI, TAPE, SCH_RK4_38>(twm, grid, blk, s, jobs, tp, counter);
 }
 
 __global__ void fill_counts_kernel(uint32_t *counts)
@@ -829,8 +829,8 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched && !tp.cyl;
     if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
-        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, RKF45
-        if (!f64 || !uni || tp.list || tp.seg < 1 || tp.scheme != SCH_RKF45) return hipErrorInvalidValue;
+        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, Method I
+        if (!f64 || !uni || tp.list || tp.seg < 1 || tp.method != FQ_METHOD_I) return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
         if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
         else launch_ts<double, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);

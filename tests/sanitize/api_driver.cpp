@@ -194,7 +194,7 @@ int main()
             need = fastqsl_q2d_workspace_size(f, pl, 1, &P);
             CHECK(fastqsl_q2d(f, pl, 1, &P, m, workspace(need), need, nullptr) == FQ_OK);
             P.events = nullptr;
-            // the adjoint: FP64 only, plane on a box face
+            // the adjoint: FP64 only, Method I, plane on a box face
             double *gb[3] = {g_dummy, g_dummy, g_dummy};
             need = fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 32);
             if (prec == FQ_PREC_F64) {
@@ -216,6 +216,16 @@ int main()
                 P.tape_steps = -1;
                 CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 32) == 0);
                 P.tape_steps = 0;
+                // the fixed-step schemes have an adjoint; Method II has none
+                fq_params P6 = P;
+                P6.scheme = FQ_SCHEME_RK4_38;
+                const size_t n6 = fastqsl_backward_workspace_size(&f[0], &pl[0], &P6, 32);
+                CHECK(n6 > 0);
+                CHECK(fastqsl_backward(&f[0], &pl[0], &P6, 32, g_dummy, g_dummy, nullptr, nullptr, gb,
+                                       workspace(n6), n6, nullptr) == FQ_OK);
+                P6 = P;
+                P6.method = FQ_METHOD_II;
+                CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P6, 32) == 0);
             } else {
                 CHECK(need == 0);
             }

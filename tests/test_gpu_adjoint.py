@@ -2,8 +2,9 @@
 
 Pins: closed-form derivatives of the sheared and hyperbolic linear fields
 (dQ/ds = 2 s L^2, dTw/ds, dx2/ds = (y1 - y0) L; dQ/dk = 4 L sinh 2kL), central
-finite differences of the GPU forward on charge fields, and finite differences of
-the FP64 oracle as an independent reference gradient. Every case prints what it
+finite differences of the GPU forward on charge fields (RKF45 and the two fixed-step
+RK4 schemes), and finite differences of the FP64 oracle as an independent reference
+gradient. Every case prints what it
 runs before touching the GPU.
 """
 
@@ -46,10 +47,10 @@ def _dev(B):
     return torch.from_numpy(np.ascontiguousarray(B)).cuda()
 
 
-def _grad(fq, B, g, pl, stats=None, segment=32, **kw):
+def _grad(fq, B, g, pl, stats=None, segment=32, pkw=None, **kw):
     import torch
 
-    p = fq.Params(precision=F64, tol_perp=TOL, stats=stats)
+    p = fq.Params(precision=F64, tol_perp=TOL, stats=stats, **(pkw or {}))
     gb = fq.backward(B, g, pl, p, segment, **kw)
     torch.cuda.synchronize()
     return gb.cpu().numpy()
@@ -157,14 +158,16 @@ def _fd_mask(fq, r):
     return dil == 0
 
 
-def _loss_fn(fq, g, pl, mask, wq, wt, we):
+def _loss_fn(fq, g, pl, mask, wq, wt, we, params=None):
     """A smooth loss of the map: weighted log10 Q, Tw and both end points on the mask."""
     import torch
 
     from paper_2208_12569_amd.autograd import qtw_map
 
+    params = params or fq.Params(precision=F64, tol_perp=TOL)
+
     def loss(B):
-        q, tw, eb, ef, st = qtw_map(B, g, pl, fq.Params(precision=F64, tol_perp=TOL), 8)
+        q, tw, eb, ef, st = qtw_map(B, g, pl, params, 8)
         m = mask
         lq = torch.log10(torch.where(m, q, torch.ones_like(q)))
         val = (wq * lq * m).sum() + (wt * torch.where(m, tw, torch.zeros_like(tw))).sum()
@@ -217,6 +220,82 @@ def test_charge_field_gradient_matches_finite_differences(fq):
     err = np.abs(grad - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
     print("grad", grad, "fd", fd, "rel err", err)
     assert err.max() < 1e-4, (err.max(), int(np.argmax(err)))
+
+
+@pytest.mark.parametrize("scheme", [1, 2], ids=["rk4", "rk4_38"])
+def test_fixed_step_scheme_adjoint(fq, scheme):
+    """The adjoint of the fixed-step RK4 schemes (Section 2.3). The sheared field's
+    lines are straight, so every scheme traces them exactly: dQ/ds = 2 s L^2 and
+    dTw/ds in closed form. On a charge field the adjoint, like RKF45's, holds every
+    recorded step length fixed except a face landing's; a fixed-step scheme's map
+    also depends on the lengths of its approach steps (shortened, from the state,
+    after a landing that could not be taken yet) at the level of its truncation
+    error, which RKF45 at tol 1e-10 keeps far smaller. At a step of 0.02 grid
+    spacings the gradient matches central differences of the GPU forward to 1e-3
+    at worst and 2e-5 in the median (RKF45: 3e-6 and 2e-8)."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    h = 0.02
+    pkw = dict(scheme=scheme, step_perp=h, step_min=h)
+    g = cubic_grid(17, 17, 17)
+    s, y0, L = 0.5, 0.5, 1.0
+    B = _dev(linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1]))
+    pl = Plane((0.41, 0.25, 0.0), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.02)
+    yy = np.asarray(g.axes()[1])[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[0] = np.broadcast_to(yy - y0, g.shape)
+    interior = np.zeros((9, 9))
+    interior[1:-1, 1:-1] = 1.0
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say(f"scheme {scheme}: shear dQ/ds and dTw/ds")
+    gq = _grad(fq, B, g, pl, stats, pkw=pkw, dq=torch.tensor(interior.ravel(), device="cuda"))
+    st = stats.tolist()
+    assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0, st
+    got, want = float((gq * dBds).sum()), interior.sum() * 2 * s * L * L
+    assert abs(got / want - 1) < 1e-7, (got, want)
+    eta = pl.points()[:, 1] - y0
+    gt = _grad(fq, B, g, pl, pkw=pkw, dtw=torch.ones(81, dtype=torch.float64, device="cuda"))
+    # (the node gradient of Tw goes through the curl's differences, whose transposes
+    # put large cancelling weights on neighbouring nodes: rounding, not the scheme,
+    # sets the last digits here, as for RKF45)
+    got, want = float((gt * dBds).sum()), float(np.sum(-L / (4 * np.pi) * (1 + s * s * eta * eta) ** -1.5))
+    assert abs(got / want - 1) < 1e-6, (got, want)
+
+    g = cubic_grid(48, 48, 32)
+    pl = synth.plane_z0(32)
+    pos0, q0 = _charges(7, 6)
+    theta0 = torch.cat([pos0.ravel(), q0]).detach()
+
+    def field(theta):
+        return charges_field_torch(g, theta[:18].view(6, 3), theta[18:], torch.float64, "cuda")
+
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    wq = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    wt = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    we = torch.randn((32, 32, 3), generator=gen, device="cuda", dtype=torch.float64)
+    params = fq.Params(precision=F64, **pkw)
+    _say(f"scheme {scheme}: charge field base map")
+    r = fq.q2d(field(theta0), g, pl, params)
+    mask = _fd_mask(fq, r)
+    assert mask.float().mean() > 0.3
+    loss = _loss_fn(fq, g, pl, mask, wq, wt, we, params)
+    theta = theta0.clone().requires_grad_(True)
+    _say(f"scheme {scheme}: charge field adjoint")
+    loss(field(theta)).backward()
+    grad = theta.grad.detach().cpu().numpy()
+    fd = np.zeros_like(grad)
+    for i in range(theta0.numel()):
+        dh = 1e-6 * max(1.0, abs(float(theta0[i])))
+        tp, tm = theta0.clone(), theta0.clone()
+        tp[i] += dh
+        tm[i] -= dh
+        with torch.no_grad():
+            fd[i] = (float(loss(field(tp))) - float(loss(field(tm)))) / (2 * dh)
+    err = np.abs(grad - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    print("scheme", scheme, "max rel err", err.max(), "median", np.median(err))
+    assert err.max() < 1e-3 and np.median(err) < 2e-5, (err.max(), int(np.argmax(err)))
 
 
 def test_segment_length_does_not_change_the_gradient(fq):
