@@ -355,12 +355,13 @@ def run_batch(seed: int, steps: int, warmup: int):
             "params": {"block": params.block, "waves_per_cu": params.waves_per_cu}}
 
 
-def run_adjoint(seed: int, steps: int, warmup: int):
+def run_adjoint(seed: int, steps: int, warmup: int, prec_name: str = "f64"):
     """The adjoint workload: the 256x256 map of a 128x128x96 FP32 cube from 8 point
     charges, and the gradient of a log10 Q + footpoint loss against a target map
-    with respect to the node values (all-FP64 form, checkpoints every 32 accepted
-    steps): per step, the map traced once with its checkpoints kept
-    (fastqsl_q2d_record), the loss, and the reverse pass (fastqsl_backward_recorded)."""
+    with respect to the node values (all-FP64 form, or the F32X form whose FP32 pass
+    is replayed and reversed in FP32; checkpoints every 32 accepted steps): per step,
+    the map traced once with its checkpoints kept (fastqsl_q2d_record), the loss,
+    and the reverse pass (fastqsl_backward_recorded)."""
     import torch
 
     import paper_2208_12569_amd as fq
@@ -372,8 +373,9 @@ def run_adjoint(seed: int, steps: int, warmup: int):
     pos, q = w.meta["charges"]
     B = charges_field_torch(g, pos, q, torch.float32, "cuda")
     tB = charges_field_torch(g, *target["charges"], torch.float32, "cuda")
-    p = fq.Params(precision=fq.FQ_PREC_F64)
-    tq = fq.q2d(tB, g, pl, p)["q"]
+    prec = fq.FQ_PREC_F64 if prec_name == "f64" else fq.FQ_PREC_F32X
+    p = fq.Params(precision=prec)
+    tq = fq.q2d(tB, g, pl, fq.Params(precision=fq.FQ_PREC_F64))["q"]
     stats = torch.zeros(5, dtype=torch.int64, device="cuda")
     gb = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
     ws = [None]  # the record's workspace, reused from step to step
@@ -387,7 +389,7 @@ def run_adjoint(seed: int, steps: int, warmup: int):
         lt = torch.log10(torch.where(m, tq, torch.ones_like(tq)))
         dq = torch.where(m, 2.0 * (lq - lt) / (qq * math.log(10.0)), torch.zeros_like(qq)) / m.sum()
         gb.zero_()
-        fq.backward_recorded(B, g, pl, r, fq.Params(precision=fq.FQ_PREC_F64, stats=st), 32,
+        fq.backward_recorded(B, g, pl, r, fq.Params(precision=prec, stats=st), 32,
                              dq=dq.reshape(-1), gb=gb)
 
     for _ in range(max(1, warmup)):
@@ -403,11 +405,12 @@ def run_adjoint(seed: int, steps: int, warmup: int):
     ms = a.elapsed_time(b) / steps
     st = [int(x) // steps for x in stats.tolist()]
     npts = pl.nu * pl.nv
-    log(f"[adjoint] {ms:.3f} ms per map + gradient; half lines differentiated {st[0]}, "
+    log(f"[adjoint {prec_name}] {ms:.3f} ms per map + gradient; half lines differentiated {st[0]}, "
         f"accepted steps reversed {st[1]}, replay mismatches {st[2]}")
+    form = "FP64" if prec_name == "f64" else "F32X: FP32 pass, replay and reverse sweep"
     return {"workload": "128x128x96 FP32 cube, 8 point charges, 256x256 seeds on z=0; forward "
                         "map traced once with checkpoints + dL/dB of a log10 Q loss vs a target "
-                        "map (FP64, checkpoint every 32 accepted steps)",
+                        f"map ({form}, checkpoint every 32 accepted steps)",
             "value": npts / (ms * 1e-3), "unit": "map points with gradient/s", "ms_per_step": ms,
             "half_lines": st[0], "steps_reversed": st[1], "replay_mismatches": st[2]}
 
@@ -777,6 +780,7 @@ def main():
                "neighbour lines)", args, uv, method=1)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
+        out["adjoint_f32x"] = run_adjoint(args.seed, args.steps, args.warmup, "f32x")
     q3d_sample = None
     if not args.no_q3d:
         out["q3d"] = run_q3d(args.seed, args.steps, args.warmup)

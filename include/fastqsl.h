@@ -281,11 +281,15 @@ int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, co
  * field's node values. Not an operation of the paper: it differentiates the map of
  * fastqsl_q2d (Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of
  * Eq. tw) so that a field model can be fitted to target maps.
- *   f, pl, p   the same inputs as the forward call; p->precision must be
- *              FQ_PREC_F64, p->method FQ_METHOD_I (any p->scheme) and the seed
- *              plane must lie on a box face (no rotated S0), else FQ_EUNSUPPORTED.
- *              Use the forward call's parameters: the lines are traced again with
- *              them.
+ *   f, pl, p   the same inputs as the forward call; p->method must be
+ *              FQ_METHOD_I (any p->scheme) on a uniform grid and the seed plane must
+ *              lie on a box face (no rotated S0), else FQ_EUNSUPPORTED. Use the
+ *              forward call's parameters: the lines are traced again with them.
+ *              p->precision picks the form differentiated: FQ_PREC_F64, or
+ *              FQ_PREC_F32X, whose FP32 pass is kept, replayed and reversed in FP32
+ *              (the map is the F32X map; half lines that its FP64 pass re-traced take
+ *              their derivative from their FP32 trace, and a half line the FP32 pass
+ *              could not finish has none and counts as a replay mismatch).
  *   segment    accepted steps between checkpoints, 1..4096.
  *   dq, dtw    dL/dQ and dL/dTw, nu*nv device doubles each (map order), or NULL;
  *   dend_b, dend_f  dL/d(end points), nu*nv x 3 device doubles each, or NULL.

@@ -406,15 +406,13 @@ def qcyl(B, grid, cyl, params: Optional[Params] = None, want_lines: bool = False
 def _bwd_prepare(B, grid, plane, params: Optional[Params], segment: int):
     lib = _lib.load()
     params = params or Params(precision=FQ_PREC_F64)
-    if params.precision != FQ_PREC_F64:
-        raise ValueError("the derivative is taken in the all-FP64 form (precision=FQ_PREC_F64)")
     f = _field(B, grid)
     pl = _plane(plane)
     p = params.c()
     need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
     if need == 0:
-        raise ValueError("invalid or unsupported backward call (FP64 form, plane on a box face, "
-                         "1 <= segment <= 4096)")
+        raise ValueError("invalid or unsupported backward call (Method I on a uniform grid, plane "
+                         "on a box face, 1 <= segment <= 4096)")
     return lib, f, pl, p, need
 
 
@@ -456,7 +454,9 @@ def _bwd_reverse(name, B, grid, plane, params, segment, dq, dtw, dend_b, dend_f,
 def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32, dq=None, dtw=None,
              dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
     """Reverse-mode derivative of the q2d map of (B, grid, plane) with respect to the
-    field's node values (fastqsl_backward; all-FP64 form, seed plane on a box face).
+    field's node values (fastqsl_backward; seed plane on a box face). params.precision
+    picks the form differentiated: all-FP64 (the default here), or F32X, whose FP32
+    pass is replayed and reversed in FP32.
 
     dq, dtw: CUDA float64 tensors of nu*nv values (dL/dQ, dL/dTw), dend_b, dend_f:
     nu*nv x 3 (dL/d end points); any may be None. The result is ADDED into gb, a
@@ -468,8 +468,9 @@ def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32,
 
 def q2d_record(B, grid, plane, params: Optional[Params] = None, segment: int = 32,
                want_lines: bool = False, stream=None, ws=None) -> dict:
-    """The all-FP64 q2d map of (B, grid, plane), traced once with the checkpoints of
-    its derivative kept (fastqsl_q2d_record). The returned dict holds the map and,
+    """The q2d map of (B, grid, plane) (all-FP64 unless params ask for F32X), traced
+    once with the checkpoints of its derivative kept (fastqsl_q2d_record). The
+    returned dict holds the map and,
     under "_ws", the workspace to hand to backward_recorded (which must not be
     written by anything else in between)."""
     lib, f, pl, p, need = _bwd_prepare(B, grid, plane, params, segment)

@@ -1,8 +1,9 @@
 """Q/Tw maps as a differentiable torch operation.
 
 QTwMap.apply(B, grid, plane, params, segment) returns the q2d map (Q, Tw, backward
-and forward end points, status) of the all-FP64 form, traced once with the
-checkpoints of its derivative kept (fastqsl_q2d_record); its backward runs the
+and forward end points, status) of the all-FP64 form (or of the F32X form, if params
+ask for it), traced once with the checkpoints of its derivative kept
+(fastqsl_q2d_record); its backward runs the
 hand-written adjoint of the tracer and the Q stencil on them
 (fastqsl_backward_recorded) and returns dL/dB. Composed with a field model written in torch (for instance point
 charges -> node values), autograd then yields the gradient with respect to the
@@ -20,8 +21,6 @@ class QTwMap(torch.autograd.Function):
     @staticmethod
     def forward(ctx, B, grid, plane, params=None, segment: int = 32):
         params = params or Params(precision=FQ_PREC_F64)
-        if params.precision != FQ_PREC_F64:
-            raise ValueError("QTwMap differentiates the all-FP64 form")
         r = q2d_record(B.detach(), grid, plane, params, segment, want_lines=True)
         shape = (plane.nv, plane.nu)
         eb = r["lines"]["end_b"].view(*shape, 3)

@@ -258,17 +258,17 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
 // Discrete adjoint of one accepted Runge-Kutta step (FP64).
 
 // value and gradient (local coordinates) of P(u,v,w) in monomial form
-__device__ __forceinline__ void poly_grad(const double c[8], double u, double v, double w,
-                                          double g[3])
+template <typename T>
+__device__ __forceinline__ void poly_grad(const T c[8], T u, T v, T w, T g[3])
 {
     g[0] = c[1] + c[4] * v + c[5] * w + c[7] * v * w;
     g[1] = c[2] + c[4] * u + c[6] * w + c[7] * u * w;
     g[2] = c[3] + c[5] * u + c[6] * v + c[7] * u * v;
 }
 
-__device__ __forceinline__ double tri_w(int q, double u, double v, double w)
+template <typename T> __device__ __forceinline__ T tri_w(int q, T u, T v, T w)
 {
-    return ((q & 1) ? u : 1.0 - u) * ((q & 2) ? v : 1.0 - v) * ((q & 4) ? w : 1.0 - w);
+    return ((q & 1) ? u : T(1) - u) * ((q & 2) ? v : T(1) - v) * ((q & 4) ? w : T(1) - w);
 }
 
 // The tableaux the forward step uses, by Scheme: Fehlberg 4(5) with its fifth-order
@@ -304,34 +304,38 @@ __constant__ double kB[3][6] = {
 // values) of B and curl B to gB, gJ.
 // endb: for the last accepted step of a half line, the axis of the box face the line
 // ends on (-1 otherwise).
-template <bool TW, int SCH>
-__device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const StepRec &sr,
-                             const LaneConst<double> &K, double sgn, int endb, double lam[3],
-                             double ltw, double gB[3][8], double gJ[3][8])
+// T: the arithmetic of the sweep, FP64, or FP32 in the F32X form (whose forward
+// steps were FP32); the callers accumulate gB, gJ per cell and add them to FP64
+// node gradients.
+template <typename T, bool TW, int SCH>
+__device__ void step_adjoint(const T cb[3][8], const T cj[3][8], const StepRec &sr,
+                             const LaneConst<T> &K, T sgn, int endb, T lam[3], T ltw, T gB[3][8],
+                             T gJ[3][8])
 {
     constexpr int NS = SCH == SCH_RKF45 ? 6 : 4;  // stages
-    const double(*A)[5] = kA[SCH];
-    const double *Bw = kB[SCH];
-    const double R[3] = {K.rx, K.ry, K.rz};
-    const double p[3] = {sr.p0, sr.p1, sr.p2};
-    const double H = sr.H;
+    // the tableau, read where it is used (the loops are over uniform indices)
+    auto A = [](int st, int jj) { return (T)kA[SCH][st][jj]; };
+    auto Bw = [](int st) { return (T)kB[SCH][st]; };
+    const T R[3] = {K.rx, K.ry, K.rz};
+    const T p[3] = {(T)sr.p0, (T)sr.p1, (T)sr.p2};
+    const T H = (T)sr.H;
     const int ax = sr.axis;
-    double y[6][3], k[6][3], G[6], g[6];
+    T y[6][3], k[6][3], G[6], g[6];
     for (int st = 0; st < NS; st++) {
         for (int q = 0; q < 3; q++) {
-            double acc = 0.0;
-            for (int jj = 0; jj < st; jj++) acc += A[st][jj] * k[jj][q];
+            T acc = T(0);
+            for (int jj = 0; jj < st; jj++) acc += A(st, jj) * k[jj][q];
             y[st][q] = p[q] + H * acc;
         }
-        double B[3], J[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < 3; c++) B[c] = poly<double>(cb[c], y[st][0], y[st][1], y[st][2]);
+        T B[3], J[3] = {T(0), T(0), T(0)};
+        for (int c = 0; c < 3; c++) B[c] = poly<T>(cb[c], y[st][0], y[st][1], y[st][2]);
         if (TW)
-            for (int c = 0; c < 3; c++) J[c] = poly<double>(cj[c], y[st][0], y[st][1], y[st][2]);
-        const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-        const double inv = 1.0 / sqrt(b2);
-        double F[3];
+            for (int c = 0; c < 3; c++) J[c] = poly<T>(cj[c], y[st][0], y[st][1], y[st][2]);
+        const T b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        const T inv = T(1) / sqrt(b2);
+        T F[3];
         for (int c = 0; c < 3; c++) F[c] = sgn * inv * B[c] * R[c];
-        G[st] = TW ? K.twk * (J[0] * B[0] + J[1] * B[1] + J[2] * B[2]) * inv * inv : 0.0;
+        G[st] = TW ? K.twk * (J[0] * B[0] + J[1] * B[1] + J[2] * B[2]) * inv * inv : T(0);
         g[st] = ax >= 0 ? F[ax] : 1.0;
         for (int c = 0; c < 3; c++) k[st][c] = F[c] / g[st];
     }
@@ -342,57 +346,57 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
     // the end constraint: the landing (if any) is incidental, the step length is held
     // fixed, and the end moves along the line's direction onto the face,
     // p_end = p* - k (p*_b - face_b) / k_b, whose adjoint is taken here.
-    double lo[3];
+    T lo[3];
     int b = -1;
     if (endb >= 0 && endb != ax) b = endb;
     else if (endb < 0 && sr.clamp) b = (sr.clamp & 1) ? 0 : ((sr.clamp & 2) ? 1 : 2);
     const bool onbox = b >= 0;
     if (!onbox) {
-        for (int q = 0; q < 3; q++) lo[q] = q == ax ? 0.0 : lam[q];
+        for (int q = 0; q < 3; q++) lo[q] = q == ax ? T(0) : lam[q];
     } else {
-        double pe[3];
+        T pe[3];
         for (int q = 0; q < 3; q++) {
-            double dy = 0.0;
-            for (int st = 0; st < NS; st++) dy += Bw[st] * k[st][q];
+            T dy = T(0);
+            for (int st = 0; st < NS; st++) dy += Bw(st) * k[st][q];
             pe[q] = p[q] + H * dy;
         }
         // direction F and twist integrand G at the end: moving the end by dt along the
         // line moves p by F dt and Tw by G dt, with dt = -(p*_b - face_b) / F_b
-        double Be[3], Je[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < 3; c++) Be[c] = poly<double>(cb[c], pe[0], pe[1], pe[2]);
+        T Be[3], Je[3] = {T(0), T(0), T(0)};
+        for (int c = 0; c < 3; c++) Be[c] = poly<T>(cb[c], pe[0], pe[1], pe[2]);
         if (TW)
-            for (int c = 0; c < 3; c++) Je[c] = poly<double>(cj[c], pe[0], pe[1], pe[2]);
-        const double be2 = Be[0] * Be[0] + Be[1] * Be[1] + Be[2] * Be[2];
-        const double inve = 1.0 / sqrt(be2);
-        double Fe[3];
+            for (int c = 0; c < 3; c++) Je[c] = poly<T>(cj[c], pe[0], pe[1], pe[2]);
+        const T be2 = Be[0] * Be[0] + Be[1] * Be[1] + Be[2] * Be[2];
+        const T inve = T(1) / sqrt(be2);
+        T Fe[3];
         for (int c = 0; c < 3; c++) Fe[c] = sgn * inve * Be[c] * R[c];
-        double s_ = 0.0;
+        T s_ = T(0);
         for (int q = 0; q < 3; q++)
             if (q != b) s_ += lam[q] * Fe[q];
         if (TW) s_ += ltw * K.twk * (Je[0] * Be[0] + Je[1] * Be[1] + Je[2] * Be[2]) * inve * inve;
         for (int q = 0; q < 3; q++) lo[q] = q == b ? -s_ / Fe[b] : lam[q];
     }
-    double mu[6][3];
-    double dH = 0.0;
+    T mu[6][3];
+    T dH = T(0);
     for (int st = 0; st < NS; st++) {
-        for (int q = 0; q < 3; q++) mu[st][q] = H * Bw[st] * lo[q];
-        dH += Bw[st] * (k[st][0] * lo[0] + k[st][1] * lo[1] + k[st][2] * lo[2]);
-        if (TW) dH += ltw * Bw[st] * G[st] / g[st];
+        for (int q = 0; q < 3; q++) mu[st][q] = H * Bw(st) * lo[q];
+        dH += Bw(st) * (k[st][0] * lo[0] + k[st][1] * lo[1] + k[st][2] * lo[2]);
+        if (TW) dH += ltw * Bw(st) * G[st] / g[st];
     }
-    double ln[3] = {lo[0], lo[1], lo[2]};
+    T ln[3] = {lo[0], lo[1], lo[2]};
     for (int st = NS - 1; st >= 0; st--) {
-        const double u = y[st][0], v = y[st][1], w = y[st][2];
-        double B[3], J[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < 3; c++) B[c] = poly<double>(cb[c], u, v, w);
+        const T u = y[st][0], v = y[st][1], w = y[st][2];
+        T B[3], J[3] = {T(0), T(0), T(0)};
+        for (int c = 0; c < 3; c++) B[c] = poly<T>(cb[c], u, v, w);
         if (TW)
-            for (int c = 0; c < 3; c++) J[c] = poly<double>(cj[c], u, v, w);
-        const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-        const double inv = 1.0 / sqrt(b2);
-        const double tau = TW ? H * Bw[st] * ltw : 0.0;
-        double Fb[3], Gb;
+            for (int c = 0; c < 3; c++) J[c] = poly<T>(cj[c], u, v, w);
+        const T b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        const T inv = T(1) / sqrt(b2);
+        const T tau = TW ? H * Bw(st) * ltw : T(0);
+        T Fb[3], Gb;
         if (ax >= 0) {
-            const double ig = 1.0 / g[st];
-            const double mk = mu[st][0] * k[st][0] + mu[st][1] * k[st][1] + mu[st][2] * k[st][2];
+            const T ig = 1.0 / g[st];
+            const T mk = mu[st][0] * k[st][0] + mu[st][1] * k[st][1] + mu[st][2] * k[st][2];
             for (int c = 0; c < 3; c++) Fb[c] = mu[st][c] * ig;
             Gb = tau * ig;
             Fb[ax] += -mk * ig - tau * G[st] * ig * ig;
@@ -401,26 +405,26 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
             Gb = tau;
         }
         // F = sgn R (B / |B|)
-        double d[3], db[3];
+        T d[3], db[3];
         for (int c = 0; c < 3; c++) {
             d[c] = B[c] * inv;
             db[c] = sgn * R[c] * Fb[c];
         }
-        const double dd = db[0] * d[0] + db[1] * d[1] + db[2] * d[2];
-        double Bb[3], Jb[3] = {0.0, 0.0, 0.0};
+        const T dd = db[0] * d[0] + db[1] * d[1] + db[2] * d[2];
+        T Bb[3], Jb[3] = {T(0), T(0), T(0)};
         for (int c = 0; c < 3; c++) Bb[c] = (db[c] - dd * d[c]) * inv;
-        if (TW && Gb != 0.0) {
+        if (TW && Gb != T(0)) {
             // G = twk (J.B) / |B|^2
-            const double i2 = inv * inv;
-            const double jb = J[0] * B[0] + J[1] * B[1] + J[2] * B[2];
+            const T i2 = inv * inv;
+            const T jb = J[0] * B[0] + J[1] * B[1] + J[2] * B[2];
             for (int c = 0; c < 3; c++) {
                 Jb[c] = K.twk * Gb * B[c] * i2;
-                Bb[c] += K.twk * Gb * (J[c] * i2 - 2.0 * jb * i2 * i2 * B[c]);
+                Bb[c] += K.twk * Gb * (J[c] * i2 - T(2) * jb * i2 * i2 * B[c]);
             }
         }
-        double yb[3] = {0.0, 0.0, 0.0};
+        T yb[3] = {T(0), T(0), T(0)};
         for (int c = 0; c < 3; c++) {
-            double gr[3];
+            T gr[3];
             poly_grad(cb[c], u, v, w, gr);
             for (int a = 0; a < 3; a++) yb[a] += Bb[c] * gr[a];
             if (TW) {
@@ -429,7 +433,7 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
             }
         }
         for (int q = 0; q < 8; q++) {
-            const double wq = tri_w(q, u, v, w);
+            const T wq = tri_w(q, u, v, w);
             for (int c = 0; c < 3; c++) {
                 gB[c][q] += Bb[c] * wq;
                 if (TW) gJ[c][q] += Jb[c] * wq;
@@ -437,8 +441,8 @@ __device__ void step_adjoint(const double cb[3][8], const double cj[3][8], const
         }
         for (int a = 0; a < 3; a++) ln[a] += yb[a];
         for (int jj = 0; jj < st; jj++) {
-            for (int a = 0; a < 3; a++) mu[jj][a] += H * A[st][jj] * yb[a];
-            dH += A[st][jj] * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
+            for (int a = 0; a < 3; a++) mu[jj][a] += H * A(st, jj) * yb[a];
+            dH += A(st, jj) * (yb[0] * k[jj][0] + yb[1] * k[jj][1] + yb[2] * k[jj][2]);
         }
     }
     if (ax >= 0 && !onbox) ln[ax] -= dH;  // H = face - p_axis
@@ -459,26 +463,28 @@ struct Capture {
     }
 };
 
-template <bool TW>
+template <typename T, bool TW>
 __device__ void flush_cell(double *gnode, int64_t nn, int nx, int ny, int c0, int c1, int c2,
-                           double gB[3][8], double gJ[3][8])
+                           T gB[3][8], T gJ[3][8])
 {
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t base = (int64_t)c2 * sz + (int64_t)c1 * sy + c0;
     for (int q = 0; q < 8; q++) {
         const int64_t o = base + (q & 1) + ((q >> 1) & 1) * sy + ((q >> 2) & 1) * sz;
         for (int c = 0; c < 3; c++) {
-            if (gB[c][q] != 0.0) atomicAdd(gnode + c * nn + o, gB[c][q]);
-            gB[c][q] = 0.0;
+            if (gB[c][q] != T(0)) atomicAdd(gnode + c * nn + o, (double)gB[c][q]);
+            gB[c][q] = T(0);
             if (TW) {
-                if (gJ[c][q] != 0.0) atomicAdd(gnode + (3 + c) * nn + o, gJ[c][q]);
-                gJ[c][q] = 0.0;
+                if (gJ[c][q] != T(0)) atomicAdd(gnode + (3 + c) * nn + o, (double)gJ[c][q]);
+                gJ[c][q] = T(0);
             }
         }
     }
 }
 
-template <typename S, bool TW, int SCH>
+// T: the arithmetic of the replay (that of the forward pass, so the replay is bit
+// for bit) and of the reverse sweep; S: the node records.
+template <typename T, typename S, bool TW, int SCH>
 __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__restrict__ jobs,
                                                             BwdParams bp)
 {
@@ -486,27 +492,27 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= bp.nslots) return;
     StepRec *buf = bp.buf + slot * bp.seg;
-    LaneConst<double> K;
+    LaneConst<T> K;
     K.nx = J.n[0];
     K.ny = J.n[1];
     K.nz = J.n[2];
-    K.rx = (double)J.rscale[0];
-    K.ry = (double)J.rscale[1];
-    K.rz = (double)J.rscale[2];
-    K.twk = (double)J.twk;
-    K.bnull2 = (double)Num<double>::null_rel * (double)(*J.bmax2);
+    K.rx = (T)J.rscale[0];
+    K.ry = (T)J.rscale[1];
+    K.rz = (T)J.rscale[2];
+    K.twk = (T)J.twk;
+    K.bnull2 = (T)((double)Num<T>::null_rel * (double)(*J.bmax2));
     K.max_steps = bp.max_steps;
     const int64_t nn = (int64_t)K.nx * K.ny * K.nz;
     unsigned long long n_half = 0, n_steps = 0, n_bad = 0, n_drop = 0;
-    double cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
+    T cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
     for (int c = 0; c < 3; c++)
-        for (int q = 0; q < 8; q++) gB[c][q] = gJ[c][q] = 0.0;
+        for (int q = 0; q < 8; q++) gB[c][q] = gJ[c][q] = T(0);
     // A lane reverses its half line one segment per iteration and takes the next half
     // line as soon as its own is done, so the lanes of a wave stay busy while their
     // half lines differ in length (a segment costs about the same everywhere).
     int64_t h = -1;       // the lane's half line, -1 = none
     bool drained = false; // the queue is empty
-    double lam[3] = {0.0, 0.0, 0.0}, ltw = 0.0, sgn = 1.0;
+    T lam[3] = {T(0), T(0), T(0)}, ltw = T(0), sgn = T(1);
     int endax = -1, ckslot = -1, next = -1, ck = -1, nck = 0, nacc = 0;
     bool bad = false;
     for (;;) {
@@ -518,13 +524,13 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             }
             // long half lines first: they set the end of the launch
             const int64_t hh = bp.order ? (int64_t)bp.order[hq] : (int64_t)hq;
-            for (int a = 0; a < 3; a++) lam[a] = bp.lam_end[3 * hh + a] * J.spacing[a];
+            for (int a = 0; a < 3; a++) lam[a] = (T)(bp.lam_end[3 * hh + a] * J.spacing[a]);
             // the end lies on its box face: only its in-face coordinates can move
             const int fe = J.rec.face[hh];
-            if (fe >= 0) lam[fe >> 1] = 0.0;
+            if (fe >= 0) lam[fe >> 1] = T(0);
             endax = fe >= 0 ? (fe >> 1) : -1;
-            ltw = TW ? bp.lam_tw[hh] : 0.0;
-            if (lam[0] == 0.0 && lam[1] == 0.0 && lam[2] == 0.0 && ltw == 0.0) continue;
+            ltw = TW ? (T)bp.lam_tw[hh] : T(0);
+            if (lam[0] == T(0) && lam[1] == T(0) && lam[2] == T(0) && ltw == T(0)) continue;
             const uint16_t st = J.rec.st[hh];
             nck = bp.tape_n[hh];
             nacc = bp.tape_acc[hh];
@@ -533,7 +539,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                 continue;
             }
             if (nck <= 0 || nacc <= 0) continue;  // no step taken (a seed on its exit face)
-            sgn = hh >= J.nlines ? 1.0 : -1.0;
+            sgn = hh >= J.nlines ? T(1) : T(-1);
             n_half++;
             bad = false;
             ckslot = bp.tape_last[hh];
@@ -546,10 +552,10 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
         {
             // replay the segment from its checkpoint
             const Ckpt cp = bp.tape[ckslot];
-            Lane<double> L;
+            Lane<T> L;
             L.c0 = cp.c0, L.c1 = cp.c1, L.c2 = cp.c2;
-            L.p0 = cp.p0, L.p1 = cp.p1, L.p2 = cp.p2;
-            L.h = cp.h, L.tol = cp.tol, L.sgn = sgn;
+            L.p0 = (T)cp.p0, L.p1 = (T)cp.p1, L.p2 = (T)cp.p2;
+            L.h = (T)cp.h, L.tol = (T)cp.tol, L.sgn = sgn;
             L.tw = 0.0, L.len = 0.0;
             L.trials = cp.trials;
             L.force = cp.force;
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             if (target < 0 || target > bp.seg || (target == 0 && !last)) bad = true;
             int nrec = 0;
             if (!bad) {
-                load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                load_cell<T, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
                 unsigned acc = 0;
                 int cap_axis = -1, cap_clamp = 0;
                 double cap_H = 0.0;
@@ -571,8 +577,8 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     int fin_st = -1, fin_face = -1;
                     bool need_load = false;
                     const unsigned before = acc;
-                    lane_iterate<double, TW, Capture, SCH>(L, cb, cj, K, fin_st, fin_face, need_load,
-                                                            acc, capture);
+                    lane_iterate<T, TW, Capture, SCH>(L, cb, cj, K, fin_st, fin_face, need_load, acc,
+                                                       capture);
                     if (acc != before) {
                         if (nrec >= target) {
                             bad = true;
@@ -588,12 +594,12 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                         break;
                     }
                     if (need_load)
-                        load_cell<double, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                        load_cell<T, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
                 }
                 if (!bad && !last) {
                     const Ckpt nx = bp.tape[next];
-                    if (nx.c0 != L.c0 || nx.c1 != L.c1 || nx.c2 != L.c2 || nx.p0 != L.p0 ||
-                        nx.p1 != L.p1 || nx.p2 != L.p2 || nx.h != L.h)
+                    if (nx.c0 != L.c0 || nx.c1 != L.c1 || nx.c2 != L.c2 || nx.p0 != (double)L.p0 ||
+                        nx.p1 != (double)L.p1 || nx.p2 != (double)L.p2 || nx.h != (double)L.h)
                         bad = true;
                 }
             }
@@ -603,15 +609,15 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                 for (int r = nrec - 1; r >= 0; r--) {
                     const StepRec sr = buf[r];
                     if (sr.c0 != cc0 || sr.c1 != cc1 || sr.c2 != cc2) {
-                        if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                        if (cc0 >= 0) flush_cell<T, TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
                         cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
-                        load_cell<double, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+                        load_cell<T, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
                     }
                     const int endb = (last && r == nrec - 1) ? endax : -1;
-                    step_adjoint<TW, SCH>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
+                    step_adjoint<T, TW, SCH>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
                     n_steps++;
                 }
-                if (cc0 >= 0) flush_cell<TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                if (cc0 >= 0) flush_cell<T, TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
                 next = ckslot;
                 ckslot = cp.prev;
                 ck--;
@@ -726,16 +732,18 @@ hipError_t launch_bwd_order(const int32_t *tape_acc, int64_t nhalves, int32_t *k
 }
 
 namespace {
+// FP64 records: the all-FP64 form; FP32 records: the F32X form, whose forward pass and
+// so its replay and reverse sweep are FP32
 template <int SCH>
 void launch_bwd_s(int store, int want_tw, const TraceJob *job_dev, const BwdParams &bp, hipStream_t s)
 {
     const dim3 grid((unsigned)((bp.nslots + 63) / 64)), blk(64);
     if (store == FQ_DT_F64) {
-        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<double, true, SCH>), grid, blk, 0, s, job_dev, bp);
-        else hipLaunchKernelGGL((trace_backward_kernel<double, false, SCH>), grid, blk, 0, s, job_dev, bp);
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<double, double, true, SCH>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<double, double, false, SCH>), grid, blk, 0, s, job_dev, bp);
     } else {
-        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<float, true, SCH>), grid, blk, 0, s, job_dev, bp);
-        else hipLaunchKernelGGL((trace_backward_kernel<float, false, SCH>), grid, blk, 0, s, job_dev, bp);
+        if (want_tw) hipLaunchKernelGGL((trace_backward_kernel<float, float, true, SCH>), grid, blk, 0, s, job_dev, bp);
+        else hipLaunchKernelGGL((trace_backward_kernel<float, float, false, SCH>), grid, blk, 0, s, job_dev, bp);
     }
 }
 }  // namespace

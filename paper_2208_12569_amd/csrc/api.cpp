@@ -356,8 +356,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     size_t off_buf = 0, off_bkey = 0, off_border = 0, off_bcnt = 0;
     int64_t bwd_halves = 0, bwd_nodes = 0;
     if (bwd) {
-        if (ns != 1 || nrot != 0 || specs[0].kind != SPEC_PLANE || P.precision != FQ_PREC_F64)
-            return FQ_EUNSUPPORTED;
+        if (ns != 1 || nrot != 0 || specs[0].kind != SPEC_PLANE) return FQ_EUNSUPPORTED;
         bwd_halves = 2 * W[0].nlines;
         bwd_nodes = nodes_of(specs[0].f);
         off_tape = cv.take((size_t)bwd->pool * sizeof(Ckpt));
@@ -589,7 +588,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         FQ_TRY(launch_trace(P.precision, P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
                             jobs_dev, tp, counter, P.block, P.waves_per_cu, stream));
     if (ev && ev[1]) FQ_TRY(hipEventRecord(ev[1], stream));
-    if (fixup) {
+    if (fixup && fwd) {
         // FP64 pass over the grazing lines of the FP32 pass, and over the lines whose
         // map point has a large Q by the FP32 pass (formed here first)
         const bool qsel = P.qfix > 0;
@@ -637,6 +636,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             fix_jobs = j64;
         }
         TraceParams fp = tp;
+        fp.tape = nullptr;  // the adjoint's checkpoints come from the FP32 pass only
         fp.list = list;
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;
@@ -693,7 +693,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         bp.max_steps = P.max_steps;
         bp.want_tw = P.want_tw;
         bp.scheme = P.scheme;
-        FQ_TRY(launch_trace_backward(FQ_DT_F64, P.want_tw, jobs_dev, bp, stream));
+        // the reverse pass replays the forward pass's steps in its own arithmetic: FP64
+        // records and FP64 steps, or the F32X form's FP32 records and FP32 pass
+        FQ_TRY(launch_trace_backward(P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
+                                     jobs_dev, bp, stream));
         FQ_TRY(launch_grad_planes(*specs[0].f, gnode, P.want_tw, bwd->gb, stream));
         return FQ_OK;
     }
@@ -755,7 +758,7 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
 {
     int rc = resolve_params(p, P);
     if (rc) return rc;
-    if (P.precision != FQ_PREC_F64 || P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
+    if (P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
     if (f && stretched(f)) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;

@@ -37,8 +37,9 @@ using namespace dev;
 
 // UNI: a single job without a rotated-S0 companion, so every job constant is
 // uniform across the grid (kept in scalar registers).
-// TAPE: the adjoint's forward pass (FP64, single job), which also stores the lane
-// state at the start of every half line and after every tp.seg accepted steps.
+// TAPE: the adjoint's forward pass (single job; FP64, or the FP32 pass of the F32X
+// form), which also stores the lane state at the start of every half line and after
+// every tp.seg accepted steps.
 template <typename T, int TWM, bool UNI, bool TAPE>
 __device__ __forceinline__ bool store_ckpt(const TraceParams &tp, int &last, const Lane<T> &L)
 {
@@ -829,11 +830,13 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched && !tp.cyl;
     if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
-        // the adjoint's forward pass: FP64, one job, no FP64 re-trace list, Method I
-        if (!f64 || !uni || tp.list || tp.seg < 1 || tp.method != FQ_METHOD_I) return hipErrorInvalidValue;
+        // the adjoint's forward pass: one job, no FP64 re-trace list, Method I; FP64
+        // on FP64 records, or the FP32 pass of the F32X form
+        if (!uni || tp.list || tp.seg < 1 || tp.method != FQ_METHOD_I || f64 != s64)
+            return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
         if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<double, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
+        else launch_ts<float, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
         return hipGetLastError();
     }
     const void *fn;

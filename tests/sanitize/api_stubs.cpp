@@ -59,6 +59,12 @@ hipError_t launch_trace(int, int, int, const TraceJob *jobs, const TraceParams &
     in_ws(counter, 8, "trace counter");
     if (tp.list) in_ws(tp.list, (size_t)tp.list_cap * sizeof(FixEntry), "re-trace list");
     if (tp.tape) in_ws(tp.tape, (size_t)tp.pool_cap * sizeof(Ckpt), "checkpoint pool");
+    if (tp.tape && tp.list) {
+        // the adjoint keeps the checkpoints of the first pass only (the kernels refuse
+        // a taped re-trace list)
+        fprintf(stderr, "a re-trace pass was launched with the checkpoint pool\n");
+        abort();
+    }
     g_calls++;
     return hipSuccess;
 }

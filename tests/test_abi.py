@@ -179,9 +179,9 @@ def test_python_layer_fails_loudly_without_gpu():
 
 
 def test_backward_workspace_query(lib):
-    """The adjoint is taken in the all-FP64 form on a seed plane on a box face; its
-    workspace holds a pool of 2 + ceil(2048/segment) checkpoints of 64 bytes per half
-    line."""
+    """The adjoint is taken on a seed plane on a box face, in either precision form
+    and with Method I only; its workspace holds a pool of 2 + ceil(2048/segment)
+    checkpoints of 64 bytes per half line."""
     from paper_2208_12569_amd import _lib
 
     f = _fake_field()
@@ -189,7 +189,10 @@ def test_backward_workspace_query(lib):
     p = _lib.fq_params()
     p.want_tw = 1
     p.precision = _lib.FQ_PREC_F32X
+    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32) > 0
+    p.method = _lib.FQ_METHOD_II
     assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32) == 0
+    p.method = _lib.FQ_METHOD_I
     p.precision = _lib.FQ_PREC_F64
     for seg in (0, -1, 5000):
         assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), seg) == 0

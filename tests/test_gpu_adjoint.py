@@ -298,6 +298,78 @@ def test_fixed_step_scheme_adjoint(fq, scheme):
     assert err.max() < 1e-3 and np.median(err) < 2e-5, (err.max(), int(np.argmax(err)))
 
 
+def test_f32x_adjoint(fq):
+    """The adjoint of the F32X form: the FP32 pass is kept, replayed and reversed in
+    FP32 (gradients gathered per cell in FP32, added to FP64 node sums). Against the
+    closed form of the sheared field, against the all-FP64 adjoint on a charge field
+    (the two forms' gradients of one loss), with no replay leaving its forward pass,
+    and the recorded F32X map equal to fastqsl_q2d's F32X map bit for bit."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    F32X = 0
+    g = cubic_grid(17, 17, 17)
+    s, y0, L = 0.5, 0.5, 1.0
+    B = _dev(linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1]))
+    pl = Plane((0.41, 0.25, 0.0), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.02)
+    yy = np.asarray(g.axes()[1])[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[0] = np.broadcast_to(yy - y0, g.shape)
+    interior = np.zeros((9, 9))
+    interior[1:-1, 1:-1] = 1.0
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say("f32x adjoint: shear dQ/ds")
+    gq = fq.backward(B, g, pl, fq.Params(precision=F32X, stats=stats), 32,
+                     dq=torch.tensor(interior.ravel(), device="cuda")).cpu().numpy()
+    st = stats.tolist()
+    assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0, st
+    got, want = float((gq * dBds).sum()), interior.sum() * 2 * s * L * L
+    print("f32x shear dQ/ds", got, want)
+    assert abs(got / want - 1) < 1e-4, (got, want)
+
+    g = cubic_grid(48, 48, 32)
+    pl = synth.plane_z0(32)
+    pos0, q0 = _charges(7, 6)
+    theta0 = torch.cat([pos0.ravel(), q0]).detach()
+
+    def field(theta):
+        return charges_field_torch(g, theta[:18].view(6, 3), theta[18:], torch.float64, "cuda")
+
+    p32, p64 = fq.Params(precision=F32X), fq.Params(precision=F64, tol_perp=TOL)
+    _say("f32x adjoint: record vs q2d")
+    B0 = field(theta0).float()
+    rec = fq.q2d_record(B0, g, pl, p32, 8, want_lines=True)
+    ref = fq.q2d(B0, g, pl, p32, want_lines=True)
+    torch.cuda.synchronize()
+    for k in ("q", "tw", "length", "status"):
+        assert np.array_equal(rec[k].cpu().numpy(), ref[k].cpu().numpy(), equal_nan=True), k
+    r64 = fq.q2d(field(theta0), g, pl, p64)
+    mask = _fd_mask(fq, r64) & _fd_mask(fq, ref)
+    assert mask.float().mean() > 0.3
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    wq = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    wt = torch.randn((32, 32), generator=gen, device="cuda", dtype=torch.float64)
+    we = torch.randn((32, 32, 3), generator=gen, device="cuda", dtype=torch.float64)
+    grads = {}
+    for name, p, dt in (("f64", p64, torch.float64), ("f32x", p32, torch.float32)):
+        _say(f"f32x adjoint: charge-field gradient, {name}")
+        loss = _loss_fn(fq, g, pl, mask, wq, wt, we, p)
+        theta = theta0.clone().requires_grad_(True)
+        loss(field(theta).to(dt)).backward()
+        grads[name] = theta.grad.detach().cpu().numpy()
+    a, b = grads["f32x"], grads["f64"]
+    err = np.abs(a - b) / np.maximum(np.abs(b), 1e-3 * np.abs(b).max())
+    print("f32x vs f64 adjoint: max rel", err.max(), "median", np.median(err))
+    assert err.max() < 1e-2 and np.median(err) < 1e-3, (err.max(), int(np.argmax(err)))
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    fq.backward_recorded(B0, g, pl, rec, fq.Params(precision=F32X, stats=stats), 8,
+                         dq=torch.ones(32 * 32, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    st = stats.tolist()
+    assert st[0] > 0 and st[2] == 0 and st[3] == 0, st
+
+
 def test_segment_length_does_not_change_the_gradient(fq):
     """Checkpointing every 1, 5 or 32 accepted steps replays the same steps: the node
     gradients agree to rounding, and no replay diverges from its forward pass."""

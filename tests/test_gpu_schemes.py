@@ -119,10 +119,18 @@ def test_fixed_step_map_parity(fq, prec, scheme):
     print(compare_maps(r, o, f"c1-scheme{scheme}-{prec}"))
 
 
-def test_adjoint_refuses_fixed_steps(fq):
+@pytest.mark.parametrize("scheme", [1, 2], ids=["rk4", "rk4_38"])
+def test_recorded_fixed_step_map_equals_q2d(fq, scheme):
+    """The adjoint's checkpointed forward pass of a fixed-step scheme writes the map of
+    fastqsl_q2d bit for bit (the gradient itself is checked with the adjoint)."""
     import torch
 
     w = synth.config_c1(0)
     B = torch.from_numpy(w.field).cuda()
-    with pytest.raises(ValueError):
-        fq.q2d_record(B, w.grid, w.plane, fq.Params(precision=F64, scheme=2))
+    p = fq.Params(precision=F64, scheme=scheme, step_perp=0.1, step_min=0.1)
+    _say(f"recorded map, scheme {scheme}")
+    rec = fq.q2d_record(B, w.grid, w.plane, p, 16)
+    ref = fq.q2d(B, w.grid, w.plane, p)
+    torch.cuda.synchronize()
+    for k in ("q", "tw", "length", "status"):
+        assert np.array_equal(to_np(rec[k]), to_np(ref[k]), equal_nan=True), k
