@@ -307,8 +307,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         w.nodes = cv.take((size_t)nn * (P.want_tw ? 8 : 4) * tsz);
         w.bmax = cv.take(sizeof(float));
         take_recs(cv, w.nlines, w.end, w.tw, w.len, w.face, w.st);
-        if (s.kind == SPEC_PLANE) {
-            const int64_t ntiles = ((s.pl.nu + 7) / 8) * ((s.pl.nv + 7) / 8);
+        if (s.kind == SPEC_PLANE || s.kind == SPEC_VOXELS) {
+            const int64_t ntiles = s.kind == SPEC_PLANE
+                                       ? ((s.pl.nu + 7) / 8) * ((s.pl.nv + 7) / 8)
+                                       : ((s.vx.n[0] + 3) / 4) * ((s.vx.n[1] + 3) / 4) * ((s.vx.n[2] + 3) / 4);
             w.tile_order = cv.take((size_t)ntiles * sizeof(int32_t));
             w.tile_bucket = cv.take((size_t)ntiles * sizeof(int32_t));
             w.tile_counts = cv.take(256 * sizeof(uint32_t));
@@ -509,6 +511,12 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             if (fwd)
                 FQ_TRY(launch_tile_order(J, P.precision, P.want_tw, (int32_t *)(ws + w.tile_bucket), (uint32_t *)(ws + w.tile_counts),
                                          (int32_t *)(ws + w.tile_order), stream));
+        } else if (s.kind == SPEC_VOXELS) {
+            J.tile_order = (const int32_t *)(ws + w.tile_order);
+            if (fwd)
+                FQ_TRY(launch_voxel_order(J, P.precision, P.want_tw, (int32_t *)(ws + w.tile_bucket),
+                                          (uint32_t *)(ws + w.tile_counts), (int32_t *)(ws + w.tile_order),
+                                          stream));
         }
     }
     // queue ranges of the main jobs, largest cube first: its lines reach farthest, so

@@ -203,6 +203,8 @@ hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_
 // counts (256), order (tiles) are workspace arrays.
 hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *bucket, uint32_t *counts,
                              int32_t *order, hipStream_t s);
+hipError_t launch_voxel_order(const TraceJob &J, int prec, int want_tw, int32_t *key,
+                              uint32_t *counts, int32_t *order, hipStream_t s);
 // Lists the half lines of job `job` that the FP64 pass traces again at
 // list[0, *count) and, with split, the half lines the FP32 pass could not finish
 // (whose twist is then missing too) apart at list[cap - 1 - k] for k < *count_tw.

@@ -725,6 +725,97 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
     }
 }
 
+// Tile order of a 3-D (voxel) job: a voxel map's lines sweep the whole cube, whose
+// node records do not fit the caches, so the tiles whose lines run together should be
+// traced together. Lines that share a footpoint are one flux tube: a tile's key is
+// where the coarse backward line from its central voxel leaves the box (Heun steps
+// of four grid spacings, at most 1024), a bin of that face, the bins of each face in
+// a serpentine order so that neighbouring keys are neighbouring bins: 12 x 12 bins on
+// the bottom face (z low, where most lines of a solar cube end), 4 x 5 on each other
+// face, and the last key for a line that does not leave.
+constexpr int kFootSteps = 1024;
+
+__device__ __forceinline__ int serp(float u, float v, int nu, int nv)
+{
+    const int iu = min(max((int)(u * (float)nu), 0), nu - 1);
+    const int iv = min(max((int)(v * (float)nv), 0), nv - 1);
+    return iv * nu + ((iv & 1) ? nu - 1 - iu : iu);
+}
+
+template <typename R, bool WIDE>
+__global__ void tile_foot_kernel(TraceJob J, int32_t *__restrict__ key)
+{
+    const typename V4<R>::t *A = gptr((const typename V4<R>::t *)J.nodes);
+    const int64_t ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
+    const bool str = J.geo != nullptr;
+    const double dmin = str ? J.geo->dref : fmin(J.spacing[0], fmin(J.spacing[1], J.spacing[2]));
+    const int n[3] = {J.n[0], J.n[1], J.n[2]};
+    float hs[3];
+    for (int a = 0; a < 3; a++) hs[a] = (float)(kCoarseCells * dmin / J.spacing[a]);
+    auto step_of = [&](int a, float ga) -> float {
+        if (!str) return hs[a];
+        const int c = min(max((int)floorf(ga), 0), n[a] - 2);
+        return (float)(kCoarseCells * dmin * J.iw[a][c]);
+    };
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tz = t / (J.tiles[0] * J.tiles[1]);
+        const int64_t rem = t - tz * J.tiles[0] * J.tiles[1];
+        const int64_t ty = rem / J.tiles[0], tx = rem - ty * J.tiles[0];
+        const int64_t iv[3] = {min(tx * 4 + 2, J.dims[0] - 1), min(ty * 4 + 2, J.dims[1] - 1),
+                               min(tz * 4 + 2, J.dims[2] - 1)};
+        const double sp[3] = {J.s_a[0], J.s_b[1], J.s_c[2]};
+        float g[3];
+        bool inside = true;
+        for (int a = 0; a < 3; a++) {
+            const double r = J.s_origin[a] + (double)iv[a] * sp[a];
+            if (str && J.planes.coord[a]) {
+                const double *x = J.planes.coord[a];
+                inside = inside && r >= x[0] && r <= x[n[a] - 1];
+                double p;
+                const int c = str_cell(J, a, r, p);
+                g[a] = (float)((double)c + p);
+                continue;
+            }
+            g[a] = (float)((r - J.origin[a]) * J.inv_spacing[a]);
+            inside = inside && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
+        }
+        int k = 255;
+        if (inside) {
+            bool left = false;
+            for (int m = 0; m < kFootSteps && !left; m++) {
+                float B[3], gm[3], B2[3];
+                coarse_field<R, WIDE>(A, n, g, B);
+                const float bm = sqrtf(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+                if (!(bm > 0.0f) || !isfinite(bm)) break;
+                for (int a = 0; a < 3; a++) gm[a] = g[a] - 0.5f * step_of(a, g[a]) * B[a] / bm;
+                coarse_field<R, WIDE>(A, n, gm, B2);
+                const float bm2 = sqrtf(B2[0] * B2[0] + B2[1] * B2[1] + B2[2] * B2[2]);
+                if (!(bm2 > 0.0f) || !isfinite(bm2)) break;
+                for (int a = 0; a < 3; a++) {
+                    g[a] -= step_of(a, gm[a]) * B2[a] / bm2;
+                    left = left || g[a] < 0.0f || g[a] > (float)(n[a] - 1);
+                }
+            }
+            if (left) {
+                // the face it left by: the farthest out (grid units)
+                int f = 0;
+                float out = -1.0f;
+                for (int a = 0; a < 3; a++) {
+                    const float lo = -g[a], hi = g[a] - (float)(n[a] - 1);
+                    if (lo > out) out = lo, f = 2 * a;
+                    if (hi > out) out = hi, f = 2 * a + 1;
+                }
+                const int a = f >> 1, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+                const float u = g[b] / (float)(n[b] - 1), v = g[c] / (float)(n[c] - 1);
+                if (f == 4) k = serp(u, v, 12, 12);
+                else k = 144 + 20 * (f < 4 ? f : 4) + serp(u, v, 4, 5);
+            }
+        }
+        key[t] = k;
+    }
+}
+
 // Key -> bucket, longest first (bucket 0), and the bucket counts for the placement
 // (a block histogram in LDS first: many tiles share a bucket). Blocks of 256.
 __global__ void tile_key_kernel(int64_t ntiles, int32_t *__restrict__ bucket,
@@ -799,6 +890,24 @@ hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_bucket_order(ntiles, bucket, counts, order, s);
+}
+
+hipError_t launch_voxel_order(const TraceJob &J, int prec, int want_tw, int32_t *key,
+                              uint32_t *counts, int32_t *order, hipStream_t s)
+{
+    const int64_t ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
+    int64_t bl = (ntiles + 255) / 256;
+    if (bl > 65536) bl = 65536;
+    if (prec == FQ_PREC_F64) {
+        if (want_tw) hipLaunchKernelGGL((tile_foot_kernel<double, true>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
+        else hipLaunchKernelGGL((tile_foot_kernel<double, false>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
+    } else {
+        if (want_tw) hipLaunchKernelGGL((tile_foot_kernel<float, true>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
+        else hipLaunchKernelGGL((tile_foot_kernel<float, false>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bucket_order(ntiles, key, counts, order, s);
 }
 
 hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_t *order,

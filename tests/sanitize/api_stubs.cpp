@@ -81,6 +81,11 @@ hipError_t launch_tile_order(const TraceJob &J, int, int, int32_t *bucket, uint3
 {
     return launch_bucket_order(J.tiles[0] * J.tiles[1], bucket, counts, order, s);
 }
+hipError_t launch_voxel_order(const TraceJob &J, int, int, int32_t *key, uint32_t *counts,
+                              int32_t *order, hipStream_t s)
+{
+    return launch_bucket_order(J.tiles[0] * J.tiles[1] * J.tiles[2], key, counts, order, s);
+}
 hipError_t launch_graze(const TraceJob *jobs, int job, int64_t, double, const double *, double,
                         FixEntry *list, uint32_t *count, uint32_t *count_tw, int64_t cap, int, int,
                         hipStream_t)
