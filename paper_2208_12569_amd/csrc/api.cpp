@@ -313,7 +313,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
                                        : ((s.vx.n[0] + 3) / 4) * ((s.vx.n[1] + 3) / 4) * ((s.vx.n[2] + 3) / 4);
             w.tile_order = cv.take((size_t)ntiles * sizeof(int32_t));
             w.tile_bucket = cv.take((size_t)ntiles * sizeof(int32_t));
-            w.tile_counts = cv.take(256 * sizeof(uint32_t));
+            // voxel tiles are sorted over 65536 footpoint keys, plane tiles over 256
+            w.tile_counts = cv.take((s.kind == SPEC_VOXELS ? 65536 : 256) * sizeof(uint32_t));
         }
         if (m2) w.uv = cv.take((size_t)(2 * w.nlines) * 6 * sizeof(double));
         if (stretched(s.f)) {

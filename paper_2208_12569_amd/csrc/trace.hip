@@ -730,10 +730,12 @@ __global__ void tile_len_kernel(TraceJob J, int32_t *__restrict__ len)
 // traced together. Lines that share a footpoint are one flux tube: a tile's key is
 // where the coarse backward line from its central voxel leaves the box (Heun steps
 // of four grid spacings, at most 1024), a bin of that face, the bins of each face in
-// a serpentine order so that neighbouring keys are neighbouring bins: 12 x 12 bins on
-// the bottom face (z low, where most lines of a solar cube end), 4 x 5 on each other
-// face, and the last key for a line that does not leave.
+// a serpentine order so that neighbouring keys are neighbouring bins: 224 x 224 bins
+// on the bottom face (z low, where most lines of a solar cube end), 50 x 60 on each
+// other face, and the last key (65535) for a line that does not leave. The tiles are
+// then placed by a counting sort over the 65536 keys (in any order inside a key).
 constexpr int kFootSteps = 1024;
+constexpr int kFootKeys = 65536;
 
 __device__ __forceinline__ int serp(float u, float v, int nu, int nv)
 {
@@ -780,7 +782,7 @@ __global__ void tile_foot_kernel(TraceJob J, int32_t *__restrict__ key)
             g[a] = (float)((r - J.origin[a]) * J.inv_spacing[a]);
             inside = inside && g[a] >= 0.0f && g[a] <= (float)(n[a] - 1);
         }
-        int k = 255;
+        int k = kFootKeys - 1;
         if (inside) {
             bool left = false;
             for (int m = 0; m < kFootSteps && !left; m++) {
@@ -808,8 +810,8 @@ __global__ void tile_foot_kernel(TraceJob J, int32_t *__restrict__ key)
                 }
                 const int a = f >> 1, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
                 const float u = g[b] / (float)(n[b] - 1), v = g[c] / (float)(n[c] - 1);
-                if (f == 4) k = serp(u, v, 12, 12);
-                else k = 144 + 20 * (f < 4 ? f : 4) + serp(u, v, 4, 5);
+                if (f == 4) k = serp(u, v, 224, 224);
+                else k = 224 * 224 + 3000 * (f < 4 ? f : 4) + serp(u, v, 50, 60);
             }
         }
         key[t] = k;
@@ -892,12 +894,57 @@ hipError_t launch_tile_order(const TraceJob &J, int prec, int want_tw, int32_t *
     return launch_bucket_order(ntiles, bucket, counts, order, s);
 }
 
+namespace {
+// The counting sort of voxel tiles by key: counts per key, their exclusive scan (one
+// block), and the placement (a key's cursor taken with an atomic: tiles of one key
+// land in any order, which only changes when each is traced).
+__global__ void foot_count_kernel(int64_t n, const int32_t *__restrict__ key, uint32_t *counts)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(counts + key[t], 1u);
+}
+
+__global__ __launch_bounds__(1024) void foot_scan_kernel(uint32_t *counts)
+{
+    constexpr int per = kFootKeys / 1024;
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t sum = 0;
+    for (int i = 0; i < per; i++) sum += counts[t * per + i];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t acc = part[t] - sum;
+    for (int i = 0; i < per; i++) {
+        const uint32_t c = counts[t * per + i];
+        counts[t * per + i] = acc;
+        acc += c;
+    }
+}
+
+__global__ void foot_place_kernel(int64_t n, const int32_t *__restrict__ key, uint32_t *cursor,
+                                  int32_t *__restrict__ order)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        order[atomicAdd(cursor + key[t], 1u)] = (int32_t)t;
+}
+}  // namespace
+
 hipError_t launch_voxel_order(const TraceJob &J, int prec, int want_tw, int32_t *key,
                               uint32_t *counts, int32_t *order, hipStream_t s)
 {
     const int64_t ntiles = J.tiles[0] * J.tiles[1] * J.tiles[2];
     int64_t bl = (ntiles + 255) / 256;
     if (bl > 65536) bl = 65536;
+    hipError_t e = launch_fill_u32(counts, kFootKeys, 0u, s);
+    if (e != hipSuccess) return e;
     if (prec == FQ_PREC_F64) {
         if (want_tw) hipLaunchKernelGGL((tile_foot_kernel<double, true>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
         else hipLaunchKernelGGL((tile_foot_kernel<double, false>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
@@ -905,9 +952,10 @@ hipError_t launch_voxel_order(const TraceJob &J, int prec, int want_tw, int32_t 
         if (want_tw) hipLaunchKernelGGL((tile_foot_kernel<float, true>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
         else hipLaunchKernelGGL((tile_foot_kernel<float, false>), dim3((unsigned)bl), dim3(256), 0, s, J, key);
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_bucket_order(ntiles, key, counts, order, s);
+    hipLaunchKernelGGL(foot_count_kernel, dim3((unsigned)bl), dim3(256), 0, s, ntiles, key, counts);
+    hipLaunchKernelGGL(foot_scan_kernel, dim3(1), dim3(1024), 0, s, counts);
+    hipLaunchKernelGGL(foot_place_kernel, dim3((unsigned)bl), dim3(256), 0, s, ntiles, key, counts, order);
+    return hipGetLastError();
 }
 
 hipError_t launch_bucket_order(int64_t n, int32_t *key, uint32_t *counts, int32_t *order,

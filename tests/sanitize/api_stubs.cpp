@@ -82,9 +82,14 @@ hipError_t launch_tile_order(const TraceJob &J, int, int, int32_t *bucket, uint3
     return launch_bucket_order(J.tiles[0] * J.tiles[1], bucket, counts, order, s);
 }
 hipError_t launch_voxel_order(const TraceJob &J, int, int, int32_t *key, uint32_t *counts,
-                              int32_t *order, hipStream_t s)
+                              int32_t *order, hipStream_t)
 {
-    return launch_bucket_order(J.tiles[0] * J.tiles[1] * J.tiles[2], key, counts, order, s);
+    const size_t n = (size_t)(J.tiles[0] * J.tiles[1] * J.tiles[2]);
+    in_ws(key, n * 4, "voxel tile keys");
+    in_ws(counts, 65536 * 4, "voxel key counts");
+    in_ws(order, n * 4, "voxel tile order");
+    g_calls++;
+    return hipSuccess;
 }
 hipError_t launch_graze(const TraceJob *jobs, int job, int64_t, double, const double *, double,
                         FixEntry *list, uint32_t *count, uint32_t *count_tw, int64_t cap, int, int,
