@@ -296,6 +296,9 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     // queue counters: +0 the tracer (u64, u32 spare), +64 the reverse pass, +128 the
     // checkpoint pool, +192 the FP64 pass over half lines that need their twist
     const size_t off_ctr = cv.take(256);
+    // per-XCD queue counters of a 3-D map (8, 64 bytes apart)
+    const bool xcd = ns == 1 && specs[0].kind == SPEC_VOXELS;
+    const size_t off_xctr = xcd ? cv.take(512) : 0;
     std::vector<SpecWs> W(ns);
     int nrot = 0;
     for (int i = 0; i < ns; i++) {
@@ -579,6 +582,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     tp.max_steps = P.max_steps;
     tp.want_tw = P.want_tw;
     tp.njobs = njobs;
+    if (xcd) {
+        tp.xcd_ctr = (unsigned long long *)(ws + off_xctr);
+        if (fwd) FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_xctr), 128, 0u, stream));
+    }
     tp.stats = bwd ? nullptr : (unsigned long long *)P.stats;
     tp.static_items = items;
     if (bwd) {
@@ -646,6 +653,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         }
         TraceParams fp = tp;
         fp.tape = nullptr;  // the adjoint's checkpoints come from the FP32 pass only
+        fp.xcd_ctr = nullptr;  // list mode: one queue
         fp.list = list;
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;

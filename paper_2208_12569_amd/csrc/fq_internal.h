@@ -146,6 +146,9 @@ struct TraceParams {
     int32_t seg;
     int32_t pad2;
     int64_t pool_cap;
+    // per-XCD queues (multi-job kernels, not list mode): when set, 8 counters 64 bytes
+    // apart, one per range of the queue split in 8 contiguous ranges of whole tiles
+    unsigned long long *xcd_ctr;
 };
 
 // Reverse sweep over the traced half lines of one job.

@@ -139,6 +139,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
     double sv_tw = 0.0, sv_len = 0.0, cphi = 0.0;
     T cb[3][8], cj[3][8];
     Tan<T> tn;  // Method II
+    // Per-XCD queues: the items in 8 contiguous ranges of whole tiles, range x drained
+    // first by the workgroups of XCD x (workgroups are dealt to the 8 XCDs in turn),
+    // then by any: the lines in flight on one XCD come from one part of the tile order
+    // and share more of that XCD's L2. A wave moves to the next range once it has seen
+    // its range run out, and is done once it has seen all 8 run out.
+    const bool xsplit = !UNI && tp.xcd_ctr != nullptr && !tp.list;
+    int xq = (int)(blockIdx.x & 7), xtried = 0;
+    const int64_t xr = xsplit ? ((total + 8 * 128 - 1) / (8 * 128)) * 128 : 0;
     unsigned n_trial = 0, n_acc = 0, n_fetch = 0, n_half = 0;
     int acc_half = 0, nck = 0;  // TAPE: accepted steps and checkpoints of the half line
     int last_ck = -1;           // TAPE: pool slot of the last checkpoint
@@ -154,13 +162,24 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             const int cnt = __popcll(m);
             const int leader = __ffsll((long long)m) - 1;
             unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+            int64_t lo = 0, hi = total;
+            if (xsplit) {
+                lo = (int64_t)xq * xr < total ? (int64_t)xq * xr : total;
+                hi = lo + xr < total ? lo + xr : total;
+                if (lane == leader) base = atomicAdd(tp.xcd_ctr + 8 * xq, (unsigned long long)cnt);
+            } else if (lane == leader) {
+                base = atomicAdd(counter, (unsigned long long)cnt);
+            }
             base = shfl_u64(base, leader);
+            if (xsplit && lo + (int64_t)base + cnt >= hi) {
+                xq = (xq + 1) & 7;  // this range has run out
+                xtried++;
+            }
             if (need) {
                 const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                const int64_t it = (int64_t)(base + (unsigned long long)rank);
-                if (it >= total) {
-                    exhausted = true;
+                const int64_t it = lo + (int64_t)(base + (unsigned long long)rank);
+                if (it >= hi) {
+                    if (!xsplit || xtried >= 8) exhausted = true;
                 } else {
                     int j = 0;
                     int64_t line;
