@@ -14,7 +14,9 @@ a much tighter tolerance on the same GPU.
 from __future__ import annotations
 
 import dataclasses
+import json
 import math
+import os
 from typing import Optional, Sequence
 
 from . import (FQ_PREC_F64, ST_EDGE, ST_FATAL, ST_MIXEDFACE, Params, _torch,
@@ -42,6 +44,47 @@ def _key(jobs, params: Params):
     """Launch shapes are timed per job shapes, precision and Tw flag."""
     return (tuple((tuple(B.shape), str(B.dtype), pl.nu, pl.nv) for B, _, pl in jobs),
             params.precision, params.want_tw)
+
+
+def size_class(jobs) -> str:
+    """The class a launch shape is stored under on disk: single job or batch, the
+    base-2 logarithms of the total seed count and of the largest cube edge, and the
+    grid dtype (the best block size and residency depend on these, not on the exact
+    shapes)."""
+    seeds = sum(int(pl.nu) * int(pl.nv) for _, _, pl in jobs)
+    edge = max(max(int(n) for n in B.shape[-3:]) for B, _, _ in jobs)
+    dtypes = sorted({str(B.dtype).replace("torch.", "") for B, _, _ in jobs})
+    return (f"{'batch' if len(jobs) > 1 else 'single'}-seeds2^{int(math.log2(max(seeds, 1)))}"
+            f"-edge2^{int(math.log2(max(edge, 1)))}-{'+'.join(dtypes)}")
+
+
+def _arch(device) -> str:
+    torch = _torch()
+    name = getattr(torch.cuda.get_device_properties(device), "gcnArchName", "") or "unknown"
+    return name.split(":")[0]
+
+
+def _disk_key(jobs, params: Params) -> str:
+    return f"{_arch(jobs[0][0].device)}|{size_class(jobs)}|prec{params.precision}|tw{int(params.want_tw)}"
+
+
+def _load(path: str) -> dict:
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, key: str, fields: dict) -> None:
+    d = _load(path)
+    d[key] = fields
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def _field_key(jobs):
@@ -152,18 +195,30 @@ def tune_tol(jobs: Sequence, params: Optional[Params] = None,
 
 
 def autotune(jobs: Sequence, params: Optional[Params] = None, tune_tolerance: bool = False,
-             **kw) -> Params:
-    """Tuned Params for these jobs. The launch shape is cached per job shapes,
-    precision and Tw flag; a tuned tolerance additionally per field values and seed
-    planes (it was checked against the bar on those fields only). A tolerance search
-    that finds no candidate within the bar raises NoToleranceMeetsBar and caches
-    nothing."""
+             cache_file: Optional[str] = None, **kw) -> Params:
+    """Tuned Params for these jobs. The launch shape is cached in memory per job
+    shapes, precision and Tw flag, and, with cache_file, on disk per GPU
+    architecture, size class (size_class()), precision and Tw flag, so that later
+    processes reuse it for jobs of the same class without timing them. A tuned
+    tolerance is cached in memory only, per field values and seed planes (it was
+    checked against the bar on those fields only). A tolerance search that finds no
+    candidate within the bar raises NoToleranceMeetsBar and caches nothing."""
     params = params or Params()
+    jobs = list(jobs)
     key = _key(jobs, params) + ((_field_key(jobs),) if tune_tolerance else ())
     if key in _CACHE:
         return dataclasses.replace(params, **_CACHE[key])
-    p, _ = tune_launch(jobs, params, **{k: v for k, v in kw.items() if k in ("blocks", "waves", "reps")})
-    fields = {"block": p.block, "waves_per_cu": p.waves_per_cu}
+    fields = None
+    if cache_file:
+        fields = _load(cache_file).get(_disk_key(jobs, params))
+        if fields is not None:
+            fields = {"block": int(fields["block"]), "waves_per_cu": int(fields["waves_per_cu"])}
+    if fields is None:
+        p, _ = tune_launch(jobs, params, **{k: v for k, v in kw.items() if k in ("blocks", "waves", "reps")})
+        fields = {"block": p.block, "waves_per_cu": p.waves_per_cu}
+        if cache_file:
+            _store(cache_file, _disk_key(jobs, params), fields)
+    p = dataclasses.replace(params, **fields)
     if tune_tolerance:
         p, _ = tune_tol(jobs, p, **{k: v for k, v in kw.items() if k in ("tols", "ref_tol", "margin")})
         fields["tol_perp"] = p.tol_perp
