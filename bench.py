@@ -778,6 +778,8 @@ def main():
         out["method2"] = run_variant(
             w, "C2, Method II (Q, Q_perp and Tw from U, V traced with each line; no "
                "neighbour lines)", args, uv, method=1)
+    if not args.no_batch:
+        out["batch"] = run_batch(args.seed, args.steps, args.warmup)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
         out["adjoint_f32x"] = run_adjoint(args.seed, args.steps, args.warmup, "f32x")
