@@ -92,8 +92,8 @@ extern "C" {
  * the seed cell's width along B (Section 2.3, the scaling of step and tol on
  * stretched grids). A field whose node coordinates are not strictly increasing and
  * finite, or do not span the box that origin and spacing give (to 1e-12 of its
- * extent), gives its lines FQ_ST_NONFINITE. Method II and the adjoint take uniform
- * grids only (else FQ_EUNSUPPORTED). */
+ * extent), gives its lines FQ_ST_NONFINITE. Method II takes uniform grids only (else
+ * FQ_EUNSUPPORTED). */
 typedef struct {
     int64_t n[3];         /* nodes along x, y, z; each in [2, 65535] */
     double origin[3];     /* position of node (0,0,0) */
@@ -282,9 +282,10 @@ int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, co
  * fastqsl_q2d (Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of
  * Eq. tw) so that a field model can be fitted to target maps.
  *   f, pl, p   the same inputs as the forward call; p->method must be
- *              FQ_METHOD_I (any p->scheme) on a uniform grid and the seed plane must
- *              lie on a box face (no rotated S0), else FQ_EUNSUPPORTED. Use the
- *              forward call's parameters: the lines are traced again with them.
+ *              FQ_METHOD_I (any p->scheme; uniform or stretched grid) and the seed
+ *              plane must lie on a box face (no rotated S0), else FQ_EUNSUPPORTED.
+ *              Use the forward call's parameters: the lines are traced again with
+ *              them.
  *              p->precision picks the form differentiated: FQ_PREC_F64, or
  *              FQ_PREC_F32X, whose FP32 pass is kept, replayed and reversed in FP32
  *              (the map is the F32X map; half lines that its FP64 pass re-traced take

@@ -411,8 +411,8 @@ def _bwd_prepare(B, grid, plane, params: Optional[Params], segment: int):
     p = params.c()
     need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
     if need == 0:
-        raise ValueError("invalid or unsupported backward call (Method I on a uniform grid, plane "
-                         "on a box face, 1 <= segment <= 4096)")
+        raise ValueError("invalid or unsupported backward call (Method I, plane on a box face, "
+                         "1 <= segment <= 4096)")
     return lib, f, pl, p, need
 
 

@@ -43,13 +43,23 @@ struct Tri {
 __device__ void tri_of(const MapJob &m, const double r[3], Tri &t)
 {
     int c[3];
-    double u[3];
+    double u[3], iw[3];
     for (int a = 0; a < 3; a++) {
+        if (m.coord[a]) {
+            // a stretched axis: the cell by bisection, as the FP64 interpolation
+            const double *x = m.coord[a];
+            const int ci = axis_cell(x, m.n[a], r[a]);
+            c[a] = ci;
+            iw[a] = 1.0 / (x[ci + 1] - x[ci]);
+            u[a] = (r[a] - x[ci]) * iw[a];
+            continue;
+        }
         const double g = (r[a] - m.origin[a]) / m.spacing[a];
         int ci = (int)floor(g);
         ci = ci < 0 ? 0 : (ci > m.n[a] - 2 ? m.n[a] - 2 : ci);
         c[a] = ci;
         u[a] = g - ci;
+        iw[a] = 1.0 / m.spacing[a];
     }
     const int64_t sy = m.n[0], sz = (int64_t)m.n[0] * m.n[1];
     const int64_t base = c[2] * sz + c[1] * sy + c[0];
@@ -60,9 +70,9 @@ __device__ void tri_of(const MapJob &m, const double r[3], Tri &t)
         const double sx = ix ? 1.0 : -1.0, syy = iy ? 1.0 : -1.0, szz = iz ? 1.0 : -1.0;
         t.node[q] = base + ix + iy * sy + iz * sz;
         t.w[q] = wx * wy * wz;
-        t.dw[q][0] = sx * wy * wz / m.spacing[0];
-        t.dw[q][1] = wx * syy * wz / m.spacing[1];
-        t.dw[q][2] = wx * wy * szz / m.spacing[2];
+        t.dw[q][0] = sx * wy * wz * iw[0];
+        t.dw[q][1] = wx * syy * wz * iw[1];
+        t.dw[q][2] = wx * wy * szz * iw[2];
     }
 }
 
@@ -502,6 +512,17 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
     K.twk = (T)J.twk;
     K.bnull2 = (T)((double)Num<T>::null_rel * (double)(*J.bmax2));
     K.max_steps = bp.max_steps;
+    // stretched grids: lengths in units of the smallest cell width, and every cell's
+    // own scales (set with each cell, as the forward pass did)
+    const bool str = J.geo != nullptr;
+    const double dref = str ? J.geo->dref : 0.0;
+    if (str) K.twk = (T)(dref * (0.25 / M_PI));
+    auto cell_scales = [&](int c0, int c1, int c2) {
+        if (!str) return;
+        K.rx = (T)(dref * J.iw[0][c0]);
+        K.ry = (T)(dref * J.iw[1][c1]);
+        K.rz = (T)(dref * J.iw[2][c2]);
+    };
     const int64_t nn = (int64_t)K.nx * K.ny * K.nz;
     unsigned long long n_half = 0, n_steps = 0, n_bad = 0, n_drop = 0;
     T cb[3][8], cj[3][8], gB[3][8], gJ[3][8];
@@ -524,7 +545,9 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             }
             // long half lines first: they set the end of the launch
             const int64_t hh = bp.order ? (int64_t)bp.order[hq] : (int64_t)hq;
-            for (int a = 0; a < 3; a++) lam[a] = (T)(bp.lam_end[3 * hh + a] * J.spacing[a]);
+            // in physical units here; in local units (times the end cell's widths) once
+            // the replay of the last segment has found that cell
+            for (int a = 0; a < 3; a++) lam[a] = (T)bp.lam_end[3 * hh + a];
             // the end lies on its box face: only its in-face coordinates can move
             const int fe = J.rec.face[hh];
             if (fe >= 0) lam[fe >> 1] = T(0);
@@ -565,6 +588,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             int nrec = 0;
             if (!bad) {
                 load_cell<T, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                cell_scales(L.c0, L.c1, L.c2);
                 unsigned acc = 0;
                 int cap_axis = -1, cap_clamp = 0;
                 double cap_H = 0.0;
@@ -593,8 +617,16 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                         if (fin_st != 0 || nrec != target || !last) bad = true;
                         break;
                     }
-                    if (need_load)
+                    if (need_load) {
                         load_cell<T, S, TW>(J.nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
+                        cell_scales(L.c0, L.c1, L.c2);
+                    }
+                }
+                if (!bad && last) {
+                    // the end's adjoint into the local units of the cell it ends in
+                    for (int a = 0; a < 3; a++)
+                        lam[a] *= (T)(str ? 1.0 / J.iw[a][a == 0 ? L.c0 : (a == 1 ? L.c1 : L.c2)]
+                                          : J.spacing[a]);
                 }
                 if (!bad && !last) {
                     const Ckpt nx = bp.tape[next];
@@ -612,6 +644,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                         if (cc0 >= 0) flush_cell<T, TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
                         cc0 = sr.c0, cc1 = sr.c1, cc2 = sr.c2;
                         load_cell<T, S, TW>(J.nodes, K.nx, K.ny, cc0, cc1, cc2, cb, cj);
+                        cell_scales(cc0, cc1, cc2);
                     }
                     const int endb = (last && r == nrec - 1) ? endax : -1;
                     step_adjoint<T, TW, SCH>(cb, cj, sr, K, sgn, endb, lam, ltw, gB, gJ);
@@ -650,9 +683,29 @@ __device__ __forceinline__ double dcoef(int m, int n, int N, double ih)
     return n == m + 1 ? 0.5 * ih : (n == m - 1 ? -0.5 * ih : 0.0);
 }
 
+// The same weight on a stretched axis with node coordinates x: the derivative of the
+// quadratic through node m and its two neighbours (the two inward ones on a boundary
+// node), as the prep pass takes it; a plain difference when N < 3.
+__device__ __forceinline__ double dcoef_s(int m, int n, int N, const double *x)
+{
+    if (N < 3) {
+        const double ih = 1.0 / (x[1] - x[0]);
+        return n == 1 ? ih : (n == 0 ? -ih : 0.0);
+    }
+    const int m1 = m == 0 ? 1 : (m == N - 1 ? N - 2 : m - 1);
+    const int m2 = m == 0 ? 2 : (m == N - 1 ? N - 3 : m + 1);
+    const double h1 = x[m1] - x[m], h2 = x[m2] - x[m];
+    const double D = h1 * h2 * (h2 - h1);
+    if (n == m1) return h2 * h2 / D;
+    if (n == m2) return -h1 * h1 / D;
+    if (n == m) return (h1 * h1 - h2 * h2) / D;
+    return 0.0;
+}
+
 // (D_axis)^T g at node (i, j, k): sum over the nodes m whose difference uses it
+// (x: the axis's node coordinates on a stretched axis, else NULL)
 __device__ double dT(const double *g, int axis, int i, int j, int k, int nx, int ny, int nz,
-                     double ih)
+                     double ih, const double *x)
 {
     const int N = axis == 0 ? nx : (axis == 1 ? ny : nz);
     const int n = axis == 0 ? i : (axis == 1 ? j : k);
@@ -662,13 +715,14 @@ __device__ double dT(const double *g, int axis, int i, int j, int k, int nx, int
     const int lo = N < 3 ? 0 : n - 2, hi = N < 3 ? N - 1 : n + 2;
     for (int m = lo; m <= hi; m++) {
         if (m < 0 || m >= N) continue;
-        const double c = dcoef(m, n, N, ih);
+        const double c = x ? dcoef_s(m, n, N, x) : dcoef(m, n, N, ih);
         if (c != 0.0) acc += c * g[q + (int64_t)(m - n) * stride];
     }
     return acc;
 }
 
 __global__ void grad_planes_kernel(int nx, int ny, int nz, double ihx, double ihy, double ihz,
+                                   const double *cx, const double *cy, const double *cz,
                                    const double *__restrict__ gnode, int want_tw, double *gx,
                                    double *gy, double *gz)
 {
@@ -681,9 +735,9 @@ __global__ void grad_planes_kernel(int nx, int ny, int nz, double ihx, double ih
     if (want_tw) {
         // J = (dBz/dy - dBy/dz, dBx/dz - dBz/dx, dBy/dx - dBx/dy)
         const double *gjx = gnode + 3 * nn, *gjy = gnode + 4 * nn, *gjz = gnode + 5 * nn;
-        bx += dT(gjy, 2, i, j, k, nx, ny, nz, ihz) - dT(gjz, 1, i, j, k, nx, ny, nz, ihy);
-        by += dT(gjz, 0, i, j, k, nx, ny, nz, ihx) - dT(gjx, 2, i, j, k, nx, ny, nz, ihz);
-        bz += dT(gjx, 1, i, j, k, nx, ny, nz, ihy) - dT(gjy, 0, i, j, k, nx, ny, nz, ihx);
+        bx += dT(gjy, 2, i, j, k, nx, ny, nz, ihz, cz) - dT(gjz, 1, i, j, k, nx, ny, nz, ihy, cy);
+        by += dT(gjz, 0, i, j, k, nx, ny, nz, ihx, cx) - dT(gjx, 2, i, j, k, nx, ny, nz, ihz, cz);
+        bz += dT(gjx, 1, i, j, k, nx, ny, nz, ihy, cy) - dT(gjy, 0, i, j, k, nx, ny, nz, ihx, cx);
     }
     gx[q] += bx;
     gy[q] += by;
@@ -764,7 +818,8 @@ hipError_t launch_grad_planes(const fq_field &f, const double *gnode, int want_t
     const unsigned bxs = (unsigned)((f.n[0] + 255) / 256);
     hipLaunchKernelGGL(grad_planes_kernel, dim3(bxs, (unsigned)f.n[1], (unsigned)f.n[2]), dim3(256),
                        0, s, (int)f.n[0], (int)f.n[1], (int)f.n[2], 1.0 / f.spacing[0],
-                       1.0 / f.spacing[1], 1.0 / f.spacing[2], gnode, want_tw, gb[0], gb[1], gb[2]);
+                       1.0 / f.spacing[1], 1.0 / f.spacing[2], f.coord[0], f.coord[1], f.coord[2],
+                       gnode, want_tw, gb[0], gb[1], gb[2]);
     return hipGetLastError();
 }
 

@@ -291,7 +291,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     for (int i = 0; i < ns; i++)
         if (specs[i].kind == SPEC_CYL && (m2 || bwd || P.scheme != FQ_SCHEME_RKF45)) return FQ_EUNSUPPORTED;
     for (int i = 0; i < ns; i++)
-        if (stretched(specs[i].f) && (m2 || bwd)) return FQ_EUNSUPPORTED;
+        if (stretched(specs[i].f) && m2) return FQ_EUNSUPPORTED;
     Carve cv;
     // queue counters: +0 the tracer (u64, u32 spare), +64 the reverse pass, +128 the
     // checkpoint pool, +192 the FP64 pass over half lines that need their twist
@@ -776,7 +776,6 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
     int rc = resolve_params(p, P);
     if (rc) return rc;
     if (P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
-    if (f && stretched(f)) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;
     if (!plane_on_face(*pl, *f)) return FQ_EUNSUPPORTED;

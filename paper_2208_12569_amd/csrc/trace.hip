@@ -92,6 +92,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
     constexpr bool TW = TWM == 1;
     // cylindrical mapping surfaces: the multi-job Method I kernels only
     constexpr bool CYLK = !UNI && !M2 && !TAPE;
+    // stretched grids: the multi-job kernels, and the adjoint's single-job forward pass
+    constexpr bool STRK = !UNI || TAPE;
     const int lane = threadIdx.x & 63;
 
     // queue size
@@ -130,6 +132,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
     // grid's smallest cell width, found on the device
     bool str = false;
     double dref_s = 0.0;
+    if (UNI && TAPE && jobs[0].geo != nullptr) {
+        str = true;
+        dref_s = jobs[0].geo->dref;
+        K.twk = (T)(dref_s * (0.25 / M_PI));
+    }
     // cylindrical mapping surfaces (multi-job kernels only, as stretched grids): the
     // lane's job runs inside the cylinder; the state before the trial step (a step
     // that leaves the cylinder is taken again, shorter) and phi = r^2 - R^2 there
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                             cylj = J.kind == SEED_CYL;
                             cphi = 0.0;
                             str = J.geo != nullptr;
-                            if (!UNI && str) {
+                            if (str) {
                                 dref_s = J.geo->dref;
                                 K.twk = (T)(dref_s * (0.25 / M_PI));
                             }
@@ -242,7 +249,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                         acc_half = 0;
                         nck = 0;
                         last_ck = -1;
-                        if (!UNI && str) {
+                        if (STRK && str) {
                             // stretched: the seed's cell by bisection on each axis
                             bool in = !J.geo->bad;
                             for (int a = 0; a < 3; a++) {
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                                 fresh = true;
                             }
                         }
-                        if (UNI || !str) {
+                        if (!STRK || !str) {
                             const double g0 = (r[0] - J.origin[0]) * J.inv_spacing[0],
                                          g1 = (r[1] - J.origin[1]) * J.inv_spacing[1],
                                          g2 = (r[2] - J.origin[2]) * J.inv_spacing[2];
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             load_cell<T, S, TW, TWM != 0>(nodes, K.nx, K.ny, L.c0, L.c1, L.c2, cb, cj);
             need_load = false;
             n_fetch++;
-            if (!UNI && str) {
+            if (STRK && str) {
                 // stretched grid: this cell's widths scale the direction into local
                 // coordinates (reference length / width per axis)
                 const TraceJob &J = jobs[UNI ? 0 : jb];
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 if (!(ang >= amin)) ang = amin;  // also catches NaN
                 if (ang > 1.0f) ang = 1.0f;
                 L.h = (T)fmaxf((float)tp.step_perp * ang, (float)tp.step_min);
-                if (!UNI && str) {
+                if (STRK && str) {
                     // stretched grid: the first step in units of the seed cell's width
                     // along B, 1 / |(b_x / dx, b_y / dy, b_z / dz)| (Section 2.3)
                     const float sx = bx * (float)K.rx, sy = by * (float)K.ry, sz = bz * (float)K.rz;
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 e0 = r[0];
                 e1 = r[1];
                 e2 = r[2];
-            } else if (!bad && !UNI && str) {
+            } else if (!bad && STRK && str) {
                 e0 = grid_pos(J, 0, L.c0, (double)L.p0);
                 e1 = grid_pos(J, 1, L.c1, (double)L.p1);
                 e2 = grid_pos(J, 2, L.c2, (double)L.p2);
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             ge[3 * rec + 1] = e1;
             ge[3 * rec + 2] = e2;
             if (TWM != 2) gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
-            gptr(J.rec.len)[rec] = bad ? NAN : L.len * ((!UNI && str) ? dref_s : J.dref);
+            gptr(J.rec.len)[rec] = bad ? NAN : L.len * ((STRK && str) ? dref_s : J.dref);
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
             if constexpr (M2) {
@@ -1008,7 +1015,9 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     if (tp.tape) {
         // the adjoint's forward pass: one job, no FP64 re-trace list, Method I; FP64
         // on FP64 records, or the FP32 pass of the F32X form
-        if (!uni || tp.list || tp.seg < 1 || tp.method != FQ_METHOD_I || f64 != s64)
+        // (its single-job kernels carry the stretched-grid lane state)
+        if (tp.njobs != 1 || tp.dynamic_last || tp.cyl || tp.list || tp.seg < 1 ||
+            tp.method != FQ_METHOD_I || f64 != s64)
             return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
         if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);

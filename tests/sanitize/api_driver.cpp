@@ -207,9 +207,13 @@ int main()
                                                 nullptr, gb, ws, need, nullptr) == FQ_OK);
                 CHECK(fastqsl_backward_workspace_size(&f[0], &mid, &P, 32) == 0);
                 CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 0) == 0);
+                // stretched grids have an adjoint too
                 fq_field fst = f[0];
                 fst.coord[1] = (const double *)fake_dev;
-                CHECK(fastqsl_backward_workspace_size(&fst, &pl[0], &P, 32) == 0);
+                const size_t nst = fastqsl_backward_workspace_size(&fst, &pl[0], &P, 32);
+                CHECK(nst > 0);
+                CHECK(fastqsl_backward(&fst, &pl[0], &P, 32, g_dummy, g_dummy, nullptr, nullptr, gb,
+                                       workspace(nst), nst, nullptr) == FQ_OK);
                 P.tape_steps = 100000;
                 size_t big = fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 32);
                 CHECK(big > need);

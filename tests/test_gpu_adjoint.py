@@ -370,6 +370,109 @@ def test_f32x_adjoint(fq):
     assert st[0] > 0 and st[2] == 0 and st[3] == 0, st
 
 
+def _random_stretched(nx, ny, nz, seed):
+    """Cell widths drawn in [0.3, 1.7] times the mean: neighbouring cells differ by up
+    to a factor of five."""
+    rng = np.random.default_rng(seed)
+    ax = []
+    for n in (nx, ny, nz):
+        w = rng.uniform(0.3, 1.7, n - 1)
+        x = np.concatenate([[0.0], np.cumsum(w)]) / w.sum()
+        x[-1] = 1.0
+        ax.append(x)
+    return synth.stretched_grid(*ax)
+
+
+def test_stretched_grid_adjoint(fq):
+    """The adjoint on stretched grids (Section 2.2: cells by bisection; Section 2.3:
+    per-cell scales; curl on unequal spacings): the sheared field's closed-form
+    dQ/ds and dTw/ds on a grid whose neighbouring cells differ up to five times in
+    width; explicit uniform nodes against the uniform grid's adjoint; and node
+    values of a stretched charge cube against central differences of the GPU
+    forward."""
+    import torch
+
+    g = _random_stretched(17, 15, 19, seed=3)
+    s, y0, L = 0.5, 0.5, 1.0
+    B = _dev(linear_field(g, [[0, s, 0], [0, 0, 0], [0, 0, 0]], [-s * y0, 0, 1]))
+    pl = Plane((0.41, 0.25, 0.0), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.02)
+    yy = np.asarray(g.coord(1))[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[0] = np.broadcast_to(yy - y0, g.shape)
+    interior = np.zeros((9, 9))
+    interior[1:-1, 1:-1] = 1.0
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say("stretched: shear dQ/ds and dTw/ds")
+    gq = _grad(fq, B, g, pl, stats, dq=torch.tensor(interior.ravel(), device="cuda"))
+    st = stats.tolist()
+    assert st[0] > 0 and st[1] > 0 and st[2] == 0 and st[3] == 0, st
+    got, want = float((gq * dBds).sum()), interior.sum() * 2 * s * L * L
+    assert abs(got / want - 1) < 1e-6, (got, want)
+    eta = pl.points()[:, 1] - y0
+    gt = _grad(fq, B, g, pl, dtw=torch.ones(81, dtype=torch.float64, device="cuda"))
+    got, want = float((gt * dBds).sum()), float(np.sum(-L / (4 * np.pi) * (1 + s * s * eta * eta) ** -1.5))
+    assert abs(got / want - 1) < 1e-6, (got, want)
+
+    _say("stretched: explicit uniform nodes against the uniform grid")
+    gu = cubic_grid(40, 40, 28)
+    pos, q = synth.draw_charges(np.random.default_rng(11), 5)
+    Bu = _dev(synth.charges_field(gu, pos, q))
+    plu = synth.plane_z0(24)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    dq = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    dtw = torch.randn(24 * 24, generator=gen, device="cuda", dtype=torch.float64)
+    de = torch.randn((24 * 24, 3), generator=gen, device="cuda", dtype=torch.float64)
+    ref = _grad(fq, Bu, gu, plu, dq=dq, dtw=dtw, dend_b=de, dend_f=de)
+    gs = synth.stretched_grid(*gu.axes())
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    got = _grad(fq, Bu, gs, plu, stats, dq=dq, dtw=dtw, dend_b=de, dend_f=de)
+    assert stats.tolist()[2] == 0
+    scale = np.abs(ref).max()
+    print("explicit uniform nodes: max |diff| / max |grad|", np.abs(got - ref).max() / scale)
+    assert np.abs(got - ref).max() <= 1e-6 * scale
+
+    _say("stretched: charge cube, node values against central differences")
+    x = synth.clustered_axis(33, 0.0, 1.0, 0.45, 1.3)
+    z = synth.geometric_axis(25, 0.0, 0.75, 1.04)
+    gc = synth.stretched_grid(x, x.copy(), z)
+    pos, q = synth.draw_charges(np.random.default_rng(4), 6)
+    B0 = synth.charges_field(gc, pos, q)
+    plc = Plane((0.1, 0.1, 0.0), (1, 0, 0), (0, 1, 0), 24, 24, 0.8 / 23, 0.8 / 23)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    r = fq.q2d(_dev(B0), gc, plc, p, want_lines=True)
+    mask = _fd_mask(fq, r)
+    assert mask.float().mean() > 0.3
+    wq = torch.randn((24, 24), generator=gen, device="cuda", dtype=torch.float64) * mask
+    wt = torch.randn((24, 24), generator=gen, device="cuda", dtype=torch.float64) * mask
+    we = torch.randn((24 * 24, 3), generator=gen, device="cuda", dtype=torch.float64) * mask.reshape(-1, 1)
+
+    def loss(Bn):
+        rr = fq.q2d(_dev(Bn), gc, plc, p, want_lines=True)
+        qq = torch.where(mask, rr["q"], torch.ones_like(rr["q"]))
+        tw = torch.where(mask, rr["tw"], torch.zeros_like(rr["tw"]))
+        e = rr["lines"]["end_b"] + rr["lines"]["end_f"]
+        e = torch.where(mask.reshape(-1, 1), e, torch.zeros_like(e))
+        return float((wq * torch.log10(qq)).sum() + (wt * tw).sum() + (we * e).sum())
+
+    qq = torch.where(mask, r["q"], torch.ones_like(r["q"]))
+    g_nodes = _grad(fq, _dev(B0), gc, plc, dq=(wq / (qq * math.log(10.0))).reshape(-1),
+                    dtw=wt.reshape(-1), dend_b=we, dend_f=we)
+    flat = np.abs(g_nodes).ravel()
+    rng = np.random.default_rng(8)
+    nodes = np.concatenate([np.argsort(flat)[-16:], rng.choice(np.flatnonzero(flat > 1e-3 * flat.max()), 8)])
+    errs = []
+    for n in nodes:
+        v = float(B0.ravel()[n])
+        h = 1e-5 * max(abs(v), 1e-2)
+        bp_, bm_ = B0.copy(), B0.copy()
+        bp_.ravel()[n] += h
+        bm_.ravel()[n] -= h
+        fd = (loss(bp_) - loss(bm_)) / (2 * h)
+        errs.append(abs(g_nodes.ravel()[n] - fd) / max(abs(fd), 1e-2 * flat.max()))
+    print("stretched node gradients: max rel err", max(errs))
+    assert max(errs) < 1e-4, errs
+
+
 def test_segment_length_does_not_change_the_gradient(fq):
     """Checkpointing every 1, 5 or 32 accepted steps replays the same steps: the node
     gradients agree to rounding, and no replay diverges from its forward pass."""
