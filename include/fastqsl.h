@@ -282,10 +282,11 @@ int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, co
  * fastqsl_q2d (Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of
  * Eq. tw) so that a field model can be fitted to target maps.
  *   f, pl, p   the same inputs as the forward call; p->method must be
- *              FQ_METHOD_I (any p->scheme; uniform or stretched grid) and the seed
- *              plane must lie on a box face (no rotated S0), else FQ_EUNSUPPORTED.
- *              Use the forward call's parameters: the lines are traced again with
- *              them.
+ *              FQ_METHOD_I (any p->scheme on a plane on a box face; RKF45 on an
+ *              interior plane, whose rotated-S0 lines (Section 4) are differentiated
+ *              too, their seeds' dependence on B0 included), on a uniform or
+ *              stretched grid, else FQ_EUNSUPPORTED. Use the forward call's
+ *              parameters: the lines are traced again with them.
  *              p->precision picks the form differentiated: FQ_PREC_F64, or
  *              FQ_PREC_F32X, whose FP32 pass is kept, replayed and reversed in FP32
  *              (the map is the F32X map; half lines that its FP64 pass re-traced take
@@ -300,10 +301,12 @@ int fastqsl_qcyl(const fq_field *f, const fq_cylinder *c, const fq_params *p, co
  *              dL/dBz are ADDED to them.
  *   ws         caller workspace of fastqsl_backward_workspace_size() bytes (256-byte
  *              aligned). It holds a pool of 2 + ceil(p->tape_steps/segment)
- *              checkpoints of 64 bytes per half line (shared by all half lines: room
- *              for p->tape_steps accepted steps per half line on average), per-half
- *              adjoints, node gradients, replay buffers and the reverse pass's queue
- *              order (half lines by accepted steps, most first).
+ *              checkpoints of 64 bytes per half line of the plane (shared by all half
+ *              lines: room for p->tape_steps accepted steps per half line on
+ *              average; an interior plane adds two per potential half line of its
+ *              rotated-S0 job), per-half adjoints, node gradients, replay buffers
+ *              and the reverse pass's queue order (half lines by accepted steps, most
+ *              first).
  * The lines are traced again with the lane state kept every `segment` accepted
  * steps; each segment is then replayed from its checkpoint with the same stepping
  * code and its accepted steps are differentiated last to first (the discrete

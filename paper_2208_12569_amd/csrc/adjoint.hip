@@ -147,7 +147,16 @@ __device__ __forceinline__ void axis_adj(int rule, const Line &c, const Nb &m, c
     }
 }
 
-// S1 / S2 end adjoints of line l -> the half records
+// S1 / S2 end adjoints of line l (of a job of nlines lines) -> the half records
+__device__ __forceinline__ void push_line_n(int64_t nlines, int64_t l, bool swapped, const LineAdj &a,
+                                            double *lam_end)
+{
+    const int64_t hb = l, hf = nlines + l;
+    const int64_t s1 = swapped ? hf : hb, s2 = swapped ? hb : hf;
+    add3(lam_end + 3 * s1, a.e1);
+    add3(lam_end + 3 * s2, a.e2);
+}
+
 __device__ __forceinline__ void push_line(const MapJob &m, int64_t l, bool swapped, const LineAdj &a,
                                           double *lam_end)
 {
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
                                     const double *__restrict__ dtw,
                                     const double *__restrict__ dend_b,
                                     const double *__restrict__ dend_f, double *lam_end,
-                                    double *lam_tw, double *gnode)
+                                    double *lam_tw, double *gnode, int64_t nhalf0)
 {
     const int64_t np = m.nu * m.nv;
     const int64_t nn = (int64_t)m.n[0] * m.n[1] * m.n[2];
@@ -201,12 +210,21 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
         if (!dq) continue;
         const double gq = dq[pt];
         if (!(gq != 0.0) || !isfinite(gq)) continue;
-        const bool hxm = i > 0, hxp = i < m.nu - 1, hym = j > 0, hyp = j < m.nv - 1;
+        // a rotated S0 (Section 4): the four lines seeded at r0 -+ delta U, r0 -+ delta V
+        // of the rotated-S0 job stand in for the neighbours, central differences over
+        // delta, and |B0| for Bn0
+        const int32_t ri = m.rot_index ? m.rot_index[pt] : -1;
+        if (ri == -2) continue;  // no Q there
+        const bool rot = ri >= 0;
+        const int64_t r4 = 4 * (int64_t)(rot ? ri : 0);
+        const bool hxm = rot || i > 0, hxp = rot || i < m.nu - 1, hym = rot || j > 0,
+                   hyp = rot || j < m.nv - 1;
         // a missing neighbour reads the centre's own record (never used)
-        const Nb xm = read_nb(m, m.rec, m.nlines, hxm ? pt - 1 : pt);
-        const Nb xp = read_nb(m, m.rec, m.nlines, hxp ? pt + 1 : pt);
-        const Nb ym = read_nb(m, m.rec, m.nlines, hym ? pt - m.nu : pt);
-        const Nb yp = read_nb(m, m.rec, m.nlines, hyp ? pt + m.nu : pt);
+        const Nb xm = rot ? read_nb(m, m.rot_rec, m.rot_nlines, r4 + 0) : read_nb(m, m.rec, m.nlines, hxm ? pt - 1 : pt);
+        const Nb xp = rot ? read_nb(m, m.rot_rec, m.rot_nlines, r4 + 1) : read_nb(m, m.rec, m.nlines, hxp ? pt + 1 : pt);
+        const Nb ym = rot ? read_nb(m, m.rot_rec, m.rot_nlines, r4 + 2) : read_nb(m, m.rec, m.nlines, hym ? pt - m.nu : pt);
+        const Nb yp = rot ? read_nb(m, m.rot_rec, m.rot_nlines, r4 + 3) : read_nb(m, m.rec, m.nlines, hyp ? pt + m.nu : pt);
+        const double dx = rot ? m.rot_delta : m.d0, dy = rot ? m.rot_delta : m.d1;
         const int rx = axis_rule(c, xm, hxm, xp, hxp), ry = axis_rule(c, ym, hym, yp, hyp);
         if (rx == RULE_NONE || ry == RULE_NONE) continue;  // Q = NaN there
         uint16_t st = 0;
@@ -214,8 +232,8 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
         inface(c.f1, c.e1, c1);
         inface(c.f2, c.e2, c2);
         double ax1[2], ax2[2], ay1[2], ay2[2];
-        axis_diff(rx, c1, c2, xm, xp, m.d0, ax1, ax2, st);
-        axis_diff(ry, c1, c2, ym, yp, m.d1, ay1, ay2, st);
+        axis_diff(rx, c1, c2, xm, xp, dx, ax1, ax2, st);
+        axis_diff(ry, c1, c2, ym, yp, dy, ay1, ay2, st);
         const double j00 = ax1[0], j01 = ay1[0], j10 = ax1[1], j11 = ay1[1];
         const double k00 = ax2[0], k01 = ay2[0], k10 = ax2[1], k11 = ay2[1];
         const double m00 = k00 * j11 - k01 * j10;
@@ -227,7 +245,8 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
         field64(m, r0, B0);
         field64(m, c.e1, B1);
         field64(m, c.e2, B2);
-        const double bn0 = B0[0] * m.normal[0] + B0[1] * m.normal[1] + B0[2] * m.normal[2];
+        const double bn0 = rot ? sqrt(B0[0] * B0[0] + B0[1] * B0[1] + B0[2] * B0[2])
+                               : B0[0] * m.normal[0] + B0[1] * m.normal[1] + B0[2] * m.normal[2];
         const int a1 = c.f1 >> 1, a2 = c.f2 >> 1;
         const double bn1 = comp3(B1, a1), bn2 = comp3(B2, a2);
         const double nrm = m00 * m00 + m01 * m01 + m10 * m10 + m11 * m11;
@@ -244,23 +263,35 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
         LineAdj ca = {}, xma = {}, xpa = {}, yma = {}, ypa = {};
         {
             const double d1b[2] = {jb00, jb10}, d2b[2] = {kb00, kb10};
-            axis_adj(rx, c, xm, xp, m.d0, d1b, d2b, ca, xma, xpa);
+            axis_adj(rx, c, xm, xp, dx, d1b, d2b, ca, xma, xpa);
         }
         {
             const double d1b[2] = {jb01, jb11}, d2b[2] = {kb01, kb11};
-            axis_adj(ry, c, ym, yp, m.d1, d1b, d2b, ca, yma, ypa);
+            axis_adj(ry, c, ym, yp, dy, d1b, d2b, ca, yma, ypa);
         }
         // the normal fields: Q ~ |Bn1 Bn2| / Bn0^2
         bn_adj(m, c.e1, a1, gq * Q / bn1, ca.e1, gnode, nn);
         bn_adj(m, c.e2, a2, gq * Q / bn2, ca.e2, gnode, nn);
         const double gb0 = -2.0 * gq * Q / bn0;
-        for (int comp = 0; comp < 3; comp++)
-            if (m.normal[comp] != 0.0) bn_adj(m, r0, comp, gb0 * m.normal[comp], nullptr, gnode, nn);
+        // Bn0 = n.B0, or |B0| on a rotated S0 (d|B0| / dB0 = B0 / |B0|)
+        for (int comp = 0; comp < 3; comp++) {
+            const double w = rot ? B0[comp] / bn0 : m.normal[comp];
+            if (w != 0.0) bn_adj(m, r0, comp, gb0 * w, nullptr, gnode, nn);
+        }
         push_line(m, pt, c.swapped, ca, lam_end);
-        if (rx != RULE_PLUS) push_line(m, pt - 1, xm.swapped, xma, lam_end);
-        if (rx != RULE_MINUS) push_line(m, pt + 1, xp.swapped, xpa, lam_end);
-        if (ry != RULE_PLUS) push_line(m, pt - m.nu, ym.swapped, yma, lam_end);
-        if (ry != RULE_MINUS) push_line(m, pt + m.nu, yp.swapped, ypa, lam_end);
+        if (rot) {
+            // the rotated-S0 job's records follow the plane's in the adjoint arrays
+            double *lr = lam_end + 3 * nhalf0;
+            push_line_n(m.rot_nlines, r4 + 0, xm.swapped, xma, lr);
+            push_line_n(m.rot_nlines, r4 + 1, xp.swapped, xpa, lr);
+            push_line_n(m.rot_nlines, r4 + 2, ym.swapped, yma, lr);
+            push_line_n(m.rot_nlines, r4 + 3, yp.swapped, ypa, lr);
+        } else {
+            if (rx != RULE_PLUS) push_line(m, pt - 1, xm.swapped, xma, lam_end);
+            if (rx != RULE_MINUS) push_line(m, pt + 1, xp.swapped, xpa, lam_end);
+            if (ry != RULE_PLUS) push_line(m, pt - m.nu, ym.swapped, yma, lam_end);
+            if (ry != RULE_MINUS) push_line(m, pt + m.nu, yp.swapped, ypa, lam_end);
+        }
     }
 }
 
@@ -534,7 +565,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
     int64_t h = -1;       // the lane's half line, -1 = none
     bool drained = false; // the queue is empty
     T lam[3] = {T(0), T(0), T(0)}, ltw = T(0), sgn = T(1);
-    int endax = -1, ckslot = -1, next = -1, ck = -1, nck = 0, nacc = 0;
+    int endax = -1, ckslot = -1, next = -1, ck = -1, nck = 0, nacc = 0, rj = 0;
     bool bad = false;
     for (;;) {
         while (h < 0 && !drained) {
@@ -545,16 +576,21 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
             }
             // long half lines first: they set the end of the launch
             const int64_t hh = bp.order ? (int64_t)bp.order[hq] : (int64_t)hq;
+            // the half's own job (a rotated-S0 job's halves follow the plane's) and
+            // its record there
+            rj = hh >= bp.nhalf0 ? 1 : 0;
+            const TraceJob &Jh = jobs[rj];
+            const int64_t lh = hh - (rj ? bp.nhalf0 : 0);
             // in physical units here; in local units (times the end cell's widths) once
             // the replay of the last segment has found that cell
             for (int a = 0; a < 3; a++) lam[a] = (T)bp.lam_end[3 * hh + a];
             // the end lies on its box face: only its in-face coordinates can move
-            const int fe = J.rec.face[hh];
+            const int fe = Jh.rec.face[lh];
             if (fe >= 0) lam[fe >> 1] = T(0);
             endax = fe >= 0 ? (fe >> 1) : -1;
             ltw = TW ? (T)bp.lam_tw[hh] : T(0);
             if (lam[0] == T(0) && lam[1] == T(0) && lam[2] == T(0) && ltw == T(0)) continue;
-            const uint16_t st = J.rec.st[hh];
+            const uint16_t st = Jh.rec.st[lh];
             nck = bp.tape_n[hh];
             nacc = bp.tape_acc[hh];
             if (st & kFatal) {
@@ -562,7 +598,7 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                 continue;
             }
             if (nck <= 0 || nacc <= 0) continue;  // no step taken (a seed on its exit face)
-            sgn = hh >= J.nlines ? T(1) : T(-1);
+            sgn = lh >= Jh.nlines ? T(1) : T(-1);
             n_half++;
             bad = false;
             ckslot = bp.tape_last[hh];
@@ -651,6 +687,14 @@ __global__ __launch_bounds__(64) void trace_backward_kernel(const TraceJob *__re
                     n_steps++;
                 }
                 if (cc0 >= 0) flush_cell<T, TW>(bp.gnode, nn, K.nx, K.ny, cc0, cc1, cc2, gB, gJ);
+                if (ck == 0 && rj == 1 && bp.lam_seed) {
+                    // a rotated-S0 line's adjoint at its seed, which depends on B0 (its
+                    // offset along U or V): local units -> physical
+                    const int64_t lh = h - bp.nhalf0;
+                    const int cs[3] = {cp.c0, cp.c1, cp.c2};
+                    for (int a = 0; a < 3; a++)
+                        bp.lam_seed[3 * lh + a] = (double)lam[a] * (str ? J.iw[a][cs[a]] : 1.0 / J.spacing[a]);
+                }
                 next = ckslot;
                 ckslot = cp.prev;
                 ck--;
@@ -748,14 +792,92 @@ __global__ void grad_planes_kernel(int nx, int ny, int nz, double ihx, double ih
 
 hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *dtw,
                                const double *dend_b, const double *dend_f, double *lam_end,
-                               double *lam_tw, double *gnode, hipStream_t s)
+                               double *lam_tw, double *gnode, int64_t nhalf0, hipStream_t s)
 {
     const int64_t np = m.nu * m.nv;
     int64_t b = (np + 255) / 256;
     if (b < 1) b = 1;
     if (b > 65536) b = 65536;
     hipLaunchKernelGGL(map_backward_kernel, dim3((unsigned)b), dim3(256), 0, s, m, dq, dtw, dend_b,
-                       dend_f, lam_end, lam_tw, gnode);
+                       dend_f, lam_end, lam_tw, gnode, nhalf0);
+    return hipGetLastError();
+}
+
+namespace {
+// A rotated S0's four lines start at r0 -+ delta U and r0 -+ delta V, with U the
+// normalised e_a x b (e_a the axis least aligned with b = B0/|B0|, held fixed) and
+// V = b x U: their seed adjoints (both halves of each line) give dL/dU and dL/dV,
+// taken back through V = b x U, U = w/|w|, w = e_a x b and b = B0/|B0| to dL/dB0,
+// which goes to the nodes by the FP64 trilinear weights at r0.
+__global__ void rot_seed_kernel(MapJob m, const RotEntry *__restrict__ rot,
+                                const uint32_t *__restrict__ rot_count, int64_t cap,
+                                const double *__restrict__ lam_seed, double *gnode)
+{
+    const int64_t nn = (int64_t)m.n[0] * m.n[1] * m.n[2];
+    int64_t cnt = (int64_t)*rot_count;
+    if (cnt > cap) cnt = cap;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const RotEntry E = rot[e];
+        double lk[4][3];
+        for (int k = 0; k < 4; k++) {
+            const int64_t line = 4 * e + k;
+            for (int a = 0; a < 3; a++)
+                lk[k][a] = lam_seed[3 * line + a] + lam_seed[3 * (m.rot_nlines + line) + a];
+        }
+        double gU[3], gV[3];
+        for (int a = 0; a < 3; a++) {
+            gU[a] = m.rot_delta * (lk[1][a] - lk[0][a]);
+            gV[a] = m.rot_delta * (lk[3][a] - lk[2][a]);
+        }
+        if (gU[0] == 0.0 && gU[1] == 0.0 && gU[2] == 0.0 && gV[0] == 0.0 && gV[1] == 0.0 && gV[2] == 0.0)
+            continue;
+        double B[3];
+        field64(m, E.r0, B);
+        const double bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+        const double b[3] = {B[0] / bm, B[1] / bm, B[2] / bm};
+        int ax = 0;
+        if (fabs(b[1]) < fabs(b[ax])) ax = 1;
+        if (fabs(b[2]) < fabs(b[ax])) ax = 2;
+        const double *U = E.U;
+        // V = b x U: dL/db += U x gV, dL/dU += gV x b
+        double gb[3] = {U[1] * gV[2] - U[2] * gV[1], U[2] * gV[0] - U[0] * gV[2], U[0] * gV[1] - U[1] * gV[0]};
+        const double gu[3] = {gU[0] + gV[1] * b[2] - gV[2] * b[1], gU[1] + gV[2] * b[0] - gV[0] * b[2],
+                              gU[2] + gV[0] * b[1] - gV[1] * b[0]};
+        // U = w / |w|, w = e_ax x b
+        double w[3] = {0.0, 0.0, 0.0};
+        if (ax == 0) w[1] = -b[2], w[2] = b[1];
+        else if (ax == 1) w[0] = b[2], w[2] = -b[0];
+        else w[0] = -b[1], w[1] = b[0];
+        const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        const double uu = U[0] * gu[0] + U[1] * gu[1] + U[2] * gu[2];
+        double gw[3];
+        for (int a = 0; a < 3; a++) gw[a] = (gu[a] - U[a] * uu) / wn;
+        // w = e_ax x b: dL/db += gw x e_ax
+        if (ax == 0) gb[1] += gw[2], gb[2] -= gw[1];
+        else if (ax == 1) gb[0] -= gw[2], gb[2] += gw[0];
+        else gb[0] += gw[1], gb[1] -= gw[0];
+        // b = B0 / |B0|
+        const double bb = b[0] * gb[0] + b[1] * gb[1] + b[2] * gb[2];
+        Tri t;
+        tri_of(m, E.r0, t);
+        for (int c = 0; c < 3; c++) {
+            const double gB = (gb[c] - b[c] * bb) / bm;
+            if (gB == 0.0) continue;
+            for (int q = 0; q < 8; q++) atomicAdd(gnode + c * nn + t.node[q], gB * t.w[q]);
+        }
+    }
+}
+}  // namespace
+
+hipError_t launch_rot_seed(const MapJob &m, const RotEntry *rot, const uint32_t *rot_count,
+                           int64_t cap, const double *lam_seed, double *gnode, hipStream_t s)
+{
+    int64_t b = (cap + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(rot_seed_kernel, dim3((unsigned)b), dim3(256), 0, s, m, rot, rot_count, cap,
+                       lam_seed, gnode);
     return hipGetLastError();
 }
 

@@ -359,11 +359,14 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     }
     // adjoint: checkpoints, per-half adjoints, node gradients and replay buffers
     size_t off_tape = 0, off_tl = 0, off_tn = 0, off_ta = 0, off_lam = 0, off_ltw = 0, off_gnode = 0;
-    size_t off_buf = 0, off_bkey = 0, off_border = 0, off_bcnt = 0;
+    size_t off_buf = 0, off_bkey = 0, off_border = 0, off_bcnt = 0, off_lseed = 0;
     int64_t bwd_halves = 0, bwd_nodes = 0;
     if (bwd) {
-        if (ns != 1 || nrot != 0 || specs[0].kind != SPEC_PLANE) return FQ_EUNSUPPORTED;
-        bwd_halves = 2 * W[0].nlines;
+        // one seed plane; an interior one adds its rotated-S0 job (up to four lines per
+        // point), whose half lines follow the plane's
+        if (ns != 1 || nrot > 1 || specs[0].kind != SPEC_PLANE) return FQ_EUNSUPPORTED;
+        if (W[0].rotate && P.scheme != FQ_SCHEME_RKF45) return FQ_EUNSUPPORTED;
+        bwd_halves = 2 * W[0].nlines + (W[0].rotate ? 2 * 4 * W[0].nlines : 0);
         bwd_nodes = nodes_of(specs[0].f);
         off_tape = cv.take((size_t)bwd->pool * sizeof(Ckpt));
         off_tl = cv.take((size_t)bwd_halves * sizeof(int32_t));
@@ -375,6 +378,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         off_buf = cv.take((size_t)kBwdSlots * (size_t)bwd->seg * sizeof(StepRec));
         off_bkey = cv.take((size_t)bwd_halves * sizeof(int32_t));
         off_border = cv.take((size_t)bwd_halves * sizeof(int32_t));
+        if (W[0].rotate) off_lseed = cv.take((size_t)2 * 4 * W[0].nlines * 3 * sizeof(double));
         off_bcnt = cv.take(256 * sizeof(uint32_t));
     }
     if (need) *need = cv.off;
@@ -431,8 +435,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             m.rot_rec = recs_at(ws, w.r_end, w.r_tw, w.r_len, w.r_face, w.r_st);
             m.rot_nlines = 4 * w.nlines;
             m.rot_delta = fmin(m.d0, m.d1);
-            FQ_TRY(launch_classify(m, (int32_t *)(ws + w.rot_index), (RotEntry *)(ws + w.rot),
-                                   (uint32_t *)(ws + w.rot_count), w.nlines, stream));
+            // (the reverse of a recorded forward pass reads the classification it left)
+            if (fwd)
+                FQ_TRY(launch_classify(m, (int32_t *)(ws + w.rot_index), (RotEntry *)(ws + w.rot),
+                                       (uint32_t *)(ws + w.rot_count), w.nlines, stream));
         }
     }
     // job table
@@ -596,6 +602,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         tp.tape_acc = (int32_t *)(ws + off_ta);
         tp.seg = bwd->seg;
         tp.pool_cap = bwd->pool;
+        tp.tape_base1 = 2 * W[0].nlines;
         if (fwd) FQ_TRY(launch_fill_u32((uint32_t *)(ws + off_ctr + 128), 2, 0u, stream));
     }
     hipEvent_t *ev = fwd ? (hipEvent_t *)P.events : nullptr;
@@ -685,7 +692,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         FQ_TRY(launch_fill_u32((uint32_t *)lam_tw, bwd_halves * 2, 0u, stream));
         FQ_TRY(launch_fill_u32((uint32_t *)gnode, bwd_nodes * (P.want_tw ? 12 : 6), 0u, stream));
         FQ_TRY(launch_map_backward(maps[0], bwd->dq, P.want_tw ? bwd->dtw : nullptr, bwd->dend_b,
-                                   bwd->dend_f, lam_end, lam_tw, gnode, stream));
+                                   bwd->dend_f, lam_end, lam_tw, gnode, 2 * W[0].nlines, stream));
         unsigned long long *bctr = (unsigned long long *)(ws + off_ctr + 64);
         FQ_TRY(launch_fill_u32((uint32_t *)bctr, 2, 0u, stream));
         BwdParams bp;
@@ -696,6 +703,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         bp.tape_acc = tp.tape_acc;
         bp.seg = tp.seg;
         bp.nhalves = bwd_halves;
+        bp.nhalf0 = 2 * W[0].nlines;
+        double *lseed = W[0].rotate ? (double *)(ws + off_lseed) : nullptr;
+        if (lseed) FQ_TRY(launch_fill_u32((uint32_t *)lseed, 2 * 4 * W[0].nlines * 6, 0u, stream));
+        bp.lam_seed = lseed;
         bp.lam_end = lam_end;
         bp.lam_tw = lam_tw;
         bp.gnode = gnode;
@@ -714,6 +725,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         // records and FP64 steps, or the F32X form's FP32 records and FP32 pass
         FQ_TRY(launch_trace_backward(P.precision == FQ_PREC_F64 ? FQ_DT_F64 : FQ_DT_F32, P.want_tw,
                                      jobs_dev, bp, stream));
+        if (lseed)
+            FQ_TRY(launch_rot_seed(maps[0], (const RotEntry *)(ws + W[0].rot),
+                                   (const uint32_t *)(ws + W[0].rot_count), W[0].nlines, lseed, gnode,
+                                   stream));
         FQ_TRY(launch_grad_planes(*specs[0].f, gnode, P.want_tw, bwd->gb, stream));
         return FQ_OK;
     }
@@ -778,16 +793,18 @@ int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int seg
     if (P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
     if (segment < 1 || segment > 4096) return FQ_EINVAL;
-    if (!plane_on_face(*pl, *f)) return FQ_EUNSUPPORTED;
     if (P.max_steps > INT32_MAX) return FQ_EINVAL;
     if ((rc = q2d_specs(f, pl, 1, nullptr, v))) return rc;
     memset(&b, 0, sizeof b);
     b.seg = segment;
-    // checkpoint pool: room for tape_steps accepted steps per half line on average
-    // (plus the first checkpoint and a partial segment)
+    // checkpoint pool: room for tape_steps accepted steps per half line of the plane on
+    // average (plus the first checkpoint and a partial segment), and on an interior
+    // plane those two for each potential half line of its rotated-S0 job (its lines,
+    // where a point has them, share the plane's average)
     const int64_t halves = 2 * pl->nu * pl->nv;
     if (P.tape_steps > ((int64_t)1 << 40)) return FQ_EINVAL;
     b.pool = halves * (2 + (P.tape_steps + segment - 1) / segment);
+    if (!plane_on_face(*pl, *f)) b.pool += 4 * halves * 2;
     if (b.pool > INT32_MAX) return FQ_EINVAL;
     return FQ_OK;
 }

@@ -146,6 +146,7 @@ struct TraceParams {
     int32_t seg;
     int32_t pad2;
     int64_t pool_cap;
+    int64_t tape_base1;            // first record of job 1 (a rotated-S0 job) in tape_*
     // per-XCD queues (multi-job kernels, not list mode): when set, 8 counters 64 bytes
     // apart, one per range of the queue split in 8 contiguous ranges of whole tiles
     unsigned long long *xcd_ctr;
@@ -168,6 +169,11 @@ struct BwdParams {
     int64_t max_steps;
     int32_t want_tw;
     int32_t scheme;                // Scheme of the forward pass (trace_core.h)
+    // an interior seed plane: jobs[1] is its rotated-S0 job, whose half lines follow
+    // the plane's nhalf0 ones; the adjoint at each of their seeds goes to lam_seed
+    // (3 per half of the rotated job, physical units)
+    int64_t nhalf0;
+    double *lam_seed;
 };
 
 // Host-side launchers, one per translation unit.
@@ -245,7 +251,9 @@ struct MapJob {
 // Adjoint (adjoint.hip).
 hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *dtw,
                                const double *dend_b, const double *dend_f, double *lam_end,
-                               double *lam_tw, double *gnode, hipStream_t s);
+                               double *lam_tw, double *gnode, int64_t nhalf0, hipStream_t s);
+hipError_t launch_rot_seed(const MapJob &m, const RotEntry *rot, const uint32_t *rot_count,
+                           int64_t cap, const double *lam_seed, double *gnode, hipStream_t s);
 // Queue order of the reverse kernel: half lines by their accepted steps, most first
 // (key, counts, order: workspace of nhalves, 256 and nhalves entries).
 hipError_t launch_bwd_order(const int32_t *tape_acc, int64_t nhalves, int32_t *key,

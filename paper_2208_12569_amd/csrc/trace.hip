@@ -494,9 +494,12 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
                 }
             }
             if (TAPE) {
-                gptr(tp.tape_last)[rec] = last_ck;
-                gptr(tp.tape_n)[rec] = nck;
-                gptr(tp.tape_acc)[rec] = acc_half;
+                // an interior seed plane's rotated-S0 job keeps its records after the
+                // main job's
+                const int64_t trec = rec + (jb > 0 ? tp.tape_base1 : 0);
+                gptr(tp.tape_last)[trec] = last_ck;
+                gptr(tp.tape_n)[trec] = nck;
+                gptr(tp.tape_acc)[trec] = acc_half;
             }
             jb = -1;
             need_load = false;
@@ -1013,15 +1016,23 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     const bool uni = tp.njobs == 1 && !tp.dynamic_last && !tp.stretched && !tp.cyl;
     if (tp.scheme < SCH_RKF45 || tp.scheme > SCH_RK4_38) return hipErrorInvalidValue;
     if (tp.tape) {
-        // the adjoint's forward pass: one job, no FP64 re-trace list, Method I; FP64
-        // on FP64 records, or the FP32 pass of the F32X form
-        // (its single-job kernels carry the stretched-grid lane state)
-        if (tp.njobs != 1 || tp.dynamic_last || tp.cyl || tp.list || tp.seg < 1 ||
-            tp.method != FQ_METHOD_I || f64 != s64)
+        // the adjoint's forward pass, Method I, no FP64 re-trace list; FP64 on FP64
+        // records, or the FP32 pass of the F32X form. One job (the single-job kernels,
+        // which carry the stretched-grid lane state for it), or a seed plane and its
+        // rotated-S0 job (the multi-job kernels, RKF45).
+        const bool one = tp.njobs == 1 && !tp.dynamic_last;
+        const bool two = tp.njobs == 2 && tp.dynamic_last && tp.scheme == SCH_RKF45;
+        if (!(one || two) || tp.cyl || tp.list || tp.seg < 1 || tp.method != FQ_METHOD_I || f64 != s64)
             return hipErrorInvalidValue;
         const dim3 grid((unsigned)(2 * ncu)), blk(256);
-        if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
-        else launch_ts<float, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
+        if (one) {
+            if (s64) launch_ts<double, double, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
+            else launch_ts<float, float, true, true>(twm, grid, blk, s, jobs_dev, tp, counter);
+        } else if (s64) {
+            launch_tss<double, double, false, true, SCH_RKF45>(twm, grid, blk, s, jobs_dev, tp, counter);
+        } else {
+            launch_tss<float, float, false, true, SCH_RKF45>(twm, grid, blk, s, jobs_dev, tp, counter);
+        }
         return hipGetLastError();
     }
     const void *fn;

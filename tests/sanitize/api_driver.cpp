@@ -205,7 +205,17 @@ int main()
                 CHECK(fastqsl_q2d_record(&f[0], &pl[0], &P, 32, m, ws, need, nullptr) == FQ_OK);
                 CHECK(fastqsl_backward_recorded(&f[0], &pl[0], &P, 32, g_dummy, nullptr, nullptr,
                                                 nullptr, gb, ws, need, nullptr) == FQ_OK);
-                CHECK(fastqsl_backward_workspace_size(&f[0], &mid, &P, 32) == 0);
+                // an interior plane: its rotated-S0 job's lines are differentiated too
+                const size_t nmid = fastqsl_backward_workspace_size(&f[0], &mid, &P, 32);
+                CHECK(nmid > 0);
+                CHECK(fastqsl_backward(&f[0], &mid, &P, 32, g_dummy, g_dummy, nullptr, nullptr, gb,
+                                       workspace(nmid), nmid, nullptr) == FQ_OK);
+                CHECK(fastqsl_q2d_record(&f[0], &mid, &P, 32, m, workspace(nmid), nmid, nullptr) == FQ_OK);
+                CHECK(fastqsl_backward_recorded(&f[0], &mid, &P, 32, g_dummy, nullptr, nullptr, nullptr,
+                                                gb, workspace(nmid), nmid, nullptr) == FQ_OK);
+                fq_params P7 = P;
+                P7.scheme = FQ_SCHEME_RK4;  // an interior plane's adjoint takes RKF45 only
+                CHECK(fastqsl_backward_workspace_size(&f[0], &mid, &P7, 32) == 0);
                 CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P, 0) == 0);
                 // stretched grids have an adjoint too
                 fq_field fst = f[0];

@@ -104,10 +104,21 @@ hipError_t launch_graze(const TraceJob *jobs, int job, int64_t, double, const do
 }
 hipError_t launch_map_backward(const MapJob &m, const double *, const double *, const double *,
                                const double *, double *lam_end, double *lam_tw, double *gnode,
-                               hipStream_t)
+                               int64_t nhalf0, hipStream_t)
 {
-    in_ws(lam_end, (size_t)(2 * m.nlines) * 24, "end adjoints");
-    in_ws(lam_tw, (size_t)(2 * m.nlines) * 8, "twist adjoints");
+    const size_t halves = (size_t)(nhalf0 + (m.rot_index ? 2 * m.rot_nlines : 0));
+    in_ws(lam_end, halves * 24, "end adjoints");
+    in_ws(lam_tw, halves * 8, "twist adjoints");
+    in_ws(gnode, (size_t)(m.n[0] * m.n[1] * m.n[2]) * 24, "node gradients");
+    g_calls++;
+    return hipSuccess;
+}
+hipError_t launch_rot_seed(const MapJob &m, const RotEntry *rot, const uint32_t *rot_count, int64_t cap,
+                           const double *lam_seed, double *gnode, hipStream_t)
+{
+    in_ws(rot, (size_t)cap * sizeof(RotEntry), "rotated-S0 entries");
+    in_ws(rot_count, 4, "rotated-S0 count");
+    in_ws(lam_seed, (size_t)(2 * m.rot_nlines) * 24, "seed adjoints");
     in_ws(gnode, (size_t)(m.n[0] * m.n[1] * m.n[2]) * 24, "node gradients");
     g_calls++;
     return hipSuccess;

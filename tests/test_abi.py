@@ -179,9 +179,9 @@ def test_python_layer_fails_loudly_without_gpu():
 
 
 def test_backward_workspace_query(lib):
-    """The adjoint is taken on a seed plane on a box face, in either precision form
-    and with Method I only; its workspace holds a pool of 2 + ceil(2048/segment)
-    checkpoints of 64 bytes per half line."""
+    """The adjoint is taken on a seed plane (on a box face or interior), in either
+    precision form and with Method I only; its workspace holds a pool of 2 +
+    ceil(2048/segment) checkpoints of 64 bytes per half line."""
     from paper_2208_12569_amd import _lib
 
     f = _fake_field()
@@ -196,9 +196,10 @@ def test_backward_workspace_query(lib):
     p.precision = _lib.FQ_PREC_F64
     for seg in (0, -1, 5000):
         assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), seg) == 0
-    inner = _plane(nu=64, z=0.5)
-    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(inner), C.byref(p), 32) == 0
     n32 = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), 32)
+    # an interior plane also holds its rotated-S0 job's half lines (four lines per point)
+    inner = _plane(nu=64, z=0.5)
+    assert lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(inner), C.byref(p), 32) > n32
     halves = 2 * 64 * 64
     slots = 32768  # lanes of the reverse kernel, each with `segment` 48-byte step records
     assert n32 >= halves * (2048 // 32 + 2) * 64 + slots * 32 * 48

@@ -18,6 +18,8 @@ import oracle
 import synth
 from synth import Plane, cubic_grid, linear_field
 
+from gpu_util import to_np
+
 pytestmark = pytest.mark.gpu
 
 F64 = 1
@@ -470,6 +472,77 @@ def test_stretched_grid_adjoint(fq):
         fd = (loss(bp_) - loss(bm_)) / (2 * h)
         errs.append(abs(g_nodes.ravel()[n] - fd) / max(abs(fd), 1e-2 * flat.max()))
     print("stretched node gradients: max rel err", max(errs))
+    assert max(errs) < 1e-4, errs
+
+
+def test_interior_plane_adjoint(fq):
+    """An interior seed plane, whose points with |Bn0/B| < 0.05 turn S0 perpendicular
+    to B (Section 4) and take their Q from four extra lines seeded at r0 -+ delta U,
+    r0 -+ delta V: their ends, |B0| and, through U and V, the seeds' dependence on B0
+    are differentiated too. B = (1, 0.3, s (y - y0)) on the plane z = 0.5 (x faces as
+    S1, S2) has Q = 2 + s^2 at every point, rotated or not: dQ/ds = 2 s point by
+    point. On a charge cube the node gradient of a Q loss over an interior plane with
+    rotated points matches central differences of the GPU forward."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    s, y0 = 0.5, 0.4
+    B = _dev(linear_field(g, [[0, 0, 0], [0, 0, 0], [0, s, 0]], [1.0, 0.3, -s * y0]))
+    pl = Plane((0.3, y0 - 0.16, 0.5), (1, 0, 0), (0, 1, 0), 9, 9, 0.02, 0.04)
+    yy = np.asarray(g.axes()[1])[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[2] = np.broadcast_to(yy - y0, g.shape)
+    r = fq.q2d(B, g, pl, fq.Params(precision=F64, tol_perp=TOL))
+    st = to_np(r["status"]).astype(np.int64)
+    rot = (st & fq.ST_ROTATED) != 0
+    assert rot[1:-1, 1:-1].sum() >= 10 and (~rot[1:-1, 1:-1]).sum() >= 10
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    for pt in [p for p in range(81) if 0 < p % 9 < 8 and 0 < p // 9 < 8]:
+        _say(f"interior plane: dQ/ds at point {pt} (rotated S0: {bool(rot.ravel()[pt])})")
+        dq = torch.zeros(81, dtype=torch.float64, device="cuda")
+        dq[pt] = 1.0
+        g1 = float((_grad(fq, B, g, pl, stats, dq=dq) * dBds).sum())
+        assert abs(g1 - 2 * s) < 1e-6, (pt, bool(rot.ravel()[pt]), g1)
+    st5 = stats.tolist()
+    assert st5[2] == 0 and st5[3] == 0, st5
+
+    _say("interior plane: charge cube, node values against central differences")
+    gc = cubic_grid(33, 33, 33)
+    pos, q = synth.draw_charges(np.random.default_rng(21), 5)
+    B0 = synth.charges_field(gc, pos, q)
+    plc = Plane((0.2, 0.2, 0.4), (1, 0, 0), (0, 1, 0), 20, 20, 0.6 / 19, 0.6 / 19)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    r = fq.q2d(_dev(B0), gc, plc, p)
+    mask = _fd_mask(fq, r)
+    st = r["status"].to(torch.int32)
+    nrot = int((((st & fq.ST_ROTATED) != 0) & mask).sum())
+    print("interior charge plane: rotated points in the loss", nrot, "of", int(mask.sum()))
+    assert nrot >= 3
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    wq = torch.randn((20, 20), generator=gen, device="cuda", dtype=torch.float64) * mask
+
+    def loss(Bn):
+        rr = fq.q2d(_dev(Bn), gc, plc, p)
+        qq = torch.where(mask, rr["q"], torch.ones_like(rr["q"]))
+        return float((wq * torch.log10(qq)).sum())
+
+    qq = torch.where(mask, r["q"], torch.ones_like(r["q"]))
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    g_nodes = _grad(fq, _dev(B0), gc, plc, stats, dq=(wq / (qq * math.log(10.0))).reshape(-1))
+    assert stats.tolist()[2] == 0
+    flat = np.abs(g_nodes).ravel()
+    rng = np.random.default_rng(8)
+    nodes = np.concatenate([np.argsort(flat)[-16:], rng.choice(np.flatnonzero(flat > 1e-3 * flat.max()), 8)])
+    errs = []
+    for n in nodes:
+        v = float(B0.ravel()[n])
+        h = 1e-5 * max(abs(v), 1e-2)
+        bp_, bm_ = B0.copy(), B0.copy()
+        bp_.ravel()[n] += h
+        bm_.ravel()[n] -= h
+        fd = (loss(bp_) - loss(bm_)) / (2 * h)
+        errs.append(abs(g_nodes.ravel()[n] - fd) / max(abs(fd), 1e-2 * flat.max()))
+    print("interior plane node gradients: max rel err", max(errs))
     assert max(errs) < 1e-4, errs
 
 
