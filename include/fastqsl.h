@@ -331,7 +331,8 @@ int fastqsl_backward(const fq_field *f, const fq_plane *pl, const fq_params *p, 
  * callers that need the map before they know its gradient (a training step: map,
  * loss, then derivative). The lines are traced once.
  *   fastqsl_q2d_record: the checkpointed forward pass of fastqsl_backward, and the
- *     map of fastqsl_q2d (all-FP64 form) written to `map` (as fastqsl_q2d does,
+ *     map of fastqsl_q2d (in the form p->precision picks) written to `map` (the same
+ *     values fastqsl_q2d writes, bit for bit:
  *     Section 2.1 tracing and Method-I Q, Eq. D+-2 / D+-3 / Q+-; Tw of Eq. tw).
  *   fastqsl_backward_recorded: the reverse pass of fastqsl_backward (same argument
  *     meanings), reading the checkpoints and half-line records the record call left
@@ -349,6 +350,39 @@ int fastqsl_backward_recorded(const fq_field *f, const fq_plane *pl, const fq_pa
                               int segment, const double *dq, const double *dtw,
                               const double *dend_b, const double *dend_f, double *const gb[3],
                               void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * fastqsl_q3d_backward, fastqsl_q3d_record, fastqsl_q3d_backward_recorded — the
+ * same three calls for the map of fastqsl_q3d (Section 1, Eq. qline: Q, Tw and
+ * length at voxel centres; Section 4: S0 rotated perpendicular to B where
+ * |Bz/B| < 0.05, the four extra lines and their seeds' dependence on B0
+ * differentiated as on an interior plane).
+ *   f, vx, p   the forward call's inputs; p->method FQ_METHOD_I and p->scheme
+ *              FQ_SCHEME_RKF45, else FQ_EUNSUPPORTED; either precision form; uniform
+ *              or stretched grid.
+ *   segment, dq, dtw, dend_b, dend_f, gb  as for fastqsl_backward, with
+ *              nx*ny*nz voxels in map order (x fastest, then y, then z).
+ *   ws         of fastqsl_q3d_backward_workspace_size() bytes (256-byte aligned):
+ *              the checkpoint pool holds 2 + ceil(p->tape_steps/segment)
+ *              checkpoints per half line of the voxel centres plus two per potential
+ *              half line of the rotated-S0 job, and the rest as for fastqsl_backward.
+ * fastqsl_q3d_record writes the map of fastqsl_q3d (bit for bit) with the
+ * checkpoints; fastqsl_q3d_backward_recorded reverses them. Workspace rules, stats
+ * and errors as for fastqsl_backward and its two-call form. Asynchronous on
+ * `stream`; allocate nothing.
+ * ------------------------------------------------------------------------------- */
+size_t fastqsl_q3d_backward_workspace_size(const fq_field *f, const fq_voxels *vx,
+                                           const fq_params *p, int segment);
+int fastqsl_q3d_backward(const fq_field *f, const fq_voxels *vx, const fq_params *p, int segment,
+                         const double *dq, const double *dtw, const double *dend_b,
+                         const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
+                         void *stream);
+int fastqsl_q3d_record(const fq_field *f, const fq_voxels *vx, const fq_params *p, int segment,
+                       const fq_map *map, void *ws, size_t ws_bytes, void *stream);
+int fastqsl_q3d_backward_recorded(const fq_field *f, const fq_voxels *vx, const fq_params *p,
+                                  int segment, const double *dq, const double *dtw,
+                                  const double *dend_b, const double *dend_f,
+                                  double *const gb[3], void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * fastqsl_q2d_static — fastqsl_q2d for callers that cannot allocate device memory

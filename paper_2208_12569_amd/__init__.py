@@ -403,58 +403,75 @@ def qcyl(B, grid, cyl, params: Optional[Params] = None, want_lines: bool = False
     return m
 
 
-def _bwd_prepare(B, grid, plane, params: Optional[Params], segment: int):
+def _is_voxels(target) -> bool:
+    return hasattr(target, "n") and not hasattr(target, "nu")
+
+
+def _bwd_prepare(B, grid, target, params: Optional[Params], segment: int):
+    """Checks and workspace size of an adjoint call on a seed plane or a voxel map."""
     lib = _lib.load()
     params = params or Params(precision=FQ_PREC_F64)
     f = _field(B, grid)
-    pl = _plane(plane)
     p = params.c()
-    need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(pl), C.byref(p), int(segment))
+    if _is_voxels(target):
+        t = _voxels(target)
+        need = lib.fastqsl_q3d_backward_workspace_size(C.byref(f), C.byref(t), C.byref(p),
+                                                       int(segment))
+    else:
+        t = _plane(target)
+        need = lib.fastqsl_backward_workspace_size(C.byref(f), C.byref(t), C.byref(p), int(segment))
     if need == 0:
-        raise ValueError("invalid or unsupported backward call (Method I, plane on a box face, "
-                         "1 <= segment <= 4096)")
-    return lib, f, pl, p, need
+        raise ValueError("invalid or unsupported backward call (Method I; RKF45 where S0 may "
+                         "rotate; 1 <= segment <= 4096)")
+    return lib, f, t, p, need
 
 
-def _bwd_reverse(name, B, grid, plane, params, segment, dq, dtw, dend_b, dend_f, gb, stream, ws):
+def _npoints(target) -> int:
+    if _is_voxels(target):
+        return math.prod(int(x) for x in target.n)
+    return int(target.nu) * int(target.nv)
+
+
+def _bwd_reverse(name, B, grid, target, params, segment, dq, dtw, dend_b, dend_f, gb, stream, ws):
     torch = _torch()
-    lib, f, pl, p, need = _bwd_prepare(B, grid, plane, params, segment)
+    lib, f, t, p, need = _bwd_prepare(B, grid, target, params, segment)
     if gb is None:
         gb = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
     if gb.dtype != torch.float64 or gb.shape != B.shape or not gb.is_contiguous():
         raise ValueError("gb must be a contiguous float64 tensor shaped like B")
-    npts = plane.nu * plane.nv
+    npts = _npoints(target)
 
-    def arg(t, shape):
-        if t is None:
+    def arg(x, shape):
+        if x is None:
             return None, None
-        t = t.to(device=B.device, dtype=torch.float64).contiguous()
-        if t.numel() != math.prod(shape):
-            raise ValueError(f"gradient of shape {tuple(t.shape)} does not fit {shape}")
-        return t, t.data_ptr()
+        x = x.to(device=B.device, dtype=torch.float64).contiguous()
+        if x.numel() != math.prod(shape):
+            raise ValueError(f"gradient of shape {tuple(x.shape)} does not fit {shape}")
+        return x, x.data_ptr()
 
     dq_t, dq_p = arg(dq, (npts,))
     dtw_t, dtw_p = arg(dtw, (npts,))
     db_t, db_p = arg(dend_b, (npts, 3))
     df_t, df_p = arg(dend_f, (npts, 3))
-    if name == "fastqsl_backward_recorded" and (ws is None or ws.numel() < need):
+    if name.endswith("_recorded") and (ws is None or ws.numel() < need):
         raise ValueError("the record does not belong to these inputs (workspace too small)")
     w = _workspace(need, B.device, ws)
     g3 = (C.c_void_p * 3)(gb[0].data_ptr(), gb[1].data_ptr(), gb[2].data_ptr())
-    _lib.check(getattr(lib, name)(C.byref(f), C.byref(pl), C.byref(p), int(segment), dq_p, dtw_p,
+    _lib.check(getattr(lib, name)(C.byref(f), C.byref(t), C.byref(p), int(segment), dq_p, dtw_p,
                                   db_p, df_p, g3, w.data_ptr(), w.numel(), _stream(stream)), name)
     if stream is not None:
         # temporaries freed here stay reserved until the caller's stream is done
-        for t in (dq_t, dtw_t, db_t, df_t, w):
-            if t is not None:
-                t.record_stream(stream)
+        for x in (dq_t, dtw_t, db_t, df_t, w):
+            if x is not None:
+                x.record_stream(stream)
     return gb
 
 
 def backward(B, grid, plane, params: Optional[Params] = None, segment: int = 32, dq=None, dtw=None,
              dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
     """Reverse-mode derivative of the q2d map of (B, grid, plane) with respect to the
-    field's node values (fastqsl_backward; seed plane on a box face). params.precision
+    field's node values (fastqsl_backward; a seed plane on a box face, or an interior one
+    whose rotated-S0 lines are differentiated too). params.precision
     picks the form differentiated: all-FP64 (the default here), or F32X, whose FP32
     pass is replayed and reversed in FP32.
 
@@ -487,4 +504,37 @@ def backward_recorded(B, grid, plane, rec: dict, params: Optional[Params] = None
     """backward() of a map that q2d_record produced (same B, grid, plane, params and
     segment; rec: its result), without tracing the lines again (fastqsl_backward_recorded)."""
     return _bwd_reverse("fastqsl_backward_recorded", B, grid, plane, params, segment, dq, dtw,
+                        dend_b, dend_f, gb, stream, rec["_ws"])
+
+
+def q3d_backward(B, grid, voxels, params: Optional[Params] = None, segment: int = 32, dq=None,
+                 dtw=None, dend_b=None, dend_f=None, gb=None, stream=None, ws=None):
+    """backward() for the q3d map of (B, grid, voxels) (fastqsl_q3d_backward): dq, dtw
+    hold nx*ny*nz values and dend_b, dend_f nx*ny*nz x 3, in map order (x fastest);
+    the rotated-S0 voxels' extra lines are differentiated too (RKF45 only)."""
+    return _bwd_reverse("fastqsl_q3d_backward", B, grid, voxels, params, segment, dq, dtw, dend_b,
+                        dend_f, gb, stream, ws)
+
+
+def q3d_record(B, grid, voxels, params: Optional[Params] = None, segment: int = 32,
+               want_lines: bool = False, stream=None, ws=None) -> dict:
+    """The q3d map of (B, grid, voxels), traced once with the checkpoints of its
+    derivative kept (fastqsl_q3d_record); "_ws" holds the workspace for
+    q3d_backward_recorded."""
+    lib, f, v, p, need = _bwd_prepare(B, grid, voxels, params, segment)
+    w = _workspace(need, B.device, ws)
+    nx, ny, nz = (int(x) for x in voxels.n)
+    m, s = _alloc_map(nx * ny * nz, (nz, ny, nx), B.device, want_lines)
+    _lib.check(lib.fastqsl_q3d_record(C.byref(f), C.byref(v), C.byref(p), int(segment), C.byref(s),
+                                      w.data_ptr(), w.numel(), _stream(stream)), "fastqsl_q3d_record")
+    m["_ws"] = w
+    return m
+
+
+def q3d_backward_recorded(B, grid, voxels, rec: dict, params: Optional[Params] = None,
+                          segment: int = 32, dq=None, dtw=None, dend_b=None, dend_f=None, gb=None,
+                          stream=None):
+    """q3d_backward() of a map that q3d_record produced, without tracing the lines
+    again (fastqsl_q3d_backward_recorded)."""
+    return _bwd_reverse("fastqsl_q3d_backward_recorded", B, grid, voxels, params, segment, dq, dtw,
                         dend_b, dend_f, gb, stream, rec["_ws"])

@@ -93,6 +93,8 @@ EXPORTS = [
     "fastqsl_qcyl_workspace_size", "fastqsl_qcyl",
     "fastqsl_backward_workspace_size", "fastqsl_backward",
     "fastqsl_q2d_record", "fastqsl_backward_recorded",
+    "fastqsl_q3d_backward_workspace_size", "fastqsl_q3d_backward",
+    "fastqsl_q3d_record", "fastqsl_q3d_backward_recorded",
     "fastqsl_strerror", "fastqsl_version",
     "fastqsl_static_scratch_bytes", "fastqsl_q2d_static",
 ]
@@ -146,6 +148,15 @@ def load():
     lib.fastqsl_q2d_record.restype = C.c_int
     lib.fastqsl_backward_recorded.argtypes = lib.fastqsl_backward.argtypes
     lib.fastqsl_backward_recorded.restype = C.c_int
+    lib.fastqsl_q3d_backward_workspace_size.argtypes = [P(fq_field), P(fq_voxels), P(fq_params),
+                                                        C.c_int]
+    lib.fastqsl_q3d_backward_workspace_size.restype = C.c_size_t
+    lib.fastqsl_q3d_backward.argtypes = [P(fq_field), P(fq_voxels)] + lib.fastqsl_backward.argtypes[2:]
+    lib.fastqsl_q3d_backward.restype = C.c_int
+    lib.fastqsl_q3d_record.argtypes = [P(fq_field), P(fq_voxels)] + lib.fastqsl_q2d_record.argtypes[2:]
+    lib.fastqsl_q3d_record.restype = C.c_int
+    lib.fastqsl_q3d_backward_recorded.argtypes = lib.fastqsl_q3d_backward.argtypes
+    lib.fastqsl_q3d_backward_recorded.restype = C.c_int
     lib.fastqsl_static_scratch_bytes.argtypes = []
     lib.fastqsl_static_scratch_bytes.restype = C.c_size_t
     lib.fastqsl_q2d_static.argtypes = [P(fq_field), P(fq_plane), C.c_int, P(fq_params), P(fq_map),

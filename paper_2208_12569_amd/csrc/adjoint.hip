@@ -185,11 +185,12 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
                                     const double *__restrict__ dend_f, double *lam_end,
                                     double *lam_tw, double *gnode, int64_t nhalf0)
 {
-    const int64_t np = m.nu * m.nv;
+    // a 3-D map's layers each take the plane's stencil, with neighbours in the layer
+    const int64_t lay = m.nu * m.nv, np = lay * m.nlayers;
     const int64_t nn = (int64_t)m.n[0] * m.n[1] * m.n[2];
     for (int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pt < np;
          pt += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = pt / m.nu, i = pt - j * m.nu;
+        const int64_t k = pt / lay, r2 = pt - k * lay, j = r2 / m.nu, i = r2 - j * m.nu;
         Line c;
         read_line(m.rec, m.nlines, pt, c);
         if (c.st & kFatal) continue;
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void map_backward_kernel(MapJob m, const doubl
         const double m10 = k10 * j11 - k11 * j10;
         const double m11 = -k10 * j01 + k11 * j00;
         double r0[3], B0[3], B1[3], B2[3];
-        point_pos(m, i, j, 0, r0);
+        point_pos(m, i, j, k, r0);
         field64(m, r0, B0);
         field64(m, c.e1, B1);
         field64(m, c.e2, B2);
@@ -794,7 +795,7 @@ hipError_t launch_map_backward(const MapJob &m, const double *dq, const double *
                                const double *dend_b, const double *dend_f, double *lam_end,
                                double *lam_tw, double *gnode, int64_t nhalf0, hipStream_t s)
 {
-    const int64_t np = m.nu * m.nv;
+    const int64_t np = m.nu * m.nv * m.nlayers;
     int64_t b = (np + 255) / 256;
     if (b < 1) b = 1;
     if (b > 65536) b = 65536;

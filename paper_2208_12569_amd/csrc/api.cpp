@@ -362,9 +362,10 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
     size_t off_buf = 0, off_bkey = 0, off_border = 0, off_bcnt = 0, off_lseed = 0;
     int64_t bwd_halves = 0, bwd_nodes = 0;
     if (bwd) {
-        // one seed plane; an interior one adds its rotated-S0 job (up to four lines per
-        // point), whose half lines follow the plane's
-        if (ns != 1 || nrot > 1 || specs[0].kind != SPEC_PLANE) return FQ_EUNSUPPORTED;
+        // one seed plane or voxel map; an interior plane and a voxel map add their
+        // rotated-S0 job (up to four lines per point), whose half lines follow theirs
+        if (ns != 1 || nrot > 1 || (specs[0].kind != SPEC_PLANE && specs[0].kind != SPEC_VOXELS))
+            return FQ_EUNSUPPORTED;
         if (W[0].rotate && P.scheme != FQ_SCHEME_RKF45) return FQ_EUNSUPPORTED;
         bwd_halves = 2 * W[0].nlines + (W[0].rotate ? 2 * 4 * W[0].nlines : 0);
         bwd_nodes = nodes_of(specs[0].f);
@@ -785,27 +786,55 @@ int q2d_specs(const fq_field *fields, const fq_plane *planes, int njobs, const f
     return FQ_OK;
 }
 
+// What every adjoint call checks, and its checkpoint pool: room for tape_steps
+// accepted steps per half line of the seed points on average (plus the first
+// checkpoint and a partial segment), and where points may take a rotated S0 those two
+// for each potential half line of its job (its lines, where a point has them, share
+// the points' average)
+int bwd_common(const fq_params *p, int segment, int64_t points, bool rotated, fq_params &P,
+               BwdSpec &b)
+{
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if (P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
+    if (segment < 1 || segment > 4096) return FQ_EINVAL;
+    if (P.max_steps > INT32_MAX) return FQ_EINVAL;
+    memset(&b, 0, sizeof b);
+    b.seg = segment;
+    const int64_t halves = 2 * points;
+    if (P.tape_steps > ((int64_t)1 << 40)) return FQ_EINVAL;
+    b.pool = halves * (2 + (P.tape_steps + segment - 1) / segment);
+    if (rotated) b.pool += 4 * halves * 2;
+    if (b.pool > INT32_MAX) return FQ_EINVAL;
+    return FQ_OK;
+}
+
 int bwd_setup(const fq_field *f, const fq_plane *pl, const fq_params *p, int segment,
               fq_params &P, std::vector<Spec> &v, BwdSpec &b)
 {
     int rc = resolve_params(p, P);
     if (rc) return rc;
-    if (P.method != FQ_METHOD_I) return FQ_EUNSUPPORTED;
     if ((rc = check_field(f)) || (rc = check_plane(pl))) return rc;
-    if (segment < 1 || segment > 4096) return FQ_EINVAL;
-    if (P.max_steps > INT32_MAX) return FQ_EINVAL;
-    if ((rc = q2d_specs(f, pl, 1, nullptr, v))) return rc;
-    memset(&b, 0, sizeof b);
-    b.seg = segment;
-    // checkpoint pool: room for tape_steps accepted steps per half line of the plane on
-    // average (plus the first checkpoint and a partial segment), and on an interior
-    // plane those two for each potential half line of its rotated-S0 job (its lines,
-    // where a point has them, share the plane's average)
-    const int64_t halves = 2 * pl->nu * pl->nv;
-    if (P.tape_steps > ((int64_t)1 << 40)) return FQ_EINVAL;
-    b.pool = halves * (2 + (P.tape_steps + segment - 1) / segment);
-    if (!plane_on_face(*pl, *f)) b.pool += 4 * halves * 2;
-    if (b.pool > INT32_MAX) return FQ_EINVAL;
+    if ((rc = bwd_common(p, segment, pl->nu * pl->nv, !plane_on_face(*pl, *f), P, b))) return rc;
+    return q2d_specs(f, pl, 1, nullptr, v);
+}
+
+// A 3-D map's adjoint: its voxel layers are seed planes whose points may all take a
+// rotated S0.
+int bwd_setup_vx(const fq_field *f, const fq_voxels *vx, const fq_params *p, int segment,
+                 fq_params &P, std::vector<Spec> &v, BwdSpec &b)
+{
+    int rc = resolve_params(p, P);
+    if (rc) return rc;
+    if ((rc = check_field(f)) || (rc = check_voxels(vx))) return rc;
+    if ((rc = bwd_common(p, segment, vx->n[0] * vx->n[1] * vx->n[2], true, P, b))) return rc;
+    Spec s;
+    memset(&s, 0, sizeof s);
+    s.kind = SPEC_VOXELS;
+    s.f = f;
+    s.vx = *vx;
+    s.normal[2] = 1.0;
+    v.assign(1, s);
     return FQ_OK;
 }
 
@@ -1018,6 +1047,71 @@ int fastqsl_backward_recorded(const fq_field *f, const fq_plane *pl, const fq_pa
     std::vector<Spec> v;
     BwdSpec b;
     int rc = bwd_setup(f, pl, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!gb || !gb[0] || !gb[1] || !gb[2]) return FQ_EINVAL;
+    b.dq = dq;
+    b.dtw = dtw;
+    b.dend_b = dend_b;
+    b.dend_f = dend_f;
+    b.gb = gb;
+    b.phase = 2;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
+}
+
+size_t fastqsl_q3d_backward_workspace_size(const fq_field *f, const fq_voxels *vx,
+                                           const fq_params *p, int segment)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    if (bwd_setup_vx(f, vx, p, segment, P, v, b)) return 0;
+    size_t need = 0;
+    if (run(v, P, nullptr, 0, true, &need, nullptr, &b)) return 0;
+    return need;
+}
+
+int fastqsl_q3d_backward(const fq_field *f, const fq_voxels *vx, const fq_params *p, int segment,
+                         const double *dq, const double *dtw, const double *dend_b,
+                         const double *dend_f, double *const gb[3], void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup_vx(f, vx, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!gb || !gb[0] || !gb[1] || !gb[2]) return FQ_EINVAL;
+    b.dq = dq;
+    b.dtw = dtw;
+    b.dend_b = dend_b;
+    b.dend_f = dend_f;
+    b.gb = gb;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
+}
+
+int fastqsl_q3d_record(const fq_field *f, const fq_voxels *vx, const fq_params *p, int segment,
+                       const fq_map *map, void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup_vx(f, vx, p, segment, P, v, b);
+    if (rc) return rc;
+    if (!map) return FQ_EINVAL;
+    v[0].map = map;
+    b.phase = 1;
+    return run(v, P, (char *)ws, ws_bytes, false, nullptr, (hipStream_t)stream, &b);
+}
+
+int fastqsl_q3d_backward_recorded(const fq_field *f, const fq_voxels *vx, const fq_params *p,
+                                  int segment, const double *dq, const double *dtw,
+                                  const double *dend_b, const double *dend_f,
+                                  double *const gb[3], void *ws, size_t ws_bytes, void *stream)
+{
+    fq_params P;
+    std::vector<Spec> v;
+    BwdSpec b;
+    int rc = bwd_setup_vx(f, vx, p, segment, P, v, b);
     if (rc) return rc;
     if (!gb || !gb[0] || !gb[1] || !gb[2]) return FQ_EINVAL;
     b.dq = dq;

@@ -240,6 +240,22 @@ int main()
                 P6 = P;
                 P6.method = FQ_METHOD_II;
                 CHECK(fastqsl_backward_workspace_size(&f[0], &pl[0], &P6, 32) == 0);
+                // a voxel map's adjoint: the one-call and two-call forms; RKF45 only
+                const size_t nvx = fastqsl_q3d_backward_workspace_size(&f[0], &vx, &P, 32);
+                CHECK(nvx > 0);
+                CHECK(fastqsl_q3d_backward(&f[0], &vx, &P, 32, g_dummy, g_dummy, nullptr, nullptr, gb,
+                                           workspace(nvx), nvx, nullptr) == FQ_OK);
+                CHECK(fastqsl_q3d_record(&f[0], &vx, &P, 32, &m3, workspace(nvx), nvx, nullptr) == FQ_OK);
+                CHECK(fastqsl_q3d_backward_recorded(&f[0], &vx, &P, 32, g_dummy, nullptr, nullptr,
+                                                    nullptr, gb, workspace(nvx), nvx, nullptr) == FQ_OK);
+                CHECK(fastqsl_q3d_backward(&f[0], &vx, &P, 32, g_dummy, g_dummy, nullptr, nullptr, gb,
+                                           workspace(nvx), nvx - 1, nullptr) == FQ_ENOMEM);
+                CHECK(fastqsl_q3d_record(&f[0], &vx, &P, 32, nullptr, workspace(nvx), nvx, nullptr) ==
+                      FQ_EINVAL);
+                CHECK(fastqsl_q3d_backward_workspace_size(&f[0], &vx, &P7, 32) == 0);
+                CHECK(fastqsl_q3d_backward_workspace_size(&f[0], &vx, &P6, 32) == 0);
+                CHECK(fastqsl_q3d_backward_workspace_size(&f[0], &vx, &P, 5000) == 0);
+                CHECK(fastqsl_q3d_backward_workspace_size(&fst, &vx, &P, 32) > 0);
             }
             // argument checks
             fq_field bad = f[0];

@@ -787,3 +787,229 @@ def test_c5_fit_gradient(fq):
         losses.append(float(L.detach()))
     print("c5 losses", losses)
     assert all(np.isfinite(losses)) and losses[-1] < losses[0]
+
+
+# ----------------------------------------------------------------------------------
+# 3-D maps: the voxel layers are seed planes (z = const) whose points may all take a
+# rotated S0 (Section 4)
+
+
+def _fd_mask3(fq, r):
+    """_fd_mask per voxel layer: neighbours are taken within the layer."""
+    import torch
+
+    st = r["status"].to(torch.int32)
+    bad = ((st & (fq.ST_FATAL | fq.ST_MIXEDFACE | fq.ST_ONESIDED | fq.ST_EDGE)) != 0)
+    bad |= ~torch.isfinite(r["q"]) | (r["q"] > 1e4)
+    b = bad.float()
+    pad = torch.nn.functional.pad(b[:, None], (1, 1, 1, 1), value=1.0)[:, 0]
+    dil = torch.maximum(b, pad[:, :-2, 1:-1])
+    dil = torch.maximum(dil, pad[:, 2:, 1:-1])
+    dil = torch.maximum(dil, pad[:, 1:-1, :-2])
+    dil = torch.maximum(dil, pad[:, 1:-1, 2:])
+    return dil == 0
+
+
+def _q3d_grad(fq, B, g, vx, params, segment=32, **kw):
+    import torch
+
+    gb = fq.q3d_backward(B, g, vx, params, segment, **kw)
+    torch.cuda.synchronize()
+    return gb.cpu().numpy()
+
+
+def test_q3d_adjoint_closed_form(fq):
+    """B = (1, 0.3, s (y - y0)) has Q = 2 + s^2 at every voxel of a 3-D map, whether
+    its S0 is the z = const layer or is rotated perpendicular to B (|Bz/B| < 0.05,
+    Section 4): dQ/ds = 2 s voxel by voxel, in three layers, rotated or not."""
+    import torch
+
+    g = cubic_grid(17, 17, 17)
+    s, y0 = 0.5, 0.4
+    B = _dev(linear_field(g, [[0, 0, 0], [0, 0, 0], [0, s, 0]], [1.0, 0.3, -s * y0]))
+    vx = synth.Voxels((0.3, y0 - 0.16, 0.3), (0.02, 0.04, 0.1), (9, 9, 3))
+    yy = np.asarray(g.axes()[1])[None, :, None]
+    dBds = np.zeros((3,) + g.shape)
+    dBds[2] = np.broadcast_to(yy - y0, g.shape)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    r = fq.q3d(B, g, vx, p)
+    st = to_np(r["status"]).astype(np.int64)
+    rot = (st & fq.ST_ROTATED) != 0
+    assert rot[:, 1:-1, 1:-1].sum() >= 10 and (~rot[:, 1:-1, 1:-1]).sum() >= 10
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(2)
+    picks = []
+    for k in range(3):
+        for want_rot in (True, False):
+            cand = [(j, i) for j in range(1, 8) for i in range(1, 8) if rot[k, j, i] == want_rot]
+            picks += [(k,) + cand[c] for c in rng.choice(len(cand), 2, replace=False)]
+    for k, j, i in picks:
+        pt = (k * 9 + j) * 9 + i
+        _say(f"q3d adjoint: dQ/ds at voxel ({i}, {j}, {k}) (rotated S0: {bool(rot[k, j, i])})")
+        dq = torch.zeros(243, dtype=torch.float64, device="cuda")
+        dq[pt] = 1.0
+        g1 = float((_q3d_grad(fq, B, g, vx, fq.Params(precision=F64, tol_perp=TOL, stats=stats),
+                              dq=dq) * dBds).sum())
+        assert abs(g1 - 2 * s) < 1e-6, ((i, j, k), bool(rot[k, j, i]), g1)
+    st5 = stats.tolist()
+    assert st5[2] == 0 and st5[3] == 0, st5
+
+
+@pytest.fixture(scope="module")
+def q3d_charge_case():
+    gc = cubic_grid(33, 33, 33)
+    pos, q = synth.draw_charges(np.random.default_rng(21), 5)
+    B0 = synth.charges_field(gc, pos, q)
+    vx = synth.Voxels((0.2, 0.2, 0.3), (0.6 / 13, 0.6 / 13, 0.1), (14, 14, 4))
+    return gc, B0, vx
+
+
+def test_q3d_adjoint_matches_finite_differences(fq, q3d_charge_case):
+    """On a charge cube, the node gradient of a loss of the 3-D map (log10 Q, Tw and
+    both end points, weighted at random, over voxels whose Q is smooth in the field,
+    rotated-S0 voxels among them) against central differences of the GPU forward."""
+    import torch
+
+    gc, B0, vx = q3d_charge_case
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    _say("q3d adjoint: charge cube map")
+    r = fq.q3d(_dev(B0), gc, vx, p, want_lines=True)
+    mask = _fd_mask3(fq, r)
+    st = r["status"].to(torch.int32)
+    nrot = int((((st & fq.ST_ROTATED) != 0) & mask).sum())
+    print("q3d charge cube: rotated voxels in the loss", nrot, "of", int(mask.sum()))
+    assert nrot >= 3 and mask.float().mean() > 0.3
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    shp = tuple(r["q"].shape)
+    wq = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64) * mask
+    wt = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64) * mask
+    we = torch.randn(shp + (3,), generator=gen, device="cuda", dtype=torch.float64) * mask[..., None]
+
+    def loss(Bn):
+        rr = fq.q3d(_dev(Bn), gc, vx, p, want_lines=True)
+        qq = torch.where(mask, rr["q"], torch.ones_like(rr["q"]))
+        tw = torch.where(mask, rr["tw"], torch.zeros_like(rr["tw"]))
+        eb = torch.where(mask[..., None], rr["lines"]["end_b"].view(shp + (3,)), 0.0)
+        return float((wq * torch.log10(qq)).sum() + (wt * tw).sum() + (we * eb).sum())
+
+    qq = torch.where(mask, r["q"], torch.ones_like(r["q"]))
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    g_nodes = _q3d_grad(fq, _dev(B0), gc, vx, fq.Params(precision=F64, tol_perp=TOL, stats=stats),
+                        dq=(wq / (qq * math.log(10.0))).reshape(-1), dtw=wt.reshape(-1),
+                        dend_b=we.reshape(-1, 3))
+    assert stats.tolist()[2] == 0 and stats.tolist()[3] == 0, stats.tolist()
+    flat = np.abs(g_nodes).ravel()
+    rng = np.random.default_rng(8)
+    nodes = np.concatenate([np.argsort(flat)[-16:], rng.choice(np.flatnonzero(flat > 1e-3 * flat.max()), 8)])
+    errs = []
+    for n in nodes:
+        v = float(B0.ravel()[n])
+        h = 1e-5 * max(abs(v), 1e-2)
+        bp_, bm_ = B0.copy(), B0.copy()
+        bp_.ravel()[n] += h
+        bm_.ravel()[n] -= h
+        fd = (loss(bp_) - loss(bm_)) / (2 * h)
+        errs.append(abs(g_nodes.ravel()[n] - fd) / max(abs(fd), 1e-2 * flat.max()))
+    print("q3d node gradients: max rel err", max(errs))
+    assert max(errs) < 1e-4, errs
+
+
+@pytest.mark.parametrize("stretched", [False, True], ids=["uniform", "stretched"])
+def test_q3d_adjoint_equals_its_layers_as_planes(fq, q3d_charge_case, stretched):
+    """A voxel layer z = z_k is the interior seed plane z = z_k with the same points:
+    the 3-D map's gradient of a loss is the sum over layers of the plane adjoint's
+    gradients of that loss's layer terms (two entry points, two seed kinds)."""
+    import torch
+
+    gc, B0, vx = q3d_charge_case
+    if stretched:
+        x = synth.clustered_axis(33, 0.0, 1.0, 0.45, 1.3)
+        gc = synth.stretched_grid(x, x.copy(), synth.geometric_axis(33, 0.0, 1.0, 1.03))
+        pos, q = synth.draw_charges(np.random.default_rng(21), 5)
+        B0 = synth.charges_field(gc, pos, q)
+    B = _dev(B0)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    _say(f"q3d layers as planes ({'stretched' if stretched else 'uniform'}): q3d map")
+    r = fq.q3d(B, gc, vx, p)
+    mask = _fd_mask3(fq, r)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    shp = tuple(r["q"].shape)
+    wq = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64) * mask
+    wt = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64) * mask
+    qq = torch.where(mask, r["q"], torch.ones_like(r["q"]))
+    dq = wq / qq
+    g3 = _q3d_grad(fq, B, gc, vx, p, dq=dq.reshape(-1), dtw=wt.reshape(-1))
+    acc = np.zeros_like(g3)
+    nx, ny, nz = vx.n
+    for k in range(nz):
+        pl = Plane((vx.origin[0], vx.origin[1], vx.origin[2] + k * vx.spacing[2]), (1, 0, 0), (0, 1, 0),
+                   nx, ny, vx.spacing[0], vx.spacing[1])
+        _say(f"q3d layers as planes: layer {k}")
+        rp = fq.q2d(B, gc, pl, p)
+        ok = mask[k] & torch.isfinite(rp["q"])
+        assert bool((((rp["q"] - r["q"][k]).abs() <= 1e-8 * r["q"][k].abs()) | ~ok).all())
+        acc += _grad(fq, B, gc, pl, dq=dq[k].reshape(-1), dtw=wt[k].reshape(-1))
+    scale = np.abs(g3).max()
+    print("q3d vs layer planes: max abs diff", np.abs(g3 - acc).max(), "scale", scale)
+    assert scale > 0 and np.allclose(g3, acc, rtol=1e-7, atol=1e-9 * scale)
+
+
+@pytest.mark.parametrize("prec", [F64, 0], ids=["f64", "f32x"])
+def test_q3d_record_and_reverse(fq, q3d_charge_case, prec):
+    """fastqsl_q3d_record writes fastqsl_q3d's map bit for bit; the reverse call on its
+    workspace (twice) gives the one-call gradient, no replay leaving its forward pass;
+    the F32X form's gradient follows the all-FP64 one; the autograd function takes a
+    voxel grid; fixed-step schemes and Method II are refused."""
+    import torch
+
+    from paper_2208_12569_amd.autograd import qtw_map
+
+    gc, B0, vx = q3d_charge_case
+    B = _dev(B0) if prec == F64 else _dev(B0).float()
+    p = fq.Params(precision=prec, tol_perp=TOL) if prec == F64 else fq.Params(precision=prec)
+    _say(f"q3d record vs q3d, precision {prec}")
+    rec = fq.q3d_record(B, gc, vx, p, 16, want_lines=True)
+    ref = fq.q3d(B, gc, vx, p, want_lines=True)
+    torch.cuda.synchronize()
+    for k in ("q", "tw", "length", "status"):
+        assert np.array_equal(rec[k].cpu().numpy(), ref[k].cpu().numpy(), equal_nan=True), k
+    mask = _fd_mask3(fq, ref)
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    n = int(np.prod(vx.n))
+    dq = torch.randn(n, generator=gen, device="cuda", dtype=torch.float64) * mask.reshape(-1)
+    de = torch.randn((n, 3), generator=gen, device="cuda", dtype=torch.float64)
+    _say(f"q3d one-call gradient, precision {prec}")
+    one = _q3d_grad(fq, B, gc, vx, p, 16, dq=dq, dend_f=de)
+    for rep in range(2):
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+        pr = fq.Params(precision=prec, tol_perp=TOL, stats=stats) if prec == F64 else \
+            fq.Params(precision=prec, stats=stats)
+        _say(f"q3d recorded gradient {rep}, precision {prec}")
+        gb = fq.q3d_backward_recorded(B, gc, vx, rec, pr, 16, dq=dq, dend_f=de)
+        torch.cuda.synchronize()
+        st = stats.tolist()
+        assert st[0] > 0 and st[2] == 0 and st[3] == 0, (rep, st)
+        assert np.allclose(gb.cpu().numpy(), one, rtol=1e-11, atol=1e-13 * np.abs(one).max()), rep
+    if prec != F64:
+        _say("q3d f32x gradient against the all-FP64 one")
+        p64 = fq.Params(precision=F64, tol_perp=TOL)
+        r64 = fq.q3d(_dev(B0), gc, vx, p64)
+        m2 = (mask & _fd_mask3(fq, r64)).reshape(-1)
+        g32 = _q3d_grad(fq, B, gc, vx, p, 16, dq=dq * m2)
+        g64 = _q3d_grad(fq, _dev(B0), gc, vx, p64, 16, dq=dq * m2)
+        big = np.abs(g64) > 1e-2 * np.abs(g64).max()
+        err = np.abs(g32 - g64)[big] / np.abs(g64)[big]
+        print("q3d f32x vs f64 gradient: max rel", err.max(), "median", np.median(err))
+        assert np.median(err) < 1e-3 and err.max() < 5e-2
+        return
+    _say("q3d through the autograd function")
+    Bt = _dev(B0).requires_grad_(True)
+    q, tw, eb, ef, st = qtw_map(Bt, gc, vx, p, 16)
+    assert q.shape == tuple(reversed(vx.n)) and ef.shape == tuple(reversed(vx.n)) + (3,)
+    (torch.where(mask, q, torch.zeros_like(q)) * dq.view(q.shape)).sum().backward()
+    ga = Bt.grad.cpu().numpy()
+    gd = _q3d_grad(fq, _dev(B0), gc, vx, p, 16, dq=dq * mask.reshape(-1))
+    assert np.allclose(ga, gd, rtol=1e-11, atol=1e-13 * np.abs(gd).max())
+    for bad in (fq.Params(precision=F64, scheme=fq.FQ_SCHEME_RK4), fq.Params(precision=F64, method=1)):
+        with pytest.raises(ValueError):
+            fq.q3d_backward(_dev(B0), gc, vx, bad, 16, dq=dq)
