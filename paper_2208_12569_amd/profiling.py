@@ -7,7 +7,9 @@ the same process.
   python -m paper_2208_12569_amd.profiling traffic <fetch counter csv> <write counter csv>
         <out.json> <key> "<command>" [kernel]
   python -m paper_2208_12569_amd.profiling l2 <tcc counter csv> <tcp counter csv> <out.md>
-        "<command>" [kernel]
+        "<command>" [kernel] [kernel ms]
+  python -m paper_2208_12569_amd.profiling valu <SQ pass A csv> <SQ pass B csv> <out.md>
+        "<command A>" "<command B>" <kernel ms> <trial steps> <cell fetches>
 """
 
 from __future__ import annotations
@@ -125,6 +127,51 @@ def l2_md(tcc_csv: str, tcp_csv: str, command: str, kernel: str = TRACER,
     return "\n".join(rows) + "\n"
 
 
+VALU_A = ("SQ_THREAD_CYCLES_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32",
+          "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+          "SQ_INSTS_VALU_FLOPS_FP32")
+VALU_B = ("SQ_INSTS_VALU_CVT", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64",
+          "SQ_INSTS_VALU_FLOPS_FP32_TRANS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_BRANCH",
+          "SQ_WAVES")
+
+
+def valu_md(a_csv: str, b_csv: str, command_a: str, command_b: str, kernel_ms: float,
+            trials: float, fetches: float, kernel: str = TRACER) -> str:
+    """The instruction mix of one kernel per launch from two SQ counter passes, with
+    lanes per instruction, VALU busy (4 cycles per wave instruction on 1024 SIMDs at
+    2.4 GHz) and VALU instructions per lane trial step."""
+    v = {c: _mean_counter(a_csv, c, kernel) for c in VALU_A}
+    v.update({c: _mean_counter(b_csv, c, kernel) for c in VALU_B})
+    valu = v["SQ_INSTS_VALU"]
+    share = ("SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_CVT", "SQ_INSTS_VALU_FMA_F32",
+             "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64", "SQ_INSTS_VALU_MUL_F32",
+             "SQ_INSTS_VALU_TRANS_F32")
+    rows = [f"# Instruction mix of `{kernel}`, per launch", "",
+            "Commands (two counter passes, each its own run):", "", f"`{command_a}`", "",
+            f"`{command_b}`", "",
+            f"Mean over launches; whole-chip totals. Per launch: {trials:.5g} trial steps, "
+            f"{fetches:.5g} cell fetches, {kernel_ms:.2f} ms (kernel trace of the same build).", "",
+            "| counter | value | share of VALU instructions |", "|---|---|---|"]
+    for c in sorted(v):
+        sh = f"{100 * v[c] / valu:.1f}%" if c in share else ""
+        rows.append(f"| {c} | {v[c]:.4e} | {sh} |")
+    other = valu - sum(v[c] for c in share)
+    busy = valu * 4 / (1024 * kernel_ms * 1e-3 * 2.4e9)
+    rows += ["", "Derived:", "",
+             f"* active lanes per VALU instruction: SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU = "
+             f"{v['SQ_THREAD_CYCLES_VALU'] / v['SQ_ACTIVE_INST_VALU']:.1f} of 64",
+             f"* VALU instructions other than FP32 FMA/MUL/ADD/transcendental, integer and "
+             f"conversions (moves, selects, compares, min/max, bit operations): {other:.4g}, "
+             f"{100 * other / valu:.0f}%",
+             f"* VALU busy: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x {kernel_ms:.2f} ms x 2.4 GHz) "
+             f"= {100 * busy:.0f}%",
+             f"* VALU instructions per lane trial step: SQ_INSTS_VALU x 64 / trial steps = "
+             f"{valu * 64 / trials:.0f}",
+             f"* vector memory reads per wave-level cell fetch: "
+             f"{v['SQ_INSTS_VMEM_RD'] * 64 / fetches:.1f} (16 loads per fetch)"]
+    return "\n".join(rows) + "\n"
+
+
 def main(argv):
     if argv[0] == "stats":
         open(argv[2], "w").write(stats_md(argv[1], argv[3]))
@@ -140,6 +187,9 @@ def main(argv):
         kernel = argv[5] if len(argv) > 5 else TRACER
         ms = float(argv[6]) if len(argv) > 6 else None
         open(argv[3], "w").write(l2_md(argv[1], argv[2], argv[4], kernel, ms))
+    elif argv[0] == "valu":
+        open(argv[3], "w").write(valu_md(argv[1], argv[2], argv[4], argv[5], float(argv[6]),
+                                         float(argv[7]), float(argv[8])))
     else:
         raise SystemExit(__doc__)
 
