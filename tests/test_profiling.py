@@ -86,3 +86,38 @@ def test_bench_reports_traffic_only_for_the_current_kernel_source(tmp_path, monk
     (tmp_path / "profiles" / "trace_kernel_traffic.json").write_text(json.dumps(rec))
     assert bench.traffic_from_profile("c2", "f32x") is None
 
+
+
+def _multi_counter_csv(path, dispatches):
+    """dispatches: (dispatch id, kernel name, {counter: [instance values]})"""
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for d, name, cs in dispatches:
+            for c, vals in cs.items():
+                for v in vals:
+                    w.writerow([d, name, c, v])
+
+
+def test_valu_mix_derives_busy_lanes_and_per_step_counts(tmp_path):
+    """Two launches of the tracer (instances summed per dispatch, launches averaged):
+    1.0e9 VALU instructions per launch on 1024 SIMDs for 2 ms at 4 cycles each is
+    1e9 * 4 / (1024 * 2e-3 * 2.4e9) = 81.4% busy; 1e9 * 64 / 5e7 trial steps = 1280
+    per lane trial step; 48 lanes per instruction; 'other' is VALU minus the listed
+    classes."""
+    a = tmp_path / "a.csv"
+    b = tmp_path / "b.csv"
+    ca = {c: [0.0] for c in profiling.VALU_A}
+    ca.update({"SQ_INSTS_VALU": [4e8, 6e8], "SQ_ACTIVE_INST_VALU": [1e9], "SQ_THREAD_CYCLES_VALU": [48e9],
+               "SQ_INSTS_VALU_FMA_F32": [3e8], "SQ_INSTS_VALU_MUL_F32": [1e8], "SQ_INSTS_VALU_ADD_F32": [1e8]})
+    cb = {c: [0.0] for c in profiling.VALU_B}
+    cb.update({"SQ_INSTS_VALU_INT32": [1e8], "SQ_INSTS_VMEM_RD": [2.5e7]})
+    _multi_counter_csv(a, [(1, TRACER, ca), (2, TRACER, ca), (3, COPY, {"SQ_INSTS_VALU": [5.0]})])
+    _multi_counter_csv(b, [(1, TRACER, cb), (2, TRACER, cb)])
+    md = profiling.valu_md(str(a), str(b), "cmd a", "cmd b", 2.0, 5e7, 1e8)
+    assert "= 48.0 of 64" in md
+    assert "2.4 GHz) = 81%" in md
+    assert "trial steps = 1280" in md
+    assert "bit operations): 4e+08, 40%" in md
+    assert "| SQ_INSTS_VALU_FMA_F32 | 3.0000e+08 | 30.0% |" in md
+    assert "per wave-level cell fetch: 16.0" in md
