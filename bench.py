@@ -266,7 +266,7 @@ def run_variant(w, label: str, args, uniform_value: float, method: int = 0) -> d
     out = {"workload": label, "unit": UNIT}
     maps = {}
     for form in ("f32x", "f64"):
-        r = run_gpu(w, form, args.tol, args.steps, args.warmup, method=method)
+        r = run_gpu(w, form, args.tol, args.sub_steps, args.warmup, method=method)
         out[form] = {"value": npts / (r["ms"] * 1e-3), "ms_per_step": r["ms"], "trace_ms": r["trace_ms"],
                      "fp64_pass_ms": r["fix_ms"], "trial_steps": r["stats"][0],
                      "vs_uniform_method1": npts / (r["ms"] * 1e-3) / uniform_value[form]}
@@ -684,7 +684,10 @@ def q3d_accuracy(w, idx, gvals) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=32,
+                    help="timed maps of the headline workload (both forms)")
+    ap.add_argument("--sub-steps", type=int, default=10,
+                    help="timed steps of every other run (seeds, variants, batch, adjoint, 3-D map)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=("f32x", "f64"), default="f32x")
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -715,7 +718,7 @@ def main():
     import synth
 
     if args.q3d_only:
-        r = run_q3d(args.seed, args.steps, args.warmup)
+        r = run_q3d(args.seed, args.sub_steps, args.warmup)
         r.pop("_sample")
         if args.calib_copy:
             import torch
@@ -834,7 +837,7 @@ def main():
         seeds = {}
         for sd in [x for x in (0, 1, 2) if x != args.seed][:2]:
             ws_ = synth.config_c2(sd)
-            rr = run_gpu(ws_, args.precision, args.tol, args.steps, args.warmup)
+            rr = run_gpu(ws_, args.precision, args.tol, args.sub_steps, args.warmup)
             seeds[str(sd)] = {"value": npts / (rr["ms"] * 1e-3), "ms_per_step": rr["ms"],
                               "trial_steps": rr["stats"][0]}
             del ws_, rr
@@ -852,13 +855,13 @@ def main():
             w, "C2, Method II (Q, Q_perp and Tw from U, V traced with each line; no "
                "neighbour lines)", args, uv, method=1)
     if not args.no_batch:
-        out["batch"] = run_batch(args.seed, args.steps, args.warmup)
+        out["batch"] = run_batch(args.seed, args.sub_steps, args.warmup)
     if not args.no_adjoint:
-        out["adjoint"] = run_adjoint(args.seed, args.steps, args.warmup)
-        out["adjoint_f32x"] = run_adjoint(args.seed, args.steps, args.warmup, "f32x")
+        out["adjoint"] = run_adjoint(args.seed, args.sub_steps, args.warmup)
+        out["adjoint_f32x"] = run_adjoint(args.seed, args.sub_steps, args.warmup, "f32x")
     q3d_sample = None
     if not args.no_q3d:
-        out["q3d"] = run_q3d(args.seed, args.steps, args.warmup)
+        out["q3d"] = run_q3d(args.seed, args.sub_steps, args.warmup)
         q3d_sample = out["q3d"].pop("_sample")
     if args.calib_copy:
         import torch

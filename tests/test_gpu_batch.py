@@ -176,3 +176,42 @@ def test_c4_batch_in_graph(fq, c4):
         ores = oracle.q2d_points(Bh, w.grid, w.plane, idx, ORC_TOL)
         s = compare_points(o, idx, ores, f"c4 {w.name}")
         print(w.name, s)
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_maps_in_flight_on_several_streams(fq, prec):
+    """Maps computed four at a time on four streams of default priority, each with
+    its own workspace (one map's FP64 pass overlapping the others' FP32 passes), equal
+    the same maps computed one at a time, bit for bit: a face plane, an interior plane
+    with rotated-S0 points and a 3-D map, three rounds over the streams."""
+    import torch
+
+    g = cubic_grid(48, 48, 40)
+    pos, q = synth.draw_charges(np.random.default_rng(17), 6)
+    B = torch.from_numpy(synth.charges_field(g, pos, q, dtype=np.float32)).cuda()
+    p = fq.Params(precision=prec)
+    face = plane_z0(56)
+    mid = synth.Plane((0.1, 0.1, 0.37), (1, 0, 0), (0, 1, 0), 40, 36, 0.02, 0.022)
+    vx = synth.Voxels((0.1, 0.1, 0.1), (0.05, 0.05, 0.1), (16, 16, 5))
+    calls = [lambda s, ws: fq.q2d(B, g, face, p, want_lines=True, stream=s, ws=ws),
+             lambda s, ws: fq.q2d(B, g, mid, p, want_lines=True, stream=s, ws=ws),
+             lambda s, ws: fq.q3d(B, g, vx, p, want_lines=True, stream=s, ws=ws)]
+    _say(f"maps one at a time, precision {prec}")
+    ref = [c(None, None) for c in calls]
+    torch.cuda.synchronize()
+    assert bool(((ref[1]["status"].to(torch.int32) & fq.ST_ROTATED) != 0).any())
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    wss = {}
+    outs = []
+    _say(f"maps four in flight, precision {prec}")
+    for rnd in range(3):
+        for k, c in enumerate(calls):
+            i = rnd * len(calls) + k
+            s = streams[i % 4]
+            with torch.cuda.stream(s):
+                r = c(s, wss.get((i % 4, k)))
+            wss[(i % 4, k)] = r["_ws"]
+            outs.append((k, r))
+    torch.cuda.synchronize()
+    for n, (k, r) in enumerate(outs):
+        _same(r, ref[k], f"in flight {n} (call {k})")
