@@ -179,3 +179,38 @@ def test_fp32_unfinished_half_gets_its_twist_in_the_fp64_pass(fq):
     assert np.all(np.isfinite(tw))
     assert np.allclose(tw, to_np(ref["tw"]), atol=1e-9, rtol=0)
     assert int(stats[4]) >= 12  # half lines traced again in FP64
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_rotated_s0_high_q_closed_form(fq, prec):
+    """B = (1, k (y - y0), -k (z - z0)), k = 4: lines run along x with y - y0 growing
+    as exp(k x) and z - z0 shrinking as exp(-k x), so the map between the x faces
+    has Q = 2 cosh 2k = 2981 everywhere (Bn1 = Bn2 = Bx = 1). Voxels within 0.004 of
+    y0 and z0 have |Bz/B| < 0.05 and take a rotated S0 (Section 4): Q from their four
+    extra lines matches the closed form; above the F32X form's Q threshold (300) all
+    of a rotated voxel's lines are traced again in FP64 (the FP64 pass counts them)."""
+    import torch
+
+    k, y0, z0 = 4.0, 0.5, 0.5
+    g = cubic_grid(17, 17, 17)
+    B = _dev(synth.linear_field(g, [[0, 0, 0], [0, k, 0], [0, 0, -k]], [1.0, -k * y0, k * z0]))
+    dv = 0.004
+    vx = synth.Voxels((0.5 - dv, y0 - dv, z0 - dv), (dv, dv, dv), (3, 3, 3))
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+    _say(f"rotated S0, Q = 2 cosh 8, precision {prec}")
+    r = fq.q3d(B, g, vx, fq.Params(precision=prec, stats=stats), want_lines=True)
+    torch.cuda.synchronize()
+    st = to_np(r["status"]).astype(np.int64)
+    assert np.all(st & fq.ST_ROTATED) and not np.any(st & fq.ST_FATAL), st
+    want = 2 * math.cosh(2 * k)
+    q = to_np(r["q"]).ravel()
+    lq = math.log10(want)
+    err = np.abs(np.log10(q) - lq) / lq
+    print("Q", q.min(), q.max(), "closed form", want, "max rel log10 Q error", err.max())
+    assert err.max() <= TOL_LOGQ, (q, want)
+    if prec == F32X:
+        # 27 voxels, each with its own line and four rotated-S0 lines, both halves
+        assert stats.tolist()[4] >= 27 * 5 * 2, stats.tolist()
+    o = oracle.q3d(synth.linear_field(g, [[0, 0, 0], [0, k, 0], [0, 0, -k]], [1.0, -k * y0, k * z0]),
+                   g, vx, {"tol": 1e-10})
+    print(compare_maps(r, o, f"rotated-high-q-{prec}"))

@@ -418,7 +418,9 @@ def c3():
 def test_c3_full_size_sampled_parity(fq, c3, prec):
     """3-D Q and Tw on the 256x256x128 voxel centres of the 512x512x256 FP32 cube
     (10 charges + two tubes), including rotated-S0 voxels, against the oracle at
-    sampled voxels."""
+    sampled voxels: 300 random ones, 60 random rotated ones and the 40 rotated ones
+    with the largest Q below 1e8 (where the F32X form re-traces all four of a
+    rotated voxel's lines in FP64)."""
     import torch
 
     w = c3
@@ -430,8 +432,13 @@ def test_c3_full_size_sampled_parity(fq, c3, prec):
     st_all = to_np(r["status"]).astype(np.uint16).ravel()
     rot = np.flatnonzero(st_all & fq.ST_ROTATED)
     rng = np.random.default_rng(23)
+    q_all = to_np(r["q"]).ravel()
+    qr = q_all[rot]
+    ok = np.isfinite(qr) & (qr < 1e8)
+    top = rot[ok][np.argsort(qr[ok])[-40:]]
     idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False),
-                                    rng.choice(rot, min(60, rot.size), replace=False)]))
+                                    rng.choice(rot, min(60, rot.size), replace=False), top]))
+    print("largest Q among the rotated voxels compared:", float(q_all[top].max()))
     o = oracle.q3d_points(w.field, w.grid, vx, idx, ORC_TOL)
     st = compare_points(r, idx, o, f"c3-{prec}")
     print(st, "rotated voxels:", rot.size)
