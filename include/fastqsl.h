@@ -157,6 +157,13 @@ typedef struct {
                           Eq. tol at |Bn0/B| = 1 (its S0 is perpendicular to B), RKF45 only, and
                           in the F32X form without the FP64 passes (FP32 tracing; FP64 end
                           fields and Q); the adjoint calls take Method I only */
+    int32_t in_flight; /* FQ_PREC_F32X maps: nonzero when the caller keeps other maps in flight
+                          on other streams at the same time. The FP64 pass (a tail of few,
+                          long lines) then runs at three waves per SIMD, spilling a little, so
+                          that the other maps' FP32 passes find room beside its waves: more
+                          maps per second in flight, a longer FP64 pass for one map alone.
+                          Results are the same bit for bit; default 0 */
+    int32_t reserved2; /* must be 0 */
 } fq_params;
 
 /* A 2-D seed grid on S0: seed (i, j) = origin + i du u + j dv v, i < nu, j < nv,

@@ -61,6 +61,7 @@ class Params:
     tape_steps: int = 0  # adjoint calls: checkpoint pool room in accepted steps per half line
     scheme: int = FQ_SCHEME_RKF45
     method: int = FQ_METHOD_I  # maps: FQ_METHOD_II adds Q_perp ("qperp")
+    in_flight: bool = False  # F32X maps: other maps run on other streams at the same time
     stats: object = None  # optional CUDA int64 tensor of 5 counters (added to)
     events: object = None  # optional ctypes array of 4 hipEvent_t handles
 
@@ -81,6 +82,7 @@ class Params:
         p.tape_steps = int(self.tape_steps)
         p.scheme = int(self.scheme)
         p.method = int(self.method)
+        p.in_flight = 1 if self.in_flight else 0
         p.stats = self.stats.data_ptr() if self.stats is not None else None
         p.events = C.cast(self.events, C.c_void_p) if self.events is not None else None
         return p

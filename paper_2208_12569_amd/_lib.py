@@ -52,7 +52,8 @@ class fq_params(C.Structure):
                 ("precision", C.c_int32), ("want_tw", C.c_int32), ("block", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("graze", C.c_double), ("stats", C.c_void_p),
                 ("events", C.c_void_p), ("qfix", C.c_double), ("tape_steps", C.c_int64),
-                ("scheme", C.c_int32), ("method", C.c_int32)]
+                ("scheme", C.c_int32), ("method", C.c_int32), ("in_flight", C.c_int32),
+                ("reserved2", C.c_int32)]
 
 
 class fq_plane(C.Structure):

@@ -144,6 +144,8 @@ int resolve_params(const fq_params *in, fq_params &p)
     if (p.qfix == 0) p.qfix = 300.0;
     if (p.scheme < FQ_SCHEME_RKF45 || p.scheme > FQ_SCHEME_RK4_38) return FQ_EINVAL;
     if (p.method != FQ_METHOD_I && p.method != FQ_METHOD_II) return FQ_EINVAL;
+    if (p.reserved2 != 0) return FQ_EINVAL;
+    p.in_flight = p.in_flight != 0;
     if (p.tape_steps < 0) return FQ_EINVAL;
     if (p.tape_steps == 0) p.tape_steps = 2048;
     if (in == nullptr) p.want_tw = 1;
@@ -670,7 +672,8 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         if (ev && ev[2]) FQ_TRY(hipEventRecord(ev[2], stream));
         // positions only: the twist integral is not sensitive to the end angle, so the
         // FP32 pass's Tw is kept and the latency-bound FP64 pass skips the curl
-        const int fix_twm = !P.want_tw ? 0 : (split ? 2 : 1);
+        // (with other maps in flight, the positions-only form at three waves per SIMD)
+        const int fix_twm = !P.want_tw ? 0 : (split ? (P.in_flight ? 3 : 2) : 1);
         FQ_TRY(launch_trace(FQ_PREC_F64, fix_store, fix_twm, fix_jobs, fp, counter, P.block,
                             P.waves_per_cu, stream));
         if (split) {

@@ -199,7 +199,8 @@ hipError_t launch_store_job(const TraceJob &j, TraceJob *dst, hipStream_t s);
 // prec: compute type (FQ_PREC_F32X = float, FQ_PREC_F64 = double);
 // store: node-record type (FQ_DT_F32 / FQ_DT_F64);
 // twm: 0 = no twist, 1 = twist, 2 = positions only on twist-layout records, keeping the
-// twist already in the records (the FP64 re-trace).
+// twist already in the records (the FP64 re-trace); 3 = as 2 at three waves per SIMD
+// (FP64 only: for calls that share the GPU with other maps in flight).
 hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
                         const TraceParams &tp, unsigned long long *counter, int block,
                         int waves_per_cu, hipStream_t s);

@@ -75,7 +75,9 @@ template <typename T> constexpr double kCylEnd() { return sizeof(T) == 4 ? 1e-5 
 template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 8; }
 
 // TWM: 0 = no twist (narrow records), 1 = twist, 2 = positions only on wide records
-// (the FP64 re-trace, which keeps the twist of the first pass).
+// (the FP64 re-trace, which keeps the twist of the first pass); 3 = as 2, held to
+// three waves per SIMD (168 VGPRs, about 100 bytes of spills per lane) for calls
+// that share the GPU with other maps in flight: its waves then leave room for theirs.
 // The FP32 single-job kernel is held to 168 VGPRs so that three waves fit per SIMD
 // (the latency of cell fetches is then hidden by more waves), and the FP32 Method II
 // kernels to two waves per SIMD (a few bytes of spills; at one wave their lone
@@ -84,7 +86,7 @@ template <typename T> constexpr int refill_min() { return sizeof(T) == 4 ? 24 : 
 // (TAPE) included. M2: Method II, the tangent vectors U, V ride along (their
 // end values go to the records' uv array).
 template <typename T, typename S, int TWM, bool UNI, bool TAPE, int SCH = SCH_RKF45, bool M2 = false>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3 : ((sizeof(T) == 4 && M2) ? 2 : 1)) void trace_kernel(const TraceJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, ((sizeof(T) == 4 && TWM == 1 && UNI && !M2) || TWM == 3) ? 3 : ((sizeof(T) == 4 && M2) ? 2 : 1)) void trace_kernel(const TraceJob *__restrict__ jobs,
                                                     TraceParams tp,
                                                     unsigned long long *__restrict__ counter)
 {
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && TWM == 1 && UNI && !M2) ? 3
             ge[3 * rec + 0] = e0;
             ge[3 * rec + 1] = e1;
             ge[3 * rec + 2] = e2;
-            if (TWM != 2) gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
+            if (TWM != 2 && TWM != 3) gptr(J.rec.tw)[rec] = bad ? NAN : (TW ? L.tw : NAN);
             gptr(J.rec.len)[rec] = bad ? NAN : L.len * ((STRK && str) ? dref_s : J.dref);
             gptr(J.rec.face)[rec] = bad ? (int8_t)-1 : (int8_t)fin_face;
             gptr(J.rec.st)[rec] = (uint16_t)fin_st;
@@ -601,6 +603,8 @@ __global__ void graze_kernel(const TraceJob *__restrict__ jobs, int job, double 
 template <typename T, typename S, bool UNI, int SCH>
 const void *kernel_of_s(int twm)
 {
+    if constexpr (sizeof(T) == 8)
+        if (twm == 3) return (const void *)trace_kernel<T, S, 3, UNI, false, SCH>;
     return twm == 1 ? (const void *)trace_kernel<T, S, 1, UNI, false, SCH>
                     : twm == 2 ? (const void *)trace_kernel<T, S, 2, UNI, false, SCH>
                                : (const void *)trace_kernel<T, S, 0, UNI, false, SCH>;
@@ -621,6 +625,11 @@ template <typename T, typename S, bool UNI, bool TAPE, int SCH>
 void launch_tss(int twm, dim3 grid, dim3 blk, hipStream_t s, const TraceJob *jobs,
                 const TraceParams &tp, unsigned long long *counter)
 {
+    if constexpr (sizeof(T) == 8 && !TAPE)
+        if (twm == 3) {
+            hipLaunchKernelGGL((trace_kernel<T, S, 3, UNI, false, SCH>), grid, blk, 0, s, jobs, tp, counter);
+            return;
+        }
     if (twm == 1) hipLaunchKernelGGL((trace_kernel<T, S, 1, UNI, TAPE, SCH>), grid, blk, 0, s, jobs, tp, counter);
     else if (twm == 2 && !TAPE) hipLaunchKernelGGL((trace_kernel<T, S, 2, UNI, false, SCH>), grid, blk, 0, s, jobs, tp, counter);
     else hipLaunchKernelGGL((trace_kernel<T, S, 0, UNI, TAPE, SCH>), grid, blk, 0, s, jobs, tp, counter);
@@ -1037,7 +1046,8 @@ hipError_t launch_trace(int prec, int store, int twm, const TraceJob *jobs_dev,
     }
     const void *fn;
     const int sch = tp.scheme, mt = tp.method;
-    if (mt == FQ_METHOD_II && (sch != SCH_RKF45 || twm == 2)) return hipErrorInvalidValue;
+    if (mt == FQ_METHOD_II && (sch != SCH_RKF45 || twm == 2 || twm == 3)) return hipErrorInvalidValue;
+    if (twm == 3 && !f64) return hipErrorInvalidValue;
     if (!f64) fn = uni ? kernel_of<float, float, true>(twm, sch, mt) : kernel_of<float, float, false>(twm, sch, mt);
     else if (s64) fn = uni ? kernel_of<double, double, true>(twm, sch, mt) : kernel_of<double, double, false>(twm, sch, mt);
     else fn = uni ? kernel_of<double, float, true>(twm, sch, mt) : kernel_of<double, float, false>(twm, sch, mt);

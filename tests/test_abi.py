@@ -47,7 +47,7 @@ def test_struct_sizes_match_header_layout(lib):
 
     # int64[3] + double[3] + double[3] + int32 + int32 + ptr[3]
     assert C.sizeof(_lib.fq_field) == 24 + 24 + 24 + 8 + 24 + 24
-    assert C.sizeof(_lib.fq_params) == 5 * 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(_lib.fq_params) == 5 * 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert C.sizeof(_lib.fq_plane) == 9 * 8 + 16 + 16
     assert C.sizeof(_lib.fq_voxels) == 9 * 8
     assert C.sizeof(_lib.fq_lines) == 10 * 8

@@ -181,9 +181,12 @@ def test_c4_batch_in_graph(fq, c4):
 @pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
 def test_maps_in_flight_on_several_streams(fq, prec):
     """Maps computed four at a time on four streams of default priority, each with
-    its own workspace (one map's FP64 pass overlapping the others' FP32 passes), equal
-    the same maps computed one at a time, bit for bit: a face plane, an interior plane
-    with rotated-S0 points and a 3-D map, three rounds over the streams."""
+    its own workspace (one map's FP64 pass overlapping the others' FP32 passes, run in
+    its three-waves-per-SIMD form: in_flight), equal the same maps computed one at a
+    time, bit for bit: a face plane, an interior plane with rotated-S0 points and a
+    3-D map, three rounds over the streams."""
+    import dataclasses
+
     import torch
 
     g = cubic_grid(48, 48, 40)
@@ -193,11 +196,12 @@ def test_maps_in_flight_on_several_streams(fq, prec):
     face = plane_z0(56)
     mid = synth.Plane((0.1, 0.1, 0.37), (1, 0, 0), (0, 1, 0), 40, 36, 0.02, 0.022)
     vx = synth.Voxels((0.1, 0.1, 0.1), (0.05, 0.05, 0.1), (16, 16, 5))
-    calls = [lambda s, ws: fq.q2d(B, g, face, p, want_lines=True, stream=s, ws=ws),
-             lambda s, ws: fq.q2d(B, g, mid, p, want_lines=True, stream=s, ws=ws),
-             lambda s, ws: fq.q3d(B, g, vx, p, want_lines=True, stream=s, ws=ws)]
+    pf = dataclasses.replace(p, in_flight=True)
+    calls = [lambda s, ws, q: fq.q2d(B, g, face, q, want_lines=True, stream=s, ws=ws),
+             lambda s, ws, q: fq.q2d(B, g, mid, q, want_lines=True, stream=s, ws=ws),
+             lambda s, ws, q: fq.q3d(B, g, vx, q, want_lines=True, stream=s, ws=ws)]
     _say(f"maps one at a time, precision {prec}")
-    ref = [c(None, None) for c in calls]
+    ref = [c(None, None, p) for c in calls]
     torch.cuda.synchronize()
     assert bool(((ref[1]["status"].to(torch.int32) & fq.ST_ROTATED) != 0).any())
     streams = [torch.cuda.Stream() for _ in range(4)]
@@ -209,7 +213,7 @@ def test_maps_in_flight_on_several_streams(fq, prec):
             i = rnd * len(calls) + k
             s = streams[i % 4]
             with torch.cuda.stream(s):
-                r = c(s, wss.get((i % 4, k)))
+                r = c(s, wss.get((i % 4, k)), pf)
             wss[(i % 4, k)] = r["_ws"]
             outs.append((k, r))
     torch.cuda.synchronize()
