@@ -258,6 +258,15 @@ int main()
                 CHECK(fastqsl_q3d_backward_workspace_size(&fst, &vx, &P, 32) > 0);
             }
             // argument checks
+            {
+                fq_params Pi = P;
+                Pi.in_flight = 7;  // any nonzero value: the FP64 pass's shared-GPU form
+                const size_t ni = fastqsl_q2d_workspace_size(f, pl, 1, &Pi);
+                CHECK(ni > 0);
+                CHECK(fastqsl_q2d(f, pl, 1, &Pi, m, workspace(ni), ni, nullptr) == FQ_OK);
+                Pi.reserved2 = 1;
+                CHECK(fastqsl_q2d_workspace_size(f, pl, 1, &Pi) == 0);
+            }
             fq_field bad = f[0];
             bad.n[1] = 1;
             CHECK(fastqsl_q2d_workspace_size(&bad, pl, 1, &P) == 0);
