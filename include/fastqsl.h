@@ -159,8 +159,9 @@ typedef struct {
                           fields and Q); the adjoint calls take Method I only */
     int32_t in_flight; /* FQ_PREC_F32X maps: nonzero when the caller keeps other maps in flight
                           on other streams at the same time. The FP64 pass (a tail of few,
-                          long lines) then runs at three waves per SIMD, spilling a little, so
-                          that the other maps' FP32 passes find room beside its waves: more
+                          long lines) then runs at three waves per SIMD, spilling a little, and
+                          takes its half lines longest first (waves of short lines end early),
+                          so that the other maps' FP32 passes find room beside its waves: more
                           maps per second in flight, a longer FP64 pass for one map alone.
                           Results are the same bit for bit; default 0 */
     int32_t reserved2; /* must be 0 */

@@ -347,10 +347,16 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         if (specs[i].f->dtype == FQ_DT_F64) fix_store = FQ_DT_F64;
     int64_t all_lines = 0;
     for (int i = 0; i < ns; i++) all_lines += W[i].nlines * (W[i].rotate ? 5 : 1);
-    size_t off_list = 0, off_lcount = 0, off_jobs64 = 0;
+    size_t off_list = 0, off_lcount = 0, off_jobs64 = 0, off_fkey = 0, off_fcnt = 0, off_flist = 0;
     if (fixup) {
         off_list = cv.take((size_t)(2 * all_lines) * sizeof(FixEntry));
         off_lcount = cv.take(2 * sizeof(uint32_t));  // positions-only and twist lists
+        if (P.in_flight) {
+            // the positions-only list ordered longest first (keys, counts, the list)
+            off_fkey = cv.take((size_t)(2 * all_lines) * sizeof(int32_t));
+            off_fcnt = cv.take(256 * sizeof(uint32_t));
+            off_flist = cv.take((size_t)(2 * all_lines) * sizeof(FixEntry));
+        }
         if (fix_store == FQ_DT_F64) {
             off_jobs64 = cv.take((size_t)njobs * sizeof(TraceJob));
             for (int i = 0; i < ns; i++) {
@@ -665,6 +671,14 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
         fp.tape = nullptr;  // the adjoint's checkpoints come from the FP32 pass only
         fp.xcd_ctr = nullptr;  // list mode: one queue
         fp.list = list;
+        if (P.in_flight) {
+            // with other maps in flight, a wave that holds lines of like length frees its
+            // SIMD slot for them sooner: the list longest first
+            FixEntry *sorted = (FixEntry *)(ws + off_flist);
+            FQ_TRY(launch_fix_order(jobs_dev, list, lcount, 2 * all_lines, (int32_t *)(ws + off_fkey),
+                                    (uint32_t *)(ws + off_fcnt), sorted, stream));
+            fp.list = sorted;
+        }
         fp.list_count = lcount;
         fp.list_cap = 2 * all_lines;
         // the FP64 pass is held to the FP64 floor unless the caller set a larger one
@@ -680,6 +694,7 @@ int run(const std::vector<Spec> &specs, const fq_params &P, char *ws, size_t ws_
             // half lines the FP32 pass could not finish have no twist yet: trace those
             // (usually none) with the twist integrand, on a queue counter of their own
             TraceParams ft = fp;
+            ft.list = list;  // the twist list sits at the top of the unordered array
             ft.list_count = lcount + 1;
             ft.list_rev = 1;
             unsigned long long *c2 = (unsigned long long *)(ws + off_ctr + 192);

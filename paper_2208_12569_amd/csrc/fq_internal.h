@@ -220,6 +220,11 @@ hipError_t launch_voxel_order(const TraceJob &J, int prec, int want_tw, int32_t 
 // (whose twist is then missing too) apart at list[cap - 1 - k] for k < *count_tw.
 // qmap: the job's map after the FP32 pass (the map of the job's main points for a
 // rotated-S0 job), or NULL. seed_check: also list lines whose seed is grazing.
+// The first `*count` entries of the FP64 pass's list, longest half lines first, into
+// `out` (key: cap int32, counts: 256 uint32 of scratch).
+hipError_t launch_fix_order(const TraceJob *jobs_dev, const FixEntry *list, const uint32_t *count,
+                            int64_t cap, int32_t *key, uint32_t *counts, FixEntry *out,
+                            hipStream_t s);
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr, FixEntry *list, uint32_t *count,
                         uint32_t *count_tw, int64_t cap, int split, int seed_check, hipStream_t s);

@@ -1095,6 +1095,75 @@ hipError_t launch_rot_ranges(TraceJob *jobs_dev, int first, int n, int64_t base,
     return hipGetLastError();
 }
 
+namespace {
+// The FP64 pass's list ordered longest first (by the FP32 pass's length of each half
+// line, in cells of the smallest spacing, 4 cells per key; a key per 256): a wave then
+// takes lines of like length and frees its SIMD slot when they end, instead of
+// holding it for one long line among short ones. Only the list's own entries are
+// keyed (the count is on the device); the placement is tile_place_kernel's.
+__global__ void fix_key_kernel(const TraceJob *__restrict__ jobs, const FixEntry *__restrict__ list,
+                               const uint32_t *__restrict__ count, int64_t cap,
+                               int32_t *__restrict__ key, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = (int64_t)*count < cap ? (int64_t)*count : cap;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const FixEntry e = list[t];
+        const TraceJob &J = jobs[e.job];
+        const double len = J.rec.len[e.half ? J.nlines + e.line : e.line];
+        double d = J.spacing[0];
+        if (J.spacing[1] < d) d = J.spacing[1];
+        if (J.spacing[2] < d) d = J.spacing[2];
+        const double c = len / (4.0 * d);
+        const int k = !(c > 0.0) ? 0 : (c >= 255.0 ? 255 : (int)c);
+        const int b = 255 - k;
+        key[t] = b;
+        atomicAdd(hist + b, 1u);
+    }
+    __syncthreads();
+    if (hist[threadIdx.x]) atomicAdd(counts + threadIdx.x, hist[threadIdx.x]);
+}
+
+__global__ void fix_place_kernel(const FixEntry *__restrict__ list, const uint32_t *__restrict__ count,
+                                 int64_t cap, const int32_t *__restrict__ key,
+                                 uint32_t *__restrict__ offsets, FixEntry *__restrict__ out)
+{
+    __shared__ uint32_t hist[256], base[256];
+    const int64_t n = (int64_t)*count < cap ? (int64_t)*count : cap;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n; t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        const int b = t < n ? key[t] : -1;
+        const uint32_t r = b >= 0 ? atomicAdd(hist + b, 1u) : 0u;
+        __syncthreads();
+        if (hist[threadIdx.x]) base[threadIdx.x] = atomicAdd(offsets + threadIdx.x, hist[threadIdx.x]);
+        __syncthreads();
+        if (b >= 0) out[base[b] + r] = list[t];
+        __syncthreads();
+    }
+}
+}  // namespace
+
+hipError_t launch_fix_order(const TraceJob *jobs_dev, const FixEntry *list, const uint32_t *count,
+                            int64_t cap, int32_t *key, uint32_t *counts, FixEntry *out,
+                            hipStream_t s)
+{
+    int64_t b = (cap + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    hipLaunchKernelGGL(fill_counts_kernel, dim3(1), dim3(256), 0, s, counts);
+    hipLaunchKernelGGL(fix_key_kernel, dim3((unsigned)b), dim3(256), 0, s, jobs_dev, list, count, cap,
+                       key, counts);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(64), 0, s, counts);
+    hipLaunchKernelGGL(fix_place_kernel, dim3((unsigned)b), dim3(256), 0, s, list, count, cap, key,
+                       counts, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_graze(const TraceJob *jobs_dev, int job, int64_t max_lines, double thr,
                         const double *qmap, double qthr, FixEntry *list, uint32_t *count,
                         uint32_t *count_tw, int64_t cap, int split, int seed_check, hipStream_t s)

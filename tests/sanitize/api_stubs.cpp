@@ -102,6 +102,17 @@ hipError_t launch_graze(const TraceJob *jobs, int job, int64_t, double, const do
     g_calls++;
     return hipSuccess;
 }
+hipError_t launch_fix_order(const TraceJob *, const FixEntry *list, const uint32_t *count, int64_t cap,
+                            int32_t *key, uint32_t *counts, FixEntry *out, hipStream_t)
+{
+    in_ws(list, (size_t)cap * sizeof(FixEntry), "re-trace list");
+    in_ws(count, 4, "re-trace count");
+    in_ws(key, (size_t)cap * 4, "re-trace keys");
+    in_ws(counts, 256 * 4, "re-trace key counts");
+    in_ws(out, (size_t)cap * sizeof(FixEntry), "ordered re-trace list");
+    g_calls++;
+    return hipSuccess;
+}
 hipError_t launch_map_backward(const MapJob &m, const double *, const double *, const double *,
                                const double *, double *lam_end, double *lam_tw, double *gnode,
                                int64_t nhalf0, hipStream_t)
