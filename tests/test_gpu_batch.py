@@ -67,15 +67,17 @@ def _dev(jobs):
     return [(torch.from_numpy(np.ascontiguousarray(B)).cuda(), g, pl) for B, g, pl in jobs]
 
 
-@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
-def test_graph_replays_match_eager(fq, prec):
+@pytest.mark.parametrize("prec,in_flight", [(F32X, False), (F64, False), (F32X, True)],
+                         ids=["f32x", "f64", "f32x-in-flight"])
+def test_graph_replays_match_eager(fq, prec, in_flight):
     """A captured batch replayed three times, with the fields rewritten in place and
-    eager work between replays, equals eager calls bit for bit every time."""
+    eager work between replays, equals eager calls bit for bit every time (also with
+    in_flight, whose FP64 pass takes its list through a counting sort)."""
     import torch
 
     from paper_2208_12569_amd.graph import Q2DGraph
 
-    _say(f"graph replay, 3-cube batch, precision {prec}")
+    _say(f"graph replay, 3-cube batch, precision {prec}, in_flight {in_flight}")
     A = _dev(_small_batch(1))
     Bj = _dev(_small_batch(2))
     p = fq.Params(precision=prec)
@@ -83,7 +85,7 @@ def test_graph_replays_match_eager(fq, prec):
     ref_b = fq.q2d_batch(Bj, p, want_lines=True)
     torch.cuda.synchronize()
     keep = [B.clone() for B, _, _ in A]
-    g = Q2DGraph(A, p, want_lines=True)
+    g = Q2DGraph(A, fq.Params(precision=prec, in_flight=in_flight), want_lines=True)
     for it, (src, ref) in enumerate(((None, ref_a), (Bj, ref_b), (keep, ref_a))):
         if src is not None:
             for (dst, _, _), s in zip(A, src):
