@@ -217,3 +217,19 @@ def test_malformed_node_coordinates(fq):
     _say("method II on a stretched grid")
     with pytest.raises(ValueError, match="unsupported"):
         _q2d(fq, B, g, pl, F64, method=1)
+
+
+def test_in_flight_form_equals_default_on_a_stretched_grid(fq, c1s):
+    """The F32X map with in_flight set (its FP64 pass at three waves per SIMD, the
+    list longest first) equals the default one bit for bit on the stretched cube."""
+    import torch
+
+    w, _ = c1s
+    _say("c1s in_flight form")
+    a = fq.q2d(_dev(w.field), w.grid, w.plane, fq.Params(precision=F32X), want_lines=True)
+    b = fq.q2d(_dev(w.field), w.grid, w.plane, fq.Params(precision=F32X, in_flight=True), want_lines=True)
+    torch.cuda.synchronize()
+    for k in ("q", "tw", "length", "status"):
+        assert np.array_equal(to_np(a[k]), to_np(b[k]), equal_nan=True), k
+    for k in ("end_b", "end_f"):
+        assert np.array_equal(to_np(a["lines"][k]), to_np(b["lines"][k]), equal_nan=True), k
