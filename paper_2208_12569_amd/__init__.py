@@ -339,6 +339,45 @@ def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = Fals
     return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws, perp)[0]
 
 
+def q2d_many(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
+             streams: int = 3) -> list:
+    """q2d maps of many (B, grid, plane) jobs, `streams` of them in flight at once on as
+    many streams of default priority, each with its own workspace, in_flight set: one
+    map's FP64 pass overlaps the next maps' FP32 passes (more maps per second than one
+    call after another; the same maps bit for bit). The caller's current stream waits
+    for all of them before this returns, so the results are ready in its order."""
+    import dataclasses
+
+    torch = _torch()
+    params = dataclasses.replace(params or Params(), in_flight=True)
+    n = max(1, int(streams))
+    main = torch.cuda.current_stream()
+    pool = [torch.cuda.Stream() for _ in range(n)]
+    start = torch.cuda.Event()
+    start.record(main)
+    wss: dict = {}
+    out = []
+    for k, (B, grid, plane) in enumerate(jobs):
+        s = pool[k % n]
+        s.wait_event(start)  # inputs written on the caller's stream are ready
+        with torch.cuda.stream(s):
+            r = q2d(B, grid, plane, params, want_lines, stream=s, ws=wss.get(k % n))
+        need = int(r["_ws"].numel())
+        if k % n not in wss or wss[k % n].numel() < need:
+            wss[k % n] = r["_ws"]
+        out.append(r)
+    for s in pool:
+        e = torch.cuda.Event()
+        e.record(s)
+        main.wait_event(e)
+    # tensors made on the side streams are used on the caller's stream from now on
+    for r in out:
+        for v in list(r.values()) + list(r.get("lines", {}).values()):
+            if hasattr(v, "record_stream"):
+                v.record_stream(main)
+    return out
+
+
 def q2d_static(jobs: Sequence, params: Optional[Params] = None, outs: Optional[list] = None,
                want_lines: bool = False, stream=None) -> list:
     """fastqsl_q2d_static: the maps of q2d_batch with the library's own device

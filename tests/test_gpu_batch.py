@@ -221,3 +221,22 @@ def test_maps_in_flight_on_several_streams(fq, prec):
     torch.cuda.synchronize()
     for n, (k, r) in enumerate(outs):
         _same(r, ref[k], f"in flight {n} (call {k})")
+
+
+@pytest.mark.parametrize("prec", [F32X, F64], ids=["f32x", "f64"])
+def test_q2d_many_equals_one_at_a_time(fq, prec):
+    """q2d_many (maps three in flight on three streams) over seven jobs of uneven
+    cubes and seed grids, FP32 and FP64 fields, an interior plane among them: each map
+    equals its own q2d call bit for bit, and is ready on the caller's stream."""
+    import torch
+
+    jobs = _dev(_small_batch(5)) + _dev(_small_batch(6))
+    B, g, _ = jobs[0]
+    jobs.append((B, g, synth.Plane((0.1, 0.1, 0.41), (1, 0, 0), (0, 1, 0), 30, 26, 0.025, 0.03)))
+    p = fq.Params(precision=prec)
+    _say(f"q2d_many over {len(jobs)} jobs, precision {prec}")
+    many = fq.q2d_many(jobs, p, want_lines=True)
+    for j, ((B, g, pl), r) in enumerate(zip(jobs, many)):
+        ref = fq.q2d(B, g, pl, p, want_lines=True)
+        torch.cuda.synchronize()
+        _same(r, ref, f"q2d_many job {j}")
