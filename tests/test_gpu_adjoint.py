@@ -914,22 +914,27 @@ def test_q3d_adjoint_matches_finite_differences(fq, q3d_charge_case):
     assert max(errs) < 1e-4, errs
 
 
-@pytest.mark.parametrize("stretched", [False, True], ids=["uniform", "stretched"])
-def test_q3d_adjoint_equals_its_layers_as_planes(fq, q3d_charge_case, stretched):
-    """A voxel layer z = z_k is the interior seed plane z = z_k with the same points:
-    the 3-D map's gradient of a loss is the sum over layers of the plane adjoint's
-    gradients of that loss's layer terms (two entry points, two seed kinds)."""
+@pytest.mark.parametrize("stretched,face", [(False, False), (True, False), (False, True)],
+                         ids=["uniform", "stretched", "bottom-layer-on-face-no-tw"])
+def test_q3d_adjoint_equals_its_layers_as_planes(fq, q3d_charge_case, stretched, face):
+    """A voxel layer z = z_k is the seed plane z = z_k with the same points (interior,
+    or on the bottom face for a voxel grid starting at z = 0, whose voxels there take
+    no rotated S0): the 3-D map's gradient of a loss is the sum over layers of the
+    plane adjoint's gradients of that loss's layer terms (two entry points, two seed
+    kinds); the face case also without the twist integrand."""
     import torch
 
     gc, B0, vx = q3d_charge_case
+    if face:
+        vx = synth.Voxels((vx.origin[0], vx.origin[1], 0.0), vx.spacing, (vx.n[0], vx.n[1], 3))
     if stretched:
         x = synth.clustered_axis(33, 0.0, 1.0, 0.45, 1.3)
         gc = synth.stretched_grid(x, x.copy(), synth.geometric_axis(33, 0.0, 1.0, 1.03))
         pos, q = synth.draw_charges(np.random.default_rng(21), 5)
         B0 = synth.charges_field(gc, pos, q)
     B = _dev(B0)
-    p = fq.Params(precision=F64, tol_perp=TOL)
-    _say(f"q3d layers as planes ({'stretched' if stretched else 'uniform'}): q3d map")
+    p = fq.Params(precision=F64, tol_perp=TOL, want_tw=not face)
+    _say(f"q3d layers as planes ({'stretched' if stretched else 'uniform'}, face {face}): q3d map")
     r = fq.q3d(B, gc, vx, p)
     mask = _fd_mask3(fq, r)
     gen = torch.Generator(device="cuda").manual_seed(4)
@@ -938,7 +943,7 @@ def test_q3d_adjoint_equals_its_layers_as_planes(fq, q3d_charge_case, stretched)
     wt = torch.randn(shp, generator=gen, device="cuda", dtype=torch.float64) * mask
     qq = torch.where(mask, r["q"], torch.ones_like(r["q"]))
     dq = wq / qq
-    g3 = _q3d_grad(fq, B, gc, vx, p, dq=dq.reshape(-1), dtw=wt.reshape(-1))
+    g3 = _q3d_grad(fq, B, gc, vx, p, dq=dq.reshape(-1), dtw=None if face else wt.reshape(-1))
     acc = np.zeros_like(g3)
     nx, ny, nz = vx.n
     for k in range(nz):
@@ -948,7 +953,8 @@ def test_q3d_adjoint_equals_its_layers_as_planes(fq, q3d_charge_case, stretched)
         rp = fq.q2d(B, gc, pl, p)
         ok = mask[k] & torch.isfinite(rp["q"])
         assert bool((((rp["q"] - r["q"][k]).abs() <= 1e-8 * r["q"][k].abs()) | ~ok).all())
-        acc += _grad(fq, B, gc, pl, dq=dq[k].reshape(-1), dtw=wt[k].reshape(-1))
+        acc += _grad(fq, B, gc, pl, dq=dq[k].reshape(-1), dtw=None if face else wt[k].reshape(-1),
+                     pkw={"want_tw": not face})
     scale = np.abs(g3).max()
     print("q3d vs layer planes: max abs diff", np.abs(g3 - acc).max(), "scale", scale)
     assert scale > 0 and np.allclose(g3, acc, rtol=1e-7, atol=1e-9 * scale)
