@@ -1019,3 +1019,52 @@ def test_q3d_record_and_reverse(fq, q3d_charge_case, prec):
     for bad in (fq.Params(precision=F64, scheme=fq.FQ_SCHEME_RK4), fq.Params(precision=F64, method=1)):
         with pytest.raises(ValueError):
             fq.q3d_backward(_dev(B0), gc, vx, bad, 16, dq=dq)
+
+
+def test_q3d_gradient_matches_oracle_finite_differences(fq):
+    """Reference gradient of a 3-D map: central differences of the FP64 oracle's Q at
+    12 voxels (rotated-S0 ones among them when the field has them there) for three
+    charge parameters, against the 3-D adjoint of the sum of those Q values taken
+    back through the charge field."""
+    import torch
+
+    from synth.torch_fields import charges_field_torch
+
+    g = cubic_grid(33, 33, 33)
+    rng = np.random.default_rng(21)
+    pos, q = synth.draw_charges(rng, 5)
+    vx = synth.Voxels((0.2, 0.2, 0.3), (0.6 / 13, 0.6 / 13, 0.1), (14, 14, 4))
+    _say("q3d oracle reference gradient: base map")
+    B0 = synth.charges_field(g, pos, q)
+    p = fq.Params(precision=F64, tol_perp=TOL)
+    r = fq.q3d(_dev(B0), g, vx, p)
+    mask = _fd_mask3(fq, r).cpu().numpy().ravel()
+    st = to_np(r["status"]).astype(np.int64).ravel()
+    rot = np.flatnonzero(mask & ((st & fq.ST_ROTATED) != 0))
+    plain = np.flatnonzero(mask & ((st & fq.ST_ROTATED) == 0))
+    nrot = min(4, rot.size)
+    idx = np.sort(np.concatenate([rng.choice(rot, nrot, replace=False),
+                                  rng.choice(plain, 12 - nrot, replace=False)]))
+    print("voxels:", idx.tolist(), "rotated:", nrot)
+    n = int(np.prod(vx.n))
+    dq = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dq[torch.tensor(idx, device="cuda")] = 1.0
+    theta0 = np.concatenate([pos.ravel(), q])
+    theta = torch.tensor(theta0, device="cuda", requires_grad=True)
+    Bt = charges_field_torch(g, theta[:15].view(5, 3), theta[15:], torch.float64, "cuda")
+    _say("q3d oracle reference gradient: adjoint")
+    gb = fq.q3d_backward(Bt.detach(), g, vx, p, 16, dq=dq)
+    Bt.backward(gb)
+    grad = theta.grad.cpu().numpy()
+    for i in (0, 5, 16):  # x of charge 0, z of charge 1, strength of charge 1
+        h = 1e-5 * max(1.0, abs(float(theta0[i])))
+        vals = []
+        for sgn in (1, -1):
+            th = theta0.copy()
+            th[i] += sgn * h
+            Bh = synth.charges_field(g, th[:15].reshape(5, 3), th[15:])
+            o = oracle.q3d_points(Bh, g, vx, idx, {"tol": 1e-11})
+            vals.append(float(np.sum(o["q"])))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(i, grad[i], fd)
+        assert abs(grad[i] - fd) <= 1e-4 * max(abs(fd), 1e-3), (i, grad[i], fd)
