@@ -5,8 +5,9 @@ One step = one fastqsl_q2d call on the 256x256x128 FP32 cube (6 seeded charges p
 an arched, uniformly twisted flux tube) with 1024 x 1024 seeds on z = 0: field
 preparation, FP32 tracing of both halves of every line, the FP64 re-trace of
 grazing lines, and the FP64 Q/Tw/length stencil. The field is resident in HBM
-before the timed region. The headline times K such maps with --in-flight (3) of
-them in flight on as many streams, each with its own workspace, so that one map's
+before the timed region. The headline times K such maps with --in-flight (4) of
+them in flight on as many streams (the current one among them), each with its own
+workspace, so that one map's
 FP64 pass overlaps the next maps' FP32 passes; the same maps one at a time, and
 the kernel timings the roofline takes, come from a run with one map in flight.
 Prints ONE JSON line on stdout; details go to stderr.
@@ -175,9 +176,11 @@ def run_gpu(w, prec_name: str, tol: float, steps: int, warmup: int, method: int 
 
 def run_in_flight(w, prec_name: str, tol: float, steps: int, warmup: int, n: int = 3):
     """The same maps with n of them in flight at once, on n streams of default priority
-    with a workspace each: one map's FP64 pass and stencil (a tail that leaves most
-    SIMDs idle) overlap the next maps' FP32 passes. Every map is computed whole; they
-    are checked equal, bit for bit, to the same map computed alone."""
+    (the current stream and n - 1 more: the GPU runs four hardware queues, and a fifth
+    stream would share one) with a workspace each: one map's FP64 pass and stencil (a
+    tail that leaves most SIMDs idle) overlap the next maps' FP32 passes. Every map is
+    computed whole; they are checked equal, bit for bit, to the same map computed
+    alone."""
     import torch
 
     import paper_2208_12569_amd as fq
@@ -187,7 +190,7 @@ def run_in_flight(w, prec_name: str, tol: float, steps: int, warmup: int, n: int
     # in_flight: the F32X form's FP64 pass at three waves per SIMD, leaving room for
     # the other maps' FP32 waves (same results)
     p = fq.Params(precision=prec, tol_perp=tol, in_flight=True)
-    streams = [torch.cuda.Stream() for _ in range(n)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n - 1)]
     wss = []
     for s in streams:
         with torch.cuda.stream(s):
@@ -697,7 +700,7 @@ def main():
     ap.add_argument("--precision", choices=("f32x", "f64"), default="f32x")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--in-flight", type=int, default=3,
+    ap.add_argument("--in-flight", type=int, default=4,
                     help="maps in flight on as many streams for the headline throughput "
                          "(1: one map at a time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -340,19 +340,21 @@ def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = Fals
 
 
 def q2d_many(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
-             streams: int = 3) -> list:
+             streams: int = 4) -> list:
     """q2d maps of many (B, grid, plane) jobs, `streams` of them in flight at once on as
-    many streams of default priority, each with its own workspace, in_flight set: one
-    map's FP64 pass overlaps the next maps' FP32 passes (more maps per second than one
-    call after another; the same maps bit for bit). The caller's current stream waits
-    for all of them before this returns, so the results are ready in its order."""
+    many streams of default priority (the caller's current stream and streams - 1
+    more; the GPU runs four hardware queues by default, and streams beyond them share
+    one), each with its own workspace, in_flight set: one map's FP64 pass overlaps the
+    next maps' FP32 passes (more maps per second than one call after another; the same
+    maps bit for bit). The caller's current stream waits for all of them before this
+    returns, so the results are ready in its order."""
     import dataclasses
 
     torch = _torch()
     params = dataclasses.replace(params or Params(), in_flight=True)
     n = max(1, int(streams))
     main = torch.cuda.current_stream()
-    pool = [torch.cuda.Stream() for _ in range(n)]
+    pool = [main] + [torch.cuda.Stream() for _ in range(n - 1)]
     start = torch.cuda.Event()
     start.record(main)
     wss: dict = {}
@@ -366,7 +368,7 @@ def q2d_many(jobs: Sequence, params: Optional[Params] = None, want_lines: bool =
         if k % n not in wss or wss[k % n].numel() < need:
             wss[k % n] = r["_ws"]
         out.append(r)
-    for s in pool:
+    for s in pool[1:]:
         e = torch.cuda.Event()
         e.record(s)
         main.wait_event(e)
