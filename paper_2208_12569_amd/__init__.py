@@ -339,6 +339,9 @@ def q2d(B, grid, plane, params: Optional[Params] = None, want_lines: bool = Fals
     return q2d_batch([(B, grid, plane)], params, want_lines, stream, ws, perp)[0]
 
 
+_SIDE_STREAMS: dict = {}
+
+
 def q2d_many(jobs: Sequence, params: Optional[Params] = None, want_lines: bool = False,
              streams: int = 4) -> list:
     """q2d maps of many (B, grid, plane) jobs, `streams` of them in flight at once on as
@@ -354,7 +357,13 @@ def q2d_many(jobs: Sequence, params: Optional[Params] = None, want_lines: bool =
     params = dataclasses.replace(params or Params(), in_flight=True)
     n = max(1, int(streams))
     main = torch.cuda.current_stream()
-    pool = [main] + [torch.cuda.Stream() for _ in range(n - 1)]
+    # side streams are made once per device and kept: HIP assigns hardware queues to
+    # streams in the order they are created, so streams made anew for every call would
+    # come to share a queue with the caller's
+    side = _SIDE_STREAMS.setdefault(main.device, [])
+    while len(side) < n - 1:
+        side.append(torch.cuda.Stream(device=main.device))
+    pool = [main] + side[:n - 1]
     start = torch.cuda.Event()
     start.record(main)
     wss: dict = {}
