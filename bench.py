@@ -418,12 +418,23 @@ def run_batch(seed: int, steps: int, warmup: int):
             tt.append(e0.elapsed_time(e1))
         alone += sorted(tt)[1]
         del wsb, outs
+    # the same jobs as single calls, four in flight (q2d_many), for comparison
+    for _ in range(max(1, warmup)):
+        fq.q2d_many(jobs, params)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        fq.q2d_many(jobs, params)
+    b.record()
+    torch.cuda.synchronize()
+    many_ms = a.elapsed_time(b) / steps
     log(f"[batch] {ms:.3f} ms per graph replay of 16 jobs ({npts} values); one call per job: "
-        f"{alone:.3f} ms")
+        f"{alone:.3f} ms; one call per job, four in flight: {many_ms:.3f} ms")
     return {"workload": "16 seeded cubes, edges U{64..384} (FP32, 4-12 charges), seed grids "
                         "U{128,256,512,1024}^2 on z=0, one persistent launch in a HIP graph",
             "value": npts / (ms * 1e-3), "unit": UNIT, "ms_per_batch": ms, "values": npts,
             "one_call_per_job_ms": alone, "batching_gain": alone / ms,
+            "one_call_per_job_four_in_flight_ms": many_ms,
             "params": {"block": params.block, "waves_per_cu": params.waves_per_cu}}
 
 
