@@ -869,10 +869,18 @@ def main():
     # curl B per cell fetch) per second, against the microbenchmark's sustained rate
     g = w.grid
     micro, micro_inc = gather_roofline(g.nx * g.ny * g.nz, g.nx, g.ny, g.nz)
+    # the same walks on record arrays of the other workloads' sizes: L2-resident
+    # (64^3, 8.4 MB of records), the MALL-sized C2 above (268 MB), HBM-spilling
+    # (512x512x256, 2.1 GB)
+    by_size = {"256x256x128 (C2)": {"coherent": micro / 1e9, "incoherent": micro_inc / 1e9}}
+    for label, (ax, ay, az) in (("64^3 (C1)", (64, 64, 64)), ("512x512x256 (C3)", (512, 512, 256))):
+        c, i = gather_roofline(ax * ay * az, ax, ay, az)
+        by_size[label] = {"coherent": c / 1e9, "incoherent": i / 1e9}
     gathered = s32[2] * BYTES_PER_FETCH / (main_run["trace_ms"] * 1e-3)
     per_stage = rk_trials * STAGES_PER_TRIAL * BYTES_PER_STAGE / (main_run["trace_ms"] * 1e-3)
     out["gather_roofline"] = {"achieved": gathered / 1e9, "peak": micro / 1e9, "unit": "GB/s",
                               "frac": gathered / micro, "incoherent_walks": micro_inc / 1e9,
+                              "microbenchmark_by_record_array": by_size,
                               "method_bytes_per_stage_rate": per_stage / 1e9,
                               "note": "cell fetches x 192 B / tracer time, against the same "
                                       "fetches along field-line-like walks with no arithmetic "
