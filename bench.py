@@ -704,6 +704,19 @@ def run_q3d(seed: int, steps: int, warmup: int, sample: int = 3000):
         ms = a.elapsed_time(b) / steps
         out[name] = {"value": n / (ms * 1e-3), "ms_per_map": ms, "first_call_ms": first}
         keep[name] = {k: r[k].cpu().numpy().ravel() for k in ("q", "tw", "status")}
+        if name == "f32x":
+            # the FP32 pass alone (no FP64 pass), timed on its own stream with HIP
+            # events, and its cell fetches: the tracer's gathered bytes per second
+            ev = HipEvents()
+            e4 = ev.create(4)
+            s32 = torch.zeros(5, dtype=torch.int64, device="cuda")
+            fq.q3d(w.field, w.grid, vx, fq.Params(precision=prec, graze=-1.0, stats=s32, events=e4),
+                   ws=ws)
+            torch.cuda.synchronize()
+            tms = ev.ms(e4[0], e4[1])
+            fetches = int(s32[2])
+            out[name]["fp32_pass"] = {"trace_ms": tms, "cell_fetches": fetches,
+                                      "gathered_GB_per_s": fetches * BYTES_PER_FETCH / (tms * 1e-3) / 1e9}
         log(f"[q3d {name}] {ms:.3f} ms per map (first call {first:.3f} ms)")
         del ws, r
     st = keep["f32x"]["status"].astype(np.uint16)
@@ -936,6 +949,12 @@ def main():
     if not args.no_q3d:
         out["q3d"] = run_q3d(args.seed, args.sub_steps, args.warmup)
         q3d_sample = out["q3d"].pop("_sample")
+        # its FP32 pass against the same walks on a record array of its cube's size
+        fp = out["q3d"]["f32x"].get("fp32_pass")
+        c3 = by_size.get("512x512x256 (C3)")
+        if fp and c3:
+            fp["gather_frac_of_coherent_walks"] = fp["gathered_GB_per_s"] / c3["coherent"]
+            fp["gather_vs_incoherent_walks"] = fp["gathered_GB_per_s"] / c3["incoherent"]
     if args.calib_copy:
         import torch
 
